@@ -1,0 +1,479 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle (``oracle/``) against something other than itself:
+numbers printed in the paper (tests/golden/, each file citing its table), closed
+forms, invariants, brute force on tiny inputs and textbook special cases.
+"""
+
+import csv
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import integral, levy, output, scheme
+import workloads
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return list(csv.DictReader(line for line in f if not line.startswith("#")))
+
+
+def _table1():
+    out = {}
+    for r in _rows("table1_params.csv"):
+        p = levy.nts_params(float(r["alpha"]), float(r["delta"]), float(r["lambda"]),
+                            (float(r["eta1"]), float(r["eta2"])),
+                            ((float(r["rho11"]), float(r["rho12"])), (float(r["rho12"]), float(r["rho22"]))))
+        out[r["name"]] = (p, float(r["r"]), float(r["T"]), float(r["K"]))
+    return out
+
+
+# --------------------------------------------------------------------------- #
+# Levy measure
+# --------------------------------------------------------------------------- #
+def test_table2_variance_closed_form():
+    """Table 2 (truncated to 4 decimals) from the variance of Table 5."""
+    t1 = _table1()
+    for r in _rows("table2_sd_corr.csv"):
+        V = levy.variance(t1[r["name"]][0])
+        got = (math.sqrt(V[0, 0]), math.sqrt(V[1, 1]), V[0, 1] / math.sqrt(V[0, 0] * V[1, 1]))
+        for g, key in zip(got, ("sd1", "sd2", "corr")):
+            printed = float(r[key])
+            assert printed - 1e-9 <= g < printed + 1e-4 + 1e-9, (r["name"], key, g, printed)
+
+
+def test_zmax3_printed_values():
+    """The printed z_max^III of Sec. 4 are the infinity-norm maxima over the level
+    set l = 1e-14 of the oracle's density (to the 4 printed decimals)."""
+    t1 = _table1()
+    for r in _rows("zmax3.csv"):
+        zs = integral.z_star(t1[r["name"]][0], 1e-14, n_angles=1024)
+        assert abs(zs - float(r["zmax3"])) < 0.5e-4 + 1e-9, (r["name"], zs)
+
+
+def test_density_small_z_asymptote():
+    """Near the origin l(z) ~ delta 2^alpha Gamma(1+alpha) / (pi sqrt(det rho))
+    ||z||_rho^(-2-2 alpha) (the constant C_l(0) of Sec. 4 with the small-argument
+    form of K_nu)."""
+    for name, (p, _, _, _) in _table1().items():
+        a = p["alpha"]
+        c = p["delta"] * 2 ** a * math.gamma(1 + a) / (math.pi * math.sqrt(p["det"]))
+        for ang in (0.3, 1.9, 4.0):
+            u = np.array([math.cos(ang), math.sin(ang)])
+            q = math.sqrt(u @ p["rinv"] @ u)
+            r = 1e-7 / p["c1"]
+            ratio = levy.density(p, r * u[0], r * u[1]) / (c * (r * q) ** (-2 - 2 * a))
+            assert abs(ratio - 1.0) < 1e-5, (name, ratio)
+
+
+def test_density_subordination_form():
+    """The Bessel form of l equals the subordination integral
+    int_0^inf N(z; eta g, rho g) l_G(g) dg with l_G(g) = delta e^{-lambda g} g^{-1-alpha}
+    (Appendix A: the NTS measure is that of B(G(t)), Table 4), by quadrature."""
+    import scipy.integrate as spi
+    p = levy.nts_from_std(**workloads.NIG_BASE)
+    for z in ((0.05, -0.02), (-0.3, 0.4), (0.7, 0.1)):
+        z = np.array(z)
+
+        def f(g):
+            m = z - p["eta"] * g
+            q = m @ p["rinv"] @ m
+            gauss = math.exp(-0.5 * q / g) / (2 * math.pi * g * math.sqrt(p["det"]))
+            return gauss * p["delta"] * math.exp(-p["lam"] * g) * g ** (-1 - p["alpha"])
+
+        val = spi.quad(f, 0, np.inf, epsabs=0, epsrel=1e-12, limit=500)[0]
+        assert abs(levy.density(p, z[0], z[1]) / val - 1) < 1e-9
+
+
+def test_char_exponent_second_derivative_is_variance():
+    """-d^2 psi_L / du du^T at 0 equals V[L(1)] and d psi_L/du at 0 vanishes
+    (E[L(1)] = 0), by finite differences of Table 5's psi_L."""
+    for p in [levy.nts_from_std(**workloads.NIG_BASE), levy.nts_from_std(**workloads.FV_BASE),
+              _table1()["VG0"][0]]:
+        e = 1e-4
+        H = np.zeros((2, 2))
+        for i in range(2):
+            for j in range(2):
+                ui = np.eye(2)[i] * e
+                uj = np.eye(2)[j] * e
+                f = lambda u: levy.char_exponent(p, u)
+                H[i, j] = -(f(ui + uj) - f(ui - uj) - f(-ui + uj) + f(-ui - uj)).real / (4 * e * e)
+        assert np.allclose(H, levy.variance(p), rtol=1e-5)
+        g = (levy.char_exponent(p, np.array([e, 0])) - levy.char_exponent(p, np.array([-e, 0]))) / (2 * e)
+        assert abs(g) < 1e-9
+
+
+# --------------------------------------------------------------------------- #
+# Integral discretization (Sec. 3.1)
+# --------------------------------------------------------------------------- #
+@pytest.fixture(scope="module")
+def nig_disc():
+    p = levy.nts_from_std(**workloads.NIG_BASE)
+    h = 6.0 / 63.0
+    return p, h, integral.discretize(p, h, 0.03)
+
+
+def test_sizes_nig64(nig_disc):
+    p, h, d = nig_disc
+    assert d["N_z"] == 42 and d["M1"] == 2 and d["M2"] == 13
+
+
+def test_weight_regions(nig_disc):
+    """omega = 0 exactly on R_I, positive on R_II and R_III; R_III weights are
+    midpoint values l(z_l) h^2 (Sec. 3.1 weight definition)."""
+    p, h, d = nig_disc
+    W, N = d["W"], d["N_z"]
+    c = integral.cell_norm_inf(N)
+    assert np.all(W[c <= 2] == 0.0)
+    assert np.all(W[c > 2] > 0.0)
+    zc = (np.arange(-N, N) + 0.5) * h
+    k = np.argwhere(c > d["M2"])[5]
+    assert W[k[0], k[1]] == pytest.approx(levy.density(p, zc[k[0]], zc[k[1]]) * h * h, rel=1e-14)
+
+
+def test_weight_cell_integrals_vs_adaptive(nig_disc):
+    """The tensor Gauss-Legendre cell integrals of R_II agree with an adaptive 2D
+    quadrature, including the cells next to R_I."""
+    import scipy.integrate as spi
+    p, h, d = nig_disc
+    W, N = d["W"], d["N_z"]
+    for l1, l2 in ((2, 0), (-3, -3), (2, 2), (-3, 1), (10, -12)):
+        f = lambda z2, z1: (z1 * z1 + z2 * z2) * levy.density(p, z1, z2)
+        v = spi.dblquad(f, l1 * h, (l1 + 1) * h, lambda x: l2 * h, lambda x: (l2 + 1) * h,
+                        epsabs=0, epsrel=1e-13)[0]
+        zc1, zc2 = (l1 + 0.5) * h, (l2 + 0.5) * h
+        assert W[l1 + N, l2 + N] == pytest.approx(v / (zc1 ** 2 + zc2 ** 2), rel=1e-12)
+
+
+def test_weights_symmetric_without_skew():
+    """eta = 0 makes l even, so omega_l = omega_{-1-l} (cell reflection)."""
+    p = levy.nts_from_std(0.2, 0.3, 0.4, 0.0, 0.0, 0.2, 0.4)
+    h = 0.1
+    sz = integral.grid_sizes(p, h)
+    W = integral.weights(p, h, sz["N_z"], 2, sz["M2"])
+    assert np.allclose(W, W[::-1, ::-1], rtol=1e-13, atol=0)
+
+
+def test_small_jump_cov_vs_cartesian(nig_disc):
+    """S (polar, algebraic-weight quadrature) against a Cartesian adaptive
+    quadrature over the square R_I, split at the axes."""
+    import scipy.integrate as spi
+    p, h, d = nig_disc
+    half = 2 * h
+    S = d["S"]
+    tot = 0.0
+    for (a, b) in ((-half, 0), (0, half)):
+        for (c, e) in ((-half, 0), (0, half)):
+            f = lambda z2, z1: z1 * z2 * levy.density(p, z1, z2)
+            tot += spi.dblquad(f, a, b, lambda x: c, lambda x: e, epsabs=1e-14, epsrel=1e-10)[0]
+    assert S[0, 1] == pytest.approx(tot, rel=1e-7)
+
+
+@pytest.mark.parametrize("which", ["nig", "fv", "VG1", "NIG1"])
+def test_discrete_moments_and_compensator(which):
+    """Discrete second moments S + sum omega z z^T approach V[L(1)] (Table 5) and the
+    discrete compensator sum omega (e^{z_i} - 1 - z_i) + S_ii / 2 approaches
+    psi_L(-i e_i) (Table 5, the martingale drift correction).  For the workload
+    models the observed rate under z-grid refinement is at least the
+    h^(2 - 2 alpha) of Proposition 3.1 (less a margin); the Table 1 sets VG1 and
+    NIG1, whose densities vary on a scale of a few hundredths, are only
+    pre-asymptotic at affordable N_z and are checked for size."""
+    if which == "nig":
+        p, ladder = levy.nts_from_std(**workloads.NIG_BASE), (24, 48)
+    elif which == "fv":
+        p, ladder = levy.nts_from_std(**workloads.FV_BASE), (24, 48)
+    else:
+        p, ladder = _table1()[which][0], (192,)
+    V = levy.variance(p)
+    psi = [levy.char_exponent(p, np.array([-1j, 0])).real, levy.char_exponent(p, np.array([0, -1j])).real]
+    zs = integral.z_star(p, 1e-14, n_angles=512)
+    errs = []
+    for N in ladder:
+        h = zs / (N - 0.5)
+        d = integral.discretize(p, h, 0.0)
+        W, Nz = d["W"], d["N_z"]
+        assert Nz == N
+        zc = (np.arange(-Nz, Nz) + 0.5) * h
+        Z1, Z2 = np.meshgrid(zc, zc, indexing="ij")
+        M = np.array([[np.sum(W * Z1 * Z1), np.sum(W * Z1 * Z2)], [np.sum(W * Z1 * Z2), np.sum(W * Z2 * Z2)]]) + d["S"]
+        comp = [np.sum(W * (np.expm1(Z1) - Z1)) + 0.5 * d["S"][0, 0],
+                np.sum(W * (np.expm1(Z2) - Z2)) + 0.5 * d["S"][1, 1]]
+        e = max(np.max(np.abs(M - V)) / np.max(np.abs(V)),
+                max(abs(comp[i] - psi[i]) / abs(psi[i]) for i in range(2)))
+        errs.append(e)
+    assert errs[-1] < 5e-3, errs
+    if len(errs) > 1:
+        rate = math.log2(errs[0] / errs[1])
+        assert rate > 2 - 2 * p["alpha"] - 0.35, (errs, rate)
+
+
+def test_drift_and_rate_definition(nig_disc):
+    p, h, d = nig_disc
+    W, N = d["W"], d["N_z"]
+    zc = (np.arange(-N, N) + 0.5) * h
+    assert d["r_omega"] == pytest.approx(0.03 + W.sum(), rel=1e-14)
+    assert d["kappa"][0] == pytest.approx(0.03 - np.sum(W * np.expm1(zc)[:, None]), rel=1e-12)
+    assert d["kappa"][1] == pytest.approx(0.03 - np.sum(W * np.expm1(zc)[None, :]), rel=1e-12)
+
+
+# --------------------------------------------------------------------------- #
+# Summation operator B (Sec. 3.2.2, Appendix C)
+# --------------------------------------------------------------------------- #
+def test_appendix_c_circulant_example():
+    """Appendix C: N_z = 1, #in = 3, #out = 2.  The rows of the printed circulant C
+    kept by I~ (1, 2, 4, 5, column-major vec) applied to vec(v^in) equal the
+    correlation (B v)_m = sum_l omega_l v^in_{m+l}."""
+    rng = np.random.default_rng(5)
+    w = rng.uniform(0.1, 1.0, size=(2, 2))            # Omega[l1+1, l2+1]
+    vin = rng.standard_normal((3, 3))                 # v^in[k1+1, k2+1], k in {-1,0,1}
+    first = np.zeros((3, 3))
+    first[:2, :2] = w
+    row = first.flatten(order="F")                    # vec = column-major
+    C = np.array([np.roll(row, s) for s in range(9)])  # circulant: each row shifted right by one
+    assert C[0, 1] == w[1, 0] and C[0, 3] == w[0, 1]  # printed first row: w(-1,-1), w(0,-1), 0, w(-1,0), ...
+    got = C[[0, 1, 3, 4]] @ vin.flatten(order="F")
+    out = scheme.correlate_half_grid(vin, w, 2, 2, "direct")
+    want = np.array([out[0, 0], out[1, 0], out[0, 1], out[1, 1]])
+    assert np.allclose(got, want, rtol=1e-15, atol=1e-15)
+    out_fft = scheme.correlate_half_grid(vin, w, 2, 2, "fft")
+    assert np.allclose(out, out_fft, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("P", [1, 3])
+def test_B_direct_equals_fft_and_brute_force(P):
+    """Direct sum == FFT (to rounding); both equal a brute-force evaluation of
+    sum_l omega_l * interp(v)(y_m + z_l) written with explicit loops."""
+    rng = np.random.default_rng(11)
+    n, N_z = 9, 4
+    W = rng.uniform(0, 1, size=(2 * N_z, 2 * N_z))
+    v = rng.standard_normal((n, n))
+    b_dir = scheme.apply_B(v, W, N_z, P, "direct")
+    b_fft = scheme.apply_B(v, W, N_z, P, "fft")
+    assert np.max(np.abs(b_dir - b_fft)) < 1e-13 * np.max(np.abs(b_dir))
+    offs, taps = scheme.half_shift_taps(P)
+
+    def val(i, j):
+        return v[i, j] if 0 <= i < n and 0 <= j < n else 0.0
+
+    m = (3, 6)
+    tot = 0.0
+    for l1 in range(-N_z, N_z):
+        for l2 in range(-N_z, N_z):
+            k1, k2 = m[0] + l1, m[1] + l2
+            vin = sum(taps[a] * taps[b] * val(k1 + offs[a], k2 + offs[b])
+                      for a in range(len(offs)) for b in range(len(offs)))
+            tot += W[l1 + N_z, l2 + N_z] * vin
+    assert b_dir[m] == pytest.approx(tot, rel=1e-13, abs=1e-14)
+
+
+def test_half_shift_cubic_taps():
+    offs, w = scheme.half_shift_taps(3)
+    assert offs == [-1, 0, 1, 2]
+    assert np.allclose(w, np.array([-1, 9, 9, -1]) / 16.0, rtol=0, atol=1e-16)
+
+
+def test_B_of_constant_in_interior(nig_disc):
+    """Away from the edges (further than N_z + 2 nodes) B 1 = sum omega."""
+    p, h, d = nig_disc
+    n = 2 * d["N_z"] + 12
+    b = scheme.apply_B(np.ones((n, n)), d["W"], d["N_z"], 3, "fft")
+    c = n // 2
+    assert b[c, c] == pytest.approx(d["sum_omega"], rel=1e-13)
+
+
+# --------------------------------------------------------------------------- #
+# D, T^SL, cell averaging
+# --------------------------------------------------------------------------- #
+def test_D_exact_on_quadratics():
+    n, h = 11, 0.3
+    a = np.array([[0.04, 0.013], [0.013, 0.09]])
+    D = scheme.build_D(n, h, a)
+    y = -1.5 + h * np.arange(n)
+    Y1, Y2 = np.meshgrid(y, y, indexing="ij")
+    v = 0.7 + 0.2 * Y1 - 0.3 * Y2 + 0.5 * Y1 ** 2 - 0.4 * Y1 * Y2 + 0.25 * Y2 ** 2
+    v1, v2 = 0.2 + 1.0 * Y1 - 0.4 * Y2, -0.3 - 0.4 * Y1 + 0.5 * Y2
+    v11, v12, v22 = 1.0, -0.4, 0.5
+    want = 0.5 * a[0, 0] * (v11 - v1) + a[0, 1] * v12 + 0.5 * a[1, 1] * (v22 - v2)
+    got = (D @ v.ravel()).reshape(n, n)
+    assert np.allclose(got[1:-1, 1:-1], want[1:-1, 1:-1], rtol=0, atol=1e-12)
+    # on boundary rows of axis i the a_ii group is dropped; the one-sided mixed
+    # differences stay exact on w = y1 y2 (d12 w = 1, (d_ii - d_i) w = -y_other)
+    w = Y1 * Y2
+    gw = (D @ w.ravel()).reshape(n, n)
+    int1 = np.zeros(n, bool)
+    int1[1:-1] = True
+    want_w = (a[0, 1] + np.where(int1[:, None], -0.5 * a[0, 0] * Y2, 0.0)
+              + np.where(int1[None, :], -0.5 * a[1, 1] * Y1, 0.0))
+    assert np.allclose(gw, want_w, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("P", [1, 3])
+def test_sl_exact_on_polynomials(P):
+    """T^SL reproduces polynomials of degree <= P at every node, including clamped
+    (extrapolating) stencils at both ends."""
+    n, h = 12, 0.2
+    y = h * np.arange(n)
+    for shift in (0.37, -0.81, 1.6, -2.3):
+        T = scheme.sl_matrix_1d(n, shift, P)
+        for deg in range(P + 1):
+            f = lambda t: (t - 0.3) ** deg
+            assert np.allclose(T @ f(y), f(y + shift * h), rtol=0, atol=1e-12)
+
+
+def test_cell_average_vs_adaptive():
+    """GL-with-breakpoints cell averages against adaptive QUADPACK quadrature
+    given the kink curves in closed form (y2 = ln(2 - e^y1) for the average
+    pay-offs, y1 = 0 for the single-asset ones, y2 = y1 for the exchange)."""
+    import scipy.integrate as spi
+    h = 0.13
+
+    def kinks(kind, a2, b2):
+        if kind in ("put_avg", "call_avg"):
+            inner = lambda y1: [math.log(2 - math.exp(y1))] if math.exp(y1) < 2 else []
+            outer = [math.log(2 - math.exp(t)) for t in (a2, b2) if math.exp(t) < 2]
+        elif kind in ("put_1", "call_1"):
+            inner, outer = (lambda y1: []), [0.0]
+        else:
+            inner, outer = (lambda y1: [y1]), [a2, b2]
+        return inner, outer
+
+    for kind in scheme.PAYOFFS:
+        g = scheme.payoff_g(kind)
+        for c1, c2 in ((0.02, -0.03), (-0.05, 0.06), (0.3, -0.28)):
+            a1, b1, a2, b2 = c1 - h / 2, c1 + h / 2, c2 - h / 2, c2 + h / 2
+            got = scheme.cell_average(g, a1, b1, a2, b2)
+            inner, outer = kinks(kind, a2, b2)
+            f = lambda y2, y1: max(g(y1, y2), 0.0)
+            o_pts = [t for t in outer if a1 < t < b1]
+
+            def opt_inner(y1):
+                return dict(points=[t for t in inner(y1) if a2 < t < b2], epsabs=1e-16, epsrel=1e-13, limit=200)
+
+            ref = spi.nquad(f, [[a2, b2], [a1, b1]],
+                            opts=[opt_inner, dict(points=o_pts, epsabs=1e-16, epsrel=1e-13, limit=200)])[0] / h / h
+            assert got == pytest.approx(ref, rel=1e-11, abs=1e-14), kind
+
+
+def test_initial_values_only_kink_cells_change():
+    n, h = 40, 0.05
+    y = -1.0 + h * np.arange(n)
+    V = scheme.initial_values("put_avg", 100.0, y, y, h, True)
+    V0 = scheme.initial_values("put_avg", 100.0, y, y, h, False)
+    diff = np.argwhere(V != V0)
+    g = scheme.payoff_g("put_avg")
+    for j1, j2 in diff:
+        c = [g(y[j1] + s1 * h / 2, y[j2] + s2 * h / 2) for s1 in (-1, 1) for s2 in (-1, 1)]
+        assert min(c) <= 0 <= max(c)
+    assert len(diff) > 0
+
+
+# --------------------------------------------------------------------------- #
+# Whole march (Algorithm 1)
+# --------------------------------------------------------------------------- #
+def _bs_problem(n, half, payoff, cov, r=0.03, T=1.0, N_t=None):
+    h = 2 * half / (n - 1)
+    disc = integral.discretize(None, h, r, sigma_bs=cov)
+    return scheme.Problem(n, (-half, -half), h, disc, payoff=payoff, K=100.0, T=T,
+                          N_t=N_t or n // 2, theta=0.5)
+
+
+def test_black_scholes_single_asset_put_second_order():
+    """Zero Levy measure and a single-asset put: the 2D scheme reproduces the
+    Black-Scholes price, with errors falling at second order (cubic T^SL)."""
+    s1, s2, c = 0.25, 0.2, 0.4
+    cov = np.array([[s1 * s1, c * s1 * s2], [c * s1 * s2, s2 * s2]])
+    from closed_forms import bs_put
+    errs = []
+    for n in (33, 65):
+        prob = _bs_problem(n, 2.0, "put_1", cov)
+        V, _ = scheme.solve(prob)
+        P = output.prices(V, prob.y_lo, prob.h, 100.0, [(100.0, 100.0), (90.0, 110.0)])
+        errs.append(max(abs(P[0] - bs_put(100, 100, 1, 0.03, s1)), abs(P[1] - bs_put(90, 100, 1, 0.03, s1))))
+    assert errs[1] < 5e-3
+    assert math.log2(errs[0] / errs[1]) > 1.7, errs
+
+
+def test_margrabe_exchange():
+    """Zero Levy measure, exchange pay-off max(S1 - S2, 0): Margrabe's formula."""
+    s1, s2, c = 0.3, 0.2, -0.3
+    cov = np.array([[s1 * s1, c * s1 * s2], [c * s1 * s2, s2 * s2]])
+    from closed_forms import margrabe
+    errs = []
+    for n in (33, 65):
+        prob = _bs_problem(n, 2.0, "exchange", cov)
+        V, _ = scheme.solve(prob)
+        P = output.prices(V, prob.y_lo, prob.h, 100.0, [(100.0, 100.0), (110.0, 95.0)])
+        errs.append(max(abs(P[0] - margrabe(100, 100, 1, s1, s2, c)), abs(P[1] - margrabe(110, 95, 1, s1, s2, c))))
+    assert errs[1] < 1e-2
+    assert math.log2(errs[0] / errs[1]) > 1.5, errs
+
+
+@pytest.mark.slow
+def test_nts_single_asset_put_vs_fourier():
+    """Pure-jump NTS, pay-off on asset 1 only: the 2D march converges to the 1D
+    Fourier price built from psi_L(u e_1) (Table 5)."""
+    from closed_forms import fourier_put_1d
+    p = levy.nts_from_std(**workloads.NIG_BASE)
+    psi1 = lambda u: levy.char_exponent(p, np.stack([np.asarray(u, dtype=complex), 0 * np.asarray(u, dtype=complex)], -1))
+    ref = fourier_put_1d(100.0, 100.0, 1.0, 0.03, psi1)
+    errs = []
+    for n in (48, 96):
+        h = 6.0 / (n - 1)
+        disc = integral.discretize(p, h, 0.03)
+        prob = scheme.Problem(n, (-3, -3), h, disc, payoff="put_1", T=1.0, N_t=n // 2)
+        V, _ = scheme.solve(prob, tol=1e-12)
+        errs.append(abs(output.prices(V, prob.y_lo, h, 100.0, [(100.0, 100.0)])[0] - ref))
+    assert errs[1] < 5e-2 and math.log2(errs[0] / errs[1]) > 1.6, (errs, ref)
+
+
+def test_linearity_and_put_call_parity():
+    """The scheme is linear: solve(call) - solve(put) = solve(call - put) to the
+    fixed-point tolerance; and C - P approaches (S1 + S2)/2 - K e^{-rT}."""
+    p = levy.nts_from_std(**workloads.NIG_BASE)
+    n = 40
+    h = 6.0 / (n - 1)
+    disc = integral.discretize(p, h, 0.03)
+    res = {}
+    for kind in ("put_avg", "call_avg"):
+        prob = scheme.Problem(n, (-3, -3), h, disc, payoff=kind, T=0.5, N_t=12)
+        res[kind], _ = scheme.solve(prob)
+    prob = scheme.Problem(n, (-3, -3), h, disc, payoff="call_avg", T=0.5, N_t=12)
+    y1, y2 = prob.y1, prob.y2
+    Y1, Y2 = np.meshgrid(y1, y2, indexing="ij")
+    # march the difference of the two (cell-averaged) initial grids by itself
+    v0c = scheme.Problem(n, (-3, -3), h, disc, payoff="call_avg").V0()
+    v0p = scheme.Problem(n, (-3, -3), h, disc, payoff="put_avg").V0()
+    prob.V0 = lambda: v0c - v0p
+    Vl, _ = scheme.solve(prob)
+    assert np.max(np.abs((res["call_avg"] - res["put_avg"]) - Vl) / np.maximum(1.0, np.abs(Vl))) < 1e-11
+    P = output.prices(res["call_avg"] - res["put_avg"], prob.y_lo, h, 100.0, [(100.0, 100.0)])[0]
+    assert abs(P - (100.0 - 100.0 * math.exp(-0.03 * 0.5))) < 0.05
+
+
+@pytest.mark.slow
+def test_table3_vg1_nig1():
+    """Table 3 prices near (K, K) (the paper's price-space grid, N_x = 800) against
+    the log-grid oracle on [-1.5, 1.5]^2: VG1 converges towards them under
+    refinement and NIG1 agrees at n = 128 (an O(h) scheme for alpha = 1/2 on
+    this grid)."""
+    t1 = _table1()
+    gold = _rows("table3_prices.csv")
+    spots = [(float(r["x1"]), float(r["x2"])) for r in gold]
+
+    def run(name, n, lo=-1.5, hi=1.5):
+        p, r, T, K = t1[name]
+        h = (hi - lo) / (n - 1)
+        disc = integral.discretize(p, h, r)
+        prob = scheme.Problem(n, (lo, lo), h, disc, payoff="put_avg", K=K, T=T, N_t=n // 2)
+        V, _ = scheme.solve(prob, tol=1e-10)
+        want = np.array([float(rw[name]) for rw in gold])
+        return np.max(np.abs(output.prices(V, prob.y_lo, h, K, spots) - want))
+
+    e128, e192 = run("VG1", 128), run("VG1", 192)
+    assert e192 < 1e-2 and e192 < e128 / 2, (e128, e192)
+    assert run("NIG1", 128) < 1.5e-2
