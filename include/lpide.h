@@ -1,0 +1,197 @@
+/*
+ * lpide.h -- C ABI of the MI355X solver for two-asset exponential-Levy option
+ * PIDEs (method of Moda, in 't Hout, Vanmaele and Benth, arXiv 2511.02700).
+ *
+ * The solver prices a European two-asset option u(S, T) by time-marching the
+ * pricing PIDE u_t = A u - r u (Sec. 2.2, the initial value problem) with the
+ * paper's discretization, written in log-moneyness y_i = ln(S_i / K) on a
+ * uniform n x n grid:
+ *   - the integral term is replaced by the artificial diffusion over R_I and
+ *     the weighted sum B over the z-cells of R_II and R_III (Sec. 3.1), and B is
+ *     applied as a zero-padded 2D FFT correlation (Sec. 3.2.2);
+ *   - the diffusion term is the Kronecker-sum finite-difference matrix D
+ *     (Sec. 3.2.1) and the pay-off is cell averaged near its kink (Sec. 3.2.3);
+ *   - time stepping is the semi-Lagrangian theta-method with four damped
+ *     quarter steps first and a fixed-point iteration on B in every step,
+ *     started from an extrapolated value (Sec. 3.3, Algorithm 1).
+ *
+ * Conventions for every entry point:
+ *   - All functions return an int status: LPIDE_OK (0) or a negative LPIDE_E_*
+ *     code.  Nothing throws across the ABI.  lpide_last_error() returns a
+ *     thread-local, NUL-terminated description of the last failure on the
+ *     calling thread (valid until that thread's next failing call).
+ *   - Grids are row-major n x n FP64 arrays V[j1 * n + j2] with
+ *     y_1 = y_lo[0] + j1 h (slow index) and y_2 = y_lo[1] + j2 h (fast index).
+ *   - Pointers documented as "device" must be device-accessible memory of the
+ *     plan's HIP device (e.g. torch CUDA tensors' data_ptr()); "host" pointers
+ *     are ordinary CPU memory.  The caller owns every input and output buffer.
+ *   - A plan owns all of its device workspace.  Its work is queued on the
+ *     stream given in lpide_opts.stream; a plan is not re-entrant (calls on one
+ *     plan must not overlap), different plans are independent.
+ */
+#ifndef LPIDE_H
+#define LPIDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LPIDE_OK        0
+#define LPIDE_E_PARAM  -1   /* invalid argument (parameter out of range, NULL pointer, size) */
+#define LPIDE_E_NOCONV -2   /* fixed-point iteration did not meet tol within max_iter in some step */
+#define LPIDE_E_NAN    -3   /* a NaN or Inf appeared in the fixed-point increments */
+#define LPIDE_E_HIP    -4   /* a HIP runtime call failed (no device, launch failure, ...) */
+#define LPIDE_E_OOM    -5   /* device or host allocation failed */
+
+/* pay-off kinds, all with strike K: payoff(S) = max(g(S), 0) */
+#define LPIDE_PUT_AVG   0   /* K - (S1 + S2)/2   (put-on-the-average, Sec. 4) */
+#define LPIDE_CALL_AVG  1   /* (S1 + S2)/2 - K */
+#define LPIDE_PUT_1     2   /* K - S1 */
+#define LPIDE_CALL_1    3   /* S1 - K */
+#define LPIDE_EXCHANGE  4   /* S1 - S2  (K only sets the log-moneyness origin) */
+
+/* arithmetic of the FFT correlation */
+#define LPIDE_FP64       0  /* everything in FP64 */
+#define LPIDE_FP32_CONV  1  /* FFT correlation in FP32, all else FP64 (mixed form) */
+
+/* Spatial grid and integral-discretization settings (Sec. 3.1, Sec. 4 settings). */
+typedef struct {
+    int32_t n;            /* nodes per axis, both ends included; 8 <= n <= 8192 */
+    double  y_lo[2];      /* lower ends of the log-moneyness axes y_i = ln(S_i/K) */
+    double  y_hi[2];      /* upper ends; y_hi[i] - y_lo[i] must be equal on both axes,
+                             so that one mesh width h = (y_hi - y_lo)/(n - 1) serves
+                             both axes and the z-grid (h_z = h) */
+    int32_t sl_order;     /* Lagrange order of the semi-Lagrangian interpolation T^SL:
+                             1 (bilinear) or 3 (bicubic, the paper's choice) */
+    int32_t in_order;     /* Lagrange order of the half-cell interpolation T^in from the
+                             grid to the y^in grid, 1 or 3 (paper: 3) */
+    int32_t m1;           /* z_max^I = m1 h (paper: 2) */
+    double  ell_cut;      /* z_max^III level: largest |z|_inf with l(z) = ell_cut
+                             (1e-14 reproduces the paper's printed values) */
+    double  zmax2_frac;   /* z_max^II = h ceil(zmax2_frac N_z - 1/2) (paper: sqrt(0.1)) */
+    int32_t gl_nodes;     /* Gauss-Legendre nodes per axis for the R_II cell integrals */
+} lpide_grid;
+
+/* Model (Sec. 2.1, Sec. 4): r, the 2D NTS Levy measure and an optional
+ * independent Brownian covariance sigma sigma^T. */
+typedef struct {
+    double  r;            /* risk-free rate */
+    double  alpha;        /* NTS index, 0 <= alpha < 1 (0: VG, 1/2: NIG) */
+    double  delta;        /* NTS delta > 0 */
+    double  lambda;       /* NTS lambda > 0 */
+    double  eta[2];       /* NTS drift of the subordinated Brownian motion */
+    double  rho[3];       /* NTS covariance rho11, rho12, rho22 (positive definite) */
+    double  sigma_bs[3];  /* Brownian covariance (sigma sigma^T)_11, _12, _22; the paper
+                             takes 0; must be positive semi-definite */
+    int32_t no_jumps;     /* 1: zero Levy measure (Black-Scholes); NTS fields ignored */
+} lpide_levy;
+
+typedef struct {
+    int32_t kind;         /* LPIDE_PUT_AVG ... */
+    double  K;            /* strike > 0; also the log-moneyness origin y = ln(S/K) */
+    double  T;            /* maturity > 0 */
+    int32_t cell_avg;     /* 1: cell averaging of the pay-off near its kink (Sec. 3.2.3) */
+} lpide_payoff;
+
+typedef struct {
+    double  tol;          /* fixed-point stopping tolerance on
+                             max|Y^k - Y^{k-1}| / max(1, |Y^k|)  (Sec. 3.3) */
+    int32_t max_iter;     /* fixed-point iterations allowed per time step */
+    int32_t precision;    /* LPIDE_FP64 or LPIDE_FP32_CONV */
+    int32_t damping;      /* 1: first step replaced by 4 steps of dt/4 with theta = 1 */
+    int32_t device;       /* HIP device ordinal */
+    void*   stream;       /* hipStream_t for all of the plan's work (NULL: null stream) */
+} lpide_opts;
+
+/* Plan-time quantities and run statistics. */
+typedef struct {
+    int32_t n, N_z, M1, M2, L;        /* grid size, z-grid half size, region bounds, FFT side */
+    int32_t N_t, n_steps;             /* time steps, entries of the step list (N_t + 3 damped) */
+    double  h, z_star;                /* mesh width, z_max^III before rounding to the z-grid */
+    double  sum_omega;                /* sum of the weights */
+    double  kappa[2], r_omega;        /* modified drift coefficients and kill rate (Sec. 3.1) */
+    double  S[3];                     /* artificial diffusion over R_I (11, 12, 22) */
+    double  a[3];                     /* sigma_omega sigma_omega^T = sigma sigma^T + S */
+    int64_t total_iters;              /* fixed-point iterations summed over the last solve */
+    int32_t max_step_iters;           /* largest per-step count in the last solve */
+    int32_t last_step_iters;
+    double  last_increment;           /* last stopping-rule value of the last solve */
+    int64_t device_bytes;             /* device memory held by the plan */
+} lpide_info;
+
+/* Default settings: the paper's scheme settings (Sec. 4) on an n x n grid over
+ * [y_lo, y_hi]^2: sl_order = in_order = 3, m1 = 2, ell_cut = 1e-14,
+ * zmax2_frac = sqrt(0.1), gl_nodes = 8. */
+void lpide_grid_default(lpide_grid* g, int32_t n, double y_lo, double y_hi);
+
+/* Defaults: tol = 1e-12, max_iter = 100, FP64, damping on, device 0, NULL stream. */
+void lpide_opts_default(lpide_opts* o);
+
+/* Fill an lpide_levy from the subordinated-Brownian-motion parameters: Brownian
+ * volatilities sigma1, sigma2 > 0 and correlation corr in (-1, 1) (rho), drifts
+ * theta1, theta2 (eta), subordinator variance kappa > 0 with unit mean, index
+ * alpha in [0, 1).  From Table 4: lambda = (1 - alpha)/kappa and
+ * delta = lambda^(1-alpha)/Gamma(1-alpha).  sigma_bs is set to 0.
+ * Returns LPIDE_E_PARAM for out-of-range input. */
+int lpide_levy_from_std(double sigma1, double sigma2, double corr, double theta1, double theta2,
+                        double kappa, double alpha, double r, lpide_levy* out);
+
+/* Build a plan: host-side discretization (z-grid sizes, weights, artificial
+ * diffusion, drift and kill rate, cell-averaged pay-off, line-solve factors,
+ * semi-Lagrangian weights) and, on the device, the kernel spectrum of the FFT
+ * correlation and all workspace.  theta in [0, 1]; M = N_t >= 1 time steps of
+ * size T / M (Sec. 3.3).  Validation errors (LPIDE_E_PARAM): n out of range,
+ * unequal axis widths, orders not in {1, 3}, alpha outside [0,1), delta,
+ * lambda, K, T <= 0, rho not positive definite, sigma_bs not positive
+ * semi-definite, lambda - eta_i - rho_ii/2 <= 0 (no exponential moment),
+ * theta outside [0, 1], tol <= 0, max_iter < 1.  *out is set only on success. */
+int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpide_payoff* payoff,
+                      double theta, int32_t M, const lpide_opts* opts, void** out);
+
+/* Release a plan and its device memory.  NULL is accepted. */
+int lpide_plan_destroy(void* plan);
+
+/* Copy the plan's quantities and the last solve's statistics to *info (host). */
+int lpide_plan_info(void* plan, lpide_info* info);
+
+/* Full march (Algorithm 1): V^0 -> V^{N_t}.  v_out: device, n*n FP64.  Returns
+ * LPIDE_E_NOCONV if some step needs more than max_iter iterations, LPIDE_E_NAN
+ * if an increment is not finite.  Synchronises the plan's stream before it
+ * returns (the per-iteration stopping rule is read back on the host). */
+int lpide_solve(void* plan, double* v_out);
+
+/* The first `steps` entries of the step list only (0 <= steps <= n_steps): the
+ * state after them, for step-by-step comparisons.  v_out: device, n*n. */
+int lpide_solve_steps(void* plan, int32_t steps, double* v_out);
+
+/* Cell-averaged initial grid V^0 (Sec. 3.2.3).  v_out: device, n*n. */
+int lpide_initial(void* plan, double* v_out);
+
+/* One application of the summation operator (B v)_m = sum_l omega_l v^in_{m+l}
+ * (Sec. 3.2.2) by the FFT correlation.  v, bv: device, n*n, must not alias. */
+int lpide_apply_B(void* plan, const double* v, double* bv);
+
+/* Prices (and deltas) at npts spot pairs by tensor-product cubic Lagrange
+ * interpolation of the grid v in y (Sec. 4): spots[2k], spots[2k+1] = (S1, S2);
+ * price[k]; delta[2k + i] = dP/dS_i (delta may be NULL).  All device pointers. */
+int lpide_price(void* plan, const double* v, int32_t npts, const double* spots,
+                double* price, double* delta);
+
+/* Host-only discretization (no device is touched): fills info (n, N_z, M1, M2,
+ * L, h, z_star, sum_omega, kappa, r_omega, S, a) and, if omega is not NULL and
+ * omega_len >= (2 N_z)^2, the weights omega[(l1 + N_z) * 2 N_z + (l2 + N_z)].
+ * payoff may be NULL; if v0 is not NULL (host, n*n) it receives V^0. */
+int lpide_discretize_host(const lpide_grid* grid, const lpide_levy* levy, const lpide_payoff* payoff,
+                          lpide_info* info, double* omega, int64_t omega_len, double* v0);
+
+/* Thread-local description of the last error on the calling thread. */
+const char* lpide_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LPIDE_H */

@@ -1,0 +1,101 @@
+"""ctypes binding of liblpide.so (include/lpide.h).  Argument marshalling only:
+every step of the time march runs in the library's HIP kernels."""
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblpide.so")
+
+LPIDE_OK = 0
+ERRORS = {-1: "LPIDE_E_PARAM", -2: "LPIDE_E_NOCONV", -3: "LPIDE_E_NAN", -4: "LPIDE_E_HIP", -5: "LPIDE_E_OOM"}
+PAYOFF = {"put_avg": 0, "call_avg": 1, "put_1": 2, "call_1": 3, "exchange": 4}
+PRECISION = {"fp64": 0, "fp32conv": 1}
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int32), ("y_lo", C.c_double * 2), ("y_hi", C.c_double * 2),
+                ("sl_order", C.c_int32), ("in_order", C.c_int32), ("m1", C.c_int32),
+                ("ell_cut", C.c_double), ("zmax2_frac", C.c_double), ("gl_nodes", C.c_int32)]
+
+
+class Levy(C.Structure):
+    _fields_ = [("r", C.c_double), ("alpha", C.c_double), ("delta", C.c_double), ("lambda_", C.c_double),
+                ("eta", C.c_double * 2), ("rho", C.c_double * 3), ("sigma_bs", C.c_double * 3),
+                ("no_jumps", C.c_int32)]
+
+
+class Payoff(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("K", C.c_double), ("T", C.c_double), ("cell_avg", C.c_int32)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
+                ("damping", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int32), ("N_z", C.c_int32), ("M1", C.c_int32), ("M2", C.c_int32), ("L", C.c_int32),
+                ("N_t", C.c_int32), ("n_steps", C.c_int32),
+                ("h", C.c_double), ("z_star", C.c_double), ("sum_omega", C.c_double),
+                ("kappa", C.c_double * 2), ("r_omega", C.c_double), ("S", C.c_double * 3), ("a", C.c_double * 3),
+                ("total_iters", C.c_int64), ("max_step_iters", C.c_int32), ("last_step_iters", C.c_int32),
+                ("last_increment", C.c_double), ("device_bytes", C.c_int64)]
+
+    def to_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+
+# exported symbol -> (restype, argtypes)
+SIGNATURES = {
+    "lpide_grid_default": (None, [C.POINTER(Grid), C.c_int32, C.c_double, C.c_double]),
+    "lpide_opts_default": (None, [C.POINTER(Opts)]),
+    "lpide_levy_from_std": (C.c_int, [C.c_double] * 8 + [C.POINTER(Levy)]),
+    "lpide_plan_create": (C.c_int, [C.POINTER(Grid), C.POINTER(Levy), C.POINTER(Payoff), C.c_double, C.c_int32,
+                                    C.POINTER(Opts), C.POINTER(C.c_void_p)]),
+    "lpide_plan_destroy": (C.c_int, [C.c_void_p]),
+    "lpide_plan_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
+    "lpide_solve": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lpide_solve_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "lpide_initial": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lpide_apply_B": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lpide_price": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lpide_discretize_host": (C.c_int, [C.POINTER(Grid), C.POINTER(Levy), C.POINTER(Payoff), C.POINTER(Info),
+                                        C.c_void_p, C.c_int64, C.c_void_p]),
+    "lpide_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+class LpideError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "error"), code, msg))
+        self.code = code
+
+
+def lib():
+    """The loaded library.  Raises if it has not been built: there is no
+    fallback implementation."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblpide.so is not built; run `python -m paper_2511_02700_amd.build` "
+                              "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != LPIDE_OK:
+        raise LpideError(rc, lib().lpide_last_error().decode(errors="replace"))
+    return rc

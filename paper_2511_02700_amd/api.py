@@ -1,0 +1,164 @@
+"""Python front end of the MI355X solver: builds the C structs, passes torch
+tensors' device pointers to the C ABI and returns torch tensors.  PyTorch is
+used for device memory and streams only; all arithmetic of the time march runs
+in the HIP kernels of liblpide.so."""
+
+import ctypes as C
+import math
+
+from . import _lib
+from ._lib import Grid, Info, Levy, Opts, Payoff, check, lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def levy_from_std(sigma1, sigma2, corr, theta1, theta2, kappa, alpha, r):
+    """NTS parameters from the subordinated-Brownian-motion form (unit-mean
+    subordinator with variance kappa); see lpide_levy_from_std."""
+    lv = Levy()
+    check(lib().lpide_levy_from_std(sigma1, sigma2, corr, theta1, theta2, kappa, alpha, r, C.byref(lv)))
+    return lv
+
+
+def levy_nts(alpha, delta, lam, eta, rho, r, sigma_bs=(0.0, 0.0, 0.0)):
+    """NTS parameters as in the paper (alpha, delta, lambda, eta, rho = (rho11, rho12, rho22))."""
+    lv = Levy()
+    lv.r, lv.alpha, lv.delta, lv.lambda_ = r, alpha, delta, lam
+    lv.eta[:] = list(eta)
+    lv.rho[:] = list(rho)
+    lv.sigma_bs[:] = list(sigma_bs)
+    return lv
+
+
+def levy_black_scholes(r, sigma_bs):
+    """Zero Levy measure with Brownian covariance sigma_bs = (s11, s12, s22)."""
+    lv = Levy()
+    lv.r = r
+    lv.sigma_bs[:] = list(sigma_bs)
+    lv.no_jumps = 1
+    return lv
+
+
+def make_grid(n, y_lo, y_hi, sl_order=3, in_order=3, **kw):
+    g = Grid()
+    lib().lpide_grid_default(C.byref(g), n, y_lo, y_hi)
+    g.sl_order, g.in_order = sl_order, in_order
+    for k, v in kw.items():
+        if k in ("y_lo", "y_hi"):
+            getattr(g, k)[:] = list(v)
+        else:
+            setattr(g, k, v)
+    return g
+
+
+def make_payoff(kind="put_avg", K=100.0, T=1.0, cell_avg=True):
+    return Payoff(_lib.PAYOFF[kind], K, T, 1 if cell_avg else 0)
+
+
+def discretize_host(grid, levy, payoff=None, want_omega=False, want_v0=False):
+    """Host-side plan quantities (no device needed): info dict, weights, V^0."""
+    import numpy as np
+    info = Info()
+    check(lib().lpide_discretize_host(C.byref(grid), C.byref(levy), None, C.byref(info), None, 0, None))
+    om = None
+    v0 = None
+    if want_omega and info.N_z > 0:
+        om = np.zeros((2 * info.N_z, 2 * info.N_z))
+    if want_v0:
+        v0 = np.zeros((grid.n, grid.n))
+    check(lib().lpide_discretize_host(
+        C.byref(grid), C.byref(levy), C.byref(payoff) if payoff is not None else None, C.byref(info),
+        om.ctypes.data_as(C.c_void_p) if om is not None else None, om.size if om is not None else 0,
+        v0.ctypes.data_as(C.c_void_p) if v0 is not None else None))
+    return info.to_dict(), om, v0
+
+
+class Plan:
+    """A planned solve on one HIP device (see lpide_plan_create)."""
+
+    def __init__(self, grid, levy, payoff, theta=0.5, M=32, tol=1e-12, max_iter=100, precision="fp64",
+                 damping=True, device=0, stream=None):
+        torch = _torch()
+        o = Opts()
+        lib().lpide_opts_default(C.byref(o))
+        o.tol, o.max_iter, o.precision, o.damping, o.device = tol, max_iter, _lib.PRECISION[precision], \
+            1 if damping else 0, device
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        o.stream = C.c_void_p(stream.cuda_stream)
+        self.grid, self.levy, self.payoff = grid, levy, payoff
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().lpide_plan_create(C.byref(grid), C.byref(levy), C.byref(payoff), theta, M, C.byref(o),
+                                          C.byref(h)))
+        self._h = h
+        self.n = grid.n
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().lpide_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        i = Info()
+        check(lib().lpide_plan_info(self._h, C.byref(i)))
+        return i.to_dict()
+
+    def _grid_tensor(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+        assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == self.n * self.n
+        return out
+
+    def solve(self, out=None):
+        out = self._grid_tensor(out)
+        check(lib().lpide_solve(self._h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def solve_steps(self, steps, out=None):
+        out = self._grid_tensor(out)
+        check(lib().lpide_solve_steps(self._h, int(steps), C.c_void_p(out.data_ptr())))
+        return out
+
+    def initial(self, out=None):
+        out = self._grid_tensor(out)
+        check(lib().lpide_initial(self._h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def apply_B(self, v, out=None):
+        torch = _torch()
+        v = v.to(self.device, torch.float64).contiguous()
+        out = self._grid_tensor(out)
+        check(lib().lpide_apply_B(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr())))
+        return out
+
+    def price(self, v, spots, with_delta=False):
+        torch = _torch()
+        sp = torch.as_tensor(spots, dtype=torch.float64).reshape(-1, 2).to(self.device).contiguous()
+        k = sp.shape[0]
+        pr = torch.empty(k, dtype=torch.float64, device=self.device)
+        dl = torch.empty((k, 2), dtype=torch.float64, device=self.device) if with_delta else None
+        check(lib().lpide_price(self._h, C.c_void_p(v.data_ptr()), k, C.c_void_p(sp.data_ptr()),
+                                C.c_void_p(pr.data_ptr()), C.c_void_p(dl.data_ptr()) if dl is not None else None))
+        return (pr, dl) if with_delta else pr
+
+
+def plan_from_workload(w, device=0, **over):
+    """A Plan for a workload dict of ``workloads.WORKLOADS`` (pure data)."""
+    m = w["model"]
+    lv = levy_from_std(m["sigma1"], m["sigma2"], m["corr"], m["theta1"], m["theta2"], m["kappa"], m["alpha"], w["r"])
+    g = make_grid(w["n"], w["y_lo"], w["y_hi"], sl_order=over.pop("sl_order", 3), in_order=over.pop("in_order", 3))
+    pay = make_payoff(w.get("payoff", "put_avg"), w["K"], w["T"])
+    return Plan(g, lv, pay, theta=w["theta"], M=w["N_t"], tol=over.pop("tol", w["tol"]), device=device, **over)

@@ -1,0 +1,71 @@
+// Host-side discretization of the two-asset exponential-Levy PIDE
+// (Moda, in 't Hout, Vanmaele, Benth, arXiv 2511.02700) on a uniform
+// log-moneyness grid.  Everything here runs once per plan, in FP64, on the CPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lpide.h"
+
+namespace lpide {
+
+// NTS Levy measure with derived constants (Sec. 4: the Bessel-K_{1+alpha} density).
+struct Nts {
+    bool   jumps = false;
+    double alpha = 0, delta = 0, lambda = 0, eta[2] = {0, 0}, rho[3] = {0, 0, 0};
+    double det = 0;          // det rho
+    double ri[3] = {0, 0, 0};// rho^{-1} (11, 12, 22)
+    double ri_eta[2] = {0, 0};
+    double c1 = 0;           // sqrt(||eta||_rho^2 + 2 lambda)
+    double nu = 1;           // 1 + alpha
+    double logpref = 0;      // log(delta/pi * sqrt(c1^(2 nu) / det))
+};
+
+// Everything a plan needs that is computed on the host.
+struct HostPlan {
+    // grid
+    int    n = 0;
+    double y_lo[2] = {0, 0}, h = 0;
+    int    sl_order = 3, in_order = 3;
+    // model
+    double r = 0, sbs[3] = {0, 0, 0};
+    Nts    nts;
+    // integral discretization (Sec. 3.1)
+    int    N_z = 0, M1 = 2, M2 = 0;
+    double z_star = 0, sum_omega = 0, kappa[2] = {0, 0}, r_omega = 0, S[3] = {0, 0, 0}, a[3] = {0, 0, 0};
+    std::vector<double> omega;   // (2 N_z)^2, omega[(l1+N_z)*2N_z + (l2+N_z)]
+    // folded correlation kernel K = omega (*) (s x s) on offsets [dlo, dhi]^2
+    int    dlo = 0, dhi = -1, L = 0;
+    std::vector<double> kern;    // (dhi-dlo+1)^2, row-major in d1
+};
+
+// Validates the model; fills the derived constants.  Returns false with a message.
+bool make_nts(const lpide_levy& lv, Nts& out, std::string& err);
+
+// log l(z) (Sec. 4); -inf where the density underflows every representation.
+double log_density(const Nts& p, double z1, double z2);
+
+// z_max^III before rounding: largest |z|_inf on {l = cut} (Sec. 4 settings).
+double z_star(const Nts& p, double cut);
+
+// Builds the discretization (grid + integral part + folded kernel); no device work.
+bool build_host_plan(const lpide_grid& g, const lpide_levy& lv, HostPlan& hp, std::string& err);
+
+// Cell-averaged initial grid (Sec. 3.2.3), row-major n x n.
+bool initial_values(const HostPlan& hp, const lpide_payoff& pay, std::vector<double>& v0, std::string& err);
+
+// Factors of T_i = I - c (1/2 a_ii [interior](d2 - d1) - 1/2 r_omega), c = dt theta, as
+// forward multipliers fl, backward scales bu and couplings bc (length n each).
+void line_factors(int n, double h, double aii, double r_omega, double c,
+                  std::vector<double>& fl, std::vector<double>& bu, std::vector<double>& bc);
+
+// Semi-Lagrangian interpolation weights along one axis: departure index j + shift,
+// order P, clamped stencil start; start[j] and w[j*(P+1) + t].
+void sl_weights(int n, double shift, int P, std::vector<int32_t>& start, std::vector<double>& w);
+
+// The (theta, dt) step list with optional damping (Sec. 3.3).
+std::vector<std::pair<double, double>> step_list(double theta, double T, int N_t, bool damping);
+
+}  // namespace lpide
