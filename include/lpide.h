@@ -188,6 +188,26 @@ int lpide_price(void* plan, const double* v, int32_t npts, const double* spots,
 int lpide_discretize_host(const lpide_grid* grid, const lpide_levy* levy, const lpide_payoff* payoff,
                           lpide_info* info, double* omega, int64_t omega_len, double* v0);
 
+/* Kernel classes for lpide_timing / lpide_kernel_stats. */
+#define LPIDE_K_ROWS_FWD   0   /* row pass: forward real FFTs of row pairs -> transposed half spectra */
+#define LPIDE_K_COLS       1   /* column pass: FFT, spectrum multiply, inverse FFT */
+#define LPIDE_K_ROWS_INV   2   /* row pass: inverse real FFTs + fused stencil epilogue */
+#define LPIDE_K_LINE_ROWS  3   /* line solves along axis 2 */
+#define LPIDE_K_LINE_COLS  4   /* line solves along axis 1 + update + stopping-rule maximum */
+#define LPIDE_K_SL         5   /* semi-Lagrangian gather + extrapolated start */
+#define LPIDE_KCLASSES     6
+
+/* Kernel timing.  With bit c of class_mask set, the plan records a pair of HIP
+ * events on its stream around every launch of kernel class c; the elapsed
+ * times are summed per class.  Each call resets the counters (after folding in
+ * pending events).  class_mask = 0 disables timing (the default). */
+int lpide_timing(void* plan, uint32_t class_mask);
+
+/* Per-class launch counts and summed durations in milliseconds since the last
+ * lpide_timing call (host arrays of LPIDE_KCLASSES entries).  Synchronises the
+ * plan's stream. */
+int lpide_kernel_stats(void* plan, int64_t* launches, double* ms);
+
 /* Thread-local description of the last error on the calling thread. */
 const char* lpide_last_error(void);
 

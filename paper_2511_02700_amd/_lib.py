@@ -11,6 +11,7 @@ LPIDE_OK = 0
 ERRORS = {-1: "LPIDE_E_PARAM", -2: "LPIDE_E_NOCONV", -3: "LPIDE_E_NAN", -4: "LPIDE_E_HIP", -5: "LPIDE_E_OOM"}
 PAYOFF = {"put_avg": 0, "call_avg": 1, "put_1": 2, "call_1": 3, "exchange": 4}
 PRECISION = {"fp64": 0, "fp32conv": 1}
+KCLASSES = ["rows_fwd", "cols", "rows_inv", "line_rows", "line_cols", "sl"]
 
 
 class Grid(C.Structure):
@@ -66,6 +67,8 @@ SIGNATURES = {
     "lpide_price": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lpide_discretize_host": (C.c_int, [C.POINTER(Grid), C.POINTER(Levy), C.POINTER(Payoff), C.POINTER(Info),
                                         C.c_void_p, C.c_int64, C.c_void_p]),
+    "lpide_timing": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "lpide_kernel_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "lpide_last_error": (C.c_char_p, []),
 }
 

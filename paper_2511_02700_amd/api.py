@@ -115,6 +115,21 @@ class Plan:
         check(lib().lpide_plan_info(self._h, C.byref(i)))
         return i.to_dict()
 
+    def set_timing(self, classes=()):
+        """Enable HIP-event timing for the named kernel classes (resets counters)."""
+        mask = 0
+        for c in classes:
+            mask |= 1 << _lib.KCLASSES.index(c)
+        check(lib().lpide_timing(self._h, mask))
+
+    def kernel_stats(self):
+        """{class: (launches, total ms)} since the last set_timing."""
+        n = len(_lib.KCLASSES)
+        la = (C.c_int64 * n)()
+        ms = (C.c_double * n)()
+        check(lib().lpide_kernel_stats(self._h, la, ms))
+        return {c: (la[i], ms[i]) for i, c in enumerate(_lib.KCLASSES)}
+
     def _grid_tensor(self, out=None):
         torch = _torch()
         if out is None:

@@ -470,11 +470,63 @@ struct Plan {
     std::vector<int> step_set;
     std::vector<std::pair<double, double>> steps;
     int P_cols = 16;
+    // kernel timing (HIP events on the plan's stream around each timed launch)
+    uint32_t time_mask = 0;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, size_t>> ev_recs;   // (kernel class, index of the start event)
+    size_t ev_used = 0;
+    int64_t k_launch[LPIDE_KCLASSES] = {};
+    double k_ms[LPIDE_KCLASSES] = {};
     // statistics of the last solve
     int64_t total_iters = 0;
     int max_step_iters = 0, last_step_iters = 0;
     double last_inc = 0;
 };
+
+// Event pair around one launch of kernel class cls (no-op unless timed).
+struct KTime {
+    Plan* p;
+    int cls;
+    bool on;
+    KTime(Plan* pl, int c);
+    ~KTime();
+};
+
+hipEvent_t next_event(Plan* p) {
+    if (p->ev_used == p->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p->ev_pool.push_back(e);
+    }
+    return p->ev_pool[p->ev_used++];
+}
+
+KTime::KTime(Plan* pl, int c) : p(pl), cls(c), on((pl->time_mask >> c) & 1u) {
+    if (!on) return;
+    const size_t idx = p->ev_used;
+    hipEvent_t a = next_event(p), b = next_event(p);
+    if (!a || !b) { on = false; return; }
+    (void)hipEventRecord(a, p->stream);
+    p->ev_recs.emplace_back(cls, idx);
+}
+KTime::~KTime() {
+    if (on) (void)hipEventRecord(p->ev_pool[p->ev_recs.back().second + 1], p->stream);
+}
+
+// Fold recorded event pairs into the per-class totals (synchronises the stream).
+int harvest_times(Plan* p) {
+    if (p->ev_recs.empty()) return LPIDE_OK;
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    for (auto& r : p->ev_recs) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[r.second], p->ev_pool[r.second + 1]));
+        p->k_launch[r.first] += 1;
+        p->k_ms[r.first] += ms;
+    }
+    p->ev_recs.clear();
+    p->ev_used = 0;
+    return LPIDE_OK;
+}
 
 template <typename Tp>
 int dalloc(Plan* p, Tp** out, size_t count) {
@@ -508,9 +560,16 @@ StencilArgs stencil_of(const Plan* p) {
 template <int L>
 void launch_conv(Plan* p, const double* Y, int epi, const AffineArgs& aa, double* out) {
     const int n = p->hp.n, np = (n + 1) / 2;
-    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, p->stream, Y, n, n, n, p->X, n, p->tw);
-    hipLaunchKernelGGL((k_cols<L, 0>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, p->X, n, n, n, p->spec,
-                       (double2*)nullptr, 0.0, p->tw);
+    {
+        KTime t(p, LPIDE_K_ROWS_FWD);
+        hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, p->stream, Y, n, n, n, p->X, n, p->tw);
+    }
+    {
+        KTime t(p, LPIDE_K_COLS);
+        hipLaunchKernelGGL((k_cols<L, 0>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, p->X, n, n, n, p->spec,
+                           (double2*)nullptr, 0.0, p->tw);
+    }
+    KTime t(p, LPIDE_K_ROWS_INV);
     if (epi == 0)
         hipLaunchKernelGGL((k_rows_inv<L, 0>), dim3(np), dim3(L / 8), 0, p->stream, p->X, n, n, out, aa, p->tw);
     else
@@ -577,6 +636,7 @@ int apply_affine(Plan* p, const double* P0, const double* U, double* out, double
     aa.st = stencil_of(p);
     if (p->jumps) return dispatch_conv(p, U, 1, aa, out);
     const int n = p->hp.n;
+    KTime t(p, LPIDE_K_ROWS_INV);
     hipLaunchKernelGGL(k_affine_noB, dim3((n + 255) / 256, n), dim3(256), 0, p->stream, aa);
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
@@ -585,8 +645,12 @@ int apply_affine(Plan* p, const double* P0, const double* U, double* out, double
 int line_solves(Plan* p, const StepSet& s, double* R, double* Y) {
     const int n = p->hp.n;
     const size_t rows_lds = sizeof(double) * (size_t)(((n + 256 + 1) & ~1)) + sizeof(double2) * 512;
-    hipLaunchKernelGGL(k_line_rows, dim3(n), dim3(256), rows_lds, p->stream, R, n, s.fl2, s.bu2, s.bc2);
+    {
+        KTime t(p, LPIDE_K_LINE_ROWS);
+        hipLaunchKernelGGL(k_line_rows, dim3(n), dim3(256), rows_lds, p->stream, R, n, s.fl2, s.bu2, s.bc2);
+    }
     const int P = p->P_cols;
+    KTime t(p, LPIDE_K_LINE_COLS);
     hipLaunchKernelGGL((k_line_cols<true>), dim3((n + 15) / 16), dim3(16 * P), sizeof(double2) * 2 * 16 * P,
                        p->stream, R, n, P, s.fl1, s.bu1, s.bc1, Y, p->err_d);
     HIP_TRY(hipGetLastError());
@@ -597,6 +661,7 @@ int sl_extrap(Plan* p, const StepSet& s, const double* E, double* W, const doubl
               double* Y0) {
     const int n = p->hp.n;
     dim3 grid((n + 127) / 128, n);
+    KTime t(p, LPIDE_K_SL);
     if (p->hp.sl_order == 1)
         hipLaunchKernelGGL((k_sl_extrap<1>), grid, dim3(128), 0, p->stream, E, W, n, s.s1, s.w1, s.s2, s.w2, H[0],
                            H[1], H[2], H[3], c[0], c[1], c[2], c[3], Y0);
@@ -609,6 +674,8 @@ int sl_extrap(Plan* p, const StepSet& s, const double* E, double* W, const doubl
 
 void destroy(Plan* p) {
     if (!p) return;
+    (void)hipStreamSynchronize(p->stream);
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     for (void* a : p->allocs) (void)hipFree(a);
     if (p->err_h) (void)hipHostFree(p->err_h);
     delete p;
@@ -982,6 +1049,31 @@ int lpide_price(void* plan, const double* v, int32_t npts, const double* spots, 
     hipLaunchKernelGGL(k_price, dim3((npts + 127) / 128), dim3(128), 0, p->stream, v, p->hp.n, p->hp.y_lo[0],
                        p->hp.y_lo[1], p->hp.h, p->pay.K, npts, spots, price, delta);
     HIP_TRY(hipGetLastError());
+    return LPIDE_OK;
+}
+
+int lpide_timing(void* plan, uint32_t class_mask) {
+    if (!plan) return fail(LPIDE_E_PARAM, "NULL argument");
+    Plan* p = static_cast<Plan*>(plan);
+    int rc = harvest_times(p);
+    if (rc) return rc;
+    p->time_mask = class_mask & ((1u << LPIDE_KCLASSES) - 1u);
+    for (int c = 0; c < LPIDE_KCLASSES; ++c) {
+        p->k_launch[c] = 0;
+        p->k_ms[c] = 0.0;
+    }
+    return LPIDE_OK;
+}
+
+int lpide_kernel_stats(void* plan, int64_t* launches, double* ms) {
+    if (!plan || !launches || !ms) return fail(LPIDE_E_PARAM, "NULL argument");
+    Plan* p = static_cast<Plan*>(plan);
+    int rc = harvest_times(p);
+    if (rc) return rc;
+    for (int c = 0; c < LPIDE_KCLASSES; ++c) {
+        launches[c] = p->k_launch[c];
+        ms[c] = p->k_ms[c];
+    }
     return LPIDE_OK;
 }
 
