@@ -189,12 +189,12 @@ int lpide_discretize_host(const lpide_grid* grid, const lpide_levy* levy, const 
                           lpide_info* info, double* omega, int64_t omega_len, double* v0);
 
 /* Kernel classes for lpide_timing / lpide_kernel_stats. */
-#define LPIDE_K_ROWS_FWD   0   /* row pass: forward real FFTs of row pairs -> transposed half spectra */
-#define LPIDE_K_COLS       1   /* column pass: FFT, spectrum multiply, inverse FFT */
-#define LPIDE_K_ROWS_INV   2   /* row pass: inverse real FFTs + fused stencil epilogue */
-#define LPIDE_K_LINE_ROWS  3   /* line solves along axis 2 */
-#define LPIDE_K_LINE_COLS  4   /* line solves along axis 1 + update + stopping-rule maximum */
-#define LPIDE_K_SL         5   /* semi-Lagrangian gather + extrapolated start */
+#define LPIDE_K_COLS       0   /* column pass of B Y: FFT, spectrum multiply, inverse FFT */
+#define LPIDE_K_ROWS_INV   1   /* row inverse FFTs + fused residual / explicit-part stencil */
+#define LPIDE_K_LINE_COLS  2   /* line solves along axis 1 */
+#define LPIDE_K_LINE_ROWS  3   /* line solves along axis 2 + update + stopping rule + row FFT of Y */
+#define LPIDE_K_SL         4   /* semi-Lagrangian gather + extrapolated start + row FFT of Y^0 */
+#define LPIDE_K_STEP_END   5   /* end-of-step control (convergence verdict, history rotation) */
 #define LPIDE_KCLASSES     6
 
 /* Kernel timing.  With bit c of class_mask set, the plan records a pair of HIP

@@ -28,16 +28,6 @@ struct StencilArgs {
     double h, a11, a12, a22;
 };
 
-// out = P0 + c (D U + BU - r_omega U) + c0 U  (explicit part: P0 = U = V, c0 = 0;
-// fixed-point residual: P0 = W, U = Y, c0 = -1).
-struct AffineArgs {
-    const double* P0;
-    const double* U;
-    double*       out;
-    double        c, c0, r_omega;
-    StencilArgs   st;
-};
-
 // Bijective block -> work-item remap that gives each of the 8 XCDs (which
 // receive blocks round-robin) a contiguous range of work items.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {

@@ -25,6 +25,7 @@
 #include "host_plan.hpp"
 #include "kernels.hpp"
 #include "lpide.h"
+#include "step_kernels.hpp"
 
 using namespace lpide;
 
@@ -129,11 +130,10 @@ __global__ __launch_bounds__(L / 8) void k_cols(double2* __restrict__ X, int ldx
 }
 
 // Inverse real FFT of row pairs from the transposed half spectra; keeps the
-// first n columns.  EPI 0: out = result.  EPI 1: affine stencil epilogue.
-template <int L, int EPI>
+// first n columns: row a <- real part, row b <- imaginary part.
+template <int L>
 __global__ __launch_bounds__(L / 8) void k_rows_inv(const double2* __restrict__ X, int ldx, int n,
-                                                   double* __restrict__ out, AffineArgs aa,
-                                                   const double2* __restrict__ tw) {
+                                                   double* __restrict__ out, const double2* __restrict__ tw) {
     constexpr int T = L / 8;
     __shared__ double2 lds[L];
     const int np = (n + 1) >> 1;
@@ -159,228 +159,9 @@ __global__ __launch_bounds__(L / 8) void k_rows_inv(const double2* __restrict__ 
     for (int e = 0; e < 8; ++e) {
         const int j = tid + e * T;
         if (j >= n) continue;
-        if constexpr (EPI == 0) {
-            out[(size_t)ra * n + j] = reg[e].x;
-            if (hasb) out[(size_t)rb * n + j] = reg[e].y;
-        } else {
-            {
-                const size_t o = (size_t)ra * n + j;
-                const double u = aa.U[o];
-                const double d = apply_D(aa.U, aa.st, ra, j, u);
-                aa.out[o] = aa.P0[o] + aa.c * (d + reg[e].x - aa.r_omega * u) + aa.c0 * u;
-            }
-            if (hasb) {
-                const size_t o = (size_t)rb * n + j;
-                const double u = aa.U[o];
-                const double d = apply_D(aa.U, aa.st, rb, j, u);
-                aa.out[o] = aa.P0[o] + aa.c * (d + reg[e].y - aa.r_omega * u) + aa.c0 * u;
-            }
-        }
+        out[(size_t)ra * n + j] = reg[e].x;
+        if (hasb) out[(size_t)rb * n + j] = reg[e].y;
     }
-}
-
-// Affine stencil form without the correlation (zero Levy measure).
-__global__ void k_affine_noB(AffineArgs aa) {
-    const int n = aa.st.n;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    if (j >= n) return;
-    const size_t o = (size_t)i * n + j;
-    const double u = aa.U[o];
-    const double d = apply_D(aa.U, aa.st, i, j, u);
-    aa.out[o] = aa.P0[o] + aa.c * (d - aa.r_omega * u) + aa.c0 * u;
-}
-
-// ---------------------------------------------------------------------------
-// Line solves T x = r with constant factors (forward multipliers fl, backward
-// scales bu and couplings bc):  y_i = r_i + fl_i y_{i-1};  x_i = bu_i y_i + bc_i x_{i+1}.
-// Each line is cut into P chunks of m consecutive elements, one per thread.
-// A chunk solves its recurrence locally from a zero carry, the carries between
-// chunks follow from a scan of the chunks' affine maps y_out = G y_in + B, and
-// a fix-up adds the carried-in value times the running product of the
-// multipliers.  Exact up to rounding (no truncation of the coupling).
-// ---------------------------------------------------------------------------
-constexpr int LINE_MM = 32;   // max chunk length held in registers
-
-// Exclusive scan of affine maps over t = 0..P-1 within groups of P threads
-// (group g uses slots [g*P, g*P+P) of buf, 2 * groups * P entries).  Returns the
-// carried-in value y_in(t) = (M_{t-1} o ... o M_0)(0).
-__device__ __forceinline__ double scan_affine(double G, double B, int g, int t, int P, double2* buf) {
-    double2* cur = buf;
-    double2* nxt = buf + blockDim.x;
-    const int s = g * P + t;
-    cur[s] = make_double2(G, B);
-    __syncthreads();
-    for (int d = 1; d < P; d <<= 1) {
-        double2 me = cur[s];
-        if (t >= d) {
-            const double2 pr = cur[s - d];
-            me = make_double2(me.x * pr.x, me.x * pr.y + me.y);
-        }
-        nxt[s] = me;
-        __syncthreads();
-        double2* tmp = cur;
-        cur = nxt;
-        nxt = tmp;
-    }
-    const double carry = t > 0 ? cur[s - 1].y : 0.0;
-    __syncthreads();
-    return carry;
-}
-
-// Solve one chunk (elements idx(k), k < m, of a line whose factor index is
-// i0 + k) given its carries.  x[] holds r on entry and the solution on exit.
-__device__ __forceinline__ void chunk_solve(double (&x)[LINE_MM], int i0, int m, int g, int t, int P,
-                                            const double* __restrict__ fl, const double* __restrict__ bu,
-                                            const double* __restrict__ bc, double2* buf) {
-    // forward: local pass from a zero carry
-    double y = 0.0, G = 1.0;
-#pragma unroll
-    for (int k = 0; k < LINE_MM; ++k) {
-        if (k < m) {
-            const double f = fl[i0 + k];
-            y = x[k] + f * y;
-            G *= f;
-            x[k] = y;
-        }
-    }
-    const double yin = scan_affine(G, y, g, t, P, buf);
-    double gp = 1.0;
-#pragma unroll
-    for (int k = 0; k < LINE_MM; ++k) {
-        if (k < m) {
-            gp *= fl[i0 + k];
-            x[k] += gp * yin;
-        }
-    }
-    // backward: local pass from a zero carry, scanned in reverse chunk order
-    double xh = 0.0, H = 1.0;
-#pragma unroll
-    for (int k = LINE_MM - 1; k >= 0; --k) {
-        if (k < m) {
-            const double c = bc[i0 + k];
-            xh = bu[i0 + k] * x[k] + c * xh;
-            H *= c;
-            x[k] = xh;
-        }
-    }
-    const double xin = scan_affine(H, xh, g, P - 1 - t, P, buf);
-    double hp = 1.0;
-#pragma unroll
-    for (int k = LINE_MM - 1; k >= 0; --k) {
-        if (k < m) {
-            hp *= bc[i0 + k];
-            x[k] += hp * xin;
-        }
-    }
-}
-
-// Axis 2 (rows, contiguous): one row per block of 256 threads, staged through
-// LDS with one padding slot per chunk so the chunk reads avoid bank conflicts.
-__global__ __launch_bounds__(256) void k_line_rows(double* __restrict__ U, int n, const double* __restrict__ fl,
-                                                  const double* __restrict__ bu,
-                                                  const double* __restrict__ bc) {
-    extern __shared__ double smem[];
-    const int P = blockDim.x;
-    const int m = (n + P - 1) / P;
-    double* row = smem;                                   // n + P slots
-    double2* buf = reinterpret_cast<double2*>(smem + ((n + P + 1) & ~1));   // 2P entries
-    const int r = xcd_remap(blockIdx.x, gridDim.x);
-    double* u = U + (size_t)r * n;
-    const int tid = threadIdx.x;
-    for (int i = tid; i < n; i += P) row[i + i / m] = u[i];
-    __syncthreads();
-    const int s = tid * m;
-    const int cnt = max(0, min(m, n - s));
-    double x[LINE_MM];
-#pragma unroll
-    for (int k = 0; k < LINE_MM; ++k) x[k] = k < cnt ? row[s + k + tid] : 0.0;
-    chunk_solve(x, s, cnt, 0, tid, P, fl, bu, bc, buf);
-#pragma unroll
-    for (int k = 0; k < LINE_MM; ++k)
-        if (k < cnt) row[s + k + tid] = x[k];
-    __syncthreads();
-    for (int i = tid; i < n; i += P) u[i] = row[i + i / m];
-}
-
-// Axis 1 (columns, stride n): a block covers 16 adjacent columns x P chunks
-// (thread = column + 16 * chunk, so a wave reads 4 rows x 128 contiguous bytes).
-// UPDATE: Y += x and the stopping-rule maximum max |x| / max(1, |Y_new|).
-template <bool UPDATE>
-__global__ __launch_bounds__(1024) void k_line_cols(double* __restrict__ U, int n, int P,
-                                                   const double* __restrict__ fl,
-                                                   const double* __restrict__ bu,
-                                                   const double* __restrict__ bc, double* __restrict__ Y,
-                                                   unsigned long long* __restrict__ err) {
-    extern __shared__ double2 sbuf[];
-    const int c = threadIdx.x & 15, t = threadIdx.x >> 4;
-    const int col = blockIdx.x * 16 + c;
-    const bool valid = col < n;
-    const int m = (n + P - 1) / P;
-    const int s = t * m;
-    const int cnt = valid ? max(0, min(m, n - s)) : 0;
-    double x[LINE_MM];
-#pragma unroll
-    for (int k = 0; k < LINE_MM; ++k) x[k] = k < cnt ? U[(size_t)(s + k) * n + col] : 0.0;
-    chunk_solve(x, s, cnt, c, t, P, fl, bu, bc, sbuf);
-    // chunk_solve groups threads by g = c with slots g*P + t: consistent for all threads
-    if constexpr (!UPDATE) {
-#pragma unroll
-        for (int k = 0; k < LINE_MM; ++k)
-            if (k < cnt) U[(size_t)(s + k) * n + col] = x[k];
-    } else {
-        double emax = 0.0;
-#pragma unroll
-        for (int k = 0; k < LINE_MM; ++k) {
-            if (k < cnt) {
-                const size_t o = (size_t)(s + k) * n + col;
-                const double yn = Y[o] + x[k];
-                Y[o] = yn;
-                const double e = fabs(x[k]) / fmax(1.0, fabs(yn));
-                emax = (e > emax || e != e) ? e : emax;
-            }
-        }
-        // wave reduction, then one atomic per wave (bit patterns of non-negative
-        // doubles order like the values; NaN sorts above +inf)
-        for (int off = 32; off > 0; off >>= 1) {
-            const double o = __shfl_xor(emax, off);
-            emax = (o > emax || o != o) ? o : emax;
-        }
-        if ((threadIdx.x & 63) == 0) atomicMax(err, (unsigned long long)__double_as_longlong(emax));
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Semi-Lagrangian gather W = (T_1 (x) T_2) E with per-node stencil starts and
-// weights, fused with the extrapolated start Y0 = sum_k c_k H_k.
-// ---------------------------------------------------------------------------
-template <int P>
-__global__ void k_sl_extrap(const double* __restrict__ E, double* __restrict__ W, int n,
-                            const int* __restrict__ s1, const double* __restrict__ w1,
-                            const int* __restrict__ s2, const double* __restrict__ w2,
-                            const double* __restrict__ H0, const double* __restrict__ H1,
-                            const double* __restrict__ H2, const double* __restrict__ H3, double c0,
-                            double c1, double c2, double c3, double* __restrict__ Y0) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    if (j >= n) return;
-    const int a0 = s1[i], b0 = s2[j];
-    double acc = 0.0;
-#pragma unroll
-    for (int a = 0; a <= P; ++a) {
-        const double* er = E + (size_t)(a0 + a) * n + b0;
-        double ra = 0.0;
-#pragma unroll
-        for (int b = 0; b <= P; ++b) ra += w2[j * (P + 1) + b] * er[b];
-        acc += w1[i * (P + 1) + a] * ra;
-    }
-    const size_t o = (size_t)i * n + j;
-    W[o] = acc;
-    double y = c0 * H0[o];
-    if (H1) y += c1 * H1[o];
-    if (H2) y += c2 * H2[o];
-    if (H3) y += c3 * H3[o];
-    Y0[o] = y;
 }
 
 // Prices and deltas at spot pairs: tensor cubic Lagrange in y with the clamped
@@ -432,19 +213,11 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, siz
     if (i < cnt) b[i] = a[i];
 }
 
-__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
 
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
 namespace {
-
-struct StepSet {
-    double theta = 0, dt = 0;
-    double *fl1 = nullptr, *bu1 = nullptr, *bc1 = nullptr, *fl2 = nullptr, *bu2 = nullptr, *bc2 = nullptr;
-    int *s1 = nullptr, *s2 = nullptr;
-    double *w1 = nullptr, *w2 = nullptr;
-};
 
 struct Plan {
     HostPlan hp;
@@ -453,7 +226,8 @@ struct Plan {
     double theta = 0.5;
     int N_t = 1;
     hipStream_t stream = nullptr;
-    int L = 0;
+    int L = 0;        // FFT side (0 without jumps)
+    int Lr = 0;       // threads x 8 of the row-pair kernels (L, or a power of two >= n without jumps)
     bool jumps = false;
     std::vector<void*> allocs;
     int64_t bytes = 0;
@@ -461,14 +235,20 @@ struct Plan {
     double2* spec = nullptr;
     double2* X = nullptr;
     double* V0 = nullptr;
-    double* pool[6] = {};
+    double* pool[POOL] = {};
     double* Wb = nullptr;
     double* Rb = nullptr;
-    unsigned long long* err_d = nullptr;
-    double* err_h = nullptr;
-    std::vector<StepSet> sets;
+    Ctl* ctl = nullptr;
+    Ctl* ctl_h = nullptr;          // pinned mirror for the host checks
+    int* counts = nullptr;         // per-step iteration counts (device)
+    double* incs = nullptr;
+    std::vector<int> counts_h;
+    std::vector<double> incs_h;
+    StepDesc* sets_d = nullptr;
+    int* step_set_d = nullptr;
+    std::vector<StepDesc> sets;
     std::vector<int> step_set;
-    std::vector<std::pair<double, double>> steps;
+    int n_steps = 0;
     int P_cols = 16;
     // kernel timing (HIP events on the plan's stream around each timed launch)
     uint32_t time_mask = 0;
@@ -486,8 +266,8 @@ struct Plan {
 // Event pair around one launch of kernel class cls (no-op unless timed).
 struct KTime {
     Plan* p;
-    int cls;
     bool on;
+    size_t idx = 0;
     KTime(Plan* pl, int c);
     ~KTime();
 };
@@ -501,16 +281,16 @@ hipEvent_t next_event(Plan* p) {
     return p->ev_pool[p->ev_used++];
 }
 
-KTime::KTime(Plan* pl, int c) : p(pl), cls(c), on((pl->time_mask >> c) & 1u) {
+KTime::KTime(Plan* pl, int c) : p(pl), on((pl->time_mask >> c) & 1u) {
     if (!on) return;
-    const size_t idx = p->ev_used;
+    idx = p->ev_used;
     hipEvent_t a = next_event(p), b = next_event(p);
     if (!a || !b) { on = false; return; }
     (void)hipEventRecord(a, p->stream);
-    p->ev_recs.emplace_back(cls, idx);
+    p->ev_recs.emplace_back(c, idx);
 }
 KTime::~KTime() {
-    if (on) (void)hipEventRecord(p->ev_pool[p->ev_recs.back().second + 1], p->stream);
+    if (on) (void)hipEventRecord(p->ev_pool[idx + 1], p->stream);
 }
 
 // Fold recorded event pairs into the per-class totals (synchronises the stream).
@@ -557,23 +337,37 @@ StencilArgs stencil_of(const Plan* p) {
     return s;
 }
 
+MarchArgs march_args(const Plan* p) {
+    MarchArgs a;
+    a.ctl = p->ctl;
+    for (int b = 0; b < POOL; ++b) a.pool[b] = p->pool[b];
+    a.sets = p->sets_d;
+    a.step_set = p->step_set_d;
+    a.n = p->hp.n;
+    a.n_sub = p->opts.damping ? 4 : 1;
+    a.damping = p->opts.damping ? 1 : 0;
+    a.P_cols = p->P_cols;
+    a.W = p->Wb;
+    a.R = p->Rb;
+    a.X = p->X;
+    a.spec = p->spec;
+    a.tw = p->tw;
+    a.counts = p->counts;
+    a.incs = p->incs;
+    a.tol = p->opts.tol;
+    a.r_omega = p->hp.r_omega;
+    a.st = stencil_of(p);
+    return a;
+}
+
+// ---- standalone correlation (apply_B) and plan-time spectrum ----
 template <int L>
-void launch_conv(Plan* p, const double* Y, int epi, const AffineArgs& aa, double* out) {
+void launch_conv(Plan* p, const double* Y, double* out) {
     const int n = p->hp.n, np = (n + 1) / 2;
-    {
-        KTime t(p, LPIDE_K_ROWS_FWD);
-        hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, p->stream, Y, n, n, n, p->X, n, p->tw);
-    }
-    {
-        KTime t(p, LPIDE_K_COLS);
-        hipLaunchKernelGGL((k_cols<L, 0>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, p->X, n, n, n, p->spec,
-                           (double2*)nullptr, 0.0, p->tw);
-    }
-    KTime t(p, LPIDE_K_ROWS_INV);
-    if (epi == 0)
-        hipLaunchKernelGGL((k_rows_inv<L, 0>), dim3(np), dim3(L / 8), 0, p->stream, p->X, n, n, out, aa, p->tw);
-    else
-        hipLaunchKernelGGL((k_rows_inv<L, 1>), dim3(np), dim3(L / 8), 0, p->stream, p->X, n, n, out, aa, p->tw);
+    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, p->stream, Y, n, n, n, p->X, n, p->tw);
+    hipLaunchKernelGGL((k_cols<L, 0>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, p->X, n, n, n, p->spec,
+                       (double2*)nullptr, 0.0, p->tw);
+    hipLaunchKernelGGL((k_rows_inv<L>), dim3(np), dim3(L / 8), 0, p->stream, p->X, n, n, out, p->tw);
 }
 
 template <int L>
@@ -584,90 +378,116 @@ void launch_spectrum(Plan* p, const double* G, double2* Xfull) {
                        (const double2*)nullptr, p->spec, scale, p->tw);
 }
 
-int dispatch_conv(Plan* p, const double* Y, int epi, const AffineArgs& aa, double* out) {
-    switch (p->L) {
-        case 64: launch_conv<64>(p, Y, epi, aa, out); break;
-        case 128: launch_conv<128>(p, Y, epi, aa, out); break;
-        case 256: launch_conv<256>(p, Y, epi, aa, out); break;
-        case 512: launch_conv<512>(p, Y, epi, aa, out); break;
-        case 1024: launch_conv<1024>(p, Y, epi, aa, out); break;
-        case 2048: launch_conv<2048>(p, Y, epi, aa, out); break;
-        case 4096: launch_conv<4096>(p, Y, epi, aa, out); break;
-        case 8192: launch_conv<8192>(p, Y, epi, aa, out); break;
-        default: return fail(LPIDE_E_PARAM, "unsupported FFT side");
+template <int L>
+void launch_rows_fwd(Plan* p, const double* Y) {
+    const int n = p->hp.n;
+    hipLaunchKernelGGL((k_rows_fwd<L>), dim3((n + 1) / 2), dim3(L / 8), 0, p->stream, Y, n, n, n, p->X, n, p->tw);
+}
+
+// ---- one time step of the device-controlled march ----
+template <int L, bool FFT>
+void launch_iteration(Plan* p, const MarchArgs& a, int k) {
+    const int n = p->hp.n, np = (n + 1) / 2;
+    if (FFT) {
+        {
+            KTime t(p, LPIDE_K_COLS);
+            hipLaunchKernelGGL((ks_cols<L>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, a, k);
+        }
+        KTime t(p, LPIDE_K_ROWS_INV);
+        hipLaunchKernelGGL((ks_rows_inv<L, false>), dim3(np), dim3(L / 8), 0, p->stream, a, k);
+    } else {
+        KTime t(p, LPIDE_K_ROWS_INV);
+        hipLaunchKernelGGL((ks_affine_noB<false>), dim3((n + 255) / 256, n), dim3(256), 0, p->stream, a, k);
     }
+    {
+        KTime t(p, LPIDE_K_LINE_COLS);
+        const int P = p->P_cols;
+        hipLaunchKernelGGL(ks_line_cols, dim3((n + 3) / 4), dim3(4 * P), sizeof(double2) * 2 * 4 * P, p->stream, a,
+                           k);
+    }
+    KTime t(p, LPIDE_K_LINE_ROWS);
+    hipLaunchKernelGGL((ks_line_rows<L, FFT>), dim3(np), dim3(L / 8), 0, p->stream, a, k);
+}
+
+template <int L, bool FFT>
+void launch_step(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
+    const int n = p->hp.n, np = (n + 1) / 2;
+    if (explicit_part) {
+        if (FFT) {
+            {
+                KTime t(p, LPIDE_K_COLS);
+                hipLaunchKernelGGL((ks_cols<L>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, a, 0);
+            }
+            KTime t(p, LPIDE_K_ROWS_INV);
+            hipLaunchKernelGGL((ks_rows_inv<L, true>), dim3(np), dim3(L / 8), 0, p->stream, a, 0);
+        } else {
+            KTime t(p, LPIDE_K_ROWS_INV);
+            hipLaunchKernelGGL((ks_affine_noB<true>), dim3((n + 255) / 256, n), dim3(256), 0, p->stream, a, 0);
+        }
+    }
+    {
+        KTime t(p, LPIDE_K_SL);
+        if (p->hp.sl_order == 1)
+            hipLaunchKernelGGL((ks_sl<L, 1, FFT>), dim3(np), dim3(L / 8), 0, p->stream, a);
+        else
+            hipLaunchKernelGGL((ks_sl<L, 3, FFT>), dim3(np), dim3(L / 8), 0, p->stream, a);
+    }
+    for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT>(p, a, k);
+    KTime t(p, LPIDE_K_STEP_END);
+    hipLaunchKernelGGL(ks_step_end, dim3(1), dim3(64), 0, p->stream, a, kmax);
+}
+
+#define LPIDE_SWITCH_L(Lv, FFTv, CALL)                                                   \
+    switch (Lv) {                                                                       \
+        case 64: CALL(64, FFTv); break;                                                 \
+        case 128: CALL(128, FFTv); break;                                               \
+        case 256: CALL(256, FFTv); break;                                               \
+        case 512: CALL(512, FFTv); break;                                               \
+        case 1024: CALL(1024, FFTv); break;                                             \
+        case 2048: CALL(2048, FFTv); break;                                             \
+        case 4096: CALL(4096, FFTv); break;                                             \
+        case 8192: CALL(8192, FFTv); break;                                             \
+        default: return fail(LPIDE_E_PARAM, "unsupported transform size");              \
+    }
+
+int issue_step(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
+#define CALL_STEP(Lc, Fc) launch_step<Lc, Fc>(p, a, explicit_part, kmax)
+    if (p->jumps) { LPIDE_SWITCH_L(p->Lr, true, CALL_STEP) }
+    else { LPIDE_SWITCH_L(p->Lr, false, CALL_STEP) }
+#undef CALL_STEP
+    HIP_TRY(hipGetLastError());
+    return LPIDE_OK;
+}
+
+int issue_iteration(Plan* p, const MarchArgs& a, int k) {
+#define CALL_IT(Lc, Fc) launch_iteration<Lc, Fc>(p, a, k)
+    if (p->jumps) { LPIDE_SWITCH_L(p->Lr, true, CALL_IT) }
+    else { LPIDE_SWITCH_L(p->Lr, false, CALL_IT) }
+#undef CALL_IT
+    HIP_TRY(hipGetLastError());
+    return LPIDE_OK;
+}
+
+int dispatch_conv(Plan* p, const double* Y, double* out) {
+#define CALL_CONV(Lc, Fc) launch_conv<Lc>(p, Y, out)
+    LPIDE_SWITCH_L(p->L, true, CALL_CONV)
+#undef CALL_CONV
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
 }
 
 int dispatch_spectrum(Plan* p, const double* G, double2* Xfull) {
-    switch (p->L) {
-        case 64: launch_spectrum<64>(p, G, Xfull); break;
-        case 128: launch_spectrum<128>(p, G, Xfull); break;
-        case 256: launch_spectrum<256>(p, G, Xfull); break;
-        case 512: launch_spectrum<512>(p, G, Xfull); break;
-        case 1024: launch_spectrum<1024>(p, G, Xfull); break;
-        case 2048: launch_spectrum<2048>(p, G, Xfull); break;
-        case 4096: launch_spectrum<4096>(p, G, Xfull); break;
-        case 8192: launch_spectrum<8192>(p, G, Xfull); break;
-        default: return fail(LPIDE_E_PARAM, "unsupported FFT side");
-    }
+#define CALL_SPEC(Lc, Fc) launch_spectrum<Lc>(p, G, Xfull)
+    LPIDE_SWITCH_L(p->L, true, CALL_SPEC)
+#undef CALL_SPEC
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
 }
 
-// P (chunks per column) so that a chunk holds at most LINE_MM elements.
-// At least 4 chunks, so a block has at least one full wave of 64 lanes.
-int cols_chunks(int n) {
-    int P = 4;
-    while ((n + P - 1) / P > LINE_MM) P *= 2;
-    return P;
-}
-
-// (B Y) with the chosen epilogue; for a zero Levy measure only the stencil form.
-int apply_affine(Plan* p, const double* P0, const double* U, double* out, double c, double c0) {
-    AffineArgs aa;
-    aa.P0 = P0;
-    aa.U = U;
-    aa.out = out;
-    aa.c = c;
-    aa.c0 = c0;
-    aa.r_omega = p->hp.r_omega;
-    aa.st = stencil_of(p);
-    if (p->jumps) return dispatch_conv(p, U, 1, aa, out);
-    const int n = p->hp.n;
-    KTime t(p, LPIDE_K_ROWS_INV);
-    hipLaunchKernelGGL(k_affine_noB, dim3((n + 255) / 256, n), dim3(256), 0, p->stream, aa);
-    HIP_TRY(hipGetLastError());
-    return LPIDE_OK;
-}
-
-int line_solves(Plan* p, const StepSet& s, double* R, double* Y) {
-    const int n = p->hp.n;
-    const size_t rows_lds = sizeof(double) * (size_t)(((n + 256 + 1) & ~1)) + sizeof(double2) * 512;
-    {
-        KTime t(p, LPIDE_K_LINE_ROWS);
-        hipLaunchKernelGGL(k_line_rows, dim3(n), dim3(256), rows_lds, p->stream, R, n, s.fl2, s.bu2, s.bc2);
-    }
-    const int P = p->P_cols;
-    KTime t(p, LPIDE_K_LINE_COLS);
-    hipLaunchKernelGGL((k_line_cols<true>), dim3((n + 15) / 16), dim3(16 * P), sizeof(double2) * 2 * 16 * P,
-                       p->stream, R, n, P, s.fl1, s.bu1, s.bc1, Y, p->err_d);
-    HIP_TRY(hipGetLastError());
-    return LPIDE_OK;
-}
-
-int sl_extrap(Plan* p, const StepSet& s, const double* E, double* W, const double* const H[4], const double c[4],
-              double* Y0) {
-    const int n = p->hp.n;
-    dim3 grid((n + 127) / 128, n);
-    KTime t(p, LPIDE_K_SL);
-    if (p->hp.sl_order == 1)
-        hipLaunchKernelGGL((k_sl_extrap<1>), grid, dim3(128), 0, p->stream, E, W, n, s.s1, s.w1, s.s2, s.w2, H[0],
-                           H[1], H[2], H[3], c[0], c[1], c[2], c[3], Y0);
-    else
-        hipLaunchKernelGGL((k_sl_extrap<3>), grid, dim3(128), 0, p->stream, E, W, n, s.s1, s.w1, s.s2, s.w2, H[0],
-                           H[1], H[2], H[3], c[0], c[1], c[2], c[3], Y0);
+int dispatch_rows_fwd(Plan* p, const double* Y) {
+#define CALL_RF(Lc, Fc) launch_rows_fwd<Lc>(p, Y)
+    LPIDE_SWITCH_L(p->L, true, CALL_RF)
+#undef CALL_RF
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
 }
@@ -677,100 +497,109 @@ void destroy(Plan* p) {
     (void)hipStreamSynchronize(p->stream);
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     for (void* a : p->allocs) (void)hipFree(a);
-    if (p->err_h) (void)hipHostFree(p->err_h);
+    if (p->ctl_h) (void)hipHostFree(p->ctl_h);
     delete p;
 }
 
+// Read the control block and the per-step statistics of steps [s0, s1).
+int read_back(Plan* p, int s0, int s1) {
+    HIP_TRY(hipMemcpyAsync(p->ctl_h, p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
+    if (s1 > s0) {
+        HIP_TRY(hipMemcpyAsync(p->counts_h.data() + s0, p->counts + s0, sizeof(int) * (s1 - s0),
+                               hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(hipMemcpyAsync(p->incs_h.data() + s0, p->incs + s0, sizeof(double) * (s1 - s0),
+                               hipMemcpyDeviceToHost, p->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return LPIDE_OK;
+}
+
+double bits_d(unsigned long long b) {
+    double d;
+    std::memcpy(&d, &b, sizeof d);
+    return d;
+}
+
 // March the first `count` entries of the step list from V^0; result in v_out.
+// Steps are enqueued in batches without waiting; each step launches kmax
+// iterations (a running prediction), of which those after convergence exit at
+// once.  A step that needs more is completed by extra iterations enqueued one
+// at a time after the batch (the steps behind it were no-ops).
 int march(Plan* p, int count, double* v_out) {
     const int n = p->hp.n;
     const size_t N = (size_t)n * n;
+    const MarchArgs a = march_args(p);
     p->total_iters = 0;
     p->max_step_iters = 0;
     p->last_step_iters = 0;
     p->last_inc = 0;
-    // buffer roles: hist[0..hc) newest first; vsub = state inside the damped block
-    int hist[4], hc = 0, vsub = -1;
-    auto in_use = [&](int b) {
-        for (int k = 0; k < hc; ++k)
-            if (hist[k] == b) return true;
-        return b == vsub;
-    };
-    auto grab = [&]() {
-        for (int b = 0; b < 6; ++b)
-            if (!in_use(b)) return b;
-        return -1;
-    };
     hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, p->stream, p->V0, p->pool[0], N);
-    hist[0] = 0;
-    hc = 1;
-    const int n_sub = p->opts.damping ? 4 : 1;
-    for (int s = 0; s < count; ++s) {
-        const StepSet& ss = p->sets[p->step_set[s]];
-        const double th = ss.theta, dt = ss.dt;
-        const bool damped = p->opts.damping && s < n_sub;
-        const int start = (damped && vsub >= 0) ? vsub : hist[0];
-        const double* Vs = p->pool[start];
-        // explicit part into Rb (skipped for theta = 1)
-        const double* E = Vs;
-        if (th < 1.0) {
-            int rc = apply_affine(p, Vs, Vs, p->Rb, dt * (1.0 - th), 0.0);
-            if (rc) return rc;
-            E = p->Rb;
-        }
-        // starting value
-        const int yb = grab();
-        if (yb < 0) return fail(LPIDE_E_PARAM, "internal: no free grid buffer");
-        double* Y = p->pool[yb];
-        const double* H[4] = {Vs, nullptr, nullptr, nullptr};
-        double c[4] = {1.0, 0.0, 0.0, 0.0};
-        if (!damped) {
-            for (int k = 0; k < hc; ++k) H[k] = p->pool[hist[k]];
-            if (hc == 2) { c[0] = 2; c[1] = -1; }
-            else if (hc == 3) { c[0] = 3; c[1] = -3; c[2] = 1; }
-            else if (hc >= 4) { c[0] = 4; c[1] = -6; c[2] = 4; c[3] = -1; }
-        }
-        int rc = sl_extrap(p, ss, E, p->Wb, H, c, Y);
+    if (p->jumps) {
+        int rc = dispatch_rows_fwd(p, p->pool[0]);
         if (rc) return rc;
-        // fixed-point iteration
-        int k = 0;
-        double errv = 0;
-        for (;;) {
-            ++k;
-            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, p->stream, p->err_d);
-            rc = apply_affine(p, p->Wb, Y, p->Rb, dt * th, -1.0);
-            if (rc) return rc;
-            rc = line_solves(p, ss, p->Rb, Y);
-            if (rc) return rc;
-            HIP_TRY(hipMemcpyAsync(p->err_h, p->err_d, sizeof(double), hipMemcpyDeviceToHost, p->stream));
-            HIP_TRY(hipStreamSynchronize(p->stream));
-            errv = *p->err_h;
-            if (!std::isfinite(errv)) {
-                return fail(LPIDE_E_NAN, "non-finite fixed-point increment in step " + std::to_string(s));
-            }
-            if (errv < p->opts.tol) break;
-            if (k >= p->opts.max_iter) {
-                char buf[160];
-                snprintf(buf, sizeof buf, "fixed point not converged in step %d after %d iterations (increment %.3e)",
-                         s, k, errv);
-                return fail(LPIDE_E_NOCONV, buf);
-            }
-        }
-        p->total_iters += k;
-        p->max_step_iters = std::max(p->max_step_iters, k);
-        p->last_step_iters = k;
-        p->last_inc = errv;
-        // bookkeeping of the history (main steps) and the damped sub-step state
-        if (damped && s < n_sub - 1) {
-            vsub = yb;
-        } else {
-            vsub = -1;
-            for (int q = std::min(hc, 3); q > 0; --q) hist[q] = hist[q - 1];
-            hist[0] = yb;
-            hc = std::min(hc + 1, 4);
-        }
     }
-    const int last = (vsub >= 0) ? vsub : hist[0];
+    hipLaunchKernelGGL(ks_init, dim3(1), dim3(64), 0, p->stream, a);
+    HIP_TRY(hipGetLastError());
+    const int nsets = int(p->sets.size());
+    std::vector<int> kpred(nsets, std::min(8, p->opts.max_iter));
+    std::vector<int> kused(count, 0);
+    const int batch = 32;
+    int done = 0;
+    while (done < count) {
+        const int s1 = std::min(count, done + batch);
+        for (int s = done; s < s1; ++s) {
+            const int id = p->step_set[s];
+            kused[s] = kpred[id];
+            int rc = issue_step(p, a, p->sets[id].theta < 1.0, kpred[id]);
+            if (rc) return rc;
+        }
+        int rc = read_back(p, done, s1);
+        if (rc) return rc;
+        if (p->ctl_h->fail) {
+            const int sf = p->ctl_h->fail_step;
+            int k = kused[sf];
+            for (;;) {
+                double ek = bits_d(p->ctl_h->err[k]);
+                if (!std::isfinite(ek)) return fail(LPIDE_E_NAN, "non-finite fixed-point increment in step " +
+                                                                     std::to_string(sf));
+                if (k >= p->opts.max_iter) {
+                    char buf[160];
+                    snprintf(buf, sizeof buf, "fixed point not converged in step %d after %d iterations (increment %.3e)",
+                             sf, k, ek);
+                    return fail(LPIDE_E_NOCONV, buf);
+                }
+                ++k;
+                hipLaunchKernelGGL(ks_clear_fail, dim3(1), dim3(64), 0, p->stream, a);
+                rc = issue_iteration(p, a, k);
+                if (rc) return rc;
+                hipLaunchKernelGGL(ks_step_end, dim3(1), dim3(64), 0, p->stream, a, k);
+                HIP_TRY(hipGetLastError());
+                rc = read_back(p, sf, sf + 1);
+                if (rc) return rc;
+                if (!p->ctl_h->fail) break;
+            }
+            kused[sf] = k;
+            kpred[p->step_set[sf]] = std::min(p->opts.max_iter, k);
+        }
+        const int reached = p->ctl_h->step;
+        // next prediction per set: the largest count among this batch's completed steps
+        for (int id = 0; id < nsets; ++id) {
+            int mx = 0;
+            for (int s = done; s < reached; ++s)
+                if (p->step_set[s] == id) mx = std::max(mx, p->counts_h[s]);
+            if (mx > 0) kpred[id] = std::min(p->opts.max_iter, mx);
+        }
+        done = reached;
+    }
+    for (int s = 0; s < count; ++s) {
+        p->total_iters += p->counts_h[s];
+        p->max_step_iters = std::max(p->max_step_iters, p->counts_h[s]);
+    }
+    if (count > 0) {
+        p->last_step_iters = p->counts_h[count - 1];
+        p->last_inc = p->incs_h[count - 1];
+    }
+    const int last = count > 0 ? p->ctl_h->cur : 0;   // V^0 sits in pool[0] before any step
     hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, p->stream, p->pool[last], v_out, N);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(p->stream));
@@ -870,6 +699,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     if (M < 1) return fail(LPIDE_E_PARAM, "M (time steps) must be >= 1");
     if (!(o.tol > 0.0) || o.max_iter < 1) return fail(LPIDE_E_PARAM, "tol must be > 0 and max_iter >= 1");
     if (o.precision != LPIDE_FP64) return fail(LPIDE_E_PARAM, "precision mode not available");
+    if (o.max_iter > MAX_ITER_CAP) return fail(LPIDE_E_PARAM, "max_iter must not exceed 128");
     Plan* p = new Plan();
     std::string err;
     if (!build_host_plan(*grid, *levy, p->hp, err)) { delete p; return fail(LPIDE_E_PARAM, err); }
@@ -894,44 +724,63 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     const int n = p->hp.n;
     const size_t N = (size_t)n * n;
     if ((rc = upload(p, &p->V0, v0))) return bail(rc);
-    for (int b = 0; b < 6; ++b)
+    for (int b = 0; b < POOL; ++b)
         if ((rc = dalloc(p, &p->pool[b], N))) return bail(rc);
     if ((rc = dalloc(p, &p->Wb, N))) return bail(rc);
     if ((rc = dalloc(p, &p->Rb, N))) return bail(rc);
-    if ((rc = dalloc(p, &p->err_d, 1))) return bail(rc);
-    if (hipHostMalloc((void**)&p->err_h, sizeof(double), hipHostMallocDefault) != hipSuccess)
+    if ((rc = dalloc(p, &p->ctl, 1))) return bail(rc);
+    if (hipHostMalloc((void**)&p->ctl_h, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
         return bail(fail(LPIDE_E_OOM, "hipHostMalloc failed"));
-    p->P_cols = cols_chunks(n);
-    if (16 * p->P_cols > 1024) return bail(fail(LPIDE_E_PARAM, "n too large for the column line solve"));
+    // axis-1 line solves: 4 columns per block, chunks of about 8 rows
+    p->P_cols = 16;
+    while (p->P_cols < 256 && (n + p->P_cols - 1) / p->P_cols > 8) p->P_cols *= 2;
+    if ((n + p->P_cols - 1) / p->P_cols > LINE_MM) return bail(fail(LPIDE_E_PARAM, "n too large for the line solves"));
+    // threads x 8 of the row-pair kernels
+    p->Lr = p->L;
+    if (!p->jumps) {
+        p->Lr = 64;
+        while (p->Lr < n) p->Lr *= 2;
+    }
+    if (p->Lr > 8192) return bail(fail(LPIDE_E_PARAM, "n too large"));
     // step list and its distinct (theta, dt) sets
-    p->steps = step_list(theta, payoff->T, M, o.damping != 0);
-    for (auto& st : p->steps) {
-        int id = -1;
-        for (size_t q = 0; q < p->sets.size(); ++q)
-            if (p->sets[q].theta == st.first && p->sets[q].dt == st.second) id = int(q);
-        if (id < 0) {
-            StepSet ss;
-            ss.theta = st.first;
-            ss.dt = st.second;
-            const double c = ss.dt * ss.theta;
-            std::vector<double> fl, bu, bc;
-            line_factors(n, p->hp.h, p->hp.a[0], p->hp.r_omega, c, fl, bu, bc);
-            if ((rc = upload(p, &ss.fl1, fl)) || (rc = upload(p, &ss.bu1, bu)) || (rc = upload(p, &ss.bc1, bc)))
-                return bail(rc);
-            line_factors(n, p->hp.h, p->hp.a[2], p->hp.r_omega, c, fl, bu, bc);
-            if ((rc = upload(p, &ss.fl2, fl)) || (rc = upload(p, &ss.bu2, bu)) || (rc = upload(p, &ss.bc2, bc)))
-                return bail(rc);
-            std::vector<int32_t> st1, st2;
-            std::vector<double> w1, w2;
-            sl_weights(n, p->hp.kappa[0] * ss.dt / p->hp.h, p->hp.sl_order, st1, w1);
-            sl_weights(n, p->hp.kappa[1] * ss.dt / p->hp.h, p->hp.sl_order, st2, w2);
-            if ((rc = upload(p, &ss.s1, st1)) || (rc = upload(p, &ss.s2, st2)) || (rc = upload(p, &ss.w1, w1)) ||
-                (rc = upload(p, &ss.w2, w2)))
-                return bail(rc);
-            p->sets.push_back(ss);
-            id = int(p->sets.size()) - 1;
+    {
+        auto steps = step_list(theta, payoff->T, M, o.damping != 0);
+        p->n_steps = int(steps.size());
+        for (auto& st : steps) {
+            int id = -1;
+            for (size_t q = 0; q < p->sets.size(); ++q)
+                if (p->sets[q].theta == st.first && p->sets[q].dt == st.second) id = int(q);
+            if (id < 0) {
+                StepDesc sd{};
+                sd.theta = st.first;
+                sd.dt = st.second;
+                const double c = sd.dt * sd.theta;
+                std::vector<double> fl, bu, bc;
+                double *f1, *u1, *c1, *f2, *u2, *c2, *w1, *w2;
+                int *s1, *s2;
+                line_factors(n, p->hp.h, p->hp.a[0], p->hp.r_omega, c, fl, bu, bc);
+                if ((rc = upload(p, &f1, fl)) || (rc = upload(p, &u1, bu)) || (rc = upload(p, &c1, bc))) return bail(rc);
+                line_factors(n, p->hp.h, p->hp.a[2], p->hp.r_omega, c, fl, bu, bc);
+                if ((rc = upload(p, &f2, fl)) || (rc = upload(p, &u2, bu)) || (rc = upload(p, &c2, bc))) return bail(rc);
+                std::vector<int32_t> st1, st2;
+                std::vector<double> ww1, ww2;
+                sl_weights(n, p->hp.kappa[0] * sd.dt / p->hp.h, p->hp.sl_order, st1, ww1);
+                sl_weights(n, p->hp.kappa[1] * sd.dt / p->hp.h, p->hp.sl_order, st2, ww2);
+                if ((rc = upload(p, &s1, st1)) || (rc = upload(p, &s2, st2)) || (rc = upload(p, &w1, ww1)) ||
+                    (rc = upload(p, &w2, ww2)))
+                    return bail(rc);
+                sd.fl1 = f1; sd.bu1 = u1; sd.bc1 = c1;
+                sd.fl2 = f2; sd.bu2 = u2; sd.bc2 = c2;
+                sd.s1 = s1; sd.s2 = s2; sd.w1 = w1; sd.w2 = w2;
+                p->sets.push_back(sd);
+                id = int(p->sets.size()) - 1;
+            }
+            p->step_set.push_back(id);
         }
-        p->step_set.push_back(id);
+        if ((rc = upload(p, &p->sets_d, p->sets)) || (rc = upload(p, &p->step_set_d, p->step_set))) return bail(rc);
+        if ((rc = dalloc(p, &p->counts, p->n_steps)) || (rc = dalloc(p, &p->incs, p->n_steps))) return bail(rc);
+        p->counts_h.assign(p->n_steps, 0);
+        p->incs_h.assign(p->n_steps, 0.0);
     }
     // kernel spectrum conj(FFT(K placed at d mod L)) / L^2
     if (p->jumps) {
@@ -988,7 +837,7 @@ int lpide_plan_info(void* plan, lpide_info* info) {
     info->M2 = p->hp.M2;
     info->L = p->L;
     info->N_t = p->N_t;
-    info->n_steps = int32_t(p->steps.size());
+    info->n_steps = int32_t(p->n_steps);
     info->h = p->hp.h;
     info->z_star = p->hp.z_star;
     info->sum_omega = p->hp.sum_omega;
@@ -1010,13 +859,13 @@ int lpide_plan_info(void* plan, lpide_info* info) {
 int lpide_solve(void* plan, double* v_out) {
     if (!plan || !v_out) return fail(LPIDE_E_PARAM, "NULL argument");
     Plan* p = static_cast<Plan*>(plan);
-    return march(p, int(p->steps.size()), v_out);
+    return march(p, p->n_steps, v_out);
 }
 
 int lpide_solve_steps(void* plan, int32_t steps, double* v_out) {
     if (!plan || !v_out) return fail(LPIDE_E_PARAM, "NULL argument");
     Plan* p = static_cast<Plan*>(plan);
-    if (steps < 0 || steps > int(p->steps.size())) return fail(LPIDE_E_PARAM, "steps out of range");
+    if (steps < 0 || steps > p->n_steps) return fail(LPIDE_E_PARAM, "steps out of range");
     return march(p, steps, v_out);
 }
 
@@ -1037,8 +886,7 @@ int lpide_apply_B(void* plan, const double* v, double* bv) {
         HIP_TRY(hipMemsetAsync(bv, 0, sizeof(double) * (size_t)p->hp.n * p->hp.n, p->stream));
         return LPIDE_OK;
     }
-    AffineArgs aa{};
-    return dispatch_conv(p, v, 0, aa, bv);
+    return dispatch_conv(p, v, bv);
 }
 
 int lpide_price(void* plan, const double* v, int32_t npts, const double* spots, double* price, double* delta) {

@@ -1,0 +1,430 @@
+// Device-controlled time steps (Sec. 3.3, Algorithm 1) for gfx950.
+//
+// The host enqueues whole time steps without waiting: every step is
+//   [explicit part: cols + rows_inv(explicit)]        (theta < 1 only)
+//   sl        W = T^SL E, Y^0, and the row FFT of Y^0
+//   kmax x {  cols          column pass of B Y (spectrum multiply)
+//             rows_inv      R = W + dt theta ((D - r_omega) Y + B Y) - Y
+//             line_cols     R <- T_1^{-1} R                 (axis 1)
+//             line_rows     delta = T_2^{-1} R; Y += delta; err_k; row FFT of Y }
+//   step_end  first k with err_k < tol; rotate the history; set up the next step
+// Iteration k's kernels return at once when err_{k-1} < tol (the step has
+// converged) or when a step failed to converge within its kmax iterations
+// (then everything after it is a no-op until the host has added iterations).
+// All buffers are addressed through a control block updated only by step_end,
+// so the same launch sequence serves every step of a kind.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft.hpp"
+#include "kernels.hpp"
+#include "linesolve.hpp"
+
+namespace lpide {
+
+constexpr int KSLOTS = 136;          // err[0] (sentinel) + up to 128 iterations per step
+constexpr int MAX_ITER_CAP = 128;
+constexpr int POOL = 6;               // grid buffers: history (4) + start state + iterate
+
+struct Ctl {
+    int step;                         // completed entries of the step list
+    int fail;                         // current step not converged within its launched iterations
+    int fail_step;
+    int pad0;
+    int cur;                          // pool index of the state the current step starts from
+    int y;                            // pool index of the iterate
+    int hc;                           // history length (main steps)
+    int nsrc;                         // terms of the starting-value combination
+    int hist[4];                      // pool indices, newest first
+    int src[4];
+    double coef[4];                   // Y^0 = sum_q coef[q] pool[src[q]]
+    unsigned long long err[KSLOTS];   // stopping-rule value after iteration k (bit pattern)
+};
+
+struct StepDesc {
+    double theta, dt;
+    const double *fl1, *bu1, *bc1;    // axis-1 line factors of I - dt theta A_1
+    const double *fl2, *bu2, *bc2;    // axis-2 line factors
+    const int *s1, *s2;               // semi-Lagrangian stencil starts per axis
+    const double *w1, *w2;            // semi-Lagrangian weights per axis
+};
+
+struct MarchArgs {
+    Ctl* ctl;
+    double* pool[POOL];
+    const StepDesc* sets;
+    const int* step_set;
+    int n, n_sub, damping, P_cols;
+    double* W;
+    double* R;
+    double2* X;
+    const double2* spec;
+    const double2* tw;
+    int* counts;
+    double* incs;
+    double tol, r_omega;
+    StencilArgs st;
+};
+
+__device__ __forceinline__ double bits_to_d(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// Uniform early-exit test of iteration k (k = 0: parts that run once per step).
+__device__ __forceinline__ bool halted(const MarchArgs& a, int k) {
+    const Ctl* c = a.ctl;
+    if (c->fail) return true;
+    return k > 0 && bits_to_d(c->err[k - 1]) < a.tol;
+}
+
+__device__ __forceinline__ const StepDesc& cur_set(const MarchArgs& a) { return a.sets[a.step_set[a.ctl->step]]; }
+
+// Column pass of B Y on the intermediate X (transposed half spectra).
+template <int L>
+__global__ __launch_bounds__(L / 8) void ks_cols(MarchArgs a, int k) {
+    if (halted(a, k)) return;
+    constexpr int T = L / 8;
+    __shared__ double2 lds[L];
+    const int n = a.n, col = blockIdx.x, tid = threadIdx.x;
+    double2* xc = a.X + (size_t)col * n;
+    double2 reg[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int idx = tid + e * T;
+        reg[e] = idx < n ? xc[idx] : make_double2(0.0, 0.0);
+    }
+    fft_block<L, false>(reg, lds, a.tw);
+    const double2* sc = a.spec + (size_t)col * L;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) reg[e] = cmul(reg[e], sc[tid + e * T]);
+    fft_block<L, true>(reg, lds, a.tw);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int idx = tid + e * T;
+        if (idx < n) xc[idx] = reg[e];
+    }
+}
+
+// Row inverse FFT of the pairs (2p, 2p+1) with the affine stencil epilogue:
+// EXPLICIT: out = V + dt(1-theta)((D - r_omega) V + B V)   (into R)
+// else:     out = W + dt theta((D - r_omega) Y + B Y) - Y  (into R)
+template <int L, bool EXPLICIT>
+__global__ __launch_bounds__(L / 8) void ks_rows_inv(MarchArgs a, int k) {
+    if (halted(a, k)) return;
+    constexpr int T = L / 8;
+    __shared__ double2 lds[L];
+    const int n = a.n, np = (n + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, np);
+    const int ra = 2 * p, rb = 2 * p + 1;
+    const bool hasb = rb < n;
+    const int tid = threadIdx.x;
+    double2 reg[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int idx = tid + e * T;
+        const bool lo = idx <= L / 2;
+        const int kk = lo ? idx : L - idx;
+        const double2* xk = a.X + (size_t)kk * n;
+        double2 ha = xk[ra];
+        double2 hb = hasb ? xk[rb] : make_double2(0.0, 0.0);
+        if (kk == 0 || kk == L / 2) { ha.y = 0.0; hb.y = 0.0; }
+        reg[e] = lo ? make_double2(ha.x - hb.y, ha.y + hb.x) : make_double2(ha.x + hb.y, hb.x - ha.y);
+    }
+    fft_block<L, true>(reg, lds, a.tw);
+    const StepDesc& sd = cur_set(a);
+    const double* U = EXPLICIT ? a.pool[a.ctl->cur] : a.pool[a.ctl->y];
+    const double* P0 = EXPLICIT ? U : a.W;
+    const double c = EXPLICIT ? sd.dt * (1.0 - sd.theta) : sd.dt * sd.theta;
+    const double c0 = EXPLICIT ? 0.0 : -1.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int j = tid + e * T;
+        if (j >= n) continue;
+        {
+            const size_t o = (size_t)ra * n + j;
+            const double u = U[o];
+            const double d = apply_D(U, a.st, ra, j, u);
+            a.R[o] = P0[o] + c * (d + reg[e].x - a.r_omega * u) + c0 * u;
+        }
+        if (hasb) {
+            const size_t o = (size_t)rb * n + j;
+            const double u = U[o];
+            const double d = apply_D(U, a.st, rb, j, u);
+            a.R[o] = P0[o] + c * (d + reg[e].y - a.r_omega * u) + c0 * u;
+        }
+    }
+}
+
+// The same affine forms without the correlation (zero Levy measure).
+template <bool EXPLICIT>
+__global__ void ks_affine_noB(MarchArgs a, int k) {
+    if (halted(a, k)) return;
+    const int n = a.n;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= n) return;
+    const StepDesc& sd = cur_set(a);
+    const double* U = EXPLICIT ? a.pool[a.ctl->cur] : a.pool[a.ctl->y];
+    const double* P0 = EXPLICIT ? U : a.W;
+    const double c = EXPLICIT ? sd.dt * (1.0 - sd.theta) : sd.dt * sd.theta;
+    const double c0 = EXPLICIT ? 0.0 : -1.0;
+    const size_t o = (size_t)i * n + j;
+    const double u = U[o];
+    const double d = apply_D(U, a.st, i, j, u);
+    a.R[o] = P0[o] + c * (d - a.r_omega * u) + c0 * u;
+}
+
+// Forward FFT of the row pair held in reg (canonical layout) into the
+// transposed half spectra X[k2 * n + row].
+template <int L>
+__device__ __forceinline__ void rows_fwd_store(double2 (&reg)[8], double2* lds, const double2* __restrict__ tw,
+                                               double2* __restrict__ X, int n, int ra, bool hasb) {
+    constexpr int T = L / 8;
+    const int tid = threadIdx.x;
+    __syncthreads();
+    fft_block<L, false>(reg, lds, tw);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) lds[tid + e * T] = reg[e];
+    __syncthreads();
+    for (int kk = tid; kk <= L / 2; kk += T) {
+        const double2 z = lds[kk], w = lds[(L - kk) & (L - 1)];
+        double2* xk = X + (size_t)kk * n;
+        xk[ra] = make_double2(0.5 * (z.x + w.x), 0.5 * (z.y - w.y));
+        if (hasb) xk[ra + 1] = make_double2(0.5 * (z.y + w.y), -0.5 * (z.x - w.x));
+    }
+}
+
+// Semi-Lagrangian gather W = (T_1 (x) T_2) E (order P), starting value Y^0 into
+// the iterate buffer, and (FFT) the row transform of Y^0; one row pair per block.
+template <int L, int P, bool FFT>
+__global__ __launch_bounds__(L / 8) void ks_sl(MarchArgs a) {
+    if (halted(a, 0)) return;
+    constexpr int T = L / 8;
+    __shared__ double2 lds[FFT ? L : 1];
+    const int n = a.n, np = (n + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, np);
+    const int ra = 2 * p, rb = 2 * p + 1;
+    const bool hasb = rb < n;
+    const int tid = threadIdx.x;
+    const Ctl* c = a.ctl;
+    const StepDesc& sd = cur_set(a);
+    const double* E = sd.theta < 1.0 ? a.R : a.pool[c->cur];
+    double* Y = a.pool[c->y];
+    const int nsrc = c->nsrc;
+    const double* H[4];
+    double cf[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        H[q] = a.pool[c->src[q]];
+        cf[q] = c->coef[q];
+    }
+    double2 reg[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int j = tid + e * T;
+        double y0[2] = {0.0, 0.0};
+        if (j < n) {
+            const int b0 = sd.s2[j];
+            double w2[P + 1];
+#pragma unroll
+            for (int b = 0; b <= P; ++b) w2[b] = sd.w2[j * (P + 1) + b];
+            for (int r = 0; r < 2; ++r) {
+                const int i = ra + r;
+                if (r == 1 && !hasb) break;
+                const int a0 = sd.s1[i];
+                double acc = 0.0;
+#pragma unroll
+                for (int aa = 0; aa <= P; ++aa) {
+                    const double* er = E + (size_t)(a0 + aa) * n + b0;
+                    double s = 0.0;
+#pragma unroll
+                    for (int b = 0; b <= P; ++b) s += w2[b] * er[b];
+                    acc += sd.w1[i * (P + 1) + aa] * s;
+                }
+                const size_t o = (size_t)i * n + j;
+                a.W[o] = acc;
+                double yv = 0.0;
+                for (int q = 0; q < nsrc; ++q) yv += cf[q] * H[q][o];
+                Y[o] = yv;
+                y0[r] = yv;
+            }
+        }
+        reg[e] = make_double2(y0[0], y0[1]);
+    }
+    if constexpr (FFT) rows_fwd_store<L>(reg, lds, a.tw, a.X, n, ra, hasb);
+}
+
+// Axis-1 line solves R <- T_1^{-1} R: 4 adjacent columns x P chunks per block.
+__global__ __launch_bounds__(1024) void ks_line_cols(MarchArgs a, int k) {
+    if (halted(a, k)) return;
+    extern __shared__ double2 sbuf[];
+    const int n = a.n, P = a.P_cols;
+    const int c = threadIdx.x & 3, t = threadIdx.x >> 2;
+    const int col = xcd_remap(blockIdx.x, gridDim.x) * 4 + c;
+    const int m = (n + P - 1) / P;
+    const int s = t * m;
+    const int cnt = col < n ? max(0, min(m, n - s)) : 0;
+    const StepDesc& sd = cur_set(a);
+    double x[LINE_MM];
+#pragma unroll
+    for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? a.R[(size_t)(s + q) * n + col] : 0.0;
+    chunk_solve(x, s, cnt, c, t, P, blockDim.x, sd.fl1, sd.bu1, sd.bc1, sbuf);
+#pragma unroll
+    for (int q = 0; q < LINE_MM; ++q)
+        if (q < cnt) a.R[(size_t)(s + q) * n + col] = x[q];
+}
+
+// Axis-2 line solves of a row pair, the update Y += delta, the stopping-rule
+// maximum err_k = max |delta| / max(1, |Y|), and (FFT) the row transform of the
+// updated Y for the next iteration.
+template <int L, bool FFT>
+__global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
+    if (halted(a, k)) return;
+    constexpr int T = L / 8, PR = T / 2;
+    // union: row buffer 2 (n + PR + 1) doubles | scan buffer 2T double2 | FFT buffer L double2
+    __shared__ double2 lds[L + L / 16 + 2];
+    double* rows = reinterpret_cast<double*>(lds);
+    const int n = a.n, np = (n + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, np);
+    const int ra = 2 * p, rb = 2 * p + 1;
+    const bool hasb = rb < n;
+    const int tid = threadIdx.x;
+    const int m = (n + PR - 1) / PR;
+    const int stride = n + PR + 1;
+    const StepDesc& sd = cur_set(a);
+    for (int i = tid; i < n; i += T) {
+        rows[i + i / m] = a.R[(size_t)ra * n + i];
+        if (hasb) rows[stride + i + i / m] = a.R[(size_t)rb * n + i];
+    }
+    __syncthreads();
+    const int r = tid / PR, ch = tid % PR;
+    const int s = ch * m;
+    const int cnt = (r == 1 && !hasb) ? 0 : max(0, min(m, n - s));
+    double x[LINE_MM];
+#pragma unroll
+    for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? rows[r * stride + s + q + ch] : 0.0;
+    __syncthreads();
+    chunk_solve(x, s, cnt, r, ch, PR, T, sd.fl2, sd.bu2, sd.bc2, lds);
+#pragma unroll
+    for (int q = 0; q < LINE_MM; ++q)
+        if (q < cnt) rows[r * stride + s + q + ch] = x[q];
+    __syncthreads();
+    double* Y = a.pool[a.ctl->y];
+    double emax = 0.0;
+    double2 reg[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int j = tid + e * T;
+        double ya = 0.0, yb = 0.0;
+        if (j < n) {
+            const double da = rows[j + j / m];
+            const size_t oa = (size_t)ra * n + j;
+            ya = Y[oa] + da;
+            Y[oa] = ya;
+            double ev = fabs(da) / fmax(1.0, fabs(ya));
+            emax = (ev > emax || ev != ev) ? ev : emax;
+            if (hasb) {
+                const double db = rows[stride + j + j / m];
+                const size_t ob = (size_t)rb * n + j;
+                yb = Y[ob] + db;
+                Y[ob] = yb;
+                ev = fabs(db) / fmax(1.0, fabs(yb));
+                emax = (ev > emax || ev != ev) ? ev : emax;
+            }
+        }
+        reg[e] = make_double2(ya, yb);
+    }
+    // wave maximum over the block's active lanes (T may be below 64), one atomic
+    // per wave (non-negative doubles order like their bit patterns; NaN sorts
+    // above +inf)
+    constexpr int WL = T < 64 ? T : 64;
+#pragma unroll
+    for (int off = WL / 2; off > 0; off >>= 1) {
+        const double o = __shfl_xor(emax, off, WL);
+        emax = (o > emax || o != o) ? o : emax;
+    }
+    if ((tid & 63) == 0) atomicMax(&a.ctl->err[k], (unsigned long long)__double_as_longlong(emax));
+    if constexpr (FFT) rows_fwd_store<L>(reg, lds, a.tw, a.X, n, ra, hasb);
+}
+
+// End of a step: convergence verdict, history rotation, next starting value.
+__global__ void ks_step_end(MarchArgs a, int kmax) {
+    Ctl* c = a.ctl;
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        ok = 0;
+        if (!c->fail) {
+            const int s = c->step;
+            int kk = 0;
+            for (int q = 1; q <= kmax; ++q)
+                if (bits_to_d(c->err[q]) < a.tol) { kk = q; break; }
+            if (kk == 0) {
+                c->fail = 1;
+                c->fail_step = s;
+            } else {
+                ok = 1;
+                a.counts[s] = kk;
+                a.incs[s] = bits_to_d(c->err[kk]);
+                const bool inner_sub = a.damping && s < a.n_sub - 1;
+                if (inner_sub) {
+                    c->cur = c->y;                        // next damped sub-step starts here
+                } else {
+                    for (int q = 3; q > 0; --q) c->hist[q] = c->hist[q - 1];
+                    c->hist[0] = c->y;
+                    c->hc = c->hc < 4 ? c->hc + 1 : 4;
+                    c->cur = c->y;
+                }
+                int fr = -1;
+                for (int b = 0; b < POOL && fr < 0; ++b) {
+                    bool used = b == c->cur;
+                    for (int q = 0; q < c->hc; ++q) used = used || b == c->hist[q];
+                    if (!used) fr = b;
+                }
+                c->y = fr;
+                const int s2 = s + 1;
+                c->step = s2;
+                for (int q = 0; q < 4; ++q) { c->src[q] = c->hist[q]; c->coef[q] = 0.0; }
+                if (a.damping && s2 < a.n_sub) {
+                    c->nsrc = 1;
+                    c->src[0] = c->cur;
+                    c->coef[0] = 1.0;
+                } else {
+                    c->nsrc = c->hc;
+                    if (c->hc == 1) { c->coef[0] = 1.0; }
+                    else if (c->hc == 2) { c->coef[0] = 2.0; c->coef[1] = -1.0; }
+                    else if (c->hc == 3) { c->coef[0] = 3.0; c->coef[1] = -3.0; c->coef[2] = 1.0; }
+                    else { c->coef[0] = 4.0; c->coef[1] = -6.0; c->coef[2] = 4.0; c->coef[3] = -1.0; }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (ok) {
+        for (int q = threadIdx.x; q < KSLOTS; q += blockDim.x)
+            c->err[q] = q == 0 ? (unsigned long long)0x7FF0000000000000ull : 0ull;
+    }
+}
+
+// Control block at the start of a march: V^0 in pool[0], iterate in pool[1].
+__global__ void ks_init(MarchArgs a) {
+    Ctl* c = a.ctl;
+    for (int q = threadIdx.x; q < KSLOTS; q += blockDim.x)
+        c->err[q] = q == 0 ? (unsigned long long)0x7FF0000000000000ull : 0ull;
+    if (threadIdx.x == 0) {
+        c->step = 0;
+        c->fail = 0;
+        c->fail_step = -1;
+        c->cur = 0;
+        c->y = 1;
+        c->hc = 1;
+        c->nsrc = 1;
+        for (int q = 0; q < 4; ++q) { c->hist[q] = 0; c->src[q] = 0; c->coef[q] = 0.0; }
+        c->coef[0] = 1.0;
+    }
+}
+
+__global__ void ks_clear_fail(MarchArgs a) {
+    if (threadIdx.x == 0) a.ctl->fail = 0;
+}
+
+}  // namespace lpide

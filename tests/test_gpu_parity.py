@@ -179,3 +179,27 @@ def test_fv512_full_march_properties(lp):
     assert np.all(np.diff(p1) < 0)
     info = plan.info()
     assert info["n_steps"] == 259 and info["total_iters"] > 0
+
+
+def test_tight_tolerance_uses_extra_iterations(lp):
+    """tol = 1e-14 needs more fixed-point iterations than the first prediction
+    in some steps: those steps are completed by host-added iterations and the
+    result still matches the oracle."""
+    _note("tight tol nig64 n=40")
+    w = workloads.workload("nig64", n=40, N_t=8, y_lo=-2.5, y_hi=2.5)
+    plan = lp.plan_from_workload(w, tol=1e-14)
+    Vg = plan.solve().cpu().numpy()
+    Vo, iters = scheme.solve(_oracle_problem(w), tol=1e-14)
+    assert _rel(Vg, Vo) < 1e-12
+    assert plan.info()["max_step_iters"] >= 2
+
+
+def test_non_convergence_is_reported(lp):
+    """max_iter too small for tol: the march stops with LPIDE_E_NOCONV (forced
+    from the host; every kernel still runs to completion)."""
+    _note("forced non-convergence")
+    w = workloads.workload("nig64", n=40, N_t=8, y_lo=-2.5, y_hi=2.5)
+    plan = lp.plan_from_workload(w, tol=1e-15, max_iter=2)
+    with pytest.raises(lp.LpideError) as ei:
+        plan.solve()
+    assert ei.value.code == -2
