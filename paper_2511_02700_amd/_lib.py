@@ -5,7 +5,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblpide.so")
+LIB_PATH = os.environ.get("LPIDE_LIB") or os.path.join(HERE, "liblpide.so")
 
 LPIDE_OK = 0
 ERRORS = {-1: "LPIDE_E_PARAM", -2: "LPIDE_E_NOCONV", -3: "LPIDE_E_NAN", -4: "LPIDE_E_HIP", -5: "LPIDE_E_OOM"}

@@ -13,8 +13,9 @@
 // The stage (Stockham autosort, Ns = product of the radices already applied):
 //   butterfly j, k = j mod Ns: v_r = x[j + r L/R] * W_{Ns R}^{r k},
 //   R-point DFT of v, y[(j - k) R + k + r Ns] = v_r.
-// Twiddles W_N^m = exp(-+2 pi i m / N) come from a table tw[q] = exp(-2 pi i q / L)
-// (q = m L / N), conjugated for the inverse transform.
+// Twiddles W_N^m = exp(-+2 pi i m / N) come from the table exp(-2 pi i q / L)
+// (q = m L / N), kept in LDS as its first quarter (the other three quarters
+// follow by multiplying with -i), conjugated for the inverse transform.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -106,19 +107,37 @@ __device__ __forceinline__ void dft(C* v) {
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
-// Twiddle W_N^m for N = L / step: table entry m*step, conjugated for the inverse.
-template <bool INV, typename C>
-__device__ __forceinline__ C twiddle(const C* __restrict__ tw, int q) {
-    C w = tw[q];
-    if (INV) w.y = -w.y;
-    return w;
+// Twiddle exp(-+2 pi i q / L), q in [0, L), from a quarter table
+// tw4[r] = exp(-2 pi i r / L), r in [0, L/4) (held in LDS): exp(-2 pi i q / L) =
+// (-i)^quadrant * tw4[q mod L/4]; conjugated for the inverse transform.
+template <int L, bool INV, typename C>
+__device__ __forceinline__ C twiddle(const C* tw4, int q) {
+    using Rl = typename CplxOps<C>::real;
+    constexpr int Q = L / 4;
+    const C w = tw4[q & (Q - 1)];
+    const int quad = q / Q;
+    // quadrant 0: w; 1: w (-i) = (y, -x); 2: -w; 3: w (+i) = (-y, x)  (branch-free selects)
+    const bool odd = (quad & 1) != 0;
+    const Rl a = odd ? w.y : w.x;
+    const Rl b = odd ? w.x : w.y;
+    const Rl re = quad >= 2 ? -a : a;
+    Rl im = (quad == 1 || quad == 2) ? -b : b;
+    if (INV) im = -im;
+    return CplxOps<C>::make(re, im);
+}
+
+// Cooperative load of the quarter twiddle table (first L/4 entries of the full
+// table tw) into LDS; visible to the FFT stages after the next barrier.
+template <int L, typename C>
+__device__ __forceinline__ void load_twiddles(const C* __restrict__ tw, C* tw4) {
+    for (int q = threadIdx.x; q < L / 4; q += L / 8) tw4[q] = tw[q];
 }
 
 // One Stockham stage.  Preconditions: if !FIRST, the previous stage's LDS writes
 // are complete and visible (barrier).  Postcondition: if !LAST, this stage's
 // LDS writes are complete and visible; if LAST, the result is in reg.
 template <int L, int R, bool INV, bool FIRST, bool LAST, typename C>
-__device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, const C* __restrict__ tw) {
+__device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, const C* tw4) {
     constexpr int T = L / 8;
     constexpr int NB = 8 / R;          // butterflies per thread
     const int tid = threadIdx.x;
@@ -137,7 +156,7 @@ __device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, const C* 
         for (int r = 0; r < R; ++r) v[r] = reg[b + r * NB];
         if (Ns > 1) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twiddle<INV>(tw, r * k * step));
+            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twiddle<L, INV>(tw4, r * k * step));
         }
         dft<R, INV>(v);
         if constexpr (LAST) {
@@ -153,22 +172,24 @@ __device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, const C* 
 }
 
 template <int L, bool INV, int S, int NST, typename C>
-__device__ __forceinline__ void fft_stages(C (&reg)[8], C* lds, int Ns, const C* __restrict__ tw) {
+__device__ __forceinline__ void fft_stages(C (&reg)[8], C* lds, int Ns, const C* tw4) {
     constexpr int REM = ilog2c(L) % 3;
     constexpr int R = (S == 0 && REM == 1) ? 2 : (S == 0 && REM == 2) ? 4 : 8;
-    fft_stage<L, R, INV, S == 0, S == NST - 1>(reg, lds, Ns, tw);
-    if constexpr (S + 1 < NST) fft_stages<L, INV, S + 1, NST>(reg, lds, Ns * R, tw);
+    fft_stage<L, R, INV, S == 0, S == NST - 1>(reg, lds, Ns, tw4);
+    if constexpr (S + 1 < NST) fft_stages<L, INV, S + 1, NST>(reg, lds, Ns * R, tw4);
 }
 
 // Unnormalised length-L transform of the workgroup's sequence held in the
-// canonical register layout; INV selects exp(+2 pi i jk / L).  After return,
-// other threads may still read LDS: barrier before reusing it.
+// canonical register layout; INV selects exp(+2 pi i jk / L).  tw4 is the
+// quarter twiddle table in LDS, written (load_twiddles) before the call; the
+// first stage needs no twiddles and its barrier publishes the table.  After
+// return, other threads may still read LDS: barrier before reusing it.
 template <int L, bool INV, typename C>
-__device__ __forceinline__ void fft_block(C (&reg)[8], C* lds, const C* __restrict__ tw) {
+__device__ __forceinline__ void fft_block(C (&reg)[8], C* lds, const C* tw4) {
     constexpr int LOG = ilog2c(L);
     constexpr int NST = LOG / 3 + (LOG % 3 ? 1 : 0);
     static_assert((1 << LOG) == L && L >= 64, "L must be a power of two >= 64");
-    fft_stages<L, INV, 0, NST>(reg, lds, 1, tw);
+    fft_stages<L, INV, 0, NST>(reg, lds, 1, tw4);
 }
 
 }  // namespace lpide

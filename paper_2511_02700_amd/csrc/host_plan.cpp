@@ -241,7 +241,7 @@ static void small_jump_cov(const Nts& p, double half, double S[3]) {
 
 bool build_host_plan(const lpide_grid& g, const lpide_levy& lv, HostPlan& hp, std::string& err) {
     hp = HostPlan();
-    if (g.n < 8 || g.n > 8192) { err = "n must lie in [8, 8192]"; return false; }
+    if (g.n < 8 || g.n > 4096) { err = "n must lie in [8, 4096]"; return false; }
     double w0 = g.y_hi[0] - g.y_lo[0], w1 = g.y_hi[1] - g.y_lo[1];
     if (!(w0 > 0.0) || !(w1 > 0.0) || std::fabs(w0 - w1) > 1e-12 * std::max(1.0, w0)) {
         err = "both axes need the same positive width y_hi - y_lo";
@@ -361,7 +361,7 @@ bool build_host_plan(const lpide_grid& g, const lpide_levy& lv, HostPlan& hp, st
         int need = hp.n + std::max(-hp.dlo, hp.dhi);
         hp.L = 64;   // smallest transform the workgroup FFT supports
         while (hp.L < need) hp.L *= 2;
-        if (hp.L > 8192) { err = "FFT side above 8192: grid too fine for the jump range"; return false; }
+        if (hp.L > 4096) { err = "FFT side above 4096: n + N_z + 1 must not exceed 4096"; return false; }
     }
     return true;
 }

@@ -58,6 +58,8 @@ __global__ __launch_bounds__(L / 8) void k_rows_fwd(const double* __restrict__ Y
                                                    const double2* __restrict__ tw) {
     constexpr int T = L / 8;
     __shared__ double2 lds[L];
+    __shared__ double2 tw4[L / 4];
+    load_twiddles<L>(tw, tw4);
     const int np = (n_rows + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, np);
     const int ra = 2 * p, rb = 2 * p + 1;
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(L / 8) void k_rows_fwd(const double* __restrict__ Y
         }
         reg[e] = make_double2(a, b);
     }
-    fft_block<L, false>(reg, lds, tw);
+    fft_block<L, false>(reg, lds, tw4);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 8; ++e) lds[tid + e * T] = reg[e];
@@ -101,6 +103,8 @@ __global__ __launch_bounds__(L / 8) void k_cols(double2* __restrict__ X, int ldx
                                                const double2* __restrict__ tw) {
     constexpr int T = L / 8;
     __shared__ double2 lds[L];
+    __shared__ double2 tw4[L / 4];
+    load_twiddles<L>(tw, tw4);
     const int col = blockIdx.x;
     const int tid = threadIdx.x;
     double2* xc = X + (size_t)col * ldx;
@@ -110,7 +114,7 @@ __global__ __launch_bounds__(L / 8) void k_cols(double2* __restrict__ X, int ldx
         const int idx = tid + e * T;
         reg[e] = idx < n_in ? xc[idx] : make_double2(0.0, 0.0);
     }
-    fft_block<L, false>(reg, lds, tw);
+    fft_block<L, false>(reg, lds, tw4);
     if constexpr (MODE == 1) {
         double2* so = spec_out + (size_t)col * L;
 #pragma unroll
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(L / 8) void k_cols(double2* __restrict__ X, int ldx
         const double2* sc = spec + (size_t)col * L;
 #pragma unroll
         for (int e = 0; e < 8; ++e) reg[e] = cmul(reg[e], sc[tid + e * T]);
-        fft_block<L, true>(reg, lds, tw);
+        fft_block<L, true>(reg, lds, tw4);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int idx = tid + e * T;
@@ -136,6 +140,8 @@ __global__ __launch_bounds__(L / 8) void k_rows_inv(const double2* __restrict__ 
                                                    double* __restrict__ out, const double2* __restrict__ tw) {
     constexpr int T = L / 8;
     __shared__ double2 lds[L];
+    __shared__ double2 tw4[L / 4];
+    load_twiddles<L>(tw, tw4);
     const int np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, np);
     const int ra = 2 * p, rb = 2 * p + 1;
@@ -154,7 +160,7 @@ __global__ __launch_bounds__(L / 8) void k_rows_inv(const double2* __restrict__ 
         // Z_k = A_k + i B_k, with A_{L-k} = conj A_k, B_{L-k} = conj B_k
         reg[e] = lo ? make_double2(ha.x - hb.y, ha.y + hb.x) : make_double2(ha.x + hb.y, hb.x - ha.y);
     }
-    fft_block<L, true>(reg, lds, tw);
+    fft_block<L, true>(reg, lds, tw4);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int j = tid + e * T;
@@ -446,7 +452,6 @@ void launch_step(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
         case 1024: CALL(1024, FFTv); break;                                             \
         case 2048: CALL(2048, FFTv); break;                                             \
         case 4096: CALL(4096, FFTv); break;                                             \
-        case 8192: CALL(8192, FFTv); break;                                             \
         default: return fail(LPIDE_E_PARAM, "unsupported transform size");              \
     }
 
@@ -741,7 +746,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
         p->Lr = 64;
         while (p->Lr < n) p->Lr *= 2;
     }
-    if (p->Lr > 8192) return bail(fail(LPIDE_E_PARAM, "n too large"));
+    if (p->Lr > 4096) return bail(fail(LPIDE_E_PARAM, "n too large"));
     // step list and its distinct (theta, dt) sets
     {
         auto steps = step_list(theta, payoff->T, M, o.damping != 0);

@@ -84,6 +84,8 @@ __global__ __launch_bounds__(L / 8) void ks_cols(MarchArgs a, int k) {
     if (halted(a, k)) return;
     constexpr int T = L / 8;
     __shared__ double2 lds[L];
+    __shared__ double2 tw4[L / 4];
+    load_twiddles<L>(a.tw, tw4);
     const int n = a.n, col = blockIdx.x, tid = threadIdx.x;
     double2* xc = a.X + (size_t)col * n;
     double2 reg[8];
@@ -92,11 +94,11 @@ __global__ __launch_bounds__(L / 8) void ks_cols(MarchArgs a, int k) {
         const int idx = tid + e * T;
         reg[e] = idx < n ? xc[idx] : make_double2(0.0, 0.0);
     }
-    fft_block<L, false>(reg, lds, a.tw);
+    fft_block<L, false>(reg, lds, tw4);
     const double2* sc = a.spec + (size_t)col * L;
 #pragma unroll
     for (int e = 0; e < 8; ++e) reg[e] = cmul(reg[e], sc[tid + e * T]);
-    fft_block<L, true>(reg, lds, a.tw);
+    fft_block<L, true>(reg, lds, tw4);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int idx = tid + e * T;
@@ -112,6 +114,8 @@ __global__ __launch_bounds__(L / 8) void ks_rows_inv(MarchArgs a, int k) {
     if (halted(a, k)) return;
     constexpr int T = L / 8;
     __shared__ double2 lds[L];
+    __shared__ double2 tw4[L / 4];
+    load_twiddles<L>(a.tw, tw4);
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, np);
     const int ra = 2 * p, rb = 2 * p + 1;
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(L / 8) void ks_rows_inv(MarchArgs a, int k) {
         if (kk == 0 || kk == L / 2) { ha.y = 0.0; hb.y = 0.0; }
         reg[e] = lo ? make_double2(ha.x - hb.y, ha.y + hb.x) : make_double2(ha.x + hb.y, hb.x - ha.y);
     }
-    fft_block<L, true>(reg, lds, a.tw);
+    fft_block<L, true>(reg, lds, tw4);
     const StepDesc& sd = cur_set(a);
     const double* U = EXPLICIT ? a.pool[a.ctl->cur] : a.pool[a.ctl->y];
     const double* P0 = EXPLICIT ? U : a.W;
@@ -176,12 +180,12 @@ __global__ void ks_affine_noB(MarchArgs a, int k) {
 // Forward FFT of the row pair held in reg (canonical layout) into the
 // transposed half spectra X[k2 * n + row].
 template <int L>
-__device__ __forceinline__ void rows_fwd_store(double2 (&reg)[8], double2* lds, const double2* __restrict__ tw,
+__device__ __forceinline__ void rows_fwd_store(double2 (&reg)[8], double2* lds, const double2* tw4,
                                                double2* __restrict__ X, int n, int ra, bool hasb) {
     constexpr int T = L / 8;
     const int tid = threadIdx.x;
     __syncthreads();
-    fft_block<L, false>(reg, lds, tw);
+    fft_block<L, false>(reg, lds, tw4);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 8; ++e) lds[tid + e * T] = reg[e];
@@ -201,6 +205,8 @@ __global__ __launch_bounds__(L / 8) void ks_sl(MarchArgs a) {
     if (halted(a, 0)) return;
     constexpr int T = L / 8;
     __shared__ double2 lds[FFT ? L : 1];
+    __shared__ double2 tw4[FFT ? L / 4 : 1];
+    if constexpr (FFT) load_twiddles<L>(a.tw, tw4);
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, np);
     const int ra = 2 * p, rb = 2 * p + 1;
@@ -251,7 +257,7 @@ __global__ __launch_bounds__(L / 8) void ks_sl(MarchArgs a) {
         }
         reg[e] = make_double2(y0[0], y0[1]);
     }
-    if constexpr (FFT) rows_fwd_store<L>(reg, lds, a.tw, a.X, n, ra, hasb);
+    if constexpr (FFT) rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
 }
 
 // Axis-1 line solves R <- T_1^{-1} R: 4 adjacent columns x P chunks per block.
@@ -283,6 +289,8 @@ __global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
     constexpr int T = L / 8, PR = T / 2;
     // union: row buffer 2 (n + PR + 1) doubles | scan buffer 2T double2 | FFT buffer L double2
     __shared__ double2 lds[L + L / 16 + 2];
+    __shared__ double2 tw4[FFT ? L / 4 : 1];
+    if constexpr (FFT) load_twiddles<L>(a.tw, tw4);
     double* rows = reinterpret_cast<double*>(lds);
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, np);
@@ -344,7 +352,7 @@ __global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
         emax = (o > emax || o != o) ? o : emax;
     }
     if ((tid & 63) == 0) atomicMax(&a.ctl->err[k], (unsigned long long)__double_as_longlong(emax));
-    if constexpr (FFT) rows_fwd_store<L>(reg, lds, a.tw, a.X, n, ra, hasb);
+    if constexpr (FFT) rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
 }
 
 // End of a step: convergence verdict, history rotation, next starting value.
