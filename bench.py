@@ -34,15 +34,21 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 
 
 def algorithmic_bytes(cls, n, L, s=8):
-    """Bytes a kernel class must move per launch (s bytes per real)."""
+    """Bytes a kernel class must move per launch (s bytes per real; the
+    intermediate X holds n x (L/2+1) complex values, the spectrum L x (L/2+1))."""
     hc = L // 2 + 1
     return {
-        "rows_fwd": s * (n * n + 2 * n * hc),                # read n^2 reals, write n x (L/2+1) complex
-        "cols": 2 * s * hc * (2 * n + L),                   # read + write n x (L/2+1), read the L x (L/2+1) spectrum
-        "rows_inv": s * (2 * n * hc + 3 * n * n),            # read n x (L/2+1), read W and Y, write R
-        "line_rows": s * 2 * n * n,                          # read + write R
-        "line_cols": s * 3 * n * n,                          # read R, read + write Y
-        "sl": s * 4 * n * n,                                 # read E, write W, read history, write Y0 (typical)
+        # read + write X, read the spectrum
+        "cols": 2 * s * hc * (2 * n + L),
+        # read X; residual form: read W and Y, write R
+        "rows_inv": 2 * s * n * hc + 3 * s * n * n,
+        # read + write R
+        "line_cols": 2 * s * n * n,
+        # read R, read + write Y, write X (row FFT of the new Y)
+        "line_rows": 3 * s * n * n + 2 * s * n * hc,
+        # read E, write W, read four history grids, write Y0, write X
+        "sl": 7 * s * n * n + 2 * s * n * hc,
+        "step_end": 0,
     }[cls]
 
 

@@ -4,7 +4,7 @@
 // with T = L/8 threads.  Each thread keeps E = 8 elements in registers in the
 // canonical layout reg[e] = element (tid + e*T); the radix-R stages (radix 8,
 // plus one radix-2 or radix-4 stage when log2 L is not a multiple of 3)
-// exchange data through one LDS buffer of L complex values.  Input and output
+// exchange data through one LDS buffer of L complex values (plus padding).  Input and output
 // of the whole transform are in the canonical layout, so a load or store of
 // element (tid + e*T) by thread tid is coalesced, and the output registers of a
 // forward transform are the input registers of an inverse transform, which
@@ -13,9 +13,8 @@
 // The stage (Stockham autosort, Ns = product of the radices already applied):
 //   butterfly j, k = j mod Ns: v_r = x[j + r L/R] * W_{Ns R}^{r k},
 //   R-point DFT of v, y[(j - k) R + k + r Ns] = v_r.
-// Twiddles W_N^m = exp(-+2 pi i m / N) come from the table exp(-2 pi i q / L)
-// (q = m L / N), kept in LDS as its first quarter (the other three quarters
-// follow by multiplying with -i), conjugated for the inverse transform.
+// Twiddles W_N^m = exp(-+2 pi i m / N): per stage only W_N^k is stored in LDS
+// (see TwTab), its powers are formed in registers; conjugated for the inverse.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -107,46 +106,61 @@ __device__ __forceinline__ void dft(C* v) {
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
-// Twiddle exp(-+2 pi i q / L), q in [0, L), from a quarter table
-// tw4[r] = exp(-2 pi i r / L), r in [0, L/4) (held in LDS): exp(-2 pi i q / L) =
-// (-i)^quadrant * tw4[q mod L/4]; conjugated for the inverse transform.
-template <int L, bool INV, typename C>
-__device__ __forceinline__ C twiddle(const C* tw4, int q) {
-    using Rl = typename CplxOps<C>::real;
-    constexpr int Q = L / 4;
-    const C w = tw4[q & (Q - 1)];
-    const int quad = q / Q;
-    // quadrant 0: w; 1: w (-i) = (y, -x); 2: -w; 3: w (+i) = (-y, x)  (branch-free selects)
-    const bool odd = (quad & 1) != 0;
-    const Rl a = odd ? w.y : w.x;
-    const Rl b = odd ? w.x : w.y;
-    const Rl re = quad >= 2 ? -a : a;
-    Rl im = (quad == 1 || quad == 2) ? -b : b;
-    if (INV) im = -im;
-    return CplxOps<C>::make(re, im);
-}
+// LDS slot of exchange element a: one pad slot per 16 elements.  Spreads the
+// radix-8 stage writes (stride 8 elements in the first stage) over distinct
+// banks while keeping the contiguous stage reads conflict free.  The exchange
+// buffer needs lds_slots(L) elements.
+__device__ __forceinline__ int lds_slot(int a) { return a + (a >> 4); }
+constexpr int lds_slots(int L) { return L + L / 16; }
 
-// Cooperative load of the quarter twiddle table (first L/4 entries of the full
-// table tw) into LDS; visible to the FFT stages after the next barrier.
+// Stage twiddle tables.  Stage s >= 1 is always radix 8 with Ns = R0 8^(s-1)
+// (R0 the radix of stage 0); its butterfly k needs W^r = exp(-+2 pi i r k / (8 Ns)),
+// r = 1..7.  Only the base W = exp(-2 pi i k / (8 Ns)), k in [0, Ns), is stored
+// (stage tables concatenated, k contiguous, so a wave reads consecutive
+// entries without bank conflicts); the powers W^2..W^7 are formed in registers
+// with at most three complex products each.
+template <int L>
+struct TwTab {
+    static constexpr int LOG = ilog2c(L);
+    static constexpr int R0 = (LOG % 3 == 1) ? 2 : (LOG % 3 == 2) ? 4 : 8;
+    static constexpr int NST = LOG / 3 + (LOG % 3 ? 1 : 0);
+    // Ns of stage s and the offset of its table (sum of Ns over stages 1..s-1);
+    // closed forms, so runtime uses compile to shifts (no recursion on the device)
+    static constexpr __host__ __device__ int ns(int s) { return s == 0 ? 1 : R0 << (3 * (s - 1)); }
+    static constexpr __host__ __device__ int off(int s) { return s <= 1 ? 0 : R0 * ((1 << (3 * (s - 1))) - 1) / 7; }
+    static constexpr int size = off(NST);           // entries over stages 1..NST-1
+};
+template <int L>
+constexpr int tw_slots() { return TwTab<L>::size; }
+
+// Build the stage tables in LDS from the full table tw[q] = exp(-2 pi i q / L);
+// visible to the FFT stages after the next barrier (stage 0 needs none).
 template <int L, typename C>
-__device__ __forceinline__ void load_twiddles(const C* __restrict__ tw, C* tw4) {
-    for (int q = threadIdx.x; q < L / 4; q += L / 8) tw4[q] = tw[q];
+__device__ __forceinline__ void load_twiddles(const C* __restrict__ tw, C* tab) {
+    using TT = TwTab<L>;
+    for (int i = threadIdx.x; i < TT::size; i += L / 8) {
+        int s = 1;
+#pragma unroll
+        for (int q = 2; q < TT::NST; ++q)
+            if (i >= TT::off(q)) s = q;
+        const int k = i - TT::off(s);
+        tab[i] = tw[k * (L / (TT::ns(s) * 8))];
+    }
 }
 
 // One Stockham stage.  Preconditions: if !FIRST, the previous stage's LDS writes
 // are complete and visible (barrier).  Postcondition: if !LAST, this stage's
 // LDS writes are complete and visible; if LAST, the result is in reg.
 template <int L, int R, bool INV, bool FIRST, bool LAST, typename C>
-__device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, const C* tw4) {
+__device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, int toff, const C* tab) {
     constexpr int T = L / 8;
     constexpr int NB = 8 / R;          // butterflies per thread
     const int tid = threadIdx.x;
     if constexpr (!FIRST) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) reg[e] = lds[tid + e * T];
+        for (int e = 0; e < 8; ++e) reg[e] = lds[lds_slot(tid + e * T)];
     }
     if constexpr (!LAST) __syncthreads();
-    const int step = L / (Ns * R);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = tid + b * T;
@@ -154,9 +168,18 @@ __device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, const C* 
         C v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = reg[b + r * NB];
-        if (Ns > 1) {
-#pragma unroll
-            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twiddle<L, INV>(tw4, r * k * step));
+        if constexpr (!FIRST) {
+            static_assert(R == 8, "stages after the first are radix 8");
+            const C t = tab[toff + k];
+            const C w1 = CplxOps<C>::make(t.x, INV ? -t.y : t.y);
+            const C w2 = cmul(w1, w1), w3 = cmul(w2, w1), w4 = cmul(w2, w2);
+            v[1] = cmul(v[1], w1);
+            v[2] = cmul(v[2], w2);
+            v[3] = cmul(v[3], w3);
+            v[4] = cmul(v[4], w4);
+            v[5] = cmul(v[5], cmul(w4, w1));
+            v[6] = cmul(v[6], cmul(w4, w2));
+            v[7] = cmul(v[7], cmul(w4, w3));
         }
         dft<R, INV>(v);
         if constexpr (LAST) {
@@ -165,31 +188,31 @@ __device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, const C* 
         } else {
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[base + r * Ns] = v[r];
+            for (int r = 0; r < R; ++r) lds[lds_slot(base + r * Ns)] = v[r];
         }
     }
     if constexpr (!LAST) __syncthreads();
 }
 
 template <int L, bool INV, int S, int NST, typename C>
-__device__ __forceinline__ void fft_stages(C (&reg)[8], C* lds, int Ns, const C* tw4) {
-    constexpr int REM = ilog2c(L) % 3;
-    constexpr int R = (S == 0 && REM == 1) ? 2 : (S == 0 && REM == 2) ? 4 : 8;
-    fft_stage<L, R, INV, S == 0, S == NST - 1>(reg, lds, Ns, tw4);
-    if constexpr (S + 1 < NST) fft_stages<L, INV, S + 1, NST>(reg, lds, Ns * R, tw4);
+__device__ __forceinline__ void fft_stages(C (&reg)[8], C* lds, const C* tab) {
+    using TT = TwTab<L>;
+    constexpr int R = S == 0 ? TT::R0 : 8;
+    fft_stage<L, R, INV, S == 0, S == NST - 1>(reg, lds, TT::ns(S), S == 0 ? 0 : TT::off(S), tab);
+    if constexpr (S + 1 < NST) fft_stages<L, INV, S + 1, NST>(reg, lds, tab);
 }
 
 // Unnormalised length-L transform of the workgroup's sequence held in the
-// canonical register layout; INV selects exp(+2 pi i jk / L).  tw4 is the
-// quarter twiddle table in LDS, written (load_twiddles) before the call; the
-// first stage needs no twiddles and its barrier publishes the table.  After
+// canonical register layout; INV selects exp(+2 pi i jk / L).  tab holds the
+// stage twiddle tables in LDS, written (load_twiddles) before the call; the
+// first stage needs no twiddles and its barrier publishes them.  After
 // return, other threads may still read LDS: barrier before reusing it.
 template <int L, bool INV, typename C>
-__device__ __forceinline__ void fft_block(C (&reg)[8], C* lds, const C* tw4) {
+__device__ __forceinline__ void fft_block(C (&reg)[8], C* lds, const C* tab) {
     constexpr int LOG = ilog2c(L);
     constexpr int NST = LOG / 3 + (LOG % 3 ? 1 : 0);
     static_assert((1 << LOG) == L && L >= 64, "L must be a power of two >= 64");
-    fft_stages<L, INV, 0, NST>(reg, lds, 1, tw4);
+    fft_stages<L, INV, 0, NST>(reg, lds, tab);
 }
 
 }  // namespace lpide

@@ -57,8 +57,8 @@ __global__ __launch_bounds__(L / 8) void k_rows_fwd(const double* __restrict__ Y
                                                    int n_cols, double2* __restrict__ X, int ldx,
                                                    const double2* __restrict__ tw) {
     constexpr int T = L / 8;
-    __shared__ double2 lds[L];
-    __shared__ double2 tw4[L / 4];
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L>()];
     load_twiddles<L>(tw, tw4);
     const int np = (n_rows + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, np);
@@ -102,8 +102,8 @@ __global__ __launch_bounds__(L / 8) void k_cols(double2* __restrict__ X, int ldx
                                                double2* __restrict__ spec_out, double scale,
                                                const double2* __restrict__ tw) {
     constexpr int T = L / 8;
-    __shared__ double2 lds[L];
-    __shared__ double2 tw4[L / 4];
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L>()];
     load_twiddles<L>(tw, tw4);
     const int col = blockIdx.x;
     const int tid = threadIdx.x;
@@ -139,8 +139,8 @@ template <int L>
 __global__ __launch_bounds__(L / 8) void k_rows_inv(const double2* __restrict__ X, int ldx, int n,
                                                    double* __restrict__ out, const double2* __restrict__ tw) {
     constexpr int T = L / 8;
-    __shared__ double2 lds[L];
-    __shared__ double2 tw4[L / 4];
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L>()];
     load_twiddles<L>(tw, tw4);
     const int np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, np);
@@ -154,9 +154,11 @@ __global__ __launch_bounds__(L / 8) void k_rows_inv(const double2* __restrict__ 
         const bool lo = idx <= L / 2;
         const int k = lo ? idx : L - idx;
         const double2* xk = X + (size_t)k * ldx;
-        double2 ha = xk[ra];
-        double2 hb = hasb ? xk[rb] : make_double2(0.0, 0.0);
-        if (k == 0 || k == L / 2) { ha.y = 0.0; hb.y = 0.0; }
+        const bool real_bin = k == 0 || k == L / 2;    // imaginary parts dropped at DC and Nyquist
+        const double2 ta = xk[ra];
+        const double2 tb = hasb ? xk[rb] : make_double2(0.0, 0.0);
+        const double2 ha = make_double2(ta.x, real_bin ? 0.0 : ta.y);
+        const double2 hb = make_double2(tb.x, real_bin ? 0.0 : tb.y);
         // Z_k = A_k + i B_k, with A_{L-k} = conj A_k, B_{L-k} = conj B_k
         reg[e] = lo ? make_double2(ha.x - hb.y, ha.y + hb.x) : make_double2(ha.x + hb.y, hb.x - ha.y);
     }
@@ -259,7 +261,9 @@ struct Plan {
     // kernel timing (HIP events on the plan's stream around each timed launch)
     uint32_t time_mask = 0;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, size_t>> ev_recs;   // (kernel class, index of the start event)
+    struct EvRec { int cls; size_t idx; int step, k; };
+    std::vector<EvRec> ev_recs;   // timed launches: class, start event, step and iteration (k = 0: once per step)
+    int tag_step = -1, tag_k = 0; // step/iteration of the launches being enqueued
     size_t ev_used = 0;
     int64_t k_launch[LPIDE_KCLASSES] = {};
     double k_ms[LPIDE_KCLASSES] = {};
@@ -293,21 +297,24 @@ KTime::KTime(Plan* pl, int c) : p(pl), on((pl->time_mask >> c) & 1u) {
     hipEvent_t a = next_event(p), b = next_event(p);
     if (!a || !b) { on = false; return; }
     (void)hipEventRecord(a, p->stream);
-    p->ev_recs.emplace_back(c, idx);
+    p->ev_recs.push_back({c, idx, p->tag_step, p->tag_k});
 }
 KTime::~KTime() {
     if (on) (void)hipEventRecord(p->ev_pool[idx + 1], p->stream);
 }
 
 // Fold recorded event pairs into the per-class totals (synchronises the stream).
+// Launches of iterations after a step had converged (they return at once) are
+// left out, so the totals describe executed launches only.
 int harvest_times(Plan* p) {
     if (p->ev_recs.empty()) return LPIDE_OK;
     HIP_TRY(hipStreamSynchronize(p->stream));
     for (auto& r : p->ev_recs) {
+        if (r.k > 0 && r.step >= 0 && r.step < (int)p->counts_h.size() && r.k > p->counts_h[r.step]) continue;
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[r.second], p->ev_pool[r.second + 1]));
-        p->k_launch[r.first] += 1;
-        p->k_ms[r.first] += ms;
+        HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[r.idx], p->ev_pool[r.idx + 1]));
+        p->k_launch[r.cls] += 1;
+        p->k_ms[r.cls] += ms;
     }
     p->ev_recs.clear();
     p->ev_used = 0;
@@ -394,6 +401,7 @@ void launch_rows_fwd(Plan* p, const double* Y) {
 template <int L, bool FFT>
 void launch_iteration(Plan* p, const MarchArgs& a, int k) {
     const int n = p->hp.n, np = (n + 1) / 2;
+    p->tag_k = k;
     if (FFT) {
         {
             KTime t(p, LPIDE_K_COLS);
@@ -418,6 +426,7 @@ void launch_iteration(Plan* p, const MarchArgs& a, int k) {
 template <int L, bool FFT>
 void launch_step(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
     const int n = p->hp.n, np = (n + 1) / 2;
+    p->tag_k = 0;
     if (explicit_part) {
         if (FFT) {
             {
@@ -439,6 +448,7 @@ void launch_step(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
             hipLaunchKernelGGL((ks_sl<L, 3, FFT>), dim3(np), dim3(L / 8), 0, p->stream, a);
     }
     for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT>(p, a, k);
+    p->tag_k = 0;
     KTime t(p, LPIDE_K_STEP_END);
     hipLaunchKernelGGL(ks_step_end, dim3(1), dim3(64), 0, p->stream, a, kmax);
 }
@@ -555,6 +565,7 @@ int march(Plan* p, int count, double* v_out) {
         for (int s = done; s < s1; ++s) {
             const int id = p->step_set[s];
             kused[s] = kpred[id];
+            p->tag_step = s;
             int rc = issue_step(p, a, p->sets[id].theta < 1.0, kpred[id]);
             if (rc) return rc;
         }
@@ -575,6 +586,7 @@ int march(Plan* p, int count, double* v_out) {
                 }
                 ++k;
                 hipLaunchKernelGGL(ks_clear_fail, dim3(1), dim3(64), 0, p->stream, a);
+                p->tag_step = sf;
                 rc = issue_iteration(p, a, k);
                 if (rc) return rc;
                 hipLaunchKernelGGL(ks_step_end, dim3(1), dim3(64), 0, p->stream, a, k);

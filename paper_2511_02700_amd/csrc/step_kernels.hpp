@@ -83,21 +83,22 @@ template <int L>
 __global__ __launch_bounds__(L / 8) void ks_cols(MarchArgs a, int k) {
     if (halted(a, k)) return;
     constexpr int T = L / 8;
-    __shared__ double2 lds[L];
-    __shared__ double2 tw4[L / 4];
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L>()];
     load_twiddles<L>(a.tw, tw4);
     const int n = a.n, col = blockIdx.x, tid = threadIdx.x;
     double2* xc = a.X + (size_t)col * n;
-    double2 reg[8];
+    const double2* sc = a.spec + (size_t)col * L;
+    double2 reg[8], sp[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int idx = tid + e * T;
         reg[e] = idx < n ? xc[idx] : make_double2(0.0, 0.0);
+        sp[e] = sc[idx];                  // spectrum fetched up front, used after the forward FFT
     }
     fft_block<L, false>(reg, lds, tw4);
-    const double2* sc = a.spec + (size_t)col * L;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) reg[e] = cmul(reg[e], sc[tid + e * T]);
+    for (int e = 0; e < 8; ++e) reg[e] = cmul(reg[e], sp[e]);
     fft_block<L, true>(reg, lds, tw4);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -113,8 +114,8 @@ template <int L, bool EXPLICIT>
 __global__ __launch_bounds__(L / 8) void ks_rows_inv(MarchArgs a, int k) {
     if (halted(a, k)) return;
     constexpr int T = L / 8;
-    __shared__ double2 lds[L];
-    __shared__ double2 tw4[L / 4];
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L>()];
     load_twiddles<L>(a.tw, tw4);
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, np);
@@ -128,9 +129,11 @@ __global__ __launch_bounds__(L / 8) void ks_rows_inv(MarchArgs a, int k) {
         const bool lo = idx <= L / 2;
         const int kk = lo ? idx : L - idx;
         const double2* xk = a.X + (size_t)kk * n;
-        double2 ha = xk[ra];
-        double2 hb = hasb ? xk[rb] : make_double2(0.0, 0.0);
-        if (kk == 0 || kk == L / 2) { ha.y = 0.0; hb.y = 0.0; }
+        const bool real_bin = kk == 0 || kk == L / 2;  // imaginary parts dropped at DC and Nyquist
+        const double2 ta = xk[ra];
+        const double2 tb = hasb ? xk[rb] : make_double2(0.0, 0.0);
+        const double2 ha = make_double2(ta.x, real_bin ? 0.0 : ta.y);
+        const double2 hb = make_double2(tb.x, real_bin ? 0.0 : tb.y);
         reg[e] = lo ? make_double2(ha.x - hb.y, ha.y + hb.x) : make_double2(ha.x + hb.y, hb.x - ha.y);
     }
     fft_block<L, true>(reg, lds, tw4);
@@ -204,8 +207,8 @@ template <int L, int P, bool FFT>
 __global__ __launch_bounds__(L / 8) void ks_sl(MarchArgs a) {
     if (halted(a, 0)) return;
     constexpr int T = L / 8;
-    __shared__ double2 lds[FFT ? L : 1];
-    __shared__ double2 tw4[FFT ? L / 4 : 1];
+    __shared__ double2 lds[FFT ? lds_slots(L) : 1];
+    __shared__ double2 tw4[FFT ? tw_slots<L>() : 1];
     if constexpr (FFT) load_twiddles<L>(a.tw, tw4);
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, np);
@@ -289,7 +292,7 @@ __global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
     constexpr int T = L / 8, PR = T / 2;
     // union: row buffer 2 (n + PR + 1) doubles | scan buffer 2T double2 | FFT buffer L double2
     __shared__ double2 lds[L + L / 16 + 2];
-    __shared__ double2 tw4[FFT ? L / 4 : 1];
+    __shared__ double2 tw4[FFT ? tw_slots<L>() : 1];
     if constexpr (FFT) load_twiddles<L>(a.tw, tw4);
     double* rows = reinterpret_cast<double*>(lds);
     const int n = a.n, np = (n + 1) >> 1;
