@@ -416,8 +416,7 @@ void launch_iteration(Plan* p, const MarchArgs& a, int k) {
     {
         KTime t(p, LPIDE_K_LINE_COLS);
         const int P = p->P_cols;
-        hipLaunchKernelGGL(ks_line_cols, dim3((n + 3) / 4), dim3(4 * P), sizeof(double2) * 2 * 4 * P, p->stream, a,
-                           k);
+        hipLaunchKernelGGL(ks_line_cols, dim3((n + 3) / 4), dim3(4 * P), sizeof(double2) * 4 * P, p->stream, a, k);
     }
     KTime t(p, LPIDE_K_LINE_ROWS);
     hipLaunchKernelGGL((ks_line_rows<L, FFT>), dim3(np), dim3(L / 8), 0, p->stream, a, k);

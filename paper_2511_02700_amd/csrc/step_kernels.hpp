@@ -263,7 +263,8 @@ __global__ __launch_bounds__(L / 8) void ks_sl(MarchArgs a) {
     if constexpr (FFT) rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
 }
 
-// Axis-1 line solves R <- T_1^{-1} R: 4 adjacent columns x P chunks per block.
+// Axis-1 line solves R <- T_1^{-1} R: 4 adjacent columns x P chunks per block
+// (thread = column + 4 * chunk).
 __global__ __launch_bounds__(1024) void ks_line_cols(MarchArgs a, int k) {
     if (halted(a, k)) return;
     extern __shared__ double2 sbuf[];
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(1024) void ks_line_cols(MarchArgs a, int k) {
     double x[LINE_MM];
 #pragma unroll
     for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? a.R[(size_t)(s + q) * n + col] : 0.0;
-    chunk_solve(x, s, cnt, c, t, P, blockDim.x, sd.fl1, sd.bu1, sd.bc1, sbuf);
+    chunk_solve(x, s, cnt, c, t, P, 4, sd.fl1, sd.bu1, sd.bc1, sbuf);
 #pragma unroll
     for (int q = 0; q < LINE_MM; ++q)
         if (q < cnt) a.R[(size_t)(s + q) * n + col] = x[q];
@@ -290,7 +291,7 @@ template <int L, bool FFT>
 __global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
     if (halted(a, k)) return;
     constexpr int T = L / 8, PR = T / 2;
-    // union: row buffer 2 (n + PR + 1) doubles | scan buffer 2T double2 | FFT buffer L double2
+    // union: row buffer 2 (n + PR + 1) doubles | scan totals | FFT exchange buffer
     __shared__ double2 lds[L + L / 16 + 2];
     __shared__ double2 tw4[FFT ? tw_slots<L>() : 1];
     if constexpr (FFT) load_twiddles<L>(a.tw, tw4);
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
 #pragma unroll
     for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? rows[r * stride + s + q + ch] : 0.0;
     __syncthreads();
-    chunk_solve(x, s, cnt, r, ch, PR, T, sd.fl2, sd.bu2, sd.bc2, lds);
+    chunk_solve(x, s, cnt, r, ch, PR, 1, sd.fl2, sd.bu2, sd.bc2, lds);
 #pragma unroll
     for (int q = 0; q < LINE_MM; ++q)
         if (q < cnt) rows[r * stride + s + q + ch] = x[q];
