@@ -33,23 +33,56 @@ METRIC = "grid-pt-steps/s + FFT-conv %HBM roofline, mixed vs plain FP64 at ≤1e
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 
 
-def algorithmic_bytes(cls, n, L, s=8):
-    """Bytes a kernel class must move per launch (s bytes per real; the
-    intermediate X holds n x (L/2+1) complex values, the spectrum L x (L/2+1))."""
+def algorithmic_bytes(cls, n, L, mixed=False):
+    """Bytes a kernel class must move per launch: 8 bytes per FP64 real, c = 8
+    (FP64) or 4 (mixed form) per real of the correlation data; the intermediate
+    X holds n x (L/2+1) complex values, the spectrum L x (L/2+1)."""
     hc = L // 2 + 1
+    c = 4 if mixed else 8
     return {
         # read + write X, read the spectrum
-        "cols": 2 * s * hc * (2 * n + L),
-        # read X; residual form: read W and Y, write R
-        "rows_inv": 2 * s * n * hc + 3 * s * n * n,
+        "cols": 2 * c * hc * (2 * n + L),
+        # read X; read W and Y, write R; mixed: read and write the FP64 B Y
+        "rows_inv": 2 * c * n * hc + (5 if mixed else 3) * 8 * n * n,
         # read + write R
-        "line_cols": 2 * s * n * n,
-        # read R, read + write Y, write X (row FFT of the new Y)
-        "line_rows": 3 * s * n * n + 2 * s * n * hc,
+        "line_cols": 2 * 8 * n * n,
+        # read R, read + write Y, write X (row FFT of the new Y, or of delta)
+        "line_rows": 3 * 8 * n * n + 2 * c * n * hc,
         # read E, write W, read four history grids, write Y0, write X
-        "sl": 7 * s * n * n + 2 * s * n * hc,
+        "sl": 7 * 8 * n * n + 2 * c * n * hc,
         "step_end": 0,
+        # FP64 column pass of B V^{n-1}
+        "expl_cols": 2 * 8 * hc * (2 * n + L),
+        # read X, read V, write E; mixed: write B V
+        "expl_rows": 2 * 8 * n * hc + (3 if mixed else 2) * 8 * n * n,
+        # read V, write X
+        "rows_fwd": 8 * n * n + 2 * 8 * n * hc,
     }[cls]
+
+
+def roofline(cls, n, L, mixed, launches, ms):
+    per_launch_ms = ms / max(1, launches)
+    b = algorithmic_bytes(cls, n, L, mixed)
+    achieved = b / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    return {"kernel": cls, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": b,
+            "mean_launch_ms": per_launch_ms, "launches": launches}
+
+
+def timed_solves(plan, out, steps, timed_classes):
+    """steps full solves with HIP events around the named kernel classes; wall
+    seconds and the per-class (launches, ms)."""
+    import torch
+    plan.set_timing(timed_classes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.solve(out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = plan.kernel_stats()
+    plan.set_timing([])
+    return wall, stats
 
 
 def cpu_baseline(w, steps):
@@ -83,6 +116,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2, help="untimed full solves")
     ap.add_argument("--workload", default="fv512")
     ap.add_argument("--sl-order", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp64", "fp32conv"], default="fp64",
+                    help="form timed for the headline value; the other form is timed beside it")
     ap.add_argument("--cpu-steps", type=int, default=8, help="step-list entries of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -99,37 +134,42 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     w = workloads.workload(args.workload)
     n, Nt = w["n"], w["N_t"]
-    plan = lp.plan_from_workload(w, sl_order=args.sl_order)
+    other = "fp32conv" if args.precision == "fp64" else "fp64"
+    plans = {pr: lp.plan_from_workload(w, sl_order=args.sl_order, precision=pr) for pr in (args.precision, other)}
+    plan = plans[args.precision]
+    mixed = args.precision == "fp32conv"
     info = plan.info()
     L = info["L"]
-    out = torch.empty((n, n), dtype=torch.float64, device="cuda")
-    for _ in range(args.warmup):
-        plan.solve(out)
+    outs = {pr: torch.empty((n, n), dtype=torch.float64, device="cuda") for pr in plans}
+    for pr in plans:
+        for _ in range(args.warmup):
+            plans[pr].solve(outs[pr])
     torch.cuda.synchronize()
 
     # one untimed profiling solve with every kernel class timed: picks the dominant class
     plan.set_timing(lp._lib.KCLASSES)
-    plan.solve(out)
+    plan.solve(outs[args.precision])
     prof = plan.kernel_stats()
     dominant = max(prof, key=lambda c: prof[c][1])
 
-    # timed region: events only around the dominant class
-    plan.set_timing([dominant])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.solve(out)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    live = plan.kernel_stats()[dominant]
-    plan.set_timing([])
+    # timed region: events only around the dominant class and the correlation's column pass
+    wall, live = timed_solves(plan, outs[args.precision], args.steps, sorted({dominant, "cols"}))
     info = plan.info()
-
     ms_per_step = 1e3 * wall / args.steps
     value = n * n * Nt * args.steps / wall
-    per_launch_ms = live[1] / max(1, live[0])
-    bytes_launch = algorithmic_bytes(dominant, n, L)
-    achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
+
+    # the other precision on the same workload: throughput, conv roofline, and
+    # the mixed-vs-plain difference of prices and deltas at seeded spot pairs
+    wall_o, live_o = timed_solves(plans[other], outs[other], args.steps, ["cols"])
+    spots = workloads.spot_pairs(64, seed=7)
+    pd = {pr: plans[pr].price(outs[pr], spots, with_delta=True) for pr in plans}
+    p64, d64 = (t.cpu().numpy() for t in pd["fp64"])
+    p32, d32 = (t.cpu().numpy() for t in pd["fp32conv"])
+    import numpy as np
+    rel_p = float(np.max(np.abs(p32 - p64) / np.maximum(1.0, np.abs(p64))))
+    abs_d = float(np.max(np.abs(d32 - d64)))
+    rel_grid = float((outs["fp32conv"] - outs["fp64"]).abs().div(outs["fp64"].abs().clamp_min(1.0)).max())
+
     result = {
         "metric": METRIC,
         "value": value,
@@ -141,22 +181,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if not mixed else "f32 correlation / f64 rest",
         "data": "synthetic",
         "config": {"workload": "%s: put-on-average K=100 T=1 r=0.03, NTS alpha=%g sigma=(%g,%g) corr=%g "
                                "theta=(%g,%g) kappa=%g, %dx%d log grid on [%g,%g]^2, %d time steps, theta=%g, "
-                               "tol %g, SL order %d" % (
+                               "tol %g, SL order %d, %s" % (
                                    args.workload, w["model"]["alpha"], w["model"]["sigma1"], w["model"]["sigma2"],
                                    w["model"]["corr"], w["model"]["theta1"], w["model"]["theta2"],
                                    w["model"]["kappa"], n, n, w["y_lo"], w["y_hi"], Nt, w["theta"], w["tol"],
-                                   args.sl_order),
-                   "n": n, "N_t": Nt, "L": L, "N_z": info["N_z"], "parallelism": "single GPU"},
-        "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bytes_launch, "mean_launch_ms": per_launch_ms, "launches": live[0]},
+                                   args.sl_order, args.precision),
+                   "n": n, "N_t": Nt, "L": L, "N_z": info["N_z"], "precision": args.precision,
+                   "parallelism": "single GPU"},
+        "roofline": roofline(dominant, n, L, mixed, *live[dominant]),
+        "conv_roofline": roofline("cols", n, L, mixed, *live["cols"]),
         "iters_per_step": info["total_iters"] / info["n_steps"],
-        "kernel_ms_per_solve": {c: prof[c][1] for c in prof},
-        "mixed_vs_plain_rel": None,
+        "kernel_ms_per_solve": {c: prof[c][1] for c in prof if prof[c][0]},
+        other: {"value": n * n * Nt * args.steps / wall_o, "ms_per_step": 1e3 * wall_o / args.steps,
+                "conv_roofline": roofline("cols", n, L, other == "fp32conv", *live_o["cols"]),
+                "iters_per_step": plans[other].info()["total_iters"] / info["n_steps"]},
+        "mixed_vs_plain_rel": {"prices": rel_p, "deltas_abs": abs_d, "grid": rel_grid, "spots": 64,
+                               "bound": 1e-6},
     }
     if rank == 0 and not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

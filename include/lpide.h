@@ -54,9 +54,14 @@ extern "C" {
 #define LPIDE_CALL_1    3   /* S1 - K */
 #define LPIDE_EXCHANGE  4   /* S1 - S2  (K only sets the log-moneyness origin) */
 
-/* arithmetic of the FFT correlation */
+/* Arithmetic of the FFT correlation.  In the mixed form every time step applies
+ * B to V^{n-1} once in FP64; the fixed-point iterations then apply B in FP32 to
+ * increments only (Y^0 - V^{n-1}, then Y^k - Y^{k-1}) and accumulate B Y^k in
+ * FP64, with twiddles entering in FP64 accuracy (split into two FP32 parts).
+ * The FP32 error is relative to the increments, so prices stay within about
+ * 1e-8 relative of the FP64 form.  Without jumps the precision has no effect. */
 #define LPIDE_FP64       0  /* everything in FP64 */
-#define LPIDE_FP32_CONV  1  /* FFT correlation in FP32, all else FP64 (mixed form) */
+#define LPIDE_FP32_CONV  1  /* iteration correlations in FP32 on increments, all else FP64 */
 
 /* Spatial grid and integral-discretization settings (Sec. 3.1, Sec. 4 settings). */
 typedef struct {
@@ -189,14 +194,20 @@ int lpide_price(void* plan, const double* v, int32_t npts, const double* spots,
 int lpide_discretize_host(const lpide_grid* grid, const lpide_levy* levy, const lpide_payoff* payoff,
                           lpide_info* info, double* omega, int64_t omega_len, double* v0);
 
-/* Kernel classes for lpide_timing / lpide_kernel_stats. */
-#define LPIDE_K_COLS       0   /* column pass of B Y: FFT, spectrum multiply, inverse FFT */
-#define LPIDE_K_ROWS_INV   1   /* row inverse FFTs + fused residual / explicit-part stencil */
+/* Kernel classes for lpide_timing / lpide_kernel_stats.  Classes 0-3 run once
+ * per fixed-point iteration, 4-8 once per time step. */
+#define LPIDE_K_COLS       0   /* column pass of B Y: FFT, spectrum multiply, inverse FFT
+                                  (FP32 in the mixed form) */
+#define LPIDE_K_ROWS_INV   1   /* row inverse FFTs + fused residual stencil */
 #define LPIDE_K_LINE_COLS  2   /* line solves along axis 1 */
-#define LPIDE_K_LINE_ROWS  3   /* line solves along axis 2 + update + stopping rule + row FFT of Y */
+#define LPIDE_K_LINE_ROWS  3   /* line solves along axis 2 + update + stopping rule + row FFT
+                                  of Y (of the increment in the mixed form) */
 #define LPIDE_K_SL         4   /* semi-Lagrangian gather + extrapolated start + row FFT of Y^0 */
 #define LPIDE_K_STEP_END   5   /* end-of-step control (convergence verdict, history rotation) */
-#define LPIDE_KCLASSES     6
+#define LPIDE_K_EXPL_COLS  6   /* FP64 column pass of B V^{n-1} (theta < 1, or the mixed form) */
+#define LPIDE_K_EXPL_ROWS  7   /* row inverse FFTs + explicit part (E, and B V^{n-1} when mixed) */
+#define LPIDE_K_ROWS_FWD   8   /* FP64 row FFTs of V^{n-1} (mixed form) */
+#define LPIDE_KCLASSES     9
 
 /* Kernel timing.  With bit c of class_mask set, the plan records a pair of HIP
  * events on its stream around every launch of kernel class c; the elapsed

@@ -11,7 +11,7 @@ LPIDE_OK = 0
 ERRORS = {-1: "LPIDE_E_PARAM", -2: "LPIDE_E_NOCONV", -3: "LPIDE_E_NAN", -4: "LPIDE_E_HIP", -5: "LPIDE_E_OOM"}
 PAYOFF = {"put_avg": 0, "call_avg": 1, "put_1": 2, "call_1": 3, "exchange": 4}
 PRECISION = {"fp64": 0, "fp32conv": 1}
-KCLASSES = ["cols", "rows_inv", "line_cols", "line_rows", "sl", "step_end"]
+KCLASSES = ["cols", "rows_inv", "line_cols", "line_rows", "sl", "step_end", "expl_cols", "expl_rows", "rows_fwd"]
 
 
 class Grid(C.Structure):

@@ -1,4 +1,5 @@
-// Workgroup-level Stockham FFT for CDNA4 (gfx950), FP64 and FP32 complex.
+// Workgroup-level Stockham FFT for CDNA4 (gfx950), FP64 and FP32 complex data
+// (twiddles always formed in FP64; see twmul).
 //
 // One workgroup transforms one length-L sequence (L a power of two, 128..8192)
 // with T = L/8 threads.  Each thread keeps E = 8 elements in registers in the
@@ -113,6 +114,19 @@ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 __device__ __forceinline__ int lds_slot(int a) { return a + (a >> 4); }
 constexpr int lds_slots(int L) { return L + L / 16; }
 
+// v * w for a twiddle w computed in FP64.  FP64 data: a complex product.  FP32
+// data: compensated product v (w_hi + w_lo) with w_hi = fl32(w) and
+// w_lo = fl32(w - w_hi), so the twiddle enters with FP64 accuracy and only the
+// FP32 arithmetic rounds.
+__device__ __forceinline__ double2 twmul(double2 v, double2 w) { return cmul(v, w); }
+__device__ __forceinline__ float2 twmul(float2 v, double2 w) {
+    const float hx = (float)w.x, hy = (float)w.y;
+    const float lx = (float)(w.x - (double)hx), ly = (float)(w.y - (double)hy);
+    const float2 a = cmul(v, make_float2(hx, hy));
+    const float2 b = cmul(v, make_float2(lx, ly));
+    return make_float2(a.x + b.x, a.y + b.y);
+}
+
 // Stage twiddle tables.  Stage s >= 1 is always radix 8 with Ns = R0 8^(s-1)
 // (R0 the radix of stage 0); its butterfly k needs W^r = exp(-+2 pi i r k / (8 Ns)),
 // r = 1..7.  Only the base W = exp(-2 pi i k / (8 Ns)), k in [0, Ns), is stored
@@ -135,8 +149,8 @@ constexpr int tw_slots() { return TwTab<L>::size; }
 
 // Build the stage tables in LDS from the full table tw[q] = exp(-2 pi i q / L);
 // visible to the FFT stages after the next barrier (stage 0 needs none).
-template <int L, typename C>
-__device__ __forceinline__ void load_twiddles(const C* __restrict__ tw, C* tab) {
+template <int L>
+__device__ __forceinline__ void load_twiddles(const double2* __restrict__ tw, double2* tab) {
     using TT = TwTab<L>;
     for (int i = threadIdx.x; i < TT::size; i += L / 8) {
         int s = 1;
@@ -152,7 +166,7 @@ __device__ __forceinline__ void load_twiddles(const C* __restrict__ tw, C* tab) 
 // are complete and visible (barrier).  Postcondition: if !LAST, this stage's
 // LDS writes are complete and visible; if LAST, the result is in reg.
 template <int L, int R, bool INV, bool FIRST, bool LAST, typename C>
-__device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, int toff, const C* tab) {
+__device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, int toff, const double2* tab) {
     constexpr int T = L / 8;
     constexpr int NB = 8 / R;          // butterflies per thread
     const int tid = threadIdx.x;
@@ -170,16 +184,16 @@ __device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, int toff,
         for (int r = 0; r < R; ++r) v[r] = reg[b + r * NB];
         if constexpr (!FIRST) {
             static_assert(R == 8, "stages after the first are radix 8");
-            const C t = tab[toff + k];
-            const C w1 = CplxOps<C>::make(t.x, INV ? -t.y : t.y);
-            const C w2 = cmul(w1, w1), w3 = cmul(w2, w1), w4 = cmul(w2, w2);
-            v[1] = cmul(v[1], w1);
-            v[2] = cmul(v[2], w2);
-            v[3] = cmul(v[3], w3);
-            v[4] = cmul(v[4], w4);
-            v[5] = cmul(v[5], cmul(w4, w1));
-            v[6] = cmul(v[6], cmul(w4, w2));
-            v[7] = cmul(v[7], cmul(w4, w3));
+            const double2 t = tab[toff + k];
+            const double2 w1 = make_double2(t.x, INV ? -t.y : t.y);
+            const double2 w2 = cmul(w1, w1), w3 = cmul(w2, w1), w4 = cmul(w2, w2);
+            v[1] = twmul(v[1], w1);
+            v[2] = twmul(v[2], w2);
+            v[3] = twmul(v[3], w3);
+            v[4] = twmul(v[4], w4);
+            v[5] = twmul(v[5], cmul(w4, w1));
+            v[6] = twmul(v[6], cmul(w4, w2));
+            v[7] = twmul(v[7], cmul(w4, w3));
         }
         dft<R, INV>(v);
         if constexpr (LAST) {
@@ -195,7 +209,7 @@ __device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, int toff,
 }
 
 template <int L, bool INV, int S, int NST, typename C>
-__device__ __forceinline__ void fft_stages(C (&reg)[8], C* lds, const C* tab) {
+__device__ __forceinline__ void fft_stages(C (&reg)[8], C* lds, const double2* tab) {
     using TT = TwTab<L>;
     constexpr int R = S == 0 ? TT::R0 : 8;
     fft_stage<L, R, INV, S == 0, S == NST - 1>(reg, lds, TT::ns(S), S == 0 ? 0 : TT::off(S), tab);
@@ -208,7 +222,7 @@ __device__ __forceinline__ void fft_stages(C (&reg)[8], C* lds, const C* tab) {
 // first stage needs no twiddles and its barrier publishes them.  After
 // return, other threads may still read LDS: barrier before reusing it.
 template <int L, bool INV, typename C>
-__device__ __forceinline__ void fft_block(C (&reg)[8], C* lds, const C* tab) {
+__device__ __forceinline__ void fft_block(C (&reg)[8], C* lds, const double2* tab) {
     constexpr int LOG = ilog2c(L);
     constexpr int NST = LOG / 3 + (LOG % 3 ? 1 : 0);
     static_assert((1 << LOG) == L && L >= 64, "L must be a power of two >= 64");

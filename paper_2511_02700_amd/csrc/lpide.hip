@@ -15,6 +15,8 @@
 // one-dimensional factors of D - r_omega without its mixed term.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -221,6 +223,12 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, siz
     if (i < cnt) b[i] = a[i];
 }
 
+// Round the FP64 spectrum to FP32 (mixed form).
+__global__ void k_to_f32(const double2* __restrict__ a, float2* __restrict__ b, size_t cnt) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+
 
 // ---------------------------------------------------------------------------
 // plan
@@ -237,11 +245,16 @@ struct Plan {
     int L = 0;        // FFT side (0 without jumps)
     int Lr = 0;       // threads x 8 of the row-pair kernels (L, or a power of two >= n without jumps)
     bool jumps = false;
+    bool mixed = false;            // FP32 iteration correlations (needs jumps)
     std::vector<void*> allocs;
     int64_t bytes = 0;
     double2* tw = nullptr;
     double2* spec = nullptr;
     double2* X = nullptr;
+    float2* X32 = nullptr;
+    float2* spec32 = nullptr;
+    double* BV = nullptr;
+    double* BY = nullptr;
     double* V0 = nullptr;
     double* pool[POOL] = {};
     double* Wb = nullptr;
@@ -370,6 +383,11 @@ MarchArgs march_args(const Plan* p) {
     a.tol = p->opts.tol;
     a.r_omega = p->hp.r_omega;
     a.st = stencil_of(p);
+    a.mixed = p->mixed ? 1 : 0;
+    a.X32 = p->X32;
+    a.spec32 = p->spec32;
+    a.BV = p->BV;
+    a.BY = p->BY;
     return a;
 }
 
@@ -398,17 +416,18 @@ void launch_rows_fwd(Plan* p, const double* Y) {
 }
 
 // ---- one time step of the device-controlled march ----
-template <int L, bool FFT>
+template <int L, bool FFT, bool MIXED>
 void launch_iteration(Plan* p, const MarchArgs& a, int k) {
     const int n = p->hp.n, np = (n + 1) / 2;
+    using C = typename std::conditional<MIXED, float2, double2>::type;
     p->tag_k = k;
     if (FFT) {
         {
             KTime t(p, LPIDE_K_COLS);
-            hipLaunchKernelGGL((ks_cols<L>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, a, k);
+            hipLaunchKernelGGL((ks_cols<L, C>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, a, k);
         }
         KTime t(p, LPIDE_K_ROWS_INV);
-        hipLaunchKernelGGL((ks_rows_inv<L, false>), dim3(np), dim3(L / 8), 0, p->stream, a, k);
+        hipLaunchKernelGGL((ks_rows_inv<L, MIXED ? 2 : 1>), dim3(np), dim3(L / 8), 0, p->stream, a, k);
     } else {
         KTime t(p, LPIDE_K_ROWS_INV);
         hipLaunchKernelGGL((ks_affine_noB<false>), dim3((n + 255) / 256, n), dim3(256), 0, p->stream, a, k);
@@ -419,37 +438,58 @@ void launch_iteration(Plan* p, const MarchArgs& a, int k) {
         hipLaunchKernelGGL(ks_line_cols, dim3((n + 3) / 4), dim3(4 * P), sizeof(double2) * 4 * P, p->stream, a, k);
     }
     KTime t(p, LPIDE_K_LINE_ROWS);
-    hipLaunchKernelGGL((ks_line_rows<L, FFT>), dim3(np), dim3(L / 8), 0, p->stream, a, k);
+    hipLaunchKernelGGL((ks_line_rows<L, FFT, MIXED>), dim3(np), dim3(L / 8), 0, p->stream, a, k);
 }
 
-template <int L, bool FFT>
+// One entry of the step list.  The FP64 correlation of V^{n-1} runs when the
+// explicit part needs it (theta < 1) and, in the mixed form, in every step
+// (B V^{n-1} anchors the FP32 increments); its row transform is left in X by
+// the previous step's last iteration in the FP64 form, and recomputed here in
+// the mixed form (where the iterations transform increments).
+template <int L, bool FFT, bool MIXED>
 void launch_step(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
     const int n = p->hp.n, np = (n + 1) / 2;
     p->tag_k = 0;
-    if (explicit_part) {
-        if (FFT) {
-            {
-                KTime t(p, LPIDE_K_COLS);
-                hipLaunchKernelGGL((ks_cols<L>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, a, 0);
-            }
-            KTime t(p, LPIDE_K_ROWS_INV);
-            hipLaunchKernelGGL((ks_rows_inv<L, true>), dim3(np), dim3(L / 8), 0, p->stream, a, 0);
-        } else {
-            KTime t(p, LPIDE_K_ROWS_INV);
-            hipLaunchKernelGGL((ks_affine_noB<true>), dim3((n + 255) / 256, n), dim3(256), 0, p->stream, a, 0);
+    if (FFT && (explicit_part || MIXED)) {
+        if (MIXED) {
+            KTime t(p, LPIDE_K_ROWS_FWD);
+            hipLaunchKernelGGL((ks_rows_fwd<L>), dim3(np), dim3(L / 8), 0, p->stream, a);
         }
+        {
+            KTime t(p, LPIDE_K_EXPL_COLS);
+            hipLaunchKernelGGL((ks_cols<L, double2>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, a, 0);
+        }
+        KTime t(p, LPIDE_K_EXPL_ROWS);
+        hipLaunchKernelGGL((ks_rows_inv<L, 0>), dim3(np), dim3(L / 8), 0, p->stream, a, 0);
+    } else if (explicit_part) {
+        KTime t(p, LPIDE_K_EXPL_ROWS);
+        hipLaunchKernelGGL((ks_affine_noB<true>), dim3((n + 255) / 256, n), dim3(256), 0, p->stream, a, 0);
     }
     {
         KTime t(p, LPIDE_K_SL);
         if (p->hp.sl_order == 1)
-            hipLaunchKernelGGL((ks_sl<L, 1, FFT>), dim3(np), dim3(L / 8), 0, p->stream, a);
+            hipLaunchKernelGGL((ks_sl<L, 1, FFT, MIXED>), dim3(np), dim3(L / 8), 0, p->stream, a);
         else
-            hipLaunchKernelGGL((ks_sl<L, 3, FFT>), dim3(np), dim3(L / 8), 0, p->stream, a);
+            hipLaunchKernelGGL((ks_sl<L, 3, FFT, MIXED>), dim3(np), dim3(L / 8), 0, p->stream, a);
     }
-    for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT>(p, a, k);
+    for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT, MIXED>(p, a, k);
     p->tag_k = 0;
     KTime t(p, LPIDE_K_STEP_END);
     hipLaunchKernelGGL(ks_step_end, dim3(1), dim3(64), 0, p->stream, a, kmax);
+}
+
+template <int L>
+void launch_step_L(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
+    if (!p->jumps) launch_step<L, false, false>(p, a, explicit_part, kmax);
+    else if (p->mixed) launch_step<L, true, true>(p, a, explicit_part, kmax);
+    else launch_step<L, true, false>(p, a, explicit_part, kmax);
+}
+
+template <int L>
+void launch_iteration_L(Plan* p, const MarchArgs& a, int k) {
+    if (!p->jumps) launch_iteration<L, false, false>(p, a, k);
+    else if (p->mixed) launch_iteration<L, true, true>(p, a, k);
+    else launch_iteration<L, true, false>(p, a, k);
 }
 
 #define LPIDE_SWITCH_L(Lv, FFTv, CALL)                                                   \
@@ -465,18 +505,16 @@ void launch_step(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
     }
 
 int issue_step(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
-#define CALL_STEP(Lc, Fc) launch_step<Lc, Fc>(p, a, explicit_part, kmax)
-    if (p->jumps) { LPIDE_SWITCH_L(p->Lr, true, CALL_STEP) }
-    else { LPIDE_SWITCH_L(p->Lr, false, CALL_STEP) }
+#define CALL_STEP(Lc, Fc) launch_step_L<Lc>(p, a, explicit_part, kmax)
+    LPIDE_SWITCH_L(p->Lr, true, CALL_STEP)
 #undef CALL_STEP
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
 }
 
 int issue_iteration(Plan* p, const MarchArgs& a, int k) {
-#define CALL_IT(Lc, Fc) launch_iteration<Lc, Fc>(p, a, k)
-    if (p->jumps) { LPIDE_SWITCH_L(p->Lr, true, CALL_IT) }
-    else { LPIDE_SWITCH_L(p->Lr, false, CALL_IT) }
+#define CALL_IT(Lc, Fc) launch_iteration_L<Lc>(p, a, k)
+    LPIDE_SWITCH_L(p->Lr, true, CALL_IT)
 #undef CALL_IT
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
@@ -548,7 +586,7 @@ int march(Plan* p, int count, double* v_out) {
     p->last_step_iters = 0;
     p->last_inc = 0;
     hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, p->stream, p->V0, p->pool[0], N);
-    if (p->jumps) {
+    if (p->jumps && !p->mixed) {          // the first step's explicit part reads the row FFT of V^0
         int rc = dispatch_rows_fwd(p, p->pool[0]);
         if (rc) return rc;
     }
@@ -714,7 +752,8 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     if (!(theta >= 0.0 && theta <= 1.0)) return fail(LPIDE_E_PARAM, "theta must lie in [0, 1]");
     if (M < 1) return fail(LPIDE_E_PARAM, "M (time steps) must be >= 1");
     if (!(o.tol > 0.0) || o.max_iter < 1) return fail(LPIDE_E_PARAM, "tol must be > 0 and max_iter >= 1");
-    if (o.precision != LPIDE_FP64) return fail(LPIDE_E_PARAM, "precision mode not available");
+    if (o.precision != LPIDE_FP64 && o.precision != LPIDE_FP32_CONV)
+        return fail(LPIDE_E_PARAM, "precision must be LPIDE_FP64 or LPIDE_FP32_CONV");
     if (o.max_iter > MAX_ITER_CAP) return fail(LPIDE_E_PARAM, "max_iter must not exceed 128");
     Plan* p = new Plan();
     std::string err;
@@ -727,6 +766,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     p->N_t = M;
     p->stream = static_cast<hipStream_t>(o.stream);
     p->jumps = p->hp.nts.jumps;
+    p->mixed = p->jumps && o.precision == LPIDE_FP32_CONV;
     p->L = p->hp.L;
     int rc = LPIDE_OK;
     auto bail = [&](int code) { destroy(p); return code; };
@@ -833,6 +873,16 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
         (void)hipFree(Xf);
         if (e != hipSuccess) return bail(fail(LPIDE_E_HIP, std::string("spectrum: ") + hipGetErrorString(e)));
         if (rc) return bail(rc);
+        if (p->mixed) {
+            const size_t ns = (size_t)(L / 2 + 1) * L;
+            if ((rc = dalloc(p, &p->spec32, ns)) || (rc = dalloc(p, &p->X32, (size_t)(L / 2 + 1) * n)) ||
+                (rc = dalloc(p, &p->BV, N)) || (rc = dalloc(p, &p->BY, N)))
+                return bail(rc);
+            hipLaunchKernelGGL(k_to_f32, dim3((ns + 255) / 256), dim3(256), 0, p->stream, p->spec, p->spec32, ns);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+            if (e != hipSuccess) return bail(fail(LPIDE_E_HIP, std::string("spectrum32: ") + hipGetErrorString(e)));
+        }
     }
     *out = p;
     return LPIDE_OK;

@@ -13,9 +13,18 @@
 // (then everything after it is a no-op until the host has added iterations).
 // All buffers are addressed through a control block updated only by step_end,
 // so the same launch sequence serves every step of a kind.
+//
+// Mixed form (FP32 correlation, FP64 everything else): each step first applies
+// B to V^{n-1} in FP64 (BV, and the explicit part), then the iteration
+// correlations run in FP32 on increments only: B Y^0 = BV + B32(Y^0 - V^{n-1})
+// and B Y^k = B Y^{k-1} + B32(delta^k), accumulated in FP64.  FP32 rounding is
+// thus relative to the increments, which shrink geometrically, and does not
+// accumulate across steps.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "fft.hpp"
 #include "kernels.hpp"
@@ -65,7 +74,19 @@ struct MarchArgs {
     double* incs;
     double tol, r_omega;
     StencilArgs st;
+    int mixed;                        // FP32 iteration correlations on increments
+    float2* X32;                      // FP32 intermediate (mixed form)
+    const float2* spec32;             // FP32 spectrum (mixed form)
+    double* BV;                       // B V^{n-1}, FP64 (mixed form)
+    double* BY;                       // B Y^k accumulated in FP64 (mixed form)
 };
+
+template <typename C> __device__ __forceinline__ C* xbuf(const MarchArgs& a);
+template <> __device__ __forceinline__ double2* xbuf<double2>(const MarchArgs& a) { return a.X; }
+template <> __device__ __forceinline__ float2* xbuf<float2>(const MarchArgs& a) { return a.X32; }
+template <typename C> __device__ __forceinline__ const C* specbuf(const MarchArgs& a);
+template <> __device__ __forceinline__ const double2* specbuf<double2>(const MarchArgs& a) { return a.spec; }
+template <> __device__ __forceinline__ const float2* specbuf<float2>(const MarchArgs& a) { return a.spec32; }
 
 __device__ __forceinline__ double bits_to_d(unsigned long long b) { return __longlong_as_double((long long)b); }
 
@@ -78,22 +99,23 @@ __device__ __forceinline__ bool halted(const MarchArgs& a, int k) {
 
 __device__ __forceinline__ const StepDesc& cur_set(const MarchArgs& a) { return a.sets[a.step_set[a.ctl->step]]; }
 
-// Column pass of B Y on the intermediate X (transposed half spectra).
-template <int L>
+// Column pass of the correlation on the intermediate X (transposed half
+// spectra), FP64 (C = double2) or FP32 (C = float2).
+template <int L, typename C>
 __global__ __launch_bounds__(L / 8) void ks_cols(MarchArgs a, int k) {
     if (halted(a, k)) return;
     constexpr int T = L / 8;
-    __shared__ double2 lds[lds_slots(L)];
+    __shared__ C lds[lds_slots(L)];
     __shared__ double2 tw4[tw_slots<L>()];
     load_twiddles<L>(a.tw, tw4);
     const int n = a.n, col = blockIdx.x, tid = threadIdx.x;
-    double2* xc = a.X + (size_t)col * n;
-    const double2* sc = a.spec + (size_t)col * L;
-    double2 reg[8], sp[8];
+    C* xc = xbuf<C>(a) + (size_t)col * n;
+    const C* sc = specbuf<C>(a) + (size_t)col * L;
+    C reg[8], sp[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int idx = tid + e * T;
-        reg[e] = idx < n ? xc[idx] : make_double2(0.0, 0.0);
+        reg[e] = idx < n ? xc[idx] : CplxOps<C>::make(0, 0);
         sp[e] = sc[idx];                  // spectrum fetched up front, used after the forward FFT
     }
     fft_block<L, false>(reg, lds, tw4);
@@ -107,14 +129,23 @@ __global__ __launch_bounds__(L / 8) void ks_cols(MarchArgs a, int k) {
     }
 }
 
-// Row inverse FFT of the pairs (2p, 2p+1) with the affine stencil epilogue:
-// EXPLICIT: out = V + dt(1-theta)((D - r_omega) V + B V)   (into R)
-// else:     out = W + dt theta((D - r_omega) Y + B Y) - Y  (into R)
-template <int L, bool EXPLICIT>
+// Forward FFT of the row pair (ra, ra+1) of the FP64 grid U at the step start
+// (mixed form: the FP64 correlation of V^{n-1}).
+template <int L>
+__global__ __launch_bounds__(L / 8) void ks_rows_fwd(MarchArgs a);
+
+// Row inverse FFT of the pairs (2p, 2p+1) with a fused epilogue.
+// MODE 0 (once per step, FP64): E = V + dt(1-theta)((D - r_omega) V + B V) into R
+//         (theta < 1), and B V into BV (mixed form);
+// MODE 1 (FP64 iteration):  R = W + dt theta((D - r_omega) Y + B Y) - Y;
+// MODE 2 (mixed iteration): B Y = (k == 1 ? BV : B Y) + B32(increment) into BY,
+//         then R as in MODE 1 with that B Y.
+template <int L, int MODE>
 __global__ __launch_bounds__(L / 8) void ks_rows_inv(MarchArgs a, int k) {
     if (halted(a, k)) return;
+    using C = typename std::conditional<MODE == 2, float2, double2>::type;
     constexpr int T = L / 8;
-    __shared__ double2 lds[lds_slots(L)];
+    __shared__ C lds[lds_slots(L)];
     __shared__ double2 tw4[tw_slots<L>()];
     load_twiddles<L>(a.tw, tw4);
     const int n = a.n, np = (n + 1) >> 1;
@@ -122,41 +153,51 @@ __global__ __launch_bounds__(L / 8) void ks_rows_inv(MarchArgs a, int k) {
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
     const int tid = threadIdx.x;
-    double2 reg[8];
+    const C* X = xbuf<C>(a);
+    C reg[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int idx = tid + e * T;
         const bool lo = idx <= L / 2;
         const int kk = lo ? idx : L - idx;
-        const double2* xk = a.X + (size_t)kk * n;
+        const C* xk = X + (size_t)kk * n;
         const bool real_bin = kk == 0 || kk == L / 2;  // imaginary parts dropped at DC and Nyquist
-        const double2 ta = xk[ra];
-        const double2 tb = hasb ? xk[rb] : make_double2(0.0, 0.0);
-        const double2 ha = make_double2(ta.x, real_bin ? 0.0 : ta.y);
-        const double2 hb = make_double2(tb.x, real_bin ? 0.0 : tb.y);
-        reg[e] = lo ? make_double2(ha.x - hb.y, ha.y + hb.x) : make_double2(ha.x + hb.y, hb.x - ha.y);
+        const C ta = xk[ra];
+        const C tb = hasb ? xk[rb] : CplxOps<C>::make(0, 0);
+        const C ha = CplxOps<C>::make(ta.x, real_bin ? 0 : ta.y);
+        const C hb = CplxOps<C>::make(tb.x, real_bin ? 0 : tb.y);
+        reg[e] = lo ? CplxOps<C>::make(ha.x - hb.y, ha.y + hb.x) : CplxOps<C>::make(ha.x + hb.y, hb.x - ha.y);
     }
     fft_block<L, true>(reg, lds, tw4);
     const StepDesc& sd = cur_set(a);
-    const double* U = EXPLICIT ? a.pool[a.ctl->cur] : a.pool[a.ctl->y];
-    const double* P0 = EXPLICIT ? U : a.W;
-    const double c = EXPLICIT ? sd.dt * (1.0 - sd.theta) : sd.dt * sd.theta;
-    const double c0 = EXPLICIT ? 0.0 : -1.0;
+    const double* U = MODE == 0 ? a.pool[a.ctl->cur] : a.pool[a.ctl->y];
+    const double* P0 = MODE == 0 ? U : a.W;
+    const double c = MODE == 0 ? sd.dt * (1.0 - sd.theta) : sd.dt * sd.theta;
+    const double c0 = MODE == 0 ? 0.0 : -1.0;
+    const bool want_r = MODE != 0 || sd.theta < 1.0;
+    const double* base = (MODE == 2 && k == 1) ? a.BV : a.BY;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int j = tid + e * T;
         if (j >= n) continue;
-        {
-            const size_t o = (size_t)ra * n + j;
-            const double u = U[o];
-            const double d = apply_D(U, a.st, ra, j, u);
-            a.R[o] = P0[o] + c * (d + reg[e].x - a.r_omega * u) + c0 * u;
-        }
-        if (hasb) {
-            const size_t o = (size_t)rb * n + j;
-            const double u = U[o];
-            const double d = apply_D(U, a.st, rb, j, u);
-            a.R[o] = P0[o] + c * (d + reg[e].y - a.r_omega * u) + c0 * u;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            if (r == 1 && !hasb) break;
+            const int i = ra + r;
+            const size_t o = (size_t)i * n + j;
+            double bu = r == 0 ? (double)reg[e].x : (double)reg[e].y;
+            if constexpr (MODE == 2) {
+                bu += base[o];
+                a.BY[o] = bu;
+            }
+            if constexpr (MODE == 0) {
+                if (a.mixed) a.BV[o] = bu;
+            }
+            if (want_r) {
+                const double u = U[o];
+                const double d = apply_D(U, a.st, i, j, u);
+                a.R[o] = P0[o] + c * (d + bu - a.r_omega * u) + c0 * u;
+            }
         }
     }
 }
@@ -182,10 +223,11 @@ __global__ void ks_affine_noB(MarchArgs a, int k) {
 
 // Forward FFT of the row pair held in reg (canonical layout) into the
 // transposed half spectra X[k2 * n + row].
-template <int L>
-__device__ __forceinline__ void rows_fwd_store(double2 (&reg)[8], double2* lds, const double2* tw4,
-                                               double2* __restrict__ X, int n, int ra, bool hasb) {
+template <int L, typename C>
+__device__ __forceinline__ void rows_fwd_store(C (&reg)[8], C* lds, const double2* tw4, C* __restrict__ X, int n,
+                                               int ra, bool hasb) {
     constexpr int T = L / 8;
+    using Rl = typename CplxOps<C>::real;
     const int tid = threadIdx.x;
     __syncthreads();
     fft_block<L, false>(reg, lds, tw4);
@@ -194,20 +236,44 @@ __device__ __forceinline__ void rows_fwd_store(double2 (&reg)[8], double2* lds, 
     for (int e = 0; e < 8; ++e) lds[tid + e * T] = reg[e];
     __syncthreads();
     for (int kk = tid; kk <= L / 2; kk += T) {
-        const double2 z = lds[kk], w = lds[(L - kk) & (L - 1)];
-        double2* xk = X + (size_t)kk * n;
-        xk[ra] = make_double2(0.5 * (z.x + w.x), 0.5 * (z.y - w.y));
-        if (hasb) xk[ra + 1] = make_double2(0.5 * (z.y + w.y), -0.5 * (z.x - w.x));
+        const C z = lds[kk], w = lds[(L - kk) & (L - 1)];
+        C* xk = X + (size_t)kk * n;
+        xk[ra] = CplxOps<C>::make(Rl(0.5) * (z.x + w.x), Rl(0.5) * (z.y - w.y));
+        if (hasb) xk[ra + 1] = CplxOps<C>::make(Rl(0.5) * (z.y + w.y), Rl(-0.5) * (z.x - w.x));
     }
 }
 
+template <int L>
+__global__ __launch_bounds__(L / 8) void ks_rows_fwd(MarchArgs a) {
+    if (halted(a, 0)) return;
+    constexpr int T = L / 8;
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L>()];
+    load_twiddles<L>(a.tw, tw4);
+    const int n = a.n, np = (n + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, np);
+    const int ra = 2 * p, rb = 2 * p + 1;
+    const bool hasb = rb < n;
+    const double* U = a.pool[a.ctl->cur];
+    double2 reg[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int j = threadIdx.x + e * T;
+        reg[e] = j < n ? make_double2(U[(size_t)ra * n + j], hasb ? U[(size_t)rb * n + j] : 0.0)
+                       : make_double2(0.0, 0.0);
+    }
+    rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
+}
+
 // Semi-Lagrangian gather W = (T_1 (x) T_2) E (order P), starting value Y^0 into
-// the iterate buffer, and (FFT) the row transform of Y^0; one row pair per block.
-template <int L, int P, bool FFT>
+// the iterate buffer, and (FFT) the row transform of Y^0 (FP64) or, in the
+// mixed form, of Y^0 - V^{n-1} (FP32); one row pair per block.
+template <int L, int P, bool FFT, bool MIXED>
 __global__ __launch_bounds__(L / 8) void ks_sl(MarchArgs a) {
     if (halted(a, 0)) return;
     constexpr int T = L / 8;
-    __shared__ double2 lds[FFT ? lds_slots(L) : 1];
+    using C = typename std::conditional<MIXED, float2, double2>::type;
+    __shared__ C lds[FFT ? lds_slots(L) : 1];
     __shared__ double2 tw4[FFT ? tw_slots<L>() : 1];
     if constexpr (FFT) load_twiddles<L>(a.tw, tw4);
     const int n = a.n, np = (n + 1) >> 1;
@@ -227,7 +293,8 @@ __global__ __launch_bounds__(L / 8) void ks_sl(MarchArgs a) {
         H[q] = a.pool[c->src[q]];
         cf[q] = c->coef[q];
     }
-    double2 reg[8];
+    const double* V = a.pool[c->cur];
+    C reg[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int j = tid + e * T;
@@ -255,12 +322,12 @@ __global__ __launch_bounds__(L / 8) void ks_sl(MarchArgs a) {
                 double yv = 0.0;
                 for (int q = 0; q < nsrc; ++q) yv += cf[q] * H[q][o];
                 Y[o] = yv;
-                y0[r] = yv;
+                y0[r] = MIXED ? yv - V[o] : yv;
             }
         }
-        reg[e] = make_double2(y0[0], y0[1]);
+        reg[e] = CplxOps<C>::make(y0[0], y0[1]);
     }
-    if constexpr (FFT) rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
+    if constexpr (FFT) rows_fwd_store<L>(reg, lds, tw4, xbuf<C>(a), n, ra, hasb);
 }
 
 // Axis-1 line solves R <- T_1^{-1} R: 4 adjacent columns x P chunks per block
@@ -286,11 +353,12 @@ __global__ __launch_bounds__(1024) void ks_line_cols(MarchArgs a, int k) {
 
 // Axis-2 line solves of a row pair, the update Y += delta, the stopping-rule
 // maximum err_k = max |delta| / max(1, |Y|), and (FFT) the row transform of the
-// updated Y for the next iteration.
-template <int L, bool FFT>
+// updated Y (FP64) or, in the mixed form, of delta (FP32) for the next iteration.
+template <int L, bool FFT, bool MIXED>
 __global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
     if (halted(a, k)) return;
     constexpr int T = L / 8, PR = T / 2;
+    using C = typename std::conditional<MIXED, float2, double2>::type;
     // union: row buffer 2 (n + PR + 1) doubles | scan totals | FFT exchange buffer
     __shared__ double2 lds[L + L / 16 + 2];
     __shared__ double2 tw4[FFT ? tw_slots<L>() : 1];
@@ -323,20 +391,20 @@ __global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
     __syncthreads();
     double* Y = a.pool[a.ctl->y];
     double emax = 0.0;
-    double2 reg[8];
+    C reg[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int j = tid + e * T;
-        double ya = 0.0, yb = 0.0;
+        double ya = 0.0, yb = 0.0, da = 0.0, db = 0.0;
         if (j < n) {
-            const double da = rows[j + j / m];
+            da = rows[j + j / m];
             const size_t oa = (size_t)ra * n + j;
             ya = Y[oa] + da;
             Y[oa] = ya;
             double ev = fabs(da) / fmax(1.0, fabs(ya));
             emax = (ev > emax || ev != ev) ? ev : emax;
             if (hasb) {
-                const double db = rows[stride + j + j / m];
+                db = rows[stride + j + j / m];
                 const size_t ob = (size_t)rb * n + j;
                 yb = Y[ob] + db;
                 Y[ob] = yb;
@@ -344,7 +412,7 @@ __global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
                 emax = (ev > emax || ev != ev) ? ev : emax;
             }
         }
-        reg[e] = make_double2(ya, yb);
+        reg[e] = MIXED ? CplxOps<C>::make(da, db) : CplxOps<C>::make(ya, yb);
     }
     // wave maximum over the block's active lanes (T may be below 64), one atomic
     // per wave (non-negative doubles order like their bit patterns; NaN sorts
@@ -356,7 +424,7 @@ __global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
         emax = (o > emax || o != o) ? o : emax;
     }
     if ((tid & 63) == 0) atomicMax(&a.ctl->err[k], (unsigned long long)__double_as_longlong(emax));
-    if constexpr (FFT) rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
+    if constexpr (FFT) rows_fwd_store<L>(reg, reinterpret_cast<C*>(lds), tw4, xbuf<C>(a), n, ra, hasb);
 }
 
 // End of a step: convergence verdict, history rotation, next starting value.
