@@ -60,12 +60,48 @@ def algorithmic_bytes(cls, n, L, mixed=False):
     }[cls]
 
 
-def roofline(cls, n, L, mixed, launches, ms):
+def kernel_symbol(cls, L, mixed, sl_order):
+    """The kernel instantiation a timing class launches in the march."""
+    tf = "true" if mixed else "false"
+    c = "float" if mixed and cls == "cols" else "double"
+    return {
+        "cols": "lpide::ks_cols<%d, HIP_vector_type<%s, 2u> >" % (L, c),
+        "expl_cols": "lpide::ks_cols<%d, HIP_vector_type<double, 2u> >" % L,
+        "rows_inv": "lpide::ks_rows_inv<%d, %d>" % (L, 2 if mixed else 1),
+        "expl_rows": "lpide::ks_rows_inv<%d, 0>" % L,
+        "line_cols": "lpide::ks_line_cols",
+        "line_rows": "lpide::ks_line_rows<%d, true, %s>" % (L, tf),
+        "sl": "lpide::ks_sl<%d, %d, true, %s>" % (L, sl_order, tf),
+        "step_end": "lpide::ks_step_end",
+        "rows_fwd": "lpide::ks_rows_fwd<%d>" % L,
+    }[cls]
+
+
+def measured_traffic(path, symbol):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when there
+    is none or the device sources changed since the counters were taken."""
+    if not path or not os.path.exists(path):
+        return None
+    from paper_2511_02700_amd import profsum
+    with open(path) as fh:
+        s = json.load(fh)
+    if s.get("source_sha256") != profsum.source_digest():
+        return None
+    for k, v in s["kernels"].items():
+        bare = k[5:] if k.startswith("void ") else k
+        if bare.startswith(symbol + "(") or bare == symbol:
+            return v["hbm_bytes"]
+    return None
+
+
+def roofline(cls, n, L, mixed, launches, ms, traffic_json=None, sl_order=3):
     per_launch_ms = ms / max(1, launches)
     b = algorithmic_bytes(cls, n, L, mixed)
     achieved = b / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
-    return {"kernel": cls, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": b,
+    sym = kernel_symbol(cls, L, mixed, sl_order)
+    return {"kernel": cls, "symbol": sym, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(traffic_json, sym), "bytes_per_launch": b,
             "mean_launch_ms": per_launch_ms, "launches": launches}
 
 
@@ -120,6 +156,9 @@ def main():
                     help="form timed for the headline value; the other form is timed beside it")
     ap.add_argument("--cpu-steps", type=int, default=8, help="step-list entries of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=None,
+                    help="rocprofv3 counter summary (profsum pmc --json) giving measured HBM bytes per launch; "
+                         "default profiles/pmc_<workload>.json")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this solver has no multi-GPU path); got --gpus %d" % args.gpus,
@@ -132,6 +171,7 @@ def main():
     import workloads
 
     rank = int(os.environ.get("RANK", "0"))
+    tj = args.traffic_json or os.path.join(ROOT, "profiles", "pmc_%s.json" % args.workload)
     w = workloads.workload(args.workload)
     n, Nt = w["n"], w["N_t"]
     other = "fp32conv" if args.precision == "fp64" else "fp64"
@@ -192,12 +232,13 @@ def main():
                                    args.sl_order, args.precision),
                    "n": n, "N_t": Nt, "L": L, "N_z": info["N_z"], "precision": args.precision,
                    "parallelism": "single GPU"},
-        "roofline": roofline(dominant, n, L, mixed, *live[dominant]),
-        "conv_roofline": roofline("cols", n, L, mixed, *live["cols"]),
+        "roofline": roofline(dominant, n, L, mixed, *live[dominant], traffic_json=tj, sl_order=args.sl_order),
+        "conv_roofline": roofline("cols", n, L, mixed, *live["cols"], traffic_json=tj, sl_order=args.sl_order),
         "iters_per_step": info["total_iters"] / info["n_steps"],
         "kernel_ms_per_solve": {c: prof[c][1] for c in prof if prof[c][0]},
         other: {"value": n * n * Nt * args.steps / wall_o, "ms_per_step": 1e3 * wall_o / args.steps,
-                "conv_roofline": roofline("cols", n, L, other == "fp32conv", *live_o["cols"]),
+                "conv_roofline": roofline("cols", n, L, other == "fp32conv", *live_o["cols"], traffic_json=tj,
+                                          sl_order=args.sl_order),
                 "iters_per_step": plans[other].info()["total_iters"] / info["n_steps"]},
         "mixed_vs_plain_rel": {"prices": rel_p, "deltas_abs": abs_d, "grid": rel_grid, "spots": 64,
                                "bound": 1e-6},

@@ -1,0 +1,176 @@
+"""Summaries of rocprofv3 output for the solver's kernels (text for the
+profile records, JSON for bench.py's measured-traffic field).
+
+    python -m paper_2511_02700_amd.profsum stats DIR
+        kernel table (calls, mean/min/max duration, total, share) from the
+        *_kernel_stats.csv that `rocprofv3 --kernel-trace --stats
+        --output-format csv -d DIR -o run` writes.
+
+    python -m paper_2511_02700_amd.profsum pmc FETCH_DIR WRITE_DIR [--json OUT]
+        per-kernel FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two
+        `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs, calibrated by
+        the plain copy kernel k_copy of the same runs (one FP64 value per
+        thread: known bytes = 8 x grid size).  Dispatches of a kernel that read
+        or wrote less than 5% of that kernel's largest dispatch are early-exit
+        launches (iterations after convergence) and are left out of the mean.
+"""
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# kernel-name prefixes of the march kernels -> the timing classes of the C ABI
+# (the template arguments tell the FP64 and mixed instantiations apart)
+CLASS_OF = [
+    ("lpide::ks_cols<", "cols"),
+    ("lpide::ks_rows_inv<", "rows_inv"),
+    ("lpide::ks_line_cols", "line_cols"),
+    ("lpide::ks_line_rows<", "line_rows"),
+    ("lpide::ks_sl<", "sl"),
+    ("lpide::ks_step_end", "step_end"),
+    ("lpide::ks_rows_fwd<", "rows_fwd"),
+]
+
+
+def source_digest():
+    """SHA-256 over the device sources: the measured traffic of a kernel is
+    valid only for the sources it was measured on."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            with open(f, "rb") as fh:
+                h.update(os.path.basename(f).encode())
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def _one(pattern):
+    hits = sorted(glob.glob(pattern, recursive=True))
+    if not hits:
+        raise SystemExit("no file matches " + pattern)
+    return hits[0]
+
+
+def kernel_stats(d):
+    path = _one(os.path.join(d, "**", "*kernel_stats.csv"))
+    rows = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]), float(r["AverageNs"]),
+                         float(r["MinNs"]), float(r["MaxNs"]), float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[2])
+    return rows
+
+
+def active_durations(d):
+    """Per kernel: (calls, active calls, mean active duration in us) from the
+    kernel trace.  Active = at least a quarter of the median of the kernel's
+    upper half of durations, which separates the early-exit launches (about
+    1 us) of iterations after convergence from the launches that work."""
+    path = _one(os.path.join(d, "**", "*kernel_trace.csv"))
+    per = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            per.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out = {}
+    for k, ds in per.items():
+        s = sorted(ds)
+        up = s[len(s) // 2:]
+        thr = 0.25 * up[len(up) // 2]
+        act = [x for x in ds if x >= thr]
+        out[k] = (len(ds), len(act), sum(act) / len(act) / 1e3)
+    return out
+
+
+def print_stats(d, out=sys.stdout):
+    rows = kernel_stats(d)
+    act = active_durations(d)
+    tot = sum(r[2] for r in rows)
+    out.write("%-64s %7s %9s %9s %9s %10s %6s %7s %13s\n" % ("kernel", "calls", "avg_us", "min_us", "max_us",
+                                                             "total_ms", "pct", "active", "active_avg_us"))
+    for name, calls, t, avg, mn, mx, pct in rows:
+        a = act.get(name, (calls, calls, avg / 1e3))
+        out.write("%-64s %7d %9.2f %9.2f %9.2f %10.2f %6.2f %7d %13.2f\n" % (name[:64], calls, avg / 1e3, mn / 1e3,
+                                                                             mx / 1e3, t / 1e6, pct, a[1], a[2]))
+    out.write("total kernel time %.2f ms\n" % (tot / 1e6))
+
+
+def counters(d, counter):
+    path = _one(os.path.join(d, "**", "*counter_collection.csv"))
+    per = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            per.setdefault(r["Kernel_Name"], []).append((float(r["Counter_Value"]), int(r["Grid_Size"])))
+    return per
+
+
+def _active_mean(vals):
+    top = max(v for v, _ in vals)
+    act = [v for v, _ in vals if v >= 0.05 * top]
+    return (sum(act) / len(act) if act else 0.0), len(act), len(vals)
+
+
+def pmc_summary(fetch_dir, write_dir):
+    fetch, write = counters(fetch_dir, "FETCH_SIZE"), counters(write_dir, "WRITE_SIZE")
+    cal = {}
+    for nm, per, key in (("FETCH_SIZE", fetch, "read"), ("WRITE_SIZE", write, "write")):
+        copies = [(v, g) for k, vals in per.items() if k.startswith(("k_copy", "void k_copy")) for v, g in vals]
+        big = max(copies, key=lambda x: x[1]) if copies else None
+        if big is None or big[0] <= 0:
+            raise SystemExit("no k_copy dispatch to calibrate " + nm)
+        # bytes the copy must move per counter KiB
+        cal[key] = {"copy_bytes": 8 * big[1], "counter_kib": big[0], "scale": 8 * big[1] / (1024.0 * big[0])}
+    kernels = {}
+    for k in sorted(set(fetch) | set(write)):
+        bare = k[5:] if k.startswith("void ") else k
+        cls = next((c for p, c in CLASS_OF if bare.startswith(p)), None)
+        f = _active_mean(fetch[k]) if k in fetch else (0.0, 0, 0)
+        w = _active_mean(write[k]) if k in write else (0.0, 0, 0)
+        kernels[k] = {"class": cls, "fetch_kib": f[0], "write_kib": w[0], "dispatches": f[2],
+                      "active_dispatches": f[1],
+                      "hbm_bytes": 1024.0 * (f[0] * cal["read"]["scale"] + w[0] * cal["write"]["scale"])}
+    return {"calibration": cal, "kernels": kernels, "source_sha256": source_digest()}
+
+
+def print_pmc(s, out=sys.stdout):
+    c = s["calibration"]
+    out.write("calibration (k_copy): read %d B -> FETCH_SIZE %.1f KiB (scale %.4f); write %d B -> WRITE_SIZE %.1f KiB "
+              "(scale %.4f)\n" % (c["read"]["copy_bytes"], c["read"]["counter_kib"], c["read"]["scale"],
+                                  c["write"]["copy_bytes"], c["write"]["counter_kib"], c["write"]["scale"]))
+    out.write("%-64s %9s %12s %12s %14s\n" % ("kernel", "active", "FETCH_KiB", "WRITE_KiB", "HBM_MB/launch"))
+    for k, v in sorted(s["kernels"].items(), key=lambda kv: -kv[1]["hbm_bytes"]):
+        out.write("%-64s %4d/%-4d %12.1f %12.1f %14.3f\n" % (k[:64], v["active_dispatches"], v["dispatches"],
+                                                             v["fetch_kib"], v["write_kib"], v["hbm_bytes"] / 1e6))
+    out.write("device sources sha256 %s\n" % s["source_sha256"])
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("dir")
+    b = sub.add_parser("pmc")
+    b.add_argument("fetch_dir")
+    b.add_argument("write_dir")
+    b.add_argument("--json")
+    args = ap.parse_args(argv)
+    if args.cmd == "stats":
+        print_stats(args.dir)
+    else:
+        s = pmc_summary(args.fetch_dir, args.write_dir)
+        print_pmc(s)
+        if args.json:
+            with open(args.json, "w") as fh:
+                json.dump(s, fh, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()
