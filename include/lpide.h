@@ -220,6 +220,57 @@ int lpide_timing(void* plan, uint32_t class_mask);
  * plan's stream. */
 int lpide_kernel_stats(void* plan, int64_t* launches, double* ms);
 
+/* ---- Batched form ----
+ * Many independent plans (different grids, Levy parameters, pay-offs, step
+ * counts) marched together.  Plans with the same row-kernel size (lpide_info.L,
+ * or the power of two >= n without jumps), jump switch, precision and SL order
+ * form a group: every march kernel is launched once for the whole group
+ * (one grid, the plan in the second grid dimension), each plan converging and
+ * stopping on its own.  Each group runs on a stream of its own, and the host
+ * interleaves the groups.  With use_graph, a group's step slots (one step of
+ * every plan each) are captured once in a hipGraph and replayed. */
+typedef struct {
+    int32_t use_graph;   /* 1: replay captured hipGraphs of the step slots (default) */
+    int32_t slots;       /* step slots enqueued between host checks, 1..256 (default 32) */
+    void*   stream;      /* hipStream_t of the caller: the batch's work starts after the work
+                            queued on it before lpide_batch_solve, and later work on it waits for
+                            the batch (NULL: the null stream) */
+} lpide_batch_opts;
+
+typedef struct {
+    int32_t n_plans, L, mixed;        /* plans of the group, row-kernel size, mixed form */
+    int32_t P_cols, slots, use_graph; /* launch configuration (set by lpide_batch_tune) */
+    double  trial_ms;                 /* wall time of the tuning trial kept (0 before tuning) */
+} lpide_group_info;
+
+void lpide_batch_opts_default(lpide_batch_opts* o);
+
+/* Create a batch over count plans (host array of handles from
+ * lpide_plan_create, all on one device).  The plans stay owned by the caller,
+ * must outlive the batch and must not be used concurrently with it. */
+int lpide_batch_create(int32_t count, void* const* plans, const lpide_batch_opts* opts, void** out);
+int lpide_batch_destroy(void* batch);
+
+/* March every plan over its whole step list (Algorithm 1 per plan).  v_out:
+ * host array of count device pointers, plan i's n_i * n_i FP64 result.
+ * Returns when the results are queued on the caller's stream.  Errors as
+ * lpide_solve, for the first plan that fails. */
+int lpide_batch_solve(void* batch, double* const* v_out);
+
+/* As lpide_batch_solve over the first min(steps, n_steps_i) entries of each
+ * step list; v_out may be NULL (results not copied: timing and tuning). */
+int lpide_batch_solve_steps(void* batch, int32_t steps, double* const* v_out);
+
+/* Autotuner: for each group, time the march of the first trial_steps entries
+ * under every candidate launch configuration (axis-1 line-solve chunking
+ * P_cols in {P/2, P, 2P} around the default P, hipGraph replay on/off, 16 or
+ * 32 step slots per host check), each run twice with the second timed, and
+ * keep the fastest.  Synchronises the device work of the batch. */
+int lpide_batch_tune(void* batch, int32_t trial_steps);
+
+/* Groups of the batch: *n_groups, and up to cap entries of groups (may be NULL). */
+int lpide_batch_info(void* batch, int32_t* n_groups, lpide_group_info* groups, int32_t cap);
+
 /* Thread-local description of the last error on the calling thread. */
 const char* lpide_last_error(void);
 

@@ -51,6 +51,18 @@ class Info(C.Structure):
         return out
 
 
+class BatchOpts(C.Structure):
+    _fields_ = [("use_graph", C.c_int32), ("slots", C.c_int32), ("stream", C.c_void_p)]
+
+
+class GroupInfo(C.Structure):
+    _fields_ = [("n_plans", C.c_int32), ("L", C.c_int32), ("mixed", C.c_int32), ("P_cols", C.c_int32),
+                ("slots", C.c_int32), ("use_graph", C.c_int32), ("trial_ms", C.c_double)]
+
+    def to_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # exported symbol -> (restype, argtypes)
 SIGNATURES = {
     "lpide_grid_default": (None, [C.POINTER(Grid), C.c_int32, C.c_double, C.c_double]),
@@ -69,6 +81,14 @@ SIGNATURES = {
                                         C.c_void_p, C.c_int64, C.c_void_p]),
     "lpide_timing": (C.c_int, [C.c_void_p, C.c_uint32]),
     "lpide_kernel_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "lpide_batch_opts_default": (None, [C.POINTER(BatchOpts)]),
+    "lpide_batch_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(BatchOpts),
+                                     C.POINTER(C.c_void_p)]),
+    "lpide_batch_destroy": (C.c_int, [C.c_void_p]),
+    "lpide_batch_solve": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lpide_batch_solve_steps": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "lpide_batch_tune": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lpide_batch_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(GroupInfo), C.c_int32]),
     "lpide_last_error": (C.c_char_p, []),
 }
 

@@ -170,6 +170,69 @@ class Plan:
         return (pr, dl) if with_delta else pr
 
 
+class Batch:
+    """Many plans marched together (see lpide_batch_create).  The plans must
+    stay alive while the batch is used; results are torch float64 tensors."""
+
+    def __init__(self, plans, use_graph=True, slots=32, stream=None):
+        torch = _torch()
+        if not plans:
+            raise ValueError("empty batch")
+        self.plans = list(plans)
+        self.device = self.plans[0].device
+        o = _lib.BatchOpts()
+        lib().lpide_batch_opts_default(C.byref(o))
+        o.use_graph, o.slots = (1 if use_graph else 0), slots
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        o.stream = C.c_void_p(stream.cuda_stream)
+        hs = (C.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().lpide_batch_create(len(self.plans), hs, C.byref(o), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().lpide_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _outs(self, outs):
+        if outs is None:
+            outs = [p._grid_tensor() for p in self.plans]
+        for p, o in zip(self.plans, outs):
+            p._grid_tensor(o)
+        return outs, (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+
+    def solve(self, outs=None):
+        outs, ptrs = self._outs(outs)
+        check(lib().lpide_batch_solve(self._h, ptrs))
+        return outs
+
+    def solve_steps(self, steps, outs=None):
+        outs, ptrs = self._outs(outs)
+        check(lib().lpide_batch_solve_steps(self._h, int(steps), ptrs))
+        return outs
+
+    def tune(self, trial_steps=12):
+        check(lib().lpide_batch_tune(self._h, int(trial_steps)))
+        return self.groups()
+
+    def groups(self):
+        n = C.c_int32()
+        check(lib().lpide_batch_info(self._h, C.byref(n), None, 0))
+        arr = (_lib.GroupInfo * max(1, n.value))()
+        check(lib().lpide_batch_info(self._h, C.byref(n), arr, n.value))
+        return [arr[i].to_dict() for i in range(n.value)]
+
+
 def plan_from_workload(w, device=0, **over):
     """A Plan for a workload dict of ``workloads.WORKLOADS`` (pure data)."""
     m = w["model"]

@@ -18,6 +18,7 @@
 #include <type_traits>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -235,6 +236,46 @@ __global__ void k_to_f32(const double2* __restrict__ a, float2* __restrict__ b, 
 // ---------------------------------------------------------------------------
 namespace {
 
+struct Plan;
+
+// Launch shape of a group of plans that share the transform size: the march
+// kernels run one grid for all of them (blockIdx.y = plan).
+struct Launch {
+    hipStream_t stream = nullptr;
+    const MarchArgs* A = nullptr;   // device array, np entries
+    int np = 0;
+    int L = 0;                      // Lr of the plans (threads x 8 of the row kernels)
+    int xrows = 0;                  // max row pairs
+    int xcols = 0;                  // max 4-column groups of the axis-1 line solves
+    int xaff = 0;                   // max rows (affine kernels without jumps)
+    int P_cols = 16;
+    int sl_order = 3;
+    bool jumps = false, mixed = false;
+    Plan* timer = nullptr;          // records kernel timing (single-plan marches only)
+};
+
+// Control state of a march over a group: one control block and per-step
+// statistics per plan, with pinned host mirrors.
+struct Group {
+    std::vector<Plan*> plans;
+    Launch lc;
+    std::vector<MarchArgs> args_h;
+    MarchArgs* A = nullptr;
+    Ctl* ctl = nullptr;
+    Ctl* ctl_h = nullptr;
+    int* counts = nullptr;          // np x maxsteps
+    double* incs = nullptr;
+    std::vector<int> counts_h;
+    std::vector<double> incs_h;
+    int maxsteps = 0;
+    bool use_graph = false;
+    int slots = 32;                 // step slots enqueued between host checks
+    struct G { int kmax, nslots; hipGraphExec_t exec; };
+    std::vector<G> graphs;
+    std::vector<void*> allocs;
+    double tuned_ms = 0.0;
+};
+
 struct Plan {
     HostPlan hp;
     lpide_opts opts{};
@@ -259,18 +300,14 @@ struct Plan {
     double* pool[POOL] = {};
     double* Wb = nullptr;
     double* Rb = nullptr;
-    Ctl* ctl = nullptr;
-    Ctl* ctl_h = nullptr;          // pinned mirror for the host checks
-    int* counts = nullptr;         // per-step iteration counts (device)
-    double* incs = nullptr;
-    std::vector<int> counts_h;
-    std::vector<double> incs_h;
     StepDesc* sets_d = nullptr;
     int* step_set_d = nullptr;
     std::vector<StepDesc> sets;
     std::vector<int> step_set;
     int n_steps = 0;
     int P_cols = 16;
+    Group* solo = nullptr;         // this plan alone, on its own stream
+    std::vector<int> counts_h;     // per-step iteration counts of the last march
     // kernel timing (HIP events on the plan's stream around each timed launch)
     uint32_t time_mask = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -304,7 +341,7 @@ hipEvent_t next_event(Plan* p) {
     return p->ev_pool[p->ev_used++];
 }
 
-KTime::KTime(Plan* pl, int c) : p(pl), on((pl->time_mask >> c) & 1u) {
+KTime::KTime(Plan* pl, int c) : p(pl), on(pl && ((pl->time_mask >> c) & 1u)) {
     if (!on) return;
     idx = p->ev_used;
     hipEvent_t a = next_event(p), b = next_event(p);
@@ -317,13 +354,18 @@ KTime::~KTime() {
 }
 
 // Fold recorded event pairs into the per-class totals (synchronises the stream).
-// Launches of iterations after a step had converged (they return at once) are
-// left out, so the totals describe executed launches only.
+// Launches of iterations after a step had converged, and per-step kernels that
+// had nothing to do (explicit part of a theta = 1 step), are left out, so the
+// totals describe working launches only.
 int harvest_times(Plan* p) {
     if (p->ev_recs.empty()) return LPIDE_OK;
     HIP_TRY(hipStreamSynchronize(p->stream));
     for (auto& r : p->ev_recs) {
-        if (r.k > 0 && r.step >= 0 && r.step < (int)p->counts_h.size() && r.k > p->counts_h[r.step]) continue;
+        const bool known = r.step >= 0 && r.step < (int)p->counts_h.size();
+        if (r.k > 0 && known && r.k > p->counts_h[r.step]) continue;
+        if ((r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS) && known && !p->mixed &&
+            p->sets[p->step_set[r.step]].theta >= 1.0)
+            continue;
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[r.idx], p->ev_pool[r.idx + 1]));
         p->k_launch[r.cls] += 1;
@@ -335,15 +377,18 @@ int harvest_times(Plan* p) {
 }
 
 template <typename Tp>
-int dalloc(Plan* p, Tp** out, size_t count) {
+int dalloc_into(std::vector<void*>& allocs, int64_t* bytes, Tp** out, size_t count) {
     void* d = nullptr;
-    hipError_t e = hipMalloc(&d, count * sizeof(Tp));
+    hipError_t e = hipMalloc(&d, std::max<size_t>(1, count) * sizeof(Tp));
     if (e != hipSuccess) return fail(LPIDE_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    p->allocs.push_back(d);
-    p->bytes += int64_t(count * sizeof(Tp));
+    allocs.push_back(d);
+    if (bytes) *bytes += int64_t(count * sizeof(Tp));
     *out = static_cast<Tp*>(d);
     return LPIDE_OK;
 }
+
+template <typename Tp>
+int dalloc(Plan* p, Tp** out, size_t count) { return dalloc_into(p->allocs, &p->bytes, out, count); }
 
 template <typename Tp>
 int upload(Plan* p, Tp** out, const std::vector<Tp>& v) {
@@ -363,9 +408,9 @@ StencilArgs stencil_of(const Plan* p) {
     return s;
 }
 
+// The plan's march arguments (control pointers are filled in by its group).
 MarchArgs march_args(const Plan* p) {
-    MarchArgs a;
-    a.ctl = p->ctl;
+    MarchArgs a{};
     for (int b = 0; b < POOL; ++b) a.pool[b] = p->pool[b];
     a.sets = p->sets_d;
     a.step_set = p->step_set_d;
@@ -378,8 +423,6 @@ MarchArgs march_args(const Plan* p) {
     a.X = p->X;
     a.spec = p->spec;
     a.tw = p->tw;
-    a.counts = p->counts;
-    a.incs = p->incs;
     a.tol = p->opts.tol;
     a.r_omega = p->hp.r_omega;
     a.st = stencil_of(p);
@@ -388,6 +431,8 @@ MarchArgs march_args(const Plan* p) {
     a.spec32 = p->spec32;
     a.BV = p->BV;
     a.BY = p->BY;
+    a.nsteps = p->n_steps;
+    a.step0 = 0;
     return a;
 }
 
@@ -410,159 +455,262 @@ void launch_spectrum(Plan* p, const double* G, double2* Xfull) {
 }
 
 template <int L>
-void launch_rows_fwd(Plan* p, const double* Y) {
+void launch_rows_fwd(Plan* p, const double* Y, hipStream_t s) {
     const int n = p->hp.n;
-    hipLaunchKernelGGL((k_rows_fwd<L>), dim3((n + 1) / 2), dim3(L / 8), 0, p->stream, Y, n, n, n, p->X, n, p->tw);
+    hipLaunchKernelGGL((k_rows_fwd<L>), dim3((n + 1) / 2), dim3(L / 8), 0, s, Y, n, n, n, p->X, n, p->tw);
 }
 
-// ---- one time step of the device-controlled march ----
+// ---- one step slot of the device-controlled march, for a group of plans ----
 template <int L, bool FFT, bool MIXED>
-void launch_iteration(Plan* p, const MarchArgs& a, int k) {
-    const int n = p->hp.n, np = (n + 1) / 2;
+void launch_iteration(const Launch& c, int k) {
     using C = typename std::conditional<MIXED, float2, double2>::type;
-    p->tag_k = k;
+    if (c.timer) c.timer->tag_k = k;
+    const dim3 gr(c.xrows, c.np), gc(L / 2 + 1, c.np);
     if (FFT) {
         {
-            KTime t(p, LPIDE_K_COLS);
-            hipLaunchKernelGGL((ks_cols<L, C>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, a, k);
+            KTime t(c.timer, LPIDE_K_COLS);
+            hipLaunchKernelGGL((ks_cols<L, C>), gc, dim3(L / 8), 0, c.stream, c.A, k);
         }
-        KTime t(p, LPIDE_K_ROWS_INV);
-        hipLaunchKernelGGL((ks_rows_inv<L, MIXED ? 2 : 1>), dim3(np), dim3(L / 8), 0, p->stream, a, k);
+        KTime t(c.timer, LPIDE_K_ROWS_INV);
+        hipLaunchKernelGGL((ks_rows_inv<L, MIXED ? 2 : 1>), gr, dim3(L / 8), 0, c.stream, c.A, k);
     } else {
-        KTime t(p, LPIDE_K_ROWS_INV);
-        hipLaunchKernelGGL((ks_affine_noB<false>), dim3((n + 255) / 256, n), dim3(256), 0, p->stream, a, k);
+        KTime t(c.timer, LPIDE_K_ROWS_INV);
+        hipLaunchKernelGGL((ks_affine_noB<false>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, k);
     }
     {
-        KTime t(p, LPIDE_K_LINE_COLS);
-        const int P = p->P_cols;
-        hipLaunchKernelGGL(ks_line_cols, dim3((n + 3) / 4), dim3(4 * P), sizeof(double2) * 4 * P, p->stream, a, k);
+        KTime t(c.timer, LPIDE_K_LINE_COLS);
+        hipLaunchKernelGGL(ks_line_cols, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
+                           c.stream, c.A, k);
     }
-    KTime t(p, LPIDE_K_LINE_ROWS);
-    hipLaunchKernelGGL((ks_line_rows<L, FFT, MIXED>), dim3(np), dim3(L / 8), 0, p->stream, a, k);
+    KTime t(c.timer, LPIDE_K_LINE_ROWS);
+    hipLaunchKernelGGL((ks_line_rows<L, FFT, MIXED>), gr, dim3(L / 8), 0, c.stream, c.A, k);
 }
 
-// One entry of the step list.  The FP64 correlation of V^{n-1} runs when the
-// explicit part needs it (theta < 1) and, in the mixed form, in every step
-// (B V^{n-1} anchors the FP32 increments); its row transform is left in X by
-// the previous step's last iteration in the FP64 form, and recomputed here in
-// the mixed form (where the iterations transform increments).
+// One entry of every plan's step list.  The FP64 correlation of V^{n-1} runs
+// when the explicit part needs it (theta < 1) and, in the mixed form, in every
+// step (B V^{n-1} anchors the FP32 increments); the kernels decide on the
+// device, so the launch sequence is the same for every step.  In the FP64
+// form the row transform of V^{n-1} is left in X by the previous step's last
+// iteration; the mixed form recomputes it (its iterations transform increments).
 template <int L, bool FFT, bool MIXED>
-void launch_step(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
-    const int n = p->hp.n, np = (n + 1) / 2;
-    p->tag_k = 0;
-    if (FFT && (explicit_part || MIXED)) {
+void launch_step(const Launch& c, int kmax) {
+    if (c.timer) c.timer->tag_k = 0;
+    const dim3 gr(c.xrows, c.np), gc(L / 2 + 1, c.np);
+    if (FFT) {
         if (MIXED) {
-            KTime t(p, LPIDE_K_ROWS_FWD);
-            hipLaunchKernelGGL((ks_rows_fwd<L>), dim3(np), dim3(L / 8), 0, p->stream, a);
+            KTime t(c.timer, LPIDE_K_ROWS_FWD);
+            hipLaunchKernelGGL((ks_rows_fwd<L>), gr, dim3(L / 8), 0, c.stream, c.A);
         }
         {
-            KTime t(p, LPIDE_K_EXPL_COLS);
-            hipLaunchKernelGGL((ks_cols<L, double2>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, a, 0);
+            KTime t(c.timer, LPIDE_K_EXPL_COLS);
+            hipLaunchKernelGGL((ks_cols<L, double2>), gc, dim3(L / 8), 0, c.stream, c.A, 0);
         }
-        KTime t(p, LPIDE_K_EXPL_ROWS);
-        hipLaunchKernelGGL((ks_rows_inv<L, 0>), dim3(np), dim3(L / 8), 0, p->stream, a, 0);
-    } else if (explicit_part) {
-        KTime t(p, LPIDE_K_EXPL_ROWS);
-        hipLaunchKernelGGL((ks_affine_noB<true>), dim3((n + 255) / 256, n), dim3(256), 0, p->stream, a, 0);
+        KTime t(c.timer, LPIDE_K_EXPL_ROWS);
+        hipLaunchKernelGGL((ks_rows_inv<L, 0>), gr, dim3(L / 8), 0, c.stream, c.A, 0);
+    } else {
+        KTime t(c.timer, LPIDE_K_EXPL_ROWS);
+        hipLaunchKernelGGL((ks_affine_noB<true>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, 0);
     }
     {
-        KTime t(p, LPIDE_K_SL);
-        if (p->hp.sl_order == 1)
-            hipLaunchKernelGGL((ks_sl<L, 1, FFT, MIXED>), dim3(np), dim3(L / 8), 0, p->stream, a);
+        KTime t(c.timer, LPIDE_K_SL);
+        if (c.sl_order == 1)
+            hipLaunchKernelGGL((ks_sl<L, 1, FFT, MIXED>), gr, dim3(L / 8), 0, c.stream, c.A);
         else
-            hipLaunchKernelGGL((ks_sl<L, 3, FFT, MIXED>), dim3(np), dim3(L / 8), 0, p->stream, a);
+            hipLaunchKernelGGL((ks_sl<L, 3, FFT, MIXED>), gr, dim3(L / 8), 0, c.stream, c.A);
     }
-    for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT, MIXED>(p, a, k);
-    p->tag_k = 0;
-    KTime t(p, LPIDE_K_STEP_END);
-    hipLaunchKernelGGL(ks_step_end, dim3(1), dim3(64), 0, p->stream, a, kmax);
+    for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT, MIXED>(c, k);
+    if (c.timer) c.timer->tag_k = 0;
+    KTime t(c.timer, LPIDE_K_STEP_END);
+    hipLaunchKernelGGL(ks_step_end, dim3(1, c.np), dim3(64), 0, c.stream, c.A, kmax);
 }
 
 template <int L>
-void launch_step_L(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
-    if (!p->jumps) launch_step<L, false, false>(p, a, explicit_part, kmax);
-    else if (p->mixed) launch_step<L, true, true>(p, a, explicit_part, kmax);
-    else launch_step<L, true, false>(p, a, explicit_part, kmax);
+void launch_slots_L(const Launch& c, int first_tag, int nslots, int kmax) {
+    for (int s = 0; s < nslots; ++s) {
+        if (c.timer) c.timer->tag_step = first_tag + s;
+        if (!c.jumps) launch_step<L, false, false>(c, kmax);
+        else if (c.mixed) launch_step<L, true, true>(c, kmax);
+        else launch_step<L, true, false>(c, kmax);
+    }
 }
 
 template <int L>
-void launch_iteration_L(Plan* p, const MarchArgs& a, int k) {
-    if (!p->jumps) launch_iteration<L, false, false>(p, a, k);
-    else if (p->mixed) launch_iteration<L, true, true>(p, a, k);
-    else launch_iteration<L, true, false>(p, a, k);
+void launch_iteration_L(const Launch& c, int k) {
+    if (!c.jumps) launch_iteration<L, false, false>(c, k);
+    else if (c.mixed) launch_iteration<L, true, true>(c, k);
+    else launch_iteration<L, true, false>(c, k);
 }
 
-#define LPIDE_SWITCH_L(Lv, FFTv, CALL)                                                   \
+#define LPIDE_SWITCH_L(Lv, CALL)                                                         \
     switch (Lv) {                                                                       \
-        case 64: CALL(64, FFTv); break;                                                 \
-        case 128: CALL(128, FFTv); break;                                               \
-        case 256: CALL(256, FFTv); break;                                               \
-        case 512: CALL(512, FFTv); break;                                               \
-        case 1024: CALL(1024, FFTv); break;                                             \
-        case 2048: CALL(2048, FFTv); break;                                             \
-        case 4096: CALL(4096, FFTv); break;                                             \
+        case 64: CALL(64); break;                                                       \
+        case 128: CALL(128); break;                                                     \
+        case 256: CALL(256); break;                                                     \
+        case 512: CALL(512); break;                                                     \
+        case 1024: CALL(1024); break;                                                   \
+        case 2048: CALL(2048); break;                                                   \
+        case 4096: CALL(4096); break;                                                   \
         default: return fail(LPIDE_E_PARAM, "unsupported transform size");              \
     }
 
-int issue_step(Plan* p, const MarchArgs& a, bool explicit_part, int kmax) {
-#define CALL_STEP(Lc, Fc) launch_step_L<Lc>(p, a, explicit_part, kmax)
-    LPIDE_SWITCH_L(p->Lr, true, CALL_STEP)
-#undef CALL_STEP
+int issue_slots(const Launch& c, int first_tag, int nslots, int kmax) {
+#define CALL_SLOTS(Lc) launch_slots_L<Lc>(c, first_tag, nslots, kmax)
+    LPIDE_SWITCH_L(c.L, CALL_SLOTS)
+#undef CALL_SLOTS
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
 }
 
-int issue_iteration(Plan* p, const MarchArgs& a, int k) {
-#define CALL_IT(Lc, Fc) launch_iteration_L<Lc>(p, a, k)
-    LPIDE_SWITCH_L(p->Lr, true, CALL_IT)
+int issue_iteration(const Launch& c, int k) {
+#define CALL_IT(Lc) launch_iteration_L<Lc>(c, k)
+    LPIDE_SWITCH_L(c.L, CALL_IT)
 #undef CALL_IT
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
 }
 
 int dispatch_conv(Plan* p, const double* Y, double* out) {
-#define CALL_CONV(Lc, Fc) launch_conv<Lc>(p, Y, out)
-    LPIDE_SWITCH_L(p->L, true, CALL_CONV)
+#define CALL_CONV(Lc) launch_conv<Lc>(p, Y, out)
+    LPIDE_SWITCH_L(p->L, CALL_CONV)
 #undef CALL_CONV
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
 }
 
 int dispatch_spectrum(Plan* p, const double* G, double2* Xfull) {
-#define CALL_SPEC(Lc, Fc) launch_spectrum<Lc>(p, G, Xfull)
-    LPIDE_SWITCH_L(p->L, true, CALL_SPEC)
+#define CALL_SPEC(Lc) launch_spectrum<Lc>(p, G, Xfull)
+    LPIDE_SWITCH_L(p->L, CALL_SPEC)
 #undef CALL_SPEC
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
 }
 
-int dispatch_rows_fwd(Plan* p, const double* Y) {
-#define CALL_RF(Lc, Fc) launch_rows_fwd<Lc>(p, Y)
-    LPIDE_SWITCH_L(p->L, true, CALL_RF)
+int dispatch_rows_fwd(Plan* p, const double* Y, hipStream_t s) {
+#define CALL_RF(Lc) launch_rows_fwd<Lc>(p, Y, s)
+    LPIDE_SWITCH_L(p->L, CALL_RF)
 #undef CALL_RF
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
 }
 
-void destroy(Plan* p) {
-    if (!p) return;
-    (void)hipStreamSynchronize(p->stream);
-    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-    for (void* a : p->allocs) (void)hipFree(a);
-    if (p->ctl_h) (void)hipHostFree(p->ctl_h);
-    delete p;
+// ---- groups ----
+void destroy_group(Group* g) {
+    if (!g) return;
+    if (g->lc.stream) (void)hipStreamSynchronize(g->lc.stream);
+    for (auto& x : g->graphs) (void)hipGraphExecDestroy(x.exec);
+    for (void* a : g->allocs) (void)hipFree(a);
+    if (g->ctl_h) (void)hipHostFree(g->ctl_h);
+    delete g;
 }
 
-// Read the control block and the per-step statistics of steps [s0, s1).
-int read_back(Plan* p, int s0, int s1) {
-    HIP_TRY(hipMemcpyAsync(p->ctl_h, p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
-    if (s1 > s0) {
-        HIP_TRY(hipMemcpyAsync(p->counts_h.data() + s0, p->counts + s0, sizeof(int) * (s1 - s0),
-                               hipMemcpyDeviceToHost, p->stream));
-        HIP_TRY(hipMemcpyAsync(p->incs_h.data() + s0, p->incs + s0, sizeof(double) * (s1 - s0),
-                               hipMemcpyDeviceToHost, p->stream));
+// Launch shape of the axis-1 line solves: 4 columns per block, chunks of about
+// 8 rows, P_cols a power of two in [16, 256].
+int default_P_cols(int n) {
+    int P = 16;
+    while (P < 256 && (n + P - 1) / P > 8) P *= 2;
+    return P;
+}
+
+bool P_cols_valid(int n, int P) { return P >= 16 && P <= 256 && (n + P - 1) / P <= LINE_MM; }
+
+// A group over plans that share Lr, the jump switch, the precision and the SL
+// order; the kernels run on `stream`.
+int make_group(const std::vector<Plan*>& plans, hipStream_t stream, Group** out) {
+    Group* g = new Group();
+    g->plans = plans;
+    const int np = int(plans.size());
+    Launch& c = g->lc;
+    c.stream = stream;
+    c.np = np;
+    c.L = plans[0]->Lr;
+    c.jumps = plans[0]->jumps;
+    c.mixed = plans[0]->mixed;
+    c.sl_order = plans[0]->hp.sl_order;
+    int nmax = 0;
+    for (Plan* p : plans) {
+        nmax = std::max(nmax, p->hp.n);
+        g->maxsteps = std::max(g->maxsteps, p->n_steps);
     }
-    HIP_TRY(hipStreamSynchronize(p->stream));
+    c.xrows = (nmax + 1) / 2;
+    c.xcols = (nmax + 3) / 4;
+    c.xaff = nmax;
+    c.P_cols = default_P_cols(nmax);
+    int rc = LPIDE_OK;
+    if ((rc = dalloc_into(g->allocs, nullptr, &g->A, np)) || (rc = dalloc_into(g->allocs, nullptr, &g->ctl, np)) ||
+        (rc = dalloc_into(g->allocs, nullptr, &g->counts, (size_t)np * g->maxsteps)) ||
+        (rc = dalloc_into(g->allocs, nullptr, &g->incs, (size_t)np * g->maxsteps))) {
+        destroy_group(g);
+        return rc;
+    }
+    if (hipHostMalloc((void**)&g->ctl_h, sizeof(Ctl) * np, hipHostMallocDefault) != hipSuccess) {
+        destroy_group(g);
+        return fail(LPIDE_E_OOM, "hipHostMalloc failed");
+    }
+    std::memset(g->ctl_h, 0, sizeof(Ctl) * np);
+    g->counts_h.assign((size_t)np * g->maxsteps, 0);
+    g->incs_h.assign((size_t)np * g->maxsteps, 0.0);
+    g->args_h.resize(np);
+    for (int i = 0; i < np; ++i) {
+        MarchArgs a = march_args(plans[i]);
+        a.ctl = g->ctl + i;
+        a.counts = g->counts + (size_t)i * g->maxsteps;
+        a.incs = g->incs + (size_t)i * g->maxsteps;
+        a.P_cols = c.P_cols;
+        g->args_h[i] = a;
+    }
+    *out = g;
+    return LPIDE_OK;
+}
+
+void drop_graphs(Group* g) {
+    for (auto& x : g->graphs) (void)hipGraphExecDestroy(x.exec);
+    g->graphs.clear();
+}
+
+// Set the axis-1 line-solve chunking of every plan of the group.
+int set_P_cols(Group* g, int P) {
+    for (Plan* p : g->plans)
+        if (!P_cols_valid(p->hp.n, P)) return fail(LPIDE_E_PARAM, "P_cols not valid for the grid size");
+    g->lc.P_cols = P;
+    for (auto& a : g->args_h) a.P_cols = P;
+    drop_graphs(g);
+    return LPIDE_OK;
+}
+
+// Enqueue nslots step slots with kmax iterations each: replay of a captured
+// graph when the group uses graphs (and no timing is on), else direct launches.
+int enqueue_slots(Group* g, int first_tag, int nslots, int kmax) {
+    if (!g->use_graph || g->lc.timer) return issue_slots(g->lc, first_tag, nslots, kmax);
+    hipGraphExec_t exec = nullptr;
+    for (auto& x : g->graphs)
+        if (x.kmax == kmax && x.nslots == nslots) exec = x.exec;
+    if (!exec) {
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(g->lc.stream, hipStreamCaptureModeThreadLocal));
+        int rc = issue_slots(g->lc, first_tag, nslots, kmax);
+        hipError_t e = hipStreamEndCapture(g->lc.stream, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(LPIDE_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(LPIDE_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        g->graphs.push_back({kmax, nslots, exec});
+    }
+    HIP_TRY(hipGraphLaunch(exec, g->lc.stream));
+    return LPIDE_OK;
+}
+
+// Read every plan's control block and per-step statistics.
+int read_back(Group* g) {
+    const int np = g->lc.np;
+    hipStream_t s = g->lc.stream;
+    HIP_TRY(hipMemcpyAsync(g->ctl_h, g->ctl, sizeof(Ctl) * np, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->counts_h.data(), g->counts, sizeof(int) * g->counts_h.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->incs_h.data(), g->incs, sizeof(double) * g->incs_h.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return LPIDE_OK;
 }
 
@@ -572,91 +720,238 @@ double bits_d(unsigned long long b) {
     return d;
 }
 
-// March the first `count` entries of the step list from V^0; result in v_out.
-// Steps are enqueued in batches without waiting; each step launches kmax
-// iterations (a running prediction), of which those after convergence exit at
-// once.  A step that needs more is completed by extra iterations enqueued one
-// at a time after the batch (the steps behind it were no-ops).
-int march(Plan* p, int count, double* v_out) {
-    const int n = p->hp.n;
-    const size_t N = (size_t)n * n;
-    const MarchArgs a = march_args(p);
-    p->total_iters = 0;
-    p->max_step_iters = 0;
-    p->last_step_iters = 0;
-    p->last_inc = 0;
-    hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, p->stream, p->V0, p->pool[0], N);
-    if (p->jumps && !p->mixed) {          // the first step's explicit part reads the row FFT of V^0
-        int rc = dispatch_rows_fwd(p, p->pool[0]);
-        if (rc) return rc;
+// Complete the current step of plan i, whose predicted iterations did not
+// reach tol: the other plans are held while iterations are added one at a
+// time (each followed by the step verdict).  Returns the iterations used.
+int complete_step(Group* g, int i, int kused, int* k_out) {
+    const Launch& c = g->lc;
+    Plan* p = g->plans[i];
+    hipLaunchKernelGGL(ks_hold, dim3(1), dim3(256), 0, c.stream, c.A, c.np, i);
+    int k = kused;
+    const int sf = g->ctl_h[i].fail_step;
+    int rc = LPIDE_OK;
+    for (;;) {
+        const double ek = bits_d(g->ctl_h[i].err[k]);
+        if (!std::isfinite(ek)) {
+            rc = fail(LPIDE_E_NAN, "non-finite fixed-point increment in step " + std::to_string(sf));
+            break;
+        }
+        if (k >= p->opts.max_iter) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "fixed point not converged in step %d after %d iterations (increment %.3e)", sf,
+                     k, ek);
+            rc = fail(LPIDE_E_NOCONV, buf);
+            break;
+        }
+        ++k;
+        hipLaunchKernelGGL(ks_clear_fail, dim3(1), dim3(64), 0, c.stream, c.A, i);
+        if (c.timer) c.timer->tag_step = sf;
+        if ((rc = issue_iteration(c, k))) break;
+        hipLaunchKernelGGL(ks_step_end, dim3(1, c.np), dim3(64), 0, c.stream, c.A, k);
+        if ((rc = read_back(g))) break;
+        if (!g->ctl_h[i].fail) break;
     }
-    hipLaunchKernelGGL(ks_init, dim3(1), dim3(64), 0, p->stream, a);
-    HIP_TRY(hipGetLastError());
-    const int nsets = int(p->sets.size());
-    std::vector<int> kpred(nsets, std::min(8, p->opts.max_iter));
-    std::vector<int> kused(count, 0);
-    const int batch = 32;
-    int done = 0;
-    while (done < count) {
-        const int s1 = std::min(count, done + batch);
-        for (int s = done; s < s1; ++s) {
-            const int id = p->step_set[s];
-            kused[s] = kpred[id];
-            p->tag_step = s;
-            int rc = issue_step(p, a, p->sets[id].theta < 1.0, kpred[id]);
+    hipLaunchKernelGGL(ks_hold, dim3(1), dim3(256), 0, c.stream, c.A, c.np, -1);
+    if (rc == LPIDE_OK) HIP_TRY(hipGetLastError());
+    *k_out = k;
+    return rc;
+}
+
+// March plan i of the group over step-list entries [step0, nsteps[i]) from
+// the state v_in[i] (V^0 when v_in is null), all plans together; the results
+// go to v_out[i].  Steps are enqueued in slots without waiting; each slot
+// launches kmax iterations (a running prediction), of which those after
+// convergence exit at once.  A plan whose step needs more is completed by
+// extra iterations while the others are held (the slots behind it were no-ops
+// for it, and are enqueued again).  The march is split in phases so that a
+// batch can interleave its groups: begin, then enqueue/check until done, end.
+struct MarchState {
+    std::vector<int> nsteps, at;
+    int step0 = 0, kpred = 8, maxit = 1;
+    bool done = false;
+};
+
+int march_begin(Group* g, MarchState& st, const int* nsteps, int step0, const double* const* v_in) {
+    const int np = g->lc.np;
+    hipStream_t s = g->lc.stream;
+    st.nsteps.assign(nsteps, nsteps + np);
+    st.at.assign(np, step0);
+    st.step0 = step0;
+    st.done = false;
+    for (int i = 0; i < np; ++i) {
+        Plan* p = g->plans[i];
+        const int n = p->hp.n;
+        const size_t N = (size_t)n * n;
+        if (nsteps[i] < step0 || nsteps[i] > p->n_steps) return fail(LPIDE_E_PARAM, "steps out of range");
+        g->args_h[i].nsteps = nsteps[i];
+        g->args_h[i].step0 = step0;
+        const double* src = v_in ? v_in[i] : p->V0;
+        hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, s, src, p->pool[0], N);
+        if (p->jumps && !p->mixed) {     // the first explicit part reads the row FFT of the start state
+            int rc = dispatch_rows_fwd(p, p->pool[0], s);
             if (rc) return rc;
         }
-        int rc = read_back(p, done, s1);
-        if (rc) return rc;
-        if (p->ctl_h->fail) {
-            const int sf = p->ctl_h->fail_step;
-            int k = kused[sf];
-            for (;;) {
-                double ek = bits_d(p->ctl_h->err[k]);
-                if (!std::isfinite(ek)) return fail(LPIDE_E_NAN, "non-finite fixed-point increment in step " +
-                                                                     std::to_string(sf));
-                if (k >= p->opts.max_iter) {
-                    char buf[160];
-                    snprintf(buf, sizeof buf, "fixed point not converged in step %d after %d iterations (increment %.3e)",
-                             sf, k, ek);
-                    return fail(LPIDE_E_NOCONV, buf);
-                }
-                ++k;
-                hipLaunchKernelGGL(ks_clear_fail, dim3(1), dim3(64), 0, p->stream, a);
-                p->tag_step = sf;
-                rc = issue_iteration(p, a, k);
-                if (rc) return rc;
-                hipLaunchKernelGGL(ks_step_end, dim3(1), dim3(64), 0, p->stream, a, k);
-                HIP_TRY(hipGetLastError());
-                rc = read_back(p, sf, sf + 1);
-                if (rc) return rc;
-                if (!p->ctl_h->fail) break;
-            }
-            kused[sf] = k;
-            kpred[p->step_set[sf]] = std::min(p->opts.max_iter, k);
-        }
-        const int reached = p->ctl_h->step;
-        // next prediction per set: the largest count among this batch's completed steps
-        for (int id = 0; id < nsets; ++id) {
-            int mx = 0;
-            for (int s = done; s < reached; ++s)
-                if (p->step_set[s] == id) mx = std::max(mx, p->counts_h[s]);
-            if (mx > 0) kpred[id] = std::min(p->opts.max_iter, mx);
-        }
-        done = reached;
     }
-    for (int s = 0; s < count; ++s) {
-        p->total_iters += p->counts_h[s];
-        p->max_step_iters = std::max(p->max_step_iters, p->counts_h[s]);
-    }
-    if (count > 0) {
-        p->last_step_iters = p->counts_h[count - 1];
-        p->last_inc = p->incs_h[count - 1];
-    }
-    const int last = count > 0 ? p->ctl_h->cur : 0;   // V^0 sits in pool[0] before any step
-    hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, p->stream, p->pool[last], v_out, N);
+    HIP_TRY(hipMemcpyAsync(g->A, g->args_h.data(), sizeof(MarchArgs) * np, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(ks_init, dim3(1, np), dim3(64), 0, s, g->A);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(p->stream));
+    g->lc.A = g->A;
+    st.maxit = 1;
+    for (Plan* p : g->plans) st.maxit = std::max(st.maxit, p->opts.max_iter);
+    st.kpred = std::min(8, st.maxit);
+    return LPIDE_OK;
+}
+
+int march_enqueue(Group* g, MarchState& st) {
+    int remaining = 0;
+    for (int i = 0; i < g->lc.np; ++i) remaining = std::max(remaining, st.nsteps[i] - st.at[i]);
+    if (remaining == 0) {
+        st.done = true;
+        return LPIDE_OK;
+    }
+    return enqueue_slots(g, st.at[0], std::min(g->slots, remaining), st.kpred);
+}
+
+int march_check(Group* g, MarchState& st) {
+    if (st.done) return LPIDE_OK;
+    const int np = g->lc.np;
+    int rc = read_back(g);
+    if (rc) return rc;
+    int knext = 0;
+    for (int i = 0; i < np; ++i) {
+        if (g->ctl_h[i].fail) {
+            int k = 0;
+            if ((rc = complete_step(g, i, st.kpred, &k))) return rc;
+            knext = std::max(knext, k);
+        }
+    }
+    bool all = true;
+    for (int i = 0; i < np; ++i) {
+        const int reached = g->ctl_h[i].step;
+        for (int q = st.at[i]; q < reached; ++q) knext = std::max(knext, g->counts_h[(size_t)i * g->maxsteps + q]);
+        st.at[i] = reached;
+        all = all && reached >= st.nsteps[i];
+    }
+    if (knext > 0) st.kpred = std::min(st.maxit, knext);
+    st.done = all;
+    return LPIDE_OK;
+}
+
+int march_end(Group* g, MarchState& st, double* const* v_out) {
+    hipStream_t s = g->lc.stream;
+    for (int i = 0; i < g->lc.np; ++i) {
+        Plan* p = g->plans[i];
+        const size_t N = (size_t)p->hp.n * p->hp.n;
+        const int n1 = st.nsteps[i];
+        p->counts_h.assign(p->n_steps, 0);
+        p->total_iters = 0;
+        p->max_step_iters = 0;
+        p->last_step_iters = 0;
+        p->last_inc = 0;
+        for (int q = st.step0; q < n1; ++q) {
+            const int cnt = g->counts_h[(size_t)i * g->maxsteps + q];
+            p->counts_h[q] = cnt;
+            p->total_iters += cnt;
+            p->max_step_iters = std::max(p->max_step_iters, cnt);
+        }
+        if (n1 > st.step0) {
+            p->last_step_iters = g->counts_h[(size_t)i * g->maxsteps + n1 - 1];
+            p->last_inc = g->incs_h[(size_t)i * g->maxsteps + n1 - 1];
+        }
+        const int last = n1 > st.step0 ? g->ctl_h[i].cur : 0;   // the start state sits in pool[0]
+        if (v_out && v_out[i])
+            hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, s, p->pool[last], v_out[i], N);
+    }
+    HIP_TRY(hipGetLastError());
+    return LPIDE_OK;
+}
+
+int march_group(Group* g, const int* nsteps, int step0, const double* const* v_in, double* const* v_out) {
+    MarchState st;
+    int rc = march_begin(g, st, nsteps, step0, v_in);
+    while (!rc && !st.done) {
+        rc = march_enqueue(g, st);
+        if (!rc) rc = march_check(g, st);
+    }
+    if (!rc) rc = march_end(g, st, v_out);
+    if (!rc) HIP_TRY(hipStreamSynchronize(g->lc.stream));
+    return rc;
+}
+
+// March of one plan alone (its solo group on the plan's stream).
+int march(Plan* p, int count, double* v_out) {
+    Group* g = p->solo;
+    g->lc.timer = p->time_mask ? p : nullptr;
+    return march_group(g, &count, 0, nullptr, &v_out);
+}
+
+void destroy(Plan* p) {
+    if (!p) return;
+    (void)hipStreamSynchronize(p->stream);
+    destroy_group(p->solo);
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    for (void* a : p->allocs) (void)hipFree(a);
+    delete p;
+}
+
+// ---- batches ----
+struct Batch {
+    std::vector<Plan*> plans;
+    std::vector<Group*> groups;
+    std::vector<std::vector<int>> members;     // plan indices of each group
+    std::vector<hipStream_t> streams;          // one per group
+    std::vector<hipEvent_t> events;            // one per group + 1
+    hipStream_t caller = nullptr;
+    bool tuned = false;
+};
+
+void destroy_batch(Batch* b) {
+    if (!b) return;
+    for (Group* g : b->groups) destroy_group(g);
+    for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+    delete b;
+}
+
+// March every plan of the batch over its whole step list (or its first
+// steps_cap entries); groups run on their own streams, joined to the caller's
+// stream before and after.  The host interleaves the groups: it enqueues a
+// round of slots for every group, then checks each group (waiting only on
+// that group's stream), so the device overlaps the groups.
+int batch_march(Batch* b, double* const* v_out, int steps_cap) {
+    const int ng = int(b->groups.size());
+    HIP_TRY(hipEventRecord(b->events[ng], b->caller));
+    for (int q = 0; q < ng; ++q) HIP_TRY(hipStreamWaitEvent(b->streams[q], b->events[ng], 0));
+    std::vector<MarchState> st(ng);
+    for (int q = 0; q < ng; ++q) {
+        std::vector<int> ns;
+        for (int i : b->members[q])
+            ns.push_back(steps_cap >= 0 ? std::min(steps_cap, b->plans[i]->n_steps) : b->plans[i]->n_steps);
+        int rc = march_begin(b->groups[q], st[q], ns.data(), 0, nullptr);
+        if (rc) return rc;
+    }
+    for (;;) {
+        bool all = true;
+        for (int q = 0; q < ng; ++q) {
+            if (st[q].done) continue;
+            int rc = march_enqueue(b->groups[q], st[q]);
+            if (rc) return rc;
+        }
+        for (int q = 0; q < ng; ++q) {
+            int rc = march_check(b->groups[q], st[q]);
+            if (rc) return rc;
+            all = all && st[q].done;
+        }
+        if (all) break;
+    }
+    for (int q = 0; q < ng; ++q) {
+        std::vector<double*> outs;
+        for (int i : b->members[q]) outs.push_back(v_out ? v_out[i] : nullptr);
+        int rc = march_end(b->groups[q], st[q], outs.data());
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(b->events[q], b->streams[q]));
+    }
+    for (int q = 0; q < ng; ++q) HIP_TRY(hipStreamWaitEvent(b->caller, b->events[q], 0));
     return LPIDE_OK;
 }
 
@@ -784,13 +1079,9 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
         if ((rc = dalloc(p, &p->pool[b], N))) return bail(rc);
     if ((rc = dalloc(p, &p->Wb, N))) return bail(rc);
     if ((rc = dalloc(p, &p->Rb, N))) return bail(rc);
-    if ((rc = dalloc(p, &p->ctl, 1))) return bail(rc);
-    if (hipHostMalloc((void**)&p->ctl_h, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
-        return bail(fail(LPIDE_E_OOM, "hipHostMalloc failed"));
     // axis-1 line solves: 4 columns per block, chunks of about 8 rows
-    p->P_cols = 16;
-    while (p->P_cols < 256 && (n + p->P_cols - 1) / p->P_cols > 8) p->P_cols *= 2;
-    if ((n + p->P_cols - 1) / p->P_cols > LINE_MM) return bail(fail(LPIDE_E_PARAM, "n too large for the line solves"));
+    p->P_cols = default_P_cols(n);
+    if (!P_cols_valid(n, p->P_cols)) return bail(fail(LPIDE_E_PARAM, "n too large for the line solves"));
     // threads x 8 of the row-pair kernels
     p->Lr = p->L;
     if (!p->jumps) {
@@ -834,9 +1125,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
             p->step_set.push_back(id);
         }
         if ((rc = upload(p, &p->sets_d, p->sets)) || (rc = upload(p, &p->step_set_d, p->step_set))) return bail(rc);
-        if ((rc = dalloc(p, &p->counts, p->n_steps)) || (rc = dalloc(p, &p->incs, p->n_steps))) return bail(rc);
         p->counts_h.assign(p->n_steps, 0);
-        p->incs_h.assign(p->n_steps, 0.0);
     }
     // kernel spectrum conj(FFT(K placed at d mod L)) / L^2
     if (p->jumps) {
@@ -884,6 +1173,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
             if (e != hipSuccess) return bail(fail(LPIDE_E_HIP, std::string("spectrum32: ") + hipGetErrorString(e)));
         }
     }
+    if ((rc = make_group(std::vector<Plan*>{p}, p->stream, &p->solo))) return bail(rc);
     *out = p;
     return LPIDE_OK;
 }
@@ -987,6 +1277,155 @@ int lpide_kernel_stats(void* plan, int64_t* launches, double* ms) {
     for (int c = 0; c < LPIDE_KCLASSES; ++c) {
         launches[c] = p->k_launch[c];
         ms[c] = p->k_ms[c];
+    }
+    return LPIDE_OK;
+}
+
+void lpide_batch_opts_default(lpide_batch_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->use_graph = 1;
+    o->slots = 32;
+    o->stream = nullptr;
+}
+
+int lpide_batch_create(int32_t count, void* const* plans, const lpide_batch_opts* opts, void** out) {
+    if (!plans || !out || count < 1) return fail(LPIDE_E_PARAM, "count must be >= 1 and plans, out not NULL");
+    lpide_batch_opts o;
+    if (opts) o = *opts; else lpide_batch_opts_default(&o);
+    if (o.slots < 1 || o.slots > 256) return fail(LPIDE_E_PARAM, "slots must lie in [1, 256]");
+    Batch* b = new Batch();
+    b->caller = static_cast<hipStream_t>(o.stream);
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i]) { destroy_batch(b); return fail(LPIDE_E_PARAM, "NULL plan in the batch"); }
+        b->plans.push_back(static_cast<Plan*>(plans[i]));
+    }
+    // groups: plans with the same row-kernel size, jump switch, precision and SL order
+    for (int i = 0; i < count; ++i) {
+        Plan* p = b->plans[i];
+        int q = -1;
+        for (size_t g = 0; g < b->members.size(); ++g) {
+            Plan* r = b->plans[b->members[g][0]];
+            if (r->Lr == p->Lr && r->jumps == p->jumps && r->mixed == p->mixed && r->hp.sl_order == p->hp.sl_order)
+                q = int(g);
+        }
+        if (q < 0) {
+            b->members.push_back({});
+            q = int(b->members.size()) - 1;
+        }
+        b->members[q].push_back(i);
+    }
+    for (auto& m : b->members) {
+        hipStream_t s = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) { destroy_batch(b); return fail(LPIDE_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e)); }
+        b->streams.push_back(s);
+        std::vector<Plan*> ps;
+        for (int i : m) ps.push_back(b->plans[i]);
+        Group* g = nullptr;
+        int rc = make_group(ps, s, &g);
+        if (rc) { destroy_batch(b); return rc; }
+        g->use_graph = o.use_graph != 0;
+        g->slots = o.slots;
+        b->groups.push_back(g);
+    }
+    for (size_t q = 0; q <= b->groups.size(); ++q) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            destroy_batch(b);
+            return fail(LPIDE_E_HIP, "hipEventCreate failed");
+        }
+        b->events.push_back(e);
+    }
+    *out = b;
+    return LPIDE_OK;
+}
+
+int lpide_batch_destroy(void* batch) {
+    destroy_batch(static_cast<Batch*>(batch));
+    return LPIDE_OK;
+}
+
+int lpide_batch_solve(void* batch, double* const* v_out) {
+    if (!batch || !v_out) return fail(LPIDE_E_PARAM, "NULL argument");
+    Batch* b = static_cast<Batch*>(batch);
+    for (size_t i = 0; i < b->plans.size(); ++i)
+        if (!v_out[i]) return fail(LPIDE_E_PARAM, "NULL output pointer in v_out");
+    return batch_march(b, v_out, -1);
+}
+
+int lpide_batch_solve_steps(void* batch, int32_t steps, double* const* v_out) {
+    if (!batch || steps < 0) return fail(LPIDE_E_PARAM, "NULL batch or steps < 0");
+    return batch_march(static_cast<Batch*>(batch), v_out, steps);
+}
+
+// Autotuning: per group, time the march of the first trial_steps entries for
+// every candidate launch configuration (axis-1 line-solve chunking P_cols,
+// hipGraph replay on/off, step slots per host check) and keep the fastest.
+// Each candidate runs twice; the second run is timed, so graph capture and
+// first-launch costs are not counted.
+int lpide_batch_tune(void* batch, int32_t trial_steps) {
+    if (!batch || trial_steps < 1) return fail(LPIDE_E_PARAM, "NULL batch or trial_steps < 1");
+    Batch* b = static_cast<Batch*>(batch);
+    for (size_t q = 0; q < b->groups.size(); ++q) {
+        Group* g = b->groups[q];
+        std::vector<int> ns;
+        int nmax = 0;
+        for (Plan* p : g->plans) {
+            ns.push_back(std::min<int>(trial_steps, p->n_steps));
+            nmax = std::max(nmax, p->hp.n);
+        }
+        const int P0 = default_P_cols(nmax);
+        std::vector<int> Ps;
+        for (int P : {P0 / 2, P0, 2 * P0}) {
+            bool ok = true;
+            for (Plan* p : g->plans) ok = ok && P_cols_valid(p->hp.n, P);
+            if (ok && 4 * P <= 1024) Ps.push_back(P);
+        }
+        double best = 1e300;
+        int bP = P0, bG = g->use_graph ? 1 : 0, bS = g->slots;
+        for (int P : Ps)
+            for (int G : {0, 1})
+                for (int S : {16, 32}) {
+                    int rc = set_P_cols(g, P);
+                    if (rc) return rc;
+                    g->use_graph = G != 0;
+                    g->slots = S;
+                    double ms = 0.0;
+                    for (int rep = 0; rep < 2; ++rep) {
+                        HIP_TRY(hipStreamSynchronize(g->lc.stream));
+                        const auto t0 = std::chrono::steady_clock::now();
+                        rc = march_group(g, ns.data(), 0, nullptr, nullptr);
+                        if (rc) return rc;
+                        ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                    }
+                    if (ms < best) { best = ms; bP = P; bG = G; bS = S; }
+                }
+        int rc = set_P_cols(g, bP);
+        if (rc) return rc;
+        g->use_graph = bG != 0;
+        g->slots = bS;
+        g->tuned_ms = best;
+    }
+    b->tuned = true;
+    return LPIDE_OK;
+}
+
+int lpide_batch_info(void* batch, int32_t* n_groups, lpide_group_info* groups, int32_t cap) {
+    if (!batch || !n_groups) return fail(LPIDE_E_PARAM, "NULL argument");
+    Batch* b = static_cast<Batch*>(batch);
+    *n_groups = int32_t(b->groups.size());
+    for (int q = 0; q < (int)b->groups.size() && groups && q < cap; ++q) {
+        const Group* g = b->groups[q];
+        lpide_group_info& gi = groups[q];
+        std::memset(&gi, 0, sizeof gi);
+        gi.n_plans = g->lc.np;
+        gi.L = g->lc.L;
+        gi.mixed = g->lc.mixed ? 1 : 0;
+        gi.P_cols = g->lc.P_cols;
+        gi.slots = g->slots;
+        gi.use_graph = g->use_graph ? 1 : 0;
+        gi.trial_ms = g->tuned_ms;
     }
     return LPIDE_OK;
 }

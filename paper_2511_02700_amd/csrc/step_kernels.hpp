@@ -12,7 +12,13 @@
 // converged) or when a step failed to converge within its kmax iterations
 // (then everything after it is a no-op until the host has added iterations).
 // All buffers are addressed through a control block updated only by step_end,
-// so the same launch sequence serves every step of a kind.
+// so the same launch sequence serves every step, whatever its kind (the
+// explicit-part kernels return at once in theta = 1 steps of the FP64 form).
+//
+// Every kernel serves a group of independent plans with the same transform
+// size: blockIdx.y selects the plan (its MarchArgs in device memory), and each
+// plan has its own control block, so plans advance, converge and stop
+// independently inside one launch.
 //
 // Mixed form (FP32 correlation, FP64 everything else): each step first applies
 // B to V^{n-1} in FP64 (BV, and the explicit part), then the iteration
@@ -40,7 +46,7 @@ struct Ctl {
     int step;                         // completed entries of the step list
     int fail;                         // current step not converged within its launched iterations
     int fail_step;
-    int pad0;
+    int hold;                         // set by the host while another plan of the group is being completed
     int cur;                          // pool index of the state the current step starts from
     int y;                            // pool index of the iterate
     int hc;                           // history length (main steps)
@@ -79,6 +85,8 @@ struct MarchArgs {
     const float2* spec32;             // FP32 spectrum (mixed form)
     double* BV;                       // B V^{n-1}, FP64 (mixed form)
     double* BY;                       // B Y^k accumulated in FP64 (mixed form)
+    int nsteps;                       // step-list entries to march (the plan stops after them)
+    int step0;                        // step-list index of the state in pool[0] at the start
 };
 
 template <typename C> __device__ __forceinline__ C* xbuf(const MarchArgs& a);
@@ -93,17 +101,27 @@ __device__ __forceinline__ double bits_to_d(unsigned long long b) { return __lon
 // Uniform early-exit test of iteration k (k = 0: parts that run once per step).
 __device__ __forceinline__ bool halted(const MarchArgs& a, int k) {
     const Ctl* c = a.ctl;
-    if (c->fail) return true;
+    if (c->fail || c->hold || c->step >= a.nsteps) return true;
     return k > 0 && bits_to_d(c->err[k - 1]) < a.tol;
 }
 
+// The explicit part (and the FP64 correlation of V^{n-1}) is needed when
+// theta < 1, and in every step of the mixed form.
+__device__ __forceinline__ bool needs_explicit(const MarchArgs& a);
+
 __device__ __forceinline__ const StepDesc& cur_set(const MarchArgs& a) { return a.sets[a.step_set[a.ctl->step]]; }
+
+__device__ __forceinline__ bool needs_explicit(const MarchArgs& a) { return a.mixed || cur_set(a).theta < 1.0; }
+
+// The plan of this block.
+__device__ __forceinline__ const MarchArgs& plan_args(const MarchArgs* __restrict__ A) { return A[blockIdx.y]; }
 
 // Column pass of the correlation on the intermediate X (transposed half
 // spectra), FP64 (C = double2) or FP32 (C = float2).
 template <int L, typename C>
-__global__ __launch_bounds__(L / 8) void ks_cols(MarchArgs a, int k) {
-    if (halted(a, k)) return;
+__global__ __launch_bounds__(L / 8) void ks_cols(const MarchArgs* __restrict__ A, int k) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, k) || (k == 0 && !needs_explicit(a))) return;
     constexpr int T = L / 8;
     __shared__ C lds[lds_slots(L)];
     __shared__ double2 tw4[tw_slots<L>()];
@@ -132,7 +150,7 @@ __global__ __launch_bounds__(L / 8) void ks_cols(MarchArgs a, int k) {
 // Forward FFT of the row pair (ra, ra+1) of the FP64 grid U at the step start
 // (mixed form: the FP64 correlation of V^{n-1}).
 template <int L>
-__global__ __launch_bounds__(L / 8) void ks_rows_fwd(MarchArgs a);
+__global__ __launch_bounds__(L / 8) void ks_rows_fwd(const MarchArgs* __restrict__ A);
 
 // Row inverse FFT of the pairs (2p, 2p+1) with a fused epilogue.
 // MODE 0 (once per step, FP64): E = V + dt(1-theta)((D - r_omega) V + B V) into R
@@ -141,15 +159,17 @@ __global__ __launch_bounds__(L / 8) void ks_rows_fwd(MarchArgs a);
 // MODE 2 (mixed iteration): B Y = (k == 1 ? BV : B Y) + B32(increment) into BY,
 //         then R as in MODE 1 with that B Y.
 template <int L, int MODE>
-__global__ __launch_bounds__(L / 8) void ks_rows_inv(MarchArgs a, int k) {
-    if (halted(a, k)) return;
+__global__ __launch_bounds__(L / 8) void ks_rows_inv(const MarchArgs* __restrict__ A, int k) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, k) || (MODE == 0 && !needs_explicit(a))) return;
     using C = typename std::conditional<MODE == 2, float2, double2>::type;
     constexpr int T = L / 8;
+    const int n = a.n, np = (n + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, gridDim.x);
+    if (p >= np) return;
     __shared__ C lds[lds_slots(L)];
     __shared__ double2 tw4[tw_slots<L>()];
     load_twiddles<L>(a.tw, tw4);
-    const int n = a.n, np = (n + 1) >> 1;
-    const int p = xcd_remap(blockIdx.x, np);
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
     const int tid = threadIdx.x;
@@ -202,23 +222,26 @@ __global__ __launch_bounds__(L / 8) void ks_rows_inv(MarchArgs a, int k) {
     }
 }
 
-// The same affine forms without the correlation (zero Levy measure).
+// The same affine forms without the correlation (zero Levy measure); one
+// block per grid row.
 template <bool EXPLICIT>
-__global__ void ks_affine_noB(MarchArgs a, int k) {
-    if (halted(a, k)) return;
+__global__ __launch_bounds__(256) void ks_affine_noB(const MarchArgs* __restrict__ A, int k) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, k) || (EXPLICIT && !needs_explicit(a))) return;
     const int n = a.n;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    if (j >= n) return;
+    const int i = blockIdx.x;
+    if (i >= n) return;
     const StepDesc& sd = cur_set(a);
     const double* U = EXPLICIT ? a.pool[a.ctl->cur] : a.pool[a.ctl->y];
     const double* P0 = EXPLICIT ? U : a.W;
     const double c = EXPLICIT ? sd.dt * (1.0 - sd.theta) : sd.dt * sd.theta;
     const double c0 = EXPLICIT ? 0.0 : -1.0;
-    const size_t o = (size_t)i * n + j;
-    const double u = U[o];
-    const double d = apply_D(U, a.st, i, j, u);
-    a.R[o] = P0[o] + c * (d - a.r_omega * u) + c0 * u;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const size_t o = (size_t)i * n + j;
+        const double u = U[o];
+        const double d = apply_D(U, a.st, i, j, u);
+        a.R[o] = P0[o] + c * (d - a.r_omega * u) + c0 * u;
+    }
 }
 
 // Forward FFT of the row pair held in reg (canonical layout) into the
@@ -244,14 +267,16 @@ __device__ __forceinline__ void rows_fwd_store(C (&reg)[8], C* lds, const double
 }
 
 template <int L>
-__global__ __launch_bounds__(L / 8) void ks_rows_fwd(MarchArgs a) {
-    if (halted(a, 0)) return;
+__global__ __launch_bounds__(L / 8) void ks_rows_fwd(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, 0) || !a.mixed) return;
     constexpr int T = L / 8;
+    const int n = a.n, np = (n + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, gridDim.x);
+    if (p >= np) return;
     __shared__ double2 lds[lds_slots(L)];
     __shared__ double2 tw4[tw_slots<L>()];
     load_twiddles<L>(a.tw, tw4);
-    const int n = a.n, np = (n + 1) >> 1;
-    const int p = xcd_remap(blockIdx.x, np);
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
     const double* U = a.pool[a.ctl->cur];
@@ -269,15 +294,17 @@ __global__ __launch_bounds__(L / 8) void ks_rows_fwd(MarchArgs a) {
 // the iterate buffer, and (FFT) the row transform of Y^0 (FP64) or, in the
 // mixed form, of Y^0 - V^{n-1} (FP32); one row pair per block.
 template <int L, int P, bool FFT, bool MIXED>
-__global__ __launch_bounds__(L / 8) void ks_sl(MarchArgs a) {
+__global__ __launch_bounds__(L / 8) void ks_sl(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
     if (halted(a, 0)) return;
     constexpr int T = L / 8;
     using C = typename std::conditional<MIXED, float2, double2>::type;
+    const int n = a.n, np = (n + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, gridDim.x);
+    if (p >= np) return;
     __shared__ C lds[FFT ? lds_slots(L) : 1];
     __shared__ double2 tw4[FFT ? tw_slots<L>() : 1];
     if constexpr (FFT) load_twiddles<L>(a.tw, tw4);
-    const int n = a.n, np = (n + 1) >> 1;
-    const int p = xcd_remap(blockIdx.x, np);
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
     const int tid = threadIdx.x;
@@ -332,12 +359,15 @@ __global__ __launch_bounds__(L / 8) void ks_sl(MarchArgs a) {
 
 // Axis-1 line solves R <- T_1^{-1} R: 4 adjacent columns x P chunks per block
 // (thread = column + 4 * chunk).
-__global__ __launch_bounds__(1024) void ks_line_cols(MarchArgs a, int k) {
+__global__ __launch_bounds__(1024) void ks_line_cols(const MarchArgs* __restrict__ A, int k) {
+    const MarchArgs& a = plan_args(A);
     if (halted(a, k)) return;
     extern __shared__ double2 sbuf[];
     const int n = a.n, P = a.P_cols;
     const int c = threadIdx.x & 3, t = threadIdx.x >> 2;
-    const int col = xcd_remap(blockIdx.x, gridDim.x) * 4 + c;
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    if (4 * g >= n) return;
+    const int col = g * 4 + c;
     const int m = (n + P - 1) / P;
     const int s = t * m;
     const int cnt = col < n ? max(0, min(m, n - s)) : 0;
@@ -355,17 +385,19 @@ __global__ __launch_bounds__(1024) void ks_line_cols(MarchArgs a, int k) {
 // maximum err_k = max |delta| / max(1, |Y|), and (FFT) the row transform of the
 // updated Y (FP64) or, in the mixed form, of delta (FP32) for the next iteration.
 template <int L, bool FFT, bool MIXED>
-__global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
+__global__ __launch_bounds__(L / 8) void ks_line_rows(const MarchArgs* __restrict__ A, int k) {
+    const MarchArgs& a = plan_args(A);
     if (halted(a, k)) return;
     constexpr int T = L / 8, PR = T / 2;
     using C = typename std::conditional<MIXED, float2, double2>::type;
+    const int n = a.n, np = (n + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, gridDim.x);
+    if (p >= np) return;
     // union: row buffer 2 (n + PR + 1) doubles | scan totals | FFT exchange buffer
     __shared__ double2 lds[L + L / 16 + 2];
     __shared__ double2 tw4[FFT ? tw_slots<L>() : 1];
     if constexpr (FFT) load_twiddles<L>(a.tw, tw4);
     double* rows = reinterpret_cast<double*>(lds);
-    const int n = a.n, np = (n + 1) >> 1;
-    const int p = xcd_remap(blockIdx.x, np);
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
     const int tid = threadIdx.x;
@@ -428,8 +460,11 @@ __global__ __launch_bounds__(L / 8) void ks_line_rows(MarchArgs a, int k) {
 }
 
 // End of a step: convergence verdict, history rotation, next starting value.
-__global__ void ks_step_end(MarchArgs a, int kmax) {
+// One block per plan.
+__global__ void ks_step_end(const MarchArgs* __restrict__ A, int kmax) {
+    const MarchArgs& a = plan_args(A);
     Ctl* c = a.ctl;
+    if (c->hold || c->step >= a.nsteps) return;
     __shared__ int ok;
     if (threadIdx.x == 0) {
         ok = 0;
@@ -485,15 +520,18 @@ __global__ void ks_step_end(MarchArgs a, int kmax) {
     }
 }
 
-// Control block at the start of a march: V^0 in pool[0], iterate in pool[1].
-__global__ void ks_init(MarchArgs a) {
+// Control block at the start of a march: the state of step-list entry step0
+// in pool[0], the iterate in pool[1], no history before it.  One block per plan.
+__global__ void ks_init(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
     Ctl* c = a.ctl;
     for (int q = threadIdx.x; q < KSLOTS; q += blockDim.x)
         c->err[q] = q == 0 ? (unsigned long long)0x7FF0000000000000ull : 0ull;
     if (threadIdx.x == 0) {
-        c->step = 0;
+        c->step = a.step0;
         c->fail = 0;
         c->fail_step = -1;
+        c->hold = 0;
         c->cur = 0;
         c->y = 1;
         c->hc = 1;
@@ -503,8 +541,13 @@ __global__ void ks_init(MarchArgs a) {
     }
 }
 
-__global__ void ks_clear_fail(MarchArgs a) {
-    if (threadIdx.x == 0) a.ctl->fail = 0;
+__global__ void ks_clear_fail(const MarchArgs* __restrict__ A, int plan) {
+    if (threadIdx.x == 0) A[plan].ctl->fail = 0;
+}
+
+// hold = 1 on every plan of the group except `keep` (keep < 0: release all).
+__global__ void ks_hold(const MarchArgs* __restrict__ A, int np, int keep) {
+    for (int q = threadIdx.x; q < np; q += blockDim.x) A[q].ctl->hold = (keep >= 0 && q != keep) ? 1 : 0;
 }
 
 }  // namespace lpide
