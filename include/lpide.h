@@ -80,6 +80,9 @@ typedef struct {
                              (1e-14 reproduces the paper's printed values) */
     double  zmax2_frac;   /* z_max^II = h ceil(zmax2_frac N_z - 1/2) (paper: sqrt(0.1)) */
     int32_t gl_nodes;     /* Gauss-Legendre nodes per axis for the R_II cell integrals */
+    int32_t nz_fixed;     /* 0: N_z = ceil(z_max^III / h) (Sec. 4); > 0: N_z fixed to this value
+                             (frozen structure: plans that differ only in the model parameters
+                             then share N_z, M2, the kernel window and the FFT side) */
 } lpide_grid;
 
 /* Model (Sec. 2.1, Sec. 4): r, the 2D NTS Levy measure and an optional
@@ -131,7 +134,7 @@ typedef struct {
 
 /* Default settings: the paper's scheme settings (Sec. 4) on an n x n grid over
  * [y_lo, y_hi]^2: sl_order = in_order = 3, m1 = 2, ell_cut = 1e-14,
- * zmax2_frac = sqrt(0.1), gl_nodes = 8. */
+ * zmax2_frac = sqrt(0.1), gl_nodes = 8, nz_fixed = 0. */
 void lpide_grid_default(lpide_grid* g, int32_t n, double y_lo, double y_hi);
 
 /* Defaults: tol = 1e-12, max_iter = 100, FP64, damping on, device 0, NULL stream. */
@@ -219,6 +222,48 @@ int lpide_timing(void* plan, uint32_t class_mask);
  * lpide_timing call (host arrays of LPIDE_KCLASSES entries).  Synchronises the
  * plan's stream. */
 int lpide_kernel_stats(void* plan, int64_t* launches, double* ms);
+
+/* ---- Adjoint (reverse-mode) form ----
+ * The cotangent of the whole march (Algorithm 1 as a function of the model):
+ * for J with dJ/dV^{N_t} = v_bar, each step n (V^{n-1} -> Y = V^n, the exact
+ * fixed point of (I - dt theta A) Y = T^SL (I + dt (1 - theta) A) V^{n-1},
+ * A = D + B - r_omega, Sec. 3.3) is reversed as
+ *   lam = (I - dt theta A)^{-T} Ybar      (transposed preconditioned iteration:
+ *                                          B^T by the conjugate spectrum, D^T,
+ *                                          transposed line solves; stopping rule
+ *                                          and tol as the forward),
+ *   mu = (T^SL)^T lam,  Vbar^{n-1} = (I + dt (1 - theta) A)^T mu,
+ * and the step's terms of dJ/d(a11, a12, a22, r_omega, kappa_omega, K) are
+ * accumulated (K: the folded kernel, by a spectral cross-correlation of lam
+ * with Y and of mu with V^{n-1}).  States come from checkpoints every
+ * checkpoint_every steps; each segment is recomputed with recording before it
+ * is reversed.  The structure (N_z, M2, L, stencil starts) is held fixed. */
+typedef struct {
+    int64_t adj_iters;                /* adjoint fixed-point iterations, summed over the steps */
+    int32_t max_step_iters;
+    double  forward_ms;               /* checkpointed forward (0 when the last solve recorded them) */
+    double  recompute_ms, reverse_ms, gather_ms, jacobian_ms;
+} lpide_adjoint_info;
+
+/* Keep checkpoints in later lpide_solve calls (every `every` steps; 0: off),
+ * so that an lpide_adjoint with the same stride skips its forward pass. */
+int lpide_plan_set_checkpoints(void* plan, int32_t every);
+
+/* v_bar: device n*n.  native (host, may be NULL): 6 + (2 N_z)^2 values,
+ * dJ/d(a11, a12, a22, r_omega, kappa_omega1, kappa_omega2) then dJ/d omega_l at
+ * index 6 + (l1 + N_z) * 2 N_z + (l2 + N_z).  grad (host[8], may be NULL):
+ * dJ/d(sigma1, sigma2, corr, theta1, theta2, kappa, alpha, r), the
+ * subordination parameters std_params (host[8], same order) the plan's model
+ * was made from by lpide_levy_from_std (checked); the host quantities are
+ * differentiated by central differences (step 1e-4 max(|x|, 0.1), structure
+ * fixed; cached per plan and point).  Needs a plan with jumps.  Synchronises. */
+int lpide_adjoint(void* plan, const double* v_bar, int32_t checkpoint_every, const double* std_params,
+                  double* grad, double* native, lpide_adjoint_info* info);
+
+/* Transpose of lpide_price: v_bar[node] = sum_k price_bar[k] w_k(node), the
+ * cotangent of the grid for price cotangents price_bar (device arrays: spots
+ * npts x 2, price_bar npts, v_bar n*n, overwritten). */
+int lpide_price_adjoint(void* plan, int32_t npts, const double* spots, const double* price_bar, double* v_bar);
 
 /* ---- Batched form ----
  * Many independent plans (different grids, Levy parameters, pay-offs, step

@@ -20,10 +20,13 @@ transformed to log-moneyness coordinates y_i = ln(S_i / K) on a uniform grid:
                    the time march of Algorithm 1 (Sec. 3.2, 3.3).
 * ``output``    -- prices and deltas at spot pairs by cubic Lagrange
                    interpolation (Sec. 4).
+* ``adjoint``   -- the exact discrete adjoint of the theta-scheme march with
+                   dense matrices (small grids): gradients with respect to the
+                   diffusion coefficients, kill rate, drift and weights.
 
 Every function states the passage of the paper it follows.  Where the paper is
 silent or ambiguous on the log-grid, the reading taken is stated in the
 function's docstring.
 """
 
-from . import levy, integral, scheme, output  # noqa: F401
+from . import levy, integral, scheme, output, adjoint  # noqa: F401

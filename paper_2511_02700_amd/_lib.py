@@ -17,7 +17,8 @@ KCLASSES = ["cols", "rows_inv", "line_cols", "line_rows", "sl", "step_end", "exp
 class Grid(C.Structure):
     _fields_ = [("n", C.c_int32), ("y_lo", C.c_double * 2), ("y_hi", C.c_double * 2),
                 ("sl_order", C.c_int32), ("in_order", C.c_int32), ("m1", C.c_int32),
-                ("ell_cut", C.c_double), ("zmax2_frac", C.c_double), ("gl_nodes", C.c_int32)]
+                ("ell_cut", C.c_double), ("zmax2_frac", C.c_double), ("gl_nodes", C.c_int32),
+                ("nz_fixed", C.c_int32)]
 
 
 class Levy(C.Structure):
@@ -51,6 +52,15 @@ class Info(C.Structure):
         return out
 
 
+class AdjInfo(C.Structure):
+    _fields_ = [("adj_iters", C.c_int64), ("max_step_iters", C.c_int32), ("forward_ms", C.c_double),
+                ("recompute_ms", C.c_double), ("reverse_ms", C.c_double), ("gather_ms", C.c_double),
+                ("jacobian_ms", C.c_double)]
+
+    def to_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class BatchOpts(C.Structure):
     _fields_ = [("use_graph", C.c_int32), ("slots", C.c_int32), ("stream", C.c_void_p)]
 
@@ -81,6 +91,10 @@ SIGNATURES = {
                                         C.c_void_p, C.c_int64, C.c_void_p]),
     "lpide_timing": (C.c_int, [C.c_void_p, C.c_uint32]),
     "lpide_kernel_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "lpide_plan_set_checkpoints": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lpide_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.POINTER(C.c_double), C.POINTER(AdjInfo)]),
+    "lpide_price_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lpide_batch_opts_default": (None, [C.POINTER(BatchOpts)]),
     "lpide_batch_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(BatchOpts),
                                      C.POINTER(C.c_void_p)]),

@@ -159,6 +159,41 @@ class Plan:
         check(lib().lpide_apply_B(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr())))
         return out
 
+    def set_checkpoints(self, every):
+        """Let later solve() calls keep the checkpoints an adjoint with the same
+        stride needs (0: off)."""
+        check(lib().lpide_plan_set_checkpoints(self._h, int(every)))
+
+    def adjoint(self, v_bar, checkpoint_every=32, std_params=None):
+        """Reverse-mode gradient of J with dJ/dV^{N_t} = v_bar (lpide_adjoint).
+        Returns (grad, native, info): grad = dJ/d(sigma1, sigma2, corr, theta1,
+        theta2, kappa, alpha, r) (None unless std_params, the point the plan's
+        model was built from, is given); native = numpy array of
+        dJ/d(a11, a12, a22, r_omega, kappa_omega1, kappa_omega2) followed by
+        dJ/d omega (2 N_z x 2 N_z, row-major)."""
+        import numpy as np
+        torch = _torch()
+        v_bar = v_bar.to(self.device, torch.float64).contiguous()
+        nz = self.info()["N_z"]
+        native = np.zeros(6 + (2 * nz) ** 2)
+        grad = np.zeros(8) if std_params is not None else None
+        sp = (C.c_double * 8)(*[float(x) for x in std_params]) if std_params is not None else None
+        ai = _lib.AdjInfo()
+        check(lib().lpide_adjoint(self._h, C.c_void_p(v_bar.data_ptr()), int(checkpoint_every), sp,
+                                  grad.ctypes.data_as(C.POINTER(C.c_double)) if grad is not None else None,
+                                  native.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ai)))
+        return grad, native, ai.to_dict()
+
+    def price_adjoint(self, spots, price_bar):
+        """Cotangent of the grid for price cotangents (the transpose of price)."""
+        torch = _torch()
+        sp = torch.as_tensor(spots, dtype=torch.float64).reshape(-1, 2).to(self.device).contiguous()
+        pb = torch.as_tensor(price_bar, dtype=torch.float64).reshape(-1).to(self.device).contiguous()
+        out = self._grid_tensor()
+        check(lib().lpide_price_adjoint(self._h, sp.shape[0], C.c_void_p(sp.data_ptr()), C.c_void_p(pb.data_ptr()),
+                                        C.c_void_p(out.data_ptr())))
+        return out
+
     def price(self, v, spots, with_delta=False):
         torch = _torch()
         sp = torch.as_tensor(spots, dtype=torch.float64).reshape(-1, 2).to(self.device).contiguous()
@@ -233,10 +268,73 @@ class Batch:
         return [arr[i].to_dict() for i in range(n.value)]
 
 
+def std_params_of(w):
+    """(sigma1, sigma2, corr, theta1, theta2, kappa, alpha, r) of a workload."""
+    m = w["model"]
+    return (m["sigma1"], m["sigma2"], m["corr"], m["theta1"], m["theta2"], m["kappa"], m["alpha"], w["r"])
+
+
 def plan_from_workload(w, device=0, **over):
     """A Plan for a workload dict of ``workloads.WORKLOADS`` (pure data)."""
     m = w["model"]
     lv = levy_from_std(m["sigma1"], m["sigma2"], m["corr"], m["theta1"], m["theta2"], m["kappa"], m["alpha"], w["r"])
-    g = make_grid(w["n"], w["y_lo"], w["y_hi"], sl_order=over.pop("sl_order", 3), in_order=over.pop("in_order", 3))
+    g = make_grid(w["n"], w["y_lo"], w["y_hi"], sl_order=over.pop("sl_order", 3), in_order=over.pop("in_order", 3),
+                  nz_fixed=over.pop("nz_fixed", 0))
     pay = make_payoff(w.get("payoff", "put_avg"), w["K"], w["T"])
     return Plan(g, lv, pay, theta=w["theta"], M=w["N_t"], tol=over.pop("tol", w["tol"]), device=device, **over)
+
+
+class PricesFn:
+    """Prices at spot pairs as a differentiable function of the subordination
+    parameters and the spots: ``PricesFn.apply(params, spots, grid_args,
+    payoff_args)`` with params = tensor (sigma1, sigma2, corr, theta1, theta2,
+    kappa, alpha, r) (float64), spots = tensor (k, 2); grid_args = dict(n, y_lo,
+    y_hi, N_t, theta, tol, sl_order, checkpoint_every), payoff_args =
+    dict(kind, K, T).  The backward pass is the library's adjoint march
+    (lpide_price_adjoint, lpide_adjoint) for the parameters and the deltas for
+    the spots; the structure (N_z, L) is fixed at the point of the forward."""
+
+    @staticmethod
+    def apply(params, spots, grid_args, payoff_args):
+        return _prices_function().apply(params, spots, grid_args, payoff_args)
+
+
+_PF = None
+
+
+def _prices_function():
+    global _PF
+    if _PF is not None:
+        return _PF
+    torch = _torch()
+
+    class _Prices(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, params, spots, grid_args, payoff_args):
+            x = [float(v) for v in params.detach().cpu().reshape(-1)]
+            ga = dict(grid_args)
+            lv = levy_from_std(*x)
+            g = make_grid(ga["n"], ga["y_lo"], ga["y_hi"], sl_order=ga.get("sl_order", 3),
+                          nz_fixed=ga.get("nz_fixed", 0))
+            pay = make_payoff(payoff_args.get("kind", "put_avg"), payoff_args["K"], payoff_args["T"])
+            plan = Plan(g, lv, pay, theta=ga.get("theta", 0.5), M=ga["N_t"], tol=ga.get("tol", 1e-12))
+            C_every = ga.get("checkpoint_every", 32)
+            plan.set_checkpoints(C_every)
+            V = plan.solve()
+            sp = spots.detach().to(plan.device, torch.float64).reshape(-1, 2).contiguous()
+            pr, dl = plan.price(V, sp, with_delta=True)
+            ctx.plan, ctx.x, ctx.sp, ctx.dl, ctx.C = plan, x, sp, dl, C_every
+            return pr.to(params.device)
+
+        @staticmethod
+        def backward(ctx, gout):
+            plan = ctx.plan
+            g = gout.detach().to(plan.device, torch.float64).reshape(-1).contiguous()
+            vbar = plan.price_adjoint(ctx.sp, g)
+            grad, _, _ = plan.adjoint(vbar, ctx.C, std_params=ctx.x)
+            gp = torch.as_tensor(grad, dtype=torch.float64)
+            gs = (g[:, None] * ctx.dl).to(gout.device)
+            return gp, gs, None, None
+
+    _PF = _Prices
+    return _PF

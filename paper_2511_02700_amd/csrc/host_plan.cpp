@@ -276,7 +276,7 @@ bool build_host_plan(const lpide_grid& g, const lpide_levy& lv, HostPlan& hp, st
 
     if (hp.nts.jumps) {
         hp.z_star = z_star(hp.nts, g.ell_cut);
-        hp.N_z = int(std::ceil(hp.z_star / h));
+        hp.N_z = g.nz_fixed > 0 ? g.nz_fixed : int(std::ceil(hp.z_star / h));
         hp.M2 = int(std::ceil(g.zmax2_frac * hp.N_z - 0.5));
         if (hp.N_z < 1) hp.N_z = 1;
         const int N = hp.N_z, W2 = 2 * N;
@@ -476,35 +476,108 @@ bool initial_values(const HostPlan& hp, const lpide_payoff& pay, std::vector<dou
     return true;
 }
 
-void line_factors(int n, double h, double aii, double r_omega, double c,
-                  std::vector<double>& fl, std::vector<double>& bu, std::vector<double>& bc) {
-    // T = I - c A with A = 1/2 aii [(v+ - 2v + v-)/h^2 - (v+ - v-)/(2h)] - r_omega/2 v on
-    // interior rows and A = -r_omega/2 v on the two boundary rows.
-    const double lo_in = -c * 0.5 * aii * (1.0 / (h * h) + 0.5 / h);
-    const double up_in = -c * 0.5 * aii * (1.0 / (h * h) - 0.5 / h);
-    const double di_in = 1.0 + c * (aii / (h * h) + 0.5 * r_omega);
-    const double di_bd = 1.0 + c * 0.5 * r_omega;
+namespace {
+
+// Thomas factors of the tridiagonal matrix with rows (sub[j], dia[j], up[j]).
+void thomas_factors(const std::vector<double>& sub, const std::vector<double>& dia, const std::vector<double>& up,
+                    std::vector<double>& fl, std::vector<double>& bu, std::vector<double>& bc) {
+    const int n = int(dia.size());
     fl.assign(n, 0.0);
     bu.assign(n, 0.0);
     bc.assign(n, 0.0);
-    std::vector<double> d(n), up(n);
+    std::vector<double> d(n);
     for (int j = 0; j < n; ++j) {
-        bool in = j > 0 && j < n - 1;
-        double sub = in ? lo_in : 0.0;
-        double dia = in ? di_in : di_bd;
-        up[j] = in ? up_in : 0.0;
         if (j == 0) {
-            d[j] = dia;
+            d[j] = dia[j];
         } else {
-            double l = sub / d[j - 1];
+            double l = sub[j] / d[j - 1];
             fl[j] = -l;
-            d[j] = dia - l * up[j - 1];
+            d[j] = dia[j] - l * up[j - 1];
         }
     }
     for (int j = 0; j < n; ++j) {
         bu[j] = 1.0 / d[j];
         bc[j] = -up[j] / d[j];
     }
+}
+
+// Rows of T = I - c A with A = 1/2 aii [(v+ - 2v + v-)/h^2 - (v+ - v-)/(2h)] - r_omega/2 v
+// on interior rows and A = -r_omega/2 v on the two boundary rows.
+void line_rows_of(int n, double h, double aii, double r_omega, double c, std::vector<double>& sub,
+                  std::vector<double>& dia, std::vector<double>& up) {
+    const double lo_in = -c * 0.5 * aii * (1.0 / (h * h) + 0.5 / h);
+    const double up_in = -c * 0.5 * aii * (1.0 / (h * h) - 0.5 / h);
+    const double di_in = 1.0 + c * (aii / (h * h) + 0.5 * r_omega);
+    const double di_bd = 1.0 + c * 0.5 * r_omega;
+    sub.assign(n, 0.0);
+    dia.assign(n, 0.0);
+    up.assign(n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        const bool in = j > 0 && j < n - 1;
+        sub[j] = in ? lo_in : 0.0;
+        dia[j] = in ? di_in : di_bd;
+        up[j] = in ? up_in : 0.0;
+    }
+}
+
+}  // namespace
+
+void line_factors(int n, double h, double aii, double r_omega, double c,
+                  std::vector<double>& fl, std::vector<double>& bu, std::vector<double>& bc) {
+    std::vector<double> sub, dia, up;
+    line_rows_of(n, h, aii, r_omega, c, sub, dia, up);
+    thomas_factors(sub, dia, up, fl, bu, bc);
+}
+
+void line_factors_T(int n, double h, double aii, double r_omega, double c,
+                    std::vector<double>& fl, std::vector<double>& bu, std::vector<double>& bc) {
+    std::vector<double> sub, dia, up;
+    line_rows_of(n, h, aii, r_omega, c, sub, dia, up);
+    // transpose: row j of T^T has sub = up[j-1], super = sub[j+1]
+    std::vector<double> ts(n, 0.0), tu(n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        ts[j] = j > 0 ? up[j - 1] : 0.0;
+        tu[j] = j < n - 1 ? sub[j + 1] : 0.0;
+    }
+    thomas_factors(ts, dia, tu, fl, bu, bc);
+}
+
+void sl_dweights(int n, double shift, int P, std::vector<double>& dw) {
+    dw.assign(size_t(n) * (P + 1), 0.0);
+    for (int j = 0; j < n; ++j) {
+        const double xi = j + shift;
+        int s = int(std::floor(xi)) - (P - 1) / 2;
+        s = std::min(std::max(s, 0), n - 1 - P);
+        // d/dx of the Lagrange basis through s..s+P: sum over the dropped factor
+        for (int i = 0; i <= P; ++i) {
+            double acc = 0.0;
+            for (int k = 0; k <= P; ++k) {
+                if (k == i) continue;
+                double v = 1.0 / double(i - k);
+                for (int q = 0; q <= P; ++q)
+                    if (q != i && q != k) v *= (xi - (s + q)) / double(i - q);
+                acc += v;
+            }
+            dw[size_t(j) * (P + 1) + i] = acc;
+        }
+    }
+}
+
+int sl_transpose(int n, int P, const std::vector<int32_t>& start, const std::vector<double>& w,
+                 std::vector<int32_t>& idx, std::vector<double>& wt) {
+    std::vector<std::vector<std::pair<int, double>>> rows(n);
+    for (int j = 0; j < n; ++j)
+        for (int t = 0; t <= P; ++t) rows[start[j] + t].push_back({j, w[size_t(j) * (P + 1) + t]});
+    int width = 1;
+    for (auto& r : rows) width = std::max<int>(width, int(r.size()));
+    idx.assign(size_t(n) * width, 0);
+    wt.assign(size_t(n) * width, 0.0);
+    for (int m = 0; m < n; ++m)
+        for (size_t q = 0; q < rows[m].size(); ++q) {
+            idx[size_t(m) * width + q] = rows[m][q].first;
+            wt[size_t(m) * width + q] = rows[m][q].second;
+        }
+    return width;
 }
 
 void sl_weights(int n, double shift, int P, std::vector<int32_t>& start, std::vector<double>& w) {

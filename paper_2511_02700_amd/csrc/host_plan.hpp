@@ -61,6 +61,20 @@ bool initial_values(const HostPlan& hp, const lpide_payoff& pay, std::vector<dou
 void line_factors(int n, double h, double aii, double r_omega, double c,
                   std::vector<double>& fl, std::vector<double>& bu, std::vector<double>& bc);
 
+// Factors of T_i^T (the transposed line operator, for the adjoint march).
+void line_factors_T(int n, double h, double aii, double r_omega, double c,
+                    std::vector<double>& fl, std::vector<double>& bu, std::vector<double>& bc);
+
+// Derivatives of the semi-Lagrangian weights with respect to the departure
+// position xi = j + shift, with the stencil start held fixed.
+void sl_dweights(int n, double shift, int P, std::vector<double>& dw);
+
+// Transpose of the interpolation matrix given by (start, w): for each m the
+// source rows j and weights, padded to a common width (returned):
+// idx[m*width + q], wt[m*width + q] (zero weights in the padding).
+int sl_transpose(int n, int P, const std::vector<int32_t>& start, const std::vector<double>& w,
+                 std::vector<int32_t>& idx, std::vector<double>& wt);
+
 // Semi-Lagrangian interpolation weights along one axis: departure index j + shift,
 // order P, clamped stencil start; start[j] and w[j*(P+1) + t].
 void sl_weights(int n, double shift, int P, std::vector<int32_t>& start, std::vector<double>& w);

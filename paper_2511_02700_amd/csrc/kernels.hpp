@@ -67,4 +67,82 @@ __device__ __forceinline__ double apply_D(const double* __restrict__ U, const St
     return d;
 }
 
+// The three unit-coefficient parts of D at (i, j): D u = a11 d11 + a12 d12 + a22 d22
+// (the derivative of D u with respect to each coefficient).
+__device__ __forceinline__ void apply_D_parts(const double* __restrict__ U, int n, double h, int i, int j, double u,
+                                              double& d11, double& d12, double& d22) {
+    const double ih2 = 1.0 / (h * h), i2h = 0.5 / h;
+    d11 = d12 = d22 = 0.0;
+    if (i > 0 && i < n - 1) {
+        const double um = U[(size_t)(i - 1) * n + j], up = U[(size_t)(i + 1) * n + j];
+        d11 = 0.5 * ((up - 2.0 * u + um) * ih2 - (up - um) * i2h);
+    }
+    if (j > 0 && j < n - 1) {
+        const double um = U[(size_t)i * n + j - 1], up = U[(size_t)i * n + j + 1];
+        d22 = 0.5 * ((up - 2.0 * u + um) * ih2 - (up - um) * i2h);
+    }
+    int i0, i1, j0, j1;
+    double gi, gj;
+    if (i == 0) { i0 = 0; i1 = 1; gi = 1.0 / h; }
+    else if (i == n - 1) { i0 = n - 2; i1 = n - 1; gi = 1.0 / h; }
+    else { i0 = i - 1; i1 = i + 1; gi = i2h; }
+    if (j == 0) { j0 = 0; j1 = 1; gj = 1.0 / h; }
+    else if (j == n - 1) { j0 = n - 2; j1 = n - 1; gj = 1.0 / h; }
+    else { j0 = j - 1; j1 = j + 1; gj = i2h; }
+    const double u00 = U[(size_t)i0 * n + j0], u01 = U[(size_t)i0 * n + j1];
+    const double u10 = U[(size_t)i1 * n + j0], u11 = U[(size_t)i1 * n + j1];
+    d12 = gi * gj * ((u11 - u10) - (u01 - u00));
+}
+
+// Column p of the one-dimensional first-difference matrix G used by the mixed
+// term (rows: central inside, forward at 0, backward at n-1): the (at most two)
+// rows r with G[r][p] != 0 and those entries.
+__device__ __forceinline__ int diff_T(int n, double h, int p, int* r, double* c) {
+    int m = 0;
+    const double i2h = 0.5 / h, ih = 1.0 / h;
+    if (p - 1 >= 1 && p - 1 <= n - 2) { r[m] = p - 1; c[m] = i2h; ++m; }    // G[p-1][p]
+    if (p + 1 >= 1 && p + 1 <= n - 2) { r[m] = p + 1; c[m] = -i2h; ++m; }   // G[p+1][p]
+    if (p == 0) { r[m] = 0; c[m] = -ih; ++m; }                               // row 0: (v1 - v0)/h
+    if (p == 1) { r[m] = 0; c[m] = ih; ++m; }
+    if (p == n - 2) { r[m] = n - 1; c[m] = -ih; ++m; }                       // row n-1: (v_{n-1} - v_{n-2})/h
+    if (p == n - 1) { r[m] = n - 1; c[m] = ih; ++m; }
+    return m;
+}
+
+// D^T applied to U at (i, j): the transposed log-grid stencil, boundary rows
+// included (the adjoint of apply_D).
+__device__ __forceinline__ double apply_DT(const double* __restrict__ U, const StencilArgs& s, int i, int j,
+                                           double u) {
+    const int n = s.n;
+    const double ih2 = 1.0 / (s.h * s.h), i2h = 0.5 / s.h;
+    // second-difference parts: row r (interior) holds 1/2 [(v_{r+1} - 2 v_r + v_{r-1})/h^2 - (v_{r+1} - v_{r-1})/(2h)]
+    const double cu = 0.5 * (ih2 - i2h);   // coefficient of v_{r+1} in row r
+    const double cl = 0.5 * (ih2 + i2h);   // coefficient of v_{r-1} in row r
+    double d = 0.0;
+    {
+        double t = 0.0;
+        if (i > 0 && i < n - 1) t -= ih2 * u;
+        if (i - 1 >= 1 && i - 1 <= n - 2) t += cu * U[(size_t)(i - 1) * n + j];
+        if (i + 1 >= 1 && i + 1 <= n - 2) t += cl * U[(size_t)(i + 1) * n + j];
+        d += s.a11 * t;
+    }
+    {
+        double t = 0.0;
+        if (j > 0 && j < n - 1) t -= ih2 * u;
+        if (j - 1 >= 1 && j - 1 <= n - 2) t += cu * U[(size_t)i * n + j - 1];
+        if (j + 1 >= 1 && j + 1 <= n - 2) t += cl * U[(size_t)i * n + j + 1];
+        d += s.a22 * t;
+    }
+    if (s.a12 != 0.0) {
+        int ri[4], rj[4];
+        double ci[4], cj[4];
+        const int mi = diff_T(n, s.h, i, ri, ci), mj = diff_T(n, s.h, j, rj, cj);
+        double t = 0.0;
+        for (int a = 0; a < mi; ++a)
+            for (int b = 0; b < mj; ++b) t += ci[a] * cj[b] * U[(size_t)ri[a] * n + rj[b]];
+        d += s.a12 * t;
+    }
+    return d;
+}
+
 }  // namespace lpide

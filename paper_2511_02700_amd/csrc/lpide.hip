@@ -99,6 +99,7 @@ __global__ __launch_bounds__(L / 8) void k_rows_fwd(const double* __restrict__ Y
 
 // Column pass.  MODE 0: X[col] <- first n_out of IFFT(FFT(X[col], zero padded
 // from n_in) * spec[col]).  MODE 1 (plan time): spec_out[col] = conj(FFT(X[col])) * scale.
+// MODE 2: X[col] <- first n_out of IFFT(X[col], zero padded from n_in).
 template <int L, int MODE>
 __global__ __launch_bounds__(L / 8) void k_cols(double2* __restrict__ X, int ldx, int n_in, int n_out,
                                                const double2* __restrict__ spec,
@@ -117,8 +118,16 @@ __global__ __launch_bounds__(L / 8) void k_cols(double2* __restrict__ X, int ldx
         const int idx = tid + e * T;
         reg[e] = idx < n_in ? xc[idx] : make_double2(0.0, 0.0);
     }
-    fft_block<L, false>(reg, lds, tw4);
-    if constexpr (MODE == 1) {
+    if constexpr (MODE != 2) fft_block<L, false>(reg, lds, tw4);
+    if constexpr (MODE == 2) {
+        fft_block<L, true>(reg, lds, tw4);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = tid + e * T;
+            if (idx < n_out) xc[idx] = reg[e];
+        }
+        return;
+    } else if constexpr (MODE == 1) {
         double2* so = spec_out + (size_t)col * L;
 #pragma unroll
         for (int e = 0; e < 8; ++e) so[tid + e * T] = make_double2(reg[e].x * scale, -reg[e].y * scale);
@@ -219,6 +228,31 @@ __global__ void k_price(const double* __restrict__ V, int n, double y0, double y
     }
 }
 
+// Transpose of the price interpolation: vbar[node] = sum over spot pairs whose
+// 4 x 4 stencil holds the node of price_bar[k] times its weight (one thread
+// per node, so the sum order is fixed).
+__global__ void k_price_adjoint(int n, double y0, double y1, double h, double K, int npts,
+                                const double* __restrict__ spots, const double* __restrict__ price_bar,
+                                double* __restrict__ vbar) {
+    const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (size_t)n * n) return;
+    const int i = int(o / n), j = int(o % n);
+    double acc = 0.0;
+    for (int k = 0; k < npts; ++k) {
+        const double x1 = (log(spots[2 * k] / K) - y0) / h, x2 = (log(spots[2 * k + 1] / K) - y1) / h;
+        const int a = min(max((int)floor(x1) - 1, 0), n - 4);
+        const int b = min(max((int)floor(x2) - 1, 0), n - 4);
+        if (i < a || i > a + 3 || j < b || j > b + 3) continue;
+        double wi = 1.0, wj = 1.0;
+        for (int q = 0; q < 4; ++q) {
+            if (q != i - a) wi *= (x1 - (a + q)) / double((i - a) - q);
+            if (q != j - b) wj *= (x2 - (b + q)) / double((j - b) - q);
+        }
+        acc += price_bar[k] * wi * wj;
+    }
+    vbar[o] = acc;
+}
+
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, size_t cnt) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cnt) b[i] = a[i];
@@ -252,6 +286,8 @@ struct Launch {
     int sl_order = 3;
     bool jumps = false, mixed = false;
     Plan* timer = nullptr;          // records kernel timing (single-plan marches only)
+    bool record = false;            // launch the state-recording kernels (adjoint checkpoints)
+    int store_blocks = 1;           // grid of the recording copies
 };
 
 // Control state of a march over a group: one control block and per-step
@@ -276,8 +312,11 @@ struct Group {
     double tuned_ms = 0.0;
 };
 
+struct Adjoint;
+
 struct Plan {
     HostPlan hp;
+    lpide_grid grid{};
     lpide_opts opts{};
     lpide_payoff pay{};
     double theta = 0.5;
@@ -307,6 +346,10 @@ struct Plan {
     int n_steps = 0;
     int P_cols = 16;
     Group* solo = nullptr;         // this plan alone, on its own stream
+    // adjoint march (allocated on the first lpide_adjoint call)
+    struct Adjoint* adj = nullptr;
+    int ckpt_every = 0;            // lpide_solve records checkpoints every this many steps (0: none)
+    bool ckpt_valid = false;       // checkpoints of the last full solve are in adj->ckpt
     std::vector<int> counts_h;     // per-step iteration counts of the last march
     // kernel timing (HIP events on the plan's stream around each timed launch)
     uint32_t time_mask = 0;
@@ -389,6 +432,14 @@ int dalloc_into(std::vector<void*>& allocs, int64_t* bytes, Tp** out, size_t cou
 
 template <typename Tp>
 int dalloc(Plan* p, Tp** out, size_t count) { return dalloc_into(p->allocs, &p->bytes, out, count); }
+
+template <typename Tp>
+int upload_into(std::vector<void*>& allocs, Tp** out, const std::vector<Tp>& v) {
+    int rc = dalloc_into(allocs, nullptr, out, v.size());
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(*out, v.data(), v.size() * sizeof(Tp), hipMemcpyHostToDevice));
+    return LPIDE_OK;
+}
 
 template <typename Tp>
 int upload(Plan* p, Tp** out, const std::vector<Tp>& v) {
@@ -518,10 +569,14 @@ void launch_step(const Launch& c, int kmax) {
         else
             hipLaunchKernelGGL((ks_sl<L, 3, FFT, MIXED>), gr, dim3(L / 8), 0, c.stream, c.A);
     }
+    if (c.record) hipLaunchKernelGGL(ks_store_E, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
     for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT, MIXED>(c, k);
     if (c.timer) c.timer->tag_k = 0;
-    KTime t(c.timer, LPIDE_K_STEP_END);
-    hipLaunchKernelGGL(ks_step_end, dim3(1, c.np), dim3(64), 0, c.stream, c.A, kmax);
+    {
+        KTime t(c.timer, LPIDE_K_STEP_END);
+        hipLaunchKernelGGL(ks_step_end, dim3(1, c.np), dim3(64), 0, c.stream, c.A, kmax);
+    }
+    if (c.record) hipLaunchKernelGGL(ks_store_V, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
 }
 
 template <int L>
@@ -680,7 +735,7 @@ int set_P_cols(Group* g, int P) {
 // Enqueue nslots step slots with kmax iterations each: replay of a captured
 // graph when the group uses graphs (and no timing is on), else direct launches.
 int enqueue_slots(Group* g, int first_tag, int nslots, int kmax) {
-    if (!g->use_graph || g->lc.timer) return issue_slots(g->lc, first_tag, nslots, kmax);
+    if (!g->use_graph || g->lc.timer || g->lc.record) return issue_slots(g->lc, first_tag, nslots, kmax);
     hipGraphExec_t exec = nullptr;
     for (auto& x : g->graphs)
         if (x.kmax == kmax && x.nslots == nslots) exec = x.exec;
@@ -748,6 +803,7 @@ int complete_step(Group* g, int i, int kused, int* k_out) {
         if (c.timer) c.timer->tag_step = sf;
         if ((rc = issue_iteration(c, k))) break;
         hipLaunchKernelGGL(ks_step_end, dim3(1, c.np), dim3(64), 0, c.stream, c.A, k);
+        if (c.record) hipLaunchKernelGGL(ks_store_V, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
         if ((rc = read_back(g))) break;
         if (!g->ctl_h[i].fail) break;
     }
@@ -885,10 +941,424 @@ int march(Plan* p, int count, double* v_out) {
     return march_group(g, &count, 0, nullptr, &v_out);
 }
 
+// ---- adjoint march ----
+struct Adjoint {
+    int C = 0;                      // checkpoint stride
+    int n_ckpt = 0;
+    std::vector<void*> allocs;
+    double* ckpt = nullptr;         // n_ckpt states V^{qC}
+    double* seg = nullptr;          // C + 1 states of the segment being reversed
+    double* segE = nullptr;         // C explicit parts of that segment
+    double *lam = nullptr, *mu = nullptr, *ybar = nullptr, *dummy = nullptr;
+    double2 *XA = nullptr, *XB = nullptr, *XC = nullptr, *XD = nullptr;
+    double2* S = nullptr;           // (L/2+1) x L spectral accumulator
+    double* G = nullptr;            // L x L inverse transform of S
+    double* acc = nullptr;          // n x 8 per-row accumulators
+    StepDesc* sets_d = nullptr;
+    std::vector<StepDesc> sets;
+    MarchArgs* A = nullptr;
+    MarchArgs args{};
+    Ctl* ctl = nullptr;
+    Ctl* ctl_h = nullptr;
+    int* counts = nullptr;
+    double* incs = nullptr;
+    std::vector<int> counts_h;
+    // host Jacobian of (a11, a12, a22, r_omega, kappa1, kappa2, omega) with respect to the
+    // 8 subordination parameters, cached for the std point it was taken at
+    double jac_std[8] = {};
+    bool jac_valid = false;
+    std::vector<double> jac;        // 8 x (6 + (2 N_z)^2)
+};
+
+void destroy_adjoint(Adjoint* a) {
+    if (!a) return;
+    for (void* x : a->allocs) (void)hipFree(x);
+    if (a->ctl_h) (void)hipHostFree(a->ctl_h);
+    delete a;
+}
+
+// Allocate the adjoint buffers and the transposed step sets (once per plan and
+// checkpoint stride).
+int adj_prepare(Plan* p, int C) {
+    if (p->adj && p->adj->C == C) return LPIDE_OK;
+    destroy_adjoint(p->adj);
+    p->adj = nullptr;
+    p->ckpt_valid = false;
+    Adjoint* a = new Adjoint();
+    p->adj = a;
+    const int n = p->hp.n, L = p->L, hc = L / 2 + 1, P = p->hp.sl_order;
+    const size_t N = (size_t)n * n;
+    a->C = C;
+    a->n_ckpt = p->n_steps / C + 1;
+    auto& al = a->allocs;
+    int rc = LPIDE_OK;
+    if ((rc = dalloc_into(al, nullptr, &a->ckpt, N * a->n_ckpt)) || (rc = dalloc_into(al, nullptr, &a->seg, N * (C + 1))) ||
+        (rc = dalloc_into(al, nullptr, &a->segE, N * C)) || (rc = dalloc_into(al, nullptr, &a->lam, N)) ||
+        (rc = dalloc_into(al, nullptr, &a->mu, N)) || (rc = dalloc_into(al, nullptr, &a->ybar, N)) ||
+        (rc = dalloc_into(al, nullptr, &a->dummy, N)) || (rc = dalloc_into(al, nullptr, &a->acc, (size_t)n * 8)) ||
+        (rc = dalloc_into(al, nullptr, &a->ctl, 1)) || (rc = dalloc_into(al, nullptr, &a->counts, p->n_steps)) ||
+        (rc = dalloc_into(al, nullptr, &a->incs, p->n_steps)) || (rc = dalloc_into(al, nullptr, &a->A, 1)))
+        return rc;
+    if (p->jumps) {
+        if ((rc = dalloc_into(al, nullptr, &a->XA, (size_t)hc * n)) ||
+            (rc = dalloc_into(al, nullptr, &a->XB, (size_t)hc * n)) ||
+            (rc = dalloc_into(al, nullptr, &a->XC, (size_t)hc * n)) ||
+            (rc = dalloc_into(al, nullptr, &a->XD, (size_t)hc * n)) ||
+            (rc = dalloc_into(al, nullptr, &a->S, (size_t)hc * L)) ||
+            (rc = dalloc_into(al, nullptr, &a->G, (size_t)L * L)))
+            return rc;
+    }
+    if (hipHostMalloc((void**)&a->ctl_h, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
+        return fail(LPIDE_E_OOM, "hipHostMalloc failed");
+    a->counts_h.assign(p->n_steps, 0);
+    // transposed step sets
+    for (const StepDesc& fs : p->sets) {
+        StepDesc sd = fs;
+        const double c = sd.dt * sd.theta;
+        std::vector<double> fl, bu, bc;
+        double *f1, *u1, *c1, *f2, *u2, *c2;
+        line_factors_T(n, p->hp.h, p->hp.a[0], p->hp.r_omega, c, fl, bu, bc);
+        if ((rc = upload_into(al, &f1, fl)) || (rc = upload_into(al, &u1, bu)) || (rc = upload_into(al, &c1, bc))) return rc;
+        line_factors_T(n, p->hp.h, p->hp.a[2], p->hp.r_omega, c, fl, bu, bc);
+        if ((rc = upload_into(al, &f2, fl)) || (rc = upload_into(al, &u2, bu)) || (rc = upload_into(al, &c2, bc))) return rc;
+        sd.fl1 = f1; sd.bu1 = u1; sd.bc1 = c1;
+        sd.fl2 = f2; sd.bu2 = u2; sd.bc2 = c2;
+        for (int ax = 0; ax < 2; ++ax) {
+            const double shift = p->hp.kappa[ax] * sd.dt / p->hp.h;
+            std::vector<int32_t> st, ti;
+            std::vector<double> w, dw, tw;
+            sl_weights(n, shift, P, st, w);
+            sl_dweights(n, shift, P, dw);
+            for (double& x : dw) x *= sd.dt / p->hp.h;        // d/d kappa_omega = (dt / h) d/d xi
+            const int width = sl_transpose(n, P, st, w, ti, tw);
+            int* tid = nullptr;
+            double *twd = nullptr, *dwd = nullptr;
+            if ((rc = upload_into(al, &tid, ti)) || (rc = upload_into(al, &twd, tw)) || (rc = upload_into(al, &dwd, dw)))
+                return rc;
+            if (ax == 0) { sd.t1i = tid; sd.t1w = twd; sd.wt1 = width; sd.w1d = dwd; }
+            else { sd.t2i = tid; sd.t2w = twd; sd.wt2 = width; sd.w2d = dwd; }
+        }
+        a->sets.push_back(sd);
+    }
+    if ((rc = upload_into(al, &a->sets_d, a->sets))) return rc;
+    MarchArgs m = march_args(p);
+    m.pool[0] = a->mu;
+    m.pool[1] = a->lam;
+    for (int b = 2; b < POOL; ++b) m.pool[b] = a->dummy;
+    m.sets = a->sets_d;
+    m.W = a->ybar;
+    m.ctl = a->ctl;
+    m.counts = a->counts;
+    m.incs = a->incs;
+    m.mixed = 0;
+    m.nsteps = p->n_steps;
+    m.seg = nullptr;
+    m.segE = nullptr;
+    a->args = m;
+    HIP_TRY(hipMemcpy(a->A, &a->args, sizeof(MarchArgs), hipMemcpyHostToDevice));
+    return LPIDE_OK;
+}
+
+// Forward march with recording: states every `every` steps from seg_base to
+// `seg`, and (every == 1) the explicit parts to segE.
+int march_recorded(Plan* p, int step0, int nsteps, const double* v_in, double* seg, double* segE, int every,
+                   double* v_out) {
+    Group* g = p->solo;
+    MarchArgs& m = g->args_h[0];
+    m.seg = seg;
+    m.segE = segE;
+    m.seg_base = step0;
+    m.seg_every = every;
+    g->lc.record = true;
+    g->lc.timer = nullptr;
+    const size_t N = (size_t)p->hp.n * p->hp.n;
+    g->lc.store_blocks = int(std::min<size_t>(1024, (N + 255) / 256));
+    double* outs[1] = {v_out};
+    const double* ins[1] = {v_in};
+    int rc = march_group(g, &nsteps, step0, v_in ? ins : nullptr, outs);
+    m.seg = nullptr;
+    m.segE = nullptr;
+    g->lc.record = false;
+    return rc;
+}
+
+template <int L>
+void launch_adj_iteration(const Launch& c, int k) {
+    const dim3 gr(c.xrows, 1), gc(L / 2 + 1, 1);
+    hipLaunchKernelGGL((ks_cols<L, double2, true>), gc, dim3(L / 8), 0, c.stream, c.A, k);
+    hipLaunchKernelGGL((ks_rows_inv<L, 3>), gr, dim3(L / 8), 0, c.stream, c.A, k);
+    hipLaunchKernelGGL(ks_line_cols, dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols, c.stream,
+                       c.A, k);
+    hipLaunchKernelGGL((ks_line_rows<L, true, false>), gr, dim3(L / 8), 0, c.stream, c.A, k);
+}
+
+// One reverse step s: Ybar (in adj->ybar) -> cotangent of V^s (in adj->ybar),
+// gradient terms accumulated.  Y = V^{s+1}, V = V^s, E = E_s.
+template <int L>
+int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const double* V, const double* E) {
+    Adjoint* a = p->adj;
+    const int n = p->hp.n;
+    const size_t N = (size_t)n * n;
+    const StepDesc& sd = p->sets[p->step_set[s]];
+    const dim3 gr(c.xrows, 1);
+    hipLaunchKernelGGL(ks_adj_begin, dim3(1), dim3(64), 0, c.stream, c.A, s);
+    hipLaunchKernelGGL((ks_adj_start<L>), gr, dim3(L / 8), 0, c.stream, c.A);
+    int k = *kpred;
+    for (int q = 1; q <= k; ++q) launch_adj_iteration<L>(c, q);
+    hipLaunchKernelGGL(ks_adj_end, dim3(1), dim3(64), 0, c.stream, c.A, k);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(a->ctl_h, a->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    while (a->ctl_h->fail) {
+        const double ek = bits_d(a->ctl_h->err[k]);
+        if (!std::isfinite(ek)) return fail(LPIDE_E_NAN, "non-finite adjoint increment in step " + std::to_string(s));
+        if (k >= p->opts.max_iter) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "adjoint fixed point not converged in step %d after %d iterations (increment %.3e)",
+                     s, k, ek);
+            return fail(LPIDE_E_NOCONV, buf);
+        }
+        ++k;
+        hipLaunchKernelGGL(ks_clear_fail, dim3(1), dim3(64), 0, c.stream, c.A, 0);
+        launch_adj_iteration<L>(c, k);
+        hipLaunchKernelGGL(ks_adj_end, dim3(1), dim3(64), 0, c.stream, c.A, k);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(a->ctl_h, a->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.stream));
+        HIP_TRY(hipStreamSynchronize(c.stream));
+    }
+    int used = k;
+    for (int q = 1; q <= k; ++q)
+        if (bits_d(a->ctl_h->err[q]) < p->opts.tol) { used = q; break; }
+    a->counts_h[s] = used;
+    *kpred = std::max(1, std::min(p->opts.max_iter, used));
+    // mu = (T^SL)^T lam, then the cotangent of V^s
+    hipLaunchKernelGGL((ks_adj_sl<L>), gr, dim3(L / 8), 0, c.stream, c.A);
+    if (sd.theta < 1.0) {
+        hipLaunchKernelGGL((ks_cols<L, double2, true>), dim3(L / 2 + 1, 1), dim3(L / 8), 0, c.stream, c.A, 0);
+        hipLaunchKernelGGL((ks_rows_inv<L, 4>), gr, dim3(L / 8), 0, c.stream, c.A, 0);
+    }
+    // gradient terms (they read lam and mu; the new cotangent is written last)
+    if (p->hp.sl_order == 1)
+        hipLaunchKernelGGL(ks_adj_accum<1>, dim3(n, 1), dim3(256), 0, c.stream, c.A, Y, V, E, a->acc);
+    else
+        hipLaunchKernelGGL(ks_adj_accum<3>, dim3(n, 1), dim3(256), 0, c.stream, c.A, Y, V, E, a->acc);
+    const double c1 = sd.dt * sd.theta, c2 = sd.dt * (1.0 - sd.theta);
+    if (p->jumps) {
+        const int np = (n + 1) / 2;
+        hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, a->lam, n, n, n, a->XA, n, p->tw);
+        hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, Y, n, n, n, a->XB, n, p->tw);
+        if (c2 != 0.0) {
+            hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, a->mu, n, n, n, a->XC, n, p->tw);
+            hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, V, n, n, n, a->XD, n, p->tw);
+        }
+        hipLaunchKernelGGL((ks_adj_spec<L>), dim3(L / 2 + 1), dim3(L / 8), 0, c.stream, a->XA, a->XB, a->XC, a->XD, n,
+                           c1, c2, a->S, p->tw);
+    }
+    if (sd.theta >= 1.0)
+        hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, c.stream, a->mu, a->ybar, N);
+    HIP_TRY(hipGetLastError());
+    return LPIDE_OK;
+}
+
+int dispatch_adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const double* V,
+                      const double* E) {
+#define CALL_ADJ(Lc) return adj_step<Lc>(p, c, s, kpred, Y, V, E)
+    LPIDE_SWITCH_L(p->Lr, CALL_ADJ)
+#undef CALL_ADJ
+    return LPIDE_OK;
+}
+
+// Inverse 2D transform of the spectral accumulator (column inverse FFTs in
+// place, then the row c2r): G[d1 mod L][d2 mod L] = L^2 x (kernel gradient).
+template <int L>
+void launch_adj_kernel_grad(Plan* p, hipStream_t s) {
+    Adjoint* a = p->adj;
+    hipLaunchKernelGGL((k_cols<L, 2>), dim3(L / 2 + 1), dim3(L / 8), 0, s, a->S, L, L, L, (const double2*)nullptr,
+                       (double2*)nullptr, 0.0, p->tw);
+    hipLaunchKernelGGL((k_rows_inv<L>), dim3(L / 2), dim3(L / 8), 0, s, (const double2*)a->S, L, L, a->G, p->tw);
+}
+
+int dispatch_adj_kernel_grad(Plan* p, hipStream_t s) {
+#define CALL_KG(Lc) launch_adj_kernel_grad<Lc>(p, s)
+    LPIDE_SWITCH_L(p->L, CALL_KG)
+#undef CALL_KG
+    HIP_TRY(hipGetLastError());
+    return LPIDE_OK;
+}
+
+// Host model quantities that the march depends on continuously, at the
+// subordination parameters x (sigma1, sigma2, corr, theta1, theta2, kappa,
+// alpha, r), structure frozen at the plan's N_z: a11, a12, a22, r_omega,
+// kappa_omega^(1,2), then omega.
+int model_quantities(const Plan* p, const double* x, std::vector<double>& out) {
+    lpide_levy lv;
+    int rc = lpide_levy_from_std(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], &lv);
+    if (rc) return rc;
+    lpide_grid g;
+    lpide_grid_default(&g, p->hp.n, 0.0, 1.0);
+    g.y_lo[0] = p->hp.y_lo[0];
+    g.y_lo[1] = p->hp.y_lo[1];
+    g.y_hi[0] = p->hp.y_lo[0] + p->hp.h * (p->hp.n - 1);
+    g.y_hi[1] = p->hp.y_lo[1] + p->hp.h * (p->hp.n - 1);
+    g.sl_order = p->hp.sl_order;
+    g.in_order = p->hp.in_order;
+    g.m1 = p->hp.M1;
+    g.ell_cut = p->grid.ell_cut;
+    g.zmax2_frac = p->grid.zmax2_frac;
+    g.gl_nodes = p->grid.gl_nodes;
+    g.nz_fixed = p->hp.N_z;
+    HostPlan hp;
+    std::string err;
+    if (!build_host_plan(g, lv, hp, err)) return fail(LPIDE_E_PARAM, "model quantities: " + err);
+    if (hp.M2 != p->hp.M2 || hp.L != p->L) return fail(LPIDE_E_PARAM, "structure changed under the perturbation");
+    out.assign(6 + hp.omega.size(), 0.0);
+    out[0] = hp.a[0];
+    out[1] = hp.a[1];
+    out[2] = hp.a[2];
+    out[3] = hp.r_omega;
+    out[4] = hp.kappa[0];
+    out[5] = hp.kappa[1];
+    std::copy(hp.omega.begin(), hp.omega.end(), out.begin() + 6);
+    return LPIDE_OK;
+}
+
+// Central differences of model_quantities with steps 1e-4 max(|x_q|, 0.1).
+int model_jacobian(Plan* p, const double* x) {
+    Adjoint* a = p->adj;
+    if (a->jac_valid && std::equal(x, x + 8, a->jac_std)) return LPIDE_OK;
+    std::vector<double> fp, fm;
+    for (int q = 0; q < 8; ++q) {
+        double xp[8], xm[8];
+        std::copy(x, x + 8, xp);
+        std::copy(x, x + 8, xm);
+        const double hq = 1e-4 * std::max(std::fabs(x[q]), 0.1);
+        xp[q] += hq;
+        xm[q] -= hq;
+        int rc = model_quantities(p, xp, fp);
+        if (!rc) rc = model_quantities(p, xm, fm);
+        if (rc) return rc;
+        if (q == 0) a->jac.assign(8 * fp.size(), 0.0);
+        for (size_t i = 0; i < fp.size(); ++i) a->jac[q * fp.size() + i] = (fp[i] - fm[i]) / (2.0 * hq);
+    }
+    std::copy(x, x + 8, a->jac_std);
+    a->jac_valid = true;
+    return LPIDE_OK;
+}
+
+// The full adjoint: checkpointed forward (unless the last solve recorded the
+// same checkpoints), then per segment from the last: recompute with
+// recording, reverse steps.  native[0..5] = dJ/d(a11, a12, a22, r_omega,
+// kappa1, kappa2), native[6..] = dJ/d omega.
+int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lpide_adjoint_info* info) {
+    int rc = adj_prepare(p, C);
+    if (rc) return rc;
+    Adjoint* a = p->adj;
+    const int n = p->hp.n, Ns = p->n_steps;
+    const size_t N = (size_t)n * n;
+    hipStream_t s = p->stream;
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    auto ms = [](std::chrono::steady_clock::time_point t0, std::chrono::steady_clock::time_point t1) {
+        return std::chrono::duration<double, std::milli>(t1 - t0).count();
+    };
+    auto t0 = now();
+    if (!(p->ckpt_valid && p->ckpt_every == C)) {
+        hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, s, p->V0, a->ckpt, N);
+        if ((rc = march_recorded(p, 0, Ns, nullptr, a->ckpt, nullptr, C, nullptr))) return rc;
+    }
+    auto t1 = now();
+    HIP_TRY(hipMemcpyAsync(a->ybar, v_bar, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemsetAsync(a->acc, 0, sizeof(double) * N / n * 8, s));
+    if (p->jumps) HIP_TRY(hipMemsetAsync(a->S, 0, sizeof(double2) * (size_t)(p->L / 2 + 1) * p->L, s));
+    Launch c;
+    c.stream = s;
+    c.A = a->A;
+    c.np = 1;
+    c.L = p->Lr;
+    c.xrows = (n + 1) / 2;
+    c.xcols = (n + 3) / 4;
+    c.xaff = n;
+    c.P_cols = p->solo->lc.P_cols;
+    c.sl_order = p->hp.sl_order;
+    c.jumps = p->jumps;
+    a->args.P_cols = c.P_cols;
+    HIP_TRY(hipMemcpyAsync(a->A, &a->args, sizeof(MarchArgs), hipMemcpyHostToDevice, s));
+    double t_rec = 0.0, t_rev = 0.0;
+    int kpred = std::min(8, p->opts.max_iter);
+    int64_t iters = 0;
+    int maxit = 0;
+    for (int q = (Ns - 1) / C; q >= 0; --q) {
+        const int s0 = q * C, s1 = std::min(Ns, s0 + C);
+        auto ta = now();
+        HIP_TRY(hipMemcpyAsync(a->seg, a->ckpt + (size_t)q * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        if ((rc = march_recorded(p, s0, s1, a->ckpt + (size_t)q * N, a->seg, a->segE, 1, nullptr))) return rc;
+        HIP_TRY(hipStreamSynchronize(s));
+        auto tb = now();
+        for (int st = s1 - 1; st >= s0; --st) {
+            const double* Y = a->seg + (size_t)(st + 1 - s0) * N;
+            const double* V = a->seg + (size_t)(st - s0) * N;
+            const double* E = p->sets[p->step_set[st]].theta < 1.0 ? a->segE + (size_t)(st - s0) * N : V;
+            if ((rc = dispatch_adj_step(p, c, st, &kpred, Y, V, E))) return rc;
+            iters += a->counts_h[st];
+            maxit = std::max(maxit, a->counts_h[st]);
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+        t_rec += ms(ta, tb);
+        t_rev += ms(tb, now());
+    }
+    // gradient terms to the host
+    auto tc = now();
+    std::vector<double> acc(N / n * 8);
+    HIP_TRY(hipMemcpy(acc.data(), a->acc, sizeof(double) * acc.size(), hipMemcpyDeviceToHost));
+    const int Nz = p->hp.N_z, W2 = 2 * Nz;
+    native.assign(6 + (p->jumps ? (size_t)W2 * W2 : 0), 0.0);
+    for (int q = 0; q < 6; ++q) {
+        double t = 0.0;
+        for (int i = 0; i < n; ++i) t += acc[(size_t)i * 8 + q];
+        native[q] = t;
+    }
+    if (p->jumps) {
+        if ((rc = dispatch_adj_kernel_grad(p, s))) return rc;
+        const int L = p->L;
+        std::vector<double> G((size_t)L * L);
+        HIP_TRY(hipMemcpyAsync(G.data(), a->G, sizeof(double) * G.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const double inv = 1.0 / (double(L) * double(L));
+        auto gk = [&](int d1, int d2) {
+            return G[(size_t)(((d1 % L) + L) % L) * L + (((d2 % L) + L) % L)] * inv;
+        };
+        // dJ/d omega_l = sum_j s_j1 s_j2 dJ/dK_{l + jlo + j}  (K = omega folded with the half-cell taps)
+        const int Pin = p->hp.in_order, jlo = -(Pin - 1) / 2;
+        double sw[4];
+        for (int i = 0; i <= Pin; ++i) {
+            double v = 1.0;
+            for (int j = 0; j <= Pin; ++j)
+                if (j != i) v *= (0.5 - (jlo + j)) / double(i - j);
+            sw[i] = v;
+        }
+        for (int l1 = -Nz; l1 < Nz; ++l1)
+            for (int l2 = -Nz; l2 < Nz; ++l2) {
+                double t = 0.0;
+                for (int j1 = 0; j1 <= Pin; ++j1)
+                    for (int j2 = 0; j2 <= Pin; ++j2) t += sw[j1] * sw[j2] * gk(l1 + jlo + j1, l2 + jlo + j2);
+                native[6 + (size_t)(l1 + Nz) * W2 + (l2 + Nz)] = t;
+            }
+    }
+    if (info) {
+        info->adj_iters = iters;
+        info->max_step_iters = maxit;
+        info->forward_ms = ms(t0, t1);
+        info->recompute_ms = t_rec;
+        info->reverse_ms = t_rev;
+        info->gather_ms = ms(tc, now());
+    }
+    return LPIDE_OK;
+}
+
 void destroy(Plan* p) {
     if (!p) return;
     (void)hipStreamSynchronize(p->stream);
     destroy_group(p->solo);
+    destroy_adjoint(p->adj);
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     for (void* a : p->allocs) (void)hipFree(a);
     delete p;
@@ -1056,6 +1526,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     std::vector<double> v0;
     if (!initial_values(p->hp, *payoff, v0, err)) { delete p; return fail(LPIDE_E_PARAM, err); }
     p->opts = o;
+    p->grid = *grid;
     p->pay = *payoff;
     p->theta = theta;
     p->N_t = M;
@@ -1215,7 +1686,76 @@ int lpide_plan_info(void* plan, lpide_info* info) {
 int lpide_solve(void* plan, double* v_out) {
     if (!plan || !v_out) return fail(LPIDE_E_PARAM, "NULL argument");
     Plan* p = static_cast<Plan*>(plan);
+    p->ckpt_valid = false;
+    if (p->ckpt_every > 0) {
+        int rc = adj_prepare(p, p->ckpt_every);
+        if (rc) return rc;
+        const size_t N = (size_t)p->hp.n * p->hp.n;
+        hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, p->stream, p->V0, p->adj->ckpt, N);
+        rc = march_recorded(p, 0, p->n_steps, nullptr, p->adj->ckpt, nullptr, p->ckpt_every, v_out);
+        p->ckpt_valid = rc == LPIDE_OK;
+        return rc;
+    }
     return march(p, p->n_steps, v_out);
+}
+
+int lpide_plan_set_checkpoints(void* plan, int32_t every) {
+    if (!plan || every < 0) return fail(LPIDE_E_PARAM, "NULL plan or every < 0");
+    Plan* p = static_cast<Plan*>(plan);
+    if (every > 0 && !p->jumps) return fail(LPIDE_E_PARAM, "the adjoint march needs a Levy measure");
+    p->ckpt_every = every;
+    p->ckpt_valid = false;
+    return LPIDE_OK;
+}
+
+int lpide_adjoint(void* plan, const double* v_bar, int32_t checkpoint_every, const double* std_params, double* grad,
+                  double* native, lpide_adjoint_info* info) {
+    if (!plan || !v_bar) return fail(LPIDE_E_PARAM, "NULL argument");
+    Plan* p = static_cast<Plan*>(plan);
+    if (!p->jumps) return fail(LPIDE_E_PARAM, "the adjoint march needs a Levy measure");
+    if (checkpoint_every < 1) return fail(LPIDE_E_PARAM, "checkpoint_every must be >= 1");
+    if (grad && !std_params) return fail(LPIDE_E_PARAM, "grad needs std_params");
+    if (info) std::memset(info, 0, sizeof *info);
+    std::vector<double> nat;
+    int rc = adjoint(p, v_bar, checkpoint_every, nat, info);
+    if (rc) return rc;
+    if (native) std::copy(nat.begin(), nat.end(), native);
+    if (grad) {
+        // the std point must be the one the plan's model came from
+        lpide_levy lv;
+        if ((rc = lpide_levy_from_std(std_params[0], std_params[1], std_params[2], std_params[3], std_params[4],
+                                      std_params[5], std_params[6], std_params[7], &lv)))
+            return rc;
+        const Nts& q = p->hp.nts;
+        auto close = [](double x, double y) { return std::fabs(x - y) <= 1e-12 * std::max(1.0, std::fabs(y)); };
+        if (!close(lv.alpha, q.alpha) || !close(lv.delta, q.delta) || !close(lv.lambda, q.lambda) ||
+            !close(lv.eta[0], q.eta[0]) || !close(lv.eta[1], q.eta[1]) || !close(lv.rho[0], q.rho[0]) ||
+            !close(lv.rho[1], q.rho[1]) || !close(lv.rho[2], q.rho[2]) || !close(lv.r, p->hp.r))
+            return fail(LPIDE_E_PARAM, "std_params do not map to the plan's model");
+        const auto t0 = std::chrono::steady_clock::now();
+        if ((rc = model_jacobian(p, std_params))) return rc;
+        const size_t m = nat.size();
+        for (int k = 0; k < 8; ++k) {
+            double t = 0.0;
+            const double* jr = p->adj->jac.data() + (size_t)k * m;
+            for (size_t i = 0; i < m; ++i) t += nat[i] * jr[i];
+            grad[k] = t;
+        }
+        if (info)
+            info->jacobian_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return LPIDE_OK;
+}
+
+int lpide_price_adjoint(void* plan, int32_t npts, const double* spots, const double* price_bar, double* v_bar) {
+    if (!plan || !spots || !price_bar || !v_bar || npts < 0) return fail(LPIDE_E_PARAM, "NULL argument or npts < 0");
+    Plan* p = static_cast<Plan*>(plan);
+    const int n = p->hp.n;
+    const size_t N = (size_t)n * n;
+    hipLaunchKernelGGL(k_price_adjoint, dim3((N + 255) / 256), dim3(256), 0, p->stream, n, p->hp.y_lo[0],
+                       p->hp.y_lo[1], p->hp.h, p->pay.K, npts, spots, price_bar, v_bar);
+    HIP_TRY(hipGetLastError());
+    return LPIDE_OK;
 }
 
 int lpide_solve_steps(void* plan, int32_t steps, double* v_out) {

@@ -63,6 +63,13 @@ struct StepDesc {
     const double *fl2, *bu2, *bc2;    // axis-2 line factors
     const int *s1, *s2;               // semi-Lagrangian stencil starts per axis
     const double *w1, *w2;            // semi-Lagrangian weights per axis
+    // adjoint march only (null otherwise): transposed SL matrices per axis
+    // (source rows and weights, padded to widths wt1, wt2) and the weight
+    // derivatives with respect to the drift coefficient kappa_omega^(i)
+    const int *t1i, *t2i;
+    const double *t1w, *t2w;
+    int wt1, wt2;
+    const double *w1d, *w2d;
 };
 
 struct MarchArgs {
@@ -87,6 +94,9 @@ struct MarchArgs {
     double* BY;                       // B Y^k accumulated in FP64 (mixed form)
     int nsteps;                       // step-list entries to march (the plan stops after them)
     int step0;                        // step-list index of the state in pool[0] at the start
+    double* seg;                      // recorded states: V^s to seg[(s - seg_base) / seg_every] (or null)
+    double* segE;                     // recorded explicit parts E_s = M_E V^s to segE[s - seg_base] (theta < 1)
+    int seg_base, seg_every;
 };
 
 template <typename C> __device__ __forceinline__ C* xbuf(const MarchArgs& a);
@@ -118,7 +128,9 @@ __device__ __forceinline__ const MarchArgs& plan_args(const MarchArgs* __restric
 
 // Column pass of the correlation on the intermediate X (transposed half
 // spectra), FP64 (C = double2) or FP32 (C = float2).
-template <int L, typename C>
+// CONJ (adjoint march): multiply by the conjugate spectrum, which applies B^T
+// (the correlation with the reflected kernel).
+template <int L, typename C, bool CONJ = false>
 __global__ __launch_bounds__(L / 8) void ks_cols(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, k) || (k == 0 && !needs_explicit(a))) return;
@@ -138,7 +150,7 @@ __global__ __launch_bounds__(L / 8) void ks_cols(const MarchArgs* __restrict__ A
     }
     fft_block<L, false>(reg, lds, tw4);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) reg[e] = cmul(reg[e], sp[e]);
+    for (int e = 0; e < 8; ++e) reg[e] = CONJ ? cmulc(reg[e], sp[e]) : cmul(reg[e], sp[e]);
     fft_block<L, true>(reg, lds, tw4);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -158,10 +170,15 @@ __global__ __launch_bounds__(L / 8) void ks_rows_fwd(const MarchArgs* __restrict
 // MODE 1 (FP64 iteration):  R = W + dt theta((D - r_omega) Y + B Y) - Y;
 // MODE 2 (mixed iteration): B Y = (k == 1 ? BV : B Y) + B32(increment) into BY,
 //         then R as in MODE 1 with that B Y.
+// Adjoint march (B^T from a CONJ column pass, D^T the transposed stencil):
+// MODE 3 (iteration): R = Ybar + dt theta ((D^T - r_omega) lam + B^T lam) - lam,
+//         with Ybar in W and lam the iterate;
+// MODE 4 (once per step, theta < 1): W = mu + dt (1 - theta)((D^T - r_omega) mu + B^T mu),
+//         mu in pool[cur]: the cotangent of V^{n-1}.
 template <int L, int MODE>
 __global__ __launch_bounds__(L / 8) void ks_rows_inv(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
-    if (halted(a, k) || (MODE == 0 && !needs_explicit(a))) return;
+    if (halted(a, k) || ((MODE == 0 || MODE == 4) && !needs_explicit(a))) return;
     using C = typename std::conditional<MODE == 2, float2, double2>::type;
     constexpr int T = L / 8;
     const int n = a.n, np = (n + 1) >> 1;
@@ -190,10 +207,12 @@ __global__ __launch_bounds__(L / 8) void ks_rows_inv(const MarchArgs* __restrict
     }
     fft_block<L, true>(reg, lds, tw4);
     const StepDesc& sd = cur_set(a);
-    const double* U = MODE == 0 ? a.pool[a.ctl->cur] : a.pool[a.ctl->y];
-    const double* P0 = MODE == 0 ? U : a.W;
-    const double c = MODE == 0 ? sd.dt * (1.0 - sd.theta) : sd.dt * sd.theta;
-    const double c0 = MODE == 0 ? 0.0 : -1.0;
+    constexpr bool EXPL = MODE == 0 || MODE == 4;
+    const double* U = EXPL ? a.pool[a.ctl->cur] : a.pool[a.ctl->y];
+    const double* P0 = EXPL ? U : a.W;
+    double* out = MODE == 4 ? a.W : a.R;
+    const double c = EXPL ? sd.dt * (1.0 - sd.theta) : sd.dt * sd.theta;
+    const double c0 = EXPL ? 0.0 : -1.0;
     const bool want_r = MODE != 0 || sd.theta < 1.0;
     const double* base = (MODE == 2 && k == 1) ? a.BV : a.BY;
 #pragma unroll
@@ -215,8 +234,8 @@ __global__ __launch_bounds__(L / 8) void ks_rows_inv(const MarchArgs* __restrict
             }
             if (want_r) {
                 const double u = U[o];
-                const double d = apply_D(U, a.st, i, j, u);
-                a.R[o] = P0[o] + c * (d + bu - a.r_omega * u) + c0 * u;
+                const double d = MODE >= 3 ? apply_DT(U, a.st, i, j, u) : apply_D(U, a.st, i, j, u);
+                out[o] = P0[o] + c * (d + bu - a.r_omega * u) + c0 * u;
             }
         }
     }
@@ -518,6 +537,270 @@ __global__ void ks_step_end(const MarchArgs* __restrict__ A, int kmax) {
         for (int q = threadIdx.x; q < KSLOTS; q += blockDim.x)
             c->err[q] = q == 0 ? (unsigned long long)0x7FF0000000000000ull : 0ull;
     }
+}
+
+// Recording for the adjoint march.  After sl (once per step): E_s, held in R
+// when theta < 1, to segE.  After step_end: the current state to seg when its
+// step index is on the recording stride (idempotent: a slot whose step did not
+// advance writes the same state again).
+__global__ void ks_store_E(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, 0) || !a.segE || cur_set(a).theta >= 1.0) return;
+    const size_t N = (size_t)a.n * a.n;
+    double* dst = a.segE + (size_t)(a.ctl->step - a.seg_base) * N;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = a.R[i];
+}
+
+__global__ void ks_store_V(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
+    const Ctl* c = a.ctl;
+    if (!a.seg || c->hold) return;
+    const int rel = c->step - a.seg_base;
+    if (rel < 0 || rel % a.seg_every != 0) return;
+    const size_t N = (size_t)a.n * a.n;
+    const double* src = a.pool[c->cur];
+    double* dst = a.seg + (size_t)(rel / a.seg_every) * N;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// ---- adjoint march (reverse time steps) ----
+// Per reverse step s (forward V^s -> V^{s+1} = Y): lam solves
+// (I - dt theta A)^T lam = Ybar by the transposed preconditioned iteration
+// (the forward iteration kernels with B^T, D^T and the transposed line factors),
+// mu = (T^SL)^T lam, and the cotangent of V^s is (I + dt (1 - theta) A)^T mu.
+// Buffers of the adjoint MarchArgs: pool[1] = lam, pool[0] = mu, W = Ybar.
+
+// Control block for reverse step s: iterate in pool[1], no failure, stopping values reset.
+__global__ void ks_adj_begin(const MarchArgs* __restrict__ A, int s) {
+    Ctl* c = A[0].ctl;
+    for (int q = threadIdx.x; q < KSLOTS; q += blockDim.x)
+        c->err[q] = q == 0 ? (unsigned long long)0x7FF0000000000000ull : 0ull;
+    if (threadIdx.x == 0) {
+        c->step = s;
+        c->fail = 0;
+        c->fail_step = -1;
+        c->hold = 0;
+        c->cur = 0;
+        c->y = 1;
+    }
+}
+
+// Starting value lam^0 = Ybar and its row transform.
+template <int L>
+__global__ __launch_bounds__(L / 8) void ks_adj_start(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, 0)) return;
+    constexpr int T = L / 8;
+    const int n = a.n, np = (n + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, gridDim.x);
+    if (p >= np) return;
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L>()];
+    load_twiddles<L>(a.tw, tw4);
+    const int ra = 2 * p, rb = 2 * p + 1;
+    const bool hasb = rb < n;
+    double* lam = a.pool[a.ctl->y];
+    double2 reg[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int j = threadIdx.x + e * T;
+        double va = 0.0, vb = 0.0;
+        if (j < n) {
+            va = a.W[(size_t)ra * n + j];
+            lam[(size_t)ra * n + j] = va;
+            if (hasb) {
+                vb = a.W[(size_t)rb * n + j];
+                lam[(size_t)rb * n + j] = vb;
+            }
+        }
+        reg[e] = make_double2(va, vb);
+    }
+    rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
+}
+
+// Verdict of the adjoint fixed point of the current reverse step: iteration
+// count (first k with err_k < tol) or the failure flag.
+__global__ void ks_adj_end(const MarchArgs* __restrict__ A, int kmax) {
+    const MarchArgs& a = A[0];
+    Ctl* c = a.ctl;
+    if (threadIdx.x != 0 || c->fail) return;
+    int kk = 0;
+    for (int q = 1; q <= kmax; ++q)
+        if (bits_to_d(c->err[q]) < a.tol) { kk = q; break; }
+    if (kk == 0) {
+        c->fail = 1;
+        c->fail_step = c->step;
+    } else {
+        a.counts[c->step] = kk;
+        a.incs[c->step] = bits_to_d(c->err[kk]);
+    }
+}
+
+// mu = (T_1^T (x) T_2^T) lam (the transposed semi-Lagrangian gather) into
+// pool[0]; when theta < 1 also its row transform for B^T mu.
+template <int L>
+__global__ __launch_bounds__(L / 8) void ks_adj_sl(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, 0)) return;
+    constexpr int T = L / 8;
+    const int n = a.n, np = (n + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, gridDim.x);
+    if (p >= np) return;
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L>()];
+    const StepDesc& sd = cur_set(a);
+    const bool fft = sd.theta < 1.0;
+    if (fft) load_twiddles<L>(a.tw, tw4);
+    const int ra = 2 * p, rb = 2 * p + 1;
+    const bool hasb = rb < n;
+    const double* lam = a.pool[a.ctl->y];
+    double* mu = a.pool[a.ctl->cur];
+    const int W1 = sd.wt1, W2 = sd.wt2;
+    double2 reg[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int j = threadIdx.x + e * T;
+        double out[2] = {0.0, 0.0};
+        if (j < n) {
+            for (int r = 0; r < 2; ++r) {
+                const int i = ra + r;
+                if (r == 1 && !hasb) break;
+                double acc = 0.0;
+                for (int q1 = 0; q1 < W1; ++q1) {
+                    const double wa = sd.t1w[(size_t)i * W1 + q1];
+                    if (wa == 0.0) continue;
+                    const double* lr = lam + (size_t)sd.t1i[(size_t)i * W1 + q1] * n;
+                    double s2 = 0.0;
+                    for (int q2 = 0; q2 < W2; ++q2) s2 += sd.t2w[(size_t)j * W2 + q2] * lr[sd.t2i[(size_t)j * W2 + q2]];
+                    acc += wa * s2;
+                }
+                mu[(size_t)i * n + j] = acc;
+                out[r] = acc;
+            }
+        }
+        reg[e] = make_double2(out[0], out[1]);
+    }
+    if (fft) rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
+}
+
+// Per-step gradient terms of the reverse step (one block per row pair,
+// deterministic per-block accumulators acc[block * 8 + q]):
+//   q = 0, 1, 2: dt theta lam . D_c Y + dt (1 - theta) mu . D_c V    (c = 11, 12, 22)
+//   q = 3:       -(dt theta lam . Y + dt (1 - theta) mu . V)         (r_omega)
+//   q = 4, 5:    lam . ((dT_1 (x) T_2) E), lam . ((T_1 (x) dT_2) E)   (kappa_omega^(1,2))
+// with Y = V^{s+1}, V = V^s and E = E_s (V^s when theta = 1).
+template <int P>
+__global__ __launch_bounds__(256) void ks_adj_accum(const MarchArgs* __restrict__ A, const double* __restrict__ Yg,
+                                                    const double* __restrict__ Vg, const double* __restrict__ Eg,
+                                                    double* __restrict__ acc) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, 0)) return;
+    const int n = a.n;
+    const int i = blockIdx.x;
+    if (i >= n) return;
+    const StepDesc& sd = cur_set(a);
+    const double* lam = a.pool[a.ctl->y];
+    const double* mu = a.pool[a.ctl->cur];
+    const double ci = sd.dt * sd.theta, ce = sd.dt * (1.0 - sd.theta);
+    double t[6] = {0, 0, 0, 0, 0, 0};
+    const int a0 = sd.s1[i];
+    double w1[P + 1], w1d[P + 1];
+#pragma unroll
+    for (int q = 0; q <= P; ++q) {
+        w1[q] = sd.w1[i * (P + 1) + q];
+        w1d[q] = sd.w1d[i * (P + 1) + q];
+    }
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const size_t o = (size_t)i * n + j;
+        const double l = lam[o], m = mu[o], y = Yg[o], v = Vg[o];
+        double y11, y12, y22, v11 = 0.0, v12 = 0.0, v22 = 0.0;
+        apply_D_parts(Yg, n, a.st.h, i, j, y, y11, y12, y22);
+        if (ce != 0.0) apply_D_parts(Vg, n, a.st.h, i, j, v, v11, v12, v22);
+        t[0] += ci * l * y11 + ce * m * v11;
+        t[1] += ci * l * y12 + ce * m * v12;
+        t[2] += ci * l * y22 + ce * m * v22;
+        t[3] -= ci * l * y + ce * m * v;
+        const int b0 = sd.s2[j];
+        double w2[P + 1], w2d[P + 1];
+#pragma unroll
+        for (int b = 0; b <= P; ++b) {
+            w2[b] = sd.w2[j * (P + 1) + b];
+            w2d[b] = sd.w2d[j * (P + 1) + b];
+        }
+        double g1 = 0.0, g2 = 0.0;
+#pragma unroll
+        for (int aa = 0; aa <= P; ++aa) {
+            const double* er = Eg + (size_t)(a0 + aa) * n + b0;
+            double s0 = 0.0, sdd = 0.0;
+#pragma unroll
+            for (int b = 0; b <= P; ++b) {
+                s0 += w2[b] * er[b];
+                sdd += w2d[b] * er[b];
+            }
+            g1 += w1d[aa] * s0;
+            g2 += w1[aa] * sdd;
+        }
+        t[4] += l * g1;
+        t[5] += l * g2;
+    }
+    __shared__ double red[6][256];
+    for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = t[q];
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 6; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q) acc[(size_t)i * 8 + q] += red[q][0];
+}
+
+// Spectral accumulation of the kernel gradient: per column k2 of the row
+// transforms (transposed half spectra, n rows each), the column FFTs and
+// S[k2][k1] += c1 conj(FFT XA) FFT XB (+ c2 conj(FFT XC) FFT XD when c2 != 0).
+// After the march, the inverse 2D transform of S / L^2 is sum_m lam_m Y_{m+d}
+// summed over the steps with their weights: the gradient of the loss with
+// respect to the folded kernel K_d.
+template <int L>
+__global__ __launch_bounds__(L / 8) void ks_adj_spec(const double2* __restrict__ XA, const double2* __restrict__ XB,
+                                                     const double2* __restrict__ XC, const double2* __restrict__ XD,
+                                                     int n, double c1, double c2, double2* __restrict__ S,
+                                                     const double2* __restrict__ tw) {
+    constexpr int T = L / 8;
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L>()];
+    load_twiddles<L>(tw, tw4);
+    const int col = blockIdx.x, tid = threadIdx.x;
+    double2 acc[8];
+    double2* sc = S + (size_t)col * L;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[e] = sc[tid + e * T];
+    for (int pass = 0; pass < 2; ++pass) {
+        const double cf = pass == 0 ? c1 : c2;
+        if (cf == 0.0) continue;
+        const double2* xa = (pass == 0 ? XA : XC) + (size_t)col * n;
+        const double2* xb = (pass == 0 ? XB : XD) + (size_t)col * n;
+        double2 ra[8], rb[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = tid + e * T;
+            ra[e] = idx < n ? xa[idx] : make_double2(0.0, 0.0);
+            rb[e] = idx < n ? xb[idx] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        fft_block<L, false>(ra, lds, tw4);
+        __syncthreads();
+        fft_block<L, false>(rb, lds, tw4);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const double2 pr = cmulc(rb[e], ra[e]);    // conj(A) B
+            acc[e] = make_double2(acc[e].x + cf * pr.x, acc[e].y + cf * pr.y);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sc[tid + e * T] = acc[e];
 }
 
 // Control block at the start of a march: the state of step-list entry step0
