@@ -255,8 +255,10 @@ int lpide_plan_set_checkpoints(void* plan, int32_t every);
  * dJ/d(sigma1, sigma2, corr, theta1, theta2, kappa, alpha, r), the
  * subordination parameters std_params (host[8], same order) the plan's model
  * was made from by lpide_levy_from_std (checked); the host quantities are
- * differentiated by central differences (step 1e-4 max(|x|, 0.1), structure
- * fixed; cached per plan and point).  Needs a plan with jumps.  Synchronises. */
+ * differentiated by central differences in the seven Levy parameters (step
+ * 1e-4 max(|x|, 0.1), structure fixed) and exactly in r (it enters only
+ * kappa_omega and r_omega, with unit slope); the Jacobian is cached per plan
+ * and point.  Needs a plan with jumps.  Synchronises. */
 int lpide_adjoint(void* plan, const double* v_bar, int32_t checkpoint_every, const double* std_params,
                   double* grad, double* native, lpide_adjoint_info* info);
 

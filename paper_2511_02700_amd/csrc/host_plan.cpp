@@ -77,17 +77,23 @@ void gauss_legendre(int m, std::vector<double>& x, std::vector<double>& w) {
     if (m % 2 == 1) x[m / 2] = 0.0;
 }
 
-// Run fn(i) for i in [0, count) on up to 16 host threads.
-void parallel_for(int64_t count, const std::function<void(int64_t, int64_t)>& fn) {
+// Run fn(b, e) over [0, count) on up to 16 host threads, handing out blocks of
+// `grain` items from a shared counter (the items may differ much in cost).
+void parallel_for(int64_t count, const std::function<void(int64_t, int64_t)>& fn, int64_t grain = 1) {
     unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    int64_t nt = std::min<int64_t>(hw, std::max<int64_t>(1, count / 256));
+    const int64_t nblk = (count + grain - 1) / grain;
+    const int64_t nt = std::min<int64_t>(hw, nblk);
     if (nt <= 1) { fn(0, count); return; }
+    std::atomic<int64_t> next{0};
+    auto work = [&] {
+        for (;;) {
+            const int64_t k = next.fetch_add(1);
+            if (k >= nblk) break;
+            fn(k * grain, std::min(count, (k + 1) * grain));
+        }
+    };
     std::vector<std::thread> th;
-    int64_t chunk = (count + nt - 1) / nt;
-    for (int64_t t = 0; t < nt; ++t) {
-        int64_t b = t * chunk, e = std::min(count, b + chunk);
-        if (b < e) th.emplace_back(fn, b, e);
-    }
+    for (int64_t t = 0; t < nt; ++t) th.emplace_back(work);
     for (auto& t : th) t.join();
 }
 
@@ -213,12 +219,15 @@ static void small_jump_cov(const Nts& p, double half, double S[3]) {
         tx.push_back(x);
         tw.push_back(w);
     }
-    Sum s11, s12, s22;
-    for (int oct = 0; oct < 8; ++oct) {
-        double a = oct * kPi / 4.0, b = (oct + 1) * kPi / 4.0;
-        for (size_t i = 0; i < gx.size(); ++i) {
-            double phi = 0.5 * (b - a) * gx[i] + 0.5 * (a + b);
-            double wphi = 0.5 * (b - a) * gw[i];
+    // one radial integral per (octant, angle node), in parallel; summed in order
+    const int na = int(gx.size());
+    std::vector<double> Iv(size_t(8) * na), U1(Iv.size()), U2(Iv.size());
+    parallel_for(8 * na, [&](int64_t b, int64_t e) {
+        for (int64_t q = b; q < e; ++q) {
+            const int oct = int(q / na), i = int(q % na);
+            double a = oct * kPi / 4.0, bb = (oct + 1) * kPi / 4.0;
+            double phi = 0.5 * (bb - a) * gx[i] + 0.5 * (a + bb);
+            double wphi = 0.5 * (bb - a) * gw[i];
             double u1 = std::cos(phi), u2 = std::sin(phi);
             double R = half / std::max(std::fabs(u1), std::fabs(u2));
             Sum rad;
@@ -228,11 +237,16 @@ static void small_jump_cov(const Nts& p, double half, double S[3]) {
                 if (ld == -std::numeric_limits<double>::infinity()) continue;
                 rad.add(tw[k] * R * std::exp(3.0 * std::log(r) + ld));
             }
-            double I = rad.value() * wphi;
-            s11.add(u1 * u1 * I);
-            s12.add(u1 * u2 * I);
-            s22.add(u2 * u2 * I);
+            Iv[q] = rad.value() * wphi;
+            U1[q] = u1;
+            U2[q] = u2;
         }
+    }, 8);
+    Sum s11, s12, s22;
+    for (size_t q = 0; q < Iv.size(); ++q) {
+        s11.add(U1[q] * U1[q] * Iv[q]);
+        s12.add(U1[q] * U2[q] * Iv[q]);
+        s22.add(U2[q] * U2[q] * Iv[q]);
     }
     S[0] = s11.value();
     S[1] = s12.value();

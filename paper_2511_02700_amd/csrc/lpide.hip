@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "host_plan.hpp"
@@ -949,7 +950,10 @@ struct Adjoint {
     double* ckpt = nullptr;         // n_ckpt states V^{qC}
     double* seg = nullptr;          // C + 1 states of the segment being reversed
     double* segE = nullptr;         // C explicit parts of that segment
-    double *lam = nullptr, *mu = nullptr, *ybar = nullptr, *dummy = nullptr;
+    double *lam = nullptr, *mu = nullptr, *ybar = nullptr, *dummy = nullptr, *corr = nullptr;
+    bool have_corr = false;          // corr holds lam - Ybar of the previous reverse step
+    double corr_c = 0.0;             // dt theta of that step
+    bool xb_is_v = false;            // XD holds the row transform of V^{s+1} from the previous reverse step
     double2 *XA = nullptr, *XB = nullptr, *XC = nullptr, *XD = nullptr;
     double2* S = nullptr;           // (L/2+1) x L spectral accumulator
     double* G = nullptr;            // L x L inverse transform of S
@@ -996,6 +1000,7 @@ int adj_prepare(Plan* p, int C) {
         (rc = dalloc_into(al, nullptr, &a->segE, N * C)) || (rc = dalloc_into(al, nullptr, &a->lam, N)) ||
         (rc = dalloc_into(al, nullptr, &a->mu, N)) || (rc = dalloc_into(al, nullptr, &a->ybar, N)) ||
         (rc = dalloc_into(al, nullptr, &a->dummy, N)) || (rc = dalloc_into(al, nullptr, &a->acc, (size_t)n * 8)) ||
+        (rc = dalloc_into(al, nullptr, &a->corr, N)) ||
         (rc = dalloc_into(al, nullptr, &a->ctl, 1)) || (rc = dalloc_into(al, nullptr, &a->counts, p->n_steps)) ||
         (rc = dalloc_into(al, nullptr, &a->incs, p->n_steps)) || (rc = dalloc_into(al, nullptr, &a->A, 1)))
         return rc;
@@ -1102,7 +1107,9 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     const StepDesc& sd = p->sets[p->step_set[s]];
     const dim3 gr(c.xrows, 1);
     hipLaunchKernelGGL(ks_adj_begin, dim3(1), dim3(64), 0, c.stream, c.A, s);
-    hipLaunchKernelGGL((ks_adj_start<L>), gr, dim3(L / 8), 0, c.stream, c.A);
+    const double cth = sd.dt * sd.theta;
+    hipLaunchKernelGGL((ks_adj_start<L>), gr, dim3(L / 8), 0, c.stream, c.A, a->have_corr ? a->corr : nullptr,
+                       a->have_corr && a->corr_c > 0.0 ? cth / a->corr_c : 0.0);
     int k = *kpred;
     for (int q = 1; q <= k; ++q) launch_adj_iteration<L>(c, q);
     hipLaunchKernelGGL(ks_adj_end, dim3(1), dim3(64), 0, c.stream, c.A, k);
@@ -1131,6 +1138,10 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
         if (bits_d(a->ctl_h->err[q]) < p->opts.tol) { used = q; break; }
     a->counts_h[s] = used;
     *kpred = std::max(1, std::min(p->opts.max_iter, used));
+    const int sb = int(std::min<size_t>(1024, (N + 255) / 256));
+    hipLaunchKernelGGL(ks_adj_corr, dim3(sb), dim3(256), 0, c.stream, c.A, a->corr);
+    a->have_corr = true;
+    a->corr_c = cth;
     // mu = (T^SL)^T lam, then the cotangent of V^s
     hipLaunchKernelGGL((ks_adj_sl<L>), gr, dim3(L / 8), 0, c.stream, c.A);
     if (sd.theta < 1.0) {
@@ -1145,11 +1156,15 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     const double c1 = sd.dt * sd.theta, c2 = sd.dt * (1.0 - sd.theta);
     if (p->jumps) {
         const int np = (n + 1) / 2;
+        // the row transform of Y = V^{s+1} is the V transform of reverse step s + 1 when it had one
+        if (a->xb_is_v) std::swap(a->XB, a->XD);
+        else hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, Y, n, n, n, a->XB, n, p->tw);
         hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, a->lam, n, n, n, a->XA, n, p->tw);
-        hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, Y, n, n, n, a->XB, n, p->tw);
+        a->xb_is_v = false;
         if (c2 != 0.0) {
             hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, a->mu, n, n, n, a->XC, n, p->tw);
             hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, V, n, n, n, a->XD, n, p->tw);
+            a->xb_is_v = true;
         }
         hipLaunchKernelGGL((ks_adj_spec<L>), dim3(L / 2 + 1), dim3(L / 8), 0, c.stream, a->XA, a->XB, a->XC, a->XD, n,
                            c1, c2, a->S, p->tw);
@@ -1222,12 +1237,15 @@ int model_quantities(const Plan* p, const double* x, std::vector<double>& out) {
     return LPIDE_OK;
 }
 
-// Central differences of model_quantities with steps 1e-4 max(|x_q|, 0.1).
+// Central differences of model_quantities with steps 1e-4 max(|x_q|, 0.1)
+// for the seven Levy parameters; r enters only as kappa_omega = r - ... and
+// r_omega = r + sum omega, so its column is exact (0, 0, 0, 1, 1, 1, 0...).
 int model_jacobian(Plan* p, const double* x) {
     Adjoint* a = p->adj;
     if (a->jac_valid && std::equal(x, x + 8, a->jac_std)) return LPIDE_OK;
     std::vector<double> fp, fm;
-    for (int q = 0; q < 8; ++q) {
+    size_t m = 0;
+    for (int q = 0; q < 7; ++q) {
         double xp[8], xm[8];
         std::copy(x, x + 8, xp);
         std::copy(x, x + 8, xm);
@@ -1237,9 +1255,15 @@ int model_jacobian(Plan* p, const double* x) {
         int rc = model_quantities(p, xp, fp);
         if (!rc) rc = model_quantities(p, xm, fm);
         if (rc) return rc;
-        if (q == 0) a->jac.assign(8 * fp.size(), 0.0);
-        for (size_t i = 0; i < fp.size(); ++i) a->jac[q * fp.size() + i] = (fp[i] - fm[i]) / (2.0 * hq);
+        if (q == 0) {
+            m = fp.size();
+            a->jac.assign(8 * m, 0.0);
+        }
+        for (size_t i = 0; i < m; ++i) a->jac[q * m + i] = (fp[i] - fm[i]) / (2.0 * hq);
     }
+    a->jac[7 * m + 3] = 1.0;
+    a->jac[7 * m + 4] = 1.0;
+    a->jac[7 * m + 5] = 1.0;
     std::copy(x, x + 8, a->jac_std);
     a->jac_valid = true;
     return LPIDE_OK;
@@ -1260,12 +1284,13 @@ int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lp
     auto ms = [](std::chrono::steady_clock::time_point t0, std::chrono::steady_clock::time_point t1) {
         return std::chrono::duration<double, std::milli>(t1 - t0).count();
     };
-    auto t0 = now();
+    double t_fwd = 0.0;
     if (!(p->ckpt_valid && p->ckpt_every == C)) {
+        auto t0 = now();
         hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, s, p->V0, a->ckpt, N);
         if ((rc = march_recorded(p, 0, Ns, nullptr, a->ckpt, nullptr, C, nullptr))) return rc;
+        t_fwd = ms(t0, now());
     }
-    auto t1 = now();
     HIP_TRY(hipMemcpyAsync(a->ybar, v_bar, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemsetAsync(a->acc, 0, sizeof(double) * N / n * 8, s));
     if (p->jumps) HIP_TRY(hipMemsetAsync(a->S, 0, sizeof(double2) * (size_t)(p->L / 2 + 1) * p->L, s));
@@ -1286,6 +1311,8 @@ int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lp
     int kpred = std::min(8, p->opts.max_iter);
     int64_t iters = 0;
     int maxit = 0;
+    a->have_corr = false;
+    a->xb_is_v = false;
     for (int q = (Ns - 1) / C; q >= 0; --q) {
         const int s0 = q * C, s1 = std::min(Ns, s0 + C);
         auto ta = now();
@@ -1335,18 +1362,27 @@ int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lp
                 if (j != i) v *= (0.5 - (jlo + j)) / double(i - j);
             sw[i] = v;
         }
-        for (int l1 = -Nz; l1 < Nz; ++l1)
-            for (int l2 = -Nz; l2 < Nz; ++l2) {
-                double t = 0.0;
-                for (int j1 = 0; j1 <= Pin; ++j1)
-                    for (int j2 = 0; j2 <= Pin; ++j2) t += sw[j1] * sw[j2] * gk(l1 + jlo + j1, l2 + jlo + j2);
-                native[6 + (size_t)(l1 + Nz) * W2 + (l2 + Nz)] = t;
-            }
+        auto rows = [&](int r0, int r1) {
+            for (int l1 = r0 - Nz; l1 < r1 - Nz; ++l1)
+                for (int l2 = -Nz; l2 < Nz; ++l2) {
+                    double t = 0.0;
+                    for (int j1 = 0; j1 <= Pin; ++j1)
+                        for (int j2 = 0; j2 <= Pin; ++j2) t += sw[j1] * sw[j2] * gk(l1 + jlo + j1, l2 + jlo + j2);
+                    native[6 + (size_t)(l1 + Nz) * W2 + (l2 + Nz)] = t;
+                }
+        };
+        const int nth = int(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+        std::vector<std::thread> th;
+        for (int t = 0; t < nth; ++t) {
+            const int r0 = int((int64_t)W2 * t / nth), r1 = int((int64_t)W2 * (t + 1) / nth);
+            if (r0 < r1) th.emplace_back(rows, r0, r1);
+        }
+        for (auto& x : th) x.join();
     }
     if (info) {
         info->adj_iters = iters;
         info->max_step_iters = maxit;
-        info->forward_ms = ms(t0, t1);
+        info->forward_ms = t_fwd;
         info->recompute_ms = t_rec;
         info->reverse_ms = t_rev;
         info->gather_ms = ms(tc, now());

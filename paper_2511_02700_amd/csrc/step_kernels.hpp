@@ -587,9 +587,12 @@ __global__ void ks_adj_begin(const MarchArgs* __restrict__ A, int s) {
     }
 }
 
-// Starting value lam^0 = Ybar and its row transform.
+// Starting value lam^0 = Ybar + ratio corr and its row transform, where corr
+// = lam - Ybar of the previous reverse step (lam - Ybar = dt theta A^T lam, so
+// ratio rescales it by the ratio of the steps' dt theta); corr may be null.
 template <int L>
-__global__ __launch_bounds__(L / 8) void ks_adj_start(const MarchArgs* __restrict__ A) {
+__global__ __launch_bounds__(L / 8) void ks_adj_start(const MarchArgs* __restrict__ A,
+                                                     const double* __restrict__ corr, double ratio) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0)) return;
     constexpr int T = L / 8;
@@ -608,16 +611,28 @@ __global__ __launch_bounds__(L / 8) void ks_adj_start(const MarchArgs* __restric
         const int j = threadIdx.x + e * T;
         double va = 0.0, vb = 0.0;
         if (j < n) {
-            va = a.W[(size_t)ra * n + j];
-            lam[(size_t)ra * n + j] = va;
+            const size_t oa = (size_t)ra * n + j, ob = (size_t)rb * n + j;
+            va = a.W[oa] + (corr ? ratio * corr[oa] : 0.0);
+            lam[oa] = va;
             if (hasb) {
-                vb = a.W[(size_t)rb * n + j];
-                lam[(size_t)rb * n + j] = vb;
+                vb = a.W[ob] + (corr ? ratio * corr[ob] : 0.0);
+                lam[ob] = vb;
             }
         }
         reg[e] = make_double2(va, vb);
     }
     rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
+}
+
+// corr = lam - Ybar after the adjoint fixed point converged (start of the next
+// reverse step).
+__global__ void ks_adj_corr(const MarchArgs* __restrict__ A, double* __restrict__ corr) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, 0)) return;
+    const size_t N = (size_t)a.n * a.n;
+    const double* lam = a.pool[a.ctl->y];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x)
+        corr[i] = lam[i] - a.W[i];
 }
 
 // Verdict of the adjoint fixed point of the current reverse step: iteration

@@ -96,10 +96,14 @@ def _fd_grad(lp, w, spots, wts, x0, nz, h_rel=1e-5):
 def _adjoint_grad(lp, w, spots, wts, C=32):
     import torch
     plan = lp.plan_from_workload(w)
+    plan.solve()                                  # warm-up
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     V = plan.solve()
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    plan.set_checkpoints(C)                       # the forward keeps the adjoint's checkpoints
+    V = plan.solve()
     vbar = plan.price_adjoint(spots, wts)
     t0 = time.perf_counter()
     grad, native, info = plan.adjoint(vbar, checkpoint_every=C, std_params=lp.std_params_of(w))
@@ -148,9 +152,11 @@ def test_adjoint_1024_vs_finite_differences(lp):
     _note("adjoint 1024^2, 512 steps")
     plan, grad, info, t_fwd, t_adj = _adjoint_grad(lp, w, spots, wts, C=32)
     dev = info["forward_ms"] + info["recompute_ms"] + info["reverse_ms"] + info["gather_ms"]
-    _note("forward %.1f ms; adjoint %.1f ms wall (device part %.1f ms = %.2f x forward; host Jacobian %.1f ms); "
-          "adjoint iterations %d" % (1e3 * t_fwd, 1e3 * t_adj, dev, dev / (1e3 * t_fwd), info["jacobian_ms"],
-                                     info["adj_iters"]))
+    _note("forward %.1f ms; adjoint %.1f ms wall (march part %.1f ms = %.2f x forward: recompute %.1f, reverse %.1f, "
+          "gather %.1f; host Jacobian %.1f ms); adjoint iterations %d, forward iterations %d" % (
+              1e3 * t_fwd, 1e3 * t_adj, dev, dev / (1e3 * t_fwd), info["recompute_ms"], info["reverse_ms"],
+              info["gather_ms"], info["jacobian_ms"], info["adj_iters"], plan.info()["total_iters"]))
+    assert info["forward_ms"] == 0.0              # the solve's checkpoints were reused
     fd = _fd_grad(lp, w, spots, wts, lp.std_params_of(w), plan.info()["N_z"])
     err = np.abs(grad - fd) / np.max(np.abs(fd))
     _note("grad %s\nfd   %s\nrel err %s" % (np.array2string(grad, precision=8), np.array2string(fd, precision=8),
