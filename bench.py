@@ -13,8 +13,13 @@ Default workload: the 512 x 512 finite-variation NTS case (alpha = 0.3) on
 
 Printed (one JSON line): the metric, the roofline of the dominant kernel
 (algorithmic bytes per launch / mean launch time from HIP events recorded on
-the plan's stream during the timed region) and a CPU baseline: the FP64 oracle
-timed on this host on a bounded sample of the same workload.
+the plan's stream during the timed region), the same for the correlation's
+column pass, the other precision timed beside it with the mixed-vs-plain
+differences, and a CPU baseline: the FP64 oracle timed on this host on a
+bounded sample of the same workload.  Unless --no-extras: the column-pass
+roofline at 2048^2 (cache-exceeding working set), the adjoint form on its
+1024^2 workload (ratio to the forward), and the batched form on 32 draws of
+the batched recipe (against solo solves).
 """
 
 import argparse
@@ -145,6 +150,93 @@ def cpu_baseline(w, steps):
                                                       len(os.sched_getaffinity(0))))
 
 
+def large_conv_roofline(lp, name, steps=40):
+    """Column pass of the correlation at 2048^2 (L = 4096), where the working
+    set (spectrum 134 MB + intermediate 67 MB) no longer fits in the caches:
+    HIP-event mean over the working launches of the first `steps` entries of
+    the step list, FP64 and mixed."""
+    import workloads
+    w = workloads.workload(name)
+    out = {"workload": "%s, first %d step-list entries" % (name, steps)}
+    for prec in ("fp64", "fp32conv"):
+        plan = lp.plan_from_workload(w, precision=prec)
+        plan.solve_steps(4)
+        plan.set_timing(["cols"])
+        plan.solve_steps(steps)
+        la, ms = plan.kernel_stats()["cols"]
+        plan.set_timing([])
+        info = plan.info()
+        out[prec] = roofline("cols", w["n"], info["L"], prec == "fp32conv", la, ms)
+        del plan
+    return out
+
+
+def adjoint_measure(lp, name="nts1024", C=32):
+    """The adjoint form on its workload: forward solve time, and the adjoint's
+    march part (segment recompute + reverse steps + gather, with the solve's
+    checkpoints reused) and host Jacobian, for J = a seeded combination of 64
+    spot-pair prices."""
+    import numpy as np
+    import torch
+    import workloads
+    w = workloads.workload(name)
+    spots = workloads.spot_pairs(64, seed=4)
+    wts = np.random.default_rng(4).standard_normal(64)
+    plan = lp.plan_from_workload(w)
+    plan.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.solve()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    plan.set_checkpoints(C)
+    V = plan.solve()
+    vbar = plan.price_adjoint(spots, wts)
+    t0 = time.perf_counter()
+    grad, _, info = plan.adjoint(vbar, checkpoint_every=C, std_params=lp.std_params_of(w))
+    t_adj = time.perf_counter() - t0
+    march = info["recompute_ms"] + info["reverse_ms"] + info["gather_ms"]
+    return {"workload": "%s: %dx%d, %d steps, checkpoints every %d, J = 64 seeded spot prices" % (
+                name, w["n"], w["n"], w["N_t"], C),
+            "forward_ms": 1e3 * t_fwd, "adjoint_march_ms": march, "ratio_to_forward": march / (1e3 * t_fwd),
+            "host_jacobian_ms": info["jacobian_ms"], "adjoint_wall_ms": 1e3 * t_adj,
+            "adjoint_iters_per_step": info["adj_iters"] / plan.info()["n_steps"],
+            "grad": [float(g) for g in grad]}
+
+
+def batch_measure(lp, count=32, seed=3):
+    """The batched form on the first `count` draws of the batched workload
+    recipe: grid-pt-steps/s of one batched solve (autotuned, hipGraph replay)
+    against the same plans solved one after the other."""
+    import torch
+    import workloads
+    draws = workloads.batch_draw(256, seed=seed)[:count]
+    plans = [lp.plan_from_workload(d) for d in draws]
+    work = sum(d["n"] ** 2 * d["N_t"] for d in draws)
+    batch = lp.Batch(plans)
+    groups = batch.tune(trial_steps=8)
+    outs = batch.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.solve(outs)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    solo = [p._grid_tensor() for p in plans]
+    for p, o in zip(plans, solo):
+        p.solve(o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, o in zip(plans, solo):
+        p.solve(o)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    diff = max(float((a - b).abs().max()) for a, b in zip(outs, solo))
+    return {"workload": "first %d draws of the batched recipe (seed %d): n in %s" % (
+                count, seed, sorted({d["n"] for d in draws})),
+            "value": work / t_b, "unit": "grid-pt-steps/s", "ms": 1e3 * t_b, "solo_ms": 1e3 * t_s,
+            "speedup_vs_solo": t_s / t_b, "max_abs_diff_vs_solo": diff, "groups": groups}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +248,8 @@ def main():
                     help="form timed for the headline value; the other form is timed beside it")
     ap.add_argument("--cpu-steps", type=int, default=8, help="step-list entries of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 2048^2 conv roofline, the adjoint and the batched measurements")
     ap.add_argument("--traffic-json", default=None,
                     help="rocprofv3 counter summary (profsum pmc --json) giving measured HBM bytes per launch; "
                          "default profiles/pmc_<workload>.json")
@@ -243,6 +337,12 @@ def main():
         "mixed_vs_plain_rel": {"prices": rel_p, "deltas_abs": abs_d, "grid": rel_grid, "spots": 64,
                                "bound": 1e-6},
     }
+    if not args.no_extras:
+        del plans, outs, plan
+        torch.cuda.empty_cache()
+        result["conv_roofline_2048"] = large_conv_roofline(lp, "nig2048_m")
+        result["adjoint"] = adjoint_measure(lp)
+        result["batched"] = batch_measure(lp)
     if rank == 0 and not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     if rank == 0:
