@@ -65,20 +65,22 @@ def algorithmic_bytes(cls, n, L, mixed=False):
     }[cls]
 
 
-def kernel_symbol(cls, L, mixed, sl_order):
-    """The kernel instantiation a timing class launches in the march."""
+def kernel_symbol(cls, L, mixed, sl_order, radix=(8, 8, 8, 8)):
+    """The kernel instantiation a timing class launches in the march (radix =
+    elements per thread of the column pass, row c2r, line-row and SL kernels)."""
     tf = "true" if mixed else "false"
     c = "float" if mixed and cls == "cols" else "double"
+    ec, er, el, es = radix
     return {
-        "cols": "lpide::ks_cols<%d, HIP_vector_type<%s, 2u> >" % (L, c),
-        "expl_cols": "lpide::ks_cols<%d, HIP_vector_type<double, 2u> >" % L,
-        "rows_inv": "lpide::ks_rows_inv<%d, %d>" % (L, 2 if mixed else 1),
-        "expl_rows": "lpide::ks_rows_inv<%d, 0>" % L,
+        "cols": "lpide::ks_cols<%d, %d, HIP_vector_type<%s, 2u>, false>" % (L, ec, c),
+        "expl_cols": "lpide::ks_cols<%d, %d, HIP_vector_type<double, 2u>, false>" % (L, ec),
+        "rows_inv": "lpide::ks_rows_inv<%d, %d, %d>" % (L, er, 2 if mixed else 1),
+        "expl_rows": "lpide::ks_rows_inv<%d, %d, 0>" % (L, er),
         "line_cols": "lpide::ks_line_cols",
-        "line_rows": "lpide::ks_line_rows<%d, true, %s>" % (L, tf),
-        "sl": "lpide::ks_sl<%d, %d, true, %s>" % (L, sl_order, tf),
+        "line_rows": "lpide::ks_line_rows<%d, %d, true, %s>" % (L, el, tf),
+        "sl": "lpide::ks_sl<%d, %d, %d, true, %s>" % (L, es, sl_order, tf),
         "step_end": "lpide::ks_step_end",
-        "rows_fwd": "lpide::ks_rows_fwd<%d>" % L,
+        "rows_fwd": "lpide::ks_rows_fwd<%d, %d>" % (L, er),
     }[cls]
 
 
@@ -100,19 +102,19 @@ def measured_traffic(path, symbol):
     return None
 
 
-def roofline(cls, n, L, mixed, launches, ms, traffic_json=None, sl_order=3):
+def roofline(cls, n, L, mixed, launches, ms, traffic_json=None, sl_order=3, radix=(8, 8, 8, 8)):
     per_launch_ms = ms / max(1, launches)
     b = algorithmic_bytes(cls, n, L, mixed)
     achieved = b / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
-    sym = kernel_symbol(cls, L, mixed, sl_order)
+    sym = kernel_symbol(cls, L, mixed, sl_order, radix)
     return {"kernel": cls, "symbol": sym, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(traffic_json, sym), "bytes_per_launch": b,
             "mean_launch_ms": per_launch_ms, "launches": launches}
 
 
 def timed_solves(plan, out, steps, timed_classes):
-    """steps full solves with HIP events around the named kernel classes; wall
-    seconds and the per-class (launches, ms)."""
+    """steps full solves with HIP events around the named kernel classes (none:
+    no events); wall seconds and the per-class (launches, ms)."""
     import torch
     plan.set_timing(timed_classes)
     torch.cuda.synchronize()
@@ -166,7 +168,7 @@ def large_conv_roofline(lp, name, steps=40):
         la, ms = plan.kernel_stats()["cols"]
         plan.set_timing([])
         info = plan.info()
-        out[prec] = roofline("cols", w["n"], info["L"], prec == "fp32conv", la, ms)
+        out[prec] = roofline("cols", w["n"], info["L"], prec == "fp32conv", la, ms, radix=info["radix"])
         del plan
     return out
 
@@ -286,15 +288,20 @@ def main():
     prof = plan.kernel_stats()
     dominant = max(prof, key=lambda c: prof[c][1])
 
-    # timed region: events only around the dominant class and the correlation's column pass
-    wall, live = timed_solves(plan, outs[args.precision], args.steps, sorted({dominant, "cols"}))
+    # timed region: K solves without events (each HIP event pair drains the
+    # queue, about 3 us per timed launch), giving value; then the same K
+    # solves with events around the dominant class and the correlation's
+    # column pass, giving their mean launch durations
+    wall, _ = timed_solves(plan, outs[args.precision], args.steps, [])
+    _, live = timed_solves(plan, outs[args.precision], args.steps, sorted({dominant, "cols"}))
     info = plan.info()
     ms_per_step = 1e3 * wall / args.steps
     value = n * n * Nt * args.steps / wall
 
     # the other precision on the same workload: throughput, conv roofline, and
     # the mixed-vs-plain difference of prices and deltas at seeded spot pairs
-    wall_o, live_o = timed_solves(plans[other], outs[other], args.steps, ["cols"])
+    wall_o, _ = timed_solves(plans[other], outs[other], args.steps, [])
+    _, live_o = timed_solves(plans[other], outs[other], args.steps, ["cols"])
     spots = workloads.spot_pairs(64, seed=7)
     pd = {pr: plans[pr].price(outs[pr], spots, with_delta=True) for pr in plans}
     p64, d64 = (t.cpu().numpy() for t in pd["fp64"])
@@ -326,13 +333,16 @@ def main():
                                    args.sl_order, args.precision),
                    "n": n, "N_t": Nt, "L": L, "N_z": info["N_z"], "precision": args.precision,
                    "parallelism": "single GPU"},
-        "roofline": roofline(dominant, n, L, mixed, *live[dominant], traffic_json=tj, sl_order=args.sl_order),
-        "conv_roofline": roofline("cols", n, L, mixed, *live["cols"], traffic_json=tj, sl_order=args.sl_order),
+        "roofline": roofline(dominant, n, L, mixed, *live[dominant], traffic_json=tj, sl_order=args.sl_order,
+                             radix=info["radix"]),
+        "conv_roofline": roofline("cols", n, L, mixed, *live["cols"], traffic_json=tj, sl_order=args.sl_order,
+                                  radix=info["radix"]),
+        "radix_schedule": dict(zip(("cols", "row_c2r", "line_rows", "sl"), info["radix"])),
         "iters_per_step": info["total_iters"] / info["n_steps"],
         "kernel_ms_per_solve": {c: prof[c][1] for c in prof if prof[c][0]},
         other: {"value": n * n * Nt * args.steps / wall_o, "ms_per_step": 1e3 * wall_o / args.steps,
                 "conv_roofline": roofline("cols", n, L, other == "fp32conv", *live_o["cols"], traffic_json=tj,
-                                          sl_order=args.sl_order),
+                                          sl_order=args.sl_order, radix=plans[other].info()["radix"]),
                 "iters_per_step": plans[other].info()["total_iters"] / info["n_steps"]},
         "mixed_vs_plain_rel": {"prices": rel_p, "deltas_abs": abs_d, "grid": rel_grid, "spots": 64,
                                "bound": 1e-6},

@@ -114,6 +114,9 @@ typedef struct {
     int32_t damping;      /* 1: first step replaced by 4 steps of dt/4 with theta = 1 */
     int32_t device;       /* HIP device ordinal */
     void*   stream;       /* hipStream_t for all of the plan's work (NULL: null stream) */
+    int32_t fft_radix;    /* elements per thread of every FFT kernel of the march, i.e. the radix
+                             of their stages: 4, 8 or 16 (16 needs a transform of >= 256);
+                             0: a default per kernel class and transform size */
 } lpide_opts;
 
 /* Plan-time quantities and run statistics. */
@@ -130,6 +133,8 @@ typedef struct {
     int32_t last_step_iters;
     double  last_increment;           /* last stopping-rule value of the last solve */
     int64_t device_bytes;             /* device memory held by the plan */
+    int32_t radix[4];                 /* FFT elements per thread (radix schedule) of the march's
+                                         column pass, row c2r kernels, line-row kernel, SL kernel */
 } lpide_info;
 
 /* Default settings: the paper's scheme settings (Sec. 4) on an n x n grid over
@@ -287,6 +292,7 @@ typedef struct {
 typedef struct {
     int32_t n_plans, L, mixed;        /* plans of the group, row-kernel size, mixed form */
     int32_t P_cols, slots, use_graph; /* launch configuration (set by lpide_batch_tune) */
+    int32_t radix[4];                 /* radix schedule, as lpide_info.radix */
     double  trial_ms;                 /* wall time of the tuning trial kept (0 before tuning) */
 } lpide_group_info;
 
@@ -309,10 +315,13 @@ int lpide_batch_solve(void* batch, double* const* v_out);
 int lpide_batch_solve_steps(void* batch, int32_t steps, double* const* v_out);
 
 /* Autotuner: for each group, time the march of the first trial_steps entries
- * under every candidate launch configuration (axis-1 line-solve chunking
- * P_cols in {P/2, P, 2P} around the default P, hipGraph replay on/off, 16 or
- * 32 step slots per host check), each run twice with the second timed, and
- * keep the fastest.  Synchronises the device work of the batch. */
+ * under candidate launch configurations and keep the fastest, in three
+ * rounds: the FFT radix schedule (4, 8 or 16 elements per thread, per kernel
+ * class, one class at a time from the default), the axis-1
+ * line-solve chunking P_cols in {P/2, P, 2P} around the default P, then
+ * hipGraph replay on/off with 16 or 32 step slots per host check; each
+ * candidate runs twice with the second timed.  Synchronises the device work
+ * of the batch. */
 int lpide_batch_tune(void* batch, int32_t trial_steps);
 
 /* Groups of the batch: *n_groups, and up to cap entries of groups (may be NULL). */

@@ -33,7 +33,7 @@ class Payoff(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
-                ("damping", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p)]
+                ("damping", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p), ("fft_radix", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -42,7 +42,7 @@ class Info(C.Structure):
                 ("h", C.c_double), ("z_star", C.c_double), ("sum_omega", C.c_double),
                 ("kappa", C.c_double * 2), ("r_omega", C.c_double), ("S", C.c_double * 3), ("a", C.c_double * 3),
                 ("total_iters", C.c_int64), ("max_step_iters", C.c_int32), ("last_step_iters", C.c_int32),
-                ("last_increment", C.c_double), ("device_bytes", C.c_int64)]
+                ("last_increment", C.c_double), ("device_bytes", C.c_int64), ("radix", C.c_int32 * 4)]
 
     def to_dict(self):
         out = {}
@@ -67,10 +67,15 @@ class BatchOpts(C.Structure):
 
 class GroupInfo(C.Structure):
     _fields_ = [("n_plans", C.c_int32), ("L", C.c_int32), ("mixed", C.c_int32), ("P_cols", C.c_int32),
-                ("slots", C.c_int32), ("use_graph", C.c_int32), ("trial_ms", C.c_double)]
+                ("slots", C.c_int32), ("use_graph", C.c_int32), ("radix", C.c_int32 * 4),
+                ("trial_ms", C.c_double)]
 
     def to_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
 
 
 # exported symbol -> (restype, argtypes)

@@ -1,10 +1,10 @@
 // Workgroup-level Stockham FFT for CDNA4 (gfx950), FP64 and FP32 complex data
 // (twiddles always formed in FP64; see twmul).
 //
-// One workgroup transforms one length-L sequence (L a power of two, 128..8192)
-// with T = L/8 threads.  Each thread keeps E = 8 elements in registers in the
-// canonical layout reg[e] = element (tid + e*T); the radix-R stages (radix 8,
-// plus one radix-2 or radix-4 stage when log2 L is not a multiple of 3)
+// One workgroup transforms one length-L sequence (L a power of two, 64..4096)
+// with T = L/E threads, E in {4, 8, 16} elements per thread held in registers
+// in the canonical layout reg[e] = element (tid + e*T); the stages are radix E,
+// plus one smaller first stage when log2 L is not a multiple of log2 E, and
 // exchange data through one LDS buffer of L complex values (plus padding).  Input and output
 // of the whole transform are in the canonical layout, so a load or store of
 // element (tid + e*T) by thread tid is coalesced, and the output registers of a
@@ -98,11 +98,60 @@ __device__ __forceinline__ void dft8(C* v) {
     v[7] = csub(e3, w3);
 }
 
+// 16-point DFT as 4 x 4: DFT4 over the stride-4 subsequences, twiddles
+// W16^{q k}, DFT4 across, output index k + 4 m.
+template <bool INV, typename C>
+__device__ __forceinline__ void dft16(C* v) {
+    using Rl = typename CplxOps<C>::real;
+    const Rl c1 = Rl(0.92387953251128675612818318939678829), s1 = Rl(0.38268343236508977172845998403039887);
+    const Rl h = Rl(0.70710678118654752440084436210484904);
+    C a[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        a[q][0] = v[q];
+        a[q][1] = v[q + 4];
+        a[q][2] = v[q + 8];
+        a[q][3] = v[q + 12];
+        dft4<INV>(a[q][0], a[q][1], a[q][2], a[q][3]);   // a[q][k] = sum_m v[q + 4m] W4^{mk}
+    }
+    // W16^{q k} for q, k in 0..3 (forward sign; conjugated for the inverse)
+    auto tw = [&](C x, int e) -> C {
+        // e = q k in 0..9: W16^e = cos(2 pi e/16) -/+ i sin(2 pi e/16)
+        Rl cr, si;
+        switch (e) {
+            case 0: return x;
+            case 1: cr = c1; si = s1; break;
+            case 2: cr = h; si = h; break;
+            case 3: cr = s1; si = c1; break;
+            case 4: return mul_mi<INV>(x);
+            case 6: cr = -h; si = h; break;
+            case 9: cr = -c1; si = -s1; break;
+            default: cr = 0; si = 0; break;
+        }
+        const C w = INV ? CplxOps<C>::make(cr, si) : CplxOps<C>::make(cr, -si);
+        return cmul(x, w);
+    };
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+#pragma unroll
+        for (int k = 1; k < 4; ++k) a[q][k] = tw(a[q][k], q * k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        C b0 = a[0][k], b1 = a[1][k], b2 = a[2][k], b3 = a[3][k];
+        dft4<INV>(b0, b1, b2, b3);                        // across q: output k + 4 m
+        v[k] = b0;
+        v[k + 4] = b1;
+        v[k + 8] = b2;
+        v[k + 12] = b3;
+    }
+}
+
 template <int R, bool INV, typename C>
 __device__ __forceinline__ void dft(C* v) {
     if constexpr (R == 2) dft2<INV>(v);
     else if constexpr (R == 4) dft4<INV>(v);
-    else dft8<INV>(v);
+    else if constexpr (R == 8) dft8<INV>(v);
+    else dft16<INV>(v);
 }
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
@@ -127,52 +176,76 @@ __device__ __forceinline__ float2 twmul(float2 v, double2 w) {
     return make_float2(a.x + b.x, a.y + b.y);
 }
 
-// Stage twiddle tables.  Stage s >= 1 is always radix 8 with Ns = R0 8^(s-1)
-// (R0 the radix of stage 0); its butterfly k needs W^r = exp(-+2 pi i r k / (8 Ns)),
-// r = 1..7.  Only the base W = exp(-2 pi i k / (8 Ns)), k in [0, Ns), is stored
+// Stage twiddle tables.  Stage s >= 1 is always radix E with Ns = R0 E^(s-1)
+// (R0 the radix of stage 0); its butterfly k needs W^r = exp(-+2 pi i r k / (E Ns)),
+// r = 1..E-1.  Only the base W = exp(-2 pi i k / (E Ns)), k in [0, Ns), is stored
 // (stage tables concatenated, k contiguous, so a wave reads consecutive
-// entries without bank conflicts); the powers W^2..W^7 are formed in registers
-// with at most three complex products each.
-template <int L>
+// entries without bank conflicts); the powers are formed in registers with a
+// product tree of depth log2 E.
+template <int L, int E>
 struct TwTab {
     static constexpr int LOG = ilog2c(L);
-    static constexpr int R0 = (LOG % 3 == 1) ? 2 : (LOG % 3 == 2) ? 4 : 8;
-    static constexpr int NST = LOG / 3 + (LOG % 3 ? 1 : 0);
+    static constexpr int LE = ilog2c(E);
+    static constexpr int R0 = (LOG % LE) ? (1 << (LOG % LE)) : E;
+    static constexpr int NST = LOG / LE + (LOG % LE ? 1 : 0);
     // Ns of stage s and the offset of its table (sum of Ns over stages 1..s-1);
     // closed forms, so runtime uses compile to shifts (no recursion on the device)
-    static constexpr __host__ __device__ int ns(int s) { return s == 0 ? 1 : R0 << (3 * (s - 1)); }
-    static constexpr __host__ __device__ int off(int s) { return s <= 1 ? 0 : R0 * ((1 << (3 * (s - 1))) - 1) / 7; }
+    static constexpr __host__ __device__ int ns(int s) { return s == 0 ? 1 : R0 << (LE * (s - 1)); }
+    static constexpr __host__ __device__ int off(int s) {
+        return s <= 1 ? 0 : R0 * ((1 << (LE * (s - 1))) - 1) / (E - 1);
+    }
     static constexpr int size = off(NST);           // entries over stages 1..NST-1
 };
-template <int L>
-constexpr int tw_slots() { return TwTab<L>::size; }
+template <int L, int E>
+constexpr int tw_slots() { return TwTab<L, E>::size > 0 ? TwTab<L, E>::size : 1; }
 
 // Build the stage tables in LDS from the full table tw[q] = exp(-2 pi i q / L);
 // visible to the FFT stages after the next barrier (stage 0 needs none).
-template <int L>
+template <int L, int E>
 __device__ __forceinline__ void load_twiddles(const double2* __restrict__ tw, double2* tab) {
-    using TT = TwTab<L>;
-    for (int i = threadIdx.x; i < TT::size; i += L / 8) {
+    using TT = TwTab<L, E>;
+    for (int i = threadIdx.x; i < TT::size; i += L / E) {
         int s = 1;
 #pragma unroll
         for (int q = 2; q < TT::NST; ++q)
             if (i >= TT::off(q)) s = q;
         const int k = i - TT::off(s);
-        tab[i] = tw[k * (L / (TT::ns(s) * 8))];
+        tab[i] = tw[k * (L / (TT::ns(s) * E))];
+    }
+}
+
+// W^1..W^{R-1} from W^1 = w1 by a product tree (in FP64).
+template <int R>
+__device__ __forceinline__ void twiddle_powers(double2 w1, double2 (&w)[R]) {
+    w[1] = w1;
+    if constexpr (R > 2) {
+        w[2] = cmul(w1, w1);
+        w[3] = cmul(w[2], w1);
+    }
+    if constexpr (R > 4) {
+        w[4] = cmul(w[2], w[2]);
+        w[5] = cmul(w[4], w1);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
+    }
+    if constexpr (R > 8) {
+        w[8] = cmul(w[4], w[4]);
+#pragma unroll
+        for (int r = 9; r < R; ++r) w[r] = cmul(w[8], w[r - 8]);
     }
 }
 
 // One Stockham stage.  Preconditions: if !FIRST, the previous stage's LDS writes
 // are complete and visible (barrier).  Postcondition: if !LAST, this stage's
 // LDS writes are complete and visible; if LAST, the result is in reg.
-template <int L, int R, bool INV, bool FIRST, bool LAST, typename C>
-__device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, int toff, const double2* tab) {
-    constexpr int T = L / 8;
-    constexpr int NB = 8 / R;          // butterflies per thread
+template <int L, int E, int R, bool INV, bool FIRST, bool LAST, typename C>
+__device__ __forceinline__ void fft_stage(C (&reg)[E], C* lds, int Ns, int toff, const double2* tab) {
+    constexpr int T = L / E;
+    constexpr int NB = E / R;          // butterflies per thread
     const int tid = threadIdx.x;
     if constexpr (!FIRST) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) reg[e] = lds[lds_slot(tid + e * T)];
+        for (int e = 0; e < E; ++e) reg[e] = lds[lds_slot(tid + e * T)];
     }
     if constexpr (!LAST) __syncthreads();
 #pragma unroll
@@ -183,17 +256,12 @@ __device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, int toff,
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = reg[b + r * NB];
         if constexpr (!FIRST) {
-            static_assert(R == 8, "stages after the first are radix 8");
+            static_assert(R == E, "stages after the first are radix E");
             const double2 t = tab[toff + k];
-            const double2 w1 = make_double2(t.x, INV ? -t.y : t.y);
-            const double2 w2 = cmul(w1, w1), w3 = cmul(w2, w1), w4 = cmul(w2, w2);
-            v[1] = twmul(v[1], w1);
-            v[2] = twmul(v[2], w2);
-            v[3] = twmul(v[3], w3);
-            v[4] = twmul(v[4], w4);
-            v[5] = twmul(v[5], cmul(w4, w1));
-            v[6] = twmul(v[6], cmul(w4, w2));
-            v[7] = twmul(v[7], cmul(w4, w3));
+            double2 w[R];
+            twiddle_powers<R>(make_double2(t.x, INV ? -t.y : t.y), w);
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[r] = twmul(v[r], w[r]);
         }
         dft<R, INV>(v);
         if constexpr (LAST) {
@@ -208,12 +276,12 @@ __device__ __forceinline__ void fft_stage(C (&reg)[8], C* lds, int Ns, int toff,
     if constexpr (!LAST) __syncthreads();
 }
 
-template <int L, bool INV, int S, int NST, typename C>
-__device__ __forceinline__ void fft_stages(C (&reg)[8], C* lds, const double2* tab) {
-    using TT = TwTab<L>;
-    constexpr int R = S == 0 ? TT::R0 : 8;
-    fft_stage<L, R, INV, S == 0, S == NST - 1>(reg, lds, TT::ns(S), S == 0 ? 0 : TT::off(S), tab);
-    if constexpr (S + 1 < NST) fft_stages<L, INV, S + 1, NST>(reg, lds, tab);
+template <int L, int E, bool INV, int S, int NST, typename C>
+__device__ __forceinline__ void fft_stages(C (&reg)[E], C* lds, const double2* tab) {
+    using TT = TwTab<L, E>;
+    constexpr int R = S == 0 ? TT::R0 : E;
+    fft_stage<L, E, R, INV, S == 0, S == NST - 1>(reg, lds, TT::ns(S), S == 0 ? 0 : TT::off(S), tab);
+    if constexpr (S + 1 < NST) fft_stages<L, E, INV, S + 1, NST>(reg, lds, tab);
 }
 
 // Unnormalised length-L transform of the workgroup's sequence held in the
@@ -221,12 +289,11 @@ __device__ __forceinline__ void fft_stages(C (&reg)[8], C* lds, const double2* t
 // stage twiddle tables in LDS, written (load_twiddles) before the call; the
 // first stage needs no twiddles and its barrier publishes them.  After
 // return, other threads may still read LDS: barrier before reusing it.
-template <int L, bool INV, typename C>
-__device__ __forceinline__ void fft_block(C (&reg)[8], C* lds, const double2* tab) {
-    constexpr int LOG = ilog2c(L);
-    constexpr int NST = LOG / 3 + (LOG % 3 ? 1 : 0);
-    static_assert((1 << LOG) == L && L >= 64, "L must be a power of two >= 64");
-    fft_stages<L, INV, 0, NST>(reg, lds, tab);
+template <int L, int E, bool INV, typename C>
+__device__ __forceinline__ void fft_block(C (&reg)[E], C* lds, const double2* tab) {
+    using TT = TwTab<L, E>;
+    static_assert((1 << TT::LOG) == L && L >= 64 && (E == 4 || E == 8 || E == 16), "L a power of two >= 64");
+    fft_stages<L, E, INV, 0, TT::NST>(reg, lds, tab);
 }
 
 }  // namespace lpide

@@ -62,8 +62,8 @@ __global__ __launch_bounds__(L / 8) void k_rows_fwd(const double* __restrict__ Y
                                                    const double2* __restrict__ tw) {
     constexpr int T = L / 8;
     __shared__ double2 lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L>()];
-    load_twiddles<L>(tw, tw4);
+    __shared__ double2 tw4[tw_slots<L, 8>()];
+    load_twiddles<L, 8>(tw, tw4);
     const int np = (n_rows + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, np);
     const int ra = 2 * p, rb = 2 * p + 1;
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(L / 8) void k_rows_fwd(const double* __restrict__ Y
         }
         reg[e] = make_double2(a, b);
     }
-    fft_block<L, false>(reg, lds, tw4);
+    fft_block<L, 8, false>(reg, lds, tw4);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 8; ++e) lds[tid + e * T] = reg[e];
@@ -108,8 +108,8 @@ __global__ __launch_bounds__(L / 8) void k_cols(double2* __restrict__ X, int ldx
                                                const double2* __restrict__ tw) {
     constexpr int T = L / 8;
     __shared__ double2 lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L>()];
-    load_twiddles<L>(tw, tw4);
+    __shared__ double2 tw4[tw_slots<L, 8>()];
+    load_twiddles<L, 8>(tw, tw4);
     const int col = blockIdx.x;
     const int tid = threadIdx.x;
     double2* xc = X + (size_t)col * ldx;
@@ -119,9 +119,9 @@ __global__ __launch_bounds__(L / 8) void k_cols(double2* __restrict__ X, int ldx
         const int idx = tid + e * T;
         reg[e] = idx < n_in ? xc[idx] : make_double2(0.0, 0.0);
     }
-    if constexpr (MODE != 2) fft_block<L, false>(reg, lds, tw4);
+    if constexpr (MODE != 2) fft_block<L, 8, false>(reg, lds, tw4);
     if constexpr (MODE == 2) {
-        fft_block<L, true>(reg, lds, tw4);
+        fft_block<L, 8, true>(reg, lds, tw4);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int idx = tid + e * T;
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(L / 8) void k_cols(double2* __restrict__ X, int ldx
         const double2* sc = spec + (size_t)col * L;
 #pragma unroll
         for (int e = 0; e < 8; ++e) reg[e] = cmul(reg[e], sc[tid + e * T]);
-        fft_block<L, true>(reg, lds, tw4);
+        fft_block<L, 8, true>(reg, lds, tw4);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int idx = tid + e * T;
@@ -153,8 +153,8 @@ __global__ __launch_bounds__(L / 8) void k_rows_inv(const double2* __restrict__ 
                                                    double* __restrict__ out, const double2* __restrict__ tw) {
     constexpr int T = L / 8;
     __shared__ double2 lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L>()];
-    load_twiddles<L>(tw, tw4);
+    __shared__ double2 tw4[tw_slots<L, 8>()];
+    load_twiddles<L, 8>(tw, tw4);
     const int np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, np);
     const int ra = 2 * p, rb = 2 * p + 1;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(L / 8) void k_rows_inv(const double2* __restrict__ 
         // Z_k = A_k + i B_k, with A_{L-k} = conj A_k, B_{L-k} = conj B_k
         reg[e] = lo ? make_double2(ha.x - hb.y, ha.y + hb.x) : make_double2(ha.x + hb.y, hb.x - ha.y);
     }
-    fft_block<L, true>(reg, lds, tw4);
+    fft_block<L, 8, true>(reg, lds, tw4);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int j = tid + e * T;
@@ -273,6 +273,10 @@ namespace {
 
 struct Plan;
 
+// Radix schedule (FFT elements per thread) of each kernel class of the march:
+// column pass, row c2r kernels (+ explicit part, row FFT of V), line rows, SL.
+struct Schedule { int cols, rinv, lrows, sl; };
+
 // Launch shape of a group of plans that share the transform size: the march
 // kernels run one grid for all of them (blockIdx.y = plan).
 struct Launch {
@@ -285,6 +289,9 @@ struct Launch {
     int xaff = 0;                   // max rows (affine kernels without jumps)
     int P_cols = 16;
     int sl_order = 3;
+    // FFT elements per thread (radix schedule: 4, 8 or 16) of each kernel class:
+    // column pass, row c2r (+ explicit part, row FFT of V), line rows, SL
+    int E_cols = 8, E_rinv = 8, E_lrows = 8, E_sl = 8;
     bool jumps = false, mixed = false;
     Plan* timer = nullptr;          // records kernel timing (single-plan marches only)
     bool record = false;            // launch the state-recording kernels (adjoint checkpoints)
@@ -346,6 +353,7 @@ struct Plan {
     std::vector<int> step_set;
     int n_steps = 0;
     int P_cols = 16;
+    Schedule sched{8, 8, 8, 8};    // radix schedule of the march kernels
     Group* solo = nullptr;         // this plan alone, on its own stream
     // adjoint march (allocated on the first lpide_adjoint call)
     struct Adjoint* adj = nullptr;
@@ -513,18 +521,38 @@ void launch_rows_fwd(Plan* p, const double* Y, hipStream_t s) {
 }
 
 // ---- one step slot of the device-controlled march, for a group of plans ----
+// Radix schedules instantiated per transform size: E = 4 and 8 always, E = 16
+// from L = 256 on (at least 16 threads per transform).
+constexpr bool e_supported(int L, int E) { return E == 4 || E == 8 || (E == 16 && L >= 256); }
+
+// Call f(std::integral_constant<int, E>) for the runtime E of a kernel class.
+template <int L, typename F>
+void with_E(int E, F&& f) {
+    if (E == 4) f(std::integral_constant<int, 4>{});
+    else if constexpr (L >= 256) {
+        if (E == 16) f(std::integral_constant<int, 16>{});
+        else f(std::integral_constant<int, 8>{});
+    } else f(std::integral_constant<int, 8>{});
+}
+
 template <int L, bool FFT, bool MIXED>
 void launch_iteration(const Launch& c, int k) {
     using C = typename std::conditional<MIXED, float2, double2>::type;
     if (c.timer) c.timer->tag_k = k;
-    const dim3 gr(c.xrows, c.np), gc(L / 2 + 1, c.np);
     if (FFT) {
         {
             KTime t(c.timer, LPIDE_K_COLS);
-            hipLaunchKernelGGL((ks_cols<L, C>), gc, dim3(L / 8), 0, c.stream, c.A, k);
+            with_E<L>(c.E_cols, [&](auto e) {
+                constexpr int E = decltype(e)::value;
+                hipLaunchKernelGGL((ks_cols<L, E, C>), dim3(L / 2 + 1, c.np), dim3(L / E), 0, c.stream, c.A, k);
+            });
         }
         KTime t(c.timer, LPIDE_K_ROWS_INV);
-        hipLaunchKernelGGL((ks_rows_inv<L, MIXED ? 2 : 1>), gr, dim3(L / 8), 0, c.stream, c.A, k);
+        with_E<L>(c.E_rinv, [&](auto e) {
+            constexpr int E = decltype(e)::value;
+            hipLaunchKernelGGL((ks_rows_inv<L, E, MIXED ? 2 : 1>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A,
+                               k);
+        });
     } else {
         KTime t(c.timer, LPIDE_K_ROWS_INV);
         hipLaunchKernelGGL((ks_affine_noB<false>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, k);
@@ -535,7 +563,10 @@ void launch_iteration(const Launch& c, int k) {
                            c.stream, c.A, k);
     }
     KTime t(c.timer, LPIDE_K_LINE_ROWS);
-    hipLaunchKernelGGL((ks_line_rows<L, FFT, MIXED>), gr, dim3(L / 8), 0, c.stream, c.A, k);
+    with_E<L>(c.E_lrows, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_line_rows<L, E, FFT, MIXED>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A, k);
+    });
 }
 
 // One entry of every plan's step list.  The FP64 correlation of V^{n-1} runs
@@ -551,24 +582,36 @@ void launch_step(const Launch& c, int kmax) {
     if (FFT) {
         if (MIXED) {
             KTime t(c.timer, LPIDE_K_ROWS_FWD);
-            hipLaunchKernelGGL((ks_rows_fwd<L>), gr, dim3(L / 8), 0, c.stream, c.A);
+            with_E<L>(c.E_rinv, [&](auto e) {
+                constexpr int E = decltype(e)::value;
+                hipLaunchKernelGGL((ks_rows_fwd<L, E>), gr, dim3(L / E), 0, c.stream, c.A);
+            });
         }
         {
             KTime t(c.timer, LPIDE_K_EXPL_COLS);
-            hipLaunchKernelGGL((ks_cols<L, double2>), gc, dim3(L / 8), 0, c.stream, c.A, 0);
+            with_E<L>(c.E_cols, [&](auto e) {
+                constexpr int E = decltype(e)::value;
+                hipLaunchKernelGGL((ks_cols<L, E, double2>), gc, dim3(L / E), 0, c.stream, c.A, 0);
+            });
         }
         KTime t(c.timer, LPIDE_K_EXPL_ROWS);
-        hipLaunchKernelGGL((ks_rows_inv<L, 0>), gr, dim3(L / 8), 0, c.stream, c.A, 0);
+        with_E<L>(c.E_rinv, [&](auto e) {
+            constexpr int E = decltype(e)::value;
+            hipLaunchKernelGGL((ks_rows_inv<L, E, 0>), gr, dim3(L / E), 0, c.stream, c.A, 0);
+        });
     } else {
         KTime t(c.timer, LPIDE_K_EXPL_ROWS);
         hipLaunchKernelGGL((ks_affine_noB<true>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, 0);
     }
     {
         KTime t(c.timer, LPIDE_K_SL);
-        if (c.sl_order == 1)
-            hipLaunchKernelGGL((ks_sl<L, 1, FFT, MIXED>), gr, dim3(L / 8), 0, c.stream, c.A);
-        else
-            hipLaunchKernelGGL((ks_sl<L, 3, FFT, MIXED>), gr, dim3(L / 8), 0, c.stream, c.A);
+        with_E<L>(c.E_sl, [&](auto e) {
+            constexpr int E = decltype(e)::value;
+            if (c.sl_order == 1)
+                hipLaunchKernelGGL((ks_sl<L, E, 1, FFT, MIXED>), gr, dim3(L / E), 0, c.stream, c.A);
+            else
+                hipLaunchKernelGGL((ks_sl<L, E, 3, FFT, MIXED>), gr, dim3(L / E), 0, c.stream, c.A);
+        });
     }
     if (c.record) hipLaunchKernelGGL(ks_store_E, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
     for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT, MIXED>(c, k);
@@ -595,6 +638,31 @@ void launch_iteration_L(const Launch& c, int k) {
     if (!c.jumps) launch_iteration<L, false, false>(c, k);
     else if (c.mixed) launch_iteration<L, true, true>(c, k);
     else launch_iteration<L, true, false>(c, k);
+}
+
+// Default radix schedule.  From measurements on MI355X: the column pass and
+// the line-row kernel gain from radix 16 at L >= 2048, the row c2r kernels
+// from radix 4 up to L = 1024, the SL kernel from radix 4 at every size.
+Schedule default_schedule(int L) {
+    Schedule s;
+    s.cols = L >= 2048 ? 16 : 8;
+    s.rinv = L <= 1024 ? 4 : 8;
+    s.lrows = L >= 2048 ? 16 : 8;
+    s.sl = 4;
+    return s;
+}
+
+Schedule uniform_schedule(int E) { return Schedule{E, E, E, E}; }
+
+bool schedule_ok(int L, const Schedule& s) {
+    return e_supported(L, s.cols) && e_supported(L, s.rinv) && e_supported(L, s.lrows) && e_supported(L, s.sl);
+}
+
+void apply_schedule(Launch& c, const Schedule& s) {
+    c.E_cols = s.cols;
+    c.E_rinv = s.rinv;
+    c.E_lrows = s.lrows;
+    c.E_sl = s.sl;
 }
 
 #define LPIDE_SWITCH_L(Lv, CALL)                                                         \
@@ -682,6 +750,7 @@ int make_group(const std::vector<Plan*>& plans, hipStream_t stream, Group** out)
     c.jumps = plans[0]->jumps;
     c.mixed = plans[0]->mixed;
     c.sl_order = plans[0]->hp.sl_order;
+    apply_schedule(c, plans[0]->sched);
     int nmax = 0;
     for (Plan* p : plans) {
         nmax = std::max(nmax, p->hp.n);
@@ -729,6 +798,14 @@ int set_P_cols(Group* g, int P) {
         if (!P_cols_valid(p->hp.n, P)) return fail(LPIDE_E_PARAM, "P_cols not valid for the grid size");
     g->lc.P_cols = P;
     for (auto& a : g->args_h) a.P_cols = P;
+    drop_graphs(g);
+    return LPIDE_OK;
+}
+
+// Set the radix schedule (elements per thread) of the group's FFT kernels.
+int set_schedule(Group* g, const Schedule& s) {
+    if (!schedule_ok(g->lc.L, s)) return fail(LPIDE_E_PARAM, "radix schedule not available for this size");
+    apply_schedule(g->lc, s);
     drop_graphs(g);
     return LPIDE_OK;
 }
@@ -1090,11 +1167,11 @@ int march_recorded(Plan* p, int step0, int nsteps, const double* v_in, double* s
 template <int L>
 void launch_adj_iteration(const Launch& c, int k) {
     const dim3 gr(c.xrows, 1), gc(L / 2 + 1, 1);
-    hipLaunchKernelGGL((ks_cols<L, double2, true>), gc, dim3(L / 8), 0, c.stream, c.A, k);
-    hipLaunchKernelGGL((ks_rows_inv<L, 3>), gr, dim3(L / 8), 0, c.stream, c.A, k);
+    hipLaunchKernelGGL((ks_cols<L, 8, double2, true>), gc, dim3(L / 8), 0, c.stream, c.A, k);
+    hipLaunchKernelGGL((ks_rows_inv<L, 8, 3>), gr, dim3(L / 8), 0, c.stream, c.A, k);
     hipLaunchKernelGGL(ks_line_cols, dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols, c.stream,
                        c.A, k);
-    hipLaunchKernelGGL((ks_line_rows<L, true, false>), gr, dim3(L / 8), 0, c.stream, c.A, k);
+    hipLaunchKernelGGL((ks_line_rows<L, 8, true, false>), gr, dim3(L / 8), 0, c.stream, c.A, k);
 }
 
 // One reverse step s: Ybar (in adj->ybar) -> cotangent of V^s (in adj->ybar),
@@ -1108,7 +1185,7 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     const dim3 gr(c.xrows, 1);
     hipLaunchKernelGGL(ks_adj_begin, dim3(1), dim3(64), 0, c.stream, c.A, s);
     const double cth = sd.dt * sd.theta;
-    hipLaunchKernelGGL((ks_adj_start<L>), gr, dim3(L / 8), 0, c.stream, c.A, a->have_corr ? a->corr : nullptr,
+    hipLaunchKernelGGL((ks_adj_start<L, 8>), gr, dim3(L / 8), 0, c.stream, c.A, a->have_corr ? a->corr : nullptr,
                        a->have_corr && a->corr_c > 0.0 ? cth / a->corr_c : 0.0);
     int k = *kpred;
     for (int q = 1; q <= k; ++q) launch_adj_iteration<L>(c, q);
@@ -1143,10 +1220,10 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     a->have_corr = true;
     a->corr_c = cth;
     // mu = (T^SL)^T lam, then the cotangent of V^s
-    hipLaunchKernelGGL((ks_adj_sl<L>), gr, dim3(L / 8), 0, c.stream, c.A);
+    hipLaunchKernelGGL((ks_adj_sl<L, 8>), gr, dim3(L / 8), 0, c.stream, c.A);
     if (sd.theta < 1.0) {
-        hipLaunchKernelGGL((ks_cols<L, double2, true>), dim3(L / 2 + 1, 1), dim3(L / 8), 0, c.stream, c.A, 0);
-        hipLaunchKernelGGL((ks_rows_inv<L, 4>), gr, dim3(L / 8), 0, c.stream, c.A, 0);
+        hipLaunchKernelGGL((ks_cols<L, 8, double2, true>), dim3(L / 2 + 1, 1), dim3(L / 8), 0, c.stream, c.A, 0);
+        hipLaunchKernelGGL((ks_rows_inv<L, 8, 4>), gr, dim3(L / 8), 0, c.stream, c.A, 0);
     }
     // gradient terms (they read lam and mu; the new cotangent is written last)
     if (p->hp.sl_order == 1)
@@ -1556,6 +1633,8 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     if (o.precision != LPIDE_FP64 && o.precision != LPIDE_FP32_CONV)
         return fail(LPIDE_E_PARAM, "precision must be LPIDE_FP64 or LPIDE_FP32_CONV");
     if (o.max_iter > MAX_ITER_CAP) return fail(LPIDE_E_PARAM, "max_iter must not exceed 128");
+    if (o.fft_radix != 0 && o.fft_radix != 4 && o.fft_radix != 8 && o.fft_radix != 16)
+        return fail(LPIDE_E_PARAM, "fft_radix must be 0, 4, 8 or 16");
     Plan* p = new Plan();
     std::string err;
     if (!build_host_plan(*grid, *levy, p->hp, err)) { delete p; return fail(LPIDE_E_PARAM, err); }
@@ -1680,6 +1759,8 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
             if (e != hipSuccess) return bail(fail(LPIDE_E_HIP, std::string("spectrum32: ") + hipGetErrorString(e)));
         }
     }
+    p->sched = o.fft_radix ? uniform_schedule(o.fft_radix) : default_schedule(p->Lr);
+    if (!schedule_ok(p->Lr, p->sched)) return bail(fail(LPIDE_E_PARAM, "fft_radix 16 needs a transform of at least 256"));
     if ((rc = make_group(std::vector<Plan*>{p}, p->stream, &p->solo))) return bail(rc);
     *out = p;
     return LPIDE_OK;
@@ -1716,6 +1797,10 @@ int lpide_plan_info(void* plan, lpide_info* info) {
     info->last_step_iters = p->last_step_iters;
     info->last_increment = p->last_inc;
     info->device_bytes = p->bytes;
+    info->radix[0] = p->solo->lc.E_cols;
+    info->radix[1] = p->solo->lc.E_rinv;
+    info->radix[2] = p->solo->lc.E_lrows;
+    info->radix[3] = p->solo->lc.E_sl;
     return LPIDE_OK;
 }
 
@@ -1935,10 +2020,12 @@ int lpide_batch_solve_steps(void* batch, int32_t steps, double* const* v_out) {
     return batch_march(static_cast<Batch*>(batch), v_out, steps);
 }
 
-// Autotuning: per group, time the march of the first trial_steps entries for
-// every candidate launch configuration (axis-1 line-solve chunking P_cols,
-// hipGraph replay on/off, step slots per host check) and keep the fastest.
-// Each candidate runs twice; the second run is timed, so graph capture and
+// Autotuning: per group, time the march of the first trial_steps entries
+// under candidate launch configurations and keep the fastest, in three rounds:
+// the radix schedule of the FFT kernels (4, 8 or 16 elements per thread), then
+// the axis-1 line-solve chunking P_cols (P/2, P, 2P around the default), then
+// hipGraph replay on/off with 16 or 32 step slots per host check.  Each
+// candidate runs twice; the second run is timed, so graph capture and
 // first-launch costs are not counted.
 int lpide_batch_tune(void* batch, int32_t trial_steps) {
     if (!batch || trial_steps < 1) return fail(LPIDE_E_PARAM, "NULL batch or trial_steps < 1");
@@ -1951,34 +2038,58 @@ int lpide_batch_tune(void* batch, int32_t trial_steps) {
             ns.push_back(std::min<int>(trial_steps, p->n_steps));
             nmax = std::max(nmax, p->hp.n);
         }
+        auto trial = [&](double* out) -> int {
+            double ms = 0.0;
+            for (int rep = 0; rep < 2; ++rep) {
+                HIP_TRY(hipStreamSynchronize(g->lc.stream));
+                const auto t0 = std::chrono::steady_clock::now();
+                int rc = march_group(g, ns.data(), 0, nullptr, nullptr);
+                if (rc) return rc;
+                ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            }
+            *out = ms;
+            return LPIDE_OK;
+        };
+        double best = 1e300, ms = 0.0;
+        int rc = LPIDE_OK;
+        // round 1: radix schedule, one kernel class at a time from the default
+        Schedule bs = g->lc.E_cols ? Schedule{g->lc.E_cols, g->lc.E_rinv, g->lc.E_lrows, g->lc.E_sl}
+                                   : default_schedule(g->lc.L);
+        g->use_graph = true;
+        g->slots = 32;
+        if ((rc = set_schedule(g, bs)) || (rc = trial(&best))) return rc;
+        for (int cls = 0; cls < 4; ++cls)
+            for (int E : {4, 8, 16}) {
+                Schedule t = bs;
+                int* f = cls == 0 ? &t.cols : cls == 1 ? &t.rinv : cls == 2 ? &t.lrows : &t.sl;
+                if (*f == E || !e_supported(g->lc.L, E)) continue;
+                *f = E;
+                if ((rc = set_schedule(g, t)) || (rc = trial(&ms))) return rc;
+                if (ms < best) { best = ms; bs = t; }
+            }
+        if ((rc = set_schedule(g, bs))) return rc;
+        // round 2: line-solve chunking
         const int P0 = default_P_cols(nmax);
-        std::vector<int> Ps;
+        int bP = g->lc.P_cols;
+        best = 1e300;
         for (int P : {P0 / 2, P0, 2 * P0}) {
-            bool ok = true;
+            bool ok = 4 * P <= 1024;
             for (Plan* p : g->plans) ok = ok && P_cols_valid(p->hp.n, P);
-            if (ok && 4 * P <= 1024) Ps.push_back(P);
+            if (!ok) continue;
+            if ((rc = set_P_cols(g, P)) || (rc = trial(&ms))) return rc;
+            if (ms < best) { best = ms; bP = P; }
         }
-        double best = 1e300;
-        int bP = P0, bG = g->use_graph ? 1 : 0, bS = g->slots;
-        for (int P : Ps)
-            for (int G : {0, 1})
-                for (int S : {16, 32}) {
-                    int rc = set_P_cols(g, P);
-                    if (rc) return rc;
-                    g->use_graph = G != 0;
-                    g->slots = S;
-                    double ms = 0.0;
-                    for (int rep = 0; rep < 2; ++rep) {
-                        HIP_TRY(hipStreamSynchronize(g->lc.stream));
-                        const auto t0 = std::chrono::steady_clock::now();
-                        rc = march_group(g, ns.data(), 0, nullptr, nullptr);
-                        if (rc) return rc;
-                        ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                    }
-                    if (ms < best) { best = ms; bP = P; bG = G; bS = S; }
-                }
-        int rc = set_P_cols(g, bP);
-        if (rc) return rc;
+        if ((rc = set_P_cols(g, bP))) return rc;
+        // round 3: graph replay and slots
+        int bG = 1, bS = 32;
+        best = 1e300;
+        for (int G : {0, 1})
+            for (int S : {16, 32}) {
+                g->use_graph = G != 0;
+                g->slots = S;
+                if ((rc = trial(&ms))) return rc;
+                if (ms < best) { best = ms; bG = G; bS = S; }
+            }
         g->use_graph = bG != 0;
         g->slots = bS;
         g->tuned_ms = best;
@@ -2001,6 +2112,10 @@ int lpide_batch_info(void* batch, int32_t* n_groups, lpide_group_info* groups, i
         gi.P_cols = g->lc.P_cols;
         gi.slots = g->slots;
         gi.use_graph = g->use_graph ? 1 : 0;
+        gi.radix[0] = g->lc.E_cols;
+        gi.radix[1] = g->lc.E_rinv;
+        gi.radix[2] = g->lc.E_lrows;
+        gi.radix[3] = g->lc.E_sl;
         gi.trial_ms = g->tuned_ms;
     }
     return LPIDE_OK;

@@ -130,30 +130,30 @@ __device__ __forceinline__ const MarchArgs& plan_args(const MarchArgs* __restric
 // spectra), FP64 (C = double2) or FP32 (C = float2).
 // CONJ (adjoint march): multiply by the conjugate spectrum, which applies B^T
 // (the correlation with the reflected kernel).
-template <int L, typename C, bool CONJ = false>
-__global__ __launch_bounds__(L / 8) void ks_cols(const MarchArgs* __restrict__ A, int k) {
+template <int L, int E, typename C, bool CONJ = false>
+__global__ __launch_bounds__(L / E) void ks_cols(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, k) || (k == 0 && !needs_explicit(a))) return;
-    constexpr int T = L / 8;
+    constexpr int T = L / E;
     __shared__ C lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L>()];
-    load_twiddles<L>(a.tw, tw4);
+    __shared__ double2 tw4[tw_slots<L, E>()];
+    load_twiddles<L, E>(a.tw, tw4);
     const int n = a.n, col = blockIdx.x, tid = threadIdx.x;
     C* xc = xbuf<C>(a) + (size_t)col * n;
     const C* sc = specbuf<C>(a) + (size_t)col * L;
-    C reg[8], sp[8];
+    C reg[E], sp[E];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int idx = tid + e * T;
         reg[e] = idx < n ? xc[idx] : CplxOps<C>::make(0, 0);
         sp[e] = sc[idx];                  // spectrum fetched up front, used after the forward FFT
     }
-    fft_block<L, false>(reg, lds, tw4);
+    fft_block<L, E, false>(reg, lds, tw4);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) reg[e] = CONJ ? cmulc(reg[e], sp[e]) : cmul(reg[e], sp[e]);
-    fft_block<L, true>(reg, lds, tw4);
+    for (int e = 0; e < E; ++e) reg[e] = CONJ ? cmulc(reg[e], sp[e]) : cmul(reg[e], sp[e]);
+    fft_block<L, E, true>(reg, lds, tw4);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int idx = tid + e * T;
         if (idx < n) xc[idx] = reg[e];
     }
@@ -161,8 +161,8 @@ __global__ __launch_bounds__(L / 8) void ks_cols(const MarchArgs* __restrict__ A
 
 // Forward FFT of the row pair (ra, ra+1) of the FP64 grid U at the step start
 // (mixed form: the FP64 correlation of V^{n-1}).
-template <int L>
-__global__ __launch_bounds__(L / 8) void ks_rows_fwd(const MarchArgs* __restrict__ A);
+template <int L, int E>
+__global__ __launch_bounds__(L / E) void ks_rows_fwd(const MarchArgs* __restrict__ A);
 
 // Row inverse FFT of the pairs (2p, 2p+1) with a fused epilogue.
 // MODE 0 (once per step, FP64): E = V + dt(1-theta)((D - r_omega) V + B V) into R
@@ -175,25 +175,25 @@ __global__ __launch_bounds__(L / 8) void ks_rows_fwd(const MarchArgs* __restrict
 //         with Ybar in W and lam the iterate;
 // MODE 4 (once per step, theta < 1): W = mu + dt (1 - theta)((D^T - r_omega) mu + B^T mu),
 //         mu in pool[cur]: the cotangent of V^{n-1}.
-template <int L, int MODE>
-__global__ __launch_bounds__(L / 8) void ks_rows_inv(const MarchArgs* __restrict__ A, int k) {
+template <int L, int E, int MODE>
+__global__ __launch_bounds__(L / E) void ks_rows_inv(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, k) || ((MODE == 0 || MODE == 4) && !needs_explicit(a))) return;
     using C = typename std::conditional<MODE == 2, float2, double2>::type;
-    constexpr int T = L / 8;
+    constexpr int T = L / E;
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, gridDim.x);
     if (p >= np) return;
     __shared__ C lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L>()];
-    load_twiddles<L>(a.tw, tw4);
+    __shared__ double2 tw4[tw_slots<L, E>()];
+    load_twiddles<L, E>(a.tw, tw4);
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
     const int tid = threadIdx.x;
     const C* X = xbuf<C>(a);
-    C reg[8];
+    C reg[E];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int idx = tid + e * T;
         const bool lo = idx <= L / 2;
         const int kk = lo ? idx : L - idx;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(L / 8) void ks_rows_inv(const MarchArgs* __restrict
         const C hb = CplxOps<C>::make(tb.x, real_bin ? 0 : tb.y);
         reg[e] = lo ? CplxOps<C>::make(ha.x - hb.y, ha.y + hb.x) : CplxOps<C>::make(ha.x + hb.y, hb.x - ha.y);
     }
-    fft_block<L, true>(reg, lds, tw4);
+    fft_block<L, E, true>(reg, lds, tw4);
     const StepDesc& sd = cur_set(a);
     constexpr bool EXPL = MODE == 0 || MODE == 4;
     const double* U = EXPL ? a.pool[a.ctl->cur] : a.pool[a.ctl->y];
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(L / 8) void ks_rows_inv(const MarchArgs* __restrict
     const bool want_r = MODE != 0 || sd.theta < 1.0;
     const double* base = (MODE == 2 && k == 1) ? a.BV : a.BY;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int j = tid + e * T;
         if (j >= n) continue;
 #pragma unroll
@@ -265,17 +265,17 @@ __global__ __launch_bounds__(256) void ks_affine_noB(const MarchArgs* __restrict
 
 // Forward FFT of the row pair held in reg (canonical layout) into the
 // transposed half spectra X[k2 * n + row].
-template <int L, typename C>
-__device__ __forceinline__ void rows_fwd_store(C (&reg)[8], C* lds, const double2* tw4, C* __restrict__ X, int n,
+template <int L, int E, typename C>
+__device__ __forceinline__ void rows_fwd_store(C (&reg)[E], C* lds, const double2* tw4, C* __restrict__ X, int n,
                                                int ra, bool hasb) {
-    constexpr int T = L / 8;
+    constexpr int T = L / E;
     using Rl = typename CplxOps<C>::real;
     const int tid = threadIdx.x;
     __syncthreads();
-    fft_block<L, false>(reg, lds, tw4);
+    fft_block<L, E, false>(reg, lds, tw4);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 8; ++e) lds[tid + e * T] = reg[e];
+    for (int e = 0; e < E; ++e) lds[tid + e * T] = reg[e];
     __syncthreads();
     for (int kk = tid; kk <= L / 2; kk += T) {
         const C z = lds[kk], w = lds[(L - kk) & (L - 1)];
@@ -285,51 +285,51 @@ __device__ __forceinline__ void rows_fwd_store(C (&reg)[8], C* lds, const double
     }
 }
 
-template <int L>
-__global__ __launch_bounds__(L / 8) void ks_rows_fwd(const MarchArgs* __restrict__ A) {
+template <int L, int E>
+__global__ __launch_bounds__(L / E) void ks_rows_fwd(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0) || !a.mixed) return;
-    constexpr int T = L / 8;
+    constexpr int T = L / E;
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, gridDim.x);
     if (p >= np) return;
     __shared__ double2 lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L>()];
-    load_twiddles<L>(a.tw, tw4);
+    __shared__ double2 tw4[tw_slots<L, E>()];
+    load_twiddles<L, E>(a.tw, tw4);
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
     const double* U = a.pool[a.ctl->cur];
-    double2 reg[8];
+    double2 reg[E];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int j = threadIdx.x + e * T;
         reg[e] = j < n ? make_double2(U[(size_t)ra * n + j], hasb ? U[(size_t)rb * n + j] : 0.0)
                        : make_double2(0.0, 0.0);
     }
-    rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
+    rows_fwd_store<L, E>(reg, lds, tw4, a.X, n, ra, hasb);
 }
 
 // Semi-Lagrangian gather W = (T_1 (x) T_2) E (order P), starting value Y^0 into
 // the iterate buffer, and (FFT) the row transform of Y^0 (FP64) or, in the
 // mixed form, of Y^0 - V^{n-1} (FP32); one row pair per block.
-template <int L, int P, bool FFT, bool MIXED>
-__global__ __launch_bounds__(L / 8) void ks_sl(const MarchArgs* __restrict__ A) {
+template <int L, int E, int P, bool FFT, bool MIXED>
+__global__ __launch_bounds__(L / E) void ks_sl(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0)) return;
-    constexpr int T = L / 8;
+    constexpr int T = L / E;
     using C = typename std::conditional<MIXED, float2, double2>::type;
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, gridDim.x);
     if (p >= np) return;
     __shared__ C lds[FFT ? lds_slots(L) : 1];
-    __shared__ double2 tw4[FFT ? tw_slots<L>() : 1];
-    if constexpr (FFT) load_twiddles<L>(a.tw, tw4);
+    __shared__ double2 tw4[FFT ? tw_slots<L, E>() : 1];
+    if constexpr (FFT) load_twiddles<L, E>(a.tw, tw4);
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
     const int tid = threadIdx.x;
     const Ctl* c = a.ctl;
     const StepDesc& sd = cur_set(a);
-    const double* E = sd.theta < 1.0 ? a.R : a.pool[c->cur];
+    const double* Ex = sd.theta < 1.0 ? a.R : a.pool[c->cur];   // explicit part E_s
     double* Y = a.pool[c->y];
     const int nsrc = c->nsrc;
     const double* H[4];
@@ -340,9 +340,9 @@ __global__ __launch_bounds__(L / 8) void ks_sl(const MarchArgs* __restrict__ A) 
         cf[q] = c->coef[q];
     }
     const double* V = a.pool[c->cur];
-    C reg[8];
+    C reg[E];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int j = tid + e * T;
         double y0[2] = {0.0, 0.0};
         if (j < n) {
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(L / 8) void ks_sl(const MarchArgs* __restrict__ A) 
                 double acc = 0.0;
 #pragma unroll
                 for (int aa = 0; aa <= P; ++aa) {
-                    const double* er = E + (size_t)(a0 + aa) * n + b0;
+                    const double* er = Ex + (size_t)(a0 + aa) * n + b0;
                     double s = 0.0;
 #pragma unroll
                     for (int b = 0; b <= P; ++b) s += w2[b] * er[b];
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(L / 8) void ks_sl(const MarchArgs* __restrict__ A) 
         }
         reg[e] = CplxOps<C>::make(y0[0], y0[1]);
     }
-    if constexpr (FFT) rows_fwd_store<L>(reg, lds, tw4, xbuf<C>(a), n, ra, hasb);
+    if constexpr (FFT) rows_fwd_store<L, E>(reg, lds, tw4, xbuf<C>(a), n, ra, hasb);
 }
 
 // Axis-1 line solves R <- T_1^{-1} R: 4 adjacent columns x P chunks per block
@@ -403,19 +403,19 @@ __global__ __launch_bounds__(1024) void ks_line_cols(const MarchArgs* __restrict
 // Axis-2 line solves of a row pair, the update Y += delta, the stopping-rule
 // maximum err_k = max |delta| / max(1, |Y|), and (FFT) the row transform of the
 // updated Y (FP64) or, in the mixed form, of delta (FP32) for the next iteration.
-template <int L, bool FFT, bool MIXED>
-__global__ __launch_bounds__(L / 8) void ks_line_rows(const MarchArgs* __restrict__ A, int k) {
+template <int L, int E, bool FFT, bool MIXED>
+__global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, k)) return;
-    constexpr int T = L / 8, PR = T / 2;
+    constexpr int T = L / E, PR = T / 2;
     using C = typename std::conditional<MIXED, float2, double2>::type;
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, gridDim.x);
     if (p >= np) return;
     // union: row buffer 2 (n + PR + 1) doubles | scan totals | FFT exchange buffer
     __shared__ double2 lds[L + L / 16 + 2];
-    __shared__ double2 tw4[FFT ? tw_slots<L>() : 1];
-    if constexpr (FFT) load_twiddles<L>(a.tw, tw4);
+    __shared__ double2 tw4[FFT ? tw_slots<L, E>() : 1];
+    if constexpr (FFT) load_twiddles<L, E>(a.tw, tw4);
     double* rows = reinterpret_cast<double*>(lds);
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
@@ -442,9 +442,9 @@ __global__ __launch_bounds__(L / 8) void ks_line_rows(const MarchArgs* __restric
     __syncthreads();
     double* Y = a.pool[a.ctl->y];
     double emax = 0.0;
-    C reg[8];
+    C reg[E];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int j = tid + e * T;
         double ya = 0.0, yb = 0.0, da = 0.0, db = 0.0;
         if (j < n) {
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(L / 8) void ks_line_rows(const MarchArgs* __restric
         emax = (o > emax || o != o) ? o : emax;
     }
     if ((tid & 63) == 0) atomicMax(&a.ctl->err[k], (unsigned long long)__double_as_longlong(emax));
-    if constexpr (FFT) rows_fwd_store<L>(reg, reinterpret_cast<C*>(lds), tw4, xbuf<C>(a), n, ra, hasb);
+    if constexpr (FFT) rows_fwd_store<L, E>(reg, reinterpret_cast<C*>(lds), tw4, xbuf<C>(a), n, ra, hasb);
 }
 
 // End of a step: convergence verdict, history rotation, next starting value.
@@ -590,24 +590,24 @@ __global__ void ks_adj_begin(const MarchArgs* __restrict__ A, int s) {
 // Starting value lam^0 = Ybar + ratio corr and its row transform, where corr
 // = lam - Ybar of the previous reverse step (lam - Ybar = dt theta A^T lam, so
 // ratio rescales it by the ratio of the steps' dt theta); corr may be null.
-template <int L>
-__global__ __launch_bounds__(L / 8) void ks_adj_start(const MarchArgs* __restrict__ A,
+template <int L, int E>
+__global__ __launch_bounds__(L / E) void ks_adj_start(const MarchArgs* __restrict__ A,
                                                      const double* __restrict__ corr, double ratio) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0)) return;
-    constexpr int T = L / 8;
+    constexpr int T = L / E;
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, gridDim.x);
     if (p >= np) return;
     __shared__ double2 lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L>()];
-    load_twiddles<L>(a.tw, tw4);
+    __shared__ double2 tw4[tw_slots<L, E>()];
+    load_twiddles<L, E>(a.tw, tw4);
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
     double* lam = a.pool[a.ctl->y];
-    double2 reg[8];
+    double2 reg[E];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int j = threadIdx.x + e * T;
         double va = 0.0, vb = 0.0;
         if (j < n) {
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(L / 8) void ks_adj_start(const MarchArgs* __restric
         }
         reg[e] = make_double2(va, vb);
     }
-    rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
+    rows_fwd_store<L, E>(reg, lds, tw4, a.X, n, ra, hasb);
 }
 
 // corr = lam - Ybar after the adjoint fixed point converged (start of the next
@@ -655,27 +655,27 @@ __global__ void ks_adj_end(const MarchArgs* __restrict__ A, int kmax) {
 
 // mu = (T_1^T (x) T_2^T) lam (the transposed semi-Lagrangian gather) into
 // pool[0]; when theta < 1 also its row transform for B^T mu.
-template <int L>
-__global__ __launch_bounds__(L / 8) void ks_adj_sl(const MarchArgs* __restrict__ A) {
+template <int L, int E>
+__global__ __launch_bounds__(L / E) void ks_adj_sl(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0)) return;
-    constexpr int T = L / 8;
+    constexpr int T = L / E;
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, gridDim.x);
     if (p >= np) return;
     __shared__ double2 lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L>()];
+    __shared__ double2 tw4[tw_slots<L, E>()];
     const StepDesc& sd = cur_set(a);
     const bool fft = sd.theta < 1.0;
-    if (fft) load_twiddles<L>(a.tw, tw4);
+    if (fft) load_twiddles<L, E>(a.tw, tw4);
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
     const double* lam = a.pool[a.ctl->y];
     double* mu = a.pool[a.ctl->cur];
     const int W1 = sd.wt1, W2 = sd.wt2;
-    double2 reg[8];
+    double2 reg[E];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int j = threadIdx.x + e * T;
         double out[2] = {0.0, 0.0};
         if (j < n) {
@@ -697,7 +697,7 @@ __global__ __launch_bounds__(L / 8) void ks_adj_sl(const MarchArgs* __restrict__
         }
         reg[e] = make_double2(out[0], out[1]);
     }
-    if (fft) rows_fwd_store<L>(reg, lds, tw4, a.X, n, ra, hasb);
+    if (fft) rows_fwd_store<L, E>(reg, lds, tw4, a.X, n, ra, hasb);
 }
 
 // Per-step gradient terms of the reverse step (one block per row pair,
@@ -778,44 +778,44 @@ __global__ __launch_bounds__(256) void ks_adj_accum(const MarchArgs* __restrict_
 // After the march, the inverse 2D transform of S / L^2 is sum_m lam_m Y_{m+d}
 // summed over the steps with their weights: the gradient of the loss with
 // respect to the folded kernel K_d.
-template <int L>
-__global__ __launch_bounds__(L / 8) void ks_adj_spec(const double2* __restrict__ XA, const double2* __restrict__ XB,
+template <int L, int E = 8>
+__global__ __launch_bounds__(L / E) void ks_adj_spec(const double2* __restrict__ XA, const double2* __restrict__ XB,
                                                      const double2* __restrict__ XC, const double2* __restrict__ XD,
                                                      int n, double c1, double c2, double2* __restrict__ S,
                                                      const double2* __restrict__ tw) {
-    constexpr int T = L / 8;
+    constexpr int T = L / E;
     __shared__ double2 lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L>()];
-    load_twiddles<L>(tw, tw4);
+    __shared__ double2 tw4[tw_slots<L, E>()];
+    load_twiddles<L, E>(tw, tw4);
     const int col = blockIdx.x, tid = threadIdx.x;
-    double2 acc[8];
+    double2 acc[E];
     double2* sc = S + (size_t)col * L;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) acc[e] = sc[tid + e * T];
+    for (int e = 0; e < E; ++e) acc[e] = sc[tid + e * T];
     for (int pass = 0; pass < 2; ++pass) {
         const double cf = pass == 0 ? c1 : c2;
         if (cf == 0.0) continue;
         const double2* xa = (pass == 0 ? XA : XC) + (size_t)col * n;
         const double2* xb = (pass == 0 ? XB : XD) + (size_t)col * n;
-        double2 ra[8], rb[8];
+        double2 ra[E], rb[E];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < E; ++e) {
             const int idx = tid + e * T;
             ra[e] = idx < n ? xa[idx] : make_double2(0.0, 0.0);
             rb[e] = idx < n ? xb[idx] : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        fft_block<L, false>(ra, lds, tw4);
+        fft_block<L, E, false>(ra, lds, tw4);
         __syncthreads();
-        fft_block<L, false>(rb, lds, tw4);
+        fft_block<L, E, false>(rb, lds, tw4);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < E; ++e) {
             const double2 pr = cmulc(rb[e], ra[e]);    // conj(A) B
             acc[e] = make_double2(acc[e].x + cf * pr.x, acc[e].y + cf * pr.y);
         }
     }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) sc[tid + e * T] = acc[e];
+    for (int e = 0; e < E; ++e) sc[tid + e * T] = acc[e];
 }
 
 // Control block at the start of a march: the state of step-list entry step0

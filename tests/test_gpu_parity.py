@@ -203,3 +203,28 @@ def test_non_convergence_is_reported(lp):
     with pytest.raises(lp.LpideError) as ei:
         plan.solve()
     assert ei.value.code == -2
+
+
+@pytest.mark.parametrize("radix", [4, 16])
+def test_radix_schedules(lp, radix):
+    """The march with another FFT radix schedule (elements per thread) gives
+    the same fixed points: fv512 after 8 step-list entries (L = 1024), FP64
+    against the oracle and mixed against the default schedule."""
+    _note("radix %d fv512" % radix)
+    w = workloads.workload("fv512")
+    plan = lp.plan_from_workload(w, fft_radix=radix)
+    assert plan.info()["radix"] == [radix] * 4
+    Vg = plan.solve_steps(8).cpu().numpy()
+    Vo, _ = scheme.solve(_oracle_problem(w), tol=1e-14, inner="bicgstab", n_steps=8)
+    assert _rel(Vg, Vo) < 1e-10
+    vm = lp.plan_from_workload(w, precision="fp32conv", fft_radix=radix).solve_steps(8).cpu().numpy()
+    assert _rel(vm, Vo) < 1e-6
+
+
+def test_radix_4_small_transform(lp):
+    """E = 4 on the 64 x 64 workload (L = 128, 32 threads per transform)."""
+    _note("radix 4 nig64")
+    w = workloads.workload("nig64")
+    Vg = lp.plan_from_workload(w, fft_radix=4).solve().cpu().numpy()
+    Vo, _ = scheme.solve(_oracle_problem(w), tol=1e-14)
+    assert _rel(Vg, Vo) < 1e-10
