@@ -1166,12 +1166,20 @@ int march_recorded(Plan* p, int step0, int nsteps, const double* v_in, double* s
 
 template <int L>
 void launch_adj_iteration(const Launch& c, int k) {
-    const dim3 gr(c.xrows, 1), gc(L / 2 + 1, 1);
-    hipLaunchKernelGGL((ks_cols<L, 8, double2, true>), gc, dim3(L / 8), 0, c.stream, c.A, k);
-    hipLaunchKernelGGL((ks_rows_inv<L, 8, 3>), gr, dim3(L / 8), 0, c.stream, c.A, k);
+    with_E<L>(c.E_cols, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_cols<L, E, double2, true>), dim3(L / 2 + 1, 1), dim3(L / E), 0, c.stream, c.A, k);
+    });
+    with_E<L>(c.E_rinv, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_rows_inv<L, E, 3>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);
+    });
     hipLaunchKernelGGL(ks_line_cols, dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols, c.stream,
                        c.A, k);
-    hipLaunchKernelGGL((ks_line_rows<L, 8, true, false>), gr, dim3(L / 8), 0, c.stream, c.A, k);
+    with_E<L>(c.E_lrows, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_line_rows<L, E, true, false>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);
+    });
 }
 
 // One reverse step s: Ybar (in adj->ybar) -> cotangent of V^s (in adj->ybar),
@@ -1185,8 +1193,11 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     const dim3 gr(c.xrows, 1);
     hipLaunchKernelGGL(ks_adj_begin, dim3(1), dim3(64), 0, c.stream, c.A, s);
     const double cth = sd.dt * sd.theta;
-    hipLaunchKernelGGL((ks_adj_start<L, 8>), gr, dim3(L / 8), 0, c.stream, c.A, a->have_corr ? a->corr : nullptr,
-                       a->have_corr && a->corr_c > 0.0 ? cth / a->corr_c : 0.0);
+    with_E<L>(c.E_rinv, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_adj_start<L, E>), gr, dim3(L / E), 0, c.stream, c.A, a->have_corr ? a->corr : nullptr,
+                           a->have_corr && a->corr_c > 0.0 ? cth / a->corr_c : 0.0);
+    });
     int k = *kpred;
     for (int q = 1; q <= k; ++q) launch_adj_iteration<L>(c, q);
     hipLaunchKernelGGL(ks_adj_end, dim3(1), dim3(64), 0, c.stream, c.A, k);
@@ -1220,10 +1231,19 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     a->have_corr = true;
     a->corr_c = cth;
     // mu = (T^SL)^T lam, then the cotangent of V^s
-    hipLaunchKernelGGL((ks_adj_sl<L, 8>), gr, dim3(L / 8), 0, c.stream, c.A);
+    with_E<L>(c.E_sl, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_adj_sl<L, E>), gr, dim3(L / E), 0, c.stream, c.A);
+    });
     if (sd.theta < 1.0) {
-        hipLaunchKernelGGL((ks_cols<L, 8, double2, true>), dim3(L / 2 + 1, 1), dim3(L / 8), 0, c.stream, c.A, 0);
-        hipLaunchKernelGGL((ks_rows_inv<L, 8, 4>), gr, dim3(L / 8), 0, c.stream, c.A, 0);
+        with_E<L>(c.E_cols, [&](auto e) {
+            constexpr int E = decltype(e)::value;
+            hipLaunchKernelGGL((ks_cols<L, E, double2, true>), dim3(L / 2 + 1, 1), dim3(L / E), 0, c.stream, c.A, 0);
+        });
+        with_E<L>(c.E_rinv, [&](auto e) {
+            constexpr int E = decltype(e)::value;
+            hipLaunchKernelGGL((ks_rows_inv<L, E, 4>), gr, dim3(L / E), 0, c.stream, c.A, 0);
+        });
     }
     // gradient terms (they read lam and mu; the new cotangent is written last)
     if (p->hp.sl_order == 1)
@@ -1382,6 +1402,10 @@ int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lp
     c.P_cols = p->solo->lc.P_cols;
     c.sl_order = p->hp.sl_order;
     c.jumps = p->jumps;
+    c.E_cols = p->solo->lc.E_cols;
+    c.E_rinv = p->solo->lc.E_rinv;
+    c.E_lrows = p->solo->lc.E_lrows;
+    c.E_sl = p->solo->lc.E_sl;
     a->args.P_cols = c.P_cols;
     HIP_TRY(hipMemcpyAsync(a->A, &a->args, sizeof(MarchArgs), hipMemcpyHostToDevice, s));
     double t_rec = 0.0, t_rev = 0.0;
