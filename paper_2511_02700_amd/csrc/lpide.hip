@@ -640,15 +640,15 @@ void launch_iteration_L(const Launch& c, int k) {
     else launch_iteration<L, true, false>(c, k);
 }
 
-// Default radix schedule.  From measurements on MI355X: the column pass and
-// the line-row kernel gain from radix 16 at L >= 2048, the row c2r kernels
-// from radix 4 up to L = 1024, the SL kernel from radix 4 at every size.
+// Default radix schedule.  From measurements on MI355X (each kernel alone):
+// the column pass gains from radix 16 at L >= 1024; the row c2r, line-row and
+// SL kernels from radix 4 up to L = 1024 and radix 8 above.
 Schedule default_schedule(int L) {
     Schedule s;
-    s.cols = L >= 2048 ? 16 : 8;
+    s.cols = L >= 1024 ? 16 : 8;
     s.rinv = L <= 1024 ? 4 : 8;
-    s.lrows = L >= 2048 ? 16 : 8;
-    s.sl = 4;
+    s.lrows = L <= 1024 ? 4 : 8;
+    s.sl = L <= 1024 ? 4 : 8;
     return s;
 }
 
@@ -853,6 +853,13 @@ double bits_d(unsigned long long b) {
     return d;
 }
 
+// Stopping-rule value after iteration k from a host copy of a control block.
+double err_of(const Ctl& c, int k) {
+    unsigned long long m = c.err[0][k];
+    for (int x = 1; x < NX; ++x) m = std::max(m, c.err[x][k]);
+    return bits_d(m);
+}
+
 // Complete the current step of plan i, whose predicted iterations did not
 // reach tol: the other plans are held while iterations are added one at a
 // time (each followed by the step verdict).  Returns the iterations used.
@@ -864,7 +871,7 @@ int complete_step(Group* g, int i, int kused, int* k_out) {
     const int sf = g->ctl_h[i].fail_step;
     int rc = LPIDE_OK;
     for (;;) {
-        const double ek = bits_d(g->ctl_h[i].err[k]);
+        const double ek = err_of(g->ctl_h[i], k);
         if (!std::isfinite(ek)) {
             rc = fail(LPIDE_E_NAN, "non-finite fixed-point increment in step " + std::to_string(sf));
             break;
@@ -1205,7 +1212,7 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     HIP_TRY(hipMemcpyAsync(a->ctl_h, a->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.stream));
     HIP_TRY(hipStreamSynchronize(c.stream));
     while (a->ctl_h->fail) {
-        const double ek = bits_d(a->ctl_h->err[k]);
+        const double ek = err_of(*a->ctl_h, k);
         if (!std::isfinite(ek)) return fail(LPIDE_E_NAN, "non-finite adjoint increment in step " + std::to_string(s));
         if (k >= p->opts.max_iter) {
             char buf[160];
@@ -1223,7 +1230,7 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     }
     int used = k;
     for (int q = 1; q <= k; ++q)
-        if (bits_d(a->ctl_h->err[q]) < p->opts.tol) { used = q; break; }
+        if (err_of(*a->ctl_h, q) < p->opts.tol) { used = q; break; }
     a->counts_h[s] = used;
     *kpred = std::max(1, std::min(p->opts.max_iter, used));
     const int sb = int(std::min<size_t>(1024, (N + 255) / 256));

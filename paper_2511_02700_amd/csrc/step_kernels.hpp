@@ -38,7 +38,8 @@
 
 namespace lpide {
 
-constexpr int KSLOTS = 136;          // err[0] (sentinel) + up to 128 iterations per step
+constexpr int KSLOTS = 136;          // err[.][0] (sentinel) + up to 128 iterations per step
+constexpr int NX = 8;                 // stopping-rule partial maxima per iteration (one per XCD)
 constexpr int MAX_ITER_CAP = 128;
 constexpr int POOL = 6;               // grid buffers: history (4) + start state + iterate
 
@@ -54,7 +55,11 @@ struct Ctl {
     int hist[4];                      // pool indices, newest first
     int src[4];
     double coef[4];                   // Y^0 = sum_q coef[q] pool[src[q]]
-    unsigned long long err[KSLOTS];   // stopping-rule value after iteration k (bit pattern)
+    // stopping-rule value after iteration k: the maximum over x of err[x][k]
+    // (bit patterns of non-negative doubles).  The row blocks of the line-solve
+    // kernel reduce into the partial of their XCD, so the atomics of one launch
+    // go to eight cache lines instead of one (they are serialised per line).
+    unsigned long long err[NX][KSLOTS];
 };
 
 struct StepDesc {
@@ -108,11 +113,25 @@ template <> __device__ __forceinline__ const float2* specbuf<float2>(const March
 
 __device__ __forceinline__ double bits_to_d(unsigned long long b) { return __longlong_as_double((long long)b); }
 
+// Stopping-rule value after iteration k (maximum of the partials).
+__device__ __forceinline__ double err_max(const Ctl* c, int k) {
+    unsigned long long m = c->err[0][k];
+#pragma unroll
+    for (int x = 1; x < NX; ++x) m = c->err[x][k] > m ? c->err[x][k] : m;
+    return bits_to_d(m);
+}
+
+// Reset the stopping-rule partials (err[.][0] = +inf sentinel); by all threads of a block.
+__device__ __forceinline__ void err_reset(Ctl* c) {
+    for (int q = threadIdx.x; q < NX * KSLOTS; q += blockDim.x)
+        c->err[q / KSLOTS][q % KSLOTS] = (q % KSLOTS) == 0 ? 0x7FF0000000000000ull : 0ull;
+}
+
 // Uniform early-exit test of iteration k (k = 0: parts that run once per step).
 __device__ __forceinline__ bool halted(const MarchArgs& a, int k) {
     const Ctl* c = a.ctl;
     if (c->fail || c->hold || c->step >= a.nsteps) return true;
-    return k > 0 && bits_to_d(c->err[k - 1]) < a.tol;
+    return k > 0 && err_max(c, k - 1) < a.tol;
 }
 
 // The explicit part (and the FP64 correlation of V^{n-1}) is needed when
@@ -415,6 +434,12 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
     // union: row buffer 2 (n + PR + 1) doubles | scan totals | FFT exchange buffer
     __shared__ double2 lds[L + L / 16 + 2];
     __shared__ double2 tw4[FFT ? tw_slots<L, E>() : 1];
+    // Up to L = 1024 the line factors are staged in LDS and the iterate values
+    // are fetched into registers at the start, so that every global read of the
+    // kernel is issued before the first barrier (at these sizes a block's time
+    // is mostly the latency of dependent global reads).
+    constexpr bool PF = L <= 1024;
+    __shared__ double fac[PF ? 3 * L : 1];
     if constexpr (FFT) load_twiddles<L, E>(a.tw, tw4);
     double* rows = reinterpret_cast<double*>(lds);
     const int ra = 2 * p, rb = 2 * p + 1;
@@ -423,6 +448,21 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
     const int m = (n + PR - 1) / PR;
     const int stride = n + PR + 1;
     const StepDesc& sd = cur_set(a);
+    double* Y = a.pool[a.ctl->y];
+    double yoa[PF ? E : 1], yob[PF ? E : 1];
+    if constexpr (PF) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = tid + e * T;
+            yoa[e] = j < n ? Y[(size_t)ra * n + j] : 0.0;
+            yob[e] = (j < n && hasb) ? Y[(size_t)rb * n + j] : 0.0;
+        }
+        for (int i = tid; i < n; i += T) {
+            fac[i] = sd.fl2[i];
+            fac[L + i] = sd.bu2[i];
+            fac[2 * L + i] = sd.bc2[i];
+        }
+    }
     for (int i = tid; i < n; i += T) {
         rows[i + i / m] = a.R[(size_t)ra * n + i];
         if (hasb) rows[stride + i + i / m] = a.R[(size_t)rb * n + i];
@@ -435,12 +475,12 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
 #pragma unroll
     for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? rows[r * stride + s + q + ch] : 0.0;
     __syncthreads();
-    chunk_solve(x, s, cnt, r, ch, PR, 1, sd.fl2, sd.bu2, sd.bc2, lds);
+    if constexpr (PF) chunk_solve(x, s, cnt, r, ch, PR, 1, fac, fac + L, fac + 2 * L, lds);
+    else chunk_solve(x, s, cnt, r, ch, PR, 1, sd.fl2, sd.bu2, sd.bc2, lds);
 #pragma unroll
     for (int q = 0; q < LINE_MM; ++q)
         if (q < cnt) rows[r * stride + s + q + ch] = x[q];
     __syncthreads();
-    double* Y = a.pool[a.ctl->y];
     double emax = 0.0;
     C reg[E];
 #pragma unroll
@@ -450,14 +490,14 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
         if (j < n) {
             da = rows[j + j / m];
             const size_t oa = (size_t)ra * n + j;
-            ya = Y[oa] + da;
+            ya = (PF ? yoa[e] : Y[oa]) + da;
             Y[oa] = ya;
             double ev = fabs(da) / fmax(1.0, fabs(ya));
             emax = (ev > emax || ev != ev) ? ev : emax;
             if (hasb) {
                 db = rows[stride + j + j / m];
                 const size_t ob = (size_t)rb * n + j;
-                yb = Y[ob] + db;
+                yb = (PF ? yob[e] : Y[ob]) + db;
                 Y[ob] = yb;
                 ev = fabs(db) / fmax(1.0, fabs(yb));
                 emax = (ev > emax || ev != ev) ? ev : emax;
@@ -474,7 +514,9 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
         const double o = __shfl_xor(emax, off, WL);
         emax = (o > emax || o != o) ? o : emax;
     }
-    if ((tid & 63) == 0) atomicMax(&a.ctl->err[k], (unsigned long long)__double_as_longlong(emax));
+    if ((tid & 63) == 0)
+        atomicMax(&a.ctl->err[(blockIdx.x + blockIdx.y * gridDim.x) & (NX - 1)][k],
+                  (unsigned long long)__double_as_longlong(emax));
     if constexpr (FFT) rows_fwd_store<L, E>(reg, reinterpret_cast<C*>(lds), tw4, xbuf<C>(a), n, ra, hasb);
 }
 
@@ -485,20 +527,23 @@ __global__ void ks_step_end(const MarchArgs* __restrict__ A, int kmax) {
     Ctl* c = a.ctl;
     if (c->hold || c->step >= a.nsteps) return;
     __shared__ int ok;
+    __shared__ double ek[KSLOTS];
+    for (int q = threadIdx.x; q <= kmax; q += blockDim.x) ek[q] = err_max(c, q);
+    __syncthreads();
     if (threadIdx.x == 0) {
         ok = 0;
         if (!c->fail) {
             const int s = c->step;
             int kk = 0;
             for (int q = 1; q <= kmax; ++q)
-                if (bits_to_d(c->err[q]) < a.tol) { kk = q; break; }
+                if (ek[q] < a.tol) { kk = q; break; }
             if (kk == 0) {
                 c->fail = 1;
                 c->fail_step = s;
             } else {
                 ok = 1;
                 a.counts[s] = kk;
-                a.incs[s] = bits_to_d(c->err[kk]);
+                a.incs[s] = ek[kk];
                 const bool inner_sub = a.damping && s < a.n_sub - 1;
                 if (inner_sub) {
                     c->cur = c->y;                        // next damped sub-step starts here
@@ -533,10 +578,7 @@ __global__ void ks_step_end(const MarchArgs* __restrict__ A, int kmax) {
         }
     }
     __syncthreads();
-    if (ok) {
-        for (int q = threadIdx.x; q < KSLOTS; q += blockDim.x)
-            c->err[q] = q == 0 ? (unsigned long long)0x7FF0000000000000ull : 0ull;
-    }
+    if (ok) err_reset(c);
 }
 
 // Recording for the adjoint march.  After sl (once per step): E_s, held in R
@@ -575,8 +617,7 @@ __global__ void ks_store_V(const MarchArgs* __restrict__ A) {
 // Control block for reverse step s: iterate in pool[1], no failure, stopping values reset.
 __global__ void ks_adj_begin(const MarchArgs* __restrict__ A, int s) {
     Ctl* c = A[0].ctl;
-    for (int q = threadIdx.x; q < KSLOTS; q += blockDim.x)
-        c->err[q] = q == 0 ? (unsigned long long)0x7FF0000000000000ull : 0ull;
+    err_reset(c);
     if (threadIdx.x == 0) {
         c->step = s;
         c->fail = 0;
@@ -640,16 +681,20 @@ __global__ void ks_adj_corr(const MarchArgs* __restrict__ A, double* __restrict_
 __global__ void ks_adj_end(const MarchArgs* __restrict__ A, int kmax) {
     const MarchArgs& a = A[0];
     Ctl* c = a.ctl;
-    if (threadIdx.x != 0 || c->fail) return;
+    if (c->fail) return;
+    __shared__ double ek[KSLOTS];
+    for (int q = threadIdx.x; q <= kmax; q += blockDim.x) ek[q] = err_max(c, q);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     int kk = 0;
     for (int q = 1; q <= kmax; ++q)
-        if (bits_to_d(c->err[q]) < a.tol) { kk = q; break; }
+        if (ek[q] < a.tol) { kk = q; break; }
     if (kk == 0) {
         c->fail = 1;
         c->fail_step = c->step;
     } else {
         a.counts[c->step] = kk;
-        a.incs[c->step] = bits_to_d(c->err[kk]);
+        a.incs[c->step] = ek[kk];
     }
 }
 
@@ -823,8 +868,7 @@ __global__ __launch_bounds__(L / E) void ks_adj_spec(const double2* __restrict__
 __global__ void ks_init(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
     Ctl* c = a.ctl;
-    for (int q = threadIdx.x; q < KSLOTS; q += blockDim.x)
-        c->err[q] = q == 0 ? (unsigned long long)0x7FF0000000000000ull : 0ull;
+    err_reset(c);
     if (threadIdx.x == 0) {
         c->step = a.step0;
         c->fail = 0;
