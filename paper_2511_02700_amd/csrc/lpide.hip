@@ -1034,9 +1034,9 @@ struct Adjoint {
     double* ckpt = nullptr;         // n_ckpt states V^{qC}
     double* seg = nullptr;          // C + 1 states of the segment being reversed
     double* segE = nullptr;         // C explicit parts of that segment
-    double *lam = nullptr, *mu = nullptr, *ybar = nullptr, *dummy = nullptr, *corr = nullptr;
-    bool have_corr = false;          // corr holds lam - Ybar of the previous reverse step
-    double corr_c = 0.0;             // dt theta of that step
+    double *lam = nullptr, *mu = nullptr, *ybar = nullptr, *dummy = nullptr, *corr = nullptr, *corr2 = nullptr;
+    int have_corr = 0;               // corr (corr2) hold lam - Ybar of the previous (second previous) reverse step
+    double corr_c = 0.0, corr_c2 = 0.0;   // dt theta of those steps
     bool xb_is_v = false;            // XD holds the row transform of V^{s+1} from the previous reverse step
     double2 *XA = nullptr, *XB = nullptr, *XC = nullptr, *XD = nullptr;
     double2* S = nullptr;           // (L/2+1) x L spectral accumulator
@@ -1084,7 +1084,7 @@ int adj_prepare(Plan* p, int C) {
         (rc = dalloc_into(al, nullptr, &a->segE, N * C)) || (rc = dalloc_into(al, nullptr, &a->lam, N)) ||
         (rc = dalloc_into(al, nullptr, &a->mu, N)) || (rc = dalloc_into(al, nullptr, &a->ybar, N)) ||
         (rc = dalloc_into(al, nullptr, &a->dummy, N)) || (rc = dalloc_into(al, nullptr, &a->acc, (size_t)n * 8)) ||
-        (rc = dalloc_into(al, nullptr, &a->corr, N)) ||
+        (rc = dalloc_into(al, nullptr, &a->corr, N)) || (rc = dalloc_into(al, nullptr, &a->corr2, N)) ||
         (rc = dalloc_into(al, nullptr, &a->ctl, 1)) || (rc = dalloc_into(al, nullptr, &a->counts, p->n_steps)) ||
         (rc = dalloc_into(al, nullptr, &a->incs, p->n_steps)) || (rc = dalloc_into(al, nullptr, &a->A, 1)))
         return rc;
@@ -1200,10 +1200,22 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     const dim3 gr(c.xrows, 1);
     hipLaunchKernelGGL(ks_adj_begin, dim3(1), dim3(64), 0, c.stream, c.A, s);
     const double cth = sd.dt * sd.theta;
+    const double* cp1 = nullptr;
+    const double* cp2 = nullptr;
+    double w1 = 0.0, w2 = 0.0;
+    if (a->have_corr >= 1 && a->corr_c > 0.0) {
+        const double ratio = cth / a->corr_c;
+        cp1 = a->corr;
+        w1 = ratio;
+        if (a->have_corr >= 2 && a->corr_c2 == a->corr_c) {   // same step kind: extrapolate linearly
+            cp2 = a->corr2;
+            w1 = 2.0 * ratio;
+            w2 = -ratio;
+        }
+    }
     with_E<L>(c.E_rinv, [&](auto e) {
         constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_adj_start<L, E>), gr, dim3(L / E), 0, c.stream, c.A, a->have_corr ? a->corr : nullptr,
-                           a->have_corr && a->corr_c > 0.0 ? cth / a->corr_c : 0.0);
+        hipLaunchKernelGGL((ks_adj_start<L, E>), gr, dim3(L / E), 0, c.stream, c.A, cp1, w1, cp2, w2);
     });
     int k = *kpred;
     for (int q = 1; q <= k; ++q) launch_adj_iteration<L>(c, q);
@@ -1234,8 +1246,10 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     a->counts_h[s] = used;
     *kpred = std::max(1, std::min(p->opts.max_iter, used));
     const int sb = int(std::min<size_t>(1024, (N + 255) / 256));
+    std::swap(a->corr, a->corr2);
+    a->corr_c2 = a->corr_c;
     hipLaunchKernelGGL(ks_adj_corr, dim3(sb), dim3(256), 0, c.stream, c.A, a->corr);
-    a->have_corr = true;
+    a->have_corr = std::min(2, a->have_corr + 1);
     a->corr_c = cth;
     // mu = (T^SL)^T lam, then the cotangent of V^s
     with_E<L>(c.E_sl, [&](auto e) {
@@ -1419,7 +1433,7 @@ int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lp
     int kpred = std::min(8, p->opts.max_iter);
     int64_t iters = 0;
     int maxit = 0;
-    a->have_corr = false;
+    a->have_corr = 0;
     a->xb_is_v = false;
     for (int q = (Ns - 1) / C; q >= 0; --q) {
         const int s0 = q * C, s1 = std::min(Ns, s0 + C);

@@ -628,12 +628,14 @@ __global__ void ks_adj_begin(const MarchArgs* __restrict__ A, int s) {
     }
 }
 
-// Starting value lam^0 = Ybar + ratio corr and its row transform, where corr
-// = lam - Ybar of the previous reverse step (lam - Ybar = dt theta A^T lam, so
-// ratio rescales it by the ratio of the steps' dt theta); corr may be null.
+// Starting value lam^0 = Ybar + w1 c1 + w2 c2 and its row transform, where
+// c1, c2 = lam - Ybar of the two previous reverse steps (lam - Ybar = dt theta
+// A^T lam): the correction extrapolated linearly (w1 = 2, w2 = -1) or kept
+// (w1 = 1, w2 = 0), rescaled by the ratio of the steps' dt theta; c1, c2 may be null.
 template <int L, int E>
 __global__ __launch_bounds__(L / E) void ks_adj_start(const MarchArgs* __restrict__ A,
-                                                     const double* __restrict__ corr, double ratio) {
+                                                     const double* __restrict__ c1, double w1,
+                                                     const double* __restrict__ c2, double w2) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0)) return;
     constexpr int T = L / E;
@@ -653,10 +655,10 @@ __global__ __launch_bounds__(L / E) void ks_adj_start(const MarchArgs* __restric
         double va = 0.0, vb = 0.0;
         if (j < n) {
             const size_t oa = (size_t)ra * n + j, ob = (size_t)rb * n + j;
-            va = a.W[oa] + (corr ? ratio * corr[oa] : 0.0);
+            va = a.W[oa] + (c1 ? w1 * c1[oa] : 0.0) + (c2 ? w2 * c2[oa] : 0.0);
             lam[oa] = va;
             if (hasb) {
-                vb = a.W[ob] + (corr ? ratio * corr[ob] : 0.0);
+                vb = a.W[ob] + (c1 ? w1 * c1[ob] : 0.0) + (c2 ? w2 * c2[ob] : 0.0);
                 lam[ob] = vb;
             }
         }
