@@ -477,3 +477,47 @@ def test_table3_vg1_nig1():
     e128, e192 = run("VG1", 128), run("VG1", 192)
     assert e192 < 1e-2 and e192 < e128 / 2, (e128, e192)
     assert run("NIG1", 128) < 1.5e-2
+
+
+# --------------------------------------------------------------------------- #
+# Convergence under refinement and independence of the truncated domain
+# --------------------------------------------------------------------------- #
+def _center_solution(alpha, n, half, N_t):
+    w = workloads.workload("nig64", n=n, y_lo=-half, y_hi=half, N_t=N_t, alpha=alpha)
+    m = w["model"]
+    p = levy.nts_from_std(m["sigma1"], m["sigma2"], m["corr"], m["theta1"], m["theta2"], m["kappa"], m["alpha"])
+    h = (w["y_hi"] - w["y_lo"]) / (n - 1)
+    d = integral.discretize(p, h, w["r"])
+    prob = scheme.Problem(n, (w["y_lo"], w["y_lo"]), h, d, payoff=w["payoff"], K=w["K"], T=w["T"], N_t=w["N_t"],
+                          theta=w["theta"])
+    V, _ = scheme.solve(prob, tol=1e-13)
+    return V
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("alpha", [0.5, 0.3])
+def test_observed_convergence_order(alpha):
+    """The put-on-average price at S = (100, 100) on [-2.5, 2.5]^2 with n = 33, 65,
+    129 (h halved, N_t = (n-1)/2): the observed order log2(|u1 - u2| / |u2 - u3|)
+    is at least the lower bound 2 - 2 alpha of Prop. 3.1 for the integral
+    discretization (A_l = 2 alpha) and at most about 3; infinite variation
+    (alpha = 1/2, NIG) and finite variation (alpha = 0.3) both."""
+    u = []
+    for n in (33, 65, 129):
+        V = _center_solution(alpha, n, 2.5, (n - 1) // 2)
+        c = (n - 1) // 2
+        u.append(V[c, c])
+    order = math.log2(abs(u[0] - u[1]) / abs(u[1] - u[2]))
+    assert 2.0 - 2.0 * alpha < order < 3.2, (alpha, u, order)
+
+
+def test_domain_enlargement_invariance():
+    """Readings A7-A9 (zero values outside the grid, boundary rows of D, clamped
+    SL stencils) only act near the boundary: the same h on [-2.5, 2.5]^2 and on
+    [-3.5, 3.5]^2 gives the same values within 1e-4 on the nodes with |y_i| <= 0.5
+    around S = (K, K) (prices of order 5 to 40)."""
+    V1 = _center_solution(0.5, 41, 2.5, 16)
+    V2 = _center_solution(0.5, 57, 3.5, 16)
+    c1, c2, r = 20, 28, 4
+    diff = np.max(np.abs(V1[c1 - r:c1 + r + 1, c1 - r:c1 + r + 1] - V2[c2 - r:c2 + r + 1, c2 - r:c2 + r + 1]))
+    assert diff < 1e-4, diff
