@@ -182,6 +182,13 @@ int lpide_solve(void* plan, double* v_out);
  * state after them, for step-by-step comparisons.  v_out: device, n*n. */
 int lpide_solve_steps(void* plan, int32_t steps, double* v_out);
 
+/* Entries [s0, s1) of the step list starting from the state v_in (the state
+ * after the first s0 entries; device, n*n, not modified), result in v_out
+ * (device, n*n; may equal v_in).  The extrapolated start values (Sec. 3.3)
+ * restart from v_in alone, so the result equals an uninterrupted march to the
+ * fixed-point tolerance, not bit for bit.  0 <= s0 <= s1 <= n_steps. */
+int lpide_solve_range(void* plan, int32_t s0, int32_t s1, const double* v_in, double* v_out);
+
 /* Cell-averaged initial grid V^0 (Sec. 3.2.3).  v_out: device, n*n. */
 int lpide_initial(void* plan, double* v_out);
 

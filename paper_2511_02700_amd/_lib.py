@@ -89,6 +89,7 @@ SIGNATURES = {
     "lpide_plan_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
     "lpide_solve": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lpide_solve_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "lpide_solve_range": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "lpide_initial": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lpide_apply_B": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lpide_price": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),

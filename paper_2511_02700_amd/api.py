@@ -148,6 +148,15 @@ class Plan:
         check(lib().lpide_solve_steps(self._h, int(steps), C.c_void_p(out.data_ptr())))
         return out
 
+    def solve_range(self, s0, s1, v_in, out=None):
+        """Step-list entries [s0, s1) from the state v_in (see lpide_solve_range)."""
+        torch = _torch()
+        v_in = v_in.to(self.device, torch.float64).contiguous()
+        out = self._grid_tensor(out)
+        check(lib().lpide_solve_range(self._h, int(s0), int(s1), C.c_void_p(v_in.data_ptr()),
+                                      C.c_void_p(out.data_ptr())))
+        return out
+
     def initial(self, out=None):
         out = self._grid_tensor(out)
         check(lib().lpide_initial(self._h, C.c_void_p(out.data_ptr())))

@@ -559,7 +559,7 @@ void launch_iteration(const Launch& c, int k) {
     }
     {
         KTime t(c.timer, LPIDE_K_LINE_COLS);
-        hipLaunchKernelGGL(ks_line_cols, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
+        hipLaunchKernelGGL(ks_line_cols<4>, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
                            c.stream, c.A, k);
     }
     KTime t(c.timer, LPIDE_K_LINE_ROWS);
@@ -728,10 +728,11 @@ void destroy_group(Group* g) {
 }
 
 // Launch shape of the axis-1 line solves: 4 columns per block, chunks of about
-// 8 rows, P_cols a power of two in [16, 256].
+// 8 rows, P_cols a power of two in [16, 128] (above 128 chunks per column the
+// scan across waves costs more than longer chunks; measured at n = 2048).
 int default_P_cols(int n) {
     int P = 16;
-    while (P < 256 && (n + P - 1) / P > 8) P *= 2;
+    while (P < 128 && (n + P - 1) / P > 8) P *= 2;
     return P;
 }
 
@@ -1181,7 +1182,7 @@ void launch_adj_iteration(const Launch& c, int k) {
         constexpr int E = decltype(e)::value;
         hipLaunchKernelGGL((ks_rows_inv<L, E, 3>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);
     });
-    hipLaunchKernelGGL(ks_line_cols, dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols, c.stream,
+    hipLaunchKernelGGL(ks_line_cols<4>, dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols, c.stream,
                        c.A, k);
     with_E<L>(c.E_lrows, [&](auto e) {
         constexpr int E = decltype(e)::value;
@@ -1922,6 +1923,18 @@ int lpide_price_adjoint(void* plan, int32_t npts, const double* spots, const dou
                        p->hp.y_lo[1], p->hp.h, p->pay.K, npts, spots, price_bar, v_bar);
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
+}
+
+int lpide_solve_range(void* plan, int32_t s0, int32_t s1, const double* v_in, double* v_out) {
+    if (!plan || !v_in || !v_out) return fail(LPIDE_E_PARAM, "NULL argument");
+    Plan* p = static_cast<Plan*>(plan);
+    if (s0 < 0 || s1 < s0 || s1 > p->n_steps) return fail(LPIDE_E_PARAM, "step range out of bounds");
+    Group* g = p->solo;
+    g->lc.timer = p->time_mask ? p : nullptr;
+    const double* ins[1] = {v_in};
+    double* outs[1] = {v_out};
+    int n1 = s1;
+    return march_group(g, &n1, s0, ins, outs);
 }
 
 int lpide_solve_steps(void* plan, int32_t steps, double* v_out) {

@@ -395,17 +395,18 @@ __global__ __launch_bounds__(L / E) void ks_sl(const MarchArgs* __restrict__ A) 
     if constexpr (FFT) rows_fwd_store<L, E>(reg, lds, tw4, xbuf<C>(a), n, ra, hasb);
 }
 
-// Axis-1 line solves R <- T_1^{-1} R: 4 adjacent columns x P chunks per block
-// (thread = column + 4 * chunk).
+// Axis-1 line solves R <- T_1^{-1} R: CPB adjacent columns x P chunks per block
+// (thread = column + CPB * chunk).
+template <int CPB>
 __global__ __launch_bounds__(1024) void ks_line_cols(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, k)) return;
     extern __shared__ double2 sbuf[];
     const int n = a.n, P = a.P_cols;
-    const int c = threadIdx.x & 3, t = threadIdx.x >> 2;
+    const int c = threadIdx.x % CPB, t = threadIdx.x / CPB;
     const int g = xcd_remap(blockIdx.x, gridDim.x);
-    if (4 * g >= n) return;
-    const int col = g * 4 + c;
+    if (CPB * g >= n) return;
+    const int col = g * CPB + c;
     const int m = (n + P - 1) / P;
     const int s = t * m;
     const int cnt = col < n ? max(0, min(m, n - s)) : 0;
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(1024) void ks_line_cols(const MarchArgs* __restrict
     double x[LINE_MM];
 #pragma unroll
     for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? a.R[(size_t)(s + q) * n + col] : 0.0;
-    chunk_solve(x, s, cnt, c, t, P, 4, sd.fl1, sd.bu1, sd.bc1, sbuf);
+    chunk_solve(x, s, cnt, c, t, P, CPB, sd.fl1, sd.bu1, sd.bc1, sbuf);
 #pragma unroll
     for (int q = 0; q < LINE_MM; ++q)
         if (q < cnt) a.R[(size_t)(s + q) * n + col] = x[q];

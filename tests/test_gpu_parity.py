@@ -228,3 +228,19 @@ def test_radix_4_small_transform(lp):
     Vg = lp.plan_from_workload(w, fft_radix=4).solve().cpu().numpy()
     Vo, _ = scheme.solve(_oracle_problem(w), tol=1e-14)
     assert _rel(Vg, Vo) < 1e-10
+
+
+def test_solve_range_restart(lp):
+    """Marching [0, 6) then [6, n_steps) from the intermediate state equals the
+    uninterrupted march to the fixed-point tolerance (the extrapolation
+    history restarts at the intermediate state)."""
+    _note("solve_range restart")
+    w = workloads.workload("nig64", n=40, N_t=12, y_lo=-2.5, y_hi=2.5)
+    plan = lp.plan_from_workload(w)
+    full = plan.solve().cpu().numpy()
+    mid = plan.solve_steps(6)
+    ns = plan.info()["n_steps"]
+    end = plan.solve_range(6, ns, mid).cpu().numpy()
+    assert _rel(end, full) < 1e-10
+    same = plan.solve_range(3, 3, mid).cpu().numpy()
+    assert np.array_equal(same, mid.cpu().numpy())
