@@ -2,14 +2,17 @@
 
     python -m paper_2511_02700_amd.build
 
-Compiles csrc/lpide.hip (device kernels and the C ABI of include/lpide.h) and
-csrc/host_plan.cpp (host-side discretization) with hipcc into one shared
-library next to this file.
+Compiles, in parallel, csrc/lpide.hip (plans, groups, batches, the adjoint
+driver and the C ABI of include/lpide.h), csrc/march_L.hip once per transform
+size L (the launch sequences of the march kernels for that size) and
+csrc/host_plan.cpp (host-side discretization) with hipcc, and links them into
+one shared library next to this file.
 """
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -17,29 +20,35 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblpide.so")
 
-SOURCES = ["lpide.hip", "host_plan.cpp"]
-HEADERS = ["fft.hpp", "kernels.hpp", "host_plan.hpp"]
+SIZES = [64, 128, 256, 512, 1024, 2048, 4096]
+# (source, object, extra flags)
+UNITS = ([("lpide.hip", "lpide.o", []), ("host_plan.cpp", "host_plan.o", [])] +
+         [("march_L.hip", "march_L%d.o" % L, ["-DLPIDE_L=%d" % L]) for L in SIZES])
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LPIDE_ARCH", "gfx950")
 
 
-def build(verbose=False):
-    """Compile every source (always) and link liblpide.so; returns its path."""
-    objs = []
-    common = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC]
-    for src in SOURCES:
-        obj = os.path.join(CSRC, src + ".o")
-        cmd = [HIPCC] + common
-        if src.endswith(".hip"):
-            # packed FP32 instructions are kept out of all device code
-            cmd += ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                    "-x", "hip"]
-        cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+def _compile(src, obj, extra, verbose):
+    cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC] + extra
+    if src.endswith(".hip"):
+        # packed FP32 instructions are kept out of all device code
+        cmd += ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-x", "hip"]
+    cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
+def build(verbose=False, jobs=None):
+    """Compile every translation unit (always) and link liblpide.so; returns its path."""
+    jobs = jobs or max(1, min(len(UNITS), os.cpu_count() or 1, 16))
+    objs = [os.path.join(CSRC, o) for _, o, _ in UNITS]
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = [ex.submit(_compile, src, obj, extra, verbose) for (src, _, extra), obj in zip(UNITS, objs)]
+        for f in futs:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     if verbose:

@@ -15,8 +15,6 @@
 // one-dimensional factors of D - r_omega without its mixed term.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -26,164 +24,58 @@
 #include <thread>
 #include <vector>
 
-#include "host_plan.hpp"
-#include "kernels.hpp"
-#include "lpide.h"
-#include "step_kernels.hpp"
+#include "conv_kernels.hpp"
+#include "plan.hpp"
 
-using namespace lpide;
+namespace lpide {
+namespace detail {
 
-// ---------------------------------------------------------------------------
-// error reporting
-// ---------------------------------------------------------------------------
 static thread_local std::string g_err;
 
-static int fail(int code, const std::string& msg) {
+int fail(int code, const std::string& msg) {
     g_err = msg;
     return code;
 }
 
-#define HIP_TRY(call)                                                                     \
-    do {                                                                                  \
-        hipError_t e_ = (call);                                                           \
-        if (e_ != hipSuccess)                                                             \
-            return fail(e_ == hipErrorOutOfMemory ? LPIDE_E_OOM : LPIDE_E_HIP,            \
-                        std::string(#call) + ": " + hipGetErrorString(e_));               \
-    } while (0)
-
-// ---------------------------------------------------------------------------
-// FFT correlation kernels
-// ---------------------------------------------------------------------------
-// Forward real FFT of pairs of rows (2p, 2p+1) of Y (n_rows x n_cols used,
-// zero padded to L) into the transposed half spectra X[k2 * ldx + row].
-template <int L>
-__global__ __launch_bounds__(L / 8) void k_rows_fwd(const double* __restrict__ Y, int ldy, int n_rows,
-                                                   int n_cols, double2* __restrict__ X, int ldx,
-                                                   const double2* __restrict__ tw) {
-    constexpr int T = L / 8;
-    __shared__ double2 lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L, 8>()];
-    load_twiddles<L, 8>(tw, tw4);
-    const int np = (n_rows + 1) >> 1;
-    const int p = xcd_remap(blockIdx.x, np);
-    const int ra = 2 * p, rb = 2 * p + 1;
-    const bool hasb = rb < n_rows;
-    const double* ya = Y + (size_t)ra * ldy;
-    const double* yb = Y + (size_t)(hasb ? rb : ra) * ldy;
-    const int tid = threadIdx.x;
-    double2 reg[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int idx = tid + e * T;
-        double a = 0.0, b = 0.0;
-        if (idx < n_cols) {
-            a = ya[idx];
-            b = hasb ? yb[idx] : 0.0;
-        }
-        reg[e] = make_double2(a, b);
-    }
-    fft_block<L, 8, false>(reg, lds, tw4);
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < 8; ++e) lds[tid + e * T] = reg[e];
-    __syncthreads();
-    // Z = FFT(a + i b): A_k = (Z_k + conj Z_{L-k}) / 2, B_k = (Z_k - conj Z_{L-k}) / (2i)
-    for (int k = tid; k <= L / 2; k += T) {
-        const double2 z = lds[k], w = lds[(L - k) & (L - 1)];
-        const double2 A = make_double2(0.5 * (z.x + w.x), 0.5 * (z.y - w.y));
-        const double2 B = make_double2(0.5 * (z.y + w.y), -0.5 * (z.x - w.x));
-        double2* xk = X + (size_t)k * ldx;
-        xk[ra] = A;
-        if (hasb) xk[rb] = B;
-    }
+double bits_d(unsigned long long b) {
+    double d;
+    std::memcpy(&d, &b, sizeof d);
+    return d;
 }
 
-// Column pass.  MODE 0: X[col] <- first n_out of IFFT(FFT(X[col], zero padded
-// from n_in) * spec[col]).  MODE 1 (plan time): spec_out[col] = conj(FFT(X[col])) * scale.
-// MODE 2: X[col] <- first n_out of IFFT(X[col], zero padded from n_in).
-template <int L, int MODE>
-__global__ __launch_bounds__(L / 8) void k_cols(double2* __restrict__ X, int ldx, int n_in, int n_out,
-                                               const double2* __restrict__ spec,
-                                               double2* __restrict__ spec_out, double scale,
-                                               const double2* __restrict__ tw) {
-    constexpr int T = L / 8;
-    __shared__ double2 lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L, 8>()];
-    load_twiddles<L, 8>(tw, tw4);
-    const int col = blockIdx.x;
-    const int tid = threadIdx.x;
-    double2* xc = X + (size_t)col * ldx;
-    double2 reg[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int idx = tid + e * T;
-        reg[e] = idx < n_in ? xc[idx] : make_double2(0.0, 0.0);
-    }
-    if constexpr (MODE != 2) fft_block<L, 8, false>(reg, lds, tw4);
-    if constexpr (MODE == 2) {
-        fft_block<L, 8, true>(reg, lds, tw4);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = tid + e * T;
-            if (idx < n_out) xc[idx] = reg[e];
-        }
-        return;
-    } else if constexpr (MODE == 1) {
-        double2* so = spec_out + (size_t)col * L;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) so[tid + e * T] = make_double2(reg[e].x * scale, -reg[e].y * scale);
-        return;
-    } else {
-        const double2* sc = spec + (size_t)col * L;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) reg[e] = cmul(reg[e], sc[tid + e * T]);
-        fft_block<L, 8, true>(reg, lds, tw4);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = tid + e * T;
-            if (idx < n_out) xc[idx] = reg[e];
-        }
-    }
+// Stopping-rule value after iteration k from a host copy of a control block.
+double err_of(const Ctl& c, int k) {
+    unsigned long long m = c.err[0][k];
+    for (int x = 1; x < NX; ++x) m = std::max(m, c.err[x][k]);
+    return bits_d(m);
 }
 
-// Inverse real FFT of row pairs from the transposed half spectra; keeps the
-// first n columns: row a <- real part, row b <- imaginary part.
-template <int L>
-__global__ __launch_bounds__(L / 8) void k_rows_inv(const double2* __restrict__ X, int ldx, int n,
-                                                   double* __restrict__ out, const double2* __restrict__ tw) {
-    constexpr int T = L / 8;
-    __shared__ double2 lds[lds_slots(L)];
-    __shared__ double2 tw4[tw_slots<L, 8>()];
-    load_twiddles<L, 8>(tw, tw4);
-    const int np = (n + 1) >> 1;
-    const int p = xcd_remap(blockIdx.x, np);
-    const int ra = 2 * p, rb = 2 * p + 1;
-    const bool hasb = rb < n;
-    const int tid = threadIdx.x;
-    double2 reg[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int idx = tid + e * T;
-        const bool lo = idx <= L / 2;
-        const int k = lo ? idx : L - idx;
-        const double2* xk = X + (size_t)k * ldx;
-        const bool real_bin = k == 0 || k == L / 2;    // imaginary parts dropped at DC and Nyquist
-        const double2 ta = xk[ra];
-        const double2 tb = hasb ? xk[rb] : make_double2(0.0, 0.0);
-        const double2 ha = make_double2(ta.x, real_bin ? 0.0 : ta.y);
-        const double2 hb = make_double2(tb.x, real_bin ? 0.0 : tb.y);
-        // Z_k = A_k + i B_k, with A_{L-k} = conj A_k, B_{L-k} = conj B_k
-        reg[e] = lo ? make_double2(ha.x - hb.y, ha.y + hb.x) : make_double2(ha.x + hb.y, hb.x - ha.y);
+hipEvent_t next_event(Plan* p) {
+    if (p->ev_used == p->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p->ev_pool.push_back(e);
     }
-    fft_block<L, 8, true>(reg, lds, tw4);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int j = tid + e * T;
-        if (j >= n) continue;
-        out[(size_t)ra * n + j] = reg[e].x;
-        if (hasb) out[(size_t)rb * n + j] = reg[e].y;
-    }
+    return p->ev_pool[p->ev_used++];
 }
+
+KTime::KTime(Plan* pl, int c) : p(pl), on(pl && ((pl->time_mask >> c) & 1u)) {
+    if (!on) return;
+    idx = p->ev_used;
+    hipEvent_t a = next_event(p), b = next_event(p);
+    if (!a || !b) { on = false; return; }
+    (void)hipEventRecord(a, p->stream);
+    p->ev_recs.push_back({c, idx, p->tag_step, p->tag_k});
+}
+KTime::~KTime() {
+    if (on) (void)hipEventRecord(p->ev_pool[idx + 1], p->stream);
+}
+
+}  // namespace detail
+}  // namespace lpide
+
+using namespace lpide;
+using namespace lpide::detail;
 
 // Prices and deltas at spot pairs: tensor cubic Lagrange in y with the clamped
 // stencil start clamp(floor(xi) - 1, 0, n - 4).
@@ -254,11 +146,6 @@ __global__ void k_price_adjoint(int n, double y0, double y1, double h, double K,
     vbar[o] = acc;
 }
 
-__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, size_t cnt) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) b[i] = a[i];
-}
-
 // Round the FP64 spectrum to FP32 (mixed form).
 __global__ void k_to_f32(const double2* __restrict__ a, float2* __restrict__ b, size_t cnt) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -266,144 +153,10 @@ __global__ void k_to_f32(const double2* __restrict__ a, float2* __restrict__ b, 
 }
 
 
-// ---------------------------------------------------------------------------
-// plan
-// ---------------------------------------------------------------------------
+
+namespace lpide {
+namespace detail {
 namespace {
-
-struct Plan;
-
-// Radix schedule (FFT elements per thread) of each kernel class of the march:
-// column pass, row c2r kernels (+ explicit part, row FFT of V), line rows, SL.
-struct Schedule { int cols, rinv, lrows, sl; };
-
-// Launch shape of a group of plans that share the transform size: the march
-// kernels run one grid for all of them (blockIdx.y = plan).
-struct Launch {
-    hipStream_t stream = nullptr;
-    const MarchArgs* A = nullptr;   // device array, np entries
-    int np = 0;
-    int L = 0;                      // Lr of the plans (threads x 8 of the row kernels)
-    int xrows = 0;                  // max row pairs
-    int xcols = 0;                  // max 4-column groups of the axis-1 line solves
-    int xaff = 0;                   // max rows (affine kernels without jumps)
-    int P_cols = 16;
-    int sl_order = 3;
-    // FFT elements per thread (radix schedule: 4, 8 or 16) of each kernel class:
-    // column pass, row c2r (+ explicit part, row FFT of V), line rows, SL
-    int E_cols = 8, E_rinv = 8, E_lrows = 8, E_sl = 8;
-    bool jumps = false, mixed = false;
-    Plan* timer = nullptr;          // records kernel timing (single-plan marches only)
-    bool record = false;            // launch the state-recording kernels (adjoint checkpoints)
-    int store_blocks = 1;           // grid of the recording copies
-};
-
-// Control state of a march over a group: one control block and per-step
-// statistics per plan, with pinned host mirrors.
-struct Group {
-    std::vector<Plan*> plans;
-    Launch lc;
-    std::vector<MarchArgs> args_h;
-    MarchArgs* A = nullptr;
-    Ctl* ctl = nullptr;
-    Ctl* ctl_h = nullptr;
-    int* counts = nullptr;          // np x maxsteps
-    double* incs = nullptr;
-    std::vector<int> counts_h;
-    std::vector<double> incs_h;
-    int maxsteps = 0;
-    bool use_graph = false;
-    int slots = 32;                 // step slots enqueued between host checks
-    struct G { int kmax, nslots; hipGraphExec_t exec; };
-    std::vector<G> graphs;
-    std::vector<void*> allocs;
-    double tuned_ms = 0.0;
-};
-
-struct Adjoint;
-
-struct Plan {
-    HostPlan hp;
-    lpide_grid grid{};
-    lpide_opts opts{};
-    lpide_payoff pay{};
-    double theta = 0.5;
-    int N_t = 1;
-    hipStream_t stream = nullptr;
-    int L = 0;        // FFT side (0 without jumps)
-    int Lr = 0;       // threads x 8 of the row-pair kernels (L, or a power of two >= n without jumps)
-    bool jumps = false;
-    bool mixed = false;            // FP32 iteration correlations (needs jumps)
-    std::vector<void*> allocs;
-    int64_t bytes = 0;
-    double2* tw = nullptr;
-    double2* spec = nullptr;
-    double2* X = nullptr;
-    float2* X32 = nullptr;
-    float2* spec32 = nullptr;
-    double* BV = nullptr;
-    double* BY = nullptr;
-    double* V0 = nullptr;
-    double* pool[POOL] = {};
-    double* Wb = nullptr;
-    double* Rb = nullptr;
-    StepDesc* sets_d = nullptr;
-    int* step_set_d = nullptr;
-    std::vector<StepDesc> sets;
-    std::vector<int> step_set;
-    int n_steps = 0;
-    int P_cols = 16;
-    Schedule sched{8, 8, 8, 8};    // radix schedule of the march kernels
-    Group* solo = nullptr;         // this plan alone, on its own stream
-    // adjoint march (allocated on the first lpide_adjoint call)
-    struct Adjoint* adj = nullptr;
-    int ckpt_every = 0;            // lpide_solve records checkpoints every this many steps (0: none)
-    bool ckpt_valid = false;       // checkpoints of the last full solve are in adj->ckpt
-    std::vector<int> counts_h;     // per-step iteration counts of the last march
-    // kernel timing (HIP events on the plan's stream around each timed launch)
-    uint32_t time_mask = 0;
-    std::vector<hipEvent_t> ev_pool;
-    struct EvRec { int cls; size_t idx; int step, k; };
-    std::vector<EvRec> ev_recs;   // timed launches: class, start event, step and iteration (k = 0: once per step)
-    int tag_step = -1, tag_k = 0; // step/iteration of the launches being enqueued
-    size_t ev_used = 0;
-    int64_t k_launch[LPIDE_KCLASSES] = {};
-    double k_ms[LPIDE_KCLASSES] = {};
-    // statistics of the last solve
-    int64_t total_iters = 0;
-    int max_step_iters = 0, last_step_iters = 0;
-    double last_inc = 0;
-};
-
-// Event pair around one launch of kernel class cls (no-op unless timed).
-struct KTime {
-    Plan* p;
-    bool on;
-    size_t idx = 0;
-    KTime(Plan* pl, int c);
-    ~KTime();
-};
-
-hipEvent_t next_event(Plan* p) {
-    if (p->ev_used == p->ev_pool.size()) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        p->ev_pool.push_back(e);
-    }
-    return p->ev_pool[p->ev_used++];
-}
-
-KTime::KTime(Plan* pl, int c) : p(pl), on(pl && ((pl->time_mask >> c) & 1u)) {
-    if (!on) return;
-    idx = p->ev_used;
-    hipEvent_t a = next_event(p), b = next_event(p);
-    if (!a || !b) { on = false; return; }
-    (void)hipEventRecord(a, p->stream);
-    p->ev_recs.push_back({c, idx, p->tag_step, p->tag_k});
-}
-KTime::~KTime() {
-    if (on) (void)hipEventRecord(p->ev_pool[idx + 1], p->stream);
-}
 
 // Fold recorded event pairs into the per-class totals (synchronises the stream).
 // Launches of iterations after a step had converged, and per-step kernels that
@@ -496,150 +249,6 @@ MarchArgs march_args(const Plan* p) {
     return a;
 }
 
-// ---- standalone correlation (apply_B) and plan-time spectrum ----
-template <int L>
-void launch_conv(Plan* p, const double* Y, double* out) {
-    const int n = p->hp.n, np = (n + 1) / 2;
-    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, p->stream, Y, n, n, n, p->X, n, p->tw);
-    hipLaunchKernelGGL((k_cols<L, 0>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, p->X, n, n, n, p->spec,
-                       (double2*)nullptr, 0.0, p->tw);
-    hipLaunchKernelGGL((k_rows_inv<L>), dim3(np), dim3(L / 8), 0, p->stream, p->X, n, n, out, p->tw);
-}
-
-template <int L>
-void launch_spectrum(Plan* p, const double* G, double2* Xfull) {
-    const double scale = 1.0 / (double(L) * double(L));
-    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(L / 2), dim3(L / 8), 0, p->stream, G, L, L, L, Xfull, L, p->tw);
-    hipLaunchKernelGGL((k_cols<L, 1>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, Xfull, L, L, L,
-                       (const double2*)nullptr, p->spec, scale, p->tw);
-}
-
-template <int L>
-void launch_rows_fwd(Plan* p, const double* Y, hipStream_t s) {
-    const int n = p->hp.n;
-    hipLaunchKernelGGL((k_rows_fwd<L>), dim3((n + 1) / 2), dim3(L / 8), 0, s, Y, n, n, n, p->X, n, p->tw);
-}
-
-// ---- one step slot of the device-controlled march, for a group of plans ----
-// Radix schedules instantiated per transform size: E = 4 and 8 always, E = 16
-// from L = 256 on (at least 16 threads per transform).
-constexpr bool e_supported(int L, int E) { return E == 4 || E == 8 || (E == 16 && L >= 256); }
-
-// Call f(std::integral_constant<int, E>) for the runtime E of a kernel class.
-template <int L, typename F>
-void with_E(int E, F&& f) {
-    if (E == 4) f(std::integral_constant<int, 4>{});
-    else if constexpr (L >= 256) {
-        if (E == 16) f(std::integral_constant<int, 16>{});
-        else f(std::integral_constant<int, 8>{});
-    } else f(std::integral_constant<int, 8>{});
-}
-
-template <int L, bool FFT, bool MIXED>
-void launch_iteration(const Launch& c, int k) {
-    using C = typename std::conditional<MIXED, float2, double2>::type;
-    if (c.timer) c.timer->tag_k = k;
-    if (FFT) {
-        {
-            KTime t(c.timer, LPIDE_K_COLS);
-            with_E<L>(c.E_cols, [&](auto e) {
-                constexpr int E = decltype(e)::value;
-                hipLaunchKernelGGL((ks_cols<L, E, C>), dim3(L / 2 + 1, c.np), dim3(L / E), 0, c.stream, c.A, k);
-            });
-        }
-        KTime t(c.timer, LPIDE_K_ROWS_INV);
-        with_E<L>(c.E_rinv, [&](auto e) {
-            constexpr int E = decltype(e)::value;
-            hipLaunchKernelGGL((ks_rows_inv<L, E, MIXED ? 2 : 1>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A,
-                               k);
-        });
-    } else {
-        KTime t(c.timer, LPIDE_K_ROWS_INV);
-        hipLaunchKernelGGL((ks_affine_noB<false>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, k);
-    }
-    {
-        KTime t(c.timer, LPIDE_K_LINE_COLS);
-        hipLaunchKernelGGL(ks_line_cols<4>, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
-                           c.stream, c.A, k);
-    }
-    KTime t(c.timer, LPIDE_K_LINE_ROWS);
-    with_E<L>(c.E_lrows, [&](auto e) {
-        constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_line_rows<L, E, FFT, MIXED>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A, k);
-    });
-}
-
-// One entry of every plan's step list.  The FP64 correlation of V^{n-1} runs
-// when the explicit part needs it (theta < 1) and, in the mixed form, in every
-// step (B V^{n-1} anchors the FP32 increments); the kernels decide on the
-// device, so the launch sequence is the same for every step.  In the FP64
-// form the row transform of V^{n-1} is left in X by the previous step's last
-// iteration; the mixed form recomputes it (its iterations transform increments).
-template <int L, bool FFT, bool MIXED>
-void launch_step(const Launch& c, int kmax) {
-    if (c.timer) c.timer->tag_k = 0;
-    const dim3 gr(c.xrows, c.np), gc(L / 2 + 1, c.np);
-    if (FFT) {
-        if (MIXED) {
-            KTime t(c.timer, LPIDE_K_ROWS_FWD);
-            with_E<L>(c.E_rinv, [&](auto e) {
-                constexpr int E = decltype(e)::value;
-                hipLaunchKernelGGL((ks_rows_fwd<L, E>), gr, dim3(L / E), 0, c.stream, c.A);
-            });
-        }
-        {
-            KTime t(c.timer, LPIDE_K_EXPL_COLS);
-            with_E<L>(c.E_cols, [&](auto e) {
-                constexpr int E = decltype(e)::value;
-                hipLaunchKernelGGL((ks_cols<L, E, double2>), gc, dim3(L / E), 0, c.stream, c.A, 0);
-            });
-        }
-        KTime t(c.timer, LPIDE_K_EXPL_ROWS);
-        with_E<L>(c.E_rinv, [&](auto e) {
-            constexpr int E = decltype(e)::value;
-            hipLaunchKernelGGL((ks_rows_inv<L, E, 0>), gr, dim3(L / E), 0, c.stream, c.A, 0);
-        });
-    } else {
-        KTime t(c.timer, LPIDE_K_EXPL_ROWS);
-        hipLaunchKernelGGL((ks_affine_noB<true>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, 0);
-    }
-    {
-        KTime t(c.timer, LPIDE_K_SL);
-        with_E<L>(c.E_sl, [&](auto e) {
-            constexpr int E = decltype(e)::value;
-            if (c.sl_order == 1)
-                hipLaunchKernelGGL((ks_sl<L, E, 1, FFT, MIXED>), gr, dim3(L / E), 0, c.stream, c.A);
-            else
-                hipLaunchKernelGGL((ks_sl<L, E, 3, FFT, MIXED>), gr, dim3(L / E), 0, c.stream, c.A);
-        });
-    }
-    if (c.record) hipLaunchKernelGGL(ks_store_E, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
-    for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT, MIXED>(c, k);
-    if (c.timer) c.timer->tag_k = 0;
-    {
-        KTime t(c.timer, LPIDE_K_STEP_END);
-        hipLaunchKernelGGL(ks_step_end, dim3(1, c.np), dim3(64), 0, c.stream, c.A, kmax);
-    }
-    if (c.record) hipLaunchKernelGGL(ks_store_V, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
-}
-
-template <int L>
-void launch_slots_L(const Launch& c, int first_tag, int nslots, int kmax) {
-    for (int s = 0; s < nslots; ++s) {
-        if (c.timer) c.timer->tag_step = first_tag + s;
-        if (!c.jumps) launch_step<L, false, false>(c, kmax);
-        else if (c.mixed) launch_step<L, true, true>(c, kmax);
-        else launch_step<L, true, false>(c, kmax);
-    }
-}
-
-template <int L>
-void launch_iteration_L(const Launch& c, int k) {
-    if (!c.jumps) launch_iteration<L, false, false>(c, k);
-    else if (c.mixed) launch_iteration<L, true, true>(c, k);
-    else launch_iteration<L, true, false>(c, k);
-}
-
 // Default radix schedule.  From measurements on MI355X (each kernel alone):
 // the column pass gains from radix 16 at L >= 1024; the row c2r, line-row and
 // SL kernels from radix 4 up to L = 1024 and radix 8 above.
@@ -678,7 +287,7 @@ void apply_schedule(Launch& c, const Schedule& s) {
     }
 
 int issue_slots(const Launch& c, int first_tag, int nslots, int kmax) {
-#define CALL_SLOTS(Lc) launch_slots_L<Lc>(c, first_tag, nslots, kmax)
+#define CALL_SLOTS(Lc) PerL<Lc>::slots(c, first_tag, nslots, kmax)
     LPIDE_SWITCH_L(c.L, CALL_SLOTS)
 #undef CALL_SLOTS
     HIP_TRY(hipGetLastError());
@@ -686,7 +295,7 @@ int issue_slots(const Launch& c, int first_tag, int nslots, int kmax) {
 }
 
 int issue_iteration(const Launch& c, int k) {
-#define CALL_IT(Lc) launch_iteration_L<Lc>(c, k)
+#define CALL_IT(Lc) PerL<Lc>::iteration(c, k)
     LPIDE_SWITCH_L(c.L, CALL_IT)
 #undef CALL_IT
     HIP_TRY(hipGetLastError());
@@ -694,7 +303,7 @@ int issue_iteration(const Launch& c, int k) {
 }
 
 int dispatch_conv(Plan* p, const double* Y, double* out) {
-#define CALL_CONV(Lc) launch_conv<Lc>(p, Y, out)
+#define CALL_CONV(Lc) PerL<Lc>::conv(p, Y, out)
     LPIDE_SWITCH_L(p->L, CALL_CONV)
 #undef CALL_CONV
     HIP_TRY(hipGetLastError());
@@ -702,7 +311,7 @@ int dispatch_conv(Plan* p, const double* Y, double* out) {
 }
 
 int dispatch_spectrum(Plan* p, const double* G, double2* Xfull) {
-#define CALL_SPEC(Lc) launch_spectrum<Lc>(p, G, Xfull)
+#define CALL_SPEC(Lc) PerL<Lc>::spectrum(p, G, Xfull)
     LPIDE_SWITCH_L(p->L, CALL_SPEC)
 #undef CALL_SPEC
     HIP_TRY(hipGetLastError());
@@ -710,7 +319,7 @@ int dispatch_spectrum(Plan* p, const double* G, double2* Xfull) {
 }
 
 int dispatch_rows_fwd(Plan* p, const double* Y, hipStream_t s) {
-#define CALL_RF(Lc) launch_rows_fwd<Lc>(p, Y, s)
+#define CALL_RF(Lc) PerL<Lc>::rows_fwd(p, Y, s)
     LPIDE_SWITCH_L(p->L, CALL_RF)
 #undef CALL_RF
     HIP_TRY(hipGetLastError());
@@ -846,19 +455,6 @@ int read_back(Group* g) {
     HIP_TRY(hipMemcpyAsync(g->incs_h.data(), g->incs, sizeof(double) * g->incs_h.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return LPIDE_OK;
-}
-
-double bits_d(unsigned long long b) {
-    double d;
-    std::memcpy(&d, &b, sizeof d);
-    return d;
-}
-
-// Stopping-rule value after iteration k from a host copy of a control block.
-double err_of(const Ctl& c, int k) {
-    unsigned long long m = c.err[0][k];
-    for (int x = 1; x < NX; ++x) m = std::max(m, c.err[x][k]);
-    return bits_d(m);
 }
 
 // Complete the current step of plan i, whose predicted iterations did not
@@ -1027,38 +623,6 @@ int march(Plan* p, int count, double* v_out) {
     return march_group(g, &count, 0, nullptr, &v_out);
 }
 
-// ---- adjoint march ----
-struct Adjoint {
-    int C = 0;                      // checkpoint stride
-    int n_ckpt = 0;
-    std::vector<void*> allocs;
-    double* ckpt = nullptr;         // n_ckpt states V^{qC}
-    double* seg = nullptr;          // C + 1 states of the segment being reversed
-    double* segE = nullptr;         // C explicit parts of that segment
-    double *lam = nullptr, *mu = nullptr, *ybar = nullptr, *dummy = nullptr, *corr = nullptr, *corr2 = nullptr;
-    int have_corr = 0;               // corr (corr2) hold lam - Ybar of the previous (second previous) reverse step
-    double corr_c = 0.0, corr_c2 = 0.0;   // dt theta of those steps
-    bool xb_is_v = false;            // XD holds the row transform of V^{s+1} from the previous reverse step
-    double2 *XA = nullptr, *XB = nullptr, *XC = nullptr, *XD = nullptr;
-    double2* S = nullptr;           // (L/2+1) x L spectral accumulator
-    double* G = nullptr;            // L x L inverse transform of S
-    double* acc = nullptr;          // n x 8 per-row accumulators
-    StepDesc* sets_d = nullptr;
-    std::vector<StepDesc> sets;
-    MarchArgs* A = nullptr;
-    MarchArgs args{};
-    Ctl* ctl = nullptr;
-    Ctl* ctl_h = nullptr;
-    int* counts = nullptr;
-    double* incs = nullptr;
-    std::vector<int> counts_h;
-    // host Jacobian of (a11, a12, a22, r_omega, kappa1, kappa2, omega) with respect to the
-    // 8 subordination parameters, cached for the std point it was taken at
-    double jac_std[8] = {};
-    bool jac_valid = false;
-    std::vector<double> jac;        // 8 x (6 + (2 N_z)^2)
-};
-
 void destroy_adjoint(Adjoint* a) {
     if (!a) return;
     for (void* x : a->allocs) (void)hipFree(x);
@@ -1172,148 +736,16 @@ int march_recorded(Plan* p, int step0, int nsteps, const double* v_in, double* s
     return rc;
 }
 
-template <int L>
-void launch_adj_iteration(const Launch& c, int k) {
-    with_E<L>(c.E_cols, [&](auto e) {
-        constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_cols<L, E, double2, true>), dim3(L / 2 + 1, 1), dim3(L / E), 0, c.stream, c.A, k);
-    });
-    with_E<L>(c.E_rinv, [&](auto e) {
-        constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_rows_inv<L, E, 3>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);
-    });
-    hipLaunchKernelGGL(ks_line_cols<4>, dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols, c.stream,
-                       c.A, k);
-    with_E<L>(c.E_lrows, [&](auto e) {
-        constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_line_rows<L, E, true, false>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);
-    });
-}
-
-// One reverse step s: Ybar (in adj->ybar) -> cotangent of V^s (in adj->ybar),
-// gradient terms accumulated.  Y = V^{s+1}, V = V^s, E = E_s.
-template <int L>
-int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const double* V, const double* E) {
-    Adjoint* a = p->adj;
-    const int n = p->hp.n;
-    const size_t N = (size_t)n * n;
-    const StepDesc& sd = p->sets[p->step_set[s]];
-    const dim3 gr(c.xrows, 1);
-    hipLaunchKernelGGL(ks_adj_begin, dim3(1), dim3(64), 0, c.stream, c.A, s);
-    const double cth = sd.dt * sd.theta;
-    const double* cp1 = nullptr;
-    const double* cp2 = nullptr;
-    double w1 = 0.0, w2 = 0.0;
-    if (a->have_corr >= 1 && a->corr_c > 0.0) {
-        const double ratio = cth / a->corr_c;
-        cp1 = a->corr;
-        w1 = ratio;
-        if (a->have_corr >= 2 && a->corr_c2 == a->corr_c) {   // same step kind: extrapolate linearly
-            cp2 = a->corr2;
-            w1 = 2.0 * ratio;
-            w2 = -ratio;
-        }
-    }
-    with_E<L>(c.E_rinv, [&](auto e) {
-        constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_adj_start<L, E>), gr, dim3(L / E), 0, c.stream, c.A, cp1, w1, cp2, w2);
-    });
-    int k = *kpred;
-    for (int q = 1; q <= k; ++q) launch_adj_iteration<L>(c, q);
-    hipLaunchKernelGGL(ks_adj_end, dim3(1), dim3(64), 0, c.stream, c.A, k);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(a->ctl_h, a->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.stream));
-    HIP_TRY(hipStreamSynchronize(c.stream));
-    while (a->ctl_h->fail) {
-        const double ek = err_of(*a->ctl_h, k);
-        if (!std::isfinite(ek)) return fail(LPIDE_E_NAN, "non-finite adjoint increment in step " + std::to_string(s));
-        if (k >= p->opts.max_iter) {
-            char buf[160];
-            snprintf(buf, sizeof buf, "adjoint fixed point not converged in step %d after %d iterations (increment %.3e)",
-                     s, k, ek);
-            return fail(LPIDE_E_NOCONV, buf);
-        }
-        ++k;
-        hipLaunchKernelGGL(ks_clear_fail, dim3(1), dim3(64), 0, c.stream, c.A, 0);
-        launch_adj_iteration<L>(c, k);
-        hipLaunchKernelGGL(ks_adj_end, dim3(1), dim3(64), 0, c.stream, c.A, k);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(a->ctl_h, a->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.stream));
-        HIP_TRY(hipStreamSynchronize(c.stream));
-    }
-    int used = k;
-    for (int q = 1; q <= k; ++q)
-        if (err_of(*a->ctl_h, q) < p->opts.tol) { used = q; break; }
-    a->counts_h[s] = used;
-    *kpred = std::max(1, std::min(p->opts.max_iter, used));
-    const int sb = int(std::min<size_t>(1024, (N + 255) / 256));
-    std::swap(a->corr, a->corr2);
-    a->corr_c2 = a->corr_c;
-    hipLaunchKernelGGL(ks_adj_corr, dim3(sb), dim3(256), 0, c.stream, c.A, a->corr);
-    a->have_corr = std::min(2, a->have_corr + 1);
-    a->corr_c = cth;
-    // mu = (T^SL)^T lam, then the cotangent of V^s
-    with_E<L>(c.E_sl, [&](auto e) {
-        constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_adj_sl<L, E>), gr, dim3(L / E), 0, c.stream, c.A);
-    });
-    if (sd.theta < 1.0) {
-        with_E<L>(c.E_cols, [&](auto e) {
-            constexpr int E = decltype(e)::value;
-            hipLaunchKernelGGL((ks_cols<L, E, double2, true>), dim3(L / 2 + 1, 1), dim3(L / E), 0, c.stream, c.A, 0);
-        });
-        with_E<L>(c.E_rinv, [&](auto e) {
-            constexpr int E = decltype(e)::value;
-            hipLaunchKernelGGL((ks_rows_inv<L, E, 4>), gr, dim3(L / E), 0, c.stream, c.A, 0);
-        });
-    }
-    // gradient terms (they read lam and mu; the new cotangent is written last)
-    if (p->hp.sl_order == 1)
-        hipLaunchKernelGGL(ks_adj_accum<1>, dim3(n, 1), dim3(256), 0, c.stream, c.A, Y, V, E, a->acc);
-    else
-        hipLaunchKernelGGL(ks_adj_accum<3>, dim3(n, 1), dim3(256), 0, c.stream, c.A, Y, V, E, a->acc);
-    const double c1 = sd.dt * sd.theta, c2 = sd.dt * (1.0 - sd.theta);
-    if (p->jumps) {
-        const int np = (n + 1) / 2;
-        // the row transform of Y = V^{s+1} is the V transform of reverse step s + 1 when it had one
-        if (a->xb_is_v) std::swap(a->XB, a->XD);
-        else hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, Y, n, n, n, a->XB, n, p->tw);
-        hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, a->lam, n, n, n, a->XA, n, p->tw);
-        a->xb_is_v = false;
-        if (c2 != 0.0) {
-            hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, a->mu, n, n, n, a->XC, n, p->tw);
-            hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, V, n, n, n, a->XD, n, p->tw);
-            a->xb_is_v = true;
-        }
-        hipLaunchKernelGGL((ks_adj_spec<L>), dim3(L / 2 + 1), dim3(L / 8), 0, c.stream, a->XA, a->XB, a->XC, a->XD, n,
-                           c1, c2, a->S, p->tw);
-    }
-    if (sd.theta >= 1.0)
-        hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, c.stream, a->mu, a->ybar, N);
-    HIP_TRY(hipGetLastError());
-    return LPIDE_OK;
-}
-
 int dispatch_adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const double* V,
                       const double* E) {
-#define CALL_ADJ(Lc) return adj_step<Lc>(p, c, s, kpred, Y, V, E)
+#define CALL_ADJ(Lc) return PerL<Lc>::adj_step(p, c, s, kpred, Y, V, E)
     LPIDE_SWITCH_L(p->Lr, CALL_ADJ)
 #undef CALL_ADJ
     return LPIDE_OK;
 }
 
-// Inverse 2D transform of the spectral accumulator (column inverse FFTs in
-// place, then the row c2r): G[d1 mod L][d2 mod L] = L^2 x (kernel gradient).
-template <int L>
-void launch_adj_kernel_grad(Plan* p, hipStream_t s) {
-    Adjoint* a = p->adj;
-    hipLaunchKernelGGL((k_cols<L, 2>), dim3(L / 2 + 1), dim3(L / 8), 0, s, a->S, L, L, L, (const double2*)nullptr,
-                       (double2*)nullptr, 0.0, p->tw);
-    hipLaunchKernelGGL((k_rows_inv<L>), dim3(L / 2), dim3(L / 8), 0, s, (const double2*)a->S, L, L, a->G, p->tw);
-}
-
 int dispatch_adj_kernel_grad(Plan* p, hipStream_t s) {
-#define CALL_KG(Lc) launch_adj_kernel_grad<Lc>(p, s)
+#define CALL_KG(Lc) PerL<Lc>::adj_kernel_grad(p, s)
     LPIDE_SWITCH_L(p->L, CALL_KG)
 #undef CALL_KG
     HIP_TRY(hipGetLastError());
@@ -1585,6 +1017,8 @@ int batch_march(Batch* b, double* const* v_out, int steps_cap) {
 }
 
 }  // namespace
+}  // namespace detail
+}  // namespace lpide
 
 // ---------------------------------------------------------------------------
 // C ABI

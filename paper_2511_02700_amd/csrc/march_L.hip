@@ -1,0 +1,300 @@
+// Launch sequences for one transform size L (compiled once per size with
+// -DLPIDE_L=L): the device-controlled march (one step slot or one iteration
+// for a group of plans, every kernel class with its radix schedule), the
+// stand-alone correlation and plan-time spectrum, and one reverse step of the
+// adjoint march.
+#include "conv_kernels.hpp"
+#include "plan.hpp"
+
+#ifndef LPIDE_L
+#error "compile with -DLPIDE_L=<transform size>"
+#endif
+
+namespace lpide {
+namespace detail {
+namespace {
+
+// ---- stand-alone correlation (apply_B) and plan-time spectrum ----
+template <int L>
+void launch_conv(Plan* p, const double* Y, double* out) {
+    const int n = p->hp.n, np = (n + 1) / 2;
+    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, p->stream, Y, n, n, n, p->X, n, p->tw);
+    hipLaunchKernelGGL((k_cols<L, 0>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, p->X, n, n, n, p->spec,
+                       (double2*)nullptr, 0.0, p->tw);
+    hipLaunchKernelGGL((k_rows_inv<L>), dim3(np), dim3(L / 8), 0, p->stream, p->X, n, n, out, p->tw);
+}
+
+template <int L>
+void launch_spectrum(Plan* p, const double* G, double2* Xfull) {
+    const double scale = 1.0 / (double(L) * double(L));
+    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(L / 2), dim3(L / 8), 0, p->stream, G, L, L, L, Xfull, L, p->tw);
+    hipLaunchKernelGGL((k_cols<L, 1>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, Xfull, L, L, L,
+                       (const double2*)nullptr, p->spec, scale, p->tw);
+}
+
+template <int L>
+void launch_rows_fwd(Plan* p, const double* Y, hipStream_t s) {
+    const int n = p->hp.n;
+    hipLaunchKernelGGL((k_rows_fwd<L>), dim3((n + 1) / 2), dim3(L / 8), 0, s, Y, n, n, n, p->X, n, p->tw);
+}
+
+template <int L, bool FFT, bool MIXED>
+void launch_iteration(const Launch& c, int k) {
+    using C = typename std::conditional<MIXED, float2, double2>::type;
+    if (c.timer) c.timer->tag_k = k;
+    if (FFT) {
+        {
+            KTime t(c.timer, LPIDE_K_COLS);
+            with_E<L>(c.E_cols, [&](auto e) {
+                constexpr int E = decltype(e)::value;
+                hipLaunchKernelGGL((ks_cols<L, E, C>), dim3(L / 2 + 1, c.np), dim3(L / E), 0, c.stream, c.A, k);
+            });
+        }
+        KTime t(c.timer, LPIDE_K_ROWS_INV);
+        with_E<L>(c.E_rinv, [&](auto e) {
+            constexpr int E = decltype(e)::value;
+            hipLaunchKernelGGL((ks_rows_inv<L, E, MIXED ? 2 : 1>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A,
+                               k);
+        });
+    } else {
+        KTime t(c.timer, LPIDE_K_ROWS_INV);
+        hipLaunchKernelGGL((ks_affine_noB<false>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, k);
+    }
+    {
+        KTime t(c.timer, LPIDE_K_LINE_COLS);
+        hipLaunchKernelGGL(ks_line_cols<4>, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
+                           c.stream, c.A, k);
+    }
+    KTime t(c.timer, LPIDE_K_LINE_ROWS);
+    with_E<L>(c.E_lrows, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_line_rows<L, E, FFT, MIXED>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A, k);
+    });
+}
+
+// One entry of every plan's step list.  The FP64 correlation of V^{n-1} runs
+// when the explicit part needs it (theta < 1) and, in the mixed form, in every
+// step (B V^{n-1} anchors the FP32 increments); the kernels decide on the
+// device, so the launch sequence is the same for every step.  In the FP64
+// form the row transform of V^{n-1} is left in X by the previous step's last
+// iteration; the mixed form recomputes it (its iterations transform increments).
+template <int L, bool FFT, bool MIXED>
+void launch_step(const Launch& c, int kmax) {
+    if (c.timer) c.timer->tag_k = 0;
+    const dim3 gr(c.xrows, c.np), gc(L / 2 + 1, c.np);
+    if (FFT) {
+        if (MIXED) {
+            KTime t(c.timer, LPIDE_K_ROWS_FWD);
+            with_E<L>(c.E_rinv, [&](auto e) {
+                constexpr int E = decltype(e)::value;
+                hipLaunchKernelGGL((ks_rows_fwd<L, E>), gr, dim3(L / E), 0, c.stream, c.A);
+            });
+        }
+        {
+            KTime t(c.timer, LPIDE_K_EXPL_COLS);
+            with_E<L>(c.E_cols, [&](auto e) {
+                constexpr int E = decltype(e)::value;
+                hipLaunchKernelGGL((ks_cols<L, E, double2>), gc, dim3(L / E), 0, c.stream, c.A, 0);
+            });
+        }
+        KTime t(c.timer, LPIDE_K_EXPL_ROWS);
+        with_E<L>(c.E_rinv, [&](auto e) {
+            constexpr int E = decltype(e)::value;
+            hipLaunchKernelGGL((ks_rows_inv<L, E, 0>), gr, dim3(L / E), 0, c.stream, c.A, 0);
+        });
+    } else {
+        KTime t(c.timer, LPIDE_K_EXPL_ROWS);
+        hipLaunchKernelGGL((ks_affine_noB<true>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, 0);
+    }
+    {
+        KTime t(c.timer, LPIDE_K_SL);
+        with_E<L>(c.E_sl, [&](auto e) {
+            constexpr int E = decltype(e)::value;
+            if (c.sl_order == 1)
+                hipLaunchKernelGGL((ks_sl<L, E, 1, FFT, MIXED>), gr, dim3(L / E), 0, c.stream, c.A);
+            else
+                hipLaunchKernelGGL((ks_sl<L, E, 3, FFT, MIXED>), gr, dim3(L / E), 0, c.stream, c.A);
+        });
+    }
+    if (c.record) hipLaunchKernelGGL(ks_store_E, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
+    for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT, MIXED>(c, k);
+    if (c.timer) c.timer->tag_k = 0;
+    {
+        KTime t(c.timer, LPIDE_K_STEP_END);
+        hipLaunchKernelGGL(ks_step_end, dim3(1, c.np), dim3(64), 0, c.stream, c.A, kmax);
+    }
+    if (c.record) hipLaunchKernelGGL(ks_store_V, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
+}
+
+template <int L>
+void launch_slots_L(const Launch& c, int first_tag, int nslots, int kmax) {
+    for (int s = 0; s < nslots; ++s) {
+        if (c.timer) c.timer->tag_step = first_tag + s;
+        if (!c.jumps) launch_step<L, false, false>(c, kmax);
+        else if (c.mixed) launch_step<L, true, true>(c, kmax);
+        else launch_step<L, true, false>(c, kmax);
+    }
+}
+
+template <int L>
+void launch_iteration_L(const Launch& c, int k) {
+    if (!c.jumps) launch_iteration<L, false, false>(c, k);
+    else if (c.mixed) launch_iteration<L, true, true>(c, k);
+    else launch_iteration<L, true, false>(c, k);
+}
+
+template <int L>
+void launch_adj_iteration(const Launch& c, int k) {
+    with_E<L>(c.E_cols, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_cols<L, E, double2, true>), dim3(L / 2 + 1, 1), dim3(L / E), 0, c.stream, c.A, k);
+    });
+    with_E<L>(c.E_rinv, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_rows_inv<L, E, 3>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);
+    });
+    hipLaunchKernelGGL(ks_line_cols<4>, dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols, c.stream,
+                       c.A, k);
+    with_E<L>(c.E_lrows, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_line_rows<L, E, true, false>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);
+    });
+}
+
+// One reverse step s: Ybar (in adj->ybar) -> cotangent of V^s (in adj->ybar),
+// gradient terms accumulated.  Y = V^{s+1}, V = V^s, E = E_s.
+template <int L>
+int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const double* V, const double* E) {
+    Adjoint* a = p->adj;
+    const int n = p->hp.n;
+    const size_t N = (size_t)n * n;
+    const StepDesc& sd = p->sets[p->step_set[s]];
+    const dim3 gr(c.xrows, 1);
+    hipLaunchKernelGGL(ks_adj_begin, dim3(1), dim3(64), 0, c.stream, c.A, s);
+    const double cth = sd.dt * sd.theta;
+    const double* cp1 = nullptr;
+    const double* cp2 = nullptr;
+    double w1 = 0.0, w2 = 0.0;
+    if (a->have_corr >= 1 && a->corr_c > 0.0) {
+        const double ratio = cth / a->corr_c;
+        cp1 = a->corr;
+        w1 = ratio;
+        if (a->have_corr >= 2 && a->corr_c2 == a->corr_c) {   // same step kind: extrapolate linearly
+            cp2 = a->corr2;
+            w1 = 2.0 * ratio;
+            w2 = -ratio;
+        }
+    }
+    with_E<L>(c.E_rinv, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_adj_start<L, E>), gr, dim3(L / E), 0, c.stream, c.A, cp1, w1, cp2, w2);
+    });
+    int k = *kpred;
+    for (int q = 1; q <= k; ++q) launch_adj_iteration<L>(c, q);
+    hipLaunchKernelGGL(ks_adj_end, dim3(1), dim3(64), 0, c.stream, c.A, k);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(a->ctl_h, a->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    while (a->ctl_h->fail) {
+        const double ek = err_of(*a->ctl_h, k);
+        if (!std::isfinite(ek)) return fail(LPIDE_E_NAN, "non-finite adjoint increment in step " + std::to_string(s));
+        if (k >= p->opts.max_iter) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "adjoint fixed point not converged in step %d after %d iterations (increment %.3e)",
+                     s, k, ek);
+            return fail(LPIDE_E_NOCONV, buf);
+        }
+        ++k;
+        hipLaunchKernelGGL(ks_clear_fail, dim3(1), dim3(64), 0, c.stream, c.A, 0);
+        launch_adj_iteration<L>(c, k);
+        hipLaunchKernelGGL(ks_adj_end, dim3(1), dim3(64), 0, c.stream, c.A, k);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(a->ctl_h, a->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c.stream));
+        HIP_TRY(hipStreamSynchronize(c.stream));
+    }
+    int used = k;
+    for (int q = 1; q <= k; ++q)
+        if (err_of(*a->ctl_h, q) < p->opts.tol) { used = q; break; }
+    a->counts_h[s] = used;
+    *kpred = std::max(1, std::min(p->opts.max_iter, used));
+    const int sb = int(std::min<size_t>(1024, (N + 255) / 256));
+    std::swap(a->corr, a->corr2);
+    a->corr_c2 = a->corr_c;
+    hipLaunchKernelGGL(ks_adj_corr, dim3(sb), dim3(256), 0, c.stream, c.A, a->corr);
+    a->have_corr = std::min(2, a->have_corr + 1);
+    a->corr_c = cth;
+    // mu = (T^SL)^T lam, then the cotangent of V^s
+    with_E<L>(c.E_sl, [&](auto e) {
+        constexpr int E = decltype(e)::value;
+        hipLaunchKernelGGL((ks_adj_sl<L, E>), gr, dim3(L / E), 0, c.stream, c.A);
+    });
+    if (sd.theta < 1.0) {
+        with_E<L>(c.E_cols, [&](auto e) {
+            constexpr int E = decltype(e)::value;
+            hipLaunchKernelGGL((ks_cols<L, E, double2, true>), dim3(L / 2 + 1, 1), dim3(L / E), 0, c.stream, c.A, 0);
+        });
+        with_E<L>(c.E_rinv, [&](auto e) {
+            constexpr int E = decltype(e)::value;
+            hipLaunchKernelGGL((ks_rows_inv<L, E, 4>), gr, dim3(L / E), 0, c.stream, c.A, 0);
+        });
+    }
+    // gradient terms (they read lam and mu; the new cotangent is written last)
+    if (p->hp.sl_order == 1)
+        hipLaunchKernelGGL(ks_adj_accum<1>, dim3(n, 1), dim3(256), 0, c.stream, c.A, Y, V, E, a->acc);
+    else
+        hipLaunchKernelGGL(ks_adj_accum<3>, dim3(n, 1), dim3(256), 0, c.stream, c.A, Y, V, E, a->acc);
+    const double c1 = sd.dt * sd.theta, c2 = sd.dt * (1.0 - sd.theta);
+    if (p->jumps) {
+        const int np = (n + 1) / 2;
+        // the row transform of Y = V^{s+1} is the V transform of reverse step s + 1 when it had one
+        if (a->xb_is_v) std::swap(a->XB, a->XD);
+        else hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, Y, n, n, n, a->XB, n, p->tw);
+        hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, a->lam, n, n, n, a->XA, n, p->tw);
+        a->xb_is_v = false;
+        if (c2 != 0.0) {
+            hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, a->mu, n, n, n, a->XC, n, p->tw);
+            hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, V, n, n, n, a->XD, n, p->tw);
+            a->xb_is_v = true;
+        }
+        hipLaunchKernelGGL((ks_adj_spec<L>), dim3(L / 2 + 1), dim3(L / 8), 0, c.stream, a->XA, a->XB, a->XC, a->XD, n,
+                           c1, c2, a->S, p->tw);
+    }
+    if (sd.theta >= 1.0)
+        hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, c.stream, a->mu, a->ybar, N);
+    HIP_TRY(hipGetLastError());
+    return LPIDE_OK;
+}
+
+// Inverse 2D transform of the spectral accumulator (column inverse FFTs in
+// place, then the row c2r): G[d1 mod L][d2 mod L] = L^2 x (kernel gradient).
+template <int L>
+void launch_adj_kernel_grad(Plan* p, hipStream_t s) {
+    Adjoint* a = p->adj;
+    hipLaunchKernelGGL((k_cols<L, 2>), dim3(L / 2 + 1), dim3(L / 8), 0, s, a->S, L, L, L, (const double2*)nullptr,
+                       (double2*)nullptr, 0.0, p->tw);
+    hipLaunchKernelGGL((k_rows_inv<L>), dim3(L / 2), dim3(L / 8), 0, s, (const double2*)a->S, L, L, a->G, p->tw);
+}
+
+}  // namespace
+
+template <int L>
+void PerL<L>::slots(const Launch& c, int first_tag, int nslots, int kmax) { launch_slots_L<L>(c, first_tag, nslots, kmax); }
+template <int L>
+void PerL<L>::iteration(const Launch& c, int k) { launch_iteration_L<L>(c, k); }
+template <int L>
+void PerL<L>::conv(Plan* p, const double* Y, double* out) { launch_conv<L>(p, Y, out); }
+template <int L>
+void PerL<L>::spectrum(Plan* p, const double* G, double2* Xfull) { launch_spectrum<L>(p, G, Xfull); }
+template <int L>
+void PerL<L>::rows_fwd(Plan* p, const double* Y, hipStream_t s) { launch_rows_fwd<L>(p, Y, s); }
+template <int L>
+int PerL<L>::adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const double* V, const double* E) {
+    return ::lpide::detail::adj_step<L>(p, c, s, kpred, Y, V, E);
+}
+template <int L>
+void PerL<L>::adj_kernel_grad(Plan* p, hipStream_t s) { launch_adj_kernel_grad<L>(p, s); }
+
+template struct PerL<LPIDE_L>;
+
+}  // namespace detail
+}  // namespace lpide

@@ -523,7 +523,7 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
 
 // End of a step: convergence verdict, history rotation, next starting value.
 // One block per plan.
-__global__ void ks_step_end(const MarchArgs* __restrict__ A, int kmax) {
+static __global__ void ks_step_end(const MarchArgs* __restrict__ A, int kmax) {
     const MarchArgs& a = plan_args(A);
     Ctl* c = a.ctl;
     if (c->hold || c->step >= a.nsteps) return;
@@ -586,7 +586,7 @@ __global__ void ks_step_end(const MarchArgs* __restrict__ A, int kmax) {
 // when theta < 1, to segE.  After step_end: the current state to seg when its
 // step index is on the recording stride (idempotent: a slot whose step did not
 // advance writes the same state again).
-__global__ void ks_store_E(const MarchArgs* __restrict__ A) {
+static __global__ void ks_store_E(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0) || !a.segE || cur_set(a).theta >= 1.0) return;
     const size_t N = (size_t)a.n * a.n;
@@ -595,7 +595,7 @@ __global__ void ks_store_E(const MarchArgs* __restrict__ A) {
         dst[i] = a.R[i];
 }
 
-__global__ void ks_store_V(const MarchArgs* __restrict__ A) {
+static __global__ void ks_store_V(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
     const Ctl* c = a.ctl;
     if (!a.seg || c->hold) return;
@@ -616,7 +616,7 @@ __global__ void ks_store_V(const MarchArgs* __restrict__ A) {
 // Buffers of the adjoint MarchArgs: pool[1] = lam, pool[0] = mu, W = Ybar.
 
 // Control block for reverse step s: iterate in pool[1], no failure, stopping values reset.
-__global__ void ks_adj_begin(const MarchArgs* __restrict__ A, int s) {
+static __global__ void ks_adj_begin(const MarchArgs* __restrict__ A, int s) {
     Ctl* c = A[0].ctl;
     err_reset(c);
     if (threadIdx.x == 0) {
@@ -670,7 +670,7 @@ __global__ __launch_bounds__(L / E) void ks_adj_start(const MarchArgs* __restric
 
 // corr = lam - Ybar after the adjoint fixed point converged (start of the next
 // reverse step).
-__global__ void ks_adj_corr(const MarchArgs* __restrict__ A, double* __restrict__ corr) {
+static __global__ void ks_adj_corr(const MarchArgs* __restrict__ A, double* __restrict__ corr) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0)) return;
     const size_t N = (size_t)a.n * a.n;
@@ -681,7 +681,7 @@ __global__ void ks_adj_corr(const MarchArgs* __restrict__ A, double* __restrict_
 
 // Verdict of the adjoint fixed point of the current reverse step: iteration
 // count (first k with err_k < tol) or the failure flag.
-__global__ void ks_adj_end(const MarchArgs* __restrict__ A, int kmax) {
+static __global__ void ks_adj_end(const MarchArgs* __restrict__ A, int kmax) {
     const MarchArgs& a = A[0];
     Ctl* c = a.ctl;
     if (c->fail) return;
@@ -868,7 +868,7 @@ __global__ __launch_bounds__(L / E) void ks_adj_spec(const double2* __restrict__
 
 // Control block at the start of a march: the state of step-list entry step0
 // in pool[0], the iterate in pool[1], no history before it.  One block per plan.
-__global__ void ks_init(const MarchArgs* __restrict__ A) {
+static __global__ void ks_init(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
     Ctl* c = a.ctl;
     err_reset(c);
@@ -886,12 +886,12 @@ __global__ void ks_init(const MarchArgs* __restrict__ A) {
     }
 }
 
-__global__ void ks_clear_fail(const MarchArgs* __restrict__ A, int plan) {
+static __global__ void ks_clear_fail(const MarchArgs* __restrict__ A, int plan) {
     if (threadIdx.x == 0) A[plan].ctl->fail = 0;
 }
 
 // hold = 1 on every plan of the group except `keep` (keep < 0: release all).
-__global__ void ks_hold(const MarchArgs* __restrict__ A, int np, int keep) {
+static __global__ void ks_hold(const MarchArgs* __restrict__ A, int np, int keep) {
     for (int q = threadIdx.x; q < np; q += blockDim.x) A[q].ctl->hold = (keep >= 0 && q != keep) ? 1 : 0;
 }
 
