@@ -12,12 +12,13 @@ Default workload: the 512 x 512 finite-variation NTS case (alpha = 0.3) on
 [-4, 4]^2 with 256 time steps, theta = 1/2, fixed-point tol 1e-12, FP64.
 
 Printed (one JSON line): the metric, the roofline of the dominant kernel
-(algorithmic bytes per launch / mean launch time from HIP events recorded on
-the plan's stream during the timed region), the same for the correlation's
+(algorithmic bytes per launch / mean launch time from HIP events bound to the
+kernel's own dispatches on the plan's stream, over the timed solves), the same for the correlation's
 column pass, the other precision timed beside it with the mixed-vs-plain
 differences, and a CPU baseline: the FP64 oracle timed on this host on a
 bounded sample of the same workload.  Unless --no-extras: the column-pass
-roofline at 2048^2 (cache-exceeding working set), the adjoint form on its
+roofline at 2048^2 (cache-exceeding working set), whole 2048^2 solves in
+both precisions, the adjoint form on its
 1024^2 workload (ratio to the forward), and the batched form on 32 draws of
 the batched recipe (against solo solves).
 """
@@ -173,6 +174,37 @@ def large_conv_roofline(lp, name, steps=40):
     return out
 
 
+def large_solve(lp, name="nig2048_m"):
+    """Whole solves of a 2048^2, 1024-step workload (the large-grid form), FP64
+    and mixed: grid-pt-steps/s, iterations per step and the mixed-vs-plain
+    price difference at 64 seeded spot pairs."""
+    import numpy as np
+    import torch
+    import workloads
+    w = workloads.workload(name)
+    spots = workloads.spot_pairs(64, seed=2)
+    out = {"workload": "%s: %dx%d on [%g, %g]^2, %d steps, alpha %g, corr %g" % (
+        name, w["n"], w["n"], w["y_lo"], w["y_hi"], w["N_t"], w["model"]["alpha"], w["model"]["corr"])}
+    prices = {}
+    for prec in ("fp64", "fp32conv"):
+        plan = lp.plan_from_workload(w, precision=prec)
+        V = plan.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve(V)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        info = plan.info()
+        prices[prec] = plan.price(V, spots).cpu().numpy()
+        out[prec] = {"value": w["n"] ** 2 * w["N_t"] / dt, "unit": "grid-pt-steps/s", "ms": 1e3 * dt,
+                     "iters_per_step": info["total_iters"] / info["n_steps"], "radix": info["radix"]}
+        del plan, V
+        torch.cuda.empty_cache()
+    out["mixed_vs_plain_prices_rel"] = float(np.max(np.abs(prices["fp32conv"] - prices["fp64"]) /
+                                                np.maximum(1.0, np.abs(prices["fp64"]))))
+    return out
+
+
 def adjoint_measure(lp, name="nts1024", C=32):
     """The adjoint form on its workload: forward solve time, and the adjoint's
     march part (segment recompute + reverse steps + gather, with the solve's
@@ -288,10 +320,10 @@ def main():
     prof = plan.kernel_stats()
     dominant = max(prof, key=lambda c: prof[c][1])
 
-    # timed region: K solves without events (each HIP event pair drains the
-    # queue, about 3 us per timed launch), giving value; then the same K
-    # solves with events around the dominant class and the correlation's
-    # column pass, giving their mean launch durations
+    # timed region: K solves without events, giving value; then the same K
+    # solves with start/stop events bound to every launch of the dominant
+    # class and of the correlation's column pass (the events take the
+    # dispatch's own timestamps), giving their mean launch durations
     wall, _ = timed_solves(plan, outs[args.precision], args.steps, [])
     _, live = timed_solves(plan, outs[args.precision], args.steps, sorted({dominant, "cols"}))
     info = plan.info()
@@ -351,6 +383,7 @@ def main():
         del plans, outs, plan
         torch.cuda.empty_cache()
         result["conv_roofline_2048"] = large_conv_roofline(lp, "nig2048_m")
+        result["large_2048"] = large_solve(lp, "nig2048_m")
         result["adjoint"] = adjoint_measure(lp)
         result["batched"] = batch_measure(lp)
     if rank == 0 and not args.no_cpu_baseline:

@@ -224,10 +224,12 @@ int lpide_discretize_host(const lpide_grid* grid, const lpide_levy* levy, const 
 #define LPIDE_K_ROWS_FWD   8   /* FP64 row FFTs of V^{n-1} (mixed form) */
 #define LPIDE_KCLASSES     9
 
-/* Kernel timing.  With bit c of class_mask set, the plan records a pair of HIP
- * events on its stream around every launch of kernel class c; the elapsed
- * times are summed per class.  Each call resets the counters (after folding in
- * pending events).  class_mask = 0 disables timing (the default). */
+/* Kernel timing.  With bit c of class_mask set, every launch of kernel class c
+ * in single-plan marches carries a start and a stop HIP event bound to the
+ * dispatch itself (hipExtLaunchKernel), so the elapsed time is the kernel's
+ * own duration; the times are summed per class.  Each call resets the
+ * counters (after folding in pending events).  class_mask = 0 disables timing
+ * (the default). */
 int lpide_timing(void* plan, uint32_t class_mask);
 
 /* Per-class launch counts and summed durations in milliseconds since the last

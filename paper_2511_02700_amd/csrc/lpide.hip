@@ -59,16 +59,15 @@ hipEvent_t next_event(Plan* p) {
     return p->ev_pool[p->ev_used++];
 }
 
-KTime::KTime(Plan* pl, int c) : p(pl), on(pl && ((pl->time_mask >> c) & 1u)) {
-    if (!on) return;
-    idx = p->ev_used;
-    hipEvent_t a = next_event(p), b = next_event(p);
-    if (!a || !b) { on = false; return; }
-    (void)hipEventRecord(a, p->stream);
-    p->ev_recs.push_back({c, idx, p->tag_step, p->tag_k});
-}
-KTime::~KTime() {
-    if (on) (void)hipEventRecord(p->ev_pool[idx + 1], p->stream);
+KTime::KTime(Plan* pl, int c) : p(pl), cls(c), on(pl && ((pl->time_mask >> c) & 1u)) {}
+
+bool KTime::events(hipEvent_t* a, hipEvent_t* b) {
+    const size_t idx = p->ev_used;
+    *a = next_event(p);
+    *b = next_event(p);
+    if (!*a || !*b) return false;
+    p->ev_recs.push_back({cls, idx, p->tag_step, p->tag_k});
+    return true;
 }
 
 }  // namespace detail

@@ -47,28 +47,28 @@ void launch_iteration(const Launch& c, int k) {
             KTime t(c.timer, LPIDE_K_COLS);
             with_E<L>(c.E_cols, [&](auto e) {
                 constexpr int E = decltype(e)::value;
-                hipLaunchKernelGGL((ks_cols<L, E, C>), dim3(L / 2 + 1, c.np), dim3(L / E), 0, c.stream, c.A, k);
+                t.launch((ks_cols<L, E, C>), dim3(L / 2 + 1, c.np), dim3(L / E), 0, c.stream, c.A, k);
             });
         }
         KTime t(c.timer, LPIDE_K_ROWS_INV);
         with_E<L>(c.E_rinv, [&](auto e) {
             constexpr int E = decltype(e)::value;
-            hipLaunchKernelGGL((ks_rows_inv<L, E, MIXED ? 2 : 1>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A,
+            t.launch((ks_rows_inv<L, E, MIXED ? 2 : 1>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A,
                                k);
         });
     } else {
         KTime t(c.timer, LPIDE_K_ROWS_INV);
-        hipLaunchKernelGGL((ks_affine_noB<false>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, k);
+        t.launch((ks_affine_noB<false>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, k);
     }
     {
         KTime t(c.timer, LPIDE_K_LINE_COLS);
-        hipLaunchKernelGGL(ks_line_cols<4>, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
+        t.launch(ks_line_cols<4>, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
                            c.stream, c.A, k);
     }
     KTime t(c.timer, LPIDE_K_LINE_ROWS);
     with_E<L>(c.E_lrows, [&](auto e) {
         constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_line_rows<L, E, FFT, MIXED>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A, k);
+        t.launch((ks_line_rows<L, E, FFT, MIXED>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A, k);
     });
 }
 
@@ -87,33 +87,33 @@ void launch_step(const Launch& c, int kmax) {
             KTime t(c.timer, LPIDE_K_ROWS_FWD);
             with_E<L>(c.E_rinv, [&](auto e) {
                 constexpr int E = decltype(e)::value;
-                hipLaunchKernelGGL((ks_rows_fwd<L, E>), gr, dim3(L / E), 0, c.stream, c.A);
+                t.launch((ks_rows_fwd<L, E>), gr, dim3(L / E), 0, c.stream, c.A);
             });
         }
         {
             KTime t(c.timer, LPIDE_K_EXPL_COLS);
             with_E<L>(c.E_cols, [&](auto e) {
                 constexpr int E = decltype(e)::value;
-                hipLaunchKernelGGL((ks_cols<L, E, double2>), gc, dim3(L / E), 0, c.stream, c.A, 0);
+                t.launch((ks_cols<L, E, double2>), gc, dim3(L / E), 0, c.stream, c.A, 0);
             });
         }
         KTime t(c.timer, LPIDE_K_EXPL_ROWS);
         with_E<L>(c.E_rinv, [&](auto e) {
             constexpr int E = decltype(e)::value;
-            hipLaunchKernelGGL((ks_rows_inv<L, E, 0>), gr, dim3(L / E), 0, c.stream, c.A, 0);
+            t.launch((ks_rows_inv<L, E, 0>), gr, dim3(L / E), 0, c.stream, c.A, 0);
         });
     } else {
         KTime t(c.timer, LPIDE_K_EXPL_ROWS);
-        hipLaunchKernelGGL((ks_affine_noB<true>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, 0);
+        t.launch((ks_affine_noB<true>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, 0);
     }
     {
         KTime t(c.timer, LPIDE_K_SL);
         with_E<L>(c.E_sl, [&](auto e) {
             constexpr int E = decltype(e)::value;
             if (c.sl_order == 1)
-                hipLaunchKernelGGL((ks_sl<L, E, 1, FFT, MIXED>), gr, dim3(L / E), 0, c.stream, c.A);
+                t.launch((ks_sl<L, E, 1, FFT, MIXED>), gr, dim3(L / E), 0, c.stream, c.A);
             else
-                hipLaunchKernelGGL((ks_sl<L, E, 3, FFT, MIXED>), gr, dim3(L / E), 0, c.stream, c.A);
+                t.launch((ks_sl<L, E, 3, FFT, MIXED>), gr, dim3(L / E), 0, c.stream, c.A);
         });
     }
     if (c.record) hipLaunchKernelGGL(ks_store_E, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
@@ -121,7 +121,7 @@ void launch_step(const Launch& c, int kmax) {
     if (c.timer) c.timer->tag_k = 0;
     {
         KTime t(c.timer, LPIDE_K_STEP_END);
-        hipLaunchKernelGGL(ks_step_end, dim3(1, c.np), dim3(64), 0, c.stream, c.A, kmax);
+        t.launch(ks_step_end, dim3(1, c.np), dim3(64), 0, c.stream, c.A, kmax);
     }
     if (c.record) hipLaunchKernelGGL(ks_store_V, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
 }

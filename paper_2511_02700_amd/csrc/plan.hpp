@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <string>
@@ -133,13 +134,25 @@ struct Plan {
     double last_inc = 0;
 };
 
-// Event pair around one launch of kernel class cls (no-op unless timed).
+// Timing of one launch of kernel class cls.  A timed launch goes through
+// hipExtLaunchKernelGGL with a start and a stop event, which then carry the
+// dispatch's own begin and end timestamps (no marker packets between the
+// kernels of the march, so the timed sequence runs as the untimed one).
 struct KTime {
     Plan* p;
+    int cls;
     bool on;
-    size_t idx = 0;
     KTime(Plan* pl, int c);
-    ~KTime();
+    bool events(hipEvent_t* a, hipEvent_t* b);   // a fresh pair, registered for harvest_times
+
+    template <typename... P, typename... Args>
+    void launch(void (*kernel)(P...), const dim3& g, const dim3& b, uint32_t shm, hipStream_t s, Args... args) {
+        hipEvent_t e0, e1;
+        if (on && events(&e0, &e1))
+            hipExtLaunchKernelGGL(kernel, g, b, shm, s, e0, e1, 0u, static_cast<P>(args)...);
+        else
+            hipLaunchKernelGGL(kernel, g, b, shm, s, static_cast<P>(args)...);
+    }
 };
 
 // State of the adjoint march (allocated on the first lpide_adjoint call).

@@ -112,6 +112,13 @@ def counters(d, counter):
     return per
 
 
+def _bare(name):
+    """Kernel name without a leading 'void ' and without namespace qualifiers."""
+    name = name[5:] if name.startswith("void ") else name
+    head = name.split("(", 1)[0].split("<", 1)[0]
+    return name[head.rfind("::") + 2:] if "::" in head else name
+
+
 def _active_mean(vals):
     top = max(v for v, _ in vals)
     act = [v for v, _ in vals if v >= 0.05 * top]
@@ -122,7 +129,7 @@ def pmc_summary(fetch_dir, write_dir):
     fetch, write = counters(fetch_dir, "FETCH_SIZE"), counters(write_dir, "WRITE_SIZE")
     cal = {}
     for nm, per, key in (("FETCH_SIZE", fetch, "read"), ("WRITE_SIZE", write, "write")):
-        copies = [(v, g) for k, vals in per.items() if k.startswith(("k_copy", "void k_copy")) for v, g in vals]
+        copies = [(v, g) for k, vals in per.items() if _bare(k).startswith("k_copy(") for v, g in vals]
         big = max(copies, key=lambda x: x[1]) if copies else None
         if big is None or big[0] <= 0:
             raise SystemExit("no k_copy dispatch to calibrate " + nm)
