@@ -176,8 +176,9 @@ def large_conv_roofline(lp, name, steps=40):
 
 def large_solve(lp, name="nig2048_m"):
     """Whole solves of a 2048^2, 1024-step workload (the large-grid form), FP64
-    and mixed: grid-pt-steps/s, iterations per step and the mixed-vs-plain
-    price difference at 64 seeded spot pairs."""
+    and mixed on the smallest transform side, and FP64 on the power of two
+    above it: grid-pt-steps/s, iterations per step and the price differences
+    at 64 seeded spot pairs."""
     import numpy as np
     import torch
     import workloads
@@ -186,8 +187,9 @@ def large_solve(lp, name="nig2048_m"):
     out = {"workload": "%s: %dx%d on [%g, %g]^2, %d steps, alpha %g, corr %g" % (
         name, w["n"], w["n"], w["y_lo"], w["y_hi"], w["N_t"], w["model"]["alpha"], w["model"]["corr"])}
     prices = {}
-    for prec in ("fp64", "fp32conv"):
-        plan = lp.plan_from_workload(w, precision=prec)
+    for prec in ("fp64", "fp32conv", "fp64_pow2"):
+        plan = (lp.plan_from_workload(w, precision=prec) if prec != "fp64_pow2" else
+                lp.plan_from_workload(w, fft_size=1 << (out.get("L", 2) - 1).bit_length()))
         V = plan.solve()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -196,12 +198,16 @@ def large_solve(lp, name="nig2048_m"):
         dt = time.perf_counter() - t0
         info = plan.info()
         prices[prec] = plan.price(V, spots).cpu().numpy()
+        out.setdefault("L", info["L"])
         out[prec] = {"value": w["n"] ** 2 * w["N_t"] / dt, "unit": "grid-pt-steps/s", "ms": 1e3 * dt,
-                     "iters_per_step": info["total_iters"] / info["n_steps"], "radix": info["radix"]}
+                     "iters_per_step": info["total_iters"] / info["n_steps"], "radix": info["radix"],
+                     "L": info["L"]}
         del plan, V
         torch.cuda.empty_cache()
     out["mixed_vs_plain_prices_rel"] = float(np.max(np.abs(prices["fp32conv"] - prices["fp64"]) /
                                                 np.maximum(1.0, np.abs(prices["fp64"]))))
+    out["pow2_vs_default_prices_rel"] = float(np.max(np.abs(prices["fp64_pow2"] - prices["fp64"]) /
+                                                 np.maximum(1.0, np.abs(prices["fp64"]))))
     return out
 
 
@@ -284,6 +290,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 2048^2 conv roofline, the adjoint and the batched measurements")
+    ap.add_argument("--fft-size", type=int, default=0,
+                    help="transform side of the correlation (0: the smallest supported one, 2^m or 3*2^m)")
     ap.add_argument("--traffic-json", default=None,
                     help="rocprofv3 counter summary (profsum pmc --json) giving measured HBM bytes per launch; "
                          "default profiles/pmc_<workload>.json")
@@ -303,7 +311,8 @@ def main():
     w = workloads.workload(args.workload)
     n, Nt = w["n"], w["N_t"]
     other = "fp32conv" if args.precision == "fp64" else "fp64"
-    plans = {pr: lp.plan_from_workload(w, sl_order=args.sl_order, precision=pr) for pr in (args.precision, other)}
+    plans = {pr: lp.plan_from_workload(w, sl_order=args.sl_order, precision=pr, fft_size=args.fft_size)
+             for pr in (args.precision, other)}
     plan = plans[args.precision]
     mixed = args.precision == "fp32conv"
     info = plan.info()
@@ -379,6 +388,18 @@ def main():
         "mixed_vs_plain_rel": {"prices": rel_p, "deltas_abs": abs_d, "grid": rel_grid, "spots": 64,
                                "bound": 1e-6},
     }
+    pow2 = 1 << (L - 1).bit_length()
+    if pow2 != L:
+        # the same solve on the power-of-two side above L (what a radix-2 FFT would pad to)
+        p2 = lp.plan_from_workload(w, sl_order=args.sl_order, precision=args.precision, fft_size=pow2)
+        o2 = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        p2.solve(o2)
+        wall2, _ = timed_solves(p2, o2, args.steps, [])
+        result["power_of_two_side"] = {"L": pow2, "value": n * n * Nt * args.steps / wall2,
+                                       "ms_per_step": 1e3 * wall2 / args.steps,
+                                       "max_rel_diff": float((o2 - outs[args.precision]).abs().div(
+                                           outs[args.precision].abs().clamp_min(1.0)).max())}
+        del p2, o2
     if not args.no_extras:
         del plans, outs, plan
         torch.cuda.empty_cache()

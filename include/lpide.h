@@ -115,8 +115,14 @@ typedef struct {
     int32_t device;       /* HIP device ordinal */
     void*   stream;       /* hipStream_t for all of the plan's work (NULL: null stream) */
     int32_t fft_radix;    /* elements per thread of every FFT kernel of the march, i.e. the radix
-                             of their stages: 4, 8 or 16 (16 needs a transform of >= 256);
+                             of their power-of-two stages: 4, 8 or 16 (16 needs a transform of
+                             >= 256; at L = 3 * 2^m, L / fft_radix must be a multiple of 64);
                              0: a default per kernel class and transform size */
+    int32_t fft_size;     /* side L of the zero-padded correlation transform: 0 picks the
+                             smallest supported size >= n + max(-d_lo, d_hi) (the support of
+                             the folded kernel); otherwise one of the supported sizes 64, 128,
+                             256, 512, 768, 1024, 1536, 2048, 3072, 4096 that is at least that
+                             bound (LPIDE_E_PARAM if not).  Ignored without jumps. */
 } lpide_opts;
 
 /* Plan-time quantities and run statistics. */

@@ -33,7 +33,8 @@ class Payoff(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
-                ("damping", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p), ("fft_radix", C.c_int32)]
+                ("damping", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p), ("fft_radix", C.c_int32),
+                ("fft_size", C.c_int32)]
 
 
 class Info(C.Structure):

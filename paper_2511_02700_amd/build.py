@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblpide.so")
 
-SIZES = [64, 128, 256, 512, 1024, 2048, 4096]
+SIZES = [64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096]
 # (source, object, extra flags)
 UNITS = ([("lpide.hip", "lpide.o", []), ("host_plan.cpp", "host_plan.o", [])] +
          [("march_L.hip", "march_L%d.o" % L, ["-DLPIDE_L=%d" % L]) for L in SIZES])

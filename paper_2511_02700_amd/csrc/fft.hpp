@@ -1,21 +1,27 @@
 // Workgroup-level Stockham FFT for CDNA4 (gfx950), FP64 and FP32 complex data
 // (twiddles always formed in FP64; see twmul).
 //
-// One workgroup transforms one length-L sequence (L a power of two, 64..4096)
-// with T = L/E threads, E in {4, 8, 16} elements per thread held in registers
-// in the canonical layout reg[e] = element (tid + e*T); the stages are radix E,
-// plus one smaller first stage when log2 L is not a multiple of log2 E, and
-// exchange data through one LDS buffer of L complex values (plus padding).  Input and output
-// of the whole transform are in the canonical layout, so a load or store of
-// element (tid + e*T) by thread tid is coalesced, and the output registers of a
-// forward transform are the input registers of an inverse transform, which
-// lets a pointwise spectrum multiply sit between the two without touching LDS.
+// One workgroup transforms one length-L sequence, L = 2^m (64..4096) or
+// L = 3 * 2^m (768, 1536, 3072; transform sizes whose largest prime factor is
+// small, Sec. 4), with T = L/E threads, E in {4, 8, 16} elements per thread
+// held in registers in the canonical layout reg[e] = element (tid + e*T).  The
+// power-of-two part is done by radix-E stages plus one smaller first stage
+// when its log2 is not a multiple of log2 E; for L = 3 * 2^m one radix-3 stage
+// follows the first stage.  Stages exchange data through one LDS buffer of L
+// complex values (plus padding).  Input and output of the whole transform are
+// in the canonical layout, so a load or store of element (tid + e*T) by thread
+// tid is coalesced, and the output registers of a forward transform are the
+// input registers of an inverse transform, which lets a pointwise spectrum
+// multiply sit between the two without touching LDS.
 //
 // The stage (Stockham autosort, Ns = product of the radices already applied):
 //   butterfly j, k = j mod Ns: v_r = x[j + r L/R] * W_{Ns R}^{r k},
 //   R-point DFT of v, y[(j - k) R + k + r Ns] = v_r.
 // Twiddles W_N^m = exp(-+2 pi i m / N): per stage only W_N^k is stored in LDS
 // (see TwTab), its powers are formed in registers; conjugated for the inverse.
+// The power-of-two stages hold E/R butterflies per thread in registers; the
+// radix-3 stage (L/3 butterflies, not a multiple of T) reads its operands from
+// LDS and writes back to LDS, so it is never the first or the last stage.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -146,6 +152,20 @@ __device__ __forceinline__ void dft16(C* v) {
     }
 }
 
+// 3-point DFT: y0 = v0 + t, y1,2 = v0 - t/2 -+ i sin(2 pi/3) (v1 - v2) (forward;
+// signs of the i terms swap for the inverse), t = v1 + v2.
+template <bool INV, typename C>
+__device__ __forceinline__ void dft3(C* v) {
+    using Rl = typename CplxOps<C>::real;
+    const Rl s3 = Rl(0.86602540378443864676372317075293618);
+    const C t = cadd(v[1], v[2]);
+    const C d = mul_mi<INV>(csub(v[1], v[2]));
+    const C m = CplxOps<C>::make(v[0].x - Rl(0.5) * t.x, v[0].y - Rl(0.5) * t.y);
+    v[0] = cadd(v[0], t);
+    v[1] = CplxOps<C>::make(m.x + s3 * d.x, m.y + s3 * d.y);
+    v[2] = CplxOps<C>::make(m.x - s3 * d.x, m.y - s3 * d.y);
+}
+
 template <int R, bool INV, typename C>
 __device__ __forceinline__ void dft(C* v) {
     if constexpr (R == 2) dft2<INV>(v);
@@ -176,23 +196,48 @@ __device__ __forceinline__ float2 twmul(float2 v, double2 w) {
     return make_float2(a.x + b.x, a.y + b.y);
 }
 
-// Stage twiddle tables.  Stage s >= 1 is always radix E with Ns = R0 E^(s-1)
-// (R0 the radix of stage 0); its butterfly k needs W^r = exp(-+2 pi i r k / (E Ns)),
-// r = 1..E-1.  Only the base W = exp(-2 pi i k / (E Ns)), k in [0, Ns), is stored
-// (stage tables concatenated, k contiguous, so a wave reads consecutive
+// Odd factor of a transform size: 1 for powers of two, 3 for 3 * 2^m.
+constexpr int fft_odd(int L) { return (L % 3 == 0) ? 3 : 1; }
+
+// Whether the kernels run a size-L transform with E elements per thread: the
+// workgroup is a power of two (L a power of two), or whole waves (L = 3 * 2^m:
+// the block-level reductions and line scans work on whole waves), and a
+// radix-3 stage has a power-of-two stage before and after it.
+constexpr bool fft_ok(int L, int E) {
+    return (E == 4 || E == 8 || (E == 16 && L >= 256)) &&
+           (fft_odd(L) == 1 || ((L / E) % 64 == 0 && L / 3 > E));
+}
+
+// Elements per thread of the stand-alone transform kernels (8 where allowed).
+constexpr int conv_e(int L) { return fft_ok(L, 8) ? 8 : 4; }
+
+// Stage twiddle tables.  Stage 0 (radix R0, no twiddles); for L = 3 * 2^m
+// stage 1 is radix 3; the others are radix E.  Stage s >= 1 with radix R and
+// Ns = R_0 ... R_{s-1} needs, for butterfly k, W^r = exp(-+2 pi i r k / (R Ns)),
+// r = 1..R-1.  Only the base W = exp(-2 pi i k / (R Ns)), k in [0, Ns), is
+// stored (stage tables concatenated, k contiguous, so a wave reads consecutive
 // entries without bank conflicts); the powers are formed in registers with a
-// product tree of depth log2 E.
+// product tree of depth log2 R.  All members are evaluated at compile time:
+// callers pass constant stage indices.
 template <int L, int E>
 struct TwTab {
-    static constexpr int LOG = ilog2c(L);
+    static constexpr int ODD = fft_odd(L);
+    static constexpr int LOG = ilog2c(L / ODD);     // log2 of the power-of-two part
     static constexpr int LE = ilog2c(E);
     static constexpr int R0 = (LOG % LE) ? (1 << (LOG % LE)) : E;
-    static constexpr int NST = LOG / LE + (LOG % LE ? 1 : 0);
-    // Ns of stage s and the offset of its table (sum of Ns over stages 1..s-1);
-    // closed forms, so runtime uses compile to shifts (no recursion on the device)
-    static constexpr __host__ __device__ int ns(int s) { return s == 0 ? 1 : R0 << (LE * (s - 1)); }
+    static constexpr int NP2 = LOG / LE + (LOG % LE ? 1 : 0);   // power-of-two stages
+    static constexpr int NST = NP2 + (ODD == 3 ? 1 : 0);
+    static constexpr int S3 = ODD == 3 ? 1 : -1;                 // the radix-3 stage
+    static constexpr __host__ __device__ int radix(int s) { return s == 0 ? R0 : (s == S3 ? 3 : E); }
+    static constexpr __host__ __device__ int ns(int s) {
+        int v = 1;
+        for (int q = 0; q < s; ++q) v *= radix(q);
+        return v;
+    }
     static constexpr __host__ __device__ int off(int s) {
-        return s <= 1 ? 0 : R0 * ((1 << (LE * (s - 1))) - 1) / (E - 1);
+        int v = 0;
+        for (int q = 1; q < s; ++q) v += ns(q);
+        return v;
     }
     static constexpr int size = off(NST);           // entries over stages 1..NST-1
 };
@@ -205,12 +250,11 @@ template <int L, int E>
 __device__ __forceinline__ void load_twiddles(const double2* __restrict__ tw, double2* tab) {
     using TT = TwTab<L, E>;
     for (int i = threadIdx.x; i < TT::size; i += L / E) {
-        int s = 1;
 #pragma unroll
-        for (int q = 2; q < TT::NST; ++q)
-            if (i >= TT::off(q)) s = q;
-        const int k = i - TT::off(s);
-        tab[i] = tw[k * (L / (TT::ns(s) * E))];
+        for (int q = 1; q < TT::NST; ++q) {
+            if (i >= TT::off(q) && i < TT::off(q + 1))
+                tab[i] = tw[(i - TT::off(q)) * (L / (TT::ns(q) * TT::radix(q)))];
+        }
     }
 }
 
@@ -218,10 +262,8 @@ __device__ __forceinline__ void load_twiddles(const double2* __restrict__ tw, do
 template <int R>
 __device__ __forceinline__ void twiddle_powers(double2 w1, double2 (&w)[R]) {
     w[1] = w1;
-    if constexpr (R > 2) {
-        w[2] = cmul(w1, w1);
-        w[3] = cmul(w[2], w1);
-    }
+    if constexpr (R > 2) w[2] = cmul(w1, w1);
+    if constexpr (R > 3) w[3] = cmul(w[2], w1);
     if constexpr (R > 4) {
         w[4] = cmul(w[2], w[2]);
         w[5] = cmul(w[4], w1);
@@ -235,11 +277,12 @@ __device__ __forceinline__ void twiddle_powers(double2 w1, double2 (&w)[R]) {
     }
 }
 
-// One Stockham stage.  Preconditions: if !FIRST, the previous stage's LDS writes
-// are complete and visible (barrier).  Postcondition: if !LAST, this stage's
-// LDS writes are complete and visible; if LAST, the result is in reg.
-template <int L, int E, int R, bool INV, bool FIRST, bool LAST, typename C>
-__device__ __forceinline__ void fft_stage(C (&reg)[E], C* lds, int Ns, int toff, const double2* tab) {
+// One power-of-two Stockham stage (radix R, NS = product of the earlier
+// radices).  Preconditions: if !FIRST, the previous stage's LDS writes are
+// complete and visible (barrier).  Postcondition: if !LAST, this stage's LDS
+// writes are complete and visible; if LAST, the result is in reg.
+template <int L, int E, int R, int NS, bool INV, bool FIRST, bool LAST, typename C>
+__device__ __forceinline__ void fft_stage(C (&reg)[E], C* lds, int toff, const double2* tab) {
     constexpr int T = L / E;
     constexpr int NB = E / R;          // butterflies per thread
     const int tid = threadIdx.x;
@@ -251,12 +294,12 @@ __device__ __forceinline__ void fft_stage(C (&reg)[E], C* lds, int Ns, int toff,
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = tid + b * T;
-        const int k = j & (Ns - 1);
+        const int k = j % NS;
         C v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = reg[b + r * NB];
         if constexpr (!FIRST) {
-            static_assert(R == E, "stages after the first are radix E");
+            static_assert(R == E, "power-of-two stages after the first are radix E");
             const double2 t = tab[toff + k];
             double2 w[R];
             twiddle_powers<R>(make_double2(t.x, INV ? -t.y : t.y), w);
@@ -270,17 +313,54 @@ __device__ __forceinline__ void fft_stage(C (&reg)[E], C* lds, int Ns, int toff,
         } else {
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lds_slot(base + r * Ns)] = v[r];
+            for (int r = 0; r < R; ++r) lds[lds_slot(base + r * NS)] = v[r];
         }
     }
     if constexpr (!LAST) __syncthreads();
 }
 
+// The radix-3 stage, LDS to LDS (same pre- and postcondition as a middle
+// stage): L/3 butterflies, thread tid takes j = tid, tid + T, ...
+template <int L, int E, int NS, bool INV, typename C>
+__device__ __forceinline__ void fft_stage3(C* lds, int toff, const double2* tab) {
+    constexpr int T = L / E;
+    constexpr int NBF = L / 3;
+    constexpr int MB = (NBF + T - 1) / T;
+    const int tid = threadIdx.x;
+    C v[MB][3];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const int j = tid + b * T;
+        if (j < NBF) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) v[b][r] = lds[lds_slot(j + r * NBF)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const int j = tid + b * T;
+        if (j < NBF) {
+            const int k = j % NS;
+            const double2 t = tab[toff + k];
+            const double2 w1 = make_double2(t.x, INV ? -t.y : t.y);
+            v[b][1] = twmul(v[b][1], w1);
+            v[b][2] = twmul(v[b][2], cmul(w1, w1));
+            dft3<INV>(v[b]);
+            const int base = (j - k) * 3 + k;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) lds[lds_slot(base + r * NS)] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
 template <int L, int E, bool INV, int S, int NST, typename C>
 __device__ __forceinline__ void fft_stages(C (&reg)[E], C* lds, const double2* tab) {
     using TT = TwTab<L, E>;
-    constexpr int R = S == 0 ? TT::R0 : E;
-    fft_stage<L, E, R, INV, S == 0, S == NST - 1>(reg, lds, TT::ns(S), S == 0 ? 0 : TT::off(S), tab);
+    constexpr int R = TT::radix(S), NS = TT::ns(S), OFF = TT::off(S);
+    if constexpr (S == TT::S3) fft_stage3<L, E, NS, INV>(lds, OFF, tab);
+    else fft_stage<L, E, R, NS, INV, S == 0, S == NST - 1>(reg, lds, OFF, tab);
     if constexpr (S + 1 < NST) fft_stages<L, E, INV, S + 1, NST>(reg, lds, tab);
 }
 
@@ -292,7 +372,8 @@ __device__ __forceinline__ void fft_stages(C (&reg)[E], C* lds, const double2* t
 template <int L, int E, bool INV, typename C>
 __device__ __forceinline__ void fft_block(C (&reg)[E], C* lds, const double2* tab) {
     using TT = TwTab<L, E>;
-    static_assert((1 << TT::LOG) == L && L >= 64 && (E == 4 || E == 8 || E == 16), "L a power of two >= 64");
+    static_assert((1 << TT::LOG) * TT::ODD == L && L >= 64 && fft_ok(L, E), "unsupported transform size");
+    static_assert(TT::ODD == 1 || TT::NP2 >= 2, "the radix-3 stage sits between two power-of-two stages");
     fft_stages<L, E, INV, 0, TT::NST>(reg, lds, tab);
 }
 

@@ -372,12 +372,23 @@ bool build_host_plan(const lpide_grid& g, const lpide_levy& lv, HostPlan& hp, st
                     int d2 = bb - N + jlo + j - hp.dlo;
                     hp.kern[size_t(d1) * KW + d2] += s[j] * tmp[size_t(d1) * W2 + bb];
                 }
-        int need = hp.n + std::max(-hp.dlo, hp.dhi);
-        hp.L = 64;   // smallest transform the workgroup FFT supports
-        while (hp.L < need) hp.L *= 2;
-        if (hp.L > 4096) { err = "FFT side above 4096: n + N_z + 1 must not exceed 4096"; return false; }
+        hp.L_need = hp.n + std::max(-hp.dlo, hp.dhi);
+        hp.L = fft_size_at_least(hp.L_need);
+        if (hp.L == 0) { err = "FFT side above 4096: n + N_z + 1 must not exceed 4096"; return false; }
     }
     return true;
+}
+
+bool fft_size_supported(int L) {
+    for (int v : kFftSizes)
+        if (v == L) return true;
+    return false;
+}
+
+int fft_size_at_least(int need) {
+    for (int v : kFftSizes)
+        if (v >= need) return v;
+    return 0;
 }
 
 // ---------------------------------------------------------------------------

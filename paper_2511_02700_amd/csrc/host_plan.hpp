@@ -38,6 +38,7 @@ struct HostPlan {
     std::vector<double> omega;   // (2 N_z)^2, omega[(l1+N_z)*2N_z + (l2+N_z)]
     // folded correlation kernel K = omega (*) (s x s) on offsets [dlo, dhi]^2
     int    dlo = 0, dhi = -1, L = 0;
+    int    L_need = 0;           // n + max(-dlo, dhi): the least transform side without wrap-around
     std::vector<double> kern;    // (dhi-dlo+1)^2, row-major in d1
 };
 
@@ -52,6 +53,14 @@ double z_star(const Nts& p, double cut);
 
 // Builds the discretization (grid + integral part + folded kernel); no device work.
 bool build_host_plan(const lpide_grid& g, const lpide_levy& lv, HostPlan& hp, std::string& err);
+
+// Transform sides of the workgroup FFT: powers of two and 3 * 2^m (largest
+// prime factor at most 3; Sec. 4 asks for transform sizes with small prime
+// factors), ascending.
+constexpr int kFftSizes[] = {64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096};
+bool fft_size_supported(int L);
+// The smallest supported side >= need, or 0 when need exceeds the largest.
+int fft_size_at_least(int need);
 
 // Cell-averaged initial grid (Sec. 3.2.3), row-major n x n.
 bool initial_values(const HostPlan& hp, const lpide_payoff& pay, std::vector<double>& v0, std::string& err);

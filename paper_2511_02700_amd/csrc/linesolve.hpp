@@ -20,15 +20,16 @@ constexpr int LINE_MM = 32;   // max chunk length held in registers
 
 // Exclusive scan of affine maps y_out = G y_in + B over the chunks t = 0..P-1 of
 // a line (in reverse chunk order if REV).  Chunk t of line g is held by the
-// lane that sits dl lanes after the holder of chunk t-1 inside a wave, and a
-// wave holds CW = min(P, 64/dl) consecutive chunks of each of its lines.  The
-// scan runs inside each wave with lane shuffles (log2 CW rounds), then the
-// waves of a line combine their totals through LDS (wtot: lines x P/CW
-// double2).  All threads of the block must call it.  Returns the carry-in
+// lane that sits dl lanes after the holder of chunk t-1 inside a wave; runs of
+// CW consecutive chunks, CW the largest power of two dividing P that is at most
+// 64/dl, sit inside one wave (a line's first chunk sits at a lane that is a
+// multiple of CW dl).  The scan runs inside each run with lane shuffles
+// (log2 CW rounds), then the runs of a line combine their totals through LDS
+// (wtot: lines x P/CW double2).  All threads of the block must call it.  Returns the carry-in
 // (M_{t-1} o ... o M_0)(0) (reverse order if REV).
 template <bool REV>
 __device__ __forceinline__ double scan_affine(double G, double B, int g, int t, int P, int dl, double2* wtot) {
-    const int CW = min(P, 64 / dl);
+    const int CW = min(P & -P, 64 / dl);
     const int NW = P / CW;
     const int pos = t % CW;
     const int tl = REV ? CW - 1 - pos : pos;           // position in scan order inside the wave run

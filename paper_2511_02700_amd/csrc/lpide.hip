@@ -251,12 +251,30 @@ MarchArgs march_args(const Plan* p) {
 // Default radix schedule.  From measurements on MI355X (each kernel alone):
 // the column pass gains from radix 16 at L >= 1024; the row c2r, line-row and
 // SL kernels from radix 4 up to L = 1024 and radix 8 above.
+// Preferred E per kernel class, from single-kernel timings at n = 512 (L = 768,
+// 1024) and n = 2048 (L = 3072, 4096); lowered to the next supported value
+// where the size does not allow it (L = 3 * 2^m needs whole waves: L / E a
+// multiple of 64).
+static int supported_e(int L, int E) {
+    while (E > 4 && !e_supported(L, E)) E /= 2;
+    return E;
+}
+
 Schedule default_schedule(int L) {
     Schedule s;
-    s.cols = L >= 1024 ? 16 : 8;
-    s.rinv = L <= 1024 ? 4 : 8;
-    s.lrows = L <= 1024 ? 4 : 8;
-    s.sl = L <= 1024 ? 4 : 8;
+    if (fft_odd(L) == 3) {
+        // the radix-3 stage favours many threads per transform in the FFT-heavy
+        // passes; the axis-2 line solves want short chunks (E = 16 at 3072)
+        s.cols = 4;
+        s.rinv = 4;
+        s.lrows = supported_e(L, L >= 3072 ? 16 : 8);
+        s.sl = 4;
+        return s;
+    }
+    s.cols = supported_e(L, L >= 1024 ? 16 : 8);
+    s.rinv = supported_e(L, L <= 1024 ? 4 : 8);
+    s.lrows = supported_e(L, L <= 1024 ? 4 : 8);
+    s.sl = supported_e(L, L <= 1024 ? 4 : 8);
     return s;
 }
 
@@ -279,8 +297,11 @@ void apply_schedule(Launch& c, const Schedule& s) {
         case 128: CALL(128); break;                                                     \
         case 256: CALL(256); break;                                                     \
         case 512: CALL(512); break;                                                     \
+        case 768: CALL(768); break;                                                     \
         case 1024: CALL(1024); break;                                                   \
+        case 1536: CALL(1536); break;                                                   \
         case 2048: CALL(2048); break;                                                   \
+        case 3072: CALL(3072); break;                                                   \
         case 4096: CALL(4096); break;                                                   \
         default: return fail(LPIDE_E_PARAM, "unsupported transform size");              \
     }
@@ -775,7 +796,7 @@ int model_quantities(const Plan* p, const double* x, std::vector<double>& out) {
     HostPlan hp;
     std::string err;
     if (!build_host_plan(g, lv, hp, err)) return fail(LPIDE_E_PARAM, "model quantities: " + err);
-    if (hp.M2 != p->hp.M2 || hp.L != p->L) return fail(LPIDE_E_PARAM, "structure changed under the perturbation");
+    if (hp.M2 != p->hp.M2 || hp.L_need > p->L) return fail(LPIDE_E_PARAM, "structure changed under the perturbation");
     out.assign(6 + hp.omega.size(), 0.0);
     out[0] = hp.a[0];
     out[1] = hp.a[1];
@@ -1127,6 +1148,15 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     p->stream = static_cast<hipStream_t>(o.stream);
     p->jumps = p->hp.nts.jumps;
     p->mixed = p->jumps && o.precision == LPIDE_FP32_CONV;
+    if (p->jumps && o.fft_size != 0) {
+        if (!fft_size_supported(o.fft_size) || o.fft_size < p->hp.L_need) {
+            const std::string msg = "fft_size " + std::to_string(o.fft_size) +
+                                    " is not a supported transform side of at least " + std::to_string(p->hp.L_need);
+            delete p;
+            return fail(LPIDE_E_PARAM, msg);
+        }
+        p->hp.L = o.fft_size;
+    }
     p->L = p->hp.L;
     int rc = LPIDE_OK;
     auto bail = [&](int code) { destroy(p); return code; };
@@ -1197,7 +1227,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
         const int L = p->L;
         std::vector<double2> tw(L);
         for (int q = 0; q < L; ++q) {
-            // exp(-2 pi i q / L) with the angle reduced to the first octant for accuracy
+            // exp(-2 pi i q / L), evaluated in long double
             const long double ang = -2.0L * 3.14159265358979323846264338327950288L * q / L;
             tw[q] = make_double2((double)cosl(ang), (double)sinl(ang));
         }
@@ -1239,7 +1269,9 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
         }
     }
     p->sched = o.fft_radix ? uniform_schedule(o.fft_radix) : default_schedule(p->Lr);
-    if (!schedule_ok(p->Lr, p->sched)) return bail(fail(LPIDE_E_PARAM, "fft_radix 16 needs a transform of at least 256"));
+    if (!schedule_ok(p->Lr, p->sched))
+        return bail(fail(LPIDE_E_PARAM, "fft_radix " + std::to_string(o.fft_radix) + " is not supported at transform side " +
+                                            std::to_string(p->Lr)));
     if ((rc = make_group(std::vector<Plan*>{p}, p->stream, &p->solo))) return bail(rc);
     *out = p;
     return LPIDE_OK;

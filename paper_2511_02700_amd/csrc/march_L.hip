@@ -18,24 +18,24 @@ namespace {
 template <int L>
 void launch_conv(Plan* p, const double* Y, double* out) {
     const int n = p->hp.n, np = (n + 1) / 2;
-    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, p->stream, Y, n, n, n, p->X, n, p->tw);
-    hipLaunchKernelGGL((k_cols<L, 0>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, p->X, n, n, n, p->spec,
+    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / conv_e(L)), 0, p->stream, Y, n, n, n, p->X, n, p->tw);
+    hipLaunchKernelGGL((k_cols<L, 0>), dim3(L / 2 + 1), dim3(L / conv_e(L)), 0, p->stream, p->X, n, n, n, p->spec,
                        (double2*)nullptr, 0.0, p->tw);
-    hipLaunchKernelGGL((k_rows_inv<L>), dim3(np), dim3(L / 8), 0, p->stream, p->X, n, n, out, p->tw);
+    hipLaunchKernelGGL((k_rows_inv<L>), dim3(np), dim3(L / conv_e(L)), 0, p->stream, p->X, n, n, out, p->tw);
 }
 
 template <int L>
 void launch_spectrum(Plan* p, const double* G, double2* Xfull) {
     const double scale = 1.0 / (double(L) * double(L));
-    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(L / 2), dim3(L / 8), 0, p->stream, G, L, L, L, Xfull, L, p->tw);
-    hipLaunchKernelGGL((k_cols<L, 1>), dim3(L / 2 + 1), dim3(L / 8), 0, p->stream, Xfull, L, L, L,
+    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(L / 2), dim3(L / conv_e(L)), 0, p->stream, G, L, L, L, Xfull, L, p->tw);
+    hipLaunchKernelGGL((k_cols<L, 1>), dim3(L / 2 + 1), dim3(L / conv_e(L)), 0, p->stream, Xfull, L, L, L,
                        (const double2*)nullptr, p->spec, scale, p->tw);
 }
 
 template <int L>
 void launch_rows_fwd(Plan* p, const double* Y, hipStream_t s) {
     const int n = p->hp.n;
-    hipLaunchKernelGGL((k_rows_fwd<L>), dim3((n + 1) / 2), dim3(L / 8), 0, s, Y, n, n, n, p->X, n, p->tw);
+    hipLaunchKernelGGL((k_rows_fwd<L>), dim3((n + 1) / 2), dim3(L / conv_e(L)), 0, s, Y, n, n, n, p->X, n, p->tw);
 }
 
 template <int L, bool FFT, bool MIXED>
@@ -248,15 +248,15 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
         const int np = (n + 1) / 2;
         // the row transform of Y = V^{s+1} is the V transform of reverse step s + 1 when it had one
         if (a->xb_is_v) std::swap(a->XB, a->XD);
-        else hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, Y, n, n, n, a->XB, n, p->tw);
-        hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, a->lam, n, n, n, a->XA, n, p->tw);
+        else hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / conv_e(L)), 0, c.stream, Y, n, n, n, a->XB, n, p->tw);
+        hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / conv_e(L)), 0, c.stream, a->lam, n, n, n, a->XA, n, p->tw);
         a->xb_is_v = false;
         if (c2 != 0.0) {
-            hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, a->mu, n, n, n, a->XC, n, p->tw);
-            hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / 8), 0, c.stream, V, n, n, n, a->XD, n, p->tw);
+            hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / conv_e(L)), 0, c.stream, a->mu, n, n, n, a->XC, n, p->tw);
+            hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / conv_e(L)), 0, c.stream, V, n, n, n, a->XD, n, p->tw);
             a->xb_is_v = true;
         }
-        hipLaunchKernelGGL((ks_adj_spec<L>), dim3(L / 2 + 1), dim3(L / 8), 0, c.stream, a->XA, a->XB, a->XC, a->XD, n,
+        hipLaunchKernelGGL((ks_adj_spec<L>), dim3(L / 2 + 1), dim3(L / conv_e(L)), 0, c.stream, a->XA, a->XB, a->XC, a->XD, n,
                            c1, c2, a->S, p->tw);
     }
     if (sd.theta >= 1.0)
@@ -270,9 +270,9 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
 template <int L>
 void launch_adj_kernel_grad(Plan* p, hipStream_t s) {
     Adjoint* a = p->adj;
-    hipLaunchKernelGGL((k_cols<L, 2>), dim3(L / 2 + 1), dim3(L / 8), 0, s, a->S, L, L, L, (const double2*)nullptr,
+    hipLaunchKernelGGL((k_cols<L, 2>), dim3(L / 2 + 1), dim3(L / conv_e(L)), 0, s, a->S, L, L, L, (const double2*)nullptr,
                        (double2*)nullptr, 0.0, p->tw);
-    hipLaunchKernelGGL((k_rows_inv<L>), dim3(L / 2), dim3(L / 8), 0, s, (const double2*)a->S, L, L, a->G, p->tw);
+    hipLaunchKernelGGL((k_rows_inv<L>), dim3(L / 2), dim3(L / conv_e(L)), 0, s, (const double2*)a->S, L, L, a->G, p->tw);
 }
 
 }  // namespace

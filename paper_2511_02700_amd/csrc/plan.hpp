@@ -187,18 +187,22 @@ struct Adjoint {
     std::vector<double> jac;        // 8 x (6 + (2 N_z)^2)
 };
 
-// Radix schedules instantiated per transform size: E = 4 and 8 always, E = 16
-// from L = 256 on (at least 16 threads per transform).
-constexpr bool e_supported(int L, int E) { return E == 4 || E == 8 || (E == 16 && L >= 256); }
+// Radix schedules instantiated per transform size: the E for which the
+// workgroup FFT runs at L (fft_ok: E = 4 and 8 for powers of two, E = 16 from
+// L = 256 on; at L = 3 * 2^m only E with L / E a multiple of 64).
+constexpr bool e_supported(int L, int E) { return fft_ok(L, E); }
 
-// Call f(std::integral_constant<int, E>) for the runtime E of a kernel class.
+// Call f(std::integral_constant<int, E>) for the runtime E of a kernel class
+// (E must be supported at L; E = 4 always is).
 template <int L, typename F>
 void with_E(int E, F&& f) {
-    if (E == 4) f(std::integral_constant<int, 4>{});
-    else if constexpr (L >= 256) {
-        if (E == 16) f(std::integral_constant<int, 16>{});
-        else f(std::integral_constant<int, 8>{});
-    } else f(std::integral_constant<int, 8>{});
+    if constexpr (fft_ok(L, 16)) {
+        if (E == 16) return f(std::integral_constant<int, 16>{});
+    }
+    if constexpr (fft_ok(L, 8)) {
+        if (E == 8) return f(std::integral_constant<int, 8>{});
+    }
+    f(std::integral_constant<int, 4>{});
 }
 
 double bits_d(unsigned long long b);
@@ -223,8 +227,11 @@ extern template struct PerL<64>;
 extern template struct PerL<128>;
 extern template struct PerL<256>;
 extern template struct PerL<512>;
+extern template struct PerL<768>;
 extern template struct PerL<1024>;
+extern template struct PerL<1536>;
 extern template struct PerL<2048>;
+extern template struct PerL<3072>;
 extern template struct PerL<4096>;
 
 }  // namespace detail

@@ -297,7 +297,7 @@ __device__ __forceinline__ void rows_fwd_store(C (&reg)[E], C* lds, const double
     for (int e = 0; e < E; ++e) lds[tid + e * T] = reg[e];
     __syncthreads();
     for (int kk = tid; kk <= L / 2; kk += T) {
-        const C z = lds[kk], w = lds[(L - kk) & (L - 1)];
+        const C z = lds[kk], w = lds[kk == 0 ? 0 : L - kk];
         C* xk = X + (size_t)kk * n;
         xk[ra] = CplxOps<C>::make(Rl(0.5) * (z.x + w.x), Rl(0.5) * (z.y - w.y));
         if (hasb) xk[ra + 1] = CplxOps<C>::make(Rl(0.5) * (z.y + w.y), Rl(-0.5) * (z.x - w.x));
@@ -432,8 +432,8 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, gridDim.x);
     if (p >= np) return;
-    // union: row buffer 2 (n + PR + 1) doubles | scan totals | FFT exchange buffer
-    __shared__ double2 lds[L + L / 16 + 2];
+    // union: row buffer 2 (n + PR + 1) doubles (n <= L) | scan totals | FFT exchange buffer
+    __shared__ double2 lds[L + (PR > L / 16 ? PR : L / 16) + 2];
     __shared__ double2 tw4[FFT ? tw_slots<L, E>() : 1];
     // Up to L = 1024 the line factors are staged in LDS and the iterate values
     // are fetched into registers at the start, so that every global read of the
@@ -826,7 +826,7 @@ __global__ __launch_bounds__(256) void ks_adj_accum(const MarchArgs* __restrict_
 // After the march, the inverse 2D transform of S / L^2 is sum_m lam_m Y_{m+d}
 // summed over the steps with their weights: the gradient of the loss with
 // respect to the folded kernel K_d.
-template <int L, int E = 8>
+template <int L, int E = conv_e(L)>
 __global__ __launch_bounds__(L / E) void ks_adj_spec(const double2* __restrict__ XA, const double2* __restrict__ XB,
                                                      const double2* __restrict__ XC, const double2* __restrict__ XD,
                                                      int n, double c1, double c2, double2* __restrict__ S,

@@ -55,20 +55,28 @@ def _oracle_problem(w, sl_order=3, in_order=3, payoff=None, sigma_bs=None, no_ju
 # --------------------------------------------------------------------------- #
 # FFT correlation alone
 # --------------------------------------------------------------------------- #
-@pytest.mark.parametrize("n,half,P", [(16, 1.5, 3), (50, 2.0, 3), (64, 3.0, 1), (64, 3.0, 3), (130, 2.5, 3),
-                                      (257, 3.0, 3)])
-def test_apply_B_matches_oracle(lp, n, half, P):
+@pytest.mark.parametrize("n,half,P,L", [(16, 1.5, 3, 0), (50, 2.0, 3, 0), (64, 3.0, 1, 0), (64, 3.0, 3, 0),
+                                        (130, 2.5, 3, 0), (257, 3.0, 3, 0), (450, 3.0, 3, 0), (700, 3.0, 3, 0),
+                                        (130, 2.5, 3, 768), (257, 3.0, 3, 1536), (257, 3.0, 1, 3072),
+                                        (450, 3.0, 3, 1024)])
+def test_apply_B_matches_oracle(lp, n, half, P, L):
     """(B v) by the three FFT passes vs the oracle's direct sum (n <= 64) or
-    scipy FFT; ragged sizes (not multiples of any tile) included."""
+    scipy FFT; ragged sizes (not multiples of any tile) included.  L = 0 takes
+    the smallest transform side (768 at n = 450 and 1536 at n = 700, both of
+    the form 3 * 2^m); other L force the side, a mixed-radix one far above the
+    kernel's support or the power of two above 768."""
     import torch
-    _note("apply_B n=%d half=%g P=%d" % (n, half, P))
+    _note("apply_B n=%d half=%g P=%d L=%d" % (n, half, P, L))
     w = workloads.workload("nig64", n=n, y_lo=-half, y_hi=half)
-    plan = lp.plan_from_workload(w, in_order=P)
+    plan = lp.plan_from_workload(w, in_order=P, fft_size=L)
     v = workloads.random_grid(n, seed=n + P)
     bv = plan.apply_B(torch.from_numpy(v).cuda()).cpu().numpy()
     prob = _oracle_problem(w, in_order=P)
     info = plan.info()
     assert info["N_z"] == prob.disc["N_z"]
+    assert L == 0 or info["L"] == L
+    if L == 0 and n in (450, 700):
+        assert info["L"] == {450: 768, 700: 1536}[n]
     ref = scheme.apply_B(v, prob.disc["W"], prob.disc["N_z"], P, "direct" if n <= 64 else "fft")
     err = np.max(np.abs(bv - ref)) / np.max(np.abs(ref))
     assert err < 1e-12, err
@@ -205,20 +213,45 @@ def test_non_convergence_is_reported(lp):
     assert ei.value.code == -2
 
 
-@pytest.mark.parametrize("radix", [4, 16])
-def test_radix_schedules(lp, radix):
-    """The march with another FFT radix schedule (elements per thread) gives
-    the same fixed points: fv512 after 8 step-list entries (L = 1024), FP64
-    against the oracle and mixed against the default schedule."""
-    _note("radix %d fv512" % radix)
+_FV512_ORACLE = {}
+
+
+def _fv512_oracle_8():
+    """The oracle's fv512 state after 8 step-list entries (computed once)."""
+    if "V" not in _FV512_ORACLE:
+        w = workloads.workload("fv512")
+        _FV512_ORACLE["V"] = scheme.solve(_oracle_problem(w), tol=1e-14, inner="bicgstab", n_steps=8)[0]
+    return _FV512_ORACLE["V"]
+
+
+@pytest.mark.parametrize("L,radix", [(1024, 4), (1024, 16), (768, 4), (1536, 8), (3072, 16), (3072, 4)])
+def test_radix_schedules(lp, L, radix):
+    """The march with other transform sides and FFT radix schedules (elements
+    per thread) reaches the same fixed points: fv512 after 8 step-list entries
+    (its own side is 768), FP64 against the oracle within 1e-10 and mixed
+    within 1e-6."""
+    _note("radix %d, L %d, fv512" % (radix, L))
     w = workloads.workload("fv512")
-    plan = lp.plan_from_workload(w, fft_radix=radix)
-    assert plan.info()["radix"] == [radix] * 4
+    plan = lp.plan_from_workload(w, fft_radix=radix, fft_size=L)
+    info = plan.info()
+    assert info["radix"] == [radix] * 4 and info["L"] == L
     Vg = plan.solve_steps(8).cpu().numpy()
-    Vo, _ = scheme.solve(_oracle_problem(w), tol=1e-14, inner="bicgstab", n_steps=8)
+    Vo = _fv512_oracle_8()
     assert _rel(Vg, Vo) < 1e-10
-    vm = lp.plan_from_workload(w, precision="fp32conv", fft_radix=radix).solve_steps(8).cpu().numpy()
+    vm = lp.plan_from_workload(w, precision="fp32conv", fft_radix=radix, fft_size=L).solve_steps(8).cpu().numpy()
     assert _rel(vm, Vo) < 1e-6
+
+
+def test_fft_size_validation(lp):
+    """Unsupported or too small transform sides and radices a side does not
+    allow are refused at plan time."""
+    w = workloads.workload("nig64", n=130, y_lo=-2.5, y_hi=2.5)
+    for bad in (1000, 128, 8192):
+        with pytest.raises(lp.LpideError):
+            lp.plan_from_workload(w, fft_size=bad)
+    with pytest.raises(lp.LpideError):
+        lp.plan_from_workload(w, fft_size=768, fft_radix=16)       # 768 / 16 = 48 threads: not whole waves
+    assert lp.plan_from_workload(w, fft_size=768, fft_radix=4).info()["L"] == 768
 
 
 def test_radix_4_small_transform(lp):
