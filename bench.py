@@ -154,15 +154,17 @@ def cpu_baseline(w, steps):
 
 
 def large_conv_roofline(lp, name, steps=40):
-    """Column pass of the correlation at 2048^2 (L = 4096), where the working
-    set (spectrum 134 MB + intermediate 67 MB) no longer fits in the caches:
-    HIP-event mean over the working launches of the first `steps` entries of
-    the step list, FP64 and mixed."""
+    """Column pass of the correlation at 2048^2 (automatic side L = 3072; also
+    FP64 at L = 4096), where the working set (spectrum + intermediate, 176 MB at
+    3072, 201 MB at 4096, with the grids beside them) no longer stays in the
+    caches: HIP-event mean over the working launches of the first `steps`
+    entries of the step list, FP64 and mixed."""
     import workloads
     w = workloads.workload(name)
     out = {"workload": "%s, first %d step-list entries" % (name, steps)}
-    for prec in ("fp64", "fp32conv"):
-        plan = lp.plan_from_workload(w, precision=prec)
+    for prec in ("fp64", "fp32conv", "fp64_pow2"):
+        plan = (lp.plan_from_workload(w, precision=prec) if prec != "fp64_pow2" else
+                lp.plan_from_workload(w, fft_size=1 << (out["fp64"]["L"] - 1).bit_length()))
         plan.solve_steps(4)
         plan.set_timing(["cols"])
         plan.solve_steps(steps)
@@ -170,6 +172,7 @@ def large_conv_roofline(lp, name, steps=40):
         plan.set_timing([])
         info = plan.info()
         out[prec] = roofline("cols", w["n"], info["L"], prec == "fp32conv", la, ms, radix=info["radix"])
+        out[prec]["L"] = info["L"]
         del plan
     return out
 
@@ -388,17 +391,21 @@ def main():
         "mixed_vs_plain_rel": {"prices": rel_p, "deltas_abs": abs_d, "grid": rel_grid, "spots": 64,
                                "bound": 1e-6},
     }
-    pow2 = 1 << (L - 1).bit_length()
-    if pow2 != L:
-        # the same solve on the power-of-two side above L (what a radix-2 FFT would pad to)
-        p2 = lp.plan_from_workload(w, sl_order=args.sl_order, precision=args.precision, fft_size=pow2)
+    # the same solve on the other candidate transform side: 3L/4 for a power of
+    # two L (when it still covers the kernel's support), else the power of two above
+    alt = 3 * L // 4 if L & (L - 1) == 0 else 1 << (L - 1).bit_length()
+    try:
+        p2 = lp.plan_from_workload(w, sl_order=args.sl_order, precision=args.precision, fft_size=alt)
+    except lp.LpideError:
+        p2 = None
+    if p2 is not None:
         o2 = torch.empty((n, n), dtype=torch.float64, device="cuda")
         p2.solve(o2)
         wall2, _ = timed_solves(p2, o2, args.steps, [])
-        result["power_of_two_side"] = {"L": pow2, "value": n * n * Nt * args.steps / wall2,
-                                       "ms_per_step": 1e3 * wall2 / args.steps,
-                                       "max_rel_diff": float((o2 - outs[args.precision]).abs().div(
-                                           outs[args.precision].abs().clamp_min(1.0)).max())}
+        result["other_side"] = {"L": alt, "radix": p2.info()["radix"], "value": n * n * Nt * args.steps / wall2,
+                                "ms_per_step": 1e3 * wall2 / args.steps,
+                                "max_rel_diff": float((o2 - outs[args.precision]).abs().div(
+                                    outs[args.precision].abs().clamp_min(1.0)).max())}
         del p2, o2
     if not args.no_extras:
         del plans, outs, plan

@@ -119,10 +119,11 @@ typedef struct {
                              >= 256; at L = 3 * 2^m, L / fft_radix must be a multiple of 64);
                              0: a default per kernel class and transform size */
     int32_t fft_size;     /* side L of the zero-padded correlation transform: 0 picks the
-                             smallest supported size >= n + max(-d_lo, d_hi) (the support of
-                             the folded kernel); otherwise one of the supported sizes 64, 128,
-                             256, 512, 768, 1024, 1536, 2048, 3072, 4096 that is at least that
-                             bound (LPIDE_E_PARAM if not).  Ignored without jumps. */
+                             smallest of 64, 128, 256, 512, 1024, 1536, 2048, 3072, 4096 that
+                             is >= n + max(-d_lo, d_hi) (the support of the folded kernel);
+                             otherwise one of the supported sizes 64, 128, 256, 512, 768, 1024,
+                             1536, 2048, 3072, 4096 that is at least that bound (LPIDE_E_PARAM
+                             if not).  Ignored without jumps. */
 } lpide_opts;
 
 /* Plan-time quantities and run statistics. */

@@ -386,7 +386,7 @@ bool fft_size_supported(int L) {
 }
 
 int fft_size_at_least(int need) {
-    for (int v : kFftSizes)
+    for (int v : kFftAutoSizes)
         if (v >= need) return v;
     return 0;
 }

@@ -59,7 +59,11 @@ bool build_host_plan(const lpide_grid& g, const lpide_levy& lv, HostPlan& hp, st
 // factors), ascending.
 constexpr int kFftSizes[] = {64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096};
 bool fft_size_supported(int L);
-// The smallest supported side >= need, or 0 when need exceeds the largest.
+// Sides the automatic choice takes: all but 768, which allows E = 4 only and
+// measured 3% slower than 1024 for whole solves at n = 512 (1536 and 3072 beat
+// 2048 and 4096 by 8% and 10% at n = 1024 and 2048).
+constexpr int kFftAutoSizes[] = {64, 128, 256, 512, 1024, 1536, 2048, 3072, 4096};
+// The smallest automatic side >= need, or 0 when need exceeds the largest.
 int fft_size_at_least(int need);
 
 // Cell-averaged initial grid (Sec. 3.2.3), row-major n x n.

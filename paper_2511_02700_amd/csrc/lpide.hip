@@ -263,9 +263,10 @@ static int supported_e(int L, int E) {
 Schedule default_schedule(int L) {
     Schedule s;
     if (fft_odd(L) == 3) {
-        // the radix-3 stage favours many threads per transform in the FFT-heavy
-        // passes; the axis-2 line solves want short chunks (E = 16 at 3072)
-        s.cols = 4;
+        // the radix-3 stage favours many threads per transform in the row
+        // passes; the column pass takes E = 8 at 1536 and 4 at 3072; the axis-2
+        // line solves want short chunks (E = 16 at 3072)
+        s.cols = L == 1536 ? 8 : 4;
         s.rinv = 4;
         s.lrows = supported_e(L, L >= 3072 ? 16 : 8);
         s.sl = 4;

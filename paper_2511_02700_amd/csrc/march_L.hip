@@ -62,8 +62,13 @@ void launch_iteration(const Launch& c, int k) {
     }
     {
         KTime t(c.timer, LPIDE_K_LINE_COLS);
-        t.launch(ks_line_cols<4>, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
-                           c.stream, c.A, k);
+        // blocks of 4 P_cols threads: bounds of 256 where they fit (no register cap of 128)
+        if (4 * c.P_cols <= 256)
+            t.launch(ks_line_cols<4, 256>, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
+                     c.stream, c.A, k);
+        else
+            t.launch(ks_line_cols<4, 1024>, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
+                     c.stream, c.A, k);
     }
     KTime t(c.timer, LPIDE_K_LINE_ROWS);
     with_E<L>(c.E_lrows, [&](auto e) {
@@ -153,8 +158,12 @@ void launch_adj_iteration(const Launch& c, int k) {
         constexpr int E = decltype(e)::value;
         hipLaunchKernelGGL((ks_rows_inv<L, E, 3>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);
     });
-    hipLaunchKernelGGL(ks_line_cols<4>, dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols, c.stream,
-                       c.A, k);
+    if (4 * c.P_cols <= 256)
+        hipLaunchKernelGGL((ks_line_cols<4, 256>), dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
+                           c.stream, c.A, k);
+    else
+        hipLaunchKernelGGL((ks_line_cols<4, 1024>), dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
+                           c.stream, c.A, k);
     with_E<L>(c.E_lrows, [&](auto e) {
         constexpr int E = decltype(e)::value;
         hipLaunchKernelGGL((ks_line_rows<L, E, true, false>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);

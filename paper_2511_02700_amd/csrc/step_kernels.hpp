@@ -396,9 +396,9 @@ __global__ __launch_bounds__(L / E) void ks_sl(const MarchArgs* __restrict__ A) 
 }
 
 // Axis-1 line solves R <- T_1^{-1} R: CPB adjacent columns x P chunks per block
-// (thread = column + CPB * chunk).
-template <int CPB>
-__global__ __launch_bounds__(1024) void ks_line_cols(const MarchArgs* __restrict__ A, int k) {
+// (thread = column + CPB * chunk); launched with CPB * P <= MAXT threads.
+template <int CPB, int MAXT>
+__global__ __launch_bounds__(MAXT) void ks_line_cols(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, k)) return;
     extern __shared__ double2 sbuf[];

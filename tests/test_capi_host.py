@@ -63,8 +63,8 @@ def test_host_discretization_matches_oracle(name):
     S = np.array([d["S"][0, 0], d["S"][0, 1], d["S"][1, 1]])
     assert np.allclose(info["S"], S, rtol=1e-11, atol=0)
     # FFT side: no wrap-around onto the kept outputs for the cubic T^in
-    # the smallest transform side of the form 2^m or 3 * 2^m (from 768 on) without wrap-around
-    sides = sorted([2 ** q for q in range(6, 13)] + [768, 1536, 3072])
+    # the smallest automatic transform side (2^m, or 3 * 2^m at 1536 and 3072) without wrap-around
+    sides = sorted([2 ** q for q in range(6, 13)] + [1536, 3072])
     need = w["n"] + d["N_z"] + 1
     assert info["L"] == min(s for s in sides if s >= need)
 

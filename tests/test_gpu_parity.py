@@ -57,14 +57,14 @@ def _oracle_problem(w, sl_order=3, in_order=3, payoff=None, sigma_bs=None, no_ju
 # --------------------------------------------------------------------------- #
 @pytest.mark.parametrize("n,half,P,L", [(16, 1.5, 3, 0), (50, 2.0, 3, 0), (64, 3.0, 1, 0), (64, 3.0, 3, 0),
                                         (130, 2.5, 3, 0), (257, 3.0, 3, 0), (450, 3.0, 3, 0), (700, 3.0, 3, 0),
-                                        (130, 2.5, 3, 768), (257, 3.0, 3, 1536), (257, 3.0, 1, 3072),
-                                        (450, 3.0, 3, 1024)])
+                                        (130, 2.5, 3, 768), (450, 3.0, 3, 768), (257, 3.0, 3, 1536),
+                                        (257, 3.0, 1, 3072)])
 def test_apply_B_matches_oracle(lp, n, half, P, L):
     """(B v) by the three FFT passes vs the oracle's direct sum (n <= 64) or
     scipy FFT; ragged sizes (not multiples of any tile) included.  L = 0 takes
-    the smallest transform side (768 at n = 450 and 1536 at n = 700, both of
-    the form 3 * 2^m); other L force the side, a mixed-radix one far above the
-    kernel's support or the power of two above 768."""
+    the automatic transform side (1024 at n = 450, 1536 = 3 * 512 at n = 700);
+    other L force a side of the form 3 * 2^m, at the kernel's support (768 at
+    n = 450) or far above it."""
     import torch
     _note("apply_B n=%d half=%g P=%d L=%d" % (n, half, P, L))
     w = workloads.workload("nig64", n=n, y_lo=-half, y_hi=half)
@@ -76,7 +76,7 @@ def test_apply_B_matches_oracle(lp, n, half, P, L):
     assert info["N_z"] == prob.disc["N_z"]
     assert L == 0 or info["L"] == L
     if L == 0 and n in (450, 700):
-        assert info["L"] == {450: 768, 700: 1536}[n]
+        assert info["L"] == {450: 1024, 700: 1536}[n]
     ref = scheme.apply_B(v, prob.disc["W"], prob.disc["N_z"], P, "direct" if n <= 64 else "fft")
     err = np.max(np.abs(bv - ref)) / np.max(np.abs(ref))
     assert err < 1e-12, err
