@@ -225,14 +225,16 @@ def sl_matrix(n, kappa, h, dt, P):
 # --------------------------------------------------------------------------- #
 # Pay-offs and cell-averaged initial data (Sec. 3.2.3, Sec. 4)
 # --------------------------------------------------------------------------- #
-PAYOFFS = ("put_avg", "call_avg", "put_1", "call_1", "exchange")
+PAYOFFS = ("put_avg", "call_avg", "put_1", "call_1", "exchange", "spread")
 
 
 def payoff_g(kind):
     """g with pay-off = K max(g(y1, y2), 0), y_i = ln(S_i / K).
 
-    put_avg is the put-on-the-average of Sec. 4; the others are used for checks
-    (call-on-the-average, single-asset put / call on asset 1, exchange S1 - S2).
+    put_avg is the put-on-the-average of Sec. 4; spread is the spread call
+    max(S1 - S2 - K, 0) named among the extensions of Sec. 5; the others are
+    used for checks (call-on-the-average, single-asset put / call on asset 1,
+    exchange S1 - S2).
     Each g is monotone in each variable, so its kink set {g = 0} meets a cell
     iff g changes sign over the cell's corners.
     """
@@ -246,6 +248,8 @@ def payoff_g(kind):
         return lambda y1, y2: np.exp(y1) - 1.0 + 0.0 * y2
     if kind == "exchange":
         return lambda y1, y2: np.exp(y1) - np.exp(y2)
+    if kind == "spread":
+        return lambda y1, y2: np.exp(y1) - np.exp(y2) - 1.0
     raise ValueError(kind)
 
 

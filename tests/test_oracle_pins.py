@@ -338,13 +338,19 @@ def test_cell_average_vs_adaptive():
             outer = [math.log(2 - math.exp(t)) for t in (a2, b2) if math.exp(t) < 2]
         elif kind in ("put_1", "call_1"):
             inner, outer = (lambda y1: []), [0.0]
+        elif kind == "spread":          # e^y1 = e^y2 + 1
+            inner = lambda y1: [math.log(math.exp(y1) - 1)] if math.exp(y1) > 1 else []
+            outer = [math.log1p(math.exp(t)) for t in (a2, b2)]
         else:
             inner, outer = (lambda y1: [y1]), [a2, b2]
         return inner, outer
 
     for kind in scheme.PAYOFFS:
         g = scheme.payoff_g(kind)
-        for c1, c2 in ((0.02, -0.03), (-0.05, 0.06), (0.3, -0.28)):
+        centres = ((0.02, -0.03), (-0.05, 0.06), (0.3, -0.28))
+        if kind == "spread":            # cells on its kink curve
+            centres = tuple((math.log1p(math.exp(t)) + d, t) for t, d in ((-0.03, 0.01), (0.4, -0.04), (-1.2, 0.0)))
+        for c1, c2 in centres:
             a1, b1, a2, b2 = c1 - h / 2, c1 + h / 2, c2 - h / 2, c2 + h / 2
             got = scheme.cell_average(g, a1, b1, a2, b2)
             inner, outer = kinks(kind, a2, b2)
@@ -411,6 +417,66 @@ def test_margrabe_exchange():
         errs.append(max(abs(P[0] - margrabe(100, 100, 1, s1, s2, c)), abs(P[1] - margrabe(110, 95, 1, s1, s2, c))))
     assert errs[1] < 1e-2
     assert math.log2(errs[0] / errs[1]) > 1.5, errs
+
+
+def test_spread_call_black_scholes():
+    """Zero Levy measure, spread call max(S1 - S2 - K, 0): the semi-analytic
+    price (a Gauss-Hermite integral of Black-Scholes calls), at second order."""
+    s1, s2, c = 0.3, 0.2, 0.4
+    cov = np.array([[s1 * s1, c * s1 * s2], [c * s1 * s2, s2 * s2]])
+    from closed_forms import bs_spread_call, margrabe
+    assert bs_spread_call(100, 90, 0.0, 1.0, 0.03, s1, s2, c) == pytest.approx(margrabe(100, 90, 1.0, s1, s2, c),
+                                                                            rel=1e-13)
+    errs = []
+    for n in (33, 65):
+        prob = _bs_problem(n, 2.0, "spread", cov)
+        V, _ = scheme.solve(prob)
+        P = output.prices(V, prob.y_lo, prob.h, 100.0, [(200.0, 100.0), (230.0, 95.0)])
+        errs.append(max(abs(P[0] - bs_spread_call(200, 100, 100, 1, 0.03, s1, s2, c)),
+                        abs(P[1] - bs_spread_call(230, 95, 100, 1, 0.03, s1, s2, c))))
+    assert errs[1] < 4e-2                 # prices near 100: 4e-4 relative at n = 65
+    assert math.log2(errs[0] / errs[1]) > 1.8, errs
+
+
+def test_greeks_exact_for_quadratics():
+    """The grid Greeks differentiate V = quadratic in (y1, y2) exactly (every
+    stencil is exact for quadratics), so they equal the chain rule applied
+    to the exact y-derivatives."""
+    n, h, K = 23, 0.11, 100.0
+    y_lo = (-1.3, -0.7)
+    y1 = (y_lo[0] + h * np.arange(n))[:, None]
+    y2 = (y_lo[1] + h * np.arange(n))[None, :]
+    V = 1.0 + 2.0 * y1 - 3.0 * y2 + 0.5 * y1 * y1 + 0.7 * y1 * y2 - 0.4 * y2 * y2 + 0.0 * y1 * y2
+    v1, v2 = 2.0 + y1 + 0.7 * y2, -3.0 + 0.7 * y1 - 0.8 * y2
+    S1, S2 = K * np.exp(y1), K * np.exp(y2)
+    want = (v1 / S1, v2 / S2, (1.0 - v1) / S1 ** 2, 0.7 / (S1 * S2) + 0.0 * v1, (-0.8 - v2) / S2 ** 2)
+    got = output.greeks_on_grid(V, y_lo, h, K)
+    for g, w in zip(got, want):
+        assert np.allclose(g, w, rtol=1e-10, atol=1e-13)
+
+
+def test_greeks_black_scholes_put():
+    """Zero Levy measure, put on asset 1: Delta1 and Gamma11 on the grid
+    converge to the Black-Scholes put Greeks (second order); the asset-2
+    Greeks vanish."""
+    s1, s2, c = 0.25, 0.2, 0.4
+    cov = np.array([[s1 * s1, c * s1 * s2], [c * s1 * s2, s2 * s2]])
+    from closed_forms import bs_put_delta_gamma
+    ed, eg = [], []
+    for n in (33, 65):
+        prob = _bs_problem(n, 2.0, "put_1", cov)
+        V, _ = scheme.solve(prob)
+        d1, d2, g11, g12, g22 = output.greeks_on_grid(V, prob.y_lo, prob.h, 100.0)
+        S = 100.0 * np.exp(prob.y_lo[0] + prob.h * np.arange(n))
+        sel = np.nonzero((S > 70.0) & (S < 140.0))[0]
+        j2 = n // 2
+        ref = [bs_put_delta_gamma(S[j], 100.0, 1.0, 0.03, s1) for j in sel]
+        ed.append(max(abs(d1[j, j2] - r[0]) for j, r in zip(sel, ref)))
+        eg.append(max(abs(g11[j, j2] - r[1]) for j, r in zip(sel, ref)))
+        assert np.max(np.abs(d2[sel][:, 2:-2])) < 1e-9 and np.max(np.abs(g22[sel][:, 2:-2])) < 1e-9
+        assert np.max(np.abs(g12[sel][:, 2:-2])) < 1e-9
+    assert ed[1] < 4e-3 and eg[1] < 1e-4            # Gamma is about 0.016 at the money
+    assert math.log2(ed[0] / ed[1]) > 1.8 and math.log2(eg[0] / eg[1]) > 1.8, (ed, eg)
 
 
 @pytest.mark.slow
