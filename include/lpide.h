@@ -53,6 +53,7 @@ extern "C" {
 #define LPIDE_PUT_1     2   /* K - S1 */
 #define LPIDE_CALL_1    3   /* S1 - K */
 #define LPIDE_EXCHANGE  4   /* S1 - S2  (K only sets the log-moneyness origin) */
+#define LPIDE_SPREAD    5   /* S1 - S2 - K  (spread call, among the extensions of Sec. 5) */
 
 /* Arithmetic of the FFT correlation.  In the mixed form every time step applies
  * B to V^{n-1} once in FP64; the fixed-point iterations then apply B in FP32 to
@@ -208,6 +209,18 @@ int lpide_apply_B(void* plan, const double* v, double* bv);
  * price[k]; delta[2k + i] = dP/dS_i (delta may be NULL).  All device pointers. */
 int lpide_price(void* plan, const double* v, int32_t npts, const double* spots,
                 double* price, double* delta);
+
+/* Delta and Gamma surfaces of a grid solution at the nodes (Sec. 4 plots them
+ * over the spot plane).  With S_i = K e^{y_i}:
+ *   delta_i = V_{y_i} / S_i,  gamma_ii = (V_{y_i y_i} - V_{y_i}) / S_i^2,
+ *   gamma_12 = V_{y_1 y_2} / (S_1 S_2),
+ * the y-derivatives by second-order differences: central inside, one-sided
+ * (-3, 4, -1)/2h and (2, -5, 4, -1)/h^2 on the edges; V_{y_1 y_2} is the first
+ * difference along axis 1 of the first difference along axis 2.
+ * v: device, n*n FP64 (the layout lpide_solve writes); out: device, 5*n*n FP64,
+ * caller-owned, must not alias v: delta1, delta2, gamma11, gamma12, gamma22, each
+ * n*n row-major.  Enqueued on the plan's stream (no synchronisation). */
+int lpide_greeks(void* plan, const double* v, double* out);
 
 /* Host-only discretization (no device is touched): fills info (n, N_z, M1, M2,
  * L, h, z_star, sum_omega, kappa, r_omega, S, a) and, if omega is not NULL and

@@ -9,7 +9,7 @@ LIB_PATH = os.environ.get("LPIDE_LIB") or os.path.join(HERE, "liblpide.so")
 
 LPIDE_OK = 0
 ERRORS = {-1: "LPIDE_E_PARAM", -2: "LPIDE_E_NOCONV", -3: "LPIDE_E_NAN", -4: "LPIDE_E_HIP", -5: "LPIDE_E_OOM"}
-PAYOFF = {"put_avg": 0, "call_avg": 1, "put_1": 2, "call_1": 3, "exchange": 4}
+PAYOFF = {"put_avg": 0, "call_avg": 1, "put_1": 2, "call_1": 3, "exchange": 4, "spread": 5}
 PRECISION = {"fp64": 0, "fp32conv": 1}
 KCLASSES = ["cols", "rows_inv", "line_cols", "line_rows", "sl", "step_end", "expl_cols", "expl_rows", "rows_fwd"]
 
@@ -94,6 +94,7 @@ SIGNATURES = {
     "lpide_initial": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lpide_apply_B": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lpide_price": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lpide_greeks": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lpide_discretize_host": (C.c_int, [C.POINTER(Grid), C.POINTER(Levy), C.POINTER(Payoff), C.POINTER(Info),
                                         C.c_void_p, C.c_int64, C.c_void_p]),
     "lpide_timing": (C.c_int, [C.c_void_p, C.c_uint32]),

@@ -215,6 +215,15 @@ class Plan:
                                 C.c_void_p(pr.data_ptr()), C.c_void_p(dl.data_ptr()) if dl is not None else None))
         return (pr, dl) if with_delta else pr
 
+    def greeks(self, v):
+        """Delta and Gamma surfaces at the nodes (lpide_greeks): a (5, n, n)
+        float64 tensor delta1, delta2, gamma11, gamma12, gamma22."""
+        torch = _torch()
+        n = v.shape[0]
+        out = torch.empty((5, n, n), dtype=torch.float64, device=self.device)
+        check(lib().lpide_greeks(self._h, C.c_void_p(v.contiguous().data_ptr()), C.c_void_p(out.data_ptr())))
+        return out
+
 
 class Batch:
     """Many plans marched together (see lpide_batch_create).  The plans must

@@ -403,6 +403,7 @@ double payoff_g(int kind, double y1, double y2) {
         case LPIDE_CALL_AVG: return 0.5 * (std::exp(y1) + std::exp(y2)) - 1.0;
         case LPIDE_PUT_1: return 1.0 - std::exp(y1);
         case LPIDE_CALL_1: return std::exp(y1) - 1.0;
+        case LPIDE_SPREAD: return std::exp(y1) - std::exp(y2) - 1.0;
         default: return std::exp(y1) - std::exp(y2);   // exchange
     }
 }
@@ -426,6 +427,13 @@ double inner_closed(int kind, double y1, double a2, double b2) {
         }
         case LPIDE_PUT_1: return std::max(1.0 - e1, 0.0) * (b2 - a2);
         case LPIDE_CALL_1: return std::max(e1 - 1.0, 0.0) * (b2 - a2);
+        case LPIDE_SPREAD: {            // positive for e^{y2} < e^{y1} - 1
+            const double c = e1 - 1.0;
+            if (!(c > 0.0)) return 0.0;
+            const double u = std::min(b2, std::log(c));
+            if (!(u > a2)) return 0.0;
+            return c * (u - a2) - (std::exp(u) - std::exp(a2));
+        }
         default: {                      // exchange: positive for y2 < y1
             double u = std::min(b2, y1);
             if (!(u > a2)) return 0.0;
@@ -445,6 +453,7 @@ void kink_crossings(int kind, double t, std::vector<double>& out) {
         }
         case LPIDE_PUT_1:
         case LPIDE_CALL_1: out.push_back(0.0); break;
+        case LPIDE_SPREAD: out.push_back(std::log1p(std::exp(t))); break;
         default: out.push_back(t); break;
     }
 }
@@ -452,7 +461,7 @@ void kink_crossings(int kind, double t, std::vector<double>& out) {
 }  // namespace
 
 bool initial_values(const HostPlan& hp, const lpide_payoff& pay, std::vector<double>& v0, std::string& err) {
-    if (pay.kind < LPIDE_PUT_AVG || pay.kind > LPIDE_EXCHANGE) { err = "unknown pay-off kind"; return false; }
+    if (pay.kind < LPIDE_PUT_AVG || pay.kind > LPIDE_SPREAD) { err = "unknown pay-off kind"; return false; }
     if (!(pay.K > 0.0) || !(pay.T > 0.0)) { err = "K and T must be positive"; return false; }
     const int n = hp.n;
     const double h = hp.h, hh = 0.5 * h;

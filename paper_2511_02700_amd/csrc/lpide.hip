@@ -76,6 +76,62 @@ bool KTime::events(hipEvent_t* a, hipEvent_t* b) {
 using namespace lpide;
 using namespace lpide::detail;
 
+// First-difference weights at index i of a line of n >= 3 nodes (spacing h):
+// central inside, second-order one-sided on the two ends; nodes p[0..2].
+__device__ __forceinline__ void d1_weights(int i, int n, double h, int* p, double* w) {
+    const double c = 0.5 / h;
+    if (i == 0) { p[0] = 0; p[1] = 1; p[2] = 2; w[0] = -3.0 * c; w[1] = 4.0 * c; w[2] = -c; }
+    else if (i == n - 1) { p[0] = n - 1; p[1] = n - 2; p[2] = n - 3; w[0] = 3.0 * c; w[1] = -4.0 * c; w[2] = c; }
+    else { p[0] = i - 1; p[1] = i; p[2] = i + 1; w[0] = -c; w[1] = 0.0; w[2] = c; }
+}
+
+// Second-difference weights at index i of a line of n >= 4 nodes: (1, -2, 1)/h^2
+// inside, (2, -5, 4, -1)/h^2 on the two ends; nodes p[0..3] (w[3] = 0 inside).
+__device__ __forceinline__ void d2_weights(int i, int n, double h, int* p, double* w) {
+    const double c = 1.0 / (h * h);
+    if (i == 0) { p[0] = 0; p[1] = 1; p[2] = 2; p[3] = 3; w[0] = 2.0 * c; w[1] = -5.0 * c; w[2] = 4.0 * c; w[3] = -c; }
+    else if (i == n - 1) {
+        p[0] = n - 1; p[1] = n - 2; p[2] = n - 3; p[3] = n - 4;
+        w[0] = 2.0 * c; w[1] = -5.0 * c; w[2] = 4.0 * c; w[3] = -c;
+    } else { p[0] = i - 1; p[1] = i; p[2] = i + 1; p[3] = i; w[0] = c; w[1] = -2.0 * c; w[2] = c; w[3] = 0.0; }
+}
+
+// Delta and Gamma surfaces at the nodes: one thread per node (i, j), j fast.
+// out[q * n^2 + i * n + j], q = delta1, delta2, gamma11, gamma12, gamma22.
+__global__ void k_greeks(const double* __restrict__ V, int n, double y0, double y1, double h, double K,
+                         double* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= n) return;
+    int pi[4], pj[4];
+    double wi[4], wj[4];
+    auto at = [&](int a, int b) { return V[(size_t)a * n + b]; };
+    d1_weights(i, n, h, pi, wi);
+    d1_weights(j, n, h, pj, wj);
+    double v1 = 0.0, v2 = 0.0, v12 = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        v1 += wi[q] * at(pi[q], j);
+        v2 += wj[q] * at(i, pj[q]);
+        double t = 0.0;
+        for (int r = 0; r < 3; ++r) t += wj[r] * at(pi[q], pj[r]);
+        v12 += wi[q] * t;
+    }
+    d2_weights(i, n, h, pi, wi);
+    d2_weights(j, n, h, pj, wj);
+    double v11 = 0.0, v22 = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        v11 += wi[q] * at(pi[q], j);
+        v22 += wj[q] * at(i, pj[q]);
+    }
+    const double S1 = K * exp(y0 + h * i), S2 = K * exp(y1 + h * j);
+    const size_t o = (size_t)i * n + j, N = (size_t)n * n;
+    out[o] = v1 / S1;
+    out[N + o] = v2 / S2;
+    out[2 * N + o] = (v11 - v1) / (S1 * S1);
+    out[3 * N + o] = v12 / (S1 * S2);
+    out[4 * N + o] = (v22 - v2) / (S2 * S2);
+}
+
 // Prices and deltas at spot pairs: tensor cubic Lagrange in y with the clamped
 // stencil start clamp(floor(xi) - 1, 0, n - 4).
 __global__ void k_price(const double* __restrict__ V, int n, double y0, double y1, double h, double K,
@@ -1437,6 +1493,19 @@ int lpide_price(void* plan, const double* v, int32_t npts, const double* spots, 
     if (npts == 0) return LPIDE_OK;
     hipLaunchKernelGGL(k_price, dim3((npts + 127) / 128), dim3(128), 0, p->stream, v, p->hp.n, p->hp.y_lo[0],
                        p->hp.y_lo[1], p->hp.h, p->pay.K, npts, spots, price, delta);
+    HIP_TRY(hipGetLastError());
+    return LPIDE_OK;
+}
+
+int lpide_greeks(void* plan, const double* v, double* out) {
+    if (!plan || !v || !out) return fail(LPIDE_E_PARAM, "NULL argument");
+    Plan* p = static_cast<Plan*>(plan);
+    const int n = p->hp.n;
+    if (n < 4) return fail(LPIDE_E_PARAM, "the Greeks need n >= 4");
+    const size_t N = (size_t)n * n;
+    if (out < v + N && v < out + 5 * N) return fail(LPIDE_E_PARAM, "out must not alias v");
+    hipLaunchKernelGGL(k_greeks, dim3((n + 127) / 128, n), dim3(128), 0, p->stream, v, n, p->hp.y_lo[0],
+                       p->hp.y_lo[1], p->hp.h, p->pay.K, out);
     HIP_TRY(hipGetLastError());
     return LPIDE_OK;
 }

@@ -69,7 +69,7 @@ def test_host_discretization_matches_oracle(name):
     assert info["L"] == min(s for s in sides if s >= need)
 
 
-@pytest.mark.parametrize("kind", ["put_avg", "call_avg", "put_1", "call_1", "exchange"])
+@pytest.mark.parametrize("kind", ["put_avg", "call_avg", "put_1", "call_1", "exchange", "spread"])
 def test_host_initial_values_match_oracle(kind):
     """Cell-averaged V^0: closed-form inner integrals (C++) vs root-split
     Gauss-Legendre (oracle)."""

@@ -127,7 +127,7 @@ def test_solve_ragged_sizes(lp, n):
     assert _rel(Vg, Vo) < 1e-10
 
 
-@pytest.mark.parametrize("payoff", ["put_1", "exchange"])
+@pytest.mark.parametrize("payoff", ["put_1", "exchange", "spread"])
 def test_solve_black_scholes_matches_oracle(lp, payoff):
     """Zero Levy measure with a correlated Brownian covariance: exercises D with
     the mixed term and the line-solve preconditioner at real coupling."""
