@@ -18,7 +18,8 @@ column pass, the other precision timed beside it with the mixed-vs-plain
 differences, and a CPU baseline: the FP64 oracle timed on this host on a
 bounded sample of the same workload.  Unless --no-extras: the column-pass
 roofline at 2048^2 (cache-exceeding working set), whole 2048^2 solves in
-both precisions, the adjoint form on its
+both precisions, the paper's Table 3 prices against GPU marches, the adjoint
+form on its
 1024^2 workload (ratio to the forward), and the batched form on 32 draws of
 the batched recipe (against solo solves).
 """
@@ -211,6 +212,43 @@ def large_solve(lp, name="nig2048_m"):
                                                 np.maximum(1.0, np.abs(prices["fp64"]))))
     out["pow2_vs_default_prices_rel"] = float(np.max(np.abs(prices["fp64_pow2"] - prices["fp64"]) /
                                                  np.maximum(1.0, np.abs(prices["fp64"]))))
+    return out
+
+
+def table3_check(lp):
+    """The paper's Table 3 (put-on-the-average prices at nine spot pairs for the
+    four parameter sets of Table 1) against whole GPU marches on the log grid:
+    max |price - printed price| per set, and the solve time."""
+    import csv
+    import numpy as np
+    import torch
+
+    def rows(name):
+        with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+            return list(csv.DictReader(line for line in f if not line.startswith("#")))
+
+    t1 = {r["name"]: r for r in rows("table1_params.csv")}
+    gold = rows("table3_prices.csv")
+    spots = [(float(g["x1"]), float(g["x2"])) for g in gold]
+    out = {}
+    for name, n, half in (("VG0", 1024, 4.0), ("VG1", 1024, 2.0), ("NIG0", 2048, 1.5), ("NIG1", 2048, 2.0)):
+        r = t1[name]
+        lv = lp.levy_nts(float(r["alpha"]), float(r["delta"]), float(r["lambda"]),
+                         (float(r["eta1"]), float(r["eta2"])), (float(r["rho11"]), float(r["rho12"]), float(r["rho22"])),
+                         float(r["r"]))
+        plan = lp.Plan(lp.make_grid(n, -half, half), lv, lp.make_payoff("put_avg", float(r["K"]), float(r["T"])),
+                       theta=0.5, M=n // 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        V = plan.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        got = plan.price(V, spots).cpu().numpy()
+        want = np.array([float(g[name]) for g in gold])
+        out[name] = {"n": n, "domain": [-half, half], "L": plan.info()["L"], "ms": 1e3 * dt,
+                     "max_abs_err": float(np.max(np.abs(got - want)))}
+        del plan, V
+        torch.cuda.empty_cache()
     return out
 
 
@@ -414,6 +452,7 @@ def main():
         result["large_2048"] = large_solve(lp, "nig2048_m")
         result["adjoint"] = adjoint_measure(lp)
         result["batched"] = batch_measure(lp)
+        result["paper_table3"] = table3_check(lp)
     if rank == 0 and not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     if rank == 0:
