@@ -464,18 +464,18 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
             fac[2 * L + i] = sd.bc2[i];
         }
     }
-    for (int i = tid; i < n; i += T) {
-        rows[i + i / m] = a.R[(size_t)ra * n + i];
-        if (hasb) rows[stride + i + i / m] = a.R[(size_t)rb * n + i];
-    }
-    __syncthreads();
+    // each thread reads its chunk of the residual row straight from memory: the
+    // chunks of consecutive lanes are adjacent, so the reads stay coalesced
     const int r = tid / PR, ch = tid % PR;
     const int s = ch * m;
     const int cnt = (r == 1 && !hasb) ? 0 : max(0, min(m, n - s));
     double x[LINE_MM];
+    {
+        const double* Rr = a.R + (size_t)(r == 0 ? ra : rb) * n + s;
 #pragma unroll
-    for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? rows[r * stride + s + q + ch] : 0.0;
-    __syncthreads();
+        for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? Rr[q] : 0.0;
+    }
+    __syncthreads();                      // staged factors visible
     if constexpr (PF) chunk_solve(x, s, cnt, r, ch, PR, 1, fac, fac + L, fac + 2 * L, lds);
     else chunk_solve(x, s, cnt, r, ch, PR, 1, sd.fl2, sd.bu2, sd.bc2, lds);
 #pragma unroll
@@ -506,18 +506,27 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
         }
         reg[e] = MIXED ? CplxOps<C>::make(da, db) : CplxOps<C>::make(ya, yb);
     }
-    // wave maximum over the block's active lanes (T may be below 64), one atomic
-    // per wave (non-negative doubles order like their bit patterns; NaN sorts
-    // above +inf)
-    constexpr int WL = T < 64 ? T : 64;
+    // block maximum: a wave reduction over the active lanes (T may be below
+    // 64), the wave maxima through LDS, then one atomic per block
+    // (non-negative doubles order like their bit patterns; NaN sorts above
+    // +inf).  Same-address atomics serialise in the L2, so one per block
+    // instead of one per wave shortens the tail of the kernel.
+    constexpr int WL = T < 64 ? T : 64, NWV = (T + 63) / 64;
 #pragma unroll
     for (int off = WL / 2; off > 0; off >>= 1) {
         const double o = __shfl_xor(emax, off, WL);
         emax = (o > emax || o != o) ? o : emax;
     }
-    if ((tid & 63) == 0)
+    __shared__ double wmax[NWV];
+    if ((tid & 63) == 0) wmax[tid >> 6] = emax;
+    __syncthreads();
+    if (tid == 0) {                       // issued before the row transform, which hides its latency
+        double b = wmax[0];
+#pragma unroll
+        for (int w = 1; w < NWV; ++w) b = (wmax[w] > b || wmax[w] != wmax[w]) ? wmax[w] : b;
         atomicMax(&a.ctl->err[(blockIdx.x + blockIdx.y * gridDim.x) & (NX - 1)][k],
-                  (unsigned long long)__double_as_longlong(emax));
+                  (unsigned long long)__double_as_longlong(b));
+    }
     if constexpr (FFT) rows_fwd_store<L, E>(reg, reinterpret_cast<C*>(lds), tw4, xbuf<C>(a), n, ra, hasb);
 }
 
