@@ -614,6 +614,8 @@ int sl_transpose(int n, int P, const std::vector<int32_t>& start, const std::vec
     return width;
 }
 
+// Stencil starts and Lagrange weights of the departure points j + shift:
+// start[j] = clamp(floor(j + shift) - (P - 1) / 2, 0, n - 1 - P).
 void sl_weights(int n, double shift, int P, std::vector<int32_t>& start, std::vector<double>& w) {
     start.assign(n, 0);
     w.assign(size_t(n) * (P + 1), 0.0);

@@ -384,8 +384,11 @@ __global__ __launch_bounds__(L / E) void ks_sl(const MarchArgs* __restrict__ A) 
                 }
                 const size_t o = (size_t)i * n + j;
                 a.W[o] = acc;
+                // unrolled with a predicate, so the history reads are all in flight together
                 double yv = 0.0;
-                for (int q = 0; q < nsrc; ++q) yv += cf[q] * H[q][o];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q < nsrc) yv += cf[q] * H[q][o];
                 Y[o] = yv;
                 y0[r] = MIXED ? yv - V[o] : yv;
             }
