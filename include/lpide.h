@@ -206,7 +206,8 @@ int lpide_apply_B(void* plan, const double* v, double* bv);
 
 /* Prices (and deltas) at npts spot pairs by tensor-product cubic Lagrange
  * interpolation of the grid v in y (Sec. 4): spots[2k], spots[2k+1] = (S1, S2);
- * price[k]; delta[2k + i] = dP/dS_i (delta may be NULL).  All device pointers. */
+ * price[k]; delta[2k + i] = dP/dS_i (delta may be NULL).  All device pointers;
+ * with npts = 0 nothing is read or written and spots, price may be NULL. */
 int lpide_price(void* plan, const double* v, int32_t npts, const double* spots,
                 double* price, double* delta);
 
@@ -298,7 +299,8 @@ int lpide_adjoint(void* plan, const double* v_bar, int32_t checkpoint_every, con
 
 /* Transpose of lpide_price: v_bar[node] = sum_k price_bar[k] w_k(node), the
  * cotangent of the grid for price cotangents price_bar (device arrays: spots
- * npts x 2, price_bar npts, v_bar n*n, overwritten). */
+ * npts x 2, price_bar npts, v_bar n*n, overwritten; with npts = 0 v_bar is
+ * zeroed and spots, price_bar may be NULL). */
 int lpide_price_adjoint(void* plan, int32_t npts, const double* spots, const double* price_bar, double* v_bar);
 
 /* ---- Batched form ----

@@ -1437,7 +1437,8 @@ int lpide_adjoint(void* plan, const double* v_bar, int32_t checkpoint_every, con
 }
 
 int lpide_price_adjoint(void* plan, int32_t npts, const double* spots, const double* price_bar, double* v_bar) {
-    if (!plan || !spots || !price_bar || !v_bar || npts < 0) return fail(LPIDE_E_PARAM, "NULL argument or npts < 0");
+    if (!plan || !v_bar || npts < 0 || (npts > 0 && (!spots || !price_bar)))
+        return fail(LPIDE_E_PARAM, "NULL argument or npts < 0");
     Plan* p = static_cast<Plan*>(plan);
     const int n = p->hp.n;
     const size_t N = (size_t)n * n;
@@ -1487,10 +1488,11 @@ int lpide_apply_B(void* plan, const double* v, double* bv) {
 }
 
 int lpide_price(void* plan, const double* v, int32_t npts, const double* spots, double* price, double* delta) {
-    if (!plan || !v || !spots || !price) return fail(LPIDE_E_PARAM, "NULL argument");
+    if (!plan || !v) return fail(LPIDE_E_PARAM, "NULL argument");
     if (npts < 0) return fail(LPIDE_E_PARAM, "npts < 0");
+    if (npts == 0) return LPIDE_OK;       // nothing is read or written
+    if (!spots || !price) return fail(LPIDE_E_PARAM, "NULL argument");
     Plan* p = static_cast<Plan*>(plan);
-    if (npts == 0) return LPIDE_OK;
     hipLaunchKernelGGL(k_price, dim3((npts + 127) / 128), dim3(128), 0, p->stream, v, p->hp.n, p->hp.y_lo[0],
                        p->hp.y_lo[1], p->hp.h, p->pay.K, npts, spots, price, delta);
     HIP_TRY(hipGetLastError());

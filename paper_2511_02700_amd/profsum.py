@@ -38,15 +38,21 @@ CLASS_OF = [
 ]
 
 
+# The sources that define the march kernels and their launch sequences (grid,
+# block, radix): a kernel's measured traffic holds while these are unchanged.
+# Host-only code (plans, the C ABI, pricing) is not part of it.
+KERNEL_SOURCES = ("fft.hpp", "kernels.hpp", "linesolve.hpp", "step_kernels.hpp", "conv_kernels.hpp",
+                  "march_L.hip", "plan.hpp")
+
+
 def source_digest():
-    """SHA-256 over the device sources: the measured traffic of a kernel is
+    """SHA-256 over the kernel sources: the measured traffic of a kernel is
     valid only for the sources it was measured on."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
-        if f.endswith((".hip", ".hpp", ".cpp")):
-            with open(f, "rb") as fh:
-                h.update(os.path.basename(f).encode())
-                h.update(fh.read())
+    for name in sorted(KERNEL_SOURCES):
+        with open(os.path.join(HERE, "csrc", name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
     return h.hexdigest()
 
 
