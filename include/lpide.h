@@ -335,6 +335,24 @@ void lpide_batch_opts_default(lpide_batch_opts* o);
 int lpide_batch_create(int32_t count, void* const* plans, const lpide_batch_opts* opts, void** out);
 int lpide_batch_destroy(void* batch);
 
+/* Short forms of the plan calls: lpide_plan = lpide_plan_create,
+ * lpide_destroy = lpide_plan_destroy (same arguments, ownership and errors). */
+int lpide_plan(const lpide_grid* grid, const lpide_levy* levy, const lpide_payoff* payoff, double theta, int32_t M,
+               const lpide_opts* opts, void** out);
+int lpide_destroy(void* plan);
+
+/* Plans and their batch in one call: plan i from grids[i], levys[i],
+ * payoffs[i] (host arrays of count) with M[i] time steps, theta and opts shared
+ * (opts may be NULL; its stream becomes the batch's caller stream), then a
+ * batch over them with default batch options.  The batch owns these plans:
+ * lpide_batch_destroy destroys them too.  On error nothing is left allocated
+ * and the status of the first failing plan (or of the batch) is returned. */
+int lpide_plan_batch(int32_t count, const lpide_grid* grids, const lpide_levy* levys, const lpide_payoff* payoffs,
+                     double theta, const int32_t* M, const lpide_opts* opts, void** batch);
+
+/* Same as lpide_batch_solve. */
+int lpide_solve_batch(void* batch, double* const* v_out);
+
 /* March every plan over its whole step list (Algorithm 1 per plan).  v_out:
  * host array of count device pointers, plan i's n_i * n_i FP64 result.
  * Returns when the results are queued on the caller's stream.  Errors as

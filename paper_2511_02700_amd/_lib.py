@@ -87,6 +87,12 @@ SIGNATURES = {
     "lpide_plan_create": (C.c_int, [C.POINTER(Grid), C.POINTER(Levy), C.POINTER(Payoff), C.c_double, C.c_int32,
                                     C.POINTER(Opts), C.POINTER(C.c_void_p)]),
     "lpide_plan_destroy": (C.c_int, [C.c_void_p]),
+    "lpide_plan": (C.c_int, [C.POINTER(Grid), C.POINTER(Levy), C.POINTER(Payoff), C.c_double, C.c_int32,
+                             C.POINTER(Opts), C.POINTER(C.c_void_p)]),
+    "lpide_destroy": (C.c_int, [C.c_void_p]),
+    "lpide_plan_batch": (C.c_int, [C.c_int32, C.POINTER(Grid), C.POINTER(Levy), C.POINTER(Payoff), C.c_double,
+                                   C.POINTER(C.c_int32), C.POINTER(Opts), C.POINTER(C.c_void_p)]),
+    "lpide_solve_batch": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "lpide_plan_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
     "lpide_solve": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lpide_solve_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),

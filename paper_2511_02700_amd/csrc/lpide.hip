@@ -1041,6 +1041,7 @@ struct Batch {
     std::vector<hipEvent_t> events;            // one per group + 1
     hipStream_t caller = nullptr;
     bool tuned = false;
+    bool owns_plans = false;                   // made by lpide_plan_batch
 };
 
 void destroy_batch(Batch* b) {
@@ -1048,6 +1049,8 @@ void destroy_batch(Batch* b) {
     for (Group* g : b->groups) destroy_group(g);
     for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
     for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+    if (b->owns_plans)
+        for (Plan* p : b->plans) destroy(p);
     delete b;
 }
 
@@ -1596,6 +1599,42 @@ int lpide_batch_create(int32_t count, void* const* plans, const lpide_batch_opts
     *out = b;
     return LPIDE_OK;
 }
+
+int lpide_plan(const lpide_grid* grid, const lpide_levy* levy, const lpide_payoff* payoff, double theta, int32_t M,
+               const lpide_opts* opts, void** out) {
+    return lpide_plan_create(grid, levy, payoff, theta, M, opts, out);
+}
+
+int lpide_destroy(void* plan) { return lpide_plan_destroy(plan); }
+
+int lpide_plan_batch(int32_t count, const lpide_grid* grids, const lpide_levy* levys, const lpide_payoff* payoffs,
+                     double theta, const int32_t* M, const lpide_opts* opts, void** out) {
+    if (!grids || !levys || !payoffs || !M || !out || count < 1)
+        return fail(LPIDE_E_PARAM, "count must be >= 1 and the arrays and out not NULL");
+    std::vector<void*> plans;
+    int rc = LPIDE_OK;
+    for (int i = 0; i < count && rc == LPIDE_OK; ++i) {
+        void* h = nullptr;
+        rc = lpide_plan_create(&grids[i], &levys[i], &payoffs[i], theta, M[i], opts, &h);
+        if (rc == LPIDE_OK) plans.push_back(h);
+    }
+    void* b = nullptr;
+    if (rc == LPIDE_OK) {
+        lpide_batch_opts bo;
+        lpide_batch_opts_default(&bo);
+        bo.stream = opts ? opts->stream : nullptr;
+        rc = lpide_batch_create(count, plans.data(), &bo, &b);
+    }
+    if (rc != LPIDE_OK) {
+        for (void* h : plans) destroy(static_cast<Plan*>(h));
+        return rc;
+    }
+    static_cast<Batch*>(b)->owns_plans = true;
+    *out = b;
+    return LPIDE_OK;
+}
+
+int lpide_solve_batch(void* batch, double* const* v_out) { return lpide_batch_solve(batch, v_out); }
 
 int lpide_batch_destroy(void* batch) {
     destroy_batch(static_cast<Batch*>(batch));

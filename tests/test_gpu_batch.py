@@ -151,3 +151,42 @@ def test_batched_draw_sample(lp):
     for p, o in zip(plans, outs):
         assert torch.isfinite(o).all()
         assert _rel(o.cpu().numpy(), p.solve().cpu().numpy()) < 1e-12
+
+
+def test_plan_batch_one_call(lp):
+    """lpide_plan_batch builds the plans and their batch from arrays in one call
+    (the batch owns the plans); lpide_solve_batch marches them.  The results
+    equal plans made and solved one by one."""
+    import ctypes as C
+    import torch
+    from paper_2511_02700_amd import _lib
+    cfg = [(40, "put_avg", 8, 0.5), (48, "spread", 10, 0.3), (64, "call_1", 6, 0.4)]
+    _note("lpide_plan_batch of %d plans" % len(cfg))
+    grids = (_lib.Grid * 3)()
+    levys = (_lib.Levy * 3)()
+    pays = (_lib.Payoff * 3)()
+    Ms = (C.c_int32 * 3)()
+    ws = []
+    for q, (n, pay, M, alpha) in enumerate(cfg):
+        w = workloads.workload("nig64", n=n, y_lo=-2.5, y_hi=2.5, payoff=pay, N_t=M, alpha=alpha)
+        ws.append(w)
+        m = w["model"]
+        grids[q] = lp.make_grid(n, w["y_lo"], w["y_hi"])
+        levys[q] = lp.levy_from_std(m["sigma1"], m["sigma2"], m["corr"], m["theta1"], m["theta2"], m["kappa"],
+                                    m["alpha"], w["r"])
+        pays[q] = lp.make_payoff(pay, w["K"], w["T"])
+        Ms[q] = M
+    o = _lib.Opts()
+    lp.lib().lpide_opts_default(C.byref(o))
+    o.stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    b = C.c_void_p()
+    _lib.check(lp.lib().lpide_plan_batch(3, grids, levys, pays, 0.5, Ms, C.byref(o), C.byref(b)))
+    try:
+        outs = [torch.empty((n, n), dtype=torch.float64, device="cuda") for n, _, _, _ in cfg]
+        ptrs = (C.c_void_p * 3)(*[t.data_ptr() for t in outs])
+        _lib.check(lp.lib().lpide_solve_batch(b, ptrs))
+        torch.cuda.synchronize()
+        for w, t in zip(ws, outs):
+            assert _rel(t.cpu().numpy(), lp.plan_from_workload(w).solve().cpu().numpy()) < 1e-12
+    finally:
+        _lib.check(lp.lib().lpide_batch_destroy(b))
