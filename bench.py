@@ -114,6 +114,24 @@ def roofline(cls, n, L, mixed, launches, ms, traffic_json=None, sl_order=3, radi
             "mean_launch_ms": per_launch_ms, "launches": launches}
 
 
+def conv_whole(n, L, mixed, stats):
+    """The correlation as a whole, per iteration: its algorithmic bytes
+    c [2 n^2 + 8 n (L/2+1) + 2 L (L/2+1)] (grid in and out, two round trips of
+    the intermediate, one read of the spectrum; c = 8 in FP64, 4 in the mixed
+    form) over the summed mean durations of the three kernels that carry it:
+    the row r2c sits in the line-row kernel, the column pass is its own, the row
+    c2r sits in the residual kernel.  Those two also solve lines and form the
+    residual, so the fraction is a lower bound for the correlation itself."""
+    hc = L // 2 + 1
+    c = 4 if mixed else 8
+    b = c * (2 * n * n + 8 * n * hc + 2 * L * hc)
+    ks = ("line_rows", "cols", "rows_inv")
+    ms = sum(stats[k][1] / max(1, stats[k][0]) for k in ks)
+    ach = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"kernels": list(ks), "bound": "hbm", "bytes_per_iteration": b, "ms_per_iteration": ms,
+            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+
+
 def timed_solves(plan, out, steps, timed_classes):
     """steps full solves with HIP events around the named kernel classes (none:
     no events); wall seconds and the per-class (launches, ms)."""
@@ -167,13 +185,15 @@ def large_conv_roofline(lp, name, steps=40):
         plan = (lp.plan_from_workload(w, precision=prec) if prec != "fp64_pow2" else
                 lp.plan_from_workload(w, fft_size=1 << (out["fp64"]["L"] - 1).bit_length()))
         plan.solve_steps(4)
-        plan.set_timing(["cols"])
+        plan.set_timing(["cols", "rows_inv", "line_rows"])
         plan.solve_steps(steps)
-        la, ms = plan.kernel_stats()["cols"]
+        st = plan.kernel_stats()
+        la, ms = st["cols"]
         plan.set_timing([])
         info = plan.info()
         out[prec] = roofline("cols", w["n"], info["L"], prec == "fp32conv", la, ms, radix=info["radix"])
         out[prec]["L"] = info["L"]
+        out[prec]["conv_whole"] = conv_whole(w["n"], info["L"], prec == "fp32conv", st)
         del plan
     return out
 
@@ -375,7 +395,8 @@ def main():
     # class and of the correlation's column pass (the events take the
     # dispatch's own timestamps), giving their mean launch durations
     wall, _ = timed_solves(plan, outs[args.precision], args.steps, [])
-    _, live = timed_solves(plan, outs[args.precision], args.steps, sorted({dominant, "cols"}))
+    _, live = timed_solves(plan, outs[args.precision], args.steps,
+                           sorted({dominant, "cols", "rows_inv", "line_rows"}))
     info = plan.info()
     ms_per_step = 1e3 * wall / args.steps
     value = n * n * Nt * args.steps / wall
@@ -419,6 +440,7 @@ def main():
                              radix=info["radix"]),
         "conv_roofline": roofline("cols", n, L, mixed, *live["cols"], traffic_json=tj, sl_order=args.sl_order,
                                   radix=info["radix"]),
+        "conv_whole": conv_whole(n, L, mixed, live),
         "radix_schedule": dict(zip(("cols", "row_c2r", "line_rows", "sl"), info["radix"])),
         "iters_per_step": info["total_iters"] / info["n_steps"],
         "kernel_ms_per_solve": {c: prof[c][1] for c in prof if prof[c][0]},
