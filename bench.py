@@ -191,7 +191,8 @@ def large_conv_roofline(lp, name, steps=40):
         la, ms = st["cols"]
         plan.set_timing([])
         info = plan.info()
-        out[prec] = roofline("cols", w["n"], info["L"], prec == "fp32conv", la, ms, radix=info["radix"])
+        out[prec] = roofline("cols", w["n"], info["L"], prec == "fp32conv", la, ms, radix=info["radix"],
+                             traffic_json=os.path.join(ROOT, "profiles", "pmc_%s.json" % name))
         out[prec]["L"] = info["L"]
         out[prec]["conv_whole"] = conv_whole(w["n"], info["L"], prec == "fp32conv", st)
         del plan

@@ -137,6 +137,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("liblpide.so is not built; run `python -m paper_2511_02700_amd.build` "
                               "(or __graft_entry__.build())")
+        # torch ships its own HIP runtime under the same soname as the one the
+        # library links; whichever is loaded first serves the process.  Loading
+        # torch first keeps its kernels and ours on torch's runtime (the other
+        # order makes torch's own launches fail with "invalid device function").
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
