@@ -67,7 +67,8 @@ extern "C" {
 /* Spatial grid and integral-discretization settings (Sec. 3.1, Sec. 4 settings). */
 typedef struct {
     int32_t n;            /* nodes per axis, both ends included; 8 <= n <= 4096, and the
-                             FFT side (power of two >= n + N_z + 1) must not exceed 4096 */
+                             FFT side (lpide_opts.fft_size; at least n + N_z + 1) must not
+                             exceed 4096 */
     double  y_lo[2];      /* lower ends of the log-moneyness axes y_i = ln(S_i/K) */
     double  y_hi[2];      /* upper ends; y_hi[i] - y_lo[i] must be equal on both axes,
                              so that one mesh width h = (y_hi - y_lo)/(n - 1) serves

@@ -177,9 +177,9 @@ __device__ __forceinline__ void dft(C* v) {
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
 // LDS slot of exchange element a: one pad slot per 16 elements.  Spreads the
-// radix-8 stage writes (stride 8 elements in the first stage) over distinct
-// banks while keeping the contiguous stage reads conflict free.  The exchange
-// buffer needs lds_slots(L) elements.
+// strided stage writes (stride R elements for radix R) over distinct banks
+// while keeping the contiguous stage reads conflict free.  The exchange buffer
+// needs lds_slots(L) elements.
 __device__ __forceinline__ int lds_slot(int a) { return a + (a >> 4); }
 constexpr int lds_slots(int L) { return L + L / 16; }
 

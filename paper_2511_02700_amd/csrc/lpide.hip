@@ -1237,7 +1237,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     // axis-1 line solves: 4 columns per block, chunks of about 8 rows
     p->P_cols = default_P_cols(n);
     if (!P_cols_valid(n, p->P_cols)) return bail(fail(LPIDE_E_PARAM, "n too large for the line solves"));
-    // threads x 8 of the row-pair kernels
+    // transform side of the row-pair kernels (without jumps: the power of two >= n)
     p->Lr = p->L;
     if (!p->jumps) {
         p->Lr = 64;

@@ -42,7 +42,7 @@ struct Launch {
     hipStream_t stream = nullptr;
     const MarchArgs* A = nullptr;   // device array, np entries
     int np = 0;
-    int L = 0;                      // Lr of the plans (threads x 8 of the row kernels)
+    int L = 0;                      // Lr of the plans (transform side of the row kernels)
     int xrows = 0;                  // max row pairs
     int xcols = 0;                  // max 4-column groups of the axis-1 line solves
     int xaff = 0;                   // max rows (affine kernels without jumps)
@@ -90,7 +90,7 @@ struct Plan {
     int N_t = 1;
     hipStream_t stream = nullptr;
     int L = 0;        // FFT side (0 without jumps)
-    int Lr = 0;       // threads x 8 of the row-pair kernels (L, or a power of two >= n without jumps)
+    int Lr = 0;       // transform side of the row-pair kernels (L, or a power of two >= n without jumps)
     bool jumps = false;
     bool mixed = false;            // FP32 iteration correlations (needs jumps)
     std::vector<void*> allocs;
