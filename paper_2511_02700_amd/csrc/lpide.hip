@@ -444,7 +444,8 @@ int make_group(const std::vector<Plan*>& plans, hipStream_t stream, Group** out)
         g->maxsteps = std::max(g->maxsteps, p->n_steps);
     }
     c.xrows = (nmax + 1) / 2;
-    c.xcols = (nmax + 3) / 4;
+    c.cpb = line_cols_cpb(nmax, np);
+    c.xcols = (nmax + c.cpb - 1) / c.cpb;
     c.xaff = nmax;
     c.P_cols = default_P_cols(nmax);
     int rc = LPIDE_OK;
@@ -928,7 +929,8 @@ int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lp
     c.np = 1;
     c.L = p->Lr;
     c.xrows = (n + 1) / 2;
-    c.xcols = (n + 3) / 4;
+    c.cpb = line_cols_cpb(n, 1);
+    c.xcols = (n + c.cpb - 1) / c.cpb;
     c.xaff = n;
     c.P_cols = p->solo->lc.P_cols;
     c.sl_order = p->hp.sl_order;

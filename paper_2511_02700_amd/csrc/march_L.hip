@@ -38,6 +38,20 @@ void launch_rows_fwd(Plan* p, const double* Y, hipStream_t s) {
     hipLaunchKernelGGL((k_rows_fwd<L>), dim3((n + 1) / 2), dim3(L / conv_e(L)), 0, s, Y, n, n, n, p->X, n, p->tw);
 }
 
+// The axis-1 line-solve kernel for the launch's columns per block; bounds of
+// 256 threads where the block fits (no register cap of 128).
+template <typename Go>
+void with_line_cols(const Launch& c, Go&& go) {
+    const bool small = c.cpb * c.P_cols <= 256;
+    if (c.cpb == 2) {
+        if (small) go(ks_line_cols<2, 256>);
+        else go(ks_line_cols<2, 1024>);
+    } else {
+        if (small) go(ks_line_cols<4, 256>);
+        else go(ks_line_cols<4, 1024>);
+    }
+}
+
 template <int L, bool FFT, bool MIXED>
 void launch_iteration(const Launch& c, int k) {
     using C = typename std::conditional<MIXED, float2, double2>::type;
@@ -62,13 +76,10 @@ void launch_iteration(const Launch& c, int k) {
     }
     {
         KTime t(c.timer, LPIDE_K_LINE_COLS);
-        // blocks of 4 P_cols threads: bounds of 256 where they fit (no register cap of 128)
-        if (4 * c.P_cols <= 256)
-            t.launch(ks_line_cols<4, 256>, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
-                     c.stream, c.A, k);
-        else
-            t.launch(ks_line_cols<4, 1024>, dim3(c.xcols, c.np), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
-                     c.stream, c.A, k);
+        with_line_cols(c, [&](auto kern) {
+            t.launch(kern, dim3(c.xcols, c.np), dim3(c.cpb * c.P_cols), sizeof(double2) * c.cpb * c.P_cols, c.stream,
+                     c.A, k);
+        });
     }
     KTime t(c.timer, LPIDE_K_LINE_ROWS);
     with_E<L>(c.E_lrows, [&](auto e) {
@@ -158,12 +169,10 @@ void launch_adj_iteration(const Launch& c, int k) {
         constexpr int E = decltype(e)::value;
         hipLaunchKernelGGL((ks_rows_inv<L, E, 3>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);
     });
-    if (4 * c.P_cols <= 256)
-        hipLaunchKernelGGL((ks_line_cols<4, 256>), dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
+    with_line_cols(c, [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(c.xcols, 1), dim3(c.cpb * c.P_cols), sizeof(double2) * c.cpb * c.P_cols,
                            c.stream, c.A, k);
-    else
-        hipLaunchKernelGGL((ks_line_cols<4, 1024>), dim3(c.xcols, 1), dim3(4 * c.P_cols), sizeof(double2) * 4 * c.P_cols,
-                           c.stream, c.A, k);
+    });
     with_E<L>(c.E_lrows, [&](auto e) {
         constexpr int E = decltype(e)::value;
         hipLaunchKernelGGL((ks_line_rows<L, E, true, false>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);

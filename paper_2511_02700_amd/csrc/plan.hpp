@@ -44,7 +44,8 @@ struct Launch {
     int np = 0;
     int L = 0;                      // Lr of the plans (transform side of the row kernels)
     int xrows = 0;                  // max row pairs
-    int xcols = 0;                  // max 4-column groups of the axis-1 line solves
+    int cpb = 4;                    // columns per block of the axis-1 line solves (2 or 4)
+    int xcols = 0;                  // max column groups of the axis-1 line solves
     int xaff = 0;                   // max rows (affine kernels without jumps)
     int P_cols = 16;
     int sl_order = 3;
@@ -204,6 +205,11 @@ void with_E(int E, F&& f) {
     }
     f(std::integral_constant<int, 4>{});
 }
+
+// Columns per block of the axis-1 line solves: 4 adjacent columns share cache
+// lines, but when the groups of 4 would leave CUs idle (fewer blocks than
+// CUs over the whole group of plans) blocks take 2.
+inline int line_cols_cpb(int nmax, int np) { return ((nmax + 3) / 4) * np < 256 ? 2 : 4; }
 
 double bits_d(unsigned long long b);
 
