@@ -366,7 +366,7 @@ int lpide_batch_solve_steps(void* batch, int32_t steps, double* const* v_out);
 
 /* Autotuner: for each group, time the march of the first trial_steps entries
  * under candidate launch configurations and keep the fastest, in three
- * rounds: the FFT radix schedule (4, 8 or 16 elements per thread, per kernel
+ * passes: the FFT radix schedule (4, 8 or 16 elements per thread, per kernel
  * class, one class at a time from the default), the axis-1
  * line-solve chunking P_cols in {P/2, P, 2P} around the default P, then
  * hipGraph replay on/off with 16 or 32 step slots per host check; each

@@ -1657,7 +1657,7 @@ int lpide_batch_solve_steps(void* batch, int32_t steps, double* const* v_out) {
 }
 
 // Autotuning: per group, time the march of the first trial_steps entries
-// under candidate launch configurations and keep the fastest, in three rounds:
+// under candidate launch configurations and keep the fastest, in three passes:
 // the radix schedule of the FFT kernels (4, 8 or 16 elements per thread), then
 // the axis-1 line-solve chunking P_cols (P/2, P, 2P around the default), then
 // hipGraph replay on/off with 16 or 32 step slots per host check.  Each
@@ -1688,7 +1688,7 @@ int lpide_batch_tune(void* batch, int32_t trial_steps) {
         };
         double best = 1e300, ms = 0.0;
         int rc = LPIDE_OK;
-        // round 1: radix schedule, one kernel class at a time from the default
+        // pass 1: radix schedule, one kernel class at a time from the default
         Schedule bs = g->lc.E_cols ? Schedule{g->lc.E_cols, g->lc.E_rinv, g->lc.E_lrows, g->lc.E_sl}
                                    : default_schedule(g->lc.L);
         g->use_graph = true;
@@ -1704,7 +1704,7 @@ int lpide_batch_tune(void* batch, int32_t trial_steps) {
                 if (ms < best) { best = ms; bs = t; }
             }
         if ((rc = set_schedule(g, bs))) return rc;
-        // round 2: line-solve chunking
+        // pass 2: line-solve chunking
         const int P0 = default_P_cols(nmax);
         int bP = g->lc.P_cols;
         best = 1e300;
@@ -1716,7 +1716,7 @@ int lpide_batch_tune(void* batch, int32_t trial_steps) {
             if (ms < best) { best = ms; bP = P; }
         }
         if ((rc = set_P_cols(g, bP))) return rc;
-        // round 3: graph replay and slots
+        // pass 3: graph replay and slots
         int bG = 1, bS = 32;
         best = 1e300;
         for (int G : {0, 1})
