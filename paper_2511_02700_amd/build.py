@@ -44,6 +44,9 @@ def _compile(src, obj, extra, verbose):
 def build(verbose=False, jobs=None):
     """Compile every translation unit (always) and link liblpide.so; returns its path."""
     jobs = jobs or max(1, min(len(UNITS), os.cpu_count() or 1, 16))
+    # a failed build leaves no library behind, so nothing runs stale code
+    if os.path.exists(LIB):
+        os.remove(LIB)
     objs = [os.path.join(CSRC, o) for _, o, _ in UNITS]
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         futs = [ex.submit(_compile, src, obj, extra, verbose) for (src, _, extra), obj in zip(UNITS, objs)]

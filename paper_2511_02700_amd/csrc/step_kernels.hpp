@@ -359,16 +359,20 @@ __global__ __launch_bounds__(L / E) void ks_sl(const MarchArgs* __restrict__ A) 
         cf[q] = c->coef[q];
     }
     const double* V = a.pool[c->cur];
-    C reg[E];
+    // Two phases: the gathers and the history reads of every element first,
+    // then the writes (the compiler cannot tell that W and Y alias none of the
+    // read grids, so reads after writes would wait for each element in turn).
+    double wv[E][2], yv[E][2], yf[E][2];   // W, Y^0, and the row-transform input
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int j = tid + e * T;
-        double y0[2] = {0.0, 0.0};
+        wv[e][0] = wv[e][1] = yv[e][0] = yv[e][1] = yf[e][0] = yf[e][1] = 0.0;
         if (j < n) {
             const int b0 = sd.s2[j];
             double w2[P + 1];
 #pragma unroll
             for (int b = 0; b <= P; ++b) w2[b] = sd.w2[j * (P + 1) + b];
+#pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int i = ra + r;
                 if (r == 1 && !hasb) break;
@@ -383,14 +387,30 @@ __global__ __launch_bounds__(L / E) void ks_sl(const MarchArgs* __restrict__ A) 
                     acc += sd.w1[i * (P + 1) + aa] * s;
                 }
                 const size_t o = (size_t)i * n + j;
-                a.W[o] = acc;
+                wv[e][r] = acc;
                 // unrolled with a predicate, so the history reads are all in flight together
-                double yv = 0.0;
+                double y = 0.0;
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (q < nsrc) yv += cf[q] * H[q][o];
-                Y[o] = yv;
-                y0[r] = MIXED ? yv - V[o] : yv;
+                    if (q < nsrc) y += cf[q] * H[q][o];
+                yv[e][r] = y;
+                yf[e][r] = MIXED ? y - V[o] : y;      // the mixed form transforms Y^0 - V^{n-1}
+            }
+        }
+    }
+    C reg[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = tid + e * T;
+        double y0[2] = {0.0, 0.0};
+        if (j < n) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                if (r == 1 && !hasb) break;
+                const size_t o = (size_t)(ra + r) * n + j;
+                a.W[o] = wv[e][r];
+                Y[o] = yv[e][r];
+                y0[r] = yf[e][r];
             }
         }
         reg[e] = CplxOps<C>::make(y0[0], y0[1]);
@@ -438,10 +458,9 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
     // union: row buffer 2 (n + PR + 1) doubles (n <= L) | scan totals | FFT exchange buffer
     __shared__ double2 lds[L + (PR > L / 16 ? PR : L / 16) + 2];
     __shared__ double2 tw4[FFT ? tw_slots<L, E>() : 1];
-    // Up to L = 1024 the line factors are staged in LDS and the iterate values
-    // are fetched into registers at the start, so that every global read of the
-    // kernel is issued before the first barrier (at these sizes a block's time
-    // is mostly the latency of dependent global reads).
+    // Up to L = 1024 the line factors are staged in LDS, so that every global
+    // read of the kernel is issued before the first barrier (at these sizes a
+    // block's time is mostly the latency of dependent global reads).
     constexpr bool PF = L <= 1024;
     __shared__ double fac[PF ? 3 * L : 1];
     if constexpr (FFT) load_twiddles<L, E>(a.tw, tw4);
@@ -453,14 +472,17 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
     const int stride = n + PR + 1;
     const StepDesc& sd = cur_set(a);
     double* Y = a.pool[a.ctl->y];
-    double yoa[PF ? E : 1], yob[PF ? E : 1];
-    if constexpr (PF) {
+    // the iterate values are fetched into registers at the start at every
+    // size: read after the writes of the update they would wait element by
+    // element (the compiler cannot separate them)
+    double yoa[E], yob[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int j = tid + e * T;
-            yoa[e] = j < n ? Y[(size_t)ra * n + j] : 0.0;
-            yob[e] = (j < n && hasb) ? Y[(size_t)rb * n + j] : 0.0;
-        }
+    for (int e = 0; e < E; ++e) {
+        const int j = tid + e * T;
+        yoa[e] = j < n ? Y[(size_t)ra * n + j] : 0.0;
+        yob[e] = (j < n && hasb) ? Y[(size_t)rb * n + j] : 0.0;
+    }
+    if constexpr (PF) {
         for (int i = tid; i < n; i += T) {
             fac[i] = sd.fl2[i];
             fac[L + i] = sd.bu2[i];
@@ -494,14 +516,14 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
         if (j < n) {
             da = rows[j + j / m];
             const size_t oa = (size_t)ra * n + j;
-            ya = (PF ? yoa[e] : Y[oa]) + da;
+            ya = yoa[e] + da;
             Y[oa] = ya;
             double ev = fabs(da) / fmax(1.0, fabs(ya));
             emax = (ev > emax || ev != ev) ? ev : emax;
             if (hasb) {
                 db = rows[stride + j + j / m];
                 const size_t ob = (size_t)rb * n + j;
-                yb = (PF ? yob[e] : Y[ob]) + db;
+                yb = yob[e] + db;
                 Y[ob] = yb;
                 ev = fabs(db) / fmax(1.0, fabs(yb));
                 emax = (ev > emax || ev != ev) ? ev : emax;
