@@ -16,7 +16,8 @@ Printed (one JSON line): the metric, the roofline of the dominant kernel
 kernel's own dispatches on the plan's stream, over the timed solves), the same for the correlation's
 column pass, the other precision timed beside it with the mixed-vs-plain
 differences, and a CPU baseline: the FP64 oracle timed on this host on a
-bounded sample of the same workload.  Unless --no-extras: the column-pass
+bounded sample of the same workload, and the plan time (host discretization,
+spectrum, factors).  Unless --no-extras: the column-pass
 roofline at 2048^2 (cache-exceeding working set), whole 2048^2 solves in
 both precisions, the paper's Table 3 prices against GPU marches, the adjoint
 form on its
@@ -213,8 +214,12 @@ def large_solve(lp, name="nig2048_m"):
         name, w["n"], w["n"], w["y_lo"], w["y_hi"], w["N_t"], w["model"]["alpha"], w["model"]["corr"])}
     prices = {}
     for prec in ("fp64", "fp32conv", "fp64_pow2"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         plan = (lp.plan_from_workload(w, precision=prec) if prec != "fp64_pow2" else
                 lp.plan_from_workload(w, fft_size=1 << (out.get("L", 2) - 1).bit_length()))
+        torch.cuda.synchronize()
+        plan_ms = 1e3 * (time.perf_counter() - t0)
         V = plan.solve()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -226,7 +231,7 @@ def large_solve(lp, name="nig2048_m"):
         out.setdefault("L", info["L"])
         out[prec] = {"value": w["n"] ** 2 * w["N_t"] / dt, "unit": "grid-pt-steps/s", "ms": 1e3 * dt,
                      "iters_per_step": info["total_iters"] / info["n_steps"], "radix": info["radix"],
-                     "L": info["L"]}
+                     "L": info["L"], "plan_ms": plan_ms}
         del plan, V
         torch.cuda.empty_cache()
     out["mixed_vs_plain_prices_rel"] = float(np.max(np.abs(prices["fp32conv"] - prices["fp64"]) /
@@ -373,8 +378,14 @@ def main():
     w = workloads.workload(args.workload)
     n, Nt = w["n"], w["N_t"]
     other = "fp32conv" if args.precision == "fp64" else "fp64"
-    plans = {pr: lp.plan_from_workload(w, sl_order=args.sl_order, precision=pr, fft_size=args.fft_size)
-             for pr in (args.precision, other)}
+    plan_ms = {}
+    plans = {}
+    for pr in (args.precision, other):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plans[pr] = lp.plan_from_workload(w, sl_order=args.sl_order, precision=pr, fft_size=args.fft_size)
+        torch.cuda.synchronize()
+        plan_ms[pr] = 1e3 * (time.perf_counter() - t0)
     plan = plans[args.precision]
     mixed = args.precision == "fp32conv"
     info = plan.info()
@@ -441,6 +452,7 @@ def main():
                              radix=info["radix"]),
         "conv_roofline": roofline("cols", n, L, mixed, *live["cols"], traffic_json=tj, sl_order=args.sl_order,
                                   radix=info["radix"]),
+        "plan_ms": plan_ms[args.precision],
         "conv_whole": conv_whole(n, L, mixed, live),
         "radix_schedule": dict(zip(("cols", "row_c2r", "line_rows", "sl"), info["radix"])),
         "iters_per_step": info["total_iters"] / info["n_steps"],
