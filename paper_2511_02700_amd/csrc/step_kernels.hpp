@@ -127,6 +127,14 @@ __device__ __forceinline__ void err_reset(Ctl* c) {
         c->err[q / KSLOTS][q % KSLOTS] = (q % KSLOTS) == 0 ? 0x7FF0000000000000ull : 0ull;
 }
 
+// The same for slots 0..kmax only: a step that ran iterations 1..kmax wrote
+// no other slot, and every other slot is still zero from an earlier reset.
+__device__ __forceinline__ void err_reset_upto(Ctl* c, int kmax) {
+    const int w = kmax + 1;
+    for (int q = threadIdx.x; q < NX * w; q += blockDim.x)
+        c->err[q / w][q % w] = (q % w) == 0 ? 0x7FF0000000000000ull : 0ull;
+}
+
 // Uniform early-exit test of iteration k (k = 0: parts that run once per step).
 __device__ __forceinline__ bool halted(const MarchArgs& a, int k) {
     const Ctl* c = a.ctl;
@@ -613,7 +621,7 @@ static __global__ void ks_step_end(const MarchArgs* __restrict__ A, int kmax) {
         }
     }
     __syncthreads();
-    if (ok) err_reset(c);
+    if (ok) err_reset_upto(c, kmax);
 }
 
 // Recording for the adjoint march.  After sl (once per step): E_s, held in R
