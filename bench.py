@@ -65,6 +65,8 @@ def algorithmic_bytes(cls, n, L, mixed=False):
         "expl_rows": 2 * 8 * n * hc + (3 if mixed else 2) * 8 * n * n,
         # read V, write X
         "rows_fwd": 8 * n * n + 2 * 8 * n * hc,
+        # mixed form between anchors: read B Y, write B V, read V, write E
+        "carry": 4 * 8 * n * n,
     }[cls]
 
 
@@ -84,6 +86,7 @@ def kernel_symbol(cls, L, mixed, sl_order, radix=(8, 8, 8, 8)):
         "sl": "lpide::ks_sl<%d, %d, %d, true, %s>" % (L, es, sl_order, tf),
         "step_end": "lpide::ks_step_end",
         "rows_fwd": "lpide::ks_rows_fwd<%d, %d>" % (L, er),
+        "carry": "lpide::ks_carry",
     }[cls]
 
 

@@ -55,12 +55,14 @@ extern "C" {
 #define LPIDE_EXCHANGE  4   /* S1 - S2  (K only sets the log-moneyness origin) */
 #define LPIDE_SPREAD    5   /* S1 - S2 - K  (spread call, among the extensions of Sec. 5) */
 
-/* Arithmetic of the FFT correlation.  In the mixed form every time step applies
- * B to V^{n-1} once in FP64; the fixed-point iterations then apply B in FP32 to
- * increments only (Y^0 - V^{n-1}, then Y^k - Y^{k-1}) and accumulate B Y^k in
- * FP64, with twiddles entering in FP64 accuracy (split into two FP32 parts).
- * The FP32 error is relative to the increments, so prices stay within about
- * 1e-8 relative of the FP64 form.  Without jumps the precision has no effect. */
+/* Arithmetic of the FFT correlation.  In the mixed form the fixed-point
+ * iterations apply B in FP32 to increments only (Y^0 - V^{n-1}, then
+ * Y^k - Y^{k-1}) and accumulate B Y^k in FP64, with twiddles entering in FP64
+ * accuracy (split into two FP32 parts).  B V^{n-1} is carried in FP64 from one
+ * step to the next (the previous step's accumulated B Y) and computed afresh by
+ * the FP64 correlation every lpide_opts.mixed_anchor steps.  The FP32 error is
+ * relative to the increments, so prices stay within about 1e-8 relative of the
+ * FP64 form.  Without jumps the precision has no effect. */
 #define LPIDE_FP64       0  /* everything in FP64 */
 #define LPIDE_FP32_CONV  1  /* iteration correlations in FP32 on increments, all else FP64 */
 
@@ -126,6 +128,10 @@ typedef struct {
                              otherwise one of the supported sizes 64, 128, 256, 512, 768, 1024,
                              1536, 2048, 3072, 4096 that is at least that bound (LPIDE_E_PARAM
                              if not).  Ignored without jumps. */
+    int32_t mixed_anchor; /* mixed form: B V^{n-1} is computed afresh by the FP64 correlation
+                             every mixed_anchor steps (the first step of a march always); in
+                             the steps between it is carried from the previous step's FP64
+                             sum B Y.  0: 8.  1: every step. */
 } lpide_opts;
 
 /* Plan-time quantities and run statistics. */
@@ -241,10 +247,11 @@ int lpide_discretize_host(const lpide_grid* grid, const lpide_levy* levy, const 
                                   of Y (of the increment in the mixed form) */
 #define LPIDE_K_SL         4   /* semi-Lagrangian gather + extrapolated start + row FFT of Y^0 */
 #define LPIDE_K_STEP_END   5   /* end-of-step control (convergence verdict, history rotation) */
-#define LPIDE_K_EXPL_COLS  6   /* FP64 column pass of B V^{n-1} (theta < 1, or the mixed form) */
-#define LPIDE_K_EXPL_ROWS  7   /* row inverse FFTs + explicit part (E, and B V^{n-1} when mixed) */
-#define LPIDE_K_ROWS_FWD   8   /* FP64 row FFTs of V^{n-1} (mixed form) */
-#define LPIDE_KCLASSES     9
+#define LPIDE_K_EXPL_COLS  6   /* FP64 column pass of B V^{n-1} (theta < 1; mixed form: anchor steps) */
+#define LPIDE_K_EXPL_ROWS  7   /* row inverse FFTs + explicit part (E, and B V^{n-1} at mixed anchors) */
+#define LPIDE_K_ROWS_FWD   8   /* FP64 row FFTs of V^{n-1} (mixed form, anchor steps) */
+#define LPIDE_K_CARRY      9   /* mixed form between anchors: B V^{n-1} carried, explicit part */
+#define LPIDE_KCLASSES    10
 
 /* Kernel timing.  With bit c of class_mask set, every launch of kernel class c
  * in single-plan marches carries a start and a stop HIP event bound to the

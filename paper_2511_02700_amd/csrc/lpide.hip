@@ -226,6 +226,12 @@ int harvest_times(Plan* p) {
         if ((r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS) && known && !p->mixed &&
             p->sets[p->step_set[r.step]].theta >= 1.0)
             continue;
+        if (p->mixed && known) {            // the mixed form runs either the anchor kernels or the carry
+            const bool anchor = (r.step - p->march_step0) % p->anchor_every == 0;
+            const bool anchor_cls =
+                r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS || r.cls == LPIDE_K_ROWS_FWD;
+            if ((anchor_cls && !anchor) || (r.cls == LPIDE_K_CARRY && anchor)) continue;
+        }
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[r.idx], p->ev_pool[r.idx + 1]));
         p->k_launch[r.cls] += 1;
@@ -301,6 +307,7 @@ MarchArgs march_args(const Plan* p) {
     a.BY = p->BY;
     a.nsteps = p->n_steps;
     a.step0 = 0;
+    a.anchor_every = p->anchor_every;
     return a;
 }
 
@@ -594,6 +601,7 @@ int march_begin(Group* g, MarchState& st, const int* nsteps, int step0, const do
     st.at.assign(np, step0);
     st.step0 = step0;
     st.done = false;
+    for (Plan* p : g->plans) p->march_step0 = step0;
     for (int i = 0; i < np; ++i) {
         Plan* p = g->plans[i];
         const int n = p->hp.n;
@@ -1197,6 +1205,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     if (o.max_iter > MAX_ITER_CAP) return fail(LPIDE_E_PARAM, "max_iter must not exceed 128");
     if (o.fft_radix != 0 && o.fft_radix != 4 && o.fft_radix != 8 && o.fft_radix != 16)
         return fail(LPIDE_E_PARAM, "fft_radix must be 0, 4, 8 or 16");
+    if (o.mixed_anchor < 0) return fail(LPIDE_E_PARAM, "mixed_anchor must be >= 0");
     Plan* p = new Plan();
     std::string err;
     if (!build_host_plan(*grid, *levy, p->hp, err)) { delete p; return fail(LPIDE_E_PARAM, err); }
@@ -1210,6 +1219,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     p->stream = static_cast<hipStream_t>(o.stream);
     p->jumps = p->hp.nts.jumps;
     p->mixed = p->jumps && o.precision == LPIDE_FP32_CONV;
+    p->anchor_every = o.mixed_anchor > 0 ? o.mixed_anchor : 8;
     if (p->jumps && o.fft_size != 0) {
         if (!fft_size_supported(o.fft_size) || o.fft_size < p->hp.L_need) {
             const std::string msg = "fft_size " + std::to_string(o.fft_size) +

@@ -113,11 +113,17 @@ void launch_step(const Launch& c, int kmax) {
                 t.launch((ks_cols<L, E, double2>), gc, dim3(L / E), 0, c.stream, c.A, 0);
             });
         }
-        KTime t(c.timer, LPIDE_K_EXPL_ROWS);
-        with_E<L>(c.E_rinv, [&](auto e) {
-            constexpr int E = decltype(e)::value;
-            t.launch((ks_rows_inv<L, E, 0>), gr, dim3(L / E), 0, c.stream, c.A, 0);
-        });
+        {
+            KTime t(c.timer, LPIDE_K_EXPL_ROWS);
+            with_E<L>(c.E_rinv, [&](auto e) {
+                constexpr int E = decltype(e)::value;
+                t.launch((ks_rows_inv<L, E, 0>), gr, dim3(L / E), 0, c.stream, c.A, 0);
+            });
+        }
+        if (MIXED) {                      // steps between anchors: B V^{n-1} carried (the three above exit)
+            KTime t(c.timer, LPIDE_K_CARRY);
+            t.launch(ks_carry, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
+        }
     } else {
         KTime t(c.timer, LPIDE_K_EXPL_ROWS);
         t.launch((ks_affine_noB<true>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, 0);

@@ -117,6 +117,8 @@ struct Plan {
     Group* solo = nullptr;         // this plan alone, on its own stream
     // adjoint march (allocated on the first lpide_adjoint call)
     struct Adjoint* adj = nullptr;
+    int anchor_every = 8;          // mixed form: FP64 B V^{n-1} afresh every this many steps
+    int march_step0 = 0;           // first step of the last march (anchors count from it)
     int ckpt_every = 0;            // lpide_solve records checkpoints every this many steps (0: none)
     bool ckpt_valid = false;       // checkpoints of the last full solve are in adj->ckpt
     std::vector<int> counts_h;     // per-step iteration counts of the last march

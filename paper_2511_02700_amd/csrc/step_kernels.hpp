@@ -102,6 +102,7 @@ struct MarchArgs {
     double* seg;                      // recorded states: V^s to seg[(s - seg_base) / seg_every] (or null)
     double* segE;                     // recorded explicit parts E_s = M_E V^s to segE[s - seg_base] (theta < 1)
     int seg_base, seg_every;
+    int anchor_every;                 // mixed form: B V^{n-1} afresh in FP64 every this many steps
 };
 
 template <typename C> __device__ __forceinline__ C* xbuf(const MarchArgs& a);
@@ -150,6 +151,20 @@ __device__ __forceinline__ const StepDesc& cur_set(const MarchArgs& a) { return 
 
 __device__ __forceinline__ bool needs_explicit(const MarchArgs& a) { return a.mixed || cur_set(a).theta < 1.0; }
 
+// Mixed form: the steps whose B V^{n-1} is computed afresh by the FP64
+// correlation (every anchor_every-th step of the march, its first step
+// included).  In the others B V^{n-1} is carried from the previous step
+// (ks_carry).
+__device__ __forceinline__ bool is_anchor(const MarchArgs& a) {
+    return (a.ctl->step - a.step0) % a.anchor_every == 0;
+}
+
+// Whether the step runs the FP64 correlation of V^{n-1}: for the explicit part
+// (theta < 1), or to anchor B V^{n-1} in the mixed form.
+__device__ __forceinline__ bool needs_explicit_fft(const MarchArgs& a) {
+    return a.mixed ? is_anchor(a) : cur_set(a).theta < 1.0;
+}
+
 // The plan of this block.
 __device__ __forceinline__ const MarchArgs& plan_args(const MarchArgs* __restrict__ A) { return A[blockIdx.y]; }
 
@@ -160,7 +175,7 @@ __device__ __forceinline__ const MarchArgs& plan_args(const MarchArgs* __restric
 template <int L, int E, typename C, bool CONJ = false>
 __global__ __launch_bounds__(L / E) void ks_cols(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
-    if (halted(a, k) || (k == 0 && !needs_explicit(a))) return;
+    if (halted(a, k) || (k == 0 && !needs_explicit_fft(a))) return;
     constexpr int T = L / E;
     __shared__ C lds[lds_slots(L)];
     __shared__ double2 tw4[tw_slots<L, E>()];
@@ -205,7 +220,7 @@ __global__ __launch_bounds__(L / E) void ks_rows_fwd(const MarchArgs* __restrict
 template <int L, int E, int MODE>
 __global__ __launch_bounds__(L / E) void ks_rows_inv(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
-    if (halted(a, k) || ((MODE == 0 || MODE == 4) && !needs_explicit(a))) return;
+    if (halted(a, k) || ((MODE == 0 || MODE == 4) && !needs_explicit_fft(a))) return;
     using C = typename std::conditional<MODE == 2, float2, double2>::type;
     constexpr int T = L / E;
     const int n = a.n, np = (n + 1) >> 1;
@@ -290,6 +305,33 @@ __global__ __launch_bounds__(256) void ks_affine_noB(const MarchArgs* __restrict
     }
 }
 
+// Mixed form, steps between anchors: B V^{n-1} is carried from the previous
+// step, whose last iteration left B Y in BY (FP64 sums of FP32 correlations of
+// the increments; it misses B applied to the final increment, which is below
+// the stopping tolerance), and the explicit part
+// E = V + dt (1 - theta)((D - r_omega) V + B V) (theta < 1) is formed without
+// a correlation.  One block per grid row.
+static __global__ __launch_bounds__(256) void ks_carry(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, 0) || !a.mixed || is_anchor(a)) return;
+    const int n = a.n;
+    const int i = blockIdx.x;
+    if (i >= n) return;
+    const StepDesc& sd = cur_set(a);
+    const double* U = a.pool[a.ctl->cur];
+    const double c = sd.dt * (1.0 - sd.theta);
+    const bool want_r = sd.theta < 1.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const size_t o = (size_t)i * n + j;
+        const double bv = a.BY[o];
+        a.BV[o] = bv;
+        if (want_r) {
+            const double u = U[o];
+            a.R[o] = u + c * (apply_D(U, a.st, i, j, u) + bv - a.r_omega * u);
+        }
+    }
+}
+
 // Forward FFT of the row pair held in reg (canonical layout) into the
 // transposed half spectra X[k2 * n + row].
 template <int L, int E, typename C>
@@ -315,7 +357,7 @@ __device__ __forceinline__ void rows_fwd_store(C (&reg)[E], C* lds, const double
 template <int L, int E>
 __global__ __launch_bounds__(L / E) void ks_rows_fwd(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
-    if (halted(a, 0) || !a.mixed) return;
+    if (halted(a, 0) || !a.mixed || !is_anchor(a)) return;
     constexpr int T = L / E;
     const int n = a.n, np = (n + 1) >> 1;
     const int p = xcd_remap(blockIdx.x, gridDim.x);

@@ -83,15 +83,48 @@ def test_mixed_ragged_sizes(lp, n):
 
 
 def test_mixed_steps_prefix(lp):
-    """Inside and after the damped block (every step re-anchors B V^{n-1} in FP64)."""
-    w = workloads.workload("nig64", n=40, N_t=8, y_lo=-2.5, y_hi=2.5)
+    """Inside and after the damped block, and marches that end between two
+    FP64 anchors of B V^{n-1} (every 8 steps by default)."""
+    w = workloads.workload("nig64", n=40, N_t=16, y_lo=-2.5, y_hi=2.5)
     plan = lp.plan_from_workload(w, precision="fp32conv")
     prob = _oracle_problem(w)
-    for k in (0, 1, 4, 7):
+    for k in (0, 1, 4, 7, 9, 13):
         _note("mixed solve_steps k=%d" % k)
         Vg = plan.solve_steps(k).cpu().numpy()
         Vo, _ = scheme.solve(prob, tol=1e-14, n_steps=k)
         assert _rel(Vg, Vo) < TOL_MIXED, k
+
+
+@pytest.mark.parametrize("anchor", [1, 3, 8, 40])
+def test_mixed_anchor_spacing(lp, anchor):
+    """B V^{n-1} carried between FP64 anchors every `anchor` steps (40: only the
+    first step of the march is anchored): 64 x 64 NIG, 32 steps, vs the oracle."""
+    _note("mixed anchor every %d" % anchor)
+    w = workloads.workload("nig64")
+    plan = lp.plan_from_workload(w, precision="fp32conv", mixed_anchor=anchor)
+    Vg = plan.solve().cpu().numpy()
+    Vo, _ = scheme.solve(_oracle_problem(w), tol=1e-14)
+    e = _rel(Vg, Vo)
+    _note("mixed anchor every %d: grid %.2e, iterations %d" % (anchor, e, plan.info()["total_iters"]))
+    assert e < TOL_MIXED
+
+
+def test_mixed_range_restart_between_anchors(lp):
+    """A march resumed at a step that is not a multiple of the anchor spacing
+    anchors its own first step: steps 0..5 then 5..16 equal 0..16 within the bar."""
+    _note("mixed solve_range restart at step 5")
+    w = workloads.workload("nig64", n=40, N_t=16, y_lo=-2.5, y_hi=2.5)
+    plan = lp.plan_from_workload(w, precision="fp32conv")
+    n_steps = plan.info()["n_steps"]
+    mid = plan.solve_steps(5)
+    Vr = plan.solve_range(5, n_steps, mid).cpu().numpy()
+    Vo, _ = scheme.solve(_oracle_problem(w), tol=1e-14)
+    assert _rel(Vr, Vo) < TOL_MIXED
+
+
+def test_mixed_anchor_rejects_negative(lp):
+    with pytest.raises(lp.LpideError):
+        lp.plan_from_workload(workloads.workload("nig64", n=16, N_t=2), precision="fp32conv", mixed_anchor=-1)
 
 
 def test_mixed_fv512_first_steps_matches_oracle(lp):
