@@ -301,7 +301,10 @@ int lpide_plan_set_checkpoints(void* plan, int32_t every);
  * differentiated by central differences in the seven Levy parameters (step
  * 1e-4 max(|x|, 0.1), structure fixed) and exactly in r (it enters only
  * kappa_omega and r_omega, with unit slope); the Jacobian is cached per plan
- * and point.  Needs a plan with jumps.  Synchronises. */
+ * and point.  Needs a plan with jumps.  The reverse march is FP64; on a
+ * mixed-form plan the forward states it differentiates at (recomputed from
+ * the checkpoints, with B V anchored at each checkpoint) carry the mixed
+ * form's error.  Synchronises. */
 int lpide_adjoint(void* plan, const double* v_bar, int32_t checkpoint_every, const double* std_params,
                   double* grad, double* native, lpide_adjoint_info* info);
 

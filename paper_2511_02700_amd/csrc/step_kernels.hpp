@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void ks_affine_noB(const MarchArgs* __restrict
     const MarchArgs& a = plan_args(A);
     if (halted(a, k) || (EXPLICIT && !needs_explicit(a))) return;
     const int n = a.n;
-    const int i = blockIdx.x;
+    const int i = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows on one XCD (stencil reads share L2)
     if (i >= n) return;
     const StepDesc& sd = cur_set(a);
     const double* U = EXPLICIT ? a.pool[a.ctl->cur] : a.pool[a.ctl->y];
@@ -315,7 +315,7 @@ static __global__ __launch_bounds__(256) void ks_carry(const MarchArgs* __restri
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0) || !a.mixed || is_anchor(a)) return;
     const int n = a.n;
-    const int i = blockIdx.x;
+    const int i = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows on one XCD (stencil reads share L2)
     if (i >= n) return;
     const StepDesc& sd = cur_set(a);
     const double* U = a.pool[a.ctl->cur];
@@ -845,7 +845,7 @@ __global__ __launch_bounds__(256) void ks_adj_accum(const MarchArgs* __restrict_
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0)) return;
     const int n = a.n;
-    const int i = blockIdx.x;
+    const int i = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows on one XCD (stencil reads share L2)
     if (i >= n) return;
     const StepDesc& sd = cur_set(a);
     const double* lam = a.pool[a.ctl->y];
