@@ -305,6 +305,19 @@ def plan_from_workload(w, device=0, **over):
     return Plan(g, lv, pay, theta=w["theta"], M=w["N_t"], tol=over.pop("tol", w["tol"]), device=device, **over)
 
 
+def solve(grid, levy, payoff, theta=0.5, M=32, **opts):
+    """One-shot solve: plan, march every step, return V^{N_t} as an n x n
+    float64 tensor on the plan's device (lpide_plan, lpide_solve,
+    lpide_destroy).  opts are the Plan keywords (tol, precision, ...)."""
+    plan = Plan(grid, levy, payoff, theta=theta, M=M, **opts)
+    try:
+        v = plan.solve()
+        plan.stream.synchronize()
+        return v
+    finally:
+        plan.close()
+
+
 class PricesFn:
     """Prices at spot pairs as a differentiable function of the subordination
     parameters and the spots: ``PricesFn.apply(params, spots, grid_args,

@@ -4,7 +4,8 @@ explicit part and its correlation vanish; fully explicit theta = 0, where the
 implicit operator is the identity and the fixed point is reached at once),
 the march without damping, a single time step, plans without jumps whose grid
 fills the row transform (n equal to its side, the largest row buffer of the
-line-row kernel), an empty spot list and the Greeks on the smallest grid.
+line-row kernel), an empty spot list, the Greeks on the smallest grid and the
+one-shot solve helper.
 
 Bar: |a - b| / max(1, |b|) within 1e-10, as for the other marches.
 """
@@ -106,3 +107,17 @@ def test_empty_spot_list_and_smallest_greeks(lp):
     ref = output.greeks_on_grid(G, (-1.0, -1.0), 2.0 / 7, 100.0)
     for q in range(5):
         assert np.max(np.abs(got[q] - ref[q])) <= 1e-12 * np.max(np.abs(ref[q]))
+
+
+def test_one_shot_solve_helper(lp):
+    """lp.solve (plan, march, destroy in one call) gives the oracle's grid."""
+    w = workloads.workload("nig64", n=40, N_t=8, y_lo=-2.5, y_hi=2.5)
+    _note("one-shot solve helper")
+    m = w["model"]
+    lv = lp.levy_from_std(m["sigma1"], m["sigma2"], m["corr"], m["theta1"], m["theta2"], m["kappa"], m["alpha"],
+                          w["r"])
+    g = lp.make_grid(w["n"], w["y_lo"], w["y_hi"])
+    pay = lp.make_payoff(w["payoff"], w["K"], w["T"])
+    v = lp.solve(g, lv, pay, theta=w["theta"], M=w["N_t"], tol=w["tol"])
+    assert tuple(v.shape) == (w["n"], w["n"])
+    assert _rel(v.cpu().numpy(), _oracle(w)) < 1e-10
