@@ -67,6 +67,8 @@ def algorithmic_bytes(cls, n, L, mixed=False):
         "rows_fwd": 8 * n * n + 2 * 8 * n * hc,
         # mixed form between anchors: read B Y, write B V, read V, write E
         "carry": 4 * 8 * n * n,
+        # FP64 explicit part from the previous step's equation: read V and W, write E
+        "expl_id": 3 * 8 * n * n,
     }[cls]
 
 
@@ -87,6 +89,7 @@ def kernel_symbol(cls, L, mixed, sl_order, radix=(8, 8, 8, 8)):
         "step_end": "lpide::ks_step_end",
         "rows_fwd": "lpide::ks_rows_fwd<%d, %d>" % (L, er),
         "carry": "lpide::ks_carry",
+        "expl_id": "lpide::ks_expl_identity",
     }[cls]
 
 

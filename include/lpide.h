@@ -132,6 +132,15 @@ typedef struct {
                              every mixed_anchor steps (the first step of a march always); in
                              the steps between it is carried from the previous step's FP64
                              sum B Y.  0: 8.  1: every step. */
+    int32_t explicit_fft; /* FP64 form, theta < 1: 0 takes the explicit part
+                             E = V + dt (1 - theta) A V of a step from the implicit
+                             equation of the step before it, (I - c A) V = W with
+                             c = dt theta of that step: E = V + dt (1 - theta) (V - W) / c,
+                             exact at the fixed point of the theta-scheme (Sec. 3.3; the
+                             converged iterate leaves a residual below the stopping
+                             tolerance), so B is applied to V^{n-1} by the correlation only
+                             in the first step of a march and after steps with theta = 0.
+                             1: every step applies B to V^{n-1} by the correlation. */
 } lpide_opts;
 
 /* Plan-time quantities and run statistics. */
@@ -247,11 +256,13 @@ int lpide_discretize_host(const lpide_grid* grid, const lpide_levy* levy, const 
                                   of Y (of the increment in the mixed form) */
 #define LPIDE_K_SL         4   /* semi-Lagrangian gather + extrapolated start + row FFT of Y^0 */
 #define LPIDE_K_STEP_END   5   /* end-of-step control (convergence verdict, history rotation) */
-#define LPIDE_K_EXPL_COLS  6   /* FP64 column pass of B V^{n-1} (theta < 1; mixed form: anchor steps) */
+#define LPIDE_K_EXPL_COLS  6   /* FP64 column pass of B V^{n-1} (theta < 1: first step of a march or
+                                  explicit_fft; mixed form: anchor steps) */
 #define LPIDE_K_EXPL_ROWS  7   /* row inverse FFTs + explicit part (E, and B V^{n-1} at mixed anchors) */
 #define LPIDE_K_ROWS_FWD   8   /* FP64 row FFTs of V^{n-1} (mixed form, anchor steps) */
 #define LPIDE_K_CARRY      9   /* mixed form between anchors: B V^{n-1} carried, explicit part */
-#define LPIDE_KCLASSES    10
+#define LPIDE_K_EXPL_ID   10   /* FP64: explicit part from the previous step's implicit equation */
+#define LPIDE_KCLASSES    11
 
 /* Kernel timing.  With bit c of class_mask set, every launch of kernel class c
  * in single-plan marches carries a start and a stop HIP event bound to the

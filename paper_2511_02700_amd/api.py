@@ -80,7 +80,8 @@ class Plan:
     """A planned solve on one HIP device (see lpide_plan_create)."""
 
     def __init__(self, grid, levy, payoff, theta=0.5, M=32, tol=1e-12, max_iter=100, precision="fp64",
-                 damping=True, device=0, stream=None, fft_radix=0, fft_size=0, mixed_anchor=0):
+                 damping=True, device=0, stream=None, fft_radix=0, fft_size=0, mixed_anchor=0,
+                 explicit_fft=False):
         torch = _torch()
         o = Opts()
         lib().lpide_opts_default(C.byref(o))
@@ -89,6 +90,7 @@ class Plan:
         o.fft_radix = fft_radix
         o.fft_size = fft_size
         o.mixed_anchor = mixed_anchor
+        o.explicit_fft = 1 if explicit_fft else 0
         self.device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)

@@ -214,13 +214,16 @@ namespace detail {
 namespace {
 
 // Fold recorded event pairs into the per-class totals (synchronises the stream).
-// Launches of iterations after a step had converged, and per-step kernels that
-// had nothing to do (explicit part of a theta = 1 step), are left out, so the
-// totals describe working launches only.
+// Launches of iterations after a step had converged, per-step kernels that
+// had nothing to do (explicit part of a theta = 1 step, the variant of the
+// explicit part a step did not use) and the slots enqueued behind a step that
+// needed more iterations than predicted are left out, so the totals describe
+// working launches only.
 int harvest_times(Plan* p) {
     if (p->ev_recs.empty()) return LPIDE_OK;
     HIP_TRY(hipStreamSynchronize(p->stream));
     for (auto& r : p->ev_recs) {
+        if (r.cls < 0) continue;            // launched in a slot behind a step that needed more iterations (no-op)
         const bool known = r.step >= 0 && r.step < (int)p->counts_h.size();
         if (r.k > 0 && known && r.k > p->counts_h[r.step]) continue;
         if ((r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS) && known && !p->mixed &&
@@ -231,6 +234,12 @@ int harvest_times(Plan* p) {
             const bool anchor_cls =
                 r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS || r.cls == LPIDE_K_ROWS_FWD;
             if ((anchor_cls && !anchor) || (r.cls == LPIDE_K_CARRY && anchor)) continue;
+        }
+        if (!p->mixed && known) {           // FP64: the explicit correlation or the identity kernel
+            const bool ident = !p->opts.explicit_fft && r.step > p->march_step0 && p->cn_rho[r.step] > 0.0;
+            if (((r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS) && ident) ||
+                (r.cls == LPIDE_K_EXPL_ID && !ident))
+                continue;
         }
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[r.idx], p->ev_pool[r.idx + 1]));
@@ -308,6 +317,7 @@ MarchArgs march_args(const Plan* p) {
     a.nsteps = p->n_steps;
     a.step0 = 0;
     a.anchor_every = p->anchor_every;
+    a.cn_rho = (p->mixed || p->opts.explicit_fft) ? nullptr : p->cn_rho_d;
     return a;
 }
 
@@ -633,6 +643,7 @@ int march_enqueue(Group* g, MarchState& st) {
         st.done = true;
         return LPIDE_OK;
     }
+    if (g->lc.timer) g->lc.timer->ev_mark = g->lc.timer->ev_recs.size();
     return enqueue_slots(g, st.at[0], std::min(g->slots, remaining), st.kpred);
 }
 
@@ -644,6 +655,11 @@ int march_check(Group* g, MarchState& st) {
     int knext = 0;
     for (int i = 0; i < np; ++i) {
         if (g->ctl_h[i].fail) {
+            Plan* tp = g->lc.timer;
+            if (tp && tp == g->plans[i]) {  // the slots behind the failed step ran as no-ops; enqueued again later
+                for (size_t q = tp->ev_mark; q < tp->ev_recs.size(); ++q)
+                    if (tp->ev_recs[q].step > g->ctl_h[i].fail_step) tp->ev_recs[q].cls = -1;
+            }
             int k = 0;
             if ((rc = complete_step(g, i, st.kpred, &k))) return rc;
             knext = std::max(knext, k);
@@ -791,6 +807,7 @@ int adj_prepare(Plan* p, int C) {
     m.counts = a->counts;
     m.incs = a->incs;
     m.mixed = 0;
+    m.cn_rho = nullptr;                // the reverse march forms its explicit parts by the correlation
     m.nsteps = p->n_steps;
     m.seg = nullptr;
     m.segE = nullptr;
@@ -1206,6 +1223,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     if (o.fft_radix != 0 && o.fft_radix != 4 && o.fft_radix != 8 && o.fft_radix != 16)
         return fail(LPIDE_E_PARAM, "fft_radix must be 0, 4, 8 or 16");
     if (o.mixed_anchor < 0) return fail(LPIDE_E_PARAM, "mixed_anchor must be >= 0");
+    if (o.explicit_fft != 0 && o.explicit_fft != 1) return fail(LPIDE_E_PARAM, "explicit_fft must be 0 or 1");
     Plan* p = new Plan();
     std::string err;
     if (!build_host_plan(*grid, *levy, p->hp, err)) { delete p; return fail(LPIDE_E_PARAM, err); }
@@ -1293,6 +1311,15 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
         }
         if ((rc = upload(p, &p->sets_d, p->sets)) || (rc = upload(p, &p->step_set_d, p->step_set))) return bail(rc);
         p->counts_h.assign(p->n_steps, 0);
+        // rho of the explicit part from the previous step's implicit equation:
+        // dt (1 - theta) / (dt theta of the step before); 0 where the correlation is needed
+        p->cn_rho.assign(p->n_steps, 0.0);
+        for (int q = 1; q < p->n_steps; ++q) {
+            const StepDesc& cu = p->sets[p->step_set[q]];
+            const StepDesc& pr = p->sets[p->step_set[q - 1]];
+            if (cu.theta < 1.0 && pr.theta > 0.0) p->cn_rho[q] = cu.dt * (1.0 - cu.theta) / (pr.dt * pr.theta);
+        }
+        if ((rc = upload(p, &p->cn_rho_d, p->cn_rho))) return bail(rc);
     }
     // kernel spectrum conj(FFT(K placed at d mod L)) / L^2
     if (p->jumps) {

@@ -117,6 +117,8 @@ struct Plan {
     Group* solo = nullptr;         // this plan alone, on its own stream
     // adjoint march (allocated on the first lpide_adjoint call)
     struct Adjoint* adj = nullptr;
+    std::vector<double> cn_rho;    // per step: rho of the explicit part from the previous step's equation (0: none)
+    double* cn_rho_d = nullptr;
     int anchor_every = 8;          // mixed form: FP64 B V^{n-1} afresh every this many steps
     int march_step0 = 0;           // first step of the last march (anchors count from it)
     int ckpt_every = 0;            // lpide_solve records checkpoints every this many steps (0: none)
@@ -129,6 +131,7 @@ struct Plan {
     std::vector<EvRec> ev_recs;   // timed launches: class, start event, step and iteration (k = 0: once per step)
     int tag_step = -1, tag_k = 0; // step/iteration of the launches being enqueued
     size_t ev_used = 0;
+    size_t ev_mark = 0;           // first record of the slots enqueued last
     int64_t k_launch[LPIDE_KCLASSES] = {};
     double k_ms[LPIDE_KCLASSES] = {};
     // statistics of the last solve

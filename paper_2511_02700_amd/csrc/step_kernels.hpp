@@ -103,6 +103,8 @@ struct MarchArgs {
     double* segE;                     // recorded explicit parts E_s = M_E V^s to segE[s - seg_base] (theta < 1)
     int seg_base, seg_every;
     int anchor_every;                 // mixed form: B V^{n-1} afresh in FP64 every this many steps
+    const double* cn_rho;             // per step: rho of the explicit part from the previous step's
+                                      // implicit equation (0: by the correlation); null: never
 };
 
 template <typename C> __device__ __forceinline__ C* xbuf(const MarchArgs& a);
@@ -159,10 +161,24 @@ __device__ __forceinline__ bool is_anchor(const MarchArgs& a) {
     return (a.ctl->step - a.step0) % a.anchor_every == 0;
 }
 
+// Explicit part of a step from the implicit equation of the step before it.
+// That step solved (I - c A) V^{n-1} = W (c = dt theta of that step, W still
+// in a.W), so A V^{n-1} = (V^{n-1} - W) / c and
+//   E = V^{n-1} + dt (1 - theta) A V^{n-1} = V^{n-1} + rho (V^{n-1} - W),
+// rho = dt (1 - theta) / c: the same explicit part without applying B, exact
+// at the fixed point (the converged iterate leaves the stopping-rule residual).
+// Used from the second step of a march on, when the previous step had
+// theta > 0 (cn_rho > 0, set by the host; null for the mixed form and the
+// adjoint march).
+__device__ __forceinline__ bool explicit_by_identity(const MarchArgs& a) {
+    return a.cn_rho && a.ctl->step > a.step0 && a.cn_rho[a.ctl->step] > 0.0;
+}
+
 // Whether the step runs the FP64 correlation of V^{n-1}: for the explicit part
-// (theta < 1), or to anchor B V^{n-1} in the mixed form.
+// (theta < 1, unless it comes from the previous step's equation), or to anchor
+// B V^{n-1} in the mixed form.
 __device__ __forceinline__ bool needs_explicit_fft(const MarchArgs& a) {
-    return a.mixed ? is_anchor(a) : cur_set(a).theta < 1.0;
+    return a.mixed ? is_anchor(a) : (cur_set(a).theta < 1.0 && !explicit_by_identity(a));
 }
 
 // The plan of this block.
@@ -329,6 +345,24 @@ static __global__ __launch_bounds__(256) void ks_carry(const MarchArgs* __restri
             const double u = U[o];
             a.R[o] = u + c * (apply_D(U, a.st, i, j, u) + bv - a.r_omega * u);
         }
+    }
+}
+
+// Explicit part from the previous step's implicit equation (explicit_by_identity):
+// R = V + rho (V - W); one block per grid row.
+static __global__ __launch_bounds__(256) void ks_expl_identity(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, 0) || !explicit_by_identity(a)) return;
+    const int n = a.n;
+    const int i = blockIdx.x;
+    if (i >= n) return;
+    const double rho = a.cn_rho[a.ctl->step];
+    const double* V = a.pool[a.ctl->cur] + (size_t)i * n;
+    const double* W = a.W + (size_t)i * n;
+    double* R = a.R + (size_t)i * n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const double v = V[j];
+        R[j] = v + rho * (v - W[j]);
     }
 }
 

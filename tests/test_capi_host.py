@@ -120,3 +120,28 @@ def test_levy_from_std_matches_oracle_mapping():
         assert lv.lambda_ == pytest.approx(p["lam"], rel=1e-14)
         assert list(lv.eta) == pytest.approx(list(p["eta"]))
         assert list(lv.rho) == pytest.approx([p["rho"][0, 0], p["rho"][0, 1], p["rho"][1, 1]])
+
+
+def test_binding_structs_match_header(tmp_path):
+    """The ctypes structures of the binding have the size of the header's C
+    structures, and the timing-class list its length (a C program built with
+    gcc prints sizeof of each)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    L = _lib()
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    pairs = [("lpide_grid", L.Grid), ("lpide_levy", L.Levy), ("lpide_payoff", L.Payoff), ("lpide_opts", L.Opts),
+             ("lpide_info", L.Info), ("lpide_adjoint_info", L.AdjInfo), ("lpide_batch_opts", L.BatchOpts),
+             ("lpide_group_info", L.GroupInfo)]
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include "lpide.h"\nint main(void) {\n' +
+                   "".join('    printf("%%zu\\n", sizeof(%s));\n' % c for c, _ in pairs) +
+                   '    printf("%d\\n", LPIDE_KCLASSES);\n    return 0;\n}\n')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    for (cname, py), size in zip(pairs, out):
+        assert C.sizeof(py) == size, cname
+    assert len(L.KCLASSES) == out[-1]

@@ -121,3 +121,34 @@ def test_one_shot_solve_helper(lp):
     v = lp.solve(g, lv, pay, theta=w["theta"], M=w["N_t"], tol=w["tol"])
     assert tuple(v.shape) == (w["n"], w["n"])
     assert _rel(v.cpu().numpy(), _oracle(w)) < 1e-10
+
+
+@pytest.mark.parametrize("damping", [True, False])
+def test_explicit_part_by_identity_and_by_correlation(lp, damping):
+    """The FP64 explicit part from the previous step's implicit equation (the
+    default) and by the correlation in every step (explicit_fft) both give the
+    oracle's grid; the timing classes show which kernels ran: the explicit
+    correlation in the first step of the march only, the identity kernel in
+    every later step with theta < 1."""
+    w = workloads.workload("nig64", N_t=16)
+    _note("explicit part by identity / correlation, damping=%s" % damping)
+    Vo = _oracle(w, damping)
+    res = {}
+    for fft in (False, True):
+        plan = lp.plan_from_workload(w, damping=damping, explicit_fft=fft)
+        plan.solve()
+        plan.set_timing(["expl_cols", "expl_id"])
+        V = plan.solve().cpu().numpy()
+        st = plan.kernel_stats()
+        n_steps = plan.info()["n_steps"]
+        first_cn = 4 if damping else 0          # first theta = 1/2 step of the step list
+        if fft:
+            assert st["expl_cols"][0] == n_steps - first_cn and st["expl_id"][0] == 0
+        else:
+            assert st["expl_cols"][0] == (0 if damping else 1)
+            assert st["expl_id"][0] == n_steps - first_cn - (0 if damping else 1)
+        e = _rel(V, Vo)
+        _note("explicit_fft=%s: grid %.2e" % (fft, e))
+        assert e < 1e-10
+        res[fft] = V
+    assert _rel(res[False], res[True]) < 1e-11
