@@ -132,15 +132,19 @@ typedef struct {
                              every mixed_anchor steps (the first step of a march always); in
                              the steps between it is carried from the previous step's FP64
                              sum B Y.  0: 8.  1: every step. */
-    int32_t explicit_fft; /* FP64 form, theta < 1: 0 takes the explicit part
-                             E = V + dt (1 - theta) A V of a step from the implicit
-                             equation of the step before it, (I - c A) V = W with
-                             c = dt theta of that step: E = V + dt (1 - theta) (V - W) / c,
-                             exact at the fixed point of the theta-scheme (Sec. 3.3; the
-                             converged iterate leaves a residual below the stopping
-                             tolerance), so B is applied to V^{n-1} by the correlation only
-                             in the first step of a march and after steps with theta = 0.
-                             1: every step applies B to V^{n-1} by the correlation. */
+    int32_t all_correlations; /* FP64 form with jumps.  0: two products of Algorithm 1 are
+                             taken without the correlation.  (a) The explicit part of a
+                             step, E = V + dt (1 - theta) A V, from the implicit equation of
+                             the step before it, (I - c A) V = W with c = dt theta of that
+                             step: E = V + dt (1 - theta) (V - W) / c.  (b) B Y^0 of the first
+                             iteration from the products B V stored for the grids of the
+                             start-value combination Y^0 = sum coef V (each is B applied to
+                             the last iterate of its step).  Both are exact at the fixed
+                             point of the theta-scheme (Sec. 3.3): (a) carries the stopping
+                             rule's residual, (b) only moves the start of the iteration.
+                             The first steps of a march, whose grids did not come from it,
+                             and steps after theta = 0 use the correlation.  1: every
+                             product by the correlation, as Algorithm 1 reads. */
 } lpide_opts;
 
 /* Plan-time quantities and run statistics. */
@@ -257,12 +261,14 @@ int lpide_discretize_host(const lpide_grid* grid, const lpide_levy* levy, const 
 #define LPIDE_K_SL         4   /* semi-Lagrangian gather + extrapolated start + row FFT of Y^0 */
 #define LPIDE_K_STEP_END   5   /* end-of-step control (convergence verdict, history rotation) */
 #define LPIDE_K_EXPL_COLS  6   /* FP64 column pass of B V^{n-1} (theta < 1: first step of a march or
-                                  explicit_fft; mixed form: anchor steps) */
+                                  all_correlations; mixed form: anchor steps) */
 #define LPIDE_K_EXPL_ROWS  7   /* row inverse FFTs + explicit part (E, and B V^{n-1} at mixed anchors) */
 #define LPIDE_K_ROWS_FWD   8   /* FP64 row FFTs of V^{n-1} (mixed form, anchor steps) */
 #define LPIDE_K_CARRY      9   /* mixed form between anchors: B V^{n-1} carried, explicit part */
 #define LPIDE_K_EXPL_ID   10   /* FP64: explicit part from the previous step's implicit equation */
-#define LPIDE_KCLASSES    11
+#define LPIDE_K_ROWS_LIN  11   /* FP64 iteration 1 with B Y^0 by linearity: the residual kernel without
+                                  the transform (launched as row c2r + residual) */
+#define LPIDE_KCLASSES    12
 
 /* Kernel timing.  With bit c of class_mask set, every launch of kernel class c
  * in single-plan marches carries a start and a stop HIP event bound to the

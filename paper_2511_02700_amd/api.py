@@ -81,7 +81,7 @@ class Plan:
 
     def __init__(self, grid, levy, payoff, theta=0.5, M=32, tol=1e-12, max_iter=100, precision="fp64",
                  damping=True, device=0, stream=None, fft_radix=0, fft_size=0, mixed_anchor=0,
-                 explicit_fft=False):
+                 all_correlations=False):
         torch = _torch()
         o = Opts()
         lib().lpide_opts_default(C.byref(o))
@@ -90,7 +90,7 @@ class Plan:
         o.fft_radix = fft_radix
         o.fft_size = fft_size
         o.mixed_anchor = mixed_anchor
-        o.explicit_fft = 1 if explicit_fft else 0
+        o.all_correlations = 1 if all_correlations else 0
         self.device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)

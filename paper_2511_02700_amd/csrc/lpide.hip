@@ -59,7 +59,12 @@ hipEvent_t next_event(Plan* p) {
     return p->ev_pool[p->ev_used++];
 }
 
-KTime::KTime(Plan* pl, int c) : p(pl), cls(c), on(pl && ((pl->time_mask >> c) & 1u)) {}
+// Row c2r launches are timed for either of their classes (iteration 1 with B Y^0
+// by linearity is told apart when the times are harvested).
+KTime::KTime(Plan* pl, int c)
+    : p(pl), cls(c),
+      on(pl && (((pl->time_mask >> c) & 1u) ||
+                (c == LPIDE_K_ROWS_INV && ((pl->time_mask >> LPIDE_K_ROWS_LIN) & 1u)))) {}
 
 bool KTime::events(hipEvent_t* a, hipEvent_t* b) {
     const size_t idx = p->ev_used;
@@ -213,6 +218,8 @@ namespace lpide {
 namespace detail {
 namespace {
 
+std::vector<char> linearity_steps(const Plan* p, int step0, int nend);
+
 // Fold recorded event pairs into the per-class totals (synchronises the stream).
 // Launches of iterations after a step had converged, per-step kernels that
 // had nothing to do (explicit part of a theta = 1 step, the variant of the
@@ -222,6 +229,7 @@ namespace {
 int harvest_times(Plan* p) {
     if (p->ev_recs.empty()) return LPIDE_OK;
     HIP_TRY(hipStreamSynchronize(p->stream));
+    const std::vector<char> lin = linearity_steps(p, p->march_step0, p->n_steps);
     for (auto& r : p->ev_recs) {
         if (r.cls < 0) continue;            // launched in a slot behind a step that needed more iterations (no-op)
         const bool known = r.step >= 0 && r.step < (int)p->counts_h.size();
@@ -235,8 +243,13 @@ int harvest_times(Plan* p) {
                 r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS || r.cls == LPIDE_K_ROWS_FWD;
             if ((anchor_cls && !anchor) || (r.cls == LPIDE_K_CARRY && anchor)) continue;
         }
+        if (known && r.k == 1 && lin[r.step]) {   // iteration 1 with B Y^0 by linearity
+            if (r.cls == LPIDE_K_COLS) continue;          // the column pass exits
+            if (r.cls == LPIDE_K_ROWS_INV) r.cls = LPIDE_K_ROWS_LIN;
+        }
+        if (!((p->time_mask >> r.cls) & 1u)) continue;    // class not asked for
         if (!p->mixed && known) {           // FP64: the explicit correlation or the identity kernel
-            const bool ident = !p->opts.explicit_fft && r.step > p->march_step0 && p->cn_rho[r.step] > 0.0;
+            const bool ident = !p->opts.all_correlations && r.step > p->march_step0 && p->cn_rho[r.step] > 0.0;
             if (((r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS) && ident) ||
                 (r.cls == LPIDE_K_EXPL_ID && !ident))
                 continue;
@@ -317,8 +330,51 @@ MarchArgs march_args(const Plan* p) {
     a.nsteps = p->n_steps;
     a.step0 = 0;
     a.anchor_every = p->anchor_every;
-    a.cn_rho = (p->mixed || p->opts.explicit_fft) ? nullptr : p->cn_rho_d;
+    a.cn_rho = (p->mixed || p->opts.all_correlations) ? nullptr : p->cn_rho_d;
+    for (int b = 0; b < POOL; ++b) a.bpool[b] = p->bpool[b];
     return a;
+}
+
+// Steps of a march over [step0, nend) whose first iteration takes B Y^0 by
+// linearity: the host's replay of the pool bookkeeping of ks_init and
+// ks_step_end (which grids hold a stored B, which form the start value).
+std::vector<char> linearity_steps(const Plan* p, int step0, int nend) {
+    std::vector<char> out(p->n_steps, 0);
+    if (!p->bpool[0]) return out;
+    const bool damping = p->opts.damping != 0;
+    const int n_sub = damping ? 4 : 1;
+    int cur = 0, y = 1, hc = 1, nsrc = 1, hist[4] = {0, 0, 0, 0}, src[4] = {0, 0, 0, 0};
+    unsigned valid = 0;
+    for (int s = step0; s < nend && s < p->n_steps; ++s) {
+        bool ok = true;
+        for (int q = 0; q < nsrc; ++q) ok = ok && ((valid >> src[q]) & 1u);
+        out[s] = ok ? 1 : 0;
+        if (damping && s < n_sub - 1) {
+            cur = y;
+        } else {
+            for (int q = 3; q > 0; --q) hist[q] = hist[q - 1];
+            hist[0] = y;
+            hc = hc < 4 ? hc + 1 : 4;
+            cur = y;
+        }
+        valid |= 1u << cur;
+        int fr = -1;
+        for (int b = 0; b < POOL && fr < 0; ++b) {
+            bool used = b == cur;
+            for (int q = 0; q < hc; ++q) used = used || b == hist[q];
+            if (!used) fr = b;
+        }
+        y = fr;
+        valid &= ~(1u << fr);
+        for (int q = 0; q < 4; ++q) src[q] = hist[q];
+        if (damping && s + 1 < n_sub) {
+            nsrc = 1;
+            src[0] = cur;
+        } else {
+            nsrc = hc;
+        }
+    }
+    return out;
 }
 
 // Default radix schedule.  From measurements on MI355X (each kernel alone):
@@ -808,6 +864,7 @@ int adj_prepare(Plan* p, int C) {
     m.incs = a->incs;
     m.mixed = 0;
     m.cn_rho = nullptr;                // the reverse march forms its explicit parts by the correlation
+    for (int b = 0; b < POOL; ++b) m.bpool[b] = nullptr;
     m.nsteps = p->n_steps;
     m.seg = nullptr;
     m.segE = nullptr;
@@ -1223,7 +1280,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
     if (o.fft_radix != 0 && o.fft_radix != 4 && o.fft_radix != 8 && o.fft_radix != 16)
         return fail(LPIDE_E_PARAM, "fft_radix must be 0, 4, 8 or 16");
     if (o.mixed_anchor < 0) return fail(LPIDE_E_PARAM, "mixed_anchor must be >= 0");
-    if (o.explicit_fft != 0 && o.explicit_fft != 1) return fail(LPIDE_E_PARAM, "explicit_fft must be 0 or 1");
+    if (o.all_correlations != 0 && o.all_correlations != 1) return fail(LPIDE_E_PARAM, "all_correlations must be 0 or 1");
     Plan* p = new Plan();
     std::string err;
     if (!build_host_plan(*grid, *levy, p->hp, err)) { delete p; return fail(LPIDE_E_PARAM, err); }
@@ -1264,6 +1321,9 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
         if ((rc = dalloc(p, &p->pool[b], N))) return bail(rc);
     if ((rc = dalloc(p, &p->Wb, N))) return bail(rc);
     if ((rc = dalloc(p, &p->Rb, N))) return bail(rc);
+    if (p->jumps && !p->mixed && !o.all_correlations)    // B of the pool grids, for B Y^0 by linearity
+        for (int b = 0; b < POOL; ++b)
+            if ((rc = dalloc(p, &p->bpool[b], N))) return bail(rc);
     // axis-1 line solves: 4 columns per block, chunks of about 8 rows
     p->P_cols = default_P_cols(n);
     if (!P_cols_valid(n, p->P_cols)) return bail(fail(LPIDE_E_PARAM, "n too large for the line solves"));

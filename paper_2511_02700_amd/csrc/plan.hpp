@@ -103,6 +103,7 @@ struct Plan {
     float2* spec32 = nullptr;
     double* BV = nullptr;
     double* BY = nullptr;
+    double* bpool[POOL] = {};      // B applied to the pool grids (FP64 form, B Y^0 by linearity)
     double* V0 = nullptr;
     double* pool[POOL] = {};
     double* Wb = nullptr;

@@ -53,6 +53,7 @@ struct Ctl {
     int hc;                           // history length (main steps)
     int nsrc;                         // terms of the starting-value combination
     int hist[4];                      // pool indices, newest first
+    int bvalid;                       // bit b: bpool[b] holds B applied to pool[b] (this march)
     int src[4];
     double coef[4];                   // Y^0 = sum_q coef[q] pool[src[q]]
     // stopping-rule value after iteration k: the maximum over x of err[x][k]
@@ -105,6 +106,7 @@ struct MarchArgs {
     int anchor_every;                 // mixed form: B V^{n-1} afresh in FP64 every this many steps
     const double* cn_rho;             // per step: rho of the explicit part from the previous step's
                                       // implicit equation (0: by the correlation); null: never
+    double* bpool[POOL];              // B applied to the pool grids (FP64 form; bpool[0] null: off)
 };
 
 template <typename C> __device__ __forceinline__ C* xbuf(const MarchArgs& a);
@@ -174,6 +176,22 @@ __device__ __forceinline__ bool explicit_by_identity(const MarchArgs& a) {
     return a.cn_rho && a.ctl->step > a.step0 && a.cn_rho[a.ctl->step] > 0.0;
 }
 
+// B Y^0 of the first iteration by linearity: Y^0 = sum_q coef_q V^{src_q}, so
+// B Y^0 = sum_q coef_q B V^{src_q}, with B V^{src_q} stored by the row kernel of
+// the step that produced V^{src_q} (B applied to its last iterate before the
+// final update, so B V^{src_q} is off by B of an increment below the stopping
+// tolerance; the first iteration only sets where the iteration starts, its
+// fixed point is unchanged).  Needs every source grid from this march.
+__device__ __forceinline__ bool start_by_linearity(const MarchArgs& a) {
+    if (!a.bpool[0]) return false;
+    const Ctl* c = a.ctl;
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (q < c->nsrc) ok = ok && ((c->bvalid >> c->src[q]) & 1);
+    return ok;
+}
+
 // Whether the step runs the FP64 correlation of V^{n-1}: for the explicit part
 // (theta < 1, unless it comes from the previous step's equation), or to anchor
 // B V^{n-1} in the mixed form.
@@ -191,7 +209,7 @@ __device__ __forceinline__ const MarchArgs& plan_args(const MarchArgs* __restric
 template <int L, int E, typename C, bool CONJ = false>
 __global__ __launch_bounds__(L / E) void ks_cols(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
-    if (halted(a, k) || (k == 0 && !needs_explicit_fft(a))) return;
+    if (halted(a, k) || (k == 0 && !needs_explicit_fft(a)) || (k == 1 && start_by_linearity(a))) return;
     constexpr int T = L / E;
     __shared__ C lds[lds_slots(L)];
     __shared__ double2 tw4[tw_slots<L, E>()];
@@ -249,21 +267,62 @@ __global__ __launch_bounds__(L / E) void ks_rows_inv(const MarchArgs* __restrict
     const bool hasb = rb < n;
     const int tid = threadIdx.x;
     const C* X = xbuf<C>(a);
+    // FP64 iteration 1: B Y^0 from the stored products of the history (no transform)
+    const bool lin = MODE == 1 && k == 1 && start_by_linearity(a);
     C reg[E];
+    if (!lin) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = tid + e * T;
+            const bool lo = idx <= L / 2;
+            const int kk = lo ? idx : L - idx;
+            const C* xk = X + (size_t)kk * n;
+            const bool real_bin = kk == 0 || kk == L / 2;  // imaginary parts dropped at DC and Nyquist
+            const C ta = xk[ra];
+            const C tb = hasb ? xk[rb] : CplxOps<C>::make(0, 0);
+            const C ha = CplxOps<C>::make(ta.x, real_bin ? 0 : ta.y);
+            const C hb = CplxOps<C>::make(tb.x, real_bin ? 0 : tb.y);
+            reg[e] = lo ? CplxOps<C>::make(ha.x - hb.y, ha.y + hb.x) : CplxOps<C>::make(ha.x + hb.y, hb.x - ha.y);
+        }
+        fft_block<L, E, true>(reg, lds, tw4);
+    }
+    // FP64 iterations store B Y of the iterate for the start of later steps
+    double* Bout = nullptr;
+    const double* Hb[4] = {nullptr, nullptr, nullptr, nullptr};
+    double cf[4] = {0.0, 0.0, 0.0, 0.0};
+    int nsrc = 0;
+    if constexpr (MODE == 1) {
+        const Ctl* cc = a.ctl;
+        if (a.bpool[0]) Bout = a.bpool[cc->y];
+        if (lin) {
+            nsrc = cc->nsrc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                Hb[q] = a.bpool[cc->src[q]];
+                cf[q] = cc->coef[q];
+            }
+        }
+    }
+    // the stored products of the history, all read before the first store (the
+    // compiler cannot tell that the grids written below alias none of them)
+    double bl[E][2];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int idx = tid + e * T;
-        const bool lo = idx <= L / 2;
-        const int kk = lo ? idx : L - idx;
-        const C* xk = X + (size_t)kk * n;
-        const bool real_bin = kk == 0 || kk == L / 2;  // imaginary parts dropped at DC and Nyquist
-        const C ta = xk[ra];
-        const C tb = hasb ? xk[rb] : CplxOps<C>::make(0, 0);
-        const C ha = CplxOps<C>::make(ta.x, real_bin ? 0 : ta.y);
-        const C hb = CplxOps<C>::make(tb.x, real_bin ? 0 : tb.y);
-        reg[e] = lo ? CplxOps<C>::make(ha.x - hb.y, ha.y + hb.x) : CplxOps<C>::make(ha.x + hb.y, hb.x - ha.y);
+        bl[e][0] = bl[e][1] = 0.0;
+        const int j = tid + e * T;
+        if (lin && j < n) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                if (r == 1 && !hasb) break;
+                const size_t o = (size_t)(ra + r) * n + j;
+                double v = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q < nsrc) v += cf[q] * Hb[q][o];
+                bl[e][r] = v;
+            }
+        }
     }
-    fft_block<L, E, true>(reg, lds, tw4);
     const StepDesc& sd = cur_set(a);
     constexpr bool EXPL = MODE == 0 || MODE == 4;
     const double* U = EXPL ? a.pool[a.ctl->cur] : a.pool[a.ctl->y];
@@ -282,7 +341,10 @@ __global__ __launch_bounds__(L / E) void ks_rows_inv(const MarchArgs* __restrict
             if (r == 1 && !hasb) break;
             const int i = ra + r;
             const size_t o = (size_t)i * n + j;
-            double bu = r == 0 ? (double)reg[e].x : (double)reg[e].y;
+            double bu = lin ? bl[e][r] : (r == 0 ? (double)reg[e].x : (double)reg[e].y);
+            if constexpr (MODE == 1) {
+                if (Bout) Bout[o] = bu;
+            }
             if constexpr (MODE == 2) {
                 bu += base[o];
                 a.BY[o] = bu;
@@ -499,7 +561,10 @@ __global__ __launch_bounds__(L / E) void ks_sl(const MarchArgs* __restrict__ A) 
         }
         reg[e] = CplxOps<C>::make(y0[0], y0[1]);
     }
-    if constexpr (FFT) rows_fwd_store<L, E>(reg, lds, tw4, xbuf<C>(a), n, ra, hasb);
+    if constexpr (FFT) {
+        if (!MIXED && start_by_linearity(a)) return;   // iteration 1 takes B Y^0 by linearity
+        rows_fwd_store<L, E>(reg, lds, tw4, xbuf<C>(a), n, ra, hasb);
+    }
 }
 
 // Axis-1 line solves R <- T_1^{-1} R: CPB adjacent columns x P chunks per block
@@ -672,6 +737,7 @@ static __global__ void ks_step_end(const MarchArgs* __restrict__ A, int kmax) {
                     c->hc = c->hc < 4 ? c->hc + 1 : 4;
                     c->cur = c->y;
                 }
+                c->bvalid |= 1 << c->cur;                 // its B Y was stored by the row kernel
                 int fr = -1;
                 for (int b = 0; b < POOL && fr < 0; ++b) {
                     bool used = b == c->cur;
@@ -679,6 +745,7 @@ static __global__ void ks_step_end(const MarchArgs* __restrict__ A, int kmax) {
                     if (!used) fr = b;
                 }
                 c->y = fr;
+                c->bvalid &= ~(1 << fr);                  // the free grid takes the next iterate
                 const int s2 = s + 1;
                 c->step = s2;
                 for (int q = 0; q < 4; ++q) { c->src[q] = c->hist[q]; c->coef[q] = 0.0; }
@@ -999,6 +1066,7 @@ static __global__ void ks_init(const MarchArgs* __restrict__ A) {
         c->y = 1;
         c->hc = 1;
         c->nsrc = 1;
+        c->bvalid = 0;
         for (int q = 0; q < 4; ++q) { c->hist[q] = 0; c->src[q] = 0; c->coef[q] = 0.0; }
         c->coef[0] = 1.0;
     }

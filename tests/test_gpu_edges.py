@@ -124,31 +124,37 @@ def test_one_shot_solve_helper(lp):
 
 
 @pytest.mark.parametrize("damping", [True, False])
-def test_explicit_part_by_identity_and_by_correlation(lp, damping):
-    """The FP64 explicit part from the previous step's implicit equation (the
-    default) and by the correlation in every step (explicit_fft) both give the
-    oracle's grid; the timing classes show which kernels ran: the explicit
-    correlation in the first step of the march only, the identity kernel in
-    every later step with theta < 1."""
+def test_products_without_the_correlation(lp, damping):
+    """The FP64 march with the two products taken without the correlation
+    (the default: the explicit part from the previous step's implicit equation,
+    B Y^0 of the first iteration by linearity from the stored B V of the
+    history) and with every product by the correlation (all_correlations) both
+    give the oracle's grid.  The timing classes show which kernels ran: the
+    explicit correlation in the first step of the march only, the identity
+    kernel in every later step with theta < 1, and iteration 1 without the
+    transform once every grid of the start value came from the march (damped
+    sub-steps 1-3 and steps 7 on; without damping steps 4 on)."""
     w = workloads.workload("nig64", N_t=16)
-    _note("explicit part by identity / correlation, damping=%s" % damping)
+    _note("products without the correlation, damping=%s" % damping)
     Vo = _oracle(w, damping)
     res = {}
-    for fft in (False, True):
-        plan = lp.plan_from_workload(w, damping=damping, explicit_fft=fft)
+    for allc in (False, True):
+        plan = lp.plan_from_workload(w, damping=damping, all_correlations=allc)
         plan.solve()
-        plan.set_timing(["expl_cols", "expl_id"])
+        plan.set_timing(["expl_cols", "expl_id", "rows_lin"])
         V = plan.solve().cpu().numpy()
         st = plan.kernel_stats()
         n_steps = plan.info()["n_steps"]
         first_cn = 4 if damping else 0          # first theta = 1/2 step of the step list
-        if fft:
+        if allc:
             assert st["expl_cols"][0] == n_steps - first_cn and st["expl_id"][0] == 0
+            assert st["rows_lin"][0] == 0
         else:
             assert st["expl_cols"][0] == (0 if damping else 1)
             assert st["expl_id"][0] == n_steps - first_cn - (0 if damping else 1)
+            assert st["rows_lin"][0] == (3 + n_steps - 7 if damping else n_steps - 4)
         e = _rel(V, Vo)
-        _note("explicit_fft=%s: grid %.2e" % (fft, e))
+        _note("all_correlations=%s: grid %.2e" % (allc, e))
         assert e < 1e-10
-        res[fft] = V
+        res[allc] = V
     assert _rel(res[False], res[True]) < 1e-11
