@@ -50,8 +50,9 @@ def algorithmic_bytes(cls, n, L, mixed=False):
     return {
         # read + write X, read the spectrum
         "cols": 2 * c * hc * (2 * n + L),
-        # read X; read W and Y, write R; mixed: read and write the FP64 B Y
-        "rows_inv": 2 * c * n * hc + (5 if mixed else 3) * 8 * n * n,
+        # read X; read W and Y, write R; FP64: write the stored B Y (B Y^0 of later
+        # steps by linearity); mixed: read and write the FP64 B Y
+        "rows_inv": 2 * c * n * hc + (5 if mixed else 4) * 8 * n * n,
         # read + write R
         "line_cols": 2 * 8 * n * n,
         # read R, read + write Y, write X (row FFT of the new Y, or of delta)
@@ -69,6 +70,9 @@ def algorithmic_bytes(cls, n, L, mixed=False):
         "carry": 4 * 8 * n * n,
         # FP64 explicit part from the previous step's equation: read V and W, write E
         "expl_id": 3 * 8 * n * n,
+        # FP64 iteration 1 by linearity: read 4 stored products (3 in the steps just
+        # after the damping), W and Y; write R and the stored B Y^0
+        "rows_lin": 8 * 8 * n * n,
     }[cls]
 
 
@@ -90,6 +94,7 @@ def kernel_symbol(cls, L, mixed, sl_order, radix=(8, 8, 8, 8)):
         "rows_fwd": "lpide::ks_rows_fwd<%d, %d>" % (L, er),
         "carry": "lpide::ks_carry",
         "expl_id": "lpide::ks_expl_identity",
+        "rows_lin": "lpide::ks_rows_inv<%d, %d, 1>" % (L, er),
     }[cls]
 
 
