@@ -310,13 +310,28 @@ def adjoint_measure(lp, name="nts1024", C=32):
     plan.set_checkpoints(C)
     V = plan.solve()
     vbar = plan.price_adjoint(spots, wts)
+    # one untimed call first, as for the forward solves (graph captures, Jacobian cache)
+    plan.adjoint(vbar, checkpoint_every=C, std_params=lp.std_params_of(w))
     t0 = time.perf_counter()
     grad, _, info = plan.adjoint(vbar, checkpoint_every=C, std_params=lp.std_params_of(w))
     t_adj = time.perf_counter() - t0
     march = info["recompute_ms"] + info["reverse_ms"] + info["gather_ms"]
+    # the forward with every product of B by the correlation (the reverse march
+    # has no counterpart of the forward's two shortcuts)
+    pa = lp.plan_from_workload(w, all_correlations=True)
+    pa.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pa.solve()
+    torch.cuda.synchronize()
+    t_fwd_all = time.perf_counter() - t0
+    pa.close()
     return {"workload": "%s: %dx%d, %d steps, checkpoints every %d, J = 64 seeded spot prices" % (
                 name, w["n"], w["n"], w["N_t"], C),
             "forward_ms": 1e3 * t_fwd, "adjoint_march_ms": march, "ratio_to_forward": march / (1e3 * t_fwd),
+            "recompute_ms": info["recompute_ms"], "reverse_ms": info["reverse_ms"], "gather_ms": info["gather_ms"],
+            "forward_all_correlations_ms": 1e3 * t_fwd_all,
+            "ratio_to_forward_all_correlations": march / (1e3 * t_fwd_all),
             "host_jacobian_ms": info["jacobian_ms"], "adjoint_wall_ms": 1e3 * t_adj,
             "adjoint_iters_per_step": info["adj_iters"] / plan.info()["n_steps"],
             "grad": [float(g) for g in grad]}

@@ -574,10 +574,10 @@ int set_schedule(Group* g, const Schedule& s) {
 // Enqueue nslots step slots with kmax iterations each: replay of a captured
 // graph when the group uses graphs (and no timing is on), else direct launches.
 int enqueue_slots(Group* g, int first_tag, int nslots, int kmax) {
-    if (!g->use_graph || g->lc.timer || g->lc.record) return issue_slots(g->lc, first_tag, nslots, kmax);
+    if (!g->use_graph || g->lc.timer) return issue_slots(g->lc, first_tag, nslots, kmax);
     hipGraphExec_t exec = nullptr;
     for (auto& x : g->graphs)
-        if (x.kmax == kmax && x.nslots == nslots) exec = x.exec;
+        if (x.kmax == kmax && x.nslots == nslots && x.record == g->lc.record) exec = x.exec;
     if (!exec) {
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(g->lc.stream, hipStreamCaptureModeThreadLocal));
@@ -591,7 +591,7 @@ int enqueue_slots(Group* g, int first_tag, int nslots, int kmax) {
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(LPIDE_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-        g->graphs.push_back({kmax, nslots, exec});
+        g->graphs.push_back({kmax, nslots, g->lc.record, exec});
     }
     HIP_TRY(hipGraphLaunch(exec, g->lc.stream));
     return LPIDE_OK;
@@ -762,9 +762,12 @@ int march_end(Group* g, MarchState& st, double* const* v_out) {
     return LPIDE_OK;
 }
 
-int march_group(Group* g, const int* nsteps, int step0, const double* const* v_in, double* const* v_out) {
+// kpred0 > 0: the first prediction of iterations per step (else 8).
+int march_group(Group* g, const int* nsteps, int step0, const double* const* v_in, double* const* v_out,
+                int kpred0 = 0) {
     MarchState st;
     int rc = march_begin(g, st, nsteps, step0, v_in);
+    if (!rc && kpred0 > 0) st.kpred = std::min(kpred0, st.maxit);
     while (!rc && !st.done) {
         rc = march_enqueue(g, st);
         if (!rc) rc = march_check(g, st);
@@ -876,7 +879,7 @@ int adj_prepare(Plan* p, int C) {
 // Forward march with recording: states every `every` steps from seg_base to
 // `seg`, and (every == 1) the explicit parts to segE.
 int march_recorded(Plan* p, int step0, int nsteps, const double* v_in, double* seg, double* segE, int every,
-                   double* v_out) {
+                   double* v_out, int kpred0 = 0) {
     Group* g = p->solo;
     MarchArgs& m = g->args_h[0];
     m.seg = seg;
@@ -889,7 +892,7 @@ int march_recorded(Plan* p, int step0, int nsteps, const double* v_in, double* s
     g->lc.store_blocks = int(std::min<size_t>(1024, (N + 255) / 256));
     double* outs[1] = {v_out};
     const double* ins[1] = {v_in};
-    int rc = march_group(g, &nsteps, step0, v_in ? ins : nullptr, outs);
+    int rc = march_group(g, &nsteps, step0, v_in ? ins : nullptr, outs, kpred0);
     m.seg = nullptr;
     m.segE = nullptr;
     g->lc.record = false;
@@ -1025,6 +1028,9 @@ int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lp
     HIP_TRY(hipMemcpyAsync(a->A, &a->args, sizeof(MarchArgs), hipMemcpyHostToDevice, s));
     double t_rec = 0.0, t_rev = 0.0;
     int kpred = std::min(8, p->opts.max_iter);
+    // iteration counts of the forward march: each segment's recompute starts
+    // from their maximum over the segment instead of the default prediction
+    const std::vector<int> fwd_counts = p->counts_h;
     int64_t iters = 0;
     int maxit = 0;
     a->have_corr = 0;
@@ -1033,7 +1039,9 @@ int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lp
         const int s0 = q * C, s1 = std::min(Ns, s0 + C);
         auto ta = now();
         HIP_TRY(hipMemcpyAsync(a->seg, a->ckpt + (size_t)q * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-        if ((rc = march_recorded(p, s0, s1, a->ckpt + (size_t)q * N, a->seg, a->segE, 1, nullptr))) return rc;
+        int k0 = 0;
+        for (int st = s0; st < s1 && st < (int)fwd_counts.size(); ++st) k0 = std::max(k0, fwd_counts[st]);
+        if ((rc = march_recorded(p, s0, s1, a->ckpt + (size_t)q * N, a->seg, a->segE, 1, nullptr, k0))) return rc;
         HIP_TRY(hipStreamSynchronize(s));
         auto tb = now();
         for (int st = s1 - 1; st >= s0; --st) {

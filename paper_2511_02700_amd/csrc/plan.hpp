@@ -74,7 +74,7 @@ struct Group {
     int maxsteps = 0;
     bool use_graph = false;
     int slots = 32;                 // step slots enqueued between host checks
-    struct G { int kmax, nslots; hipGraphExec_t exec; };
+    struct G { int kmax, nslots; bool record; hipGraphExec_t exec; };   // record: with the adjoint's store kernels
     std::vector<G> graphs;
     std::vector<void*> allocs;
     double tuned_ms = 0.0;
