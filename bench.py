@@ -94,7 +94,7 @@ def kernel_symbol(cls, L, mixed, sl_order, radix=(8, 8, 8, 8)):
         "rows_fwd": "lpide::ks_rows_fwd<%d, %d>" % (L, er),
         "carry": "lpide::ks_carry",
         "expl_id": "lpide::ks_expl_identity",
-        "rows_lin": "lpide::ks_rows_inv<%d, %d, 1>" % (L, er),
+        "rows_lin": "lpide::ks_rows_lin",
     }[cls]
 
 

@@ -266,8 +266,8 @@ int lpide_discretize_host(const lpide_grid* grid, const lpide_levy* levy, const 
 #define LPIDE_K_ROWS_FWD   8   /* FP64 row FFTs of V^{n-1} (mixed form, anchor steps) */
 #define LPIDE_K_CARRY      9   /* mixed form between anchors: B V^{n-1} carried, explicit part */
 #define LPIDE_K_EXPL_ID   10   /* FP64: explicit part from the previous step's implicit equation */
-#define LPIDE_K_ROWS_LIN  11   /* FP64 iteration 1 with B Y^0 by linearity: the residual kernel without
-                                  the transform (launched as row c2r + residual) */
+#define LPIDE_K_ROWS_LIN  11   /* FP64 iteration 1 with B Y^0 by linearity: residual from the stored
+                                  products (the column pass and the row c2r kernel exit) */
 #define LPIDE_KCLASSES    12
 
 /* Kernel timing.  With bit c of class_mask set, every launch of kernel class c

@@ -59,12 +59,7 @@ hipEvent_t next_event(Plan* p) {
     return p->ev_pool[p->ev_used++];
 }
 
-// Row c2r launches are timed for either of their classes (iteration 1 with B Y^0
-// by linearity is told apart when the times are harvested).
-KTime::KTime(Plan* pl, int c)
-    : p(pl), cls(c),
-      on(pl && (((pl->time_mask >> c) & 1u) ||
-                (c == LPIDE_K_ROWS_INV && ((pl->time_mask >> LPIDE_K_ROWS_LIN) & 1u)))) {}
+KTime::KTime(Plan* pl, int c) : p(pl), cls(c), on(pl && ((pl->time_mask >> c) & 1u)) {}
 
 bool KTime::events(hipEvent_t* a, hipEvent_t* b) {
     const size_t idx = p->ev_used;
@@ -243,11 +238,10 @@ int harvest_times(Plan* p) {
                 r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS || r.cls == LPIDE_K_ROWS_FWD;
             if ((anchor_cls && !anchor) || (r.cls == LPIDE_K_CARRY && anchor)) continue;
         }
-        if (known && r.k == 1 && lin[r.step]) {   // iteration 1 with B Y^0 by linearity
-            if (r.cls == LPIDE_K_COLS) continue;          // the column pass exits
-            if (r.cls == LPIDE_K_ROWS_INV) r.cls = LPIDE_K_ROWS_LIN;
+        if (known && r.k == 1) {            // iteration 1: B Y^0 by linearity or by the correlation
+            if (lin[r.step] && (r.cls == LPIDE_K_COLS || r.cls == LPIDE_K_ROWS_INV)) continue;
+            if (!lin[r.step] && r.cls == LPIDE_K_ROWS_LIN) continue;
         }
-        if (!((p->time_mask >> r.cls) & 1u)) continue;    // class not asked for
         if (!p->mixed && known) {           // FP64: the explicit correlation or the identity kernel
             const bool ident = !p->opts.all_correlations && r.step > p->march_step0 && p->cn_rho[r.step] > 0.0;
             if (((r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS) && ident) ||

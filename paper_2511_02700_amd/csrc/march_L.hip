@@ -64,12 +64,18 @@ void launch_iteration(const Launch& c, int k) {
                 t.launch((ks_cols<L, E, C>), dim3(L / 2 + 1, c.np), dim3(L / E), 0, c.stream, c.A, k);
             });
         }
-        KTime t(c.timer, LPIDE_K_ROWS_INV);
-        with_E<L>(c.E_rinv, [&](auto e) {
-            constexpr int E = decltype(e)::value;
-            t.launch((ks_rows_inv<L, E, MIXED ? 2 : 1>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A,
-                               k);
-        });
+        {
+            KTime t(c.timer, LPIDE_K_ROWS_INV);
+            with_E<L>(c.E_rinv, [&](auto e) {
+                constexpr int E = decltype(e)::value;
+                t.launch((ks_rows_inv<L, E, MIXED ? 2 : 1>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A,
+                         k);
+            });
+        }
+        if (!MIXED && k == 1) {           // B Y^0 by linearity (the two above exit then)
+            KTime t(c.timer, LPIDE_K_ROWS_LIN);
+            t.launch(ks_rows_lin, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
+        }
     } else {
         KTime t(c.timer, LPIDE_K_ROWS_INV);
         t.launch((ks_affine_noB<false>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, k);

@@ -254,7 +254,9 @@ __global__ __launch_bounds__(L / E) void ks_rows_fwd(const MarchArgs* __restrict
 template <int L, int E, int MODE>
 __global__ __launch_bounds__(L / E) void ks_rows_inv(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
-    if (halted(a, k) || ((MODE == 0 || MODE == 4) && !needs_explicit_fft(a))) return;
+    if (halted(a, k) || ((MODE == 0 || MODE == 4) && !needs_explicit_fft(a)) ||
+        (MODE == 1 && k == 1 && start_by_linearity(a)))   // ks_rows_lin runs instead
+        return;
     using C = typename std::conditional<MODE == 2, float2, double2>::type;
     constexpr int T = L / E;
     const int n = a.n, np = (n + 1) >> 1;
@@ -267,61 +269,25 @@ __global__ __launch_bounds__(L / E) void ks_rows_inv(const MarchArgs* __restrict
     const bool hasb = rb < n;
     const int tid = threadIdx.x;
     const C* X = xbuf<C>(a);
-    // FP64 iteration 1: B Y^0 from the stored products of the history (no transform)
-    const bool lin = MODE == 1 && k == 1 && start_by_linearity(a);
     C reg[E];
-    if (!lin) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int idx = tid + e * T;
-            const bool lo = idx <= L / 2;
-            const int kk = lo ? idx : L - idx;
-            const C* xk = X + (size_t)kk * n;
-            const bool real_bin = kk == 0 || kk == L / 2;  // imaginary parts dropped at DC and Nyquist
-            const C ta = xk[ra];
-            const C tb = hasb ? xk[rb] : CplxOps<C>::make(0, 0);
-            const C ha = CplxOps<C>::make(ta.x, real_bin ? 0 : ta.y);
-            const C hb = CplxOps<C>::make(tb.x, real_bin ? 0 : tb.y);
-            reg[e] = lo ? CplxOps<C>::make(ha.x - hb.y, ha.y + hb.x) : CplxOps<C>::make(ha.x + hb.y, hb.x - ha.y);
-        }
-        fft_block<L, E, true>(reg, lds, tw4);
-    }
-    // FP64 iterations store B Y of the iterate for the start of later steps
-    double* Bout = nullptr;
-    const double* Hb[4] = {nullptr, nullptr, nullptr, nullptr};
-    double cf[4] = {0.0, 0.0, 0.0, 0.0};
-    int nsrc = 0;
-    if constexpr (MODE == 1) {
-        const Ctl* cc = a.ctl;
-        if (a.bpool[0]) Bout = a.bpool[cc->y];
-        if (lin) {
-            nsrc = cc->nsrc;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                Hb[q] = a.bpool[cc->src[q]];
-                cf[q] = cc->coef[q];
-            }
-        }
-    }
-    // the stored products of the history, all read before the first store (the
-    // compiler cannot tell that the grids written below alias none of them)
-    double bl[E][2];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        bl[e][0] = bl[e][1] = 0.0;
-        const int j = tid + e * T;
-        if (lin && j < n) {
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                if (r == 1 && !hasb) break;
-                const size_t o = (size_t)(ra + r) * n + j;
-                double v = 0.0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (q < nsrc) v += cf[q] * Hb[q][o];
-                bl[e][r] = v;
-            }
-        }
+        const int idx = tid + e * T;
+        const bool lo = idx <= L / 2;
+        const int kk = lo ? idx : L - idx;
+        const C* xk = X + (size_t)kk * n;
+        const bool real_bin = kk == 0 || kk == L / 2;  // imaginary parts dropped at DC and Nyquist
+        const C ta = xk[ra];
+        const C tb = hasb ? xk[rb] : CplxOps<C>::make(0, 0);
+        const C ha = CplxOps<C>::make(ta.x, real_bin ? 0 : ta.y);
+        const C hb = CplxOps<C>::make(tb.x, real_bin ? 0 : tb.y);
+        reg[e] = lo ? CplxOps<C>::make(ha.x - hb.y, ha.y + hb.x) : CplxOps<C>::make(ha.x + hb.y, hb.x - ha.y);
+    }
+    fft_block<L, E, true>(reg, lds, tw4);
+    // FP64 iterations store B Y of the iterate for the start of later steps
+    double* Bout = nullptr;
+    if constexpr (MODE == 1) {
+        if (a.bpool[0]) Bout = a.bpool[a.ctl->y];
     }
     const StepDesc& sd = cur_set(a);
     constexpr bool EXPL = MODE == 0 || MODE == 4;
@@ -341,7 +307,7 @@ __global__ __launch_bounds__(L / E) void ks_rows_inv(const MarchArgs* __restrict
             if (r == 1 && !hasb) break;
             const int i = ra + r;
             const size_t o = (size_t)i * n + j;
-            double bu = lin ? bl[e][r] : (r == 0 ? (double)reg[e].x : (double)reg[e].y);
+            double bu = r == 0 ? (double)reg[e].x : (double)reg[e].y;
             if constexpr (MODE == 1) {
                 if (Bout) Bout[o] = bu;
             }
@@ -425,6 +391,42 @@ static __global__ __launch_bounds__(256) void ks_expl_identity(const MarchArgs* 
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const double v = V[j];
         R[j] = v + rho * (v - W[j]);
+    }
+}
+
+// FP64 iteration 1 when B Y^0 comes by linearity (start_by_linearity):
+// B Y^0 = sum_q coef_q B V^{src_q} from the stored products, the residual
+// R = W + dt theta((D - r_omega) Y^0 + B Y^0) - Y^0, and B Y^0 stored for the
+// iterate; one block per grid row (the row c2r kernel exits in these steps).
+static __global__ __launch_bounds__(256) void ks_rows_lin(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, 1) || !start_by_linearity(a)) return;
+    const int n = a.n;
+    const int i = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows on one XCD (stencil reads share L2)
+    if (i >= n) return;
+    const Ctl* c = a.ctl;
+    const StepDesc& sd = cur_set(a);
+    const double cth = sd.dt * sd.theta;
+    const int nsrc = c->nsrc;
+    const double* Hb[4];
+    double cf[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        Hb[q] = a.bpool[c->src[q]];
+        cf[q] = c->coef[q];
+    }
+    const double* U = a.pool[c->y];
+    double* Bout = a.bpool[c->y];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const size_t o = (size_t)i * n + j;
+        double bu = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < nsrc) bu += cf[q] * Hb[q][o];
+        const double u = U[o];
+        const double d = apply_D(U, a.st, i, j, u);
+        a.R[o] = a.W[o] + cth * (d + bu - a.r_omega * u) - u;
+        Bout[o] = bu;
     }
 }
 
