@@ -481,11 +481,14 @@ void destroy_group(Group* g) {
 }
 
 // Launch shape of the axis-1 line solves: 4 columns per block, chunks of about
-// 8 rows, P_cols a power of two in [16, 128] (above 128 chunks per column the
-// scan across waves costs more than longer chunks; measured at n = 2048).
+// 8 rows (4 rows up to n = 512, where the grid gives few blocks and shorter
+// chunks shorten each thread's recurrence: 2% of a 512^2 solve), P_cols a
+// power of two in [16, 128] (above 128 chunks per column the scan across waves
+// costs more than longer chunks; measured at n = 2048).
 int default_P_cols(int n) {
+    const int m = n <= 512 ? 4 : 8;
     int P = 16;
-    while (P < 128 && (n + P - 1) / P > 8) P *= 2;
+    while (P < 128 && (n + P - 1) / P > m) P *= 2;
     return P;
 }
 
