@@ -326,14 +326,35 @@ def adjoint_measure(lp, name="nts1024", C=32):
     torch.cuda.synchronize()
     t_fwd_all = time.perf_counter() - t0
     pa.close()
+    # every state and explicit part kept by the forward march (no recompute):
+    # (2 n_steps + 1) n^2 FP64 of HBM
+    n_steps = plan.info()["n_steps"]
+    plan.close()
+    pk = lp.plan_from_workload(w)
+    pk.set_checkpoints(1 << 30)
+    pk.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pk.solve()
+    torch.cuda.synchronize()
+    t_fwd_keep = time.perf_counter() - t0
+    vbar_k = pk.price_adjoint(spots, wts)
+    pk.adjoint(vbar_k, checkpoint_every=1 << 30)
+    _, _, info_k = pk.adjoint(vbar_k, checkpoint_every=1 << 30)
+    march_k = info_k["recompute_ms"] + info_k["reverse_ms"] + info_k["gather_ms"]
+    keep_all = {"forward_recording_ms": 1e3 * t_fwd_keep, "adjoint_march_ms": march_k,
+                "ratio_to_forward": march_k / (1e3 * t_fwd),
+                "hbm_bytes": (2 * pk.info()["n_steps"] + 1) * 8 * w["n"] ** 2}
+    pk.close()
     return {"workload": "%s: %dx%d, %d steps, checkpoints every %d, J = 64 seeded spot prices" % (
                 name, w["n"], w["n"], w["N_t"], C),
             "forward_ms": 1e3 * t_fwd, "adjoint_march_ms": march, "ratio_to_forward": march / (1e3 * t_fwd),
             "recompute_ms": info["recompute_ms"], "reverse_ms": info["reverse_ms"], "gather_ms": info["gather_ms"],
             "forward_all_correlations_ms": 1e3 * t_fwd_all,
             "ratio_to_forward_all_correlations": march / (1e3 * t_fwd_all),
+            "keep_all_states": keep_all,
             "host_jacobian_ms": info["jacobian_ms"], "adjoint_wall_ms": 1e3 * t_adj,
-            "adjoint_iters_per_step": info["adj_iters"] / plan.info()["n_steps"],
+            "adjoint_iters_per_step": info["adj_iters"] / n_steps,
             "grad": [float(g) for g in grad]}
 
 

@@ -297,7 +297,11 @@ int lpide_kernel_stats(void* plan, int64_t* launches, double* ms);
  * accumulated (K: the folded kernel, by a spectral cross-correlation of lam
  * with Y and of mu with V^{n-1}).  States come from checkpoints every
  * checkpoint_every steps; each segment is recomputed with recording before it
- * is reversed.  The structure (N_z, M2, L, stencil starts) is held fixed. */
+ * is reversed.  A checkpoint_every of at least the step count (lpide_info
+ * n_steps) keeps every state and explicit part of the forward march instead,
+ * (2 n_steps + 1) n^2 FP64 (8.5 GB at n = 1024, 512 time steps), and the
+ * reverse march runs without recompute.  The structure (N_z, M2, L, stencil
+ * starts) is held fixed. */
 typedef struct {
     int64_t adj_iters;                /* adjoint fixed-point iterations, summed over the steps */
     int32_t max_step_iters;
@@ -305,8 +309,9 @@ typedef struct {
     double  recompute_ms, reverse_ms, gather_ms, jacobian_ms;
 } lpide_adjoint_info;
 
-/* Keep checkpoints in later lpide_solve calls (every `every` steps; 0: off),
- * so that an lpide_adjoint with the same stride skips its forward pass. */
+/* Keep checkpoints in later lpide_solve calls (every `every` steps; 0: off;
+ * at least the step count: every state and explicit part), so that an
+ * lpide_adjoint with the same stride skips its forward pass. */
 int lpide_plan_set_checkpoints(void* plan, int32_t every);
 
 /* v_bar: device n*n.  native (host, may be NULL): 6 + (2 N_z)^2 values,

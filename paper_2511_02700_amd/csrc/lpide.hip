@@ -801,10 +801,13 @@ int adj_prepare(Plan* p, int C) {
     const size_t N = (size_t)n * n;
     a->C = C;
     a->n_ckpt = p->n_steps / C + 1;
+    // a stride of at least the step count keeps every state and explicit part
+    // of the march (one segment, recorded by the forward march itself)
+    const size_t Cs = (size_t)std::min(C, p->n_steps);
     auto& al = a->allocs;
     int rc = LPIDE_OK;
-    if ((rc = dalloc_into(al, nullptr, &a->ckpt, N * a->n_ckpt)) || (rc = dalloc_into(al, nullptr, &a->seg, N * (C + 1))) ||
-        (rc = dalloc_into(al, nullptr, &a->segE, N * C)) || (rc = dalloc_into(al, nullptr, &a->lam, N)) ||
+    if ((rc = dalloc_into(al, nullptr, &a->ckpt, N * a->n_ckpt)) || (rc = dalloc_into(al, nullptr, &a->seg, N * (Cs + 1))) ||
+        (rc = dalloc_into(al, nullptr, &a->segE, N * std::max<size_t>(1, Cs))) || (rc = dalloc_into(al, nullptr, &a->lam, N)) ||
         (rc = dalloc_into(al, nullptr, &a->mu, N)) || (rc = dalloc_into(al, nullptr, &a->ybar, N)) ||
         (rc = dalloc_into(al, nullptr, &a->dummy, N)) || (rc = dalloc_into(al, nullptr, &a->acc, (size_t)n * 8)) ||
         (rc = dalloc_into(al, nullptr, &a->corr, N)) || (rc = dalloc_into(al, nullptr, &a->corr2, N)) ||
@@ -984,6 +987,20 @@ int model_jacobian(Plan* p, const double* x) {
 // same checkpoints), then per segment from the last: recompute with
 // recording, reverse steps.  native[0..5] = dJ/d(a11, a12, a22, r_omega,
 // kappa1, kappa2), native[6..] = dJ/d omega.
+// The forward march with the adjoint's records: checkpoints every C steps, or,
+// when C is at least the step count, every state and explicit part (the
+// reverse march then needs no recompute).  Needs adj_prepare(p, C).
+int record_forward(Plan* p, int C, double* v_out) {
+    Adjoint* a = p->adj;
+    const size_t N = (size_t)p->hp.n * p->hp.n;
+    if (C >= p->n_steps) {
+        hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, p->stream, p->V0, a->seg, N);
+        return march_recorded(p, 0, p->n_steps, nullptr, a->seg, a->segE, 1, v_out);
+    }
+    hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, p->stream, p->V0, a->ckpt, N);
+    return march_recorded(p, 0, p->n_steps, nullptr, a->ckpt, nullptr, C, v_out);
+}
+
 int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lpide_adjoint_info* info) {
     int rc = adj_prepare(p, C);
     if (rc) return rc;
@@ -996,10 +1013,10 @@ int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lp
         return std::chrono::duration<double, std::milli>(t1 - t0).count();
     };
     double t_fwd = 0.0;
+    const bool keep_all = C >= Ns;     // every state kept by the forward march: no recompute
     if (!(p->ckpt_valid && p->ckpt_every == C)) {
         auto t0 = now();
-        hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, s, p->V0, a->ckpt, N);
-        if ((rc = march_recorded(p, 0, Ns, nullptr, a->ckpt, nullptr, C, nullptr))) return rc;
+        if ((rc = record_forward(p, C, nullptr))) return rc;
         t_fwd = ms(t0, now());
     }
     HIP_TRY(hipMemcpyAsync(a->ybar, v_bar, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
@@ -1035,10 +1052,12 @@ int adjoint(Plan* p, const double* v_bar, int C, std::vector<double>& native, lp
     for (int q = (Ns - 1) / C; q >= 0; --q) {
         const int s0 = q * C, s1 = std::min(Ns, s0 + C);
         auto ta = now();
-        HIP_TRY(hipMemcpyAsync(a->seg, a->ckpt + (size_t)q * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-        int k0 = 0;
-        for (int st = s0; st < s1 && st < (int)fwd_counts.size(); ++st) k0 = std::max(k0, fwd_counts[st]);
-        if ((rc = march_recorded(p, s0, s1, a->ckpt + (size_t)q * N, a->seg, a->segE, 1, nullptr, k0))) return rc;
+        if (!keep_all) {
+            HIP_TRY(hipMemcpyAsync(a->seg, a->ckpt + (size_t)q * N, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+            int k0 = 0;
+            for (int st = s0; st < s1 && st < (int)fwd_counts.size(); ++st) k0 = std::max(k0, fwd_counts[st]);
+            if ((rc = march_recorded(p, s0, s1, a->ckpt + (size_t)q * N, a->seg, a->segE, 1, nullptr, k0))) return rc;
+        }
         HIP_TRY(hipStreamSynchronize(s));
         auto tb = now();
         for (int st = s1 - 1; st >= s0; --st) {
@@ -1486,9 +1505,7 @@ int lpide_solve(void* plan, double* v_out) {
     if (p->ckpt_every > 0) {
         int rc = adj_prepare(p, p->ckpt_every);
         if (rc) return rc;
-        const size_t N = (size_t)p->hp.n * p->hp.n;
-        hipLaunchKernelGGL(k_copy, dim3((N + 255) / 256), dim3(256), 0, p->stream, p->V0, p->adj->ckpt, N);
-        rc = march_recorded(p, 0, p->n_steps, nullptr, p->adj->ckpt, nullptr, p->ckpt_every, v_out);
+        rc = record_forward(p, p->ckpt_every, v_out);
         p->ckpt_valid = rc == LPIDE_OK;
         return rc;
     }

@@ -51,7 +51,7 @@ def _oracle_problem(w):
                           theta=w["theta"])
 
 
-@pytest.mark.parametrize("alpha,corr,C", [(0.5, 0.3, 32), (0.3, -0.4, 2)])
+@pytest.mark.parametrize("alpha,corr,C", [(0.5, 0.3, 32), (0.3, -0.4, 2), (0.5, 0.3, 8)])
 def test_native_adjoint_matches_oracle(lp, alpha, corr, C):
     import torch
     w = workloads.workload("nig64", n=18, N_t=5, y_lo=-2.0, y_hi=2.0, alpha=alpha, corr=corr)
@@ -162,3 +162,28 @@ def test_adjoint_1024_vs_finite_differences(lp):
     _note("grad %s\nfd   %s\nrel err %s" % (np.array2string(grad, precision=8), np.array2string(fd, precision=8),
                                             np.array2string(err, precision=2)))
     assert np.all(err < 1e-5)
+
+
+def test_keep_every_state_equals_checkpoints(lp):
+    """A checkpoint stride of at least the step count keeps every state and
+    explicit part of the forward march and reverses it without recompute; the
+    native gradient equals the one from checkpoints every 4 steps (both from
+    the recording solve and from the adjoint's own forward pass)."""
+    import torch
+    w = workloads.workload("nig64", n=24, N_t=12, y_lo=-2.0, y_hi=2.0)
+    _note("adjoint keep-all vs checkpoints")
+    vbar = torch.from_numpy(np.random.default_rng(9).standard_normal((w["n"], w["n"]))).cuda()
+    res = {}
+    for C in (4, 1000):
+        plan = lp.plan_from_workload(w)
+        _, n_own, info_own = plan.adjoint(vbar, checkpoint_every=C)      # its own forward pass
+        plan.set_checkpoints(C)
+        plan.solve()
+        _, n_rec, info_rec = plan.adjoint(vbar, checkpoint_every=C)      # the solve's records
+        assert info_rec["forward_ms"] == 0.0
+        if C == 1000:
+            assert info_rec["recompute_ms"] < info_own["reverse_ms"]
+        res[C] = (np.asarray(n_own), np.asarray(n_rec))
+    scale = np.max(np.abs(res[4][0]))
+    for a in res[1000] + res[4][1:]:
+        assert np.max(np.abs(a - res[4][0])) / scale < 1e-11
