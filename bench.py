@@ -9,7 +9,10 @@ resident in device memory.  value = n^2 * N_t * steps / (timed wall time), in
 grid-point time steps per second.
 
 Default workload: the 512 x 512 finite-variation NTS case (alpha = 0.3) on
-[-4, 4]^2 with 256 time steps, theta = 1/2, fixed-point tol 1e-12, FP64.
+[-4, 4]^2 with 256 time steps, theta = 1/2, fixed-point tol 1e-12, FP64 (with
+the library's defaults: the explicit part from the previous step's equation
+and B Y^0 of the first iteration from stored products, both exact at the
+fixed point).
 
 Printed (one JSON line): the metric, the roofline of the dominant kernel
 (algorithmic bytes per launch / mean launch time from HIP events bound to the
@@ -21,8 +24,9 @@ spectrum, factors).  Unless --no-extras: the column-pass
 roofline at 2048^2 (cache-exceeding working set), whole 2048^2 solves in
 both precisions, the paper's Table 3 prices against GPU marches, the adjoint
 form on its
-1024^2 workload (ratio to the forward), and the batched form on 32 draws of
-the batched recipe (against solo solves).
+1024^2 workload (ratio to the forward, with checkpoints every 32 steps and
+with every state kept), and the batched form on 32 draws of the batched recipe
+(against solo solves).
 """
 
 import argparse
