@@ -77,6 +77,8 @@ def algorithmic_bytes(cls, n, L, mixed=False):
         # FP64 iteration 1 by linearity: read 4 stored products (3 in the steps just
         # after the damping), W and Y; write R and the stored B Y^0
         "rows_lin": 8 * 8 * n * n,
+        # SL without the row transform: read E, four history grids; write W and Y^0
+        "sl_lin": 7 * 8 * n * n,
     }[cls]
 
 
@@ -99,6 +101,7 @@ def kernel_symbol(cls, L, mixed, sl_order, radix=(8, 8, 8, 8)):
         "carry": "lpide::ks_carry",
         "expl_id": "lpide::ks_expl_identity",
         "rows_lin": "lpide::ks_rows_lin",
+        "sl_lin": "lpide::ks_sl_lin<%d>" % sl_order,
     }[cls]
 
 

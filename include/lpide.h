@@ -268,7 +268,9 @@ int lpide_discretize_host(const lpide_grid* grid, const lpide_levy* levy, const 
 #define LPIDE_K_EXPL_ID   10   /* FP64: explicit part from the previous step's implicit equation */
 #define LPIDE_K_ROWS_LIN  11   /* FP64 iteration 1 with B Y^0 by linearity: residual from the stored
                                   products (the column pass and the row c2r kernel exit) */
-#define LPIDE_KCLASSES    12
+#define LPIDE_K_SL_LIN    12   /* FP64 steps with B Y^0 by linearity: SL gather and start value without
+                                  the row transform (the SL kernel exits) */
+#define LPIDE_KCLASSES    13
 
 /* Kernel timing.  With bit c of class_mask set, every launch of kernel class c
  * in single-plan marches carries a start and a stop HIP event bound to the

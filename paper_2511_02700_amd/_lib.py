@@ -12,7 +12,7 @@ ERRORS = {-1: "LPIDE_E_PARAM", -2: "LPIDE_E_NOCONV", -3: "LPIDE_E_NAN", -4: "LPI
 PAYOFF = {"put_avg": 0, "call_avg": 1, "put_1": 2, "call_1": 3, "exchange": 4, "spread": 5}
 PRECISION = {"fp64": 0, "fp32conv": 1}
 KCLASSES = ["cols", "rows_inv", "line_cols", "line_rows", "sl", "step_end", "expl_cols", "expl_rows", "rows_fwd",
-            "carry", "expl_id", "rows_lin"]
+            "carry", "expl_id", "rows_lin", "sl_lin"]
 
 
 class Grid(C.Structure):

@@ -242,6 +242,10 @@ int harvest_times(Plan* p) {
             if (lin[r.step] && (r.cls == LPIDE_K_COLS || r.cls == LPIDE_K_ROWS_INV)) continue;
             if (!lin[r.step] && r.cls == LPIDE_K_ROWS_LIN) continue;
         }
+        if (known && r.k == 0) {            // the SL kernel with the row transform, or without
+            if (lin[r.step] && r.cls == LPIDE_K_SL && !p->mixed && p->jumps) continue;
+            if (!lin[r.step] && r.cls == LPIDE_K_SL_LIN) continue;
+        }
         if (!p->mixed && known) {           // FP64: the explicit correlation or the identity kernel
             const bool ident = !p->opts.all_correlations && r.step > p->march_step0 && p->cn_rho[r.step] > 0.0;
             if (((r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS) && ident) ||

@@ -147,6 +147,11 @@ void launch_step(const Launch& c, int kmax) {
                 t.launch((ks_sl<L, E, 3, FFT, MIXED>), gr, dim3(L / E), 0, c.stream, c.A);
         });
     }
+    if (FFT && !MIXED) {                  // steps with B Y^0 by linearity (ks_sl exits in them)
+        KTime t(c.timer, LPIDE_K_SL_LIN);
+        if (c.sl_order == 1) t.launch(ks_sl_lin<1>, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
+        else t.launch(ks_sl_lin<3>, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
+    }
     if (c.record) hipLaunchKernelGGL(ks_store_E, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
     for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT, MIXED>(c, k);
     if (c.timer) c.timer->tag_k = 0;

@@ -430,6 +430,56 @@ static __global__ __launch_bounds__(256) void ks_rows_lin(const MarchArgs* __res
     }
 }
 
+// SL gather W = T^SL E and start value Y^0 of an FP64 step whose B Y^0 comes by
+// linearity (no row transform of Y^0): one block per grid row, streaming.
+template <int P>
+__global__ __launch_bounds__(256) void ks_sl_lin(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, 0) || a.mixed || !start_by_linearity(a)) return;
+    const int n = a.n;
+    const int i = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows share E rows in L2
+    if (i >= n) return;
+    const Ctl* c = a.ctl;
+    const StepDesc& sd = cur_set(a);
+    // the grids read (E, history) and written (W, Y) are distinct pool, R and W buffers
+    const double* __restrict__ Ex = sd.theta < 1.0 ? a.R : a.pool[c->cur];
+    double* __restrict__ Y = a.pool[c->y];
+    double* __restrict__ Wo = a.W;
+    const int nsrc = c->nsrc;
+    const double* __restrict__ H0 = a.pool[c->src[0]];
+    const double* __restrict__ H1 = a.pool[c->src[1]];
+    const double* __restrict__ H2 = a.pool[c->src[2]];
+    const double* __restrict__ H3 = a.pool[c->src[3]];
+    const double c0 = c->coef[0], c1 = c->coef[1], c2 = c->coef[2], c3 = c->coef[3];
+    const int a0 = sd.s1[i];
+    double w1[P + 1];
+#pragma unroll
+    for (int q = 0; q <= P; ++q) w1[q] = sd.w1[i * (P + 1) + q];
+    const double* __restrict__ er0 = Ex + (size_t)a0 * n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const int b0 = sd.s2[j];
+        double w2[P + 1];
+#pragma unroll
+        for (int b = 0; b <= P; ++b) w2[b] = sd.w2[j * (P + 1) + b];
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q <= P; ++q) {
+            const double* er = er0 + (size_t)q * n + b0;
+            double sq = 0.0;
+#pragma unroll
+            for (int b = 0; b <= P; ++b) sq += w2[b] * er[b];
+            acc += w1[q] * sq;
+        }
+        const size_t o = (size_t)i * n + j;
+        double y = c0 * H0[o];
+        if (nsrc > 1) y += c1 * H1[o];
+        if (nsrc > 2) y += c2 * H2[o];
+        if (nsrc > 3) y += c3 * H3[o];
+        Wo[o] = acc;
+        Y[o] = y;
+    }
+}
+
 // Forward FFT of the row pair held in reg (canonical layout) into the
 // transposed half spectra X[k2 * n + row].
 template <int L, int E, typename C>
@@ -482,7 +532,9 @@ __global__ __launch_bounds__(L / E) void ks_rows_fwd(const MarchArgs* __restrict
 template <int L, int E, int P, bool FFT, bool MIXED>
 __global__ __launch_bounds__(L / E) void ks_sl(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
-    if (halted(a, 0)) return;
+    // FP64 steps whose B Y^0 comes by linearity need no row transform of Y^0:
+    // ks_sl_lin does their gather and start value
+    if (halted(a, 0) || (FFT && !MIXED && start_by_linearity(a))) return;
     constexpr int T = L / E;
     using C = typename std::conditional<MIXED, float2, double2>::type;
     const int n = a.n, np = (n + 1) >> 1;
@@ -563,10 +615,7 @@ __global__ __launch_bounds__(L / E) void ks_sl(const MarchArgs* __restrict__ A) 
         }
         reg[e] = CplxOps<C>::make(y0[0], y0[1]);
     }
-    if constexpr (FFT) {
-        if (!MIXED && start_by_linearity(a)) return;   // iteration 1 takes B Y^0 by linearity
-        rows_fwd_store<L, E>(reg, lds, tw4, xbuf<C>(a), n, ra, hasb);
-    }
+    if constexpr (FFT) rows_fwd_store<L, E>(reg, lds, tw4, xbuf<C>(a), n, ra, hasb);
 }
 
 // Axis-1 line solves R <- T_1^{-1} R: CPB adjacent columns x P chunks per block
