@@ -578,7 +578,7 @@ int enqueue_slots(Group* g, int first_tag, int nslots, int kmax) {
     if (!g->use_graph || g->lc.timer) return issue_slots(g->lc, first_tag, nslots, kmax);
     hipGraphExec_t exec = nullptr;
     for (auto& x : g->graphs)
-        if (x.kmax == kmax && x.nslots == nslots && x.record == g->lc.record) exec = x.exec;
+        if (x.kmax == kmax && x.nslots == nslots && x.record == g->lc.record && x.lean == g->lc.lean) exec = x.exec;
     if (!exec) {
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(g->lc.stream, hipStreamCaptureModeThreadLocal));
@@ -592,7 +592,7 @@ int enqueue_slots(Group* g, int first_tag, int nslots, int kmax) {
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(LPIDE_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-        g->graphs.push_back({kmax, nslots, g->lc.record, exec});
+        g->graphs.push_back({kmax, nslots, g->lc.record, g->lc.lean, exec});
     }
     HIP_TRY(hipGraphLaunch(exec, g->lc.stream));
     return LPIDE_OK;
@@ -668,7 +668,16 @@ int march_begin(Group* g, MarchState& st, const int* nsteps, int step0, const do
     st.at.assign(np, step0);
     st.step0 = step0;
     st.done = false;
-    for (Plan* p : g->plans) p->march_step0 = step0;
+    for (Plan* p : g->plans) {
+        p->march_step0 = step0;
+        // steps where both FP64 shortcuts apply (the device takes the same
+        // decisions: explicit_by_identity, start_by_linearity)
+        p->steady.assign(p->n_steps, 0);
+        if (p->bpool[0] && p->cn_rho_d && !p->mixed && !p->opts.all_correlations) {
+            const std::vector<char> lin = linearity_steps(p, step0, p->n_steps);
+            for (int q = step0 + 1; q < p->n_steps; ++q) p->steady[q] = (lin[q] && p->cn_rho[q] > 0.0) ? 1 : 0;
+        }
+    }
     for (int i = 0; i < np; ++i) {
         Plan* p = g->plans[i];
         const int n = p->hp.n;
@@ -701,7 +710,16 @@ int march_enqueue(Group* g, MarchState& st) {
         return LPIDE_OK;
     }
     if (g->lc.timer) g->lc.timer->ev_mark = g->lc.timer->ev_recs.size();
-    return enqueue_slots(g, st.at[0], std::min(g->slots, remaining), st.kpred);
+    const int ns = std::min(g->slots, remaining);
+    // lean slots when every plan's steps in them are steady
+    bool lean = g->lc.jumps && !g->lc.mixed;
+    for (int i = 0; i < g->lc.np && lean; ++i) {
+        const Plan* p = g->plans[i];
+        for (int q = st.at[i]; q < st.at[i] + ns && q < st.nsteps[i] && lean; ++q)
+            lean = q < (int)p->steady.size() && p->steady[q];
+    }
+    g->lc.lean = lean;
+    return enqueue_slots(g, st.at[0], ns, st.kpred);
 }
 
 int march_check(Group* g, MarchState& st) {

@@ -56,7 +56,10 @@ template <int L, bool FFT, bool MIXED>
 void launch_iteration(const Launch& c, int k) {
     using C = typename std::conditional<MIXED, float2, double2>::type;
     if (c.timer) c.timer->tag_k = k;
-    if (FFT) {
+    // steady FP64 slots: iteration 1 is rows_lin alone (the column pass and the
+    // row c2r kernel would exit)
+    const bool lean1 = FFT && !MIXED && c.lean && k == 1;
+    if (FFT && !lean1) {
         {
             KTime t(c.timer, LPIDE_K_COLS);
             with_E<L>(c.E_cols, [&](auto e) {
@@ -72,11 +75,12 @@ void launch_iteration(const Launch& c, int k) {
                          k);
             });
         }
-        if (!MIXED && k == 1) {           // B Y^0 by linearity (the two above exit then)
-            KTime t(c.timer, LPIDE_K_ROWS_LIN);
-            t.launch(ks_rows_lin, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
-        }
-    } else {
+    }
+    if (FFT && !MIXED && k == 1) {        // B Y^0 by linearity (the two above exit then)
+        KTime t(c.timer, LPIDE_K_ROWS_LIN);
+        t.launch(ks_rows_lin, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
+    }
+    if (!FFT) {
         KTime t(c.timer, LPIDE_K_ROWS_INV);
         t.launch((ks_affine_noB<false>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, k);
     }
@@ -97,14 +101,17 @@ void launch_iteration(const Launch& c, int k) {
 // One entry of every plan's step list.  The FP64 correlation of V^{n-1} runs
 // when the explicit part needs it (theta < 1) and, in the mixed form, in every
 // step (B V^{n-1} anchors the FP32 increments); the kernels decide on the
-// device, so the launch sequence is the same for every step.  In the FP64
-// form the row transform of V^{n-1} is left in X by the previous step's last
-// iteration; the mixed form recomputes it (its iterations transform increments).
+// device, so the launch sequence is the same for every step, except in slots
+// the host knows to be steady (Launch::lean: both FP64 shortcuts apply to every
+// plan), where the kernels that would exit are left out.  In the FP64 form the
+// row transform of V^{n-1} is left in X by the previous step's last iteration;
+// the mixed form recomputes it (its iterations transform increments).
 template <int L, bool FFT, bool MIXED>
 void launch_step(const Launch& c, int kmax) {
     if (c.timer) c.timer->tag_k = 0;
     const dim3 gr(c.xrows, c.np), gc(L / 2 + 1, c.np);
-    if (FFT) {
+    const bool lean = FFT && !MIXED && c.lean;
+    if (FFT && !lean) {
         if (MIXED) {
             KTime t(c.timer, LPIDE_K_ROWS_FWD);
             with_E<L>(c.E_rinv, [&](auto e) {
@@ -133,11 +140,14 @@ void launch_step(const Launch& c, int kmax) {
             KTime t(c.timer, LPIDE_K_EXPL_ID);
             t.launch(ks_expl_identity, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
         }
+    } else if (lean) {                    // steady: the explicit part from the previous step's equation
+        KTime t(c.timer, LPIDE_K_EXPL_ID);
+        t.launch(ks_expl_identity, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
     } else {
         KTime t(c.timer, LPIDE_K_EXPL_ROWS);
         t.launch((ks_affine_noB<true>), dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A, 0);
     }
-    {
+    if (!lean) {
         KTime t(c.timer, LPIDE_K_SL);
         with_E<L>(c.E_sl, [&](auto e) {
             constexpr int E = decltype(e)::value;

@@ -55,6 +55,8 @@ struct Launch {
     bool jumps = false, mixed = false;
     Plan* timer = nullptr;          // records kernel timing (single-plan marches only)
     bool record = false;            // launch the state-recording kernels (adjoint checkpoints)
+    bool lean = false;              // every plan's steps in these slots are steady (FP64 shortcuts of
+                                    // both kinds apply): the kernels that would exit are not launched
     int store_blocks = 1;           // grid of the recording copies
 };
 
@@ -74,7 +76,7 @@ struct Group {
     int maxsteps = 0;
     bool use_graph = false;
     int slots = 32;                 // step slots enqueued between host checks
-    struct G { int kmax, nslots; bool record; hipGraphExec_t exec; };   // record: with the adjoint's store kernels
+    struct G { int kmax, nslots; bool record, lean; hipGraphExec_t exec; };   // record: with the adjoint's store kernels
     std::vector<G> graphs;
     std::vector<void*> allocs;
     double tuned_ms = 0.0;
@@ -122,6 +124,7 @@ struct Plan {
     double* cn_rho_d = nullptr;
     int anchor_every = 8;          // mixed form: FP64 B V^{n-1} afresh every this many steps
     int march_step0 = 0;           // first step of the last march (anchors count from it)
+    std::vector<char> steady;      // per step of the current march: both FP64 shortcuts apply
     int ckpt_every = 0;            // lpide_solve records checkpoints every this many steps (0: none)
     bool ckpt_valid = false;       // checkpoints of the last full solve are in adj->ckpt
     std::vector<int> counts_h;     // per-step iteration counts of the last march
