@@ -479,6 +479,75 @@ def test_greeks_black_scholes_put():
     assert math.log2(ed[0] / ed[1]) > 1.8 and math.log2(eg[0] / eg[1]) > 1.8, (ed, eg)
 
 
+def test_spot_deltas_black_scholes_put():
+    """Zero Levy measure, put on asset 1: the spot deltas of the cubic
+    interpolant (Sec. 4) converge to the Black-Scholes put delta at second
+    order; the solution does not depend on S2, so the asset-2 delta vanishes
+    to rounding.  A dropped 1/h or 1/S in the chain rule fails the first
+    bound by orders of magnitude."""
+    s1, s2, c = 0.25, 0.2, 0.4
+    cov = np.array([[s1 * s1, c * s1 * s2], [c * s1 * s2, s2 * s2]])
+    from closed_forms import bs_put_delta_gamma
+    spots = [(100.0, 100.0), (90.0, 110.0), (115.0, 95.0), (83.0, 120.0)]
+    errs = []
+    for n in (33, 65):
+        prob = _bs_problem(n, 2.0, "put_1", cov)
+        V, _ = scheme.solve(prob)
+        _, Dl = output.prices(V, prob.y_lo, prob.h, 100.0, spots, with_delta=True)
+        want = np.array([bs_put_delta_gamma(s[0], 100.0, 1.0, 0.03, s1)[0] for s in spots])
+        errs.append(np.max(np.abs(Dl[:, 0] - want)))
+        assert np.max(np.abs(Dl[:, 1])) < 1e-10, Dl[:, 1]
+    assert errs[1] < 4e-3, errs                   # deltas of -0.3 to -0.7
+    assert math.log2(errs[0] / errs[1]) > 1.7, errs
+
+
+def test_spot_deltas_margrabe():
+    """Zero Levy measure, exchange pay-off max(S1 - S2, 0): both spot deltas
+    converge to Margrabe's, N(d1) and -N(d2), at second order."""
+    s1, s2, c = 0.3, 0.2, -0.3
+    cov = np.array([[s1 * s1, c * s1 * s2], [c * s1 * s2, s2 * s2]])
+    from scipy.stats import norm
+    sv = math.sqrt(s1 * s1 + s2 * s2 - 2.0 * c * s1 * s2)
+
+    def want(S1, S2):
+        d1 = (math.log(S1 / S2) + 0.5 * sv * sv) / sv
+        return norm.cdf(d1), -norm.cdf(d1 - sv)
+
+    spots = [(100.0, 100.0), (110.0, 95.0), (90.0, 105.0)]
+    errs = []
+    for n in (33, 65):
+        prob = _bs_problem(n, 2.0, "exchange", cov)
+        V, _ = scheme.solve(prob)
+        _, Dl = output.prices(V, prob.y_lo, prob.h, 100.0, spots, with_delta=True)
+        errs.append(max(abs(Dl[k, i] - want(*s)[i]) for k, s in enumerate(spots) for i in (0, 1)))
+    assert errs[1] < 1e-2, errs
+    assert math.log2(errs[0] / errs[1]) > 1.5, errs
+
+
+def test_spot_deltas_are_derivatives_of_the_prices():
+    """Under the NTS model of the nig64 workload the delta returned beside each
+    price is the derivative in S_i of that same price function: central
+    differences of the oracle's own prices with a relative step 1e-4 agree to
+    1e-6 (truncation ~1e-9 at this step, the spots keep their stencils)."""
+    w = workloads.workload("nig64", n=48, N_t=8, y_lo=-2.5, y_hi=2.5)
+    m = w["model"]
+    p = levy.nts_from_std(m["sigma1"], m["sigma2"], m["corr"], m["theta1"], m["theta2"], m["kappa"], m["alpha"])
+    h = (w["y_hi"] - w["y_lo"]) / (w["n"] - 1)
+    d = integral.discretize(p, h, w["r"])
+    prob = scheme.Problem(w["n"], (w["y_lo"], w["y_lo"]), h, d, K=w["K"], T=w["T"], N_t=w["N_t"], theta=w["theta"])
+    V, _ = scheme.solve(prob)
+    spots = workloads.spot_pairs(16, seed=5)
+    _, Dl = output.prices(V, prob.y_lo, h, w["K"], spots, with_delta=True)
+    for i in (0, 1):
+        step = 1e-4 * spots[:, i]
+        up, dn = spots.copy(), spots.copy()
+        up[:, i] += step
+        dn[:, i] -= step
+        fd = (output.prices(V, prob.y_lo, h, w["K"], up) - output.prices(V, prob.y_lo, h, w["K"], dn)) / (2 * step)
+        assert np.max(np.abs(fd - Dl[:, i])) < 1e-6, (i, fd, Dl[:, i])
+        assert np.min(np.abs(Dl[:, i])) > 1e-3         # a real slope at every spot
+
+
 @pytest.mark.slow
 def test_nts_single_asset_put_vs_fourier():
     """Pure-jump NTS, pay-off on asset 1 only: the 2D march converges to the 1D
