@@ -369,7 +369,7 @@ class Problem:
 
 
 def solve(prob, tol=1e-14, max_iter=200, inner="lu", B_method=None, n_steps=None,
-          record=None):
+          record=None, on_step=None):
     """Algorithm 1 in log coordinates: returns V after the step list (or after its
     first ``n_steps`` entries) and per-step fixed-point iteration counts.
 
@@ -385,6 +385,8 @@ def solve(prob, tol=1e-14, max_iter=200, inner="lu", B_method=None, n_steps=None
          (Sec. 3.3 stopping rule).  If rounding stalls the increments before
          tol is met, the loop stops once they stop decreasing below 1e-13.
     ``record``, if a list, receives (step, theta, dt, iterations, last increment).
+    ``on_step``, if given, is called as on_step(s, V) with the grid after step-list
+    entry s (0-based); it only observes the march.
     """
     d = prob.disc
     n = prob.n
@@ -444,6 +446,8 @@ def solve(prob, tol=1e-14, max_iter=200, inner="lu", B_method=None, n_steps=None
         if record is not None:
             record.append((s, th, dt, k, err))
         V = Y.reshape(n, n)
+        if on_step is not None:
+            on_step(s, V)
         if (not prob.damping) or s >= n_sub - 1:
             hist.append(V.copy())
             if len(hist) > 4:

@@ -360,6 +360,7 @@ def _prices_function():
             sp = spots.detach().to(plan.device, torch.float64).reshape(-1, 2).contiguous()
             pr, dl = plan.price(V, sp, with_delta=True)
             ctx.plan, ctx.x, ctx.sp, ctx.dl, ctx.C = plan, x, sp, dl, C_every
+            ctx.params_device, ctx.spots_device = params.device, spots.device
             return pr.to(params.device)
 
         @staticmethod
@@ -368,8 +369,9 @@ def _prices_function():
             g = gout.detach().to(plan.device, torch.float64).reshape(-1).contiguous()
             vbar = plan.price_adjoint(ctx.sp, g)
             grad, _, _ = plan.adjoint(vbar, ctx.C, std_params=ctx.x)
-            gp = torch.as_tensor(grad, dtype=torch.float64)
-            gs = (g[:, None] * ctx.dl).to(gout.device)
+            # each gradient lives where its input does
+            gp = torch.as_tensor(grad, dtype=torch.float64).to(ctx.params_device)
+            gs = (g[:, None] * ctx.dl).to(ctx.spots_device)
             return gp, gs, None, None
 
     _PF = _Prices

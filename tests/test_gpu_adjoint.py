@@ -6,11 +6,14 @@
   point to 1e-12).
 * The gradient with respect to the eight subordination parameters against
   central finite differences of the GPU forward march (step 1e-5 max(|x|, 0.1),
-  structure fixed), within 1e-5 relative to the largest component (the bar of
-  the adjoint form), on a small grid and on the 1024 x 1024, 512-step workload
-  with checkpoints every 32 steps.
+  structure fixed), within 1e-5 per component, each relative to its own size
+  (floored at 1e-2 of the largest component), on a small grid and on the
+  1024 x 1024, 512-step workload with checkpoints every 32 steps.
+* The spot deltas of the 1024 x 1024 march against central differences of the
+  prices at bumped spots (relative step 1e-5), within 1e-5.
 * The autograd wrapper: its parameter gradient equals the adjoint's and its
-  spot gradient equals the deltas times the cotangent.
+  spot gradient equals the deltas times the cotangent, with CPU and with GPU
+  inputs (each gradient on its input's device).
 """
 
 import sys
@@ -118,28 +121,38 @@ def test_grad_vs_finite_differences_small(lp):
     _note("adjoint grad vs FD, 40x40")
     plan, grad, info, _, _ = _adjoint_grad(lp, w, spots, wts, C=4)
     fd = _fd_grad(lp, w, spots, wts, lp.std_params_of(w), plan.info()["N_z"])
-    err = np.abs(grad - fd) / np.max(np.abs(fd))
+    err = _per_component_err(grad, fd)
     _note("grad %s\nfd   %s\nrel err %s" % (np.array2string(grad, precision=8), np.array2string(fd, precision=8),
                                             np.array2string(err, precision=2)))
     assert np.all(err < 1e-5)
 
 
-def test_autograd_prices(lp):
+def _per_component_err(grad, fd):
+    """|g - fd| relative to each component's own size, floored at 1e-2 of the
+    largest, so that a small component is held to its own scale."""
+    return np.abs(grad - fd) / np.maximum(np.abs(fd), 1e-2 * np.max(np.abs(fd)))
+
+
+@pytest.mark.parametrize("device", ["cpu", "cuda"])
+def test_autograd_prices(lp, device):
     import torch
     w = workloads.workload("nig64", n=40, N_t=8, y_lo=-2.5, y_hi=2.5)
-    _note("autograd wrapper")
-    spots = torch.tensor(workloads.spot_pairs(8, seed=6, lo=90.0, hi=110.0), dtype=torch.float64, requires_grad=True)
-    params = torch.tensor(lp.std_params_of(w), dtype=torch.float64, requires_grad=True)
+    _note("autograd wrapper, inputs on %s" % device)
+    spots = torch.tensor(workloads.spot_pairs(8, seed=6, lo=90.0, hi=110.0), dtype=torch.float64, device=device,
+                         requires_grad=True)
+    params = torch.tensor(lp.std_params_of(w), dtype=torch.float64, device=device, requires_grad=True)
     ga = dict(n=w["n"], y_lo=w["y_lo"], y_hi=w["y_hi"], N_t=w["N_t"], theta=w["theta"], tol=w["tol"],
               checkpoint_every=4)
     pa = dict(kind=w["payoff"], K=w["K"], T=w["T"])
     pr = lp.PricesFn.apply(params, spots, ga, pa)
     g = torch.linspace(0.5, 1.5, 8, dtype=torch.float64)
     (pr.cpu() * g).sum().backward()
-    plan, grad, _, _, _ = _adjoint_grad(lp, w, spots.detach().numpy(), g.numpy(), C=4)
-    assert np.max(np.abs(params.grad.numpy() - grad)) < 1e-9 * np.max(np.abs(grad))
-    _, dl = plan.price(plan.solve(), spots.detach().numpy(), with_delta=True)
-    assert np.max(np.abs(spots.grad.numpy() - g.numpy()[:, None] * dl.cpu().numpy())) < 1e-12
+    assert params.grad.device == params.device and spots.grad.device == spots.device
+    sp = spots.detach().cpu().numpy()
+    plan, grad, _, _, _ = _adjoint_grad(lp, w, sp, g.numpy(), C=4)
+    assert np.max(np.abs(params.grad.cpu().numpy() - grad)) < 1e-9 * np.max(np.abs(grad))
+    _, dl = plan.price(plan.solve(), sp, with_delta=True)
+    assert np.max(np.abs(spots.grad.cpu().numpy() - g.numpy()[:, None] * dl.cpu().numpy())) < 1e-12
 
 
 def test_adjoint_1024_vs_finite_differences(lp):
@@ -158,10 +171,31 @@ def test_adjoint_1024_vs_finite_differences(lp):
               info["gather_ms"], info["jacobian_ms"], info["adj_iters"], plan.info()["total_iters"]))
     assert info["forward_ms"] == 0.0              # the solve's checkpoints were reused
     fd = _fd_grad(lp, w, spots, wts, lp.std_params_of(w), plan.info()["N_z"])
-    err = np.abs(grad - fd) / np.max(np.abs(fd))
+    err = _per_component_err(grad, fd)
     _note("grad %s\nfd   %s\nrel err %s" % (np.array2string(grad, precision=8), np.array2string(fd, precision=8),
                                             np.array2string(err, precision=2)))
     assert np.all(err < 1e-5)
+
+
+def test_spot_deltas_1024_vs_finite_differences(lp):
+    """Spot deltas of the 1024 x 1024 march (lpide_price) against central
+    differences of lpide_price at spots bumped by 1e-5 S_i, same grid."""
+    w = workloads.workload("nts1024")
+    spots = workloads.spot_pairs(64, seed=4)
+    _note("spot deltas vs FD, 1024^2")
+    plan = lp.plan_from_workload(w)
+    V = plan.solve()
+    _, dl = plan.price(V, spots, with_delta=True)
+    dl = dl.cpu().numpy()
+    for i in (0, 1):
+        hs = 1e-5 * spots[:, i]
+        up, dn = spots.copy(), spots.copy()
+        up[:, i] += hs
+        dn[:, i] -= hs
+        fd = (plan.price(V, up).cpu().numpy() - plan.price(V, dn).cpu().numpy()) / (2 * hs)
+        err = float(np.max(np.abs(fd - dl[:, i])))
+        _note("axis %d: max |delta - FD| %.2e (deltas %.3f .. %.3f)" % (i, err, dl[:, i].min(), dl[:, i].max()))
+        assert err < 1e-5
 
 
 def test_keep_every_state_equals_checkpoints(lp):
