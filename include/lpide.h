@@ -224,6 +224,23 @@ int lpide_initial(void* plan, double* v_out);
  * (Sec. 3.2.2) by the FFT correlation.  v, bv: device, n*n, must not alias. */
 int lpide_apply_B(void* plan, const double* v, double* bv);
 
+/* Allocation-free variant of lpide_apply_B, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same correlation and the same kernels, with the
+ * transposed intermediate in a library-owned static device array of
+ * LPIDE_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends) instead of
+ * the plan's workspace.  The call itself allocates and frees nothing; the
+ * array's device address is taken when the first plan on a device is created.
+ * v, bv: device, n*n FP64, must not alias.  Needs n * (L/2 + 1) * 16 bytes of
+ * scratch (L = the plan's transform side): larger plans are refused with
+ * LPIDE_E_PARAM before anything is enqueued.  Every call on one GPU uses the
+ * same array (its contents are fully rewritten by each call; nothing needs to
+ * start at zero), so calls that overlap on one GPU -- on different streams or
+ * from different threads -- race; serialise them.  A plan without a Levy
+ * measure gets bv = 0 from a fill kernel (no memset node). */
+#define LPIDE_NOALLOC_SCRATCH_BYTES (64u << 20)
+int lpide_apply_B_noalloc(void* plan, const double* v, double* bv);
+
 /* Prices (and deltas) at npts spot pairs by tensor-product cubic Lagrange
  * interpolation of the grid v in y (Sec. 4): spots[2k], spots[2k+1] = (S1, S2);
  * price[k]; delta[2k + i] = dP/dS_i (delta may be NULL).  All device pointers;

@@ -101,6 +101,7 @@ SIGNATURES = {
     "lpide_solve_range": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "lpide_initial": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lpide_apply_B": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lpide_apply_B_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lpide_price": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lpide_greeks": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lpide_discretize_host": (C.c_int, [C.POINTER(Grid), C.POINTER(Levy), C.POINTER(Payoff), C.POINTER(Info),

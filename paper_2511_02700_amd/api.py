@@ -173,6 +173,16 @@ class Plan:
         check(lib().lpide_apply_B(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr())))
         return out
 
+    def apply_B_noalloc(self, v, out):
+        """B v into the caller's tensor out, with no device allocation by the
+        library (lpide_apply_B_noalloc): v and out must already be contiguous
+        float64 tensors on the plan's device."""
+        torch = _torch()
+        assert v.dtype == torch.float64 and v.is_contiguous() and v.device == self.device
+        out = self._grid_tensor(out)
+        check(lib().lpide_apply_B_noalloc(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr())))
+        return out
+
     def set_checkpoints(self, every):
         """Let later solve() calls keep the checkpoints an adjoint with the same
         stride needs (0: off)."""

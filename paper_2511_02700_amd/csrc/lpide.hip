@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -48,6 +49,22 @@ double err_of(const Ctl& c, int k) {
     unsigned long long m = c.err[0][k];
     for (int x = 1; x < NX; ++x) m = std::max(m, c.err[x][k]);
     return bits_d(m);
+}
+
+// Device address of `scratch` per HIP device (null until set up on it).
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double2* g_scratch[kMaxDevices] = {};
+
+// Take the address of this device's copy of `scratch` (the device must be
+// current); once per device.
+int scratch_setup(int dev);
+
+// The address taken for device dev, or null.
+double2* scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[dev];
 }
 
 hipEvent_t next_event(Plan* p) {
@@ -207,10 +224,38 @@ __global__ void k_to_f32(const double2* __restrict__ a, float2* __restrict__ b, 
     if (i < cnt) b[i] = make_float2((float)a[i].x, (float)a[i].y);
 }
 
+// Zero fill of n values (a plain kernel, so that callers under graph capture
+// record no memset node).
+__global__ void k_zero(double* __restrict__ out, size_t cnt) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) out[i] = 0.0;
+}
+
+// Scratch of the allocation-free correlation (lpide_apply_B_noalloc): the
+// transposed intermediate of the three FFT passes, LPIDE_NOALLOC_SCRATCH_BYTES
+// per GPU, held by each device the library runs on until the process ends.
+// In host code this name is only a handle: its device address (one per GPU)
+// comes from hipGetSymbolAddress, taken once per device at plan creation with
+// that device current, and only that address is passed to kernels.
+static __device__ __align__(256) double2 scratch[LPIDE_NOALLOC_SCRATCH_BYTES / sizeof(double2)];
+
 
 
 namespace lpide {
 namespace detail {
+
+int scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(LPIDE_E_PARAM, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return LPIDE_OK;
+    void* addr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !addr)
+        return fail(LPIDE_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = static_cast<double2*>(addr);
+    return LPIDE_OK;
+}
+
 namespace {
 
 std::vector<char> linearity_steps(const Plan* p, int step0, int nend);
@@ -450,8 +495,8 @@ int issue_iteration(const Launch& c, int k) {
     return LPIDE_OK;
 }
 
-int dispatch_conv(Plan* p, const double* Y, double* out) {
-#define CALL_CONV(Lc) PerL<Lc>::conv(p, Y, out)
+int dispatch_conv(Plan* p, const double* Y, double* out, double2* X) {
+#define CALL_CONV(Lc) PerL<Lc>::conv(p, Y, out, X)
     LPIDE_SWITCH_L(p->L, CALL_CONV)
 #undef CALL_CONV
     HIP_TRY(hipGetLastError());
@@ -1360,6 +1405,8 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
         e = hipSetDevice(o.device);
         if (e != hipSuccess) { destroy(p); return fail(LPIDE_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e)); }
     }
+    // this device's copy of the allocation-free entry point's scratch
+    if ((rc = scratch_setup(o.device))) return bail(rc);
     const int n = p->hp.n;
     const size_t N = (size_t)n * n;
     if ((rc = upload(p, &p->V0, v0))) return bail(rc);
@@ -1630,7 +1677,29 @@ int lpide_apply_B(void* plan, const double* v, double* bv) {
         HIP_TRY(hipMemsetAsync(bv, 0, sizeof(double) * (size_t)p->hp.n * p->hp.n, p->stream));
         return LPIDE_OK;
     }
-    return dispatch_conv(p, v, bv);
+    return dispatch_conv(p, v, bv, p->X);
+}
+
+int lpide_apply_B_noalloc(void* plan, const double* v, double* bv) {
+    if (!plan || !v || !bv) return fail(LPIDE_E_PARAM, "NULL argument");
+    if (v == bv) return fail(LPIDE_E_PARAM, "v and bv must not alias");
+    Plan* p = static_cast<Plan*>(plan);
+    const size_t N = (size_t)p->hp.n * p->hp.n;
+    if (!p->jumps) {
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, p->stream, bv, N);
+        HIP_TRY(hipGetLastError());
+        return LPIDE_OK;
+    }
+    const size_t need = (size_t)p->hp.n * (size_t)(p->L / 2 + 1) * sizeof(double2);
+    if (need > (size_t)LPIDE_NOALLOC_SCRATCH_BYTES) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "apply_B_noalloc: n = %d with transform side %d needs %zu bytes of scratch, above "
+                 "the limit of %zu", p->hp.n, p->L, need, (size_t)LPIDE_NOALLOC_SCRATCH_BYTES);
+        return fail(LPIDE_E_PARAM, buf);
+    }
+    double2* X = scratch_ptr(p->opts.device);
+    if (!X) return fail(LPIDE_E_HIP, "apply_B_noalloc: scratch not set up on the plan's device");
+    return dispatch_conv(p, v, bv, X);
 }
 
 int lpide_price(void* plan, const double* v, int32_t npts, const double* spots, double* price, double* delta) {

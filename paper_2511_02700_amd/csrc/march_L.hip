@@ -15,13 +15,15 @@ namespace detail {
 namespace {
 
 // ---- stand-alone correlation (apply_B) and plan-time spectrum ----
+// X: the transposed intermediate, (L/2 + 1) x n complex (the plan's own, or a
+// caller-independent scratch buffer of at least that size).
 template <int L>
-void launch_conv(Plan* p, const double* Y, double* out) {
+void launch_conv(Plan* p, const double* Y, double* out, double2* X) {
     const int n = p->hp.n, np = (n + 1) / 2;
-    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / conv_e(L)), 0, p->stream, Y, n, n, n, p->X, n, p->tw);
-    hipLaunchKernelGGL((k_cols<L, 0>), dim3(L / 2 + 1), dim3(L / conv_e(L)), 0, p->stream, p->X, n, n, n, p->spec,
+    hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / conv_e(L)), 0, p->stream, Y, n, n, n, X, n, p->tw);
+    hipLaunchKernelGGL((k_cols<L, 0>), dim3(L / 2 + 1), dim3(L / conv_e(L)), 0, p->stream, X, n, n, n, p->spec,
                        (double2*)nullptr, 0.0, p->tw);
-    hipLaunchKernelGGL((k_rows_inv<L>), dim3(np), dim3(L / conv_e(L)), 0, p->stream, p->X, n, n, out, p->tw);
+    hipLaunchKernelGGL((k_rows_inv<L>), dim3(np), dim3(L / conv_e(L)), 0, p->stream, X, n, n, out, p->tw);
 }
 
 template <int L>
@@ -330,7 +332,7 @@ void PerL<L>::slots(const Launch& c, int first_tag, int nslots, int kmax) { laun
 template <int L>
 void PerL<L>::iteration(const Launch& c, int k) { launch_iteration_L<L>(c, k); }
 template <int L>
-void PerL<L>::conv(Plan* p, const double* Y, double* out) { launch_conv<L>(p, Y, out); }
+void PerL<L>::conv(Plan* p, const double* Y, double* out, double2* X) { launch_conv<L>(p, Y, out, X); }
 template <int L>
 void PerL<L>::spectrum(Plan* p, const double* G, double2* Xfull) { launch_spectrum<L>(p, G, Xfull); }
 template <int L>

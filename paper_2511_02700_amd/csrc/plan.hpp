@@ -231,7 +231,7 @@ template <int L>
 struct PerL {
     static void slots(const Launch& c, int first_tag, int nslots, int kmax);
     static void iteration(const Launch& c, int k);
-    static void conv(Plan* p, const double* Y, double* out);
+    static void conv(Plan* p, const double* Y, double* out, double2* X);
     static void spectrum(Plan* p, const double* G, double2* Xfull);
     static void rows_fwd(Plan* p, const double* Y, hipStream_t s);
     static int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const double* V,
