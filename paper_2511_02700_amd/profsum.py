@@ -6,6 +6,14 @@ profile records, JSON for bench.py's measured-traffic field).
         *_kernel_stats.csv that `rocprofv3 --kernel-trace --stats
         --output-format csv -d DIR -o run` writes.
 
+    python -m paper_2511_02700_amd.profsum table DIR [DIR ...] [--ref COUNTER]
+        per kernel: the mean of every counter of the --pmc runs in the DIRs
+        over the working dispatches (those whose reference counter, by default
+        SQ_WAVE_CYCLES, reaches a quarter of the median of the kernel's upper
+        half: iterations after convergence exit at once), with the VGPR
+        count, the LDS bytes per
+        workgroup and the workgroup size the runtime reports.
+
     python -m paper_2511_02700_amd.profsum pmc FETCH_DIR WRITE_DIR [--json OUT]
         per-kernel FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two
         `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs, calibrated by
@@ -153,6 +161,57 @@ def pmc_summary(fetch_dir, write_dir):
     return {"calibration": cal, "kernels": kernels, "source_sha256": source_digest()}
 
 
+def counter_table(dirs, ref="SQ_WAVE_CYCLES"):
+    """{kernel: {"meta": (vgpr, agpr, lds, wg), "n": (working, all), counter: mean}}."""
+    rows = {}
+    for d in dirs:
+        path = _one(os.path.join(d, "**", "*counter_collection.csv"))
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                key = (d, r.get("Dispatch_Id") or r.get("Correlation_Id"))
+                e = rows.setdefault(key, {"kernel": r["Kernel_Name"], "meta": (
+                    int(r.get("VGPR_Count", 0) or 0), int(r.get("Accum_VGPR_Count", 0) or 0),
+                    int(r.get("LDS_Block_Size", 0) or 0), int(r.get("Workgroup_Size", 0) or 0)), "c": {}})
+                e["c"][r["Counter_Name"]] = e["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    per = {}
+    for (d, _), e in rows.items():
+        per.setdefault(e["kernel"], {}).setdefault(d, []).append(e)
+    out = {}
+    for k, by_dir in per.items():
+        res = {"meta": None, "n": [0, 0]}
+        for d, lst in by_dir.items():
+            # the reference counter of this run: the one asked for, else the
+            # first of a few that scale with the work a dispatch did
+            have = lst[0]["c"]
+            rname = next((c for c in (ref, "SQ_WAVE_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU", "TA_BUSY_avr",
+                                      "SQ_BUSY_CYCLES") if c in have), next(iter(have), None))
+            refs = sorted(x["c"].get(rname, 0.0) for x in lst)
+            up = refs[len(refs) // 2:]
+            thr = 0.25 * up[len(up) // 2] if up else 0.0
+            act = [x for x in lst if x["c"].get(rname, 0.0) >= thr]
+            res["meta"] = lst[0]["meta"]
+            res["n"][0] += len(act)
+            res["n"][1] += len(lst)
+            for name in act[0]["c"] if act else []:
+                res[name] = sum(x["c"].get(name, 0.0) for x in act) / len(act)
+        out[k] = res
+    return out
+
+
+def print_table(t, out=sys.stdout):
+    names = sorted({c for v in t.values() for c in v if c not in ("meta", "n")})
+    out.write("%-56s %5s %5s %6s %5s %9s" % ("kernel", "vgpr", "agpr", "lds_B", "wg", "working"))
+    for c in names:
+        out.write(" %14s" % c[:14])
+    out.write("\n")
+    for k, v in sorted(t.items(), key=lambda kv: -kv[1].get("SQ_WAVE_CYCLES", kv[1].get(names[0], 0.0) if names else 0)):
+        m = v["meta"] or (0, 0, 0, 0)
+        out.write("%-56s %5d %5d %6d %5d %4d/%-4d" % (k[:56], m[0], m[1], m[2], m[3], v["n"][0], v["n"][1]))
+        for c in names:
+            out.write(" %14.4g" % v.get(c, float("nan")))
+        out.write("\n")
+
+
 def print_pmc(s, out=sys.stdout):
     c = s["calibration"]
     out.write("calibration (k_copy): read %d B -> FETCH_SIZE %.1f KiB (scale %.4f); write %d B -> WRITE_SIZE %.1f KiB "
@@ -170,6 +229,9 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("stats")
     a.add_argument("dir")
+    t = sub.add_parser("table")
+    t.add_argument("dirs", nargs="+")
+    t.add_argument("--ref", default="SQ_WAVE_CYCLES")
     b = sub.add_parser("pmc")
     b.add_argument("fetch_dir")
     b.add_argument("write_dir")
@@ -177,6 +239,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         print_stats(args.dir)
+    elif args.cmd == "table":
+        print_table(counter_table(args.dirs, args.ref))
     else:
         s = pmc_summary(args.fetch_dir, args.write_dir)
         print_pmc(s)

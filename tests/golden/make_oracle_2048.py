@@ -1,12 +1,14 @@
-"""Write the oracle's state of the 2048 x 2048 workloads after the four damped
-quarter steps and one theta = 1/2 step, on the 256 x 256 sub-grid of every
-8th node per axis (indices 0, 8, ..., 2040), to oracle_2048_<name>.npz.
+"""Write the oracle's state of the 2048 x 2048 workloads after the first
+step-list entries (the four damped quarter steps, then theta = 1/2 steps), on
+the 256 x 256 sub-grid of every 8th node per axis (indices 0, 8, ..., 2040),
+to oracle_2048_<name>.npz.
 
-    python tests/golden/make_oracle_2048.py [nig2048_m fv2048_p]
+    python tests/golden/make_oracle_2048.py [nig2048_m nig2048_p fv2048_m fv2048_p]
 
-Calls only the oracle (FP64, BiCGSTAB inner solves, tol 1e-14); about ten
-minutes per workload on eight cores.  The stored arrays: V (256 x 256),
-idx (the sampled node indices), steps, and the workload name.
+Calls only the oracle (FP64, BiCGSTAB inner solves, tol 1e-14); about half an
+hour per workload on eight cores.  The stored arrays: V_<e> (256 x 256, the
+grid after the first e entries) for e in entries, idx (the sampled node
+indices), iters (fixed-point iterations per entry) and the workload name.
 """
 
 import os
@@ -22,7 +24,7 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 from oracle import integral, levy, scheme  # noqa: E402
 
-STEPS = 5
+ENTRIES = (5, 16)     # the damped block and one main step; then 11 more main steps
 STRIDE = 8
 
 
@@ -35,14 +37,22 @@ def make(name):
     d = integral.discretize(p, h, w["r"])
     prob = scheme.Problem(n, (w["y_lo"], w["y_lo"]), h, d, payoff=w["payoff"], K=w["K"], T=w["T"], N_t=w["N_t"],
                           theta=w["theta"])
-    t0 = time.time()
-    V, iters = scheme.solve(prob, tol=1e-14, inner="bicgstab", n_steps=STEPS)
     idx = np.arange(0, n, STRIDE)
+    kept = {}
+    t0 = time.time()
+
+    def keep(s, V):
+        print("  %s entry %d at %.0f s" % (name, s + 1, time.time() - t0), flush=True)
+        if s + 1 in ENTRIES:
+            kept["V_%d" % (s + 1)] = V[np.ix_(idx, idx)].copy()
+
+    _, iters = scheme.solve(prob, tol=1e-14, inner="bicgstab", n_steps=max(ENTRIES), on_step=keep)
     out = os.path.join(HERE, "oracle_2048_%s.npz" % name)
-    np.savez(out, V=V[np.ix_(idx, idx)], idx=idx, steps=STEPS, name=name, iters=np.array(iters))
-    print("%s: %d steps in %.0f s, iterations %s -> %s" % (name, STEPS, time.time() - t0, iters, out), flush=True)
+    np.savez(out, idx=idx, entries=np.array(ENTRIES), name=name, iters=np.array(iters), **kept)
+    print("%s: %d entries in %.0f s, iterations %s -> %s" % (name, len(iters), time.time() - t0, iters, out),
+          flush=True)
 
 
 if __name__ == "__main__":
-    for nm in (sys.argv[1:] or ["nig2048_m", "fv2048_p"]):
+    for nm in (sys.argv[1:] or ["nig2048_m", "nig2048_p", "fv2048_m", "fv2048_p"]):
         make(nm)

@@ -1,8 +1,11 @@
-"""GPU parity at the 2048 x 2048 size (L = 4096): the state after the damped
-block and the first theta = 1/2 step against stored oracle values on the
-256 x 256 sub-grid of every 8th node (written by
-tests/golden/make_oracle_2048.py, which calls only the oracle), and the full
-1024-step march in the mixed form against the plain FP64 march.
+"""GPU parity at the 2048 x 2048 size (transform side L = 3072): the four
+workloads with alpha in {0.5, 0.3} and correlation -0.5 or +0.5, their state
+after the damped block and one theta = 1/2 step (5 entries) and after 16
+entries, against stored oracle values on the 256 x 256 sub-grid of every 8th
+node (written by tests/golden/make_oracle_2048.py, which calls only the
+oracle); the 16 entries also through a one-plan batch with 4-step slots, whose
+slots after the first main steps run without the kernels that would exit; and
+the full 1024-step march in the mixed form against the plain FP64 march.
 
 Bars: plain FP64 within 1e-10 and mixed within 1e-6 in the metric
 |a - b| / max(1, |b|); prices within 1e-6 relative, deltas 1e-6 absolute.
@@ -48,17 +51,37 @@ def _golden(name):
     return np.load(path)
 
 
-@pytest.mark.parametrize("name", ["nig2048_m", "fv2048_p"])
+NAMES = ["nig2048_m", "nig2048_p", "fv2048_m", "fv2048_p"]
+
+
+@pytest.mark.parametrize("name", NAMES)
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32conv", 1e-6)])
 def test_first_steps_2048_vs_oracle(lp, name, precision, bar):
     g = _golden(name)
-    steps, idx = int(g["steps"]), g["idx"]
-    _note("2048 %s %s first %d steps" % (name, precision, steps))
+    idx = g["idx"]
     plan = lp.plan_from_workload(workloads.workload(name), precision=precision)
-    V = plan.solve_steps(steps).cpu().numpy()
-    e = _rel(V[np.ix_(idx, idx)], g["V"])
-    _note("2048 %s %s: sampled grid %.2e" % (name, precision, e))
-    assert e < bar
+    assert plan.info()["L"] == 3072
+    for e in g["entries"]:
+        e = int(e)
+        _note("2048 %s %s first %d entries" % (name, precision, e))
+        V = plan.solve_steps(e).cpu().numpy()
+        err = _rel(V[np.ix_(idx, idx)], g["V_%d" % e])
+        _note("2048 %s %s: sampled grid %.2e" % (name, precision, err))
+        assert err < bar
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_first_steps_2048_batched_lean_slots(lp, name):
+    g = _golden(name)
+    idx, e = g["idx"], int(max(g["entries"]))
+    plan = lp.plan_from_workload(workloads.workload(name))
+    _note("2048 %s one-plan batch, 4-step slots, first %d entries" % (name, e))
+    b = lp.Batch([plan], slots=4)
+    V = b.solve_steps(e)[0].cpu().numpy()
+    b.close()
+    err = _rel(V[np.ix_(idx, idx)], g["V_%d" % e])
+    _note("2048 %s batch: sampled grid %.2e" % (name, err))
+    assert err < 1e-10
 
 
 @pytest.mark.parametrize("name", ["nig2048_m", "fv2048_p"])
