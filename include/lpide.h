@@ -415,14 +415,17 @@ int lpide_batch_solve(void* batch, double* const* v_out);
  * step list; v_out may be NULL (results not copied: timing and tuning). */
 int lpide_batch_solve_steps(void* batch, int32_t steps, double* const* v_out);
 
-/* Autotuner: for each group, time the march of the first trial_steps entries
- * under candidate launch configurations and keep the fastest, in three
- * passes: the FFT radix schedule (4, 8 or 16 elements per thread, per kernel
- * class, one class at a time from the default), the axis-1
+/* Autotuner: for each group, march every plan once to step-list entry
+ * min(8, n_steps) (past the damped block and the first main steps), then time
+ * the march of the next trial_steps entries from there -- steady steps, as in
+ * the bulk of a march -- under candidate launch configurations and keep the
+ * fastest, in three passes: the FFT radix schedule (4, 8 or 16 elements per
+ * thread, per kernel class, one class at a time from the default), the axis-1
  * line-solve chunking P_cols in {P/2, P, 2P} around the default P, then
- * hipGraph replay on/off with 16 or 32 step slots per host check; each
- * candidate runs twice with the second timed.  Synchronises the device work
- * of the batch. */
+ * hipGraph replay on/off with 32 step slots per host check, and with 16 when
+ * trial_steps >= 32; each candidate runs twice with the second timed.
+ * Allocates one n*n start state per plan for its duration.  Synchronises the
+ * device work of the batch. */
 int lpide_batch_tune(void* batch, int32_t trial_steps);
 
 /* Groups of the batch: *n_groups, and up to cap entries of groups (may be NULL). */

@@ -115,6 +115,22 @@ __device__ __forceinline__ double apply_DT(const double* __restrict__ U, const S
                                            double u) {
     const int n = s.n;
     const double ih2 = 1.0 / (s.h * s.h), i2h = 0.5 / s.h;
+    // Away from the edges (every neighbour an interior node) the transposed
+    // stencil is the forward one with the first differences negated: the
+    // second differences and the product of two central differences are
+    // symmetric, a central difference is antisymmetric.
+    if (i >= 2 && i <= n - 3 && j >= 2 && j <= n - 3) {
+        const double u1m = U[(size_t)(i - 1) * n + j], u1p = U[(size_t)(i + 1) * n + j];
+        const double u2m = U[(size_t)i * n + j - 1], u2p = U[(size_t)i * n + j + 1];
+        double d = 0.5 * s.a11 * ((u1p - 2.0 * u + u1m) * ih2 + (u1p - u1m) * i2h) +
+                   0.5 * s.a22 * ((u2p - 2.0 * u + u2m) * ih2 + (u2p - u2m) * i2h);
+        if (s.a12 != 0.0) {
+            const double* rm = U + (size_t)(i - 1) * n;
+            const double* rp = U + (size_t)(i + 1) * n;
+            d += s.a12 * i2h * i2h * ((rp[j + 1] - rp[j - 1]) - (rm[j + 1] - rm[j - 1]));
+        }
+        return d;
+    }
     // second-difference parts: row r (interior) holds 1/2 [(v_{r+1} - 2 v_r + v_{r-1})/h^2 - (v_{r+1} - v_{r-1})/(2h)]
     const double cu = 0.5 * (ih2 - i2h);   // coefficient of v_{r+1} in row r
     const double cl = 0.5 * (ih2 + i2h);   // coefficient of v_{r-1} in row r

@@ -755,13 +755,26 @@ int march_enqueue(Group* g, MarchState& st) {
         return LPIDE_OK;
     }
     if (g->lc.timer) g->lc.timer->ev_mark = g->lc.timer->ev_recs.size();
-    const int ns = std::min(g->slots, remaining);
-    // lean slots when every plan's steps in them are steady
-    bool lean = g->lc.jumps && !g->lc.mixed;
-    for (int i = 0; i < g->lc.np && lean; ++i) {
-        const Plan* p = g->plans[i];
-        for (int q = st.at[i]; q < st.at[i] + ns && q < st.nsteps[i] && lean; ++q)
-            lean = q < (int)p->steady.size() && p->steady[q];
+    int ns = std::min(g->slots, remaining);
+    // lean slots when every plan's steps in them are steady.  A window whose
+    // first steps are not steady (the start of a march, or of a recompute
+    // segment) ends where the steady run of every plan begins, so that the
+    // rest goes out lean in the next windows.
+    auto steady_from = [&](int k) {          // every plan steady on [at + k, at + ns)
+        for (int i = 0; i < g->lc.np; ++i) {
+            const Plan* p = g->plans[i];
+            for (int q = st.at[i] + k; q < st.at[i] + ns && q < st.nsteps[i]; ++q)
+                if (q >= (int)p->steady.size() || !p->steady[q]) return false;
+        }
+        return true;
+    };
+    bool lean = g->lc.jumps && !g->lc.mixed && steady_from(0);
+    if (g->lc.jumps && !g->lc.mixed && !lean) {
+        for (int k = 1; k < ns; ++k)
+            if (steady_from(k)) {
+                ns = k;
+                break;
+            }
     }
     g->lc.lean = lean;
     return enqueue_slots(g, st.at[0], ns, st.kpred);
@@ -878,6 +891,7 @@ int adj_prepare(Plan* p, int C) {
         (rc = dalloc_into(al, nullptr, &a->mu, N)) || (rc = dalloc_into(al, nullptr, &a->ybar, N)) ||
         (rc = dalloc_into(al, nullptr, &a->dummy, N)) || (rc = dalloc_into(al, nullptr, &a->acc, (size_t)n * 8)) ||
         (rc = dalloc_into(al, nullptr, &a->corr, N)) || (rc = dalloc_into(al, nullptr, &a->corr2, N)) ||
+            (rc = dalloc_into(al, nullptr, &a->corr3, N)) ||
         (rc = dalloc_into(al, nullptr, &a->ctl, 1)) || (rc = dalloc_into(al, nullptr, &a->counts, p->n_steps)) ||
         (rc = dalloc_into(al, nullptr, &a->incs, p->n_steps)) || (rc = dalloc_into(al, nullptr, &a->A, 1)))
         return rc;
@@ -1876,20 +1890,41 @@ int lpide_batch_solve_steps(void* batch, int32_t steps, double* const* v_out) {
 int lpide_batch_tune(void* batch, int32_t trial_steps) {
     if (!batch || trial_steps < 1) return fail(LPIDE_E_PARAM, "NULL batch or trial_steps < 1");
     Batch* b = static_cast<Batch*>(batch);
+    // Candidates are timed on a window of trial_steps entries that starts
+    // after the damped block and the first main steps (entry S0, from states
+    // marched there once), so the window is made of the steady steps that
+    // dominate a real march (explicit part from the previous step's equation,
+    // B Y^0 by linearity, slots without the exiting kernels).
+    constexpr int S0 = 8;
     for (size_t q = 0; q < b->groups.size(); ++q) {
         Group* g = b->groups[q];
-        std::vector<int> ns;
+        std::vector<int> ns, ns0;
         int nmax = 0;
+        int s0 = S0;
+        for (Plan* p : g->plans) s0 = std::min(s0, p->n_steps);
+        std::vector<double*> start;
+        struct Free {
+            std::vector<double*>& v;
+            ~Free() { for (double* x : v) (void)hipFree(x); }
+        } free_start{start};
         for (Plan* p : g->plans) {
-            ns.push_back(std::min<int>(trial_steps, p->n_steps));
+            ns0.push_back(s0);
+            ns.push_back(std::min<int>(s0 + trial_steps, p->n_steps));
             nmax = std::max(nmax, p->hp.n);
+            double* d = nullptr;
+            HIP_TRY(hipMalloc(&d, sizeof(double) * (size_t)p->hp.n * p->hp.n));
+            start.push_back(d);
+        }
+        {
+            int rc = march_group(g, ns0.data(), 0, nullptr, start.data());
+            if (rc) return rc;
         }
         auto trial = [&](double* out) -> int {
             double ms = 0.0;
             for (int rep = 0; rep < 2; ++rep) {
                 HIP_TRY(hipStreamSynchronize(g->lc.stream));
                 const auto t0 = std::chrono::steady_clock::now();
-                int rc = march_group(g, ns.data(), 0, nullptr, nullptr);
+                int rc = march_group(g, ns.data(), s0, start.data(), nullptr);
                 if (rc) return rc;
                 ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             }
@@ -1926,11 +1961,13 @@ int lpide_batch_tune(void* batch, int32_t trial_steps) {
             if (ms < best) { best = ms; bP = P; }
         }
         if ((rc = set_P_cols(g, bP))) return rc;
-        // pass 3: graph replay and slots
+        // pass 3: graph replay and slots (a slot count is compared only when
+        // the window spans at least two of its batches of slots)
         int bG = 1, bS = 32;
         best = 1e300;
         for (int G : {0, 1})
             for (int S : {16, 32}) {
+                if (trial_steps < 2 * S && S != 32) continue;
                 g->use_graph = G != 0;
                 g->slots = S;
                 if ((rc = trial(&ms))) return rc;

@@ -224,20 +224,30 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     const double cth = sd.dt * sd.theta;
     const double* cp1 = nullptr;
     const double* cp2 = nullptr;
-    double w1 = 0.0, w2 = 0.0;
+    const double* cp3 = nullptr;
+    double w1 = 0.0, w2 = 0.0, w3 = 0.0;
     if (a->have_corr >= 1 && a->corr_c > 0.0) {
+        // the correction lam - Ybar = dt theta A^T lam, rescaled to this step's
+        // dt theta and extrapolated over the previous steps of the same kind:
+        // kept, linear (2, -1) or quadratic (3, -3, 1)
         const double ratio = cth / a->corr_c;
         cp1 = a->corr;
         w1 = ratio;
-        if (a->have_corr >= 2 && a->corr_c2 == a->corr_c) {   // same step kind: extrapolate linearly
+        if (a->have_corr >= 2 && a->corr_c2 == a->corr_c) {
             cp2 = a->corr2;
             w1 = 2.0 * ratio;
             w2 = -ratio;
+            if (a->have_corr >= 3 && a->corr_c3 == a->corr_c) {
+                cp3 = a->corr3;
+                w1 = 3.0 * ratio;
+                w2 = -3.0 * ratio;
+                w3 = ratio;
+            }
         }
     }
     with_E<L>(c.E_rinv, [&](auto e) {
         constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_adj_start<L, E>), gr, dim3(L / E), 0, c.stream, c.A, cp1, w1, cp2, w2);
+        hipLaunchKernelGGL((ks_adj_start<L, E>), gr, dim3(L / E), 0, c.stream, c.A, cp1, w1, cp2, w2, cp3, w3);
     });
     int k = *kpred;
     for (int q = 1; q <= k; ++q) launch_adj_iteration<L>(c, q);
@@ -265,18 +275,33 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     int used = k;
     for (int q = 1; q <= k; ++q)
         if (err_of(*a->ctl_h, q) < p->opts.tol) { used = q; break; }
+    // the last iteration left the row transform of the converged lam in X:
+    // kept for the spectral gradient term (the transposed SL overwrites X)
+    const size_t xbytes = sizeof(double2) * (size_t)(L / 2 + 1) * n;
+    if (p->jumps) HIP_TRY(hipMemcpyAsync(a->XA, p->X, xbytes, hipMemcpyDeviceToDevice, c.stream));
     a->counts_h[s] = used;
     *kpred = std::max(1, std::min(p->opts.max_iter, used));
     const int sb = int(std::min<size_t>(1024, (N + 255) / 256));
-    std::swap(a->corr, a->corr2);
-    a->corr_c2 = a->corr_c;
+    {
+        double* oldest = a->corr3;
+        a->corr3 = a->corr2;
+        a->corr2 = a->corr;
+        a->corr = oldest;
+        a->corr_c3 = a->corr_c2;
+        a->corr_c2 = a->corr_c;
+    }
     hipLaunchKernelGGL(ks_adj_corr, dim3(sb), dim3(256), 0, c.stream, c.A, a->corr);
-    a->have_corr = std::min(2, a->have_corr + 1);
+    a->have_corr = std::min(3, a->have_corr + 1);
     a->corr_c = cth;
-    // mu = (T^SL)^T lam, then the cotangent of V^s
+    // mu = (T^SL)^T lam (its row transform also into XC for the spectral
+    // gradient term when theta < 1), then the cotangent of V^s
+    const double c1 = sd.dt * sd.theta, c2 = sd.dt * (1.0 - sd.theta);
+    double2* x2 = (p->jumps && c2 != 0.0) ? a->XC : nullptr;
+    const bool narrow = sd.wt1 <= 8 && sd.wt2 <= 8;
     with_E<L>(c.E_sl, [&](auto e) {
         constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_adj_sl<L, E>), gr, dim3(L / E), 0, c.stream, c.A);
+        if (narrow) hipLaunchKernelGGL((ks_adj_sl<L, E, 8>), gr, dim3(L / E), 0, c.stream, c.A, x2);
+        else hipLaunchKernelGGL((ks_adj_sl<L, E, 0>), gr, dim3(L / E), 0, c.stream, c.A, x2);
     });
     if (sd.theta < 1.0) {
         with_E<L>(c.E_cols, [&](auto e) {
@@ -293,16 +318,14 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
         hipLaunchKernelGGL(ks_adj_accum<1>, dim3(n, 1), dim3(256), 0, c.stream, c.A, Y, V, E, a->acc);
     else
         hipLaunchKernelGGL(ks_adj_accum<3>, dim3(n, 1), dim3(256), 0, c.stream, c.A, Y, V, E, a->acc);
-    const double c1 = sd.dt * sd.theta, c2 = sd.dt * (1.0 - sd.theta);
     if (p->jumps) {
         const int np = (n + 1) / 2;
-        // the row transform of Y = V^{s+1} is the V transform of reverse step s + 1 when it had one
+        // the row transform of Y = V^{s+1} is the V transform of reverse step s + 1 when it had one;
+        // those of lam (XA) and mu (XC) are in place already
         if (a->xb_is_v) std::swap(a->XB, a->XD);
         else hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / conv_e(L)), 0, c.stream, Y, n, n, n, a->XB, n, p->tw);
-        hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / conv_e(L)), 0, c.stream, a->lam, n, n, n, a->XA, n, p->tw);
         a->xb_is_v = false;
         if (c2 != 0.0) {
-            hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / conv_e(L)), 0, c.stream, a->mu, n, n, n, a->XC, n, p->tw);
             hipLaunchKernelGGL((k_rows_fwd<L>), dim3(np), dim3(L / conv_e(L)), 0, c.stream, V, n, n, n, a->XD, n, p->tw);
             a->xb_is_v = true;
         }

@@ -173,9 +173,10 @@ struct Adjoint {
     double* ckpt = nullptr;         // n_ckpt states V^{qC}
     double* seg = nullptr;          // C + 1 states of the segment being reversed
     double* segE = nullptr;         // C explicit parts of that segment
-    double *lam = nullptr, *mu = nullptr, *ybar = nullptr, *dummy = nullptr, *corr = nullptr, *corr2 = nullptr;
-    int have_corr = 0;               // corr (corr2) hold lam - Ybar of the previous (second previous) reverse step
-    double corr_c = 0.0, corr_c2 = 0.0;   // dt theta of those steps
+    double *lam = nullptr, *mu = nullptr, *ybar = nullptr, *dummy = nullptr;
+    double *corr = nullptr, *corr2 = nullptr, *corr3 = nullptr;
+    int have_corr = 0;               // corr, corr2, corr3 hold lam - Ybar of the last three reverse steps (newest first)
+    double corr_c = 0.0, corr_c2 = 0.0, corr_c3 = 0.0;   // dt theta of those steps
     bool xb_is_v = false;            // XD holds the row transform of V^{s+1} from the previous reverse step
     double2 *XA = nullptr, *XB = nullptr, *XC = nullptr, *XD = nullptr;
     double2* S = nullptr;           // (L/2+1) x L spectral accumulator

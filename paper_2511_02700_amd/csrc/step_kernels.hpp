@@ -482,9 +482,10 @@ __global__ __launch_bounds__(256) void ks_sl_lin(const MarchArgs* __restrict__ A
 
 // Forward FFT of the row pair held in reg (canonical layout) into the
 // transposed half spectra X[k2 * n + row].
+// X2, if not null, receives a second copy.
 template <int L, int E, typename C>
 __device__ __forceinline__ void rows_fwd_store(C (&reg)[E], C* lds, const double2* tw4, C* __restrict__ X, int n,
-                                               int ra, bool hasb) {
+                                               int ra, bool hasb, C* __restrict__ X2 = nullptr) {
     constexpr int T = L / E;
     using Rl = typename CplxOps<C>::real;
     const int tid = threadIdx.x;
@@ -496,9 +497,16 @@ __device__ __forceinline__ void rows_fwd_store(C (&reg)[E], C* lds, const double
     __syncthreads();
     for (int kk = tid; kk <= L / 2; kk += T) {
         const C z = lds[kk], w = lds[kk == 0 ? 0 : L - kk];
+        const C va = CplxOps<C>::make(Rl(0.5) * (z.x + w.x), Rl(0.5) * (z.y - w.y));
+        const C vb = CplxOps<C>::make(Rl(0.5) * (z.y + w.y), Rl(-0.5) * (z.x - w.x));
         C* xk = X + (size_t)kk * n;
-        xk[ra] = CplxOps<C>::make(Rl(0.5) * (z.x + w.x), Rl(0.5) * (z.y - w.y));
-        if (hasb) xk[ra + 1] = CplxOps<C>::make(Rl(0.5) * (z.y + w.y), Rl(-0.5) * (z.x - w.x));
+        xk[ra] = va;
+        if (hasb) xk[ra + 1] = vb;
+        if (X2) {
+            C* x2 = X2 + (size_t)kk * n;
+            x2[ra] = va;
+            if (hasb) x2[ra + 1] = vb;
+        }
     }
 }
 
@@ -865,14 +873,16 @@ static __global__ void ks_adj_begin(const MarchArgs* __restrict__ A, int s) {
     }
 }
 
-// Starting value lam^0 = Ybar + w1 c1 + w2 c2 and its row transform, where
-// c1, c2 = lam - Ybar of the two previous reverse steps (lam - Ybar = dt theta
-// A^T lam): the correction extrapolated linearly (w1 = 2, w2 = -1) or kept
-// (w1 = 1, w2 = 0), rescaled by the ratio of the steps' dt theta; c1, c2 may be null.
+// Starting value lam^0 = Ybar + w1 c1 + w2 c2 + w3 c3 and its row transform,
+// where c1, c2, c3 = lam - Ybar of the previous reverse steps, newest first
+// (lam - Ybar = dt theta A^T lam): the correction extrapolated quadratically
+// (3, -3, 1), linearly (2, -1) or kept (1), rescaled by the ratio of the
+// steps' dt theta; c1, c2, c3 may be null.
 template <int L, int E>
 __global__ __launch_bounds__(L / E) void ks_adj_start(const MarchArgs* __restrict__ A,
                                                      const double* __restrict__ c1, double w1,
-                                                     const double* __restrict__ c2, double w2) {
+                                                     const double* __restrict__ c2, double w2,
+                                                     const double* __restrict__ c3, double w3) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0)) return;
     constexpr int T = L / E;
@@ -892,10 +902,10 @@ __global__ __launch_bounds__(L / E) void ks_adj_start(const MarchArgs* __restric
         double va = 0.0, vb = 0.0;
         if (j < n) {
             const size_t oa = (size_t)ra * n + j, ob = (size_t)rb * n + j;
-            va = a.W[oa] + (c1 ? w1 * c1[oa] : 0.0) + (c2 ? w2 * c2[oa] : 0.0);
+            va = a.W[oa] + (c1 ? w1 * c1[oa] : 0.0) + (c2 ? w2 * c2[oa] : 0.0) + (c3 ? w3 * c3[oa] : 0.0);
             lam[oa] = va;
             if (hasb) {
-                vb = a.W[ob] + (c1 ? w1 * c1[ob] : 0.0) + (c2 ? w2 * c2[ob] : 0.0);
+                vb = a.W[ob] + (c1 ? w1 * c1[ob] : 0.0) + (c2 ? w2 * c2[ob] : 0.0) + (c3 ? w3 * c3[ob] : 0.0);
                 lam[ob] = vb;
             }
         }
@@ -938,9 +948,13 @@ static __global__ void ks_adj_end(const MarchArgs* __restrict__ A, int kmax) {
 }
 
 // mu = (T_1^T (x) T_2^T) lam (the transposed semi-Lagrangian gather) into
-// pool[0]; when theta < 1 also its row transform for B^T mu.
-template <int L, int E>
-__global__ __launch_bounds__(L / E) void ks_adj_sl(const MarchArgs* __restrict__ A) {
+// pool[0]; when theta < 1 also its row transform for B^T mu, into X and, if
+// X2 is not null, into X2 as well (the spectral gradient term reads it).
+// WM > 0: the transposed tables are at most WM wide (the host checks), so
+// each thread holds its columns' sources and weights in registers and the
+// loops have fixed bounds; WM = 0: any width.
+template <int L, int E, int WM>
+__global__ __launch_bounds__(L / E) void ks_adj_sl(const MarchArgs* __restrict__ A, double2* __restrict__ X2) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0)) return;
     constexpr int T = L / E;
@@ -954,34 +968,91 @@ __global__ __launch_bounds__(L / E) void ks_adj_sl(const MarchArgs* __restrict__
     if (fft) load_twiddles<L, E>(a.tw, tw4);
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < n;
-    const double* lam = a.pool[a.ctl->y];
-    double* mu = a.pool[a.ctl->cur];
+    const double* __restrict__ lam = a.pool[a.ctl->y];
+    double* __restrict__ mu = a.pool[a.ctl->cur];
     const int W1 = sd.wt1, W2 = sd.wt2;
+    double outv[E][2];
+    if constexpr (WM > 0) {
+        // the sources of rows ra and rb (block-uniform)
+        int ia[WM], ib[WM];
+        double wa[WM], wb[WM];
+#pragma unroll
+        for (int q = 0; q < WM; ++q) {
+            const bool in = q < W1;
+            ia[q] = in ? sd.t1i[(size_t)ra * W1 + q] : ra;
+            wa[q] = in ? sd.t1w[(size_t)ra * W1 + q] : 0.0;
+            ib[q] = (in && hasb) ? sd.t1i[(size_t)rb * W1 + q] : ra;
+            wb[q] = (in && hasb) ? sd.t1w[(size_t)rb * W1 + q] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = threadIdx.x + e * T;
+            double sa = 0.0, sb = 0.0;
+            if (j < n) {
+                int jc[WM];
+                double wc[WM];
+#pragma unroll
+                for (int q = 0; q < WM; ++q) {
+                    const bool in = q < W2;
+                    jc[q] = in ? sd.t2i[(size_t)j * W2 + q] : j;
+                    wc[q] = in ? sd.t2w[(size_t)j * W2 + q] : 0.0;
+                }
+#pragma unroll
+                for (int q1 = 0; q1 < WM; ++q1) {
+                    if (q1 >= W1) break;
+                    const double* la = lam + (size_t)ia[q1] * n;
+                    const double* lb = lam + (size_t)ib[q1] * n;
+                    double ta = 0.0, tb = 0.0;
+#pragma unroll
+                    for (int q2 = 0; q2 < WM; ++q2) {
+                        if (q2 < W2) {
+                            ta += wc[q2] * la[jc[q2]];
+                            tb += wc[q2] * lb[jc[q2]];
+                        }
+                    }
+                    sa += wa[q1] * ta;
+                    sb += wb[q1] * tb;
+                }
+            }
+            outv[e][0] = sa;
+            outv[e][1] = hasb ? sb : 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = threadIdx.x + e * T;
+            outv[e][0] = outv[e][1] = 0.0;
+            if (j < n) {
+                for (int r = 0; r < 2; ++r) {
+                    const int i = ra + r;
+                    if (r == 1 && !hasb) break;
+                    double acc = 0.0;
+                    for (int q1 = 0; q1 < W1; ++q1) {
+                        const double w = sd.t1w[(size_t)i * W1 + q1];
+                        const double* lr = lam + (size_t)sd.t1i[(size_t)i * W1 + q1] * n;
+                        double s2 = 0.0;
+                        for (int q2 = 0; q2 < W2; ++q2)
+                            s2 += sd.t2w[(size_t)j * W2 + q2] * lr[sd.t2i[(size_t)j * W2 + q2]];
+                        acc += w * s2;
+                    }
+                    outv[e][r] = acc;
+                }
+            }
+        }
+    }
+    // the writes after every read (mu is not read here, but the compiler
+    // cannot tell)
     double2 reg[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int j = threadIdx.x + e * T;
-        double out[2] = {0.0, 0.0};
         if (j < n) {
-            for (int r = 0; r < 2; ++r) {
-                const int i = ra + r;
-                if (r == 1 && !hasb) break;
-                double acc = 0.0;
-                for (int q1 = 0; q1 < W1; ++q1) {
-                    const double wa = sd.t1w[(size_t)i * W1 + q1];
-                    if (wa == 0.0) continue;
-                    const double* lr = lam + (size_t)sd.t1i[(size_t)i * W1 + q1] * n;
-                    double s2 = 0.0;
-                    for (int q2 = 0; q2 < W2; ++q2) s2 += sd.t2w[(size_t)j * W2 + q2] * lr[sd.t2i[(size_t)j * W2 + q2]];
-                    acc += wa * s2;
-                }
-                mu[(size_t)i * n + j] = acc;
-                out[r] = acc;
-            }
+            mu[(size_t)ra * n + j] = outv[e][0];
+            if (hasb) mu[(size_t)rb * n + j] = outv[e][1];
         }
-        reg[e] = make_double2(out[0], out[1]);
+        reg[e] = make_double2(outv[e][0], outv[e][1]);
     }
-    if (fft) rows_fwd_store<L, E>(reg, lds, tw4, a.X, n, ra, hasb);
+    if (fft) rows_fwd_store<L, E>(reg, lds, tw4, a.X, n, ra, hasb, X2);
 }
 
 // Per-step gradient terms of the reverse step (one block per row pair,

@@ -5,12 +5,14 @@ oracle_fv512.npz:
     python tests/golden/make_oracle_fv512.py
 
 Calls only the oracle (FP64, BiCGSTAB inner solves to 1e-15, fixed-point tol
-1e-14); about ten minutes on eight cores.  Stored arrays:
+1e-14); about three minutes on four cores.  Stored arrays:
   idx              the sampled node indices 0, 8, ..., 504 (per axis)
   entries          step-list entries (1-based counts) at which the grid is kept
   V_<e>            the grid after the first e entries on the sampled nodes
   spots            64 seeded spot pairs (workloads.spot_pairs(64, seed=1))
   price, delta     prices and spot deltas there after the whole march
+  greeks           the Delta and Gamma surfaces of the final grid (delta1, delta2,
+                   gamma11, gamma12, gamma22) on the sampled nodes
   iters            fixed-point iterations of every entry
 """
 
@@ -53,8 +55,9 @@ def make(name="fv512"):
     V, iters = scheme.solve(prob, tol=1e-14, inner="bicgstab", on_step=keep)
     spots = workloads.spot_pairs(64, seed=1)
     price, delta = output.prices(V, prob.y_lo, h, w["K"], spots, with_delta=True)
+    greeks = np.stack([g[np.ix_(idx, idx)] for g in output.greeks_on_grid(V, prob.y_lo, h, w["K"])])
     out = os.path.join(HERE, "oracle_%s.npz" % name)
-    np.savez(out, idx=idx, entries=np.array(ENTRIES), spots=spots, price=price, delta=delta,
+    np.savez(out, idx=idx, entries=np.array(ENTRIES), spots=spots, price=price, delta=delta, greeks=greeks,
              iters=np.array(iters), name=name, **kept)
     print("%s: %d entries in %.0f s -> %s" % (name, len(iters), time.time() - t0, out), flush=True)
 

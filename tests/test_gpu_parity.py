@@ -228,7 +228,7 @@ def _fv512_oracle_8():
 def test_radix_schedules(lp, L, radix):
     """The march with other transform sides and FFT radix schedules (elements
     per thread) reaches the same fixed points: fv512 after 8 step-list entries
-    (its own side is 768), FP64 against the oracle within 1e-10 and mixed
+    (its own side is 1024), FP64 against the oracle within 1e-10 and mixed
     within 1e-6."""
     _note("radix %d, L %d, fv512" % (radix, L))
     w = workloads.workload("fv512")
