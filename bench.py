@@ -8,25 +8,27 @@ the step list including the damped block) from V^0 to V^{N_t}, with the inputs
 resident in device memory.  value = n^2 * N_t * steps / (timed wall time), in
 grid-point time steps per second.
 
-Default workload: the 512 x 512 finite-variation NTS case (alpha = 0.3) on
-[-4, 4]^2 with 256 time steps, theta = 1/2, fixed-point tol 1e-12, FP64 (with
-the library's defaults: the explicit part from the previous step's equation
-and B Y^0 of the first iteration from stored products, both exact at the
-fixed point).
+Default workload: nig2048_m, the 2048 x 2048 NIG case (alpha = 1/2,
+correlation -0.5) on [-5, 5]^2 with 1024 time steps, theta = 1/2, fixed-point
+tol 1e-12, FP64 (with the library's defaults: the explicit part from the
+previous step's equation and B Y^0 of the first iteration from stored
+products, both exact at the fixed point).  Its working set (grids, the
+transposed intermediate and the spectrum: about 0.7 GB) exceeds the caches, so
+the kernels are measured against HBM.
 
 Printed (one JSON line): the metric, the roofline of the dominant kernel
 (algorithmic bytes per launch / mean launch time from HIP events bound to the
-kernel's own dispatches on the plan's stream, over the timed solves), the same for the correlation's
-column pass, the other precision timed beside it with the mixed-vs-plain
-differences, and a CPU baseline: the FP64 oracle timed on this host on a
-bounded sample of the same workload, and the plan time (host discretization,
-spectrum, factors).  Unless --no-extras: the column-pass
-roofline at 2048^2 (cache-exceeding working set), whole 2048^2 solves in
-both precisions, the paper's Table 3 prices against GPU marches, the adjoint
-form on its
-1024^2 workload (ratio to the forward, with checkpoints every 32 steps and
-with every state kept), and the batched form on 32 draws of the batched recipe
-(against solo solves).
+kernel's own dispatches on the plan's stream, over the timed solves), the same
+for the correlation's column pass and for the correlation as a whole, the
+other precision timed beside it with the mixed-vs-plain differences (prices,
+deltas, Delta/Gamma surfaces), the other candidate transform side, and a CPU
+baseline: the FP64 oracle timed on this host on a bounded sample of the same
+workload (in a child process, while the GPU extras run), and the plan time.
+Unless --no-extras: the 512^2 finite-variation workload (fv512), the paper's
+Table 3 prices against GPU marches, the adjoint form on its 1024^2 workload
+(ratio to the forward, with checkpoints every 32 steps and with every state
+kept), and the batched form on all 256 draws of the batched recipe (autotuned,
+against solo solves).
 """
 
 import argparse
@@ -167,9 +169,13 @@ def timed_solves(plan, out, steps, timed_classes):
     return wall, stats
 
 
-def cpu_baseline(w, steps):
-    """The oracle (unchanged) on the first `steps` entries of the step list of
-    the same workload; grid-pt-steps/s and the threads it kept busy."""
+def cpu_baseline(w, entries=2):
+    """The oracle (unchanged) on the first `entries` entries of the step list of
+    the same workload; the sample is the last of them, timed from the previous
+    entry's end with the oracle's own step observer (the set-up before it --
+    cell averages of V^0, the ILU factors of the first step -- is left out).
+    grid-pt-steps/s (one entry stands for N_t / n_entries time steps, as in
+    the GPU figure) and the threads it kept busy in that entry."""
     from oracle import integral, levy, scheme
     m = w["model"]
     p = levy.nts_from_std(m["sigma1"], m["sigma2"], m["corr"], m["theta1"], m["theta2"], m["kappa"], m["alpha"])
@@ -177,86 +183,169 @@ def cpu_baseline(w, steps):
     h = (w["y_hi"] - w["y_lo"]) / (n - 1)
     d = integral.discretize(p, h, w["r"])
     prob = scheme.Problem(n, (w["y_lo"], w["y_lo"]), h, d, K=w["K"], T=w["T"], N_t=w["N_t"], theta=w["theta"])
-    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    n_entries = len(scheme.step_list(w["theta"], w["T"], w["N_t"]))
+    marks = []
+
+    def mark(s, V):
+        r = resource.getrusage(resource.RUSAGE_SELF)
+        marks.append((time.perf_counter(), r.ru_utime + r.ru_stime))
+
     t0 = time.perf_counter()
-    scheme.solve(prob, tol=w["tol"], inner="bicgstab", n_steps=steps)
-    wall = time.perf_counter() - t0
-    r1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    return dict(value=n * n * steps / wall, unit="grid-pt-steps/s", cores=max(1, int(round(cpu / wall))),
-                kind="oracle",
-                sample="first %d entries of the step list (4 damped theta=1 quarter steps + %d theta=1/2 steps) "
-                       "of the %dx%d workload, BiCGSTAB+ILU inner solves, tol %g; %.1f s wall, %.1f s CPU; "
-                       "host threads available %d" % (steps, max(0, steps - 4), n, n, w["tol"], wall, cpu,
-                                                      len(os.sched_getaffinity(0))))
+    scheme.solve(prob, tol=w["tol"], inner="bicgstab", n_steps=entries, on_step=mark)
+    total = time.perf_counter() - t0
+    wall = marks[-1][0] - marks[-2][0]
+    cpu = marks[-1][1] - marks[-2][1]
+    return dict(value=n * n * (w["N_t"] / n_entries) / wall, unit="grid-pt-steps/s",
+                cores=max(1, int(round(cpu / wall))), kind="oracle",
+                sample="step-list entry %d of %d (a damped theta=1 quarter step) of the %dx%d workload, timed from the "
+                       "end of entry %d (the oracle's set-up and first entry, %.0f s, left out): %.1f s wall, %.1f s "
+                       "CPU; BiCGSTAB+ILU inner solves, tol %g; host threads available %d" % (
+                           entries, n_entries, n, n, entries - 1, total - wall, wall, cpu, w["tol"],
+                           len(os.sched_getaffinity(0))))
 
 
-def large_conv_roofline(lp, name, steps=40):
-    """Column pass of the correlation at 2048^2 (automatic side L = 3072; also
-    FP64 at L = 4096), where the working set (spectrum + intermediate, 176 MB at
-    3072, 201 MB at 4096, with the grids beside them) no longer stays in the
-    caches: HIP-event mean over the working launches of the first `steps`
-    entries of the step list, FP64 and mixed."""
-    import workloads
-    w = workloads.workload(name)
-    out = {"workload": "%s, first %d step-list entries" % (name, steps)}
-    for prec in ("fp64", "fp32conv", "fp64_pow2"):
-        plan = (lp.plan_from_workload(w, precision=prec) if prec != "fp64_pow2" else
-                lp.plan_from_workload(w, fft_size=1 << (out["fp64"]["L"] - 1).bit_length()))
-        plan.solve_steps(4)
-        plan.set_timing(["cols", "rows_inv", "line_rows"])
-        plan.solve_steps(steps)
-        st = plan.kernel_stats()
-        la, ms = st["cols"]
-        plan.set_timing([])
-        info = plan.info()
-        out[prec] = roofline("cols", w["n"], info["L"], prec == "fp32conv", la, ms, radix=info["radix"],
-                             traffic_json=os.path.join(ROOT, "profiles", "pmc_%s.json" % name))
-        out[prec]["L"] = info["L"]
-        out[prec]["conv_whole"] = conv_whole(w["n"], info["L"], prec == "fp32conv", st)
-        del plan
-    return out
+def cpu_baseline_start(name):
+    """The oracle sample in a child process (CPU only), so it runs while the
+    GPU extras do; returns the process (cpu_baseline_finish reads its line)."""
+    import subprocess
+    env = dict(os.environ, PYTHONPATH=ROOT)
+    code = ("import json, bench, workloads; "
+            "print(json.dumps(bench.cpu_baseline(workloads.workload(%r))))" % name)
+    return subprocess.Popen([sys.executable, "-c", code], cwd=ROOT, env=env, stdout=subprocess.PIPE,
+                            stderr=subprocess.PIPE, text=True)
 
 
-def large_solve(lp, name="nig2048_m"):
-    """Whole solves of a 2048^2, 1024-step workload (the large-grid form), FP64
-    and mixed on the smallest transform side, and FP64 on the power of two
-    above it: grid-pt-steps/s, iterations per step and the price differences
-    at 64 seeded spot pairs."""
+def cpu_baseline_finish(proc, timeout=900):
+    out, err = proc.communicate(timeout=timeout)
+    if proc.returncode != 0:
+        return {"error": "oracle sample failed: " + err.strip()[-400:]}
+    return json.loads(out.strip().splitlines()[-1])
+
+
+def central_nodes(w, lo=80.0, hi=120.0):
+    """Grid indices whose spot S = K e^y lies in [lo, hi] (per axis)."""
+    import numpy as np
+    n = w["n"]
+    y = w["y_lo"] + (w["y_hi"] - w["y_lo"]) / (n - 1) * np.arange(n)
+    S = w["K"] * np.exp(y)
+    return np.nonzero((S >= lo) & (S <= hi))[0]
+
+
+def greek_diffs(pa, Va, pb, Vb, sel):
+    """Max |a - b| / max |b| of the five Delta/Gamma surfaces on the nodes sel x sel."""
+    import numpy as np
+    ga = pa.greeks(Va).cpu().numpy()[:, sel][:, :, sel]
+    gb = pb.greeks(Vb).cpu().numpy()[:, sel][:, :, sel]
+    names = ("delta1", "delta2", "gamma11", "gamma12", "gamma22")
+    return {k: float(np.max(np.abs(ga[q] - gb[q])) / max(1e-300, float(np.max(np.abs(gb[q])))))
+            for q, k in enumerate(names)}
+
+
+def measure_workload(lp, name, steps, warmup, precision="fp64", sl_order=3, fft_size=0, traffic_json=None,
+                     other_side=True):
+    """Throughput and rooflines of full solves of a workload (both forms), as in
+    the headline: `steps` timed solves without events, then `steps` with HIP
+    events bound to the dominant class and the three correlation kernels."""
     import numpy as np
     import torch
     import workloads
     w = workloads.workload(name)
-    spots = workloads.spot_pairs(64, seed=2)
-    out = {"workload": "%s: %dx%d on [%g, %g]^2, %d steps, alpha %g, corr %g" % (
-        name, w["n"], w["n"], w["y_lo"], w["y_hi"], w["N_t"], w["model"]["alpha"], w["model"]["corr"])}
-    prices = {}
-    for prec in ("fp64", "fp32conv", "fp64_pow2"):
+    n, Nt = w["n"], w["N_t"]
+    other = "fp32conv" if precision == "fp64" else "fp64"
+    plan_ms, plans = {}, {}
+    for pr in (precision, other):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plan = (lp.plan_from_workload(w, precision=prec) if prec != "fp64_pow2" else
-                lp.plan_from_workload(w, fft_size=1 << (out.get("L", 2) - 1).bit_length()))
+        plans[pr] = lp.plan_from_workload(w, sl_order=sl_order, precision=pr, fft_size=fft_size)
         torch.cuda.synchronize()
-        plan_ms = 1e3 * (time.perf_counter() - t0)
-        V = plan.solve()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.solve(V)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        info = plan.info()
-        prices[prec] = plan.price(V, spots).cpu().numpy()
-        out.setdefault("L", info["L"])
-        out[prec] = {"value": w["n"] ** 2 * w["N_t"] / dt, "unit": "grid-pt-steps/s", "ms": 1e3 * dt,
-                     "iters_per_step": info["total_iters"] / info["n_steps"], "radix": info["radix"],
-                     "L": info["L"], "plan_ms": plan_ms}
-        del plan, V
-        torch.cuda.empty_cache()
-    out["mixed_vs_plain_prices_rel"] = float(np.max(np.abs(prices["fp32conv"] - prices["fp64"]) /
-                                                np.maximum(1.0, np.abs(prices["fp64"]))))
-    out["pow2_vs_default_prices_rel"] = float(np.max(np.abs(prices["fp64_pow2"] - prices["fp64"]) /
-                                                 np.maximum(1.0, np.abs(prices["fp64"]))))
-    return out
+        plan_ms[pr] = 1e3 * (time.perf_counter() - t0)
+    plan = plans[precision]
+    mixed = precision == "fp32conv"
+    info = plan.info()
+    L = info["L"]
+    outs = {pr: torch.empty((n, n), dtype=torch.float64, device="cuda") for pr in plans}
+    for pr in plans:
+        for _ in range(warmup):
+            plans[pr].solve(outs[pr])
+    torch.cuda.synchronize()
+    # one untimed profiling solve with every kernel class timed: picks the dominant class
+    plan.set_timing(lp._lib.KCLASSES)
+    plan.solve(outs[precision])
+    prof = plan.kernel_stats()
+    dominant = max(prof, key=lambda c: prof[c][1])
+    # timed region: K solves without events, giving value; then the same K
+    # solves with start/stop events bound to every launch of the dominant
+    # class and of the correlation's three kernels (the events take the
+    # dispatch's own timestamps), giving their mean launch durations
+    wall, _ = timed_solves(plan, outs[precision], steps, [])
+    _, live = timed_solves(plan, outs[precision], steps, sorted({dominant, "cols", "rows_inv", "line_rows"}))
+    info = plan.info()
+    # the other precision on the same workload: throughput, conv roofline, and
+    # the mixed-vs-plain differences at seeded spot pairs and on the Greeks
+    wall_o, _ = timed_solves(plans[other], outs[other], steps, [])
+    _, live_o = timed_solves(plans[other], outs[other], steps, ["cols", "rows_inv", "line_rows"])
+    spots = workloads.spot_pairs(64, seed=7)
+    pd = {pr: plans[pr].price(outs[pr], spots, with_delta=True) for pr in plans}
+    p64, d64 = (t.cpu().numpy() for t in pd["fp64"])
+    p32, d32 = (t.cpu().numpy() for t in pd["fp32conv"])
+    rel_grid = float((outs["fp32conv"] - outs["fp64"]).abs().div(outs["fp64"].abs().clamp_min(1.0)).max())
+    oinfo = plans[other].info()
+    res = {
+        "value": n * n * Nt * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "dtype": "f64" if not mixed else "f32 correlation / f64 rest",
+        "config": {"workload": "%s: put-on-average K=100 T=1 r=0.03, NTS alpha=%g sigma=(%g,%g) corr=%g "
+                               "theta=(%g,%g) kappa=%g, %dx%d log grid on [%g,%g]^2, %d time steps, theta=%g, "
+                               "tol %g, SL order %d, %s" % (
+                                   name, w["model"]["alpha"], w["model"]["sigma1"], w["model"]["sigma2"],
+                                   w["model"]["corr"], w["model"]["theta1"], w["model"]["theta2"],
+                                   w["model"]["kappa"], n, n, w["y_lo"], w["y_hi"], Nt, w["theta"], w["tol"],
+                                   sl_order, precision),
+                   "n": n, "N_t": Nt, "L": L, "N_z": info["N_z"], "precision": precision,
+                   "parallelism": "single GPU"},
+        "roofline": roofline(dominant, n, L, mixed, *live[dominant], traffic_json=traffic_json, sl_order=sl_order,
+                             radix=info["radix"]),
+        "conv_roofline": roofline("cols", n, L, mixed, *live["cols"], traffic_json=traffic_json,
+                                  sl_order=sl_order, radix=info["radix"]),
+        "conv_whole": conv_whole(n, L, mixed, live),
+        "plan_ms": plan_ms[precision],
+        "radix_schedule": dict(zip(("cols", "row_c2r", "line_rows", "sl"), info["radix"])),
+        "iters_per_step": info["total_iters"] / info["n_steps"],
+        "kernel_ms_per_solve": {c: prof[c][1] for c in prof if prof[c][0]},
+        other: {"value": n * n * Nt * steps / wall_o, "ms_per_step": 1e3 * wall_o / steps,
+                "conv_roofline": roofline("cols", n, L, other == "fp32conv", *live_o["cols"],
+                                          traffic_json=traffic_json, sl_order=sl_order, radix=oinfo["radix"]),
+                "conv_whole": conv_whole(n, L, other == "fp32conv", live_o),
+                "iters_per_step": oinfo["total_iters"] / oinfo["n_steps"], "plan_ms": plan_ms[other]},
+        "mixed_vs_plain_rel": {"prices": float(np.max(np.abs(p32 - p64) / np.maximum(1.0, np.abs(p64)))),
+                               "deltas_abs": float(np.max(np.abs(d32 - d64))), "grid": rel_grid,
+                               "greeks_rel_S_80_120": greek_diffs(plans["fp32conv"], outs["fp32conv"],
+                                                                  plans["fp64"], outs["fp64"], central_nodes(w)),
+                               "spots": 64, "bound": 1e-6},
+    }
+    if other_side:
+        # the same solve on the other candidate transform side: 3L/4 for a power
+        # of two L (when it still covers the kernel's support), else the power of two above
+        alt = 3 * L // 4 if L & (L - 1) == 0 else 1 << (L - 1).bit_length()
+        try:
+            p2 = lp.plan_from_workload(w, sl_order=sl_order, precision=precision, fft_size=alt)
+        except lp.LpideError:
+            p2 = None
+        if p2 is not None:
+            o2 = torch.empty((n, n), dtype=torch.float64, device="cuda")
+            p2.solve(o2)
+            wall2, _ = timed_solves(p2, o2, steps, [])
+            res["other_side"] = {"L": alt, "radix": p2.info()["radix"], "value": n * n * Nt * steps / wall2,
+                                 "ms_per_step": 1e3 * wall2 / steps,
+                                 "max_rel_diff": float((o2 - outs[precision]).abs().div(
+                                     outs[precision].abs().clamp_min(1.0)).max())}
+            p2.close()
+            del o2
+    for pr in plans:
+        plans[pr].close()
+    del outs
+    torch.cuda.empty_cache()
+    return res
 
 
 def table3_check(lp):
@@ -365,17 +454,23 @@ def adjoint_measure(lp, name="nts1024", C=32):
             "grad": [float(g) for g in grad]}
 
 
-def batch_measure(lp, count=32, seed=3):
-    """The batched form on the first `count` draws of the batched workload
-    recipe: grid-pt-steps/s of one batched solve (autotuned, hipGraph replay)
-    against the same plans solved one after the other."""
+def batch_measure(lp, count=256, seed=3, trial_steps=32):
+    """The batched form on `count` draws of the batched workload recipe: grid-
+    pt-steps/s of one batched solve (autotuned on steady windows, hipGraph
+    replay, one launch per kernel and group) against the same plans solved one
+    after the other."""
     import torch
     import workloads
     draws = workloads.batch_draw(256, seed=seed)[:count]
+    t0 = time.perf_counter()
     plans = [lp.plan_from_workload(d) for d in draws]
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
     work = sum(d["n"] ** 2 * d["N_t"] for d in draws)
     batch = lp.Batch(plans)
-    groups = batch.tune(trial_steps=8)
+    t0 = time.perf_counter()
+    groups = batch.tune(trial_steps=trial_steps)
+    tune_s = time.perf_counter() - t0
     outs = batch.solve()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -392,10 +487,47 @@ def batch_measure(lp, count=32, seed=3):
     torch.cuda.synchronize()
     t_s = time.perf_counter() - t0
     diff = max(float((a - b).abs().max()) for a, b in zip(outs, solo))
-    return {"workload": "first %d draws of the batched recipe (seed %d): n in %s" % (
-                count, seed, sorted({d["n"] for d in draws})),
+    ns = {}
+    for d in draws:
+        ns[d["n"]] = ns.get(d["n"], 0) + 1
+    batch.close()
+    for p in plans:
+        p.close()
+    del outs, solo
+    torch.cuda.empty_cache()
+    return {"workload": "%d draws of the batched recipe (seed %d): plans per n %s, alpha ~ U[0.2, 0.6], sigma ~ "
+                        "U[0.1, 0.4], corr ~ U[-0.7, 0.7], K ~ U[80, 120], T ~ U[0.25, 2], N_t = n/2" % (
+                            count, seed, dict(sorted(ns.items()))),
             "value": work / t_b, "unit": "grid-pt-steps/s", "ms": 1e3 * t_b, "solo_ms": 1e3 * t_s,
-            "speedup_vs_solo": t_s / t_b, "max_abs_diff_vs_solo": diff, "groups": groups}
+            "speedup_vs_solo": t_s / t_b, "max_abs_diff_vs_solo": diff, "plans_s": plan_s, "tune_s": tune_s,
+            "trial_steps": trial_steps, "groups": groups}
+
+
+def fv512_vs_oracle(lp):
+    """The whole fv512 march in both forms against the oracle's (the committed
+    golden written by tests/golden/make_oracle_fv512.py): prices and deltas at
+    its 64 spot pairs, the grid on its sampled nodes, and the Delta/Gamma
+    surfaces there when the golden holds them."""
+    import numpy as np
+    import workloads
+    g = np.load(os.path.join(ROOT, "tests", "golden", "oracle_fv512.npz"))
+    idx = g["idx"]
+    out = {}
+    for pr in ("fp64", "fp32conv"):
+        plan = lp.plan_from_workload(workloads.workload("fv512"), precision=pr)
+        V = plan.solve()
+        p, d = plan.price(V, g["spots"], with_delta=True)
+        r = {"prices_rel": float(np.max(np.abs(p.cpu().numpy() - g["price"]) / np.maximum(1.0, np.abs(g["price"])))),
+             "deltas_abs": float(np.max(np.abs(d.cpu().numpy() - g["delta"]))),
+             "grid_rel": float(np.max(np.abs(V.cpu().numpy()[np.ix_(idx, idx)] - g["V_259"]) /
+                                      np.maximum(1.0, np.abs(g["V_259"]))))}
+        if "greeks" in g:
+            gs = plan.greeks(V).cpu().numpy()[:, idx][:, :, idx]
+            for q, k in enumerate(("delta1", "delta2", "gamma11", "gamma12", "gamma22")):
+                r[k + "_rel"] = float(np.max(np.abs(gs[q] - g["greeks"][q])) / np.max(np.abs(g["greeks"][q])))
+        out[pr] = r
+        plan.close()
+    return out
 
 
 def main():
@@ -403,14 +535,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed full solves")
     ap.add_argument("--warmup", type=int, default=2, help="untimed full solves")
-    ap.add_argument("--workload", default="fv512")
+    ap.add_argument("--workload", default="nig2048_m")
     ap.add_argument("--sl-order", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "fp32conv"], default="fp64",
                     help="form timed for the headline value; the other form is timed beside it")
-    ap.add_argument("--cpu-steps", type=int, default=8, help="step-list entries of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the 2048^2 conv roofline, the adjoint and the batched measurements")
+                    help="skip fv512, Table 3, the adjoint and the batched measurements")
+    ap.add_argument("--batch-count", type=int, default=256, help="draws of the batched recipe in the batched leg")
     ap.add_argument("--fft-size", type=int, default=0,
                     help="transform side of the correlation (0: the smallest supported one, 2^m or 3*2^m)")
     ap.add_argument("--traffic-json", default=None,
@@ -422,128 +554,43 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
+    import torch  # noqa: F401
 
     import paper_2511_02700_amd as lp
-    import workloads
 
     rank = int(os.environ.get("RANK", "0"))
     tj = args.traffic_json or os.path.join(ROOT, "profiles", "pmc_%s.json" % args.workload)
-    w = workloads.workload(args.workload)
-    n, Nt = w["n"], w["N_t"]
-    other = "fp32conv" if args.precision == "fp64" else "fp64"
-    plan_ms = {}
-    plans = {}
-    for pr in (args.precision, other):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plans[pr] = lp.plan_from_workload(w, sl_order=args.sl_order, precision=pr, fft_size=args.fft_size)
-        torch.cuda.synchronize()
-        plan_ms[pr] = 1e3 * (time.perf_counter() - t0)
-    plan = plans[args.precision]
-    mixed = args.precision == "fp32conv"
-    info = plan.info()
-    L = info["L"]
-    outs = {pr: torch.empty((n, n), dtype=torch.float64, device="cuda") for pr in plans}
-    for pr in plans:
-        for _ in range(args.warmup):
-            plans[pr].solve(outs[pr])
-    torch.cuda.synchronize()
-
-    # one untimed profiling solve with every kernel class timed: picks the dominant class
-    plan.set_timing(lp._lib.KCLASSES)
-    plan.solve(outs[args.precision])
-    prof = plan.kernel_stats()
-    dominant = max(prof, key=lambda c: prof[c][1])
-
-    # timed region: K solves without events, giving value; then the same K
-    # solves with start/stop events bound to every launch of the dominant
-    # class and of the correlation's column pass (the events take the
-    # dispatch's own timestamps), giving their mean launch durations
-    wall, _ = timed_solves(plan, outs[args.precision], args.steps, [])
-    _, live = timed_solves(plan, outs[args.precision], args.steps,
-                           sorted({dominant, "cols", "rows_inv", "line_rows"}))
-    info = plan.info()
-    ms_per_step = 1e3 * wall / args.steps
-    value = n * n * Nt * args.steps / wall
-
-    # the other precision on the same workload: throughput, conv roofline, and
-    # the mixed-vs-plain difference of prices and deltas at seeded spot pairs
-    wall_o, _ = timed_solves(plans[other], outs[other], args.steps, [])
-    _, live_o = timed_solves(plans[other], outs[other], args.steps, ["cols"])
-    spots = workloads.spot_pairs(64, seed=7)
-    pd = {pr: plans[pr].price(outs[pr], spots, with_delta=True) for pr in plans}
-    p64, d64 = (t.cpu().numpy() for t in pd["fp64"])
-    p32, d32 = (t.cpu().numpy() for t in pd["fp32conv"])
-    import numpy as np
-    rel_p = float(np.max(np.abs(p32 - p64) / np.maximum(1.0, np.abs(p64))))
-    abs_d = float(np.max(np.abs(d32 - d64)))
-    rel_grid = float((outs["fp32conv"] - outs["fp64"]).abs().div(outs["fp64"].abs().clamp_min(1.0)).max())
-
+    head = measure_workload(lp, args.workload, args.steps, args.warmup, args.precision, args.sl_order,
+                            args.fft_size, tj)
     result = {
         "metric": METRIC,
-        "value": value,
+        "value": head.pop("value"),
         "unit": "grid-pt-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if not mixed else "f32 correlation / f64 rest",
+        "dtype": head.pop("dtype"),
         "data": "synthetic",
-        "config": {"workload": "%s: put-on-average K=100 T=1 r=0.03, NTS alpha=%g sigma=(%g,%g) corr=%g "
-                               "theta=(%g,%g) kappa=%g, %dx%d log grid on [%g,%g]^2, %d time steps, theta=%g, "
-                               "tol %g, SL order %d, %s" % (
-                                   args.workload, w["model"]["alpha"], w["model"]["sigma1"], w["model"]["sigma2"],
-                                   w["model"]["corr"], w["model"]["theta1"], w["model"]["theta2"],
-                                   w["model"]["kappa"], n, n, w["y_lo"], w["y_hi"], Nt, w["theta"], w["tol"],
-                                   args.sl_order, args.precision),
-                   "n": n, "N_t": Nt, "L": L, "N_z": info["N_z"], "precision": args.precision,
-                   "parallelism": "single GPU"},
-        "roofline": roofline(dominant, n, L, mixed, *live[dominant], traffic_json=tj, sl_order=args.sl_order,
-                             radix=info["radix"]),
-        "conv_roofline": roofline("cols", n, L, mixed, *live["cols"], traffic_json=tj, sl_order=args.sl_order,
-                                  radix=info["radix"]),
-        "plan_ms": plan_ms[args.precision],
-        "conv_whole": conv_whole(n, L, mixed, live),
-        "radix_schedule": dict(zip(("cols", "row_c2r", "line_rows", "sl"), info["radix"])),
-        "iters_per_step": info["total_iters"] / info["n_steps"],
-        "kernel_ms_per_solve": {c: prof[c][1] for c in prof if prof[c][0]},
-        other: {"value": n * n * Nt * args.steps / wall_o, "ms_per_step": 1e3 * wall_o / args.steps,
-                "conv_roofline": roofline("cols", n, L, other == "fp32conv", *live_o["cols"], traffic_json=tj,
-                                          sl_order=args.sl_order, radix=plans[other].info()["radix"]),
-                "iters_per_step": plans[other].info()["total_iters"] / info["n_steps"]},
-        "mixed_vs_plain_rel": {"prices": rel_p, "deltas_abs": abs_d, "grid": rel_grid, "spots": 64,
-                               "bound": 1e-6},
+        "config": head.pop("config"),
+        "roofline": head.pop("roofline"),
     }
-    # the same solve on the other candidate transform side: 3L/4 for a power of
-    # two L (when it still covers the kernel's support), else the power of two above
-    alt = 3 * L // 4 if L & (L - 1) == 0 else 1 << (L - 1).bit_length()
-    try:
-        p2 = lp.plan_from_workload(w, sl_order=args.sl_order, precision=args.precision, fft_size=alt)
-    except lp.LpideError:
-        p2 = None
-    if p2 is not None:
-        o2 = torch.empty((n, n), dtype=torch.float64, device="cuda")
-        p2.solve(o2)
-        wall2, _ = timed_solves(p2, o2, args.steps, [])
-        result["other_side"] = {"L": alt, "radix": p2.info()["radix"], "value": n * n * Nt * args.steps / wall2,
-                                "ms_per_step": 1e3 * wall2 / args.steps,
-                                "max_rel_diff": float((o2 - outs[args.precision]).abs().div(
-                                    outs[args.precision].abs().clamp_min(1.0)).max())}
-        del p2, o2
+    result.update(head)
+    # the oracle sample runs on the host while the GPU extras run
+    child = cpu_baseline_start(args.workload) if rank == 0 and not args.no_cpu_baseline else None
     if not args.no_extras:
-        del plans, outs, plan
-        torch.cuda.empty_cache()
-        result["conv_roofline_2048"] = large_conv_roofline(lp, "nig2048_m")
-        result["large_2048"] = large_solve(lp, "nig2048_m")
-        result["adjoint"] = adjoint_measure(lp)
-        result["batched"] = batch_measure(lp)
+        fv = measure_workload(lp, "fv512", args.steps, args.warmup,
+                              traffic_json=os.path.join(ROOT, "profiles", "pmc_fv512.json"), other_side=True)
+        fv["vs_oracle"] = fv512_vs_oracle(lp)
+        result["fv512"] = fv
         result["paper_table3"] = table3_check(lp)
-    if rank == 0 and not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        result["adjoint"] = adjoint_measure(lp)
+        result["batched"] = batch_measure(lp, count=args.batch_count)
+    if child is not None:
+        result["cpu_baseline"] = cpu_baseline_finish(child)
     if rank == 0:
         print(json.dumps(result), flush=True)
 
