@@ -890,8 +890,8 @@ int adj_prepare(Plan* p, int C) {
         (rc = dalloc_into(al, nullptr, &a->segE, N * std::max<size_t>(1, Cs))) || (rc = dalloc_into(al, nullptr, &a->lam, N)) ||
         (rc = dalloc_into(al, nullptr, &a->mu, N)) || (rc = dalloc_into(al, nullptr, &a->ybar, N)) ||
         (rc = dalloc_into(al, nullptr, &a->dummy, N)) || (rc = dalloc_into(al, nullptr, &a->acc, (size_t)n * 8)) ||
-        (rc = dalloc_into(al, nullptr, &a->corr, N)) || (rc = dalloc_into(al, nullptr, &a->corr2, N)) ||
-            (rc = dalloc_into(al, nullptr, &a->corr3, N)) ||
+        (rc = dalloc_into(al, nullptr, &a->corr[0], N)) || (rc = dalloc_into(al, nullptr, &a->corr[1], N)) ||
+            (rc = dalloc_into(al, nullptr, &a->corr[2], N)) || (rc = dalloc_into(al, nullptr, &a->corr[3], N)) ||
         (rc = dalloc_into(al, nullptr, &a->ctl, 1)) || (rc = dalloc_into(al, nullptr, &a->counts, p->n_steps)) ||
         (rc = dalloc_into(al, nullptr, &a->incs, p->n_steps)) || (rc = dalloc_into(al, nullptr, &a->A, 1)))
         return rc;

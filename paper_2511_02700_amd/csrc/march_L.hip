@@ -222,32 +222,26 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     const dim3 gr(c.xrows, 1);
     hipLaunchKernelGGL(ks_adj_begin, dim3(1), dim3(64), 0, c.stream, c.A, s);
     const double cth = sd.dt * sd.theta;
-    const double* cp1 = nullptr;
-    const double* cp2 = nullptr;
-    const double* cp3 = nullptr;
-    double w1 = 0.0, w2 = 0.0, w3 = 0.0;
-    if (a->have_corr >= 1 && a->corr_c > 0.0) {
-        // the correction lam - Ybar = dt theta A^T lam, rescaled to this step's
-        // dt theta and extrapolated over the previous steps of the same kind:
-        // kept, linear (2, -1) or quadratic (3, -3, 1)
-        const double ratio = cth / a->corr_c;
-        cp1 = a->corr;
-        w1 = ratio;
-        if (a->have_corr >= 2 && a->corr_c2 == a->corr_c) {
-            cp2 = a->corr2;
-            w1 = 2.0 * ratio;
-            w2 = -ratio;
-            if (a->have_corr >= 3 && a->corr_c3 == a->corr_c) {
-                cp3 = a->corr3;
-                w1 = 3.0 * ratio;
-                w2 = -3.0 * ratio;
-                w3 = ratio;
-            }
-        }
+    // the correction lam - Ybar = dt theta A^T lam of the previous reverse
+    // steps, rescaled to this step's dt theta and extrapolated over the run of
+    // previous steps of the same kind (up to four: kept, linear, quadratic,
+    // cubic, as the forward march extrapolates its start values)
+    static constexpr double kExtrap[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
+    int run = 0;
+    if (a->have_corr >= 1 && a->corr_c[0] > 0.0) {
+        run = 1;
+        while (run < a->have_corr && a->corr_c[run] == a->corr_c[0]) ++run;
+    }
+    const double* cp[4] = {nullptr, nullptr, nullptr, nullptr};
+    double cw[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < run; ++q) {
+        cp[q] = a->corr[q];
+        cw[q] = kExtrap[run - 1][q] * (cth / a->corr_c[0]);
     }
     with_E<L>(c.E_rinv, [&](auto e) {
         constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_adj_start<L, E>), gr, dim3(L / E), 0, c.stream, c.A, cp1, w1, cp2, w2, cp3, w3);
+        hipLaunchKernelGGL((ks_adj_start<L, E>), gr, dim3(L / E), 0, c.stream, c.A, cp[0], cw[0], cp[1], cw[1], cp[2],
+                           cw[2], cp[3], cw[3]);
     });
     int k = *kpred;
     for (int q = 1; q <= k; ++q) launch_adj_iteration<L>(c, q);
@@ -283,16 +277,16 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     *kpred = std::max(1, std::min(p->opts.max_iter, used));
     const int sb = int(std::min<size_t>(1024, (N + 255) / 256));
     {
-        double* oldest = a->corr3;
-        a->corr3 = a->corr2;
-        a->corr2 = a->corr;
-        a->corr = oldest;
-        a->corr_c3 = a->corr_c2;
-        a->corr_c2 = a->corr_c;
+        double* oldest = a->corr[3];
+        for (int q = 3; q > 0; --q) {
+            a->corr[q] = a->corr[q - 1];
+            a->corr_c[q] = a->corr_c[q - 1];
+        }
+        a->corr[0] = oldest;
     }
-    hipLaunchKernelGGL(ks_adj_corr, dim3(sb), dim3(256), 0, c.stream, c.A, a->corr);
-    a->have_corr = std::min(3, a->have_corr + 1);
-    a->corr_c = cth;
+    hipLaunchKernelGGL(ks_adj_corr, dim3(sb), dim3(256), 0, c.stream, c.A, a->corr[0]);
+    a->have_corr = std::min(4, a->have_corr + 1);
+    a->corr_c[0] = cth;
     // mu = (T^SL)^T lam (its row transform also into XC for the spectral
     // gradient term when theta < 1), then the cotangent of V^s
     const double c1 = sd.dt * sd.theta, c2 = sd.dt * (1.0 - sd.theta);

@@ -174,9 +174,9 @@ struct Adjoint {
     double* seg = nullptr;          // C + 1 states of the segment being reversed
     double* segE = nullptr;         // C explicit parts of that segment
     double *lam = nullptr, *mu = nullptr, *ybar = nullptr, *dummy = nullptr;
-    double *corr = nullptr, *corr2 = nullptr, *corr3 = nullptr;
-    int have_corr = 0;               // corr, corr2, corr3 hold lam - Ybar of the last three reverse steps (newest first)
-    double corr_c = 0.0, corr_c2 = 0.0, corr_c3 = 0.0;   // dt theta of those steps
+    double* corr[4] = {};            // lam - Ybar of the last reverse steps, newest first
+    double corr_c[4] = {};           // dt theta of those steps
+    int have_corr = 0;               // how many of corr[] are set
     bool xb_is_v = false;            // XD holds the row transform of V^{s+1} from the previous reverse step
     double2 *XA = nullptr, *XB = nullptr, *XC = nullptr, *XD = nullptr;
     double2* S = nullptr;           // (L/2+1) x L spectral accumulator

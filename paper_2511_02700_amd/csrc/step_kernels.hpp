@@ -705,8 +705,21 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
     double x[LINE_MM];
     {
         const double* Rr = a.R + (size_t)(r == 0 ? ra : rb) * n + s;
+        if (((n | m) & 1) == 0) {
+            // 16-byte loads: the chunk starts at an even element of a row of
+            // even length, so every pair is aligned (half the load
+            // instructions and addresses of element-wise reads)
+            const double2* R2 = reinterpret_cast<const double2*>(Rr);
 #pragma unroll
-        for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? Rr[q] : 0.0;
+            for (int q = 0; q < LINE_MM / 2; ++q) {
+                const double2 v = 2 * q < cnt ? R2[q] : make_double2(0.0, 0.0);
+                x[2 * q] = v.x;
+                x[2 * q + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? Rr[q] : 0.0;
+        }
     }
     __syncthreads();                      // staged factors visible
     if constexpr (PF) chunk_solve(x, s, cnt, r, ch, PR, 1, fac, fac + L, fac + 2 * L, lds);
@@ -873,16 +886,17 @@ static __global__ void ks_adj_begin(const MarchArgs* __restrict__ A, int s) {
     }
 }
 
-// Starting value lam^0 = Ybar + w1 c1 + w2 c2 + w3 c3 and its row transform,
-// where c1, c2, c3 = lam - Ybar of the previous reverse steps, newest first
-// (lam - Ybar = dt theta A^T lam): the correction extrapolated quadratically
-// (3, -3, 1), linearly (2, -1) or kept (1), rescaled by the ratio of the
-// steps' dt theta; c1, c2, c3 may be null.
+// Starting value lam^0 = Ybar + w1 c1 + w2 c2 + w3 c3 + w4 c4 and its row
+// transform, where c1..c4 = lam - Ybar of the previous reverse steps, newest
+// first (lam - Ybar = dt theta A^T lam), weighted by the host: the correction
+// extrapolated over the previous steps of the same kind and rescaled to this
+// step's dt theta; unused c are null.
 template <int L, int E>
 __global__ __launch_bounds__(L / E) void ks_adj_start(const MarchArgs* __restrict__ A,
                                                      const double* __restrict__ c1, double w1,
                                                      const double* __restrict__ c2, double w2,
-                                                     const double* __restrict__ c3, double w3) {
+                                                     const double* __restrict__ c3, double w3,
+                                                     const double* __restrict__ c4, double w4) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0)) return;
     constexpr int T = L / E;
@@ -902,10 +916,12 @@ __global__ __launch_bounds__(L / E) void ks_adj_start(const MarchArgs* __restric
         double va = 0.0, vb = 0.0;
         if (j < n) {
             const size_t oa = (size_t)ra * n + j, ob = (size_t)rb * n + j;
-            va = a.W[oa] + (c1 ? w1 * c1[oa] : 0.0) + (c2 ? w2 * c2[oa] : 0.0) + (c3 ? w3 * c3[oa] : 0.0);
+            va = a.W[oa] + (c1 ? w1 * c1[oa] : 0.0) + (c2 ? w2 * c2[oa] : 0.0) + (c3 ? w3 * c3[oa] : 0.0) +
+                 (c4 ? w4 * c4[oa] : 0.0);
             lam[oa] = va;
             if (hasb) {
-                vb = a.W[ob] + (c1 ? w1 * c1[ob] : 0.0) + (c2 ? w2 * c2[ob] : 0.0) + (c3 ? w3 * c3[ob] : 0.0);
+                vb = a.W[ob] + (c1 ? w1 * c1[ob] : 0.0) + (c2 ? w2 * c2[ob] : 0.0) + (c3 ? w3 * c3[ob] : 0.0) +
+                     (c4 ? w4 * c4[ob] : 0.0);
                 lam[ob] = vb;
             }
         }

@@ -1,0 +1,128 @@
+// CPU check of the workgroup FFT of paper_2511_02700_amd/csrc/fft.hpp (the
+// unchanged header, compiled for the host against tests/cpu/emu): every
+// transform side and elements-per-thread choice the library instantiates, FP64
+// and FP32 data, forward and inverse, one OS thread per GPU thread with a
+// barrier for __syncthreads, the LDS exchange buffer and the twiddle tables in
+// exactly sized heap arrays (so AddressSanitizer reports any access outside
+// them).  Each transform is compared with the DFT evaluated in long double.
+// Prints one line per case and "ALL OK" at the end; exits non-zero on a
+// mismatch.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <memory>
+#include <random>
+#include <thread>
+#include <vector>
+
+#include "fft.hpp"
+
+using namespace lpide;
+
+template <typename C>
+struct Real;
+template <>
+struct Real<double2> { using T = double; };
+template <>
+struct Real<float2> { using T = float; };
+
+// one workgroup: T threads transform x (length L, canonical layout in and out)
+template <int L, int E, bool INV, typename C>
+void run_block(const std::vector<double2>& tw_full, std::vector<C>& x) {
+    constexpr int T = L / E;
+    auto lds = std::make_unique<C[]>(lds_slots(L));
+    auto tab = std::make_unique<double2[]>(tw_slots<L, E>());
+    std::barrier<> bar(T);
+    emu_block_barrier = &bar;
+    std::vector<std::thread> th;
+    th.reserve(T);
+    for (int t = 0; t < T; ++t) {
+        th.emplace_back([&, t] {
+            threadIdx.x = unsigned(t);
+            load_twiddles<L, E>(tw_full.data(), tab.get());
+            C reg[E];
+            for (int e = 0; e < E; ++e) reg[e] = x[t + e * T];
+            bar.arrive_and_wait();       // every thread has read x before anyone writes it
+            fft_block<L, E, INV>(reg, lds.get(), tab.get());
+            for (int e = 0; e < E; ++e) x[t + e * T] = reg[e];
+        });
+    }
+    for (auto& h : th) h.join();
+    emu_block_barrier = nullptr;
+}
+
+template <int L, int E, typename C>
+bool check(std::mt19937_64& rng, double tol) {
+    using R = typename Real<C>::T;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<double2> tw(L);
+    for (int q = 0; q < L; ++q) {
+        const long double a = -2.0L * pi * q / L;
+        tw[q] = make_double2(double(cosl(a)), double(sinl(a)));
+    }
+    std::vector<long double> cs(L), sn(L);       // exp(-2 pi i q / L) in long double
+    for (int q = 0; q < L; ++q) {
+        cs[q] = cosl(2.0L * pi * q / L);
+        sn[q] = -sinl(2.0L * pi * q / L);
+    }
+    std::normal_distribution<double> nd;
+    bool ok = true;
+    for (int inv = 0; inv < 2; ++inv) {
+        std::vector<C> x(L);
+        for (auto& v : x) v = C{R(nd(rng)), R(nd(rng))};
+        const std::vector<C> x0 = x;
+        if (inv) run_block<L, E, true>(tw, x);
+        else run_block<L, E, false>(tw, x);
+        long double err = 0.0L, scale = 0.0L;
+        for (int k = 0; k < L; ++k) {
+            long double re = 0.0L, im = 0.0L;
+            for (int j = 0; j < L; ++j) {
+                const int q = int((long long)j * k % L);
+                const long double c = cs[q], s = inv ? -sn[q] : sn[q];
+                re += x0[j].x * c - x0[j].y * s;
+                im += x0[j].x * s + x0[j].y * c;
+            }
+            err = std::max(err, fabsl(re - x[k].x) + fabsl(im - x[k].y));
+            scale = std::max(scale, fabsl(re) + fabsl(im));
+        }
+        const double rel = double(err / scale);
+        const bool good = rel < tol;
+        std::printf("L=%4d E=%2d %s %s max rel err %.3e %s\n", L, E, sizeof(R) == 8 ? "fp64" : "fp32",
+                    inv ? "inverse" : "forward", rel, good ? "ok" : "FAIL");
+        ok = ok && good;
+    }
+    return ok;
+}
+
+template <int L, typename C>
+bool sizes(std::mt19937_64& rng, double tol) {
+    bool ok = true;
+    if constexpr (fft_ok(L, 4)) ok = check<L, 4, C>(rng, tol) && ok;
+    if constexpr (fft_ok(L, 8)) ok = check<L, 8, C>(rng, tol) && ok;
+    if constexpr (fft_ok(L, 16)) ok = check<L, 16, C>(rng, tol) && ok;
+    return ok;
+}
+
+template <typename C>
+bool all_sizes(std::mt19937_64& rng, double tol) {
+    bool ok = true;
+    ok = sizes<64, C>(rng, tol) && ok;
+    ok = sizes<128, C>(rng, tol) && ok;
+    ok = sizes<256, C>(rng, tol) && ok;
+    ok = sizes<512, C>(rng, tol) && ok;
+    ok = sizes<768, C>(rng, tol) && ok;
+    ok = sizes<1024, C>(rng, tol) && ok;
+    ok = sizes<1536, C>(rng, tol) && ok;
+    ok = sizes<2048, C>(rng, tol) && ok;
+    ok = sizes<3072, C>(rng, tol) && ok;
+    ok = sizes<4096, C>(rng, tol) && ok;
+    return ok;
+}
+
+int main() {
+    std::mt19937_64 rng(20251102);
+    bool ok = all_sizes<double2>(rng, 1e-14);
+    ok = all_sizes<float2>(rng, 2e-6) && ok;
+    std::printf(ok ? "ALL OK\n" : "MISMATCH\n");
+    return ok ? 0 : 1;
+}

@@ -153,6 +153,33 @@ def test_batched_draw_sample(lp):
         assert _rel(o.cpu().numpy(), p.solve().cpu().numpy()) < 1e-12
 
 
+def test_batched_recipe_16_draws_vs_oracle(lp):
+    """The first 16 draws of the batched workload recipe (n = 128 to 1024 with
+    six at 512 and one at 1024, drawn model, strike and maturity) in one batch
+    with 4-step slots (slots without the exiting kernels from the first main
+    steps on), against the oracle's state after six step-list
+    entries (tests/golden/oracle_batch.npz, written by
+    tests/golden/make_oracle_batch.py, which calls only the oracle), on 64 x 64
+    sampled nodes each: within 1e-10."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_batch.npz")
+    g = np.load(path)
+    count, entries = int(g["count"]), int(g["entries"])
+    draws = workloads.batch_draw(256, seed=3)[:count]
+    assert {512, 1024} <= {d["n"] for d in draws}
+    _note("batched recipe: %d draws, n %s, first %d entries" % (count, sorted({d["n"] for d in draws}), entries))
+    plans = [lp.plan_from_workload(d) for d in draws]
+    batch = lp.Batch(plans, slots=4)
+    outs = batch.solve_steps(entries)
+    worst = 0.0
+    for q, o in enumerate(outs):
+        idx = g["idx_%d" % q]
+        err = _rel(o.cpu().numpy()[np.ix_(idx, idx)], g["V_%d" % q])
+        worst = max(worst, err)
+        assert err < 1e-10, (q, draws[q]["n"], err)
+    _note("batched recipe vs oracle: worst sampled grid %.2e" % worst)
+
+
 def test_plan_batch_one_call(lp):
     """lpide_plan_batch builds the plans and their batch from arrays in one call
     (the batch owns the plans); lpide_solve_batch marches them.  The results
