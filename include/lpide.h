@@ -434,6 +434,125 @@ int lpide_batch_info(void* batch, int32_t* n_groups, lpide_group_info* groups, i
 /* Thread-local description of the last error on the calling thread. */
 const char* lpide_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * The paper's own price-space discretization (Sec. 3.2, Sec. 3.3 and the
+ * Sec. 4 settings), a second plan type beside the log-moneyness plan above.
+ *
+ * The grid is x_m = phi(xi_max m / N_x), m = 0..N_x, in each price axis:
+ * uniform on [0, x_int], sinh-graded on [x_int, x_max] (Sec. 4), the same on
+ * both axes.  Grids are row-major (N_x+1) x (N_x+1) FP64 arrays
+ * V[m1 * (N_x+1) + m2] at (x_{m1}, x_{m2}).
+ *   - D: three-point differences on the nonuniform grid with the x_i and x_i^2
+ *     factors (Sec. 3.2.1); no derivative terms at x_i = 0, no second
+ *     derivative and a backward first difference at x_max.
+ *   - B_omega = T^out I~ C T^in (Sec. 3.2.2): cubic Lagrange interpolation
+ *     T^in from the x grid to the log-uniform grid y^in (v = 0 outside
+ *     [0, x_max]^2), the correlation C with the weights omega on
+ *     #in x #in points by a zero-padded 2D FFT, the kept #out x #out outputs
+ *     on y^out, and cubic Lagrange interpolation T^out back to the x grid
+ *     (linear extrapolation to the x_i = 0 rows).  h_z = z_max^III / N_z with
+ *     N_z = nz_per_nx N_x, N_y^-, N_y^+ and the least N_y^* that makes #in
+ *     7-smooth as in Sec. 4.
+ *   - Time stepping: the semi-Lagrangian theta-method of Sec. 3.3 with the
+ *     departure points x e^{kappa_omega^(i) dt} (cubic Lagrange, stencils of
+ *     the four nearest nodes, extrapolating beyond x_max), four damped
+ *     quarter steps, extrapolated start values and the fixed-point
+ *     iteration on B of Algorithm 1.  The implicit systems are solved by the
+ *     same preconditioned iteration as the log-moneyness plan (tridiagonal
+ *     line solves in each axis, residual of the full step equation), whose
+ *     fixed point is the step equation's solution.
+ * Pay-offs: LPIDE_PUT_AVG and LPIDE_PUT_1, cell averaged on the cells
+ * [x_{m-1/2}, x_{m+1/2}]^2 that meet the kink when cell_avg = 1.  Options
+ * used: tol, max_iter, damping, device, stream, fft_size (0: the smallest
+ * supported transform side >= #in among 64 ... 4096; otherwise a supported
+ * side >= #in) and all_correlations (0: the explicit part of a step after one
+ * with theta > 0 from that step's implicit equation, as the log plan does;
+ * 1: by the correlation).  precision must be LPIDE_FP64. */
+typedef struct {
+    int32_t N_x;          /* grid intervals per axis, 8 <= N_x <= 4095 */
+    double  x_max;        /* upper end of both price axes */
+    double  x_int;        /* end of the uniform part; 0: 5K/2 (Sec. 4) */
+    double  fraction;     /* F target: c makes the limit fraction of nodes in [0, x_int]
+                             max(fraction, x_int / x_max) (paper: 0.65) */
+    double  c;            /* > 0: the constant of the map phi as given (Sec. 4 prints one
+                             per parameter set); 0: the root of the relation for F */
+    int32_t nz_per_nx;    /* N_z = nz_per_nx N_x (paper: 2) */
+    int32_t m1;           /* z_max^I = m1 h_z (paper: 2) */
+    double  ell_cut;      /* z_max^III level (1e-14 reproduces the printed values) */
+    double  zmax2_frac;   /* z_max^II = h_z ceil(zmax2_frac N_z - 1/2) (paper: sqrt(0.1)) */
+    int32_t gl_nodes;     /* Gauss-Legendre nodes per axis for the R_II cell integrals */
+} lpide_ps_grid;
+
+typedef struct {
+    int32_t N_x, n;                   /* intervals, nodes per axis (N_x + 1) */
+    int32_t N_z, M1, M2;              /* z-grid half size and region bounds */
+    int32_t N_ym, N_yp, N_ystar;      /* N_y^-, N_y^+, N_y^* (Sec. 4) */
+    int32_t n_in, n_out;              /* #in and #out per axis */
+    int32_t n_nz;                     /* y^in nodes inside [0, x_max] (rows of T^in that are not zero) */
+    int32_t L;                        /* side of the zero-padded correlation transform (>= #in) */
+    int32_t N_t, n_steps;             /* time steps, entries of the step list */
+    double  c, x_int, F;              /* grid constant, end of the uniform part, fraction target */
+    double  h_z, z_star, sum_omega;
+    double  kappa[2], r_omega, S[3], a[3];
+    int64_t total_iters;              /* fixed-point iterations of the last march */
+    int32_t max_step_iters;
+    double  last_increment;           /* last stopping-rule value of the last march */
+    int64_t device_bytes;
+} lpide_ps_info;
+
+/* The paper's settings on N_x intervals over [0, x_max]: x_int = 5K/2,
+ * fraction 0.65, c from the relation for F, N_z = 2 N_x, m1 = 2,
+ * ell_cut = 1e-14, zmax2_frac = sqrt(0.1), gl_nodes = 8. */
+void lpide_ps_grid_default(lpide_ps_grid* g, int32_t N_x, double x_max);
+
+/* Host-only discretization of the price-space plan (no device is touched):
+ * fills info (sizes of the grids, c, h_z, z_star, sum_omega, kappa, r_omega,
+ * S, a; L is the automatic transform side, 0 without jumps) and, where not
+ * NULL, x (host, N_x + 1 nodes), v0 (host, (N_x+1)^2 pay-off grid) and omega
+ * (host, (2 N_z)^2 weights, only if omega_len is at least that).  Errors as
+ * lpide_ps_plan_create's validation. */
+int lpide_ps_discretize_host(const lpide_ps_grid* grid, const lpide_levy* levy, const lpide_payoff* payoff,
+                             lpide_ps_info* info, double* x, double* v0, double* omega, int64_t omega_len);
+
+/* Build a price-space plan: the grid, the integral discretization with
+ * h_z = z_max^III / N_z, the y grids and interpolation tables, the
+ * difference operator, the cell-averaged pay-off, the semi-Lagrangian tables
+ * and line factors of every step kind, and on the device the spectrum of the
+ * weights and all workspace.  N_t >= 1 steps of T / N_t (the paper takes
+ * N_t = round(N_x / 2)).  Errors: LPIDE_E_PARAM for invalid settings (as
+ * lpide_plan_create, plus x_max <= x_int, a pay-off other than the two above,
+ * precision other than FP64, #in above the transform side or 4096),
+ * LPIDE_E_OOM, LPIDE_E_HIP.  *out is set only on success. */
+int lpide_ps_plan_create(const lpide_ps_grid* grid, const lpide_levy* levy, const lpide_payoff* payoff,
+                         double theta, int32_t N_t, const lpide_opts* opts, void** out);
+
+/* Release a price-space plan and its device memory.  NULL is accepted. */
+int lpide_ps_plan_destroy(void* plan);
+
+/* Plan quantities and last-march statistics (host). */
+int lpide_ps_plan_info(void* plan, lpide_ps_info* info);
+
+/* The grid nodes x_0 .. x_{N_x} (host array of N_x + 1). */
+int lpide_ps_nodes(void* plan, double* x);
+
+/* The cell-averaged pay-off V^0.  v_out: device, (N_x+1)^2. */
+int lpide_ps_initial(void* plan, double* v_out);
+
+/* One application of B_omega = T^out I~ C T^in.  v, bv: device, (N_x+1)^2,
+ * must not alias.  Enqueued on the plan's stream. */
+int lpide_ps_apply_B(void* plan, const double* v, double* bv);
+
+/* The first `steps` entries of the step list (0 <= steps <= n_steps; the
+ * whole march with steps = n_steps).  v_out: device, (N_x+1)^2.  Errors as
+ * lpide_solve (LPIDE_E_NOCONV, LPIDE_E_NAN).  Synchronises the plan's
+ * stream (the stopping rule is read back between batches of steps). */
+int lpide_ps_solve_steps(void* plan, int32_t steps, double* v_out);
+
+/* Prices at npts spot pairs by tensor-product cubic Lagrange interpolation in
+ * x (stencils of the four nearest nodes): spots[2k], spots[2k+1] = (S1, S2),
+ * price[k].  Device pointers; npts = 0 reads and writes nothing. */
+int lpide_ps_price(void* plan, const double* v, int32_t npts, const double* spots, double* price);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,30 @@ class GroupInfo(C.Structure):
         return out
 
 
+class PsGrid(C.Structure):
+    _fields_ = [("N_x", C.c_int32), ("x_max", C.c_double), ("x_int", C.c_double), ("fraction", C.c_double),
+                ("c", C.c_double), ("nz_per_nx", C.c_int32), ("m1", C.c_int32), ("ell_cut", C.c_double),
+                ("zmax2_frac", C.c_double), ("gl_nodes", C.c_int32)]
+
+
+class PsInfo(C.Structure):
+    _fields_ = [("N_x", C.c_int32), ("n", C.c_int32), ("N_z", C.c_int32), ("M1", C.c_int32), ("M2", C.c_int32),
+                ("N_ym", C.c_int32), ("N_yp", C.c_int32), ("N_ystar", C.c_int32), ("n_in", C.c_int32),
+                ("n_out", C.c_int32), ("n_nz", C.c_int32), ("L", C.c_int32), ("N_t", C.c_int32),
+                ("n_steps", C.c_int32), ("c", C.c_double), ("x_int", C.c_double), ("F", C.c_double),
+                ("h_z", C.c_double), ("z_star", C.c_double), ("sum_omega", C.c_double),
+                ("kappa", C.c_double * 2), ("r_omega", C.c_double), ("S", C.c_double * 3), ("a", C.c_double * 3),
+                ("total_iters", C.c_int64), ("max_step_iters", C.c_int32), ("last_increment", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+    def to_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+
 # exported symbol -> (restype, argtypes)
 SIGNATURES = {
     "lpide_grid_default": (None, [C.POINTER(Grid), C.c_int32, C.c_double, C.c_double]),
@@ -121,6 +145,18 @@ SIGNATURES = {
     "lpide_batch_tune": (C.c_int, [C.c_void_p, C.c_int32]),
     "lpide_batch_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(GroupInfo), C.c_int32]),
     "lpide_last_error": (C.c_char_p, []),
+    "lpide_ps_grid_default": (None, [C.POINTER(PsGrid), C.c_int32, C.c_double]),
+    "lpide_ps_discretize_host": (C.c_int, [C.POINTER(PsGrid), C.POINTER(Levy), C.POINTER(Payoff), C.POINTER(PsInfo),
+                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "lpide_ps_plan_create": (C.c_int, [C.POINTER(PsGrid), C.POINTER(Levy), C.POINTER(Payoff), C.c_double,
+                                       C.c_int32, C.POINTER(Opts), C.POINTER(C.c_void_p)]),
+    "lpide_ps_plan_destroy": (C.c_int, [C.c_void_p]),
+    "lpide_ps_plan_info": (C.c_int, [C.c_void_p, C.POINTER(PsInfo)]),
+    "lpide_ps_nodes": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lpide_ps_initial": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lpide_ps_apply_B": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lpide_ps_solve_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "lpide_ps_price": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
 }
 
 _lib = None

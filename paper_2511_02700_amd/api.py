@@ -7,7 +7,7 @@ import ctypes as C
 import math
 
 from . import _lib
-from ._lib import Grid, Info, Levy, Opts, Payoff, check, lib
+from ._lib import Grid, Info, Levy, Opts, Payoff, PsGrid, PsInfo, check, lib
 
 
 def _torch():
@@ -328,6 +328,118 @@ def solve(grid, levy, payoff, theta=0.5, M=32, **opts):
         return v
     finally:
         plan.close()
+
+
+def make_ps_grid(N_x, x_max, **kw):
+    """Price-space grid settings (lpide_ps_grid); the paper's defaults unless
+    overridden (x_int, fraction, c, nz_per_nx, m1, ell_cut, zmax2_frac, gl_nodes)."""
+    g = PsGrid()
+    lib().lpide_ps_grid_default(C.byref(g), int(N_x), float(x_max))
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+def ps_discretize_host(grid, levy, payoff, want_v0=False, want_omega=False):
+    """Host-side quantities of the price-space plan (no device needed):
+    (info dict, x nodes, V^0 or None, omega or None)."""
+    import numpy as np
+    info = PsInfo()
+    x = np.zeros(grid.N_x + 1)
+    check(lib().lpide_ps_discretize_host(C.byref(grid), C.byref(levy), C.byref(payoff), C.byref(info),
+                                         x.ctypes.data_as(C.c_void_p), None, None, 0))
+    v0 = np.zeros((grid.N_x + 1, grid.N_x + 1)) if want_v0 else None
+    om = np.zeros((2 * info.N_z, 2 * info.N_z)) if want_omega and info.N_z > 0 else None
+    if v0 is not None or om is not None:
+        check(lib().lpide_ps_discretize_host(
+            C.byref(grid), C.byref(levy), C.byref(payoff), C.byref(info), None,
+            v0.ctypes.data_as(C.c_void_p) if v0 is not None else None,
+            om.ctypes.data_as(C.c_void_p) if om is not None else None, om.size if om is not None else 0))
+    return info.to_dict(), x, v0, om
+
+
+class PsPlan:
+    """A price-space plan on one HIP device (see lpide_ps_plan_create)."""
+
+    def __init__(self, grid, levy, payoff, theta=0.5, N_t=None, tol=1e-10, max_iter=128, damping=True, device=0,
+                 stream=None, fft_size=0, all_correlations=False):
+        torch = _torch()
+        o = Opts()
+        lib().lpide_opts_default(C.byref(o))
+        o.tol, o.max_iter, o.damping, o.device = tol, max_iter, 1 if damping else 0, device
+        o.fft_size = fft_size
+        o.all_correlations = 1 if all_correlations else 0
+        if N_t is None:
+            N_t = max(1, int(round(0.5 * grid.N_x)))     # Sec. 4: N_t = round(N_x / 2)
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        o.stream = C.c_void_p(stream.cuda_stream)
+        self.grid, self.levy, self.payoff = grid, levy, payoff
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().lpide_ps_plan_create(C.byref(grid), C.byref(levy), C.byref(payoff), theta, int(N_t),
+                                             C.byref(o), C.byref(h)))
+        self._h = h
+        self.n = grid.N_x + 1
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().lpide_ps_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        i = PsInfo()
+        check(lib().lpide_ps_plan_info(self._h, C.byref(i)))
+        return i.to_dict()
+
+    def nodes(self):
+        import numpy as np
+        x = np.zeros(self.n)
+        check(lib().lpide_ps_nodes(self._h, x.ctypes.data_as(C.c_void_p)))
+        return x
+
+    def _grid_tensor(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+        assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == self.n * self.n
+        return out
+
+    def initial(self, out=None):
+        out = self._grid_tensor(out)
+        check(lib().lpide_ps_initial(self._h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def apply_B(self, v, out=None):
+        torch = _torch()
+        v = v.to(self.device, torch.float64).contiguous()
+        out = self._grid_tensor(out)
+        check(lib().lpide_ps_apply_B(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr())))
+        return out
+
+    def solve_steps(self, steps, out=None):
+        out = self._grid_tensor(out)
+        check(lib().lpide_ps_solve_steps(self._h, int(steps), C.c_void_p(out.data_ptr())))
+        return out
+
+    def solve(self, out=None):
+        return self.solve_steps(self.info()["n_steps"], out)
+
+    def price(self, v, spots):
+        torch = _torch()
+        sp = torch.as_tensor(spots, dtype=torch.float64).reshape(-1, 2).to(self.device).contiguous()
+        out = torch.empty(sp.shape[0], dtype=torch.float64, device=self.device)
+        check(lib().lpide_ps_price(self._h, C.c_void_p(v.data_ptr()), int(sp.shape[0]), C.c_void_p(sp.data_ptr()),
+                                   C.c_void_p(out.data_ptr())))
+        return out
 
 
 class PricesFn:

@@ -4,9 +4,10 @@
 
 Compiles, in parallel, csrc/lpide.hip (plans, groups, batches, the adjoint
 driver and the C ABI of include/lpide.h), csrc/march_L.hip once per transform
-size L (the launch sequences of the march kernels for that size) and
-csrc/host_plan.cpp (host-side discretization) with hipcc, and links them into
-one shared library next to this file.
+size L (the launch sequences of the march kernels for that size),
+csrc/host_plan.cpp (host-side discretization), and the price-space plan
+(csrc/ps.hip, csrc/ps_host.cpp, csrc/ps_L.hip once per size) with hipcc, and
+links them into one shared library next to this file.
 """
 
 import os
@@ -22,8 +23,10 @@ LIB = os.path.join(HERE, "liblpide.so")
 
 SIZES = [64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096]
 # (source, object, extra flags)
-UNITS = ([("lpide.hip", "lpide.o", []), ("host_plan.cpp", "host_plan.o", [])] +
-         [("march_L.hip", "march_L%d.o" % L, ["-DLPIDE_L=%d" % L]) for L in SIZES])
+UNITS = ([("lpide.hip", "lpide.o", []), ("host_plan.cpp", "host_plan.o", []), ("ps.hip", "ps.o", []),
+          ("ps_host.cpp", "ps_host.o", [])] +
+         [("march_L.hip", "march_L%d.o" % L, ["-DLPIDE_L=%d" % L]) for L in SIZES] +
+         [("ps_L.hip", "ps_L%d.o" % L, ["-DLPIDE_L=%d" % L]) for L in SIZES])
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LPIDE_ARCH", "gfx950")

@@ -204,7 +204,7 @@ double z_star(const Nts& p, double cut) {
 // Artificial diffusion S = int over [-M1 h, M1 h]^2 of z z^T l(z) dz (Sec. 3.1):
 // polar coordinates per octant, Gauss-Legendre in the angle, tanh-sinh in the
 // radius (the radial integrand r^3 l(r u) ~ r^(1 - 2 alpha) at the origin).
-static void small_jump_cov(const Nts& p, double half, double S[3]) {
+void small_jump_cov(const Nts& p, double half, double S[3]) {
     std::vector<double> gx, gw;
     gauss_legendre(48, gx, gw);
     // tanh-sinh nodes on [0, 1]: x = 1/(1 + e^{-pi sinh t}), dx = pi cosh t e^{-pi sinh t}/(1+e^{-pi sinh t})^2
@@ -253,6 +253,61 @@ static void small_jump_cov(const Nts& p, double half, double S[3]) {
     S[2] = s22.value();
 }
 
+void integral_weights(const Nts& p, double h, int N_z, int M1, int M2, int ng, std::vector<double>& omega) {
+    const int N = N_z, W2 = 2 * N;
+    omega.assign(size_t(W2) * W2, 0.0);
+    std::vector<double> gx, gw;
+    gauss_legendre(ng, gx, gw);
+    parallel_for(W2, [&](int64_t b, int64_t e) {
+        for (int64_t a = b; a < e; ++a) {
+            int l1 = int(a) - N;
+            double c1 = (l1 + 0.5) * h;
+            for (int bb = 0; bb < W2; ++bb) {
+                int l2 = bb - N;
+                double c2 = (l2 + 0.5) * h;
+                double cn = std::max(std::fabs(l1 + 0.5), std::fabs(l2 + 0.5));
+                double w;
+                if (cn <= M1) {
+                    w = 0.0;                                  // R_I
+                } else if (cn <= M2) {                        // R_II: ||z_l||^-2 int_cell ||z||^2 l
+                    Sum acc;
+                    for (int i = 0; i < ng; ++i) {
+                        double z1 = c1 + 0.5 * h * gx[i];
+                        for (int j = 0; j < ng; ++j) {
+                            double z2 = c2 + 0.5 * h * gx[j];
+                            acc.add(gw[i] * gw[j] * (z1 * z1 + z2 * z2) * density(p, z1, z2));
+                        }
+                    }
+                    w = acc.value() * 0.25 * h * h / (c1 * c1 + c2 * c2);
+                } else {                                      // R_III: midpoint
+                    w = density(p, c1, c2) * h * h;
+                }
+                omega[size_t(a) * W2 + bb] = w;
+            }
+        }
+    });
+}
+
+void drift_and_rate(const std::vector<double>& omega, double h, int N_z, double r, double* sum_omega,
+                    double kappa[2], double* r_omega) {
+    const int N = N_z, W2 = 2 * N;
+    Sum so, k1, k2;
+    for (int a = 0; a < W2; ++a) {
+        double e1 = std::expm1((a - N + 0.5) * h);
+        for (int bb = 0; bb < W2; ++bb) {
+            double w = omega[size_t(a) * W2 + bb];
+            double e2 = std::expm1((bb - N + 0.5) * h);
+            so.add(w);
+            k1.add(w * e1);
+            k2.add(w * e2);
+        }
+    }
+    *sum_omega = so.value();
+    kappa[0] = r - k1.value();
+    kappa[1] = r - k2.value();
+    *r_omega = r + *sum_omega;
+}
+
 bool build_host_plan(const lpide_grid& g, const lpide_levy& lv, HostPlan& hp, std::string& err) {
     hp = HostPlan();
     if (g.n < 8 || g.n > 4096) { err = "n must lie in [8, 4096]"; return false; }
@@ -293,56 +348,9 @@ bool build_host_plan(const lpide_grid& g, const lpide_levy& lv, HostPlan& hp, st
         hp.N_z = g.nz_fixed > 0 ? g.nz_fixed : int(std::ceil(hp.z_star / h));
         hp.M2 = int(std::ceil(g.zmax2_frac * hp.N_z - 0.5));
         if (hp.N_z < 1) hp.N_z = 1;
-        const int N = hp.N_z, W2 = 2 * N;
-        hp.omega.assign(size_t(W2) * W2, 0.0);
-        std::vector<double> gx, gw;
-        gauss_legendre(g.gl_nodes, gx, gw);
-        const Nts& p = hp.nts;
-        const int M1 = hp.M1, M2 = hp.M2, ng = g.gl_nodes;
-        parallel_for(W2, [&](int64_t b, int64_t e) {
-            for (int64_t a = b; a < e; ++a) {
-                int l1 = int(a) - N;
-                double c1 = (l1 + 0.5) * h;
-                for (int bb = 0; bb < W2; ++bb) {
-                    int l2 = bb - N;
-                    double c2 = (l2 + 0.5) * h;
-                    double cn = std::max(std::fabs(l1 + 0.5), std::fabs(l2 + 0.5));
-                    double w;
-                    if (cn <= M1) {
-                        w = 0.0;                                  // R_I
-                    } else if (cn <= M2) {                        // R_II: ||z_l||^-2 int_cell ||z||^2 l
-                        Sum acc;
-                        for (int i = 0; i < ng; ++i) {
-                            double z1 = c1 + 0.5 * h * gx[i];
-                            for (int j = 0; j < ng; ++j) {
-                                double z2 = c2 + 0.5 * h * gx[j];
-                                acc.add(gw[i] * gw[j] * (z1 * z1 + z2 * z2) * density(p, z1, z2));
-                            }
-                        }
-                        w = acc.value() * 0.25 * h * h / (c1 * c1 + c2 * c2);
-                    } else {                                      // R_III: midpoint
-                        w = density(p, c1, c2) * h * h;
-                    }
-                    hp.omega[size_t(a) * W2 + bb] = w;
-                }
-            }
-        });
-        small_jump_cov(p, M1 * h, hp.S);
-        Sum so, k1, k2;
-        for (int a = 0; a < W2; ++a) {
-            double e1 = std::expm1((a - N + 0.5) * h);
-            for (int bb = 0; bb < W2; ++bb) {
-                double w = hp.omega[size_t(a) * W2 + bb];
-                double e2 = std::expm1((bb - N + 0.5) * h);
-                so.add(w);
-                k1.add(w * e1);
-                k2.add(w * e2);
-            }
-        }
-        hp.sum_omega = so.value();
-        hp.kappa[0] = lv.r - k1.value();
-        hp.kappa[1] = lv.r - k2.value();
-        hp.r_omega = lv.r + hp.sum_omega;
+        integral_weights(hp.nts, h, hp.N_z, hp.M1, hp.M2, g.gl_nodes, hp.omega);
+        small_jump_cov(hp.nts, hp.M1 * h, hp.S);
+        drift_and_rate(hp.omega, h, hp.N_z, lv.r, &hp.sum_omega, hp.kappa, &hp.r_omega);
     } else {
         hp.kappa[0] = hp.kappa[1] = lv.r;
         hp.r_omega = lv.r;
@@ -510,8 +518,6 @@ bool initial_values(const HostPlan& hp, const lpide_payoff& pay, std::vector<dou
     return true;
 }
 
-namespace {
-
 // Thomas factors of the tridiagonal matrix with rows (sub[j], dia[j], up[j]).
 void thomas_factors(const std::vector<double>& sub, const std::vector<double>& dia, const std::vector<double>& up,
                     std::vector<double>& fl, std::vector<double>& bu, std::vector<double>& bc) {
@@ -534,6 +540,8 @@ void thomas_factors(const std::vector<double>& sub, const std::vector<double>& d
         bc[j] = -up[j] / d[j];
     }
 }
+
+namespace {
 
 // Rows of T = I - c A with A = 1/2 aii [(v+ - 2v + v-)/h^2 - (v+ - v-)/(2h)] - r_omega/2 v
 // on interior rows and A = -r_omega/2 v on the two boundary rows.

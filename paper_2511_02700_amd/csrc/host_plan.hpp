@@ -51,6 +51,23 @@ double log_density(const Nts& p, double z1, double z2);
 // z_max^III before rounding: largest |z|_inf on {l = cut} (Sec. 4 settings).
 double z_star(const Nts& p, double cut);
 
+// Weights omega_l of the z-cells l in [-N_z, N_z)^2 of width h (Sec. 3.1): zero on
+// R_I (|l + 1/2|_inf <= M1), the ||z||^2-weighted cell integral over ||z_l||^2 on
+// R_II (<= M2, ng x ng Gauss-Legendre), the midpoint rule on R_III.
+void integral_weights(const Nts& p, double h, int N_z, int M1, int M2, int ng, std::vector<double>& omega);
+
+// Artificial diffusion S = integral over [-half, half]^2 of z z^T l(z) dz (Sec. 3.1).
+void small_jump_cov(const Nts& p, double half, double S[3]);
+
+// sum omega, kappa_omega^(i) = r - sum omega_l (e^{z_l^(i)} - 1) and r_omega = r + sum omega (Sec. 3.1).
+void drift_and_rate(const std::vector<double>& omega, double h, int N_z, double r, double* sum_omega,
+                    double kappa[2], double* r_omega);
+
+// Thomas factors of the tridiagonal matrix with rows (sub[j], dia[j], up[j]):
+// forward multipliers fl, backward scales bu and couplings bc.
+void thomas_factors(const std::vector<double>& sub, const std::vector<double>& dia, const std::vector<double>& up,
+                    std::vector<double>& fl, std::vector<double>& bu, std::vector<double>& bc);
+
 // Builds the discretization (grid + integral part + folded kernel); no device work.
 bool build_host_plan(const lpide_grid& g, const lpide_levy& lv, HostPlan& hp, std::string& err);
 

@@ -1,0 +1,487 @@
+// Device kernels of the price-space march (Sec. 3.2, Sec. 3.3, Sec. 4
+// settings; gfx950).  Grids are row-major n x n, V[i * n + j] at (x_i, x_j).
+//
+// B_omega v = T^out I~ C T^in v is four passes:
+//   tin2     : U = v (T^in)^T, the axis-2 interpolation to the y^in nodes
+//              inside [0, x_max] (n x n_nz; the rows of T^in beyond x_max are
+//              zero, so those nodes are the zero padding of the transform);
+//   rows_fwd : per pair of y^in rows, the axis-1 interpolation (four rows of
+//              U), one complex length-L FFT, the two half spectra stored
+//              transposed, X[k2 * ldx + i];
+//   cols     : per column k2: FFT over i, times the stored spectrum
+//              conj(FFT(omega placed at j mod L)) / L^2, inverse FFT, the
+//              first n_out entries kept (the rows I~ keeps);
+//   rows_inv : per pair of y^out rows: inverse FFT and the axis-2 T^out
+//              gather from LDS, Z = (C T^in v on y^out x y^out) (T^out)^T,
+//              n_out x n.
+// The axis-1 T^out gather, B v = T^out Z, is taken inside the kernel that
+// uses it (the residual, the explicit part, the stand-alone product).
+//
+// One fixed-point iteration of a step (c = dt theta) is
+//   tin2, rows_fwd, cols, rows_inv on Y (B Y),
+//   resid_rows: R = W - (I - c (D + B - r_omega)) Y on each grid row, then
+//               the axis-2 solve Q = T_2^{-1} R,
+//   line_cols : the axis-1 solve delta = T_1^{-1} Q, Y += delta and the
+//               stopping-rule maximum max |delta| / max(1, |Y|),
+// with T_1 = I - c (a_11 x_1^2 D2_1 / 2 - r_omega), T_2 = I - c a_22 x_2^2 D2_2 / 2
+// tridiagonal.  Its fixed point solves the step equation
+// (I - c (D + B - r_omega)) Y = W exactly.
+// Every kernel of iteration k returns at once when iteration k - 1 met the
+// tolerance or the control block's failure flag is set.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft.hpp"
+#include "kernels.hpp"
+#include "linesolve.hpp"
+
+namespace lpide {
+namespace ps {
+
+constexpr int PS_MAXK = 128;   // iterations per step the control block can record
+
+// Control block of a price-space march.
+struct PsCtl {
+    unsigned long long err[PS_MAXK + 2];   // err[k]: stopping-rule value of iteration k (FP64 bits); 0 = unset
+    unsigned long long last;               // stopping-rule value of the last converged step
+    int fail;                              // 1: the enqueued iterations of a step did not meet tol; 2: NaN
+    int pad;
+};
+
+// Spatial operator tables (device pointers) and the coefficients of D.
+struct PsOps {
+    int n, n_nz, n_out, ldx;
+    const int* tin_s;        // n_nz rows of T^in: stencil start and 4 weights
+    const double* tin_w;
+    const int* tout_s;       // n rows of T^out (from the n_out nodes of y^out)
+    const double* tout_w;
+    const double* A1;        // per node m: x_m d1 (3 coefficients at m-1, m, m+1)
+    const double* A2;        // per node m: x_m^2 d2 / 2
+    double a11, a12, a22, r_omega;
+};
+
+// One step kind: c = dt theta and the Thomas factors of T_1 and T_2.
+struct PsStepK {
+    double c;
+    const double *fl1, *bu1, *bc1, *fl2, *bu2, *bc2;
+};
+
+__device__ __forceinline__ double ps_bits(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+__device__ __forceinline__ bool ps_halted(const PsCtl* c, int k, double tol) {
+    if (c == nullptr) return false;
+    if (c->fail) return true;
+    return k > 1 && ps_bits(c->err[k - 1]) < tol;
+}
+
+// D Y at (i, j): a11 x_i^2 d2_i / 2 + a22 x_j^2 d2_j / 2 + a12 (x_i d1_i)(x_j d1_j).
+// Indices outside the grid carry zero coefficients (clamped reads).
+__device__ __forceinline__ double ps_DY(const double* __restrict__ Y, const PsOps& o, int i, int j) {
+    const int n = o.n;
+    const int im = i > 0 ? i - 1 : 0, ip = i < n - 1 ? i + 1 : n - 1;
+    const int jm = j > 0 ? j - 1 : 0, jp = j < n - 1 ? j + 1 : n - 1;
+    const double* a1i = o.A1 + 3 * i;
+    const double* a2i = o.A2 + 3 * i;
+    const double* a1j = o.A1 + 3 * j;
+    const double* a2j = o.A2 + 3 * j;
+    const double* r0 = Y + (size_t)im * n;
+    const double* r1 = Y + (size_t)i * n;
+    const double* r2 = Y + (size_t)ip * n;
+    const double yc = r1[j];
+    double d = o.a11 * (a2i[0] * r0[j] + a2i[1] * yc + a2i[2] * r2[j]) +
+               o.a22 * (a2j[0] * r1[jm] + a2j[1] * yc + a2j[2] * r1[jp]);
+    if (o.a12 != 0.0) {
+        const double g0 = a1j[0] * r0[jm] + a1j[1] * r0[j] + a1j[2] * r0[jp];
+        const double g1 = a1j[0] * r1[jm] + a1j[1] * yc + a1j[2] * r1[jp];
+        const double g2 = a1j[0] * r2[jm] + a1j[1] * r2[j] + a1j[2] * r2[jp];
+        d += o.a12 * (a1i[0] * g0 + a1i[1] * g1 + a1i[2] * g2);
+    }
+    return d;
+}
+
+// (B Y)(i, j) = sum_t T^out_{i, s_i + t} Z[s_i + t][j].
+__device__ __forceinline__ double ps_BY(const double* __restrict__ Z, const PsOps& o, int i, int j) {
+    const int s = o.tout_s[i];
+    const double* w = o.tout_w + 4 * i;
+    const double* z = Z + (size_t)s * o.n + j;
+    return w[0] * z[0] + w[1] * z[o.n] + w[2] * z[2 * o.n] + w[3] * z[3 * o.n];
+}
+
+// U[row][q] = sum_t T^in_{q, s_q + t} Y[row][s_q + t]; grid (ceil(n_nz / 256), n).
+static __global__ __launch_bounds__(256) void ps_tin2(const double* __restrict__ Y, double* __restrict__ U, PsOps o,
+                                                      const PsCtl* ctl, int k, double tol) {
+    if (ps_halted(ctl, k, tol)) return;
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= o.n_nz) return;
+    const int row = blockIdx.y;
+    const int s = o.tin_s[q];
+    const double* w = o.tin_w + 4 * q;
+    const double* y = Y + (size_t)row * o.n + s;
+    U[(size_t)row * o.n_nz + q] = w[0] * y[0] + w[1] * y[1] + w[2] * y[2] + w[3] * y[3];
+}
+
+// Rows (2p, 2p+1) of v^in = T^in U (four rows of U each, zero beyond n_nz
+// columns), one complex FFT, the half spectra into X[k2 * ldx + row].
+template <int L>
+__global__ __launch_bounds__(L / conv_e(L)) void ps_rows_fwd(const double* __restrict__ U, double2* __restrict__ X,
+                                                             PsOps o, const double2* __restrict__ tw,
+                                                             const PsCtl* ctl, int k, double tol) {
+    if (ps_halted(ctl, k, tol)) return;
+    constexpr int KE = conv_e(L), T = L / KE;
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L, KE>()];
+    load_twiddles<L, KE>(tw, tw4);
+    const int m = o.n_nz, np = (m + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, np);
+    const int ra = 2 * p, rb = 2 * p + 1;
+    const bool hasb = rb < m;
+    const int sa = o.tin_s[ra], sb = o.tin_s[hasb ? rb : ra];
+    double wa[4], wb[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        wa[t] = o.tin_w[4 * ra + t];
+        wb[t] = hasb ? o.tin_w[4 * rb + t] : 0.0;
+    }
+    const double* ua = U + (size_t)sa * m;
+    const double* ub = U + (size_t)sb * m;
+    const int tid = threadIdx.x;
+    double2 reg[KE];
+#pragma unroll
+    for (int e = 0; e < KE; ++e) {
+        const int idx = tid + e * T;
+        double a = 0.0, b = 0.0;
+        if (idx < m) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                a += wa[t] * ua[(size_t)t * m + idx];
+                b += wb[t] * ub[(size_t)t * m + idx];
+            }
+        }
+        reg[e] = make_double2(a, b);
+    }
+    fft_block<L, KE, false>(reg, lds, tw4);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < KE; ++e) lds[tid + e * T] = reg[e];
+    __syncthreads();
+    // Z = FFT(a + i b): A_k = (Z_k + conj Z_{L-k}) / 2, B_k = (Z_k - conj Z_{L-k}) / (2i)
+    for (int kk = tid; kk <= L / 2; kk += T) {
+        const double2 z = lds[kk], w = lds[kk == 0 ? 0 : L - kk];
+        double2* xk = X + (size_t)kk * o.ldx;
+        xk[ra] = make_double2(0.5 * (z.x + w.x), 0.5 * (z.y - w.y));
+        if (hasb) xk[rb] = make_double2(0.5 * (z.y + w.y), -0.5 * (z.x - w.x));
+    }
+}
+
+// Column k2: FFT over the n_nz rows (zero padded to L), times the spectrum,
+// inverse FFT, the first n_out entries back into X.
+template <int L>
+__global__ __launch_bounds__(L / conv_e(L)) void ps_cols(double2* __restrict__ X, const double2* __restrict__ spec,
+                                                         PsOps o, const double2* __restrict__ tw, const PsCtl* ctl,
+                                                         int k, double tol) {
+    if (ps_halted(ctl, k, tol)) return;
+    constexpr int KE = conv_e(L), T = L / KE;
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L, KE>()];
+    load_twiddles<L, KE>(tw, tw4);
+    const int col = blockIdx.x;
+    const int tid = threadIdx.x;
+    double2* xc = X + (size_t)col * o.ldx;
+    double2 reg[KE];
+#pragma unroll
+    for (int e = 0; e < KE; ++e) {
+        const int idx = tid + e * T;
+        reg[e] = idx < o.n_nz ? xc[idx] : make_double2(0.0, 0.0);
+    }
+    fft_block<L, KE, false>(reg, lds, tw4);
+    const double2* sc = spec + (size_t)col * L;
+#pragma unroll
+    for (int e = 0; e < KE; ++e) reg[e] = cmul(reg[e], sc[tid + e * T]);
+    fft_block<L, KE, true>(reg, lds, tw4);
+#pragma unroll
+    for (int e = 0; e < KE; ++e) {
+        const int idx = tid + e * T;
+        if (idx < o.n_out) xc[idx] = reg[e];
+    }
+}
+
+// y^out rows (2p, 2p+1): Hermitian completion of the two half spectra, inverse
+// FFT, the n_out kept columns staged in LDS, then the axis-2 T^out gather:
+// Z[row][m] = sum_t T^out_{m, s_m + t} row[s_m + t], m < n.
+template <int L>
+__global__ __launch_bounds__(L / conv_e(L)) void ps_rows_inv(const double2* __restrict__ X, double* __restrict__ Z,
+                                                             PsOps o, const double2* __restrict__ tw,
+                                                             const PsCtl* ctl, int k, double tol) {
+    if (ps_halted(ctl, k, tol)) return;
+    constexpr int KE = conv_e(L), T = L / KE;
+    __shared__ double2 lds[lds_slots(L)];
+    __shared__ double2 tw4[tw_slots<L, KE>()];
+    load_twiddles<L, KE>(tw, tw4);
+    const int m = o.n_out, np = (m + 1) >> 1;
+    const int p = xcd_remap(blockIdx.x, np);
+    const int ra = 2 * p, rb = 2 * p + 1;
+    const bool hasb = rb < m;
+    const int tid = threadIdx.x;
+    double2 reg[KE];
+#pragma unroll
+    for (int e = 0; e < KE; ++e) {
+        const int idx = tid + e * T;
+        const bool lo = idx <= L / 2;
+        const int kk = lo ? idx : L - idx;
+        const double2* xk = X + (size_t)kk * o.ldx;
+        const bool real_bin = kk == 0 || kk == L / 2;    // imaginary parts dropped at DC and Nyquist
+        const double2 ta = xk[ra];
+        const double2 tb = hasb ? xk[rb] : make_double2(0.0, 0.0);
+        const double2 ha = make_double2(ta.x, real_bin ? 0.0 : ta.y);
+        const double2 hb = make_double2(tb.x, real_bin ? 0.0 : tb.y);
+        // Z_k = A_k + i B_k, with A_{L-k} = conj A_k, B_{L-k} = conj B_k
+        reg[e] = lo ? make_double2(ha.x - hb.y, ha.y + hb.x) : make_double2(ha.x + hb.y, hb.x - ha.y);
+    }
+    fft_block<L, KE, true>(reg, lds, tw4);
+    __syncthreads();
+    double* rows = reinterpret_cast<double*>(lds);       // row a at [0, L), row b at [L, 2L)
+#pragma unroll
+    for (int e = 0; e < KE; ++e) {
+        const int j = tid + e * T;
+        if (j < m) {
+            rows[j] = reg[e].x;
+            rows[L + j] = reg[e].y;
+        }
+    }
+    __syncthreads();
+    const int n = o.n;
+    for (int q = tid; q < n; q += T) {
+        const int s = o.tout_s[q];
+        const double* w = o.tout_w + 4 * q;
+        Z[(size_t)ra * n + q] = w[0] * rows[s] + w[1] * rows[s + 1] + w[2] * rows[s + 2] + w[3] * rows[s + 3];
+        if (hasb)
+            Z[(size_t)rb * n + q] =
+                w[0] * rows[L + s] + w[1] * rows[L + s + 1] + w[2] * rows[L + s + 2] + w[3] * rows[L + s + 3];
+    }
+}
+
+// Residual of the step equation on grid rows and the axis-2 solve:
+// Q = T_2^{-1} (W - Y + c (D Y + B Y - r_omega Y)).  256 threads: 256 / P rows
+// per block, P chunks per row (P a power of two, n <= LINE_MM P).  Z = nullptr:
+// no jumps (B = 0).
+static __global__ __launch_bounds__(256) void ps_resid_rows(const double* __restrict__ Y,
+                                                            const double* __restrict__ W,
+                                                            const double* __restrict__ Z, double* __restrict__ Q,
+                                                            PsOps o, PsStepK sk, int P, const PsCtl* ctl, int k,
+                                                            double tol) {
+    if (ps_halted(ctl, k, tol)) return;
+    __shared__ double2 wtot[256];
+    const int n = o.n, lpb = 256 / P;
+    const int g = threadIdx.x / P, t = threadIdx.x % P;
+    const int i = blockIdx.x * lpb + g;
+    const int mlen = (n + P - 1) / P;
+    const int s = t * mlen;
+    const int cnt = i < n ? max(0, min(mlen, n - s)) : 0;
+    double x[LINE_MM];
+#pragma unroll
+    for (int q = 0; q < LINE_MM; ++q) {
+        x[q] = 0.0;
+        if (q < cnt) {
+            const int j = s + q;
+            const size_t o_ = (size_t)i * n + j;
+            const double y = Y[o_];
+            const double by = Z ? ps_BY(Z, o, i, j) : 0.0;
+            x[q] = W[o_] - y + sk.c * (ps_DY(Y, o, i, j) + by - o.r_omega * y);
+        }
+    }
+    chunk_solve(x, s, cnt, g, t, P, 1, sk.fl2, sk.bu2, sk.bc2, wtot);
+#pragma unroll
+    for (int q = 0; q < LINE_MM; ++q)
+        if (q < cnt) Q[(size_t)i * n + s + q] = x[q];
+}
+
+// Axis-1 solve of 4 adjacent columns (P chunks each, 4 P threads, P >= 16),
+// the update Y += delta and the block maximum of |delta| / max(1, |Y|) into
+// err[k] (non-negative doubles order like their bit patterns; NaN above inf).
+static __global__ __launch_bounds__(1024) void ps_line_cols(const double* __restrict__ Q, double* __restrict__ Y,
+                                                            PsOps o, PsStepK sk, int P, PsCtl* ctl, int k,
+                                                            double tol) {
+    if (ps_halted(ctl, k, tol)) return;
+    __shared__ double2 wtot[256];
+    __shared__ double wmax[16];
+    const int n = o.n;
+    const int c = threadIdx.x & 3, t = threadIdx.x >> 2;
+    const int col = blockIdx.x * 4 + c;
+    const int mlen = (n + P - 1) / P;
+    const int s = t * mlen;
+    const int cnt = col < n ? max(0, min(mlen, n - s)) : 0;
+    double x[LINE_MM];
+#pragma unroll
+    for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? Q[(size_t)(s + q) * n + col] : 0.0;
+    chunk_solve(x, s, cnt, c, t, P, 4, sk.fl1, sk.bu1, sk.bc1, wtot);
+    double emax = 0.0;
+#pragma unroll
+    for (int q = 0; q < LINE_MM; ++q) {
+        if (q < cnt) {
+            const size_t o_ = (size_t)(s + q) * n + col;
+            const double y = Y[o_] + x[q];
+            Y[o_] = y;
+            const double ev = fabs(x[q]) / fmax(1.0, fabs(y));
+            emax = (ev > emax || ev != ev) ? ev : emax;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double v = __shfl_xor(emax, off, 64);
+        emax = (v > emax || v != v) ? v : emax;
+    }
+    const int nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = emax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = wmax[0];
+        for (int w = 1; w < nw; ++w) b = (wmax[w] > b || wmax[w] != wmax[w]) ? wmax[w] : b;
+        atomicMax(&ctl->err[k], (unsigned long long)__double_as_longlong(b));
+    }
+}
+
+// Explicit part E = V + d (D V + B V - r_omega V), d = dt (1 - theta).
+static __global__ __launch_bounds__(256) void ps_expl(const double* __restrict__ V, const double* __restrict__ Z,
+                                                      double* __restrict__ E, PsOps o, double d,
+                                                      const PsCtl* ctl) {
+    if (ctl && ctl->fail) return;
+    const int n = o.n;
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (size_t)n * n) return;
+    const int i = int(idx / n), j = int(idx % n);
+    const double v = V[idx];
+    const double bv = Z ? ps_BY(Z, o, i, j) : 0.0;
+    E[idx] = v + d * (ps_DY(V, o, i, j) + bv - o.r_omega * v);
+}
+
+// Semi-Lagrangian step and start value of a step.
+struct PsSL {
+    const int *s1, *s2;             // per node: stencil starts of the departure points, axis 1 / axis 2
+    const double *w1, *w2;          // and their 4 weights
+    const double* src;              // E~ = src + rho (src - wp) (wp = nullptr: E~ = src)
+    const double* wp;
+    double rho;
+    double* W;                      // W = (T^SL_1 (x) T^SL_2) E~
+    const double* H[4];             // Y^0 = sum_q coef_q H_q
+    double coef[4];
+    int nh;
+    double* Y;
+};
+
+static __global__ __launch_bounds__(256) void ps_sl(PsOps o, PsSL a, const PsCtl* ctl) {
+    if (ctl->fail) return;
+    const int n = o.n;
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (size_t)n * n) return;
+    const int i = int(idx / n), j = int(idx % n);
+    const int s1 = a.s1[i], s2 = a.s2[j];
+    const double* w1 = a.w1 + 4 * i;
+    const double* w2 = a.w2 + 4 * j;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const size_t rowo = (size_t)(s1 + t) * n + s2;
+        double r = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double e = a.src[rowo + u];
+            if (a.wp) e += a.rho * (e - a.wp[rowo + u]);
+            r += w2[u] * e;
+        }
+        acc += w1[t] * r;
+    }
+    a.W[idx] = acc;
+    double y = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (q < a.nh) y += a.coef[q] * a.H[q][idx];
+    a.Y[idx] = y;
+}
+
+// End of step s after kmax iterations: the first k with err_k < tol becomes
+// the step's count and err is cleared for the next step; without one the
+// failure flag is set (2 if an increment was not finite) and err is kept, so
+// that the host can add iterations.  One thread.
+static __global__ void ps_step_end(PsCtl* ctl, int* counts, int s, int kmax, double tol) {
+    if (ctl->fail) return;
+    int kc = 0;
+    bool nan = false;
+    for (int k = 1; k <= kmax; ++k) {
+        const double e = ps_bits(ctl->err[k]);
+        if (e != e) nan = true;
+        if (kc == 0 && e < tol) kc = k;
+    }
+    if (kc == 0) {
+        ctl->fail = nan ? 2 : 1;
+        counts[s] = 0;
+        return;
+    }
+    counts[s] = kc;
+    ctl->last = ctl->err[kc];
+    for (int k = 0; k < PS_MAXK + 2; ++k) ctl->err[k] = 0ull;
+}
+
+static __global__ void ps_ctl_reset(PsCtl* ctl, int clear_err) {
+    ctl->fail = 0;
+    if (clear_err) {
+        for (int k = 0; k < PS_MAXK + 2; ++k) ctl->err[k] = 0ull;
+        ctl->last = 0ull;
+    }
+}
+
+// Stand-alone product: bv = T^out Z (axis 1).
+static __global__ __launch_bounds__(256) void ps_tout1(const double* __restrict__ Z, double* __restrict__ bv,
+                                                       PsOps o) {
+    const int n = o.n;
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (size_t)n * n) return;
+    bv[idx] = ps_BY(Z, o, int(idx / n), int(idx % n));
+}
+
+static __global__ __launch_bounds__(256) void ps_fill(double* __restrict__ a, size_t cnt, double v) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < cnt) a[i] = v;
+}
+
+// Prices at spot pairs: tensor-product cubic Lagrange on the four nearest
+// nodes of each axis (stencil start clamp(j - 1, 0, n - 4), x_j <= S < x_{j+1}).
+__device__ __forceinline__ int ps_stencil(const double* __restrict__ x, int n, double t, double* w) {
+    int lo = 0, hi = n;                          // first index with x > t
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (x[mid] <= t) lo = mid + 1; else hi = mid;
+    }
+    int j = lo - 1;
+    j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+    int s = j - 1;
+    s = s < 0 ? 0 : (s > n - 4 ? n - 4 : s);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        double v = 1.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (b != a) v *= (t - x[s + b]) / (x[s + a] - x[s + b]);
+        w[a] = v;
+    }
+    return s;
+}
+
+static __global__ void ps_price(const double* __restrict__ V, const double* __restrict__ x, int n, int npts,
+                                const double* __restrict__ spots, double* __restrict__ price) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npts) return;
+    double w1[4], w2[4];
+    const int s1 = ps_stencil(x, n, spots[2 * q], w1);
+    const int s2 = ps_stencil(x, n, spots[2 * q + 1], w2);
+    double acc = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        double r = 0.0;
+        for (int b = 0; b < 4; ++b) r += w2[b] * V[(size_t)(s1 + a) * n + s2 + b];
+        acc += w1[a] * r;
+    }
+    price[q] = acc;
+}
+
+}  // namespace ps
+}  // namespace lpide
