@@ -385,6 +385,54 @@ def table3_check(lp):
     return out
 
 
+def price_space_check(lp):
+    """The paper's own price-space discretization (Sec. 3.2, 3.3, Sec. 4
+    settings) on each Table 1 set at the largest N_x whose #in fits a
+    transform side of 4096, N_t = N_x / 2, fixed-point tol 1e-10: march time
+    (second of two marches), throughput in grid-pt-steps/s ((N_x+1)^2 x
+    step-list entries / time), iterations, and max |price - Table 3| over the
+    nine spots (the paper's N_x = 800, 400 for NIG0)."""
+    import csv
+    import numpy as np
+    import torch
+
+    def rows(name):
+        with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+            return list(csv.DictReader(line for line in f if not line.startswith("#")))
+
+    t1 = {r["name"]: r for r in rows("table1_params.csv")}
+    gold = rows("table3_prices.csv")
+    spots = [(float(g["x1"]), float(g["x2"])) for g in gold]
+    printed_c = {"VG0": 21.6164, "VG1": 67.1487, "NIG0": 55.0673, "NIG1": 45.0189}     # Sec. 4
+    x_max = {"VG0": 5700.0, "VG1": 500.0, "NIG0": 600.0, "NIG1": 700.0}               # Sec. 4
+    out = {}
+    for name, N_x in (("VG0", 700), ("VG1", 400), ("NIG0", 128), ("NIG1", 224)):
+        r = t1[name]
+        lv = lp.levy_nts(float(r["alpha"]), float(r["delta"]), float(r["lambda"]),
+                         (float(r["eta1"]), float(r["eta2"])), (float(r["rho11"]), float(r["rho12"]), float(r["rho22"])),
+                         float(r["r"]))
+        plan = lp.PsPlan(lp.make_ps_grid(N_x, x_max[name], c=printed_c[name]), lv,
+                         lp.make_payoff("put_avg", float(r["K"]), float(r["T"])), N_t=N_x // 2, tol=1e-10,
+                         max_iter=128)
+        V = plan.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        V = plan.solve(V)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        info = plan.info()
+        got = plan.price(V, spots).cpu().numpy()
+        want = np.array([float(g[name]) for g in gold])
+        out[name] = {"N_x": N_x, "n_in": info["n_in"], "L": info["L"], "n_steps": info["n_steps"],
+                     "iterations": info["total_iters"], "ms": 1e3 * dt,
+                     "grid_pt_steps_per_s": (N_x + 1) ** 2 * info["n_steps"] / dt,
+                     "max_abs_err_vs_table3": float(np.max(np.abs(got - want)))}
+        plan.close()
+        del V
+        torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_measure(lp, name="nts1024", C=32):
     """The adjoint form on its workload: forward solve time, and the adjoint's
     march part (segment recompute + reverse steps + gather, with the solve's
@@ -541,7 +589,7 @@ def main():
                     help="form timed for the headline value; the other form is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip fv512, Table 3, the adjoint and the batched measurements")
+                    help="skip fv512, Table 3, the price-space plan, the adjoint and the batched measurements")
     ap.add_argument("--batch-count", type=int, default=256, help="draws of the batched recipe in the batched leg")
     ap.add_argument("--fft-size", type=int, default=0,
                     help="transform side of the correlation (0: the smallest supported one, 2^m or 3*2^m)")
@@ -587,6 +635,7 @@ def main():
         fv["vs_oracle"] = fv512_vs_oracle(lp)
         result["fv512"] = fv
         result["paper_table3"] = table3_check(lp)
+        result["price_space"] = price_space_check(lp)
         result["adjoint"] = adjoint_measure(lp)
         result["batched"] = batch_measure(lp, count=args.batch_count)
     if child is not None:
