@@ -464,8 +464,9 @@ const char* lpide_last_error(void);
  * Pay-offs: LPIDE_PUT_AVG and LPIDE_PUT_1, cell averaged on the cells
  * [x_{m-1/2}, x_{m+1/2}]^2 that meet the kink when cell_avg = 1.  Options
  * used: tol, max_iter, damping, device, stream, fft_size (0: the smallest
- * supported transform side >= #in among 64 ... 4096; otherwise a supported
- * side >= #in) and all_correlations (0: the explicit part of a step after one
+ * supported transform side >= #in among 64, 128, 256, 512, 1024, 1536, 2048,
+ * 3072, 4096, 6144, 8192; otherwise one of these or 768, at least #in) and
+ * all_correlations (0: the explicit part of a step after one
  * with theta > 0 from that step's implicit equation, as the log plan does;
  * 1: by the correlation).  precision must be LPIDE_FP64. */
 typedef struct {
@@ -521,7 +522,7 @@ int lpide_ps_discretize_host(const lpide_ps_grid* grid, const lpide_levy* levy, 
  * weights and all workspace.  N_t >= 1 steps of T / N_t (the paper takes
  * N_t = round(N_x / 2)).  Errors: LPIDE_E_PARAM for invalid settings (as
  * lpide_plan_create, plus x_max <= x_int, a pay-off other than the two above,
- * precision other than FP64, #in above the transform side or 4096),
+ * precision other than FP64, #in above the transform side or 8192),
  * LPIDE_E_OOM, LPIDE_E_HIP.  *out is set only on success. */
 int lpide_ps_plan_create(const lpide_ps_grid* grid, const lpide_levy* levy, const lpide_payoff* payoff,
                          double theta, int32_t N_t, const lpide_opts* opts, void** out);

@@ -22,11 +22,12 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblpide.so")
 
 SIZES = [64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096]
+PS_SIZES = SIZES + [6144, 8192]     # the price-space plan's transform sides
 # (source, object, extra flags)
 UNITS = ([("lpide.hip", "lpide.o", []), ("host_plan.cpp", "host_plan.o", []), ("ps.hip", "ps.o", []),
           ("ps_host.cpp", "ps_host.o", [])] +
          [("march_L.hip", "march_L%d.o" % L, ["-DLPIDE_L=%d" % L]) for L in SIZES] +
-         [("ps_L.hip", "ps_L%d.o" % L, ["-DLPIDE_L=%d" % L]) for L in SIZES])
+         [("ps_L.hip", "ps_L%d.o" % L, ["-DLPIDE_L=%d" % L]) for L in PS_SIZES])
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LPIDE_ARCH", "gfx950")

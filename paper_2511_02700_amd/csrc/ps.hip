@@ -33,6 +33,23 @@ namespace {
 using detail::fail;
 
 constexpr int POOLN = 6;        // 4 history grids, the current grid, the iterate
+
+// Transform sides of the price-space correlation: those of the workgroup FFT
+// up to 4096, and 6144 = 3 * 2048 and 8192, which still fit one workgroup's LDS.
+constexpr int kPsSides[] = {64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192};
+constexpr int kPsAutoSides[] = {64, 128, 256, 512, 1024, 1536, 2048, 3072, 4096, 6144, 8192};
+
+bool ps_side_supported(int L) {
+    for (int v : kPsSides)
+        if (v == L) return true;
+    return false;
+}
+
+int ps_side_at_least(int need) {
+    for (int v : kPsAutoSides)
+        if (v >= need) return v;
+    return 0;
+}
 constexpr int BATCH = 16;       // steps enqueued between host checks
 
 struct Kind {
@@ -125,7 +142,7 @@ void bapply(PsPlan* p, const PsConv& c, const double* Y, int k) {
 #define PS_CASE(Lc) \
     case Lc: PsL<Lc>::bapply(c, Y, k); break;
         PS_CASE(64) PS_CASE(128) PS_CASE(256) PS_CASE(512) PS_CASE(768) PS_CASE(1024) PS_CASE(1536)
-        PS_CASE(2048) PS_CASE(3072) PS_CASE(4096)
+        PS_CASE(2048) PS_CASE(3072) PS_CASE(4096) PS_CASE(6144) PS_CASE(8192)
 #undef PS_CASE
         default: break;
     }
@@ -136,7 +153,7 @@ void spectrum(PsPlan* p, const double* G, double2* Xf) {
 #define PS_CASE(Lc) \
     case Lc: PsL<Lc>::spectrum(p->stream, G, Xf, const_cast<double2*>(p->conv.spec), p->conv.tw); break;
         PS_CASE(64) PS_CASE(128) PS_CASE(256) PS_CASE(512) PS_CASE(768) PS_CASE(1024) PS_CASE(1536)
-        PS_CASE(2048) PS_CASE(3072) PS_CASE(4096)
+        PS_CASE(2048) PS_CASE(3072) PS_CASE(4096) PS_CASE(6144) PS_CASE(8192)
 #undef PS_CASE
         default: break;
     }
@@ -211,7 +228,7 @@ int create(const lpide_ps_grid* g, const lpide_levy* lv, const lpide_payoff* pay
     const PsHost& hp = p->hp;
     if (p->jumps) {
         if (o.fft_size != 0) {
-            if (!fft_size_supported(o.fft_size) || o.fft_size < hp.n_in) {
+            if (!ps_side_supported(o.fft_size) || o.fft_size < hp.n_in) {
                 const std::string msg = "fft_size " + std::to_string(o.fft_size) +
                                         " is not a supported transform side of at least #in = " +
                                         std::to_string(hp.n_in);
@@ -220,9 +237,9 @@ int create(const lpide_ps_grid* g, const lpide_levy* lv, const lpide_payoff* pay
             }
             p->L = o.fft_size;
         } else {
-            p->L = fft_size_at_least(hp.n_in);
+            p->L = ps_side_at_least(hp.n_in);
             if (p->L == 0) {
-                const std::string msg = "#in = " + std::to_string(hp.n_in) + " exceeds the largest transform side 4096";
+                const std::string msg = "#in = " + std::to_string(hp.n_in) + " exceeds the largest transform side 8192";
                 delete p;
                 return fail(LPIDE_E_PARAM, msg);
             }
@@ -562,7 +579,7 @@ int lpide_ps_discretize_host(const lpide_ps_grid* grid, const lpide_levy* levy, 
     info->n_in = hp.n_in;
     info->n_out = hp.n_out;
     info->n_nz = hp.n_nz;
-    info->L = hp.nts.jumps ? lpide::fft_size_at_least(hp.n_in) : 0;
+    info->L = hp.nts.jumps ? lpide::ps::ps_side_at_least(hp.n_in) : 0;
     info->c = hp.c;
     info->x_int = hp.x_int;
     info->F = hp.F;

@@ -12,7 +12,7 @@ namespace ps {
 
 template <int L>
 void PsL<L>::bapply(const PsConv& c, const double* Y, int k) {
-    constexpr int T = L / conv_e(L);
+    constexpr int T = L / ps_e(L);
     const PsOps& o = c.o;
     hipLaunchKernelGGL(ps_tin2, dim3((o.n_nz + 255) / 256, o.n), dim3(256), 0, c.stream, Y, c.U, o, c.ctl, k, c.tol);
     hipLaunchKernelGGL((ps_rows_fwd<L>), dim3((o.n_nz + 1) / 2), dim3(T), 0, c.stream, (const double*)c.U, c.X, o, c.tw,

@@ -41,6 +41,10 @@ namespace ps {
 
 constexpr int PS_MAXK = 128;   // iterations per step the control block can record
 
+// FFT elements per thread of the price-space transforms: 16 above 4096 (one
+// workgroup of 384 or 512 threads, 104 or 148 KB of LDS at 6144 and 8192).
+constexpr int ps_e(int L) { return L > 4096 ? 16 : conv_e(L); }
+
 // Control block of a price-space march.
 struct PsCtl {
     unsigned long long err[PS_MAXK + 2];   // err[k]: stopping-rule value of iteration k (FP64 bits); 0 = unset
@@ -124,11 +128,11 @@ static __global__ __launch_bounds__(256) void ps_tin2(const double* __restrict__
 // Rows (2p, 2p+1) of v^in = T^in U (four rows of U each, zero beyond n_nz
 // columns), one complex FFT, the half spectra into X[k2 * ldx + row].
 template <int L>
-__global__ __launch_bounds__(L / conv_e(L)) void ps_rows_fwd(const double* __restrict__ U, double2* __restrict__ X,
+__global__ __launch_bounds__(L / ps_e(L)) void ps_rows_fwd(const double* __restrict__ U, double2* __restrict__ X,
                                                              PsOps o, const double2* __restrict__ tw,
                                                              const PsCtl* ctl, int k, double tol) {
     if (ps_halted(ctl, k, tol)) return;
-    constexpr int KE = conv_e(L), T = L / KE;
+    constexpr int KE = ps_e(L), T = L / KE;
     __shared__ double2 lds[lds_slots(L)];
     __shared__ double2 tw4[tw_slots<L, KE>()];
     load_twiddles<L, KE>(tw, tw4);
@@ -177,11 +181,11 @@ __global__ __launch_bounds__(L / conv_e(L)) void ps_rows_fwd(const double* __res
 // Column k2: FFT over the n_nz rows (zero padded to L), times the spectrum,
 // inverse FFT, the first n_out entries back into X.
 template <int L>
-__global__ __launch_bounds__(L / conv_e(L)) void ps_cols(double2* __restrict__ X, const double2* __restrict__ spec,
+__global__ __launch_bounds__(L / ps_e(L)) void ps_cols(double2* __restrict__ X, const double2* __restrict__ spec,
                                                          PsOps o, const double2* __restrict__ tw, const PsCtl* ctl,
                                                          int k, double tol) {
     if (ps_halted(ctl, k, tol)) return;
-    constexpr int KE = conv_e(L), T = L / KE;
+    constexpr int KE = ps_e(L), T = L / KE;
     __shared__ double2 lds[lds_slots(L)];
     __shared__ double2 tw4[tw_slots<L, KE>()];
     load_twiddles<L, KE>(tw, tw4);
@@ -210,11 +214,11 @@ __global__ __launch_bounds__(L / conv_e(L)) void ps_cols(double2* __restrict__ X
 // FFT, the n_out kept columns staged in LDS, then the axis-2 T^out gather:
 // Z[row][m] = sum_t T^out_{m, s_m + t} row[s_m + t], m < n.
 template <int L>
-__global__ __launch_bounds__(L / conv_e(L)) void ps_rows_inv(const double2* __restrict__ X, double* __restrict__ Z,
+__global__ __launch_bounds__(L / ps_e(L)) void ps_rows_inv(const double2* __restrict__ X, double* __restrict__ Z,
                                                              PsOps o, const double2* __restrict__ tw,
                                                              const PsCtl* ctl, int k, double tol) {
     if (ps_halted(ctl, k, tol)) return;
-    constexpr int KE = conv_e(L), T = L / KE;
+    constexpr int KE = ps_e(L), T = L / KE;
     __shared__ double2 lds[lds_slots(L)];
     __shared__ double2 tw4[tw_slots<L, KE>()];
     load_twiddles<L, KE>(tw, tw4);

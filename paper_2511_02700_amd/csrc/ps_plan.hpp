@@ -40,6 +40,8 @@ extern template struct PsL<1536>;
 extern template struct PsL<2048>;
 extern template struct PsL<3072>;
 extern template struct PsL<4096>;
+extern template struct PsL<6144>;
+extern template struct PsL<8192>;
 
 }  // namespace ps
 }  // namespace lpide

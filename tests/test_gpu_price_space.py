@@ -17,7 +17,10 @@ Bars:
     below 1e-12 (measured: 3e-13 to 8e-12);
   - on growing grids the prices approach Table 3 (the paper's N_x = 800, 400
     for NIG0) at an observed order of at least 1.5 (GPU tol 1e-10; the paper
-    iterates to 1e-7).
+    iterates to 1e-7);
+  - on the paper's own grid for VG0 (N_x = 800, #in = 4536, L = 6144) the nine
+    prices equal Table 3 within 1e-4: the print's rounding (5e-5) plus the
+    paper's fixed-point tolerance 1e-7 (measured 6.3e-5).
 """
 
 import csv
@@ -104,7 +107,8 @@ def test_sizes_and_initial_values(lp, name, N_x):
 
 
 @pytest.mark.parametrize("name,N_x,fft_size", [("VG1", 32, 0), ("NIG1", 32, 0), ("VG0", 40, 0), ("NIG0", 32, 768),
-                                               ("NIG0", 32, 0), ("VG1", 48, 1024)])
+                                               ("NIG0", 32, 0), ("VG1", 48, 1024), ("VG1", 32, 6144),
+                                               ("NIG0", 24, 8192)])
 def test_apply_B_matches_oracle(lp, name, N_x, fft_size):
     import torch
     plan = _gpu_plan(lp, name, N_x, fft_size=fft_size)
@@ -214,3 +218,18 @@ def test_table3_approached_at_second_order(lp, name, sizes):
         plan.close()
     for (n0, e0), (n1, e1) in zip(zip(sizes, errs), zip(sizes[1:], errs[1:])):
         assert math.log(e0 / e1) / math.log(n1 / n0) > 1.5, errs
+
+
+def test_table3_on_the_papers_grid_vg0(lp):
+    """VG0 on the paper's own discretization (N_x = 800, N_z = 1600,
+    N_t = 400, x_max = 57K, c = 21.6164): the nine Table 3 prices."""
+    spots, want = _spots_and_table3("VG0")
+    plan = _gpu_plan(lp, "VG0", 800, tol=1e-10, max_iter=128)
+    info = plan.info()
+    V = plan.solve()
+    P = plan.price(V, spots).cpu().numpy()
+    err = float(np.max(np.abs(P - want)))
+    _note("VG0 N_x=800 (#in %d, L %d, %d iterations over %d entries): max |P - Table 3| = %.2e" % (
+        info["n_in"], info["L"], plan.info()["total_iters"], info["n_steps"], err))
+    assert info["L"] == 6144
+    assert err < 1e-4
