@@ -465,8 +465,9 @@ const char* lpide_last_error(void);
  * [x_{m-1/2}, x_{m+1/2}]^2 that meet the kink when cell_avg = 1.  Options
  * used: tol, max_iter, damping, device, stream, fft_size (0: the smallest
  * supported transform side >= #in among 64, 128, 256, 512, 1024, 1536, 2048,
- * 3072, 4096, 6144, 8192; otherwise one of these or 768, at least #in) and
- * all_correlations (0: the explicit part of a step after one
+ * 3072, 4096, 6144, 8192, 12288, 16384, 24576; otherwise one of these or 768,
+ * at least #in; sides above 8192 run as (3, 4, 6) transforms of length 4096
+ * per sequence) and all_correlations (0: the explicit part of a step after one
  * with theta > 0 from that step's implicit equation, as the log plan does;
  * 1: by the correlation).  precision must be LPIDE_FP64. */
 typedef struct {
@@ -522,7 +523,7 @@ int lpide_ps_discretize_host(const lpide_ps_grid* grid, const lpide_levy* levy, 
  * weights and all workspace.  N_t >= 1 steps of T / N_t (the paper takes
  * N_t = round(N_x / 2)).  Errors: LPIDE_E_PARAM for invalid settings (as
  * lpide_plan_create, plus x_max <= x_int, a pay-off other than the two above,
- * precision other than FP64, #in above the transform side or 8192),
+ * precision other than FP64, #in above the transform side or 24576),
  * LPIDE_E_OOM, LPIDE_E_HIP.  *out is set only on success. */
 int lpide_ps_plan_create(const lpide_ps_grid* grid, const lpide_levy* levy, const lpide_payoff* payoff,
                          double theta, int32_t N_t, const lpide_opts* opts, void** out);

@@ -22,7 +22,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblpide.so")
 
 SIZES = [64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096]
-PS_SIZES = SIZES + [6144, 8192]     # the price-space plan's transform sides
+PS_SIZES = SIZES + [6144, 8192, 12288, 16384, 24576]     # the price-space plan's transform sides
 # (source, object, extra flags)
 UNITS = ([("lpide.hip", "lpide.o", []), ("host_plan.cpp", "host_plan.o", []), ("ps.hip", "ps.o", []),
           ("ps_host.cpp", "ps_host.o", [])] +

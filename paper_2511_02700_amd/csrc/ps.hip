@@ -21,6 +21,7 @@
 
 #include "lpide.h"
 #include "ps_host.hpp"
+#include "ps_big.hpp"
 #include "ps_plan.hpp"
 
 namespace lpide {
@@ -35,9 +36,10 @@ using detail::fail;
 constexpr int POOLN = 6;        // 4 history grids, the current grid, the iterate
 
 // Transform sides of the price-space correlation: those of the workgroup FFT
-// up to 4096, and 6144 = 3 * 2048 and 8192, which still fit one workgroup's LDS.
-constexpr int kPsSides[] = {64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192};
-constexpr int kPsAutoSides[] = {64, 128, 256, 512, 1024, 1536, 2048, 3072, 4096, 6144, 8192};
+// up to 4096, 6144 = 3 * 2048 and 8192, which still fit one workgroup's LDS,
+// and the two-level sides 12288, 16384 and 24576 = (3, 4, 6) x 4096.
+constexpr int kPsSides[] = {64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192, 12288, 16384, 24576};
+constexpr int kPsAutoSides[] = {64, 128, 256, 512, 1024, 1536, 2048, 3072, 4096, 6144, 8192, 12288, 16384, 24576};
 
 bool ps_side_supported(int L) {
     for (int v : kPsSides)
@@ -142,18 +144,20 @@ void bapply(PsPlan* p, const PsConv& c, const double* Y, int k) {
 #define PS_CASE(Lc) \
     case Lc: PsL<Lc>::bapply(c, Y, k); break;
         PS_CASE(64) PS_CASE(128) PS_CASE(256) PS_CASE(512) PS_CASE(768) PS_CASE(1024) PS_CASE(1536)
-        PS_CASE(2048) PS_CASE(3072) PS_CASE(4096) PS_CASE(6144) PS_CASE(8192)
+        PS_CASE(2048) PS_CASE(3072) PS_CASE(4096) PS_CASE(6144) PS_CASE(8192) PS_CASE(12288) \
+        PS_CASE(16384) PS_CASE(24576)
 #undef PS_CASE
         default: break;
     }
 }
 
-void spectrum(PsPlan* p, const double* G, double2* Xf) {
+void spectrum(PsPlan* p, const double* W, int W2, double2* Xf) {
     switch (p->L) {
 #define PS_CASE(Lc) \
-    case Lc: PsL<Lc>::spectrum(p->stream, G, Xf, const_cast<double2*>(p->conv.spec), p->conv.tw); break;
+    case Lc: PsL<Lc>::spectrum(p->stream, W, W2, Xf, const_cast<double2*>(p->conv.spec), p->conv.tw, p->conv.twM); break;
         PS_CASE(64) PS_CASE(128) PS_CASE(256) PS_CASE(512) PS_CASE(768) PS_CASE(1024) PS_CASE(1536)
-        PS_CASE(2048) PS_CASE(3072) PS_CASE(4096) PS_CASE(6144) PS_CASE(8192)
+        PS_CASE(2048) PS_CASE(3072) PS_CASE(4096) PS_CASE(6144) PS_CASE(8192) PS_CASE(12288) \
+        PS_CASE(16384) PS_CASE(24576)
 #undef PS_CASE
         default: break;
     }
@@ -239,7 +243,7 @@ int create(const lpide_ps_grid* g, const lpide_levy* lv, const lpide_payoff* pay
         } else {
             p->L = ps_side_at_least(hp.n_in);
             if (p->L == 0) {
-                const std::string msg = "#in = " + std::to_string(hp.n_in) + " exceeds the largest transform side 8192";
+                const std::string msg = "#in = " + std::to_string(hp.n_in) + " exceeds the largest transform side 24576";
                 delete p;
                 return fail(LPIDE_E_PARAM, msg);
             }
@@ -287,17 +291,21 @@ int create(const lpide_ps_grid* g, const lpide_levy* lv, const lpide_payoff* pay
         op.tout_s = s;
         op.tout_w = w;
         const int L = p->L;
-        std::vector<double2> tw(L);
-        for (int q = 0; q < L; ++q) {
-            // exp(-2 pi i q / L), evaluated in long double
-            const long double ang = -2.0L * 3.14159265358979323846264338327950288L * q / L;
-            tw[q] = make_double2((double)cosl(ang), (double)sinl(ang));
-        }
-        double2 *twd = nullptr, *spec = nullptr, *X = nullptr;
+        auto twiddles = [](int N) {
+            std::vector<double2> t(N);
+            for (int q = 0; q < N; ++q) {
+                // exp(-2 pi i q / N), evaluated in long double
+                const long double ang = -2.0L * 3.14159265358979323846264338327950288L * q / N;
+                t[q] = make_double2((double)cosl(ang), (double)sinl(ang));
+            }
+            return t;
+        };
+        double2 *twd = nullptr, *twM = nullptr, *spec = nullptr, *X = nullptr;
         double *U = nullptr, *Z = nullptr;
-        if ((rc = upload(p, &twd, tw)) || (rc = dalloc(p, &spec, size_t(L / 2 + 1) * L)) ||
-            (rc = dalloc(p, &X, size_t(L / 2 + 1) * op.ldx)) || (rc = dalloc(p, &U, size_t(n) * hp.n_nz)) ||
-            (rc = dalloc(p, &Z, size_t(hp.n_out) * n)))
+        if ((rc = upload(p, &twd, twiddles(L)))) return bail(rc);
+        if (L > 8192 && (rc = upload(p, &twM, twiddles(BIG_M)))) return bail(rc);
+        if ((rc = dalloc(p, &spec, size_t(L / 2 + 1) * L)) || (rc = dalloc(p, &X, size_t(L / 2 + 1) * op.ldx)) ||
+            (rc = dalloc(p, &U, size_t(n) * hp.n_nz)) || (rc = dalloc(p, &Z, size_t(hp.n_out) * n)))
             return bail(rc);
         PsConv& c = p->conv;
         c.stream = p->stream;
@@ -307,28 +315,26 @@ int create(const lpide_ps_grid* g, const lpide_levy* lv, const lpide_payoff* pay
         c.Z = Z;
         c.spec = spec;
         c.tw = twd;
+        c.twM = twM;
         c.ctl = p->ctl;
         c.tol = o.tol;
-        // weights omega_{j1 - N_z, j2 - N_z} at offset (j1, j2) mod L: the
+        // the weights omega_{j1 - N_z, j2 - N_z} at offset (j1, j2) mod L: the
         // correlation out[o] = sum_j omega_j v^in[o + j] (Sec. 3.2.2)
         const int W2 = 2 * hp.N_z;
-        std::vector<double> G(size_t(L) * L, 0.0);
-        for (int a = 0; a < W2; ++a)
-            for (int b = 0; b < W2; ++b) G[size_t(a) * L + b] = hp.omega[size_t(a) * W2 + b];
-        double* Gd = nullptr;
+        double* Wd = nullptr;
         double2* Xf = nullptr;
-        if (hipMalloc(&Gd, G.size() * sizeof(double)) != hipSuccess) return bail(fail(LPIDE_E_OOM, "hipMalloc G"));
-        if (hipMalloc(&Xf, size_t(L / 2 + 1) * L * sizeof(double2)) != hipSuccess) {
-            (void)hipFree(Gd);
+        if (hipMalloc(&Wd, hp.omega.size() * sizeof(double)) != hipSuccess) return bail(fail(LPIDE_E_OOM, "hipMalloc W"));
+        if (hipMalloc(&Xf, size_t(L / 2 + 1) * W2 * sizeof(double2)) != hipSuccess) {
+            (void)hipFree(Wd);
             return bail(fail(LPIDE_E_OOM, "hipMalloc Xf"));
         }
-        hipError_t e = hipMemcpy(Gd, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice);
+        hipError_t e = hipMemcpy(Wd, hp.omega.data(), hp.omega.size() * sizeof(double), hipMemcpyHostToDevice);
         if (e == hipSuccess) {
-            spectrum(p, Gd, Xf);
+            spectrum(p, Wd, W2, Xf);
             e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-        (void)hipFree(Gd);
+        (void)hipFree(Wd);
         (void)hipFree(Xf);
         if (e != hipSuccess) return bail(fail(LPIDE_E_HIP, std::string("spectrum: ") + hipGetErrorString(e)));
     }

@@ -19,6 +19,7 @@ struct PsConv {
     double* Z = nullptr;            // n_out x n
     const double2* spec = nullptr;  // (L/2 + 1) x L
     const double2* tw = nullptr;    // L twiddles exp(-2 pi i q / L)
+    const double2* twM = nullptr;   // sides above 8192: the 4096 twiddles of the inner length-4096 transforms
     const PsCtl* ctl = nullptr;     // nullptr: no early exit
     double tol = 0.0;
 };
@@ -27,8 +28,12 @@ template <int L>
 struct PsL {
     // Z = (C T^in Y restricted to y^out) (T^out)^T for iteration k (k = 0: always runs).
     static void bapply(const PsConv& c, const double* Y, int k);
-    // spec = conj(FFT2(G)) / L^2 of the L x L real grid G (Xfull: (L/2 + 1) x L scratch).
-    static void spectrum(hipStream_t s, const double* G, double2* Xfull, double2* spec, const double2* tw);
+    // spec = conj(FFT2(G)) / L^2 of the L x L real grid G that holds the W2 x W2
+    // weights W (row-major) in its corner [0, W2)^2 and zeros elsewhere (Xf:
+    // (L/2 + 1) x W2 scratch).  Natural order up to 8192; in the (r, q) order of
+    // the two-level transforms above.
+    static void spectrum(hipStream_t s, const double* W, int W2, double2* Xf, double2* spec, const double2* tw,
+                         const double2* twM);
 };
 extern template struct PsL<64>;
 extern template struct PsL<128>;
@@ -42,6 +47,9 @@ extern template struct PsL<3072>;
 extern template struct PsL<4096>;
 extern template struct PsL<6144>;
 extern template struct PsL<8192>;
+extern template struct PsL<12288>;
+extern template struct PsL<16384>;
+extern template struct PsL<24576>;
 
 }  // namespace ps
 }  // namespace lpide

@@ -18,9 +18,12 @@ Bars:
   - on growing grids the prices approach Table 3 (the paper's N_x = 800, 400
     for NIG0) at an observed order of at least 1.5 (GPU tol 1e-10; the paper
     iterates to 1e-7);
-  - on the paper's own grid for VG0 (N_x = 800, #in = 4536, L = 6144) the nine
-    prices equal Table 3 within 1e-4: the print's rounding (5e-5) plus the
-    paper's fixed-point tolerance 1e-7 (measured 6.3e-5).
+  - on the paper's own grids for VG0 and VG1 (N_x = 800; #in = 4536 and 8400,
+    L = 6144 and the two-level 12288) the nine prices equal Table 3 within
+    1e-4: the print's rounding (5e-5) plus the paper's fixed-point tolerance
+    1e-7 (measured 6.3e-5 and 6.9e-5; NIG0 at N_x = 400 and NIG1 at 800, with
+    L = 16384 and 24576, give 1.1e-4 and 6.8e-5 in marches of about a minute,
+    run by bench.py --table3-paper-grids).
 """
 
 import csv
@@ -108,7 +111,8 @@ def test_sizes_and_initial_values(lp, name, N_x):
 
 @pytest.mark.parametrize("name,N_x,fft_size", [("VG1", 32, 0), ("NIG1", 32, 0), ("VG0", 40, 0), ("NIG0", 32, 768),
                                                ("NIG0", 32, 0), ("VG1", 48, 1024), ("VG1", 32, 6144),
-                                               ("NIG0", 24, 8192)])
+                                               ("NIG0", 24, 8192), ("VG1", 32, 12288), ("NIG0", 24, 16384),
+                                               ("NIG1", 32, 24576)])
 def test_apply_B_matches_oracle(lp, name, N_x, fft_size):
     import torch
     plan = _gpu_plan(lp, name, N_x, fft_size=fft_size)
@@ -220,16 +224,17 @@ def test_table3_approached_at_second_order(lp, name, sizes):
         assert math.log(e0 / e1) / math.log(n1 / n0) > 1.5, errs
 
 
-def test_table3_on_the_papers_grid_vg0(lp):
-    """VG0 on the paper's own discretization (N_x = 800, N_z = 1600,
-    N_t = 400, x_max = 57K, c = 21.6164): the nine Table 3 prices."""
-    spots, want = _spots_and_table3("VG0")
-    plan = _gpu_plan(lp, "VG0", 800, tol=1e-10, max_iter=128)
+@pytest.mark.parametrize("name,L", [("VG0", 6144), ("VG1", 12288)])
+def test_table3_on_the_papers_grid(lp, name, L):
+    """The paper's own discretization (N_x = 800, N_z = 1600, N_t = 400, and
+    x_max, c of Sec. 4): the nine Table 3 prices."""
+    spots, want = _spots_and_table3(name)
+    plan = _gpu_plan(lp, name, 800, tol=1e-10, max_iter=128)
     info = plan.info()
     V = plan.solve()
     P = plan.price(V, spots).cpu().numpy()
     err = float(np.max(np.abs(P - want)))
-    _note("VG0 N_x=800 (#in %d, L %d, %d iterations over %d entries): max |P - Table 3| = %.2e" % (
-        info["n_in"], info["L"], plan.info()["total_iters"], info["n_steps"], err))
-    assert info["L"] == 6144
+    _note("%s N_x=800 (#in %d, L %d, %d iterations over %d entries): max |P - Table 3| = %.2e" % (
+        name, info["n_in"], info["L"], plan.info()["total_iters"], info["n_steps"], err))
+    assert info["L"] == L
     assert err < 1e-4
