@@ -385,6 +385,53 @@ def table3_check(lp):
     return out
 
 
+def price_space_paper_grids(lp):
+    """All four Table 1 sets on the paper's own price-space grids (N_x = 800,
+    NIG0 400; N_z = 2 N_x, N_t = N_x / 2, x_max and c of Sec. 4), tol 1e-10:
+    max |price - Table 3| over the nine spots, march time, iterations."""
+    import csv
+    import numpy as np
+    import torch
+
+    def rows(name):
+        with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+            return list(csv.DictReader(line for line in f if not line.startswith("#")))
+
+    t1 = {r["name"]: r for r in rows("table1_params.csv")}
+    gold = rows("table3_prices.csv")
+    spots = [(float(g["x1"]), float(g["x2"])) for g in gold]
+    printed_c = {"VG0": 21.6164, "VG1": 67.1487, "NIG0": 55.0673, "NIG1": 45.0189}     # Sec. 4
+    x_max = {"VG0": 5700.0, "VG1": 500.0, "NIG0": 600.0, "NIG1": 700.0}               # Sec. 4
+    out = {}
+    for name, N_x in (("VG0", 800), ("VG1", 800), ("NIG0", 400), ("NIG1", 800)):
+        r = t1[name]
+        lv = lp.levy_nts(float(r["alpha"]), float(r["delta"]), float(r["lambda"]),
+                         (float(r["eta1"]), float(r["eta2"])), (float(r["rho11"]), float(r["rho12"]), float(r["rho22"])),
+                         float(r["r"]))
+        t0 = time.perf_counter()
+        plan = lp.PsPlan(lp.make_ps_grid(N_x, x_max[name], c=printed_c[name]), lv,
+                         lp.make_payoff("put_avg", float(r["K"]), float(r["T"])), N_t=N_x // 2, tol=1e-10,
+                         max_iter=128)
+        plan_s = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        V = plan.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        info = plan.info()
+        got = plan.price(V, spots).cpu().numpy()
+        want = np.array([float(g[name]) for g in gold])
+        out[name] = {"N_x": N_x, "n_in": info["n_in"], "L": info["L"], "n_steps": info["n_steps"],
+                     "iterations": info["total_iters"], "plan_s": plan_s, "march_s": dt,
+                     "prices": [round(float(v), 6) for v in got],
+                     "max_abs_err_vs_table3": float(np.max(np.abs(got - want)))}
+        print("[price-space paper grid] %s: %s" % (name, json.dumps(out[name])), file=sys.stderr, flush=True)
+        plan.close()
+        del V
+        torch.cuda.empty_cache()
+    return out
+
+
 def price_space_check(lp):
     """The paper's own price-space discretization (Sec. 3.2, 3.3, Sec. 4
     settings) on each Table 1 set at the largest N_x whose #in fits a
@@ -591,6 +638,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip fv512, Table 3, the price-space plan, the adjoint and the batched measurements")
     ap.add_argument("--batch-count", type=int, default=256, help="draws of the batched recipe in the batched leg")
+    ap.add_argument("--table3-paper-grids", action="store_true",
+                    help="also run the four Table 3 sets on the paper's own price-space grids (N_x = 800, NIG0 "
+                         "400; a few minutes)")
     ap.add_argument("--fft-size", type=int, default=0,
                     help="transform side of the correlation (0: the smallest supported one, 2^m or 3*2^m)")
     ap.add_argument("--traffic-json", default=None,
@@ -627,15 +677,19 @@ def main():
         "roofline": head.pop("roofline"),
     }
     result.update(head)
-    # the oracle sample runs on the host while the GPU extras run
-    child = cpu_baseline_start(args.workload) if rank == 0 and not args.no_cpu_baseline else None
+    # the small, launch-bound fv512 leg runs with the host cores idle; the oracle
+    # sample then runs on the host while the other GPU extras run
     if not args.no_extras:
         fv = measure_workload(lp, "fv512", args.steps, args.warmup,
                               traffic_json=os.path.join(ROOT, "profiles", "pmc_fv512.json"), other_side=True)
         fv["vs_oracle"] = fv512_vs_oracle(lp)
         result["fv512"] = fv
+    child = cpu_baseline_start(args.workload) if rank == 0 and not args.no_cpu_baseline else None
+    if not args.no_extras:
         result["paper_table3"] = table3_check(lp)
         result["price_space"] = price_space_check(lp)
+        if args.table3_paper_grids:
+            result["price_space_paper_grids"] = price_space_paper_grids(lp)
         result["adjoint"] = adjoint_measure(lp)
         result["batched"] = batch_measure(lp, count=args.batch_count)
     if child is not None:
