@@ -303,7 +303,7 @@ int create(const lpide_ps_grid* g, const lpide_levy* lv, const lpide_payoff* pay
         double2 *twd = nullptr, *twM = nullptr, *spec = nullptr, *X = nullptr;
         double *U = nullptr, *Z = nullptr;
         if ((rc = upload(p, &twd, twiddles(L)))) return bail(rc);
-        if (L > 8192 && (rc = upload(p, &twM, twiddles(BIG_M)))) return bail(rc);
+        if (L > 8192 && (rc = upload(p, &twM, twiddles(big_m(L))))) return bail(rc);
         if ((rc = dalloc(p, &spec, size_t(L / 2 + 1) * L)) || (rc = dalloc(p, &X, size_t(L / 2 + 1) * op.ldx)) ||
             (rc = dalloc(p, &U, size_t(n) * hp.n_nz)) || (rc = dalloc(p, &Z, size_t(hp.n_out) * n)))
             return bail(rc);

@@ -1,21 +1,23 @@
 // Two-level transforms of the price-space correlation for sides L = R M
-// beyond one workgroup's LDS (M = 4096; R = 3, 4, 6: L = 12288, 16384,
-// 24576; the paper's grids need up to #in = 16807, Sec. 4).
+// beyond one workgroup's LDS (M = 4096; R = 3, 4, 6: L = 12288, 16384, 24576;
+// the paper's grids need up to #in = 16807, Sec. 4).
 //
 // With w_N = exp(-2 pi i / N), a length-L transform splits by decimation in
 // frequency into R transforms of length M,
 //   Z_{R q + r} = FFT_M(y^(r))_q,   y^(r)_m = w_L^{m r} sum_s z_{m + s M} w_R^{s r},
 // and its inverse by decimation in time back into them,
 //   z_{m + s M} = sum_r w_R^{-s r} w_L^{-m r} IFFT_M(Z_{R . + r})_m.
-// One workgroup (M / 8 threads) handles one length-L sequence and runs its R
+// One workgroup of 512 threads handles one length-L sequence and runs its R
 // length-M transforms one after the other through LDS; the inverse sums the
 // R contributions in registers, for the SO segments of length M that hold
 // kept outputs (SO = ceil(n_out / M) <= R).  The spectrum of the weights is stored per
 // column in the order (r, q): entry r M + q of column k2 holds frequency
 // R q + r, so that the column pass multiplies each length-M transform by a
 // contiguous slice.  The row r2c split needs Z_k and Z_{L-k}: for k = R q + r
-// the partner lies in sub-sequence R - r (0 for r = 0), so the row kernel
-// transforms the sub-sequences in those pairs.
+// the partner lies in sub-sequence R - r at index M - 1 - q (sub-sequence 0
+// at (M - q) mod M for r = 0), so the row kernel transforms the
+// sub-sequences in those pairs, one held in registers and its partner in LDS,
+// and each thread writes both members of its pairs (k, L - k).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,8 +27,12 @@
 namespace lpide {
 namespace ps {
 
-constexpr int BIG_M = 4096;
-constexpr int BIG_E = 8;     // 512 threads: up to 4 output segments of accumulators stay in registers
+constexpr int BIG_T = 512;   // threads of every two-level kernel
+// Inner transform length of a two-level side: 4096 (8 elements per thread).
+// Inner transforms of 8192 would halve the sub-transforms, but with 16
+// elements per thread the column pass and row inverse spill their
+// accumulators (700-1000 bytes per lane at 512 threads).
+constexpr int big_m(int) { return 4096; }
 
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
@@ -34,18 +40,17 @@ __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -
 // complex sequence), the half spectra into X[k * ldx + row], k = 0..L/2.
 // MODE 0: the rows of v^in = T^in U (U: n x ldu; n_nz rows and columns);
 // MODE 1: rows of a dense real array G (nrows x ncols, row stride ldu).
-template <int R, int MODE>
-__global__ __launch_bounds__(BIG_M / BIG_E) void ps_big_rows_fwd(const double* __restrict__ U, int ldu, int nrows,
-                                                                 int ncols, double2* __restrict__ X, int ldx,
-                                                                 const int* __restrict__ tin_s,
-                                                                 const double* __restrict__ tin_w,
-                                                                 const double2* __restrict__ twL,
-                                                                 const double2* __restrict__ twM, const PsCtl* ctl,
-                                                                 int k, double tol) {
+template <int M, int R, int MODE>
+__global__ __launch_bounds__(BIG_T) void ps_big_rows_fwd(const double* __restrict__ U, int ldu, int nrows, int ncols,
+                                                         double2* __restrict__ X, int ldx,
+                                                         const int* __restrict__ tin_s,
+                                                         const double* __restrict__ tin_w,
+                                                         const double2* __restrict__ twL,
+                                                         const double2* __restrict__ twM, const PsCtl* ctl, int k,
+                                                         double tol) {
     if (ps_halted(ctl, k, tol)) return;
-    constexpr int M = BIG_M, E = BIG_E, T = M / E, L = R * M;
+    constexpr int E = M / BIG_T, T = BIG_T, L = R * M;
     __shared__ double2 lds[lds_slots(M)];
-    __shared__ double2 bufA[M];
     __shared__ double2 tw4[tw_slots<M, E>()];
     load_twiddles<M, E>(twM, tw4);
     const int np = (nrows + 1) >> 1;
@@ -68,13 +73,14 @@ __global__ __launch_bounds__(BIG_M / BIG_E) void ps_big_rows_fwd(const double* _
         ub = U + (size_t)(hasb ? rb : ra) * ldu;
         wb[0] = hasb ? 1.0 : 0.0;
     }
-    // y^(r) for this thread's m, then its length-M transform (in natural order in reg)
-    auto sub_fft = [&](int r, double2 (&reg)[E]) {
+    // y^(r) and y^(r2) for this thread's m from one pass over the inputs (the
+    // two sub-sequences of a pair read the same z), then the transform of y^(r)
+    auto gather2 = [&](int r, int r2, double2 (&y1)[E], double2 (&y2)[E]) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) reg[e] = make_double2(0.0, 0.0);
+        for (int e = 0; e < E; ++e) y1[e] = y2[e] = make_double2(0.0, 0.0);
 #pragma unroll 1
         for (int s = 0; s < R; ++s) {
-            const double2 w = twL[((s * r) % R) * M];
+            const double2 w1 = twL[((s * r) % R) * M], w2 = twL[((s * r2) % R) * M];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int j = tid + e * T + s * M;
@@ -90,49 +96,58 @@ __global__ __launch_bounds__(BIG_M / BIG_E) void ps_big_rows_fwd(const double* _
                         a = ua[j];
                         b = wb[0] * ub[j];
                     }
-                    reg[e].x += a * w.x - b * w.y;
-                    reg[e].y += a * w.y + b * w.x;
+                    y1[e].x += a * w1.x - b * w1.y;
+                    y1[e].y += a * w1.y + b * w1.x;
+                    y2[e].x += a * w2.x - b * w2.y;
+                    y2[e].y += a * w2.y + b * w2.x;
                 }
             }
         }
 #pragma unroll
-        for (int e = 0; e < E; ++e) reg[e] = cmul(reg[e], twL[(tid + e * T) * r]);
+        for (int e = 0; e < E; ++e) {
+            y1[e] = cmul(y1[e], twL[(tid + e * T) * r]);
+            y2[e] = cmul(y2[e], twL[(tid + e * T) * r2]);
+        }
+    };
+    auto fft = [&](double2 (&reg)[E]) {
         __syncthreads();                                  // LDS free for the transform
         fft_block<M, E, false>(reg, lds, tw4);
+    };
+    // A_k, B_k of the two rows from Z_k = z and Z_{L-k} = w
+    auto put = [&](int kk, double2 z, double2 w) {
+        double2* xk = X + (size_t)kk * ldx;
+        xk[ra] = make_double2(0.5 * (z.x + w.x), 0.5 * (z.y - w.y));
+        if (hasb) xk[rb] = make_double2(0.5 * (z.y + w.y), -0.5 * (z.x - w.x));
     };
 #pragma unroll 1
     for (int r = 0; r <= R / 2; ++r) {
         const int r2 = (R - r) % R;                       // the partner sub-sequence
-        double2 reg[E];
-        sub_fft(r, reg);
+        double2 yr[E], yp[E];
+        gather2(r, r2, yr, yp);                           // (yp = yr when the pair is r itself)
+        fft(yr);
+        if (r2 != r) fft(yp);
+        __syncthreads();
         if (r2 != r) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) bufA[tid + e * T] = reg[e];
-            sub_fft(r2, reg);
+            for (int e = 0; e < E; ++e) lds[tid + e * T] = yp[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) lds[tid + e * T] = yr[e];
         }
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < E; ++e) lds[tid + e * T] = reg[e];
-        __syncthreads();
-        const double2* Yr = r2 != r ? bufA : lds;         // sub-sequence r
-        const double2* Yp = lds;                          // sub-sequence r2
-        for (int q = tid; q < M; q += T) {
-            // k = R q + r with partner L - k in r2 at (M - q) mod M (r = 0) or M - 1 - q
+        for (int e = 0; e < E; ++e) {
+            const int q = tid + e * T;
             const int kk = R * q + r;
-            if (kk <= L / 2) {
-                const double2 z = Yr[q], w = Yp[r == 0 ? ((M - q) & (M - 1)) : M - 1 - q];
-                double2* xk = X + (size_t)kk * ldx;
-                xk[ra] = make_double2(0.5 * (z.x + w.x), 0.5 * (z.y - w.y));
-                if (hasb) xk[rb] = make_double2(0.5 * (z.y + w.y), -0.5 * (z.x - w.x));
-            }
-            if (r2 != r) {
-                const int k2 = R * q + r2;
-                if (k2 <= L / 2) {
-                    const double2 z = Yp[q], w = Yr[M - 1 - q];
-                    double2* xk = X + (size_t)k2 * ldx;
-                    xk[ra] = make_double2(0.5 * (z.x + w.x), 0.5 * (z.y - w.y));
-                    if (hasb) xk[rb] = make_double2(0.5 * (z.y + w.y), -0.5 * (z.x - w.x));
-                }
+            if (r2 == r) {
+                // the partner of R q + r lies in the same sub-sequence
+                const double2 w = lds[r == 0 ? ((M - q) & (M - 1)) : M - 1 - q];
+                if (kk <= L / 2) put(kk, yr[e], w);
+            } else {
+                const double2 w = lds[M - 1 - q];             // Y^(r2)_{M-1-q} = Z_{L-k}
+                if (kk <= L / 2) put(kk, yr[e], w);
+                const int k2 = R * (M - 1 - q) + r2;          // and Z_{L-k2} = Y^(r)_q
+                if (k2 <= L / 2) put(k2, w, yr[e]);
             }
         }
     }
@@ -142,15 +157,15 @@ __global__ __launch_bounds__(BIG_M / BIG_E) void ps_big_rows_fwd(const double* _
 // transform, product with the stored spectrum, inverse, the first n_out entries
 // back into X.  MODE 1 (plan time): spec_out column = conj(forward) * scale in
 // the (r, q) order.
-template <int R, int SO, int MODE>
-__global__ __launch_bounds__(BIG_M / BIG_E) void ps_big_cols(double2* __restrict__ X, int ldx, int n_in, int n_out,
+template <int M, int R, int SO, int MODE>
+__global__ __launch_bounds__(BIG_T) void ps_big_cols(double2* __restrict__ X, int ldx, int n_in, int n_out,
                                                              const double2* __restrict__ spec,
                                                              double2* __restrict__ spec_out, double scale,
                                                              const double2* __restrict__ twL,
                                                              const double2* __restrict__ twM, const PsCtl* ctl, int k,
                                                              double tol) {
     if (ps_halted(ctl, k, tol)) return;
-    constexpr int M = BIG_M, E = BIG_E, T = M / E, L = R * M;
+    constexpr int E = M / BIG_T, T = BIG_T, L = R * M;
     __shared__ double2 lds[lds_slots(M)];
     __shared__ double2 tw4[tw_slots<M, E>()];
     load_twiddles<M, E>(twM, tw4);
@@ -225,13 +240,13 @@ __global__ __launch_bounds__(BIG_M / BIG_E) void ps_big_cols(double2* __restrict
 // y^out rows (2p, 2p+1): the inverse length-L transform of A + i B (Hermitian
 // completion of the half spectra), then the axis-2 T^out gather through LDS
 // windows of the inverse row: Z[row][m] = sum_t T^out_{m, s_m + t} row[s_m + t].
-template <int R, int SO>
-__global__ __launch_bounds__(BIG_M / BIG_E) void ps_big_rows_inv(const double2* __restrict__ X, double* __restrict__ Z,
+template <int M, int R, int SO>
+__global__ __launch_bounds__(BIG_T) void ps_big_rows_inv(const double2* __restrict__ X, double* __restrict__ Z,
                                                                  PsOps o, const double2* __restrict__ twL,
                                                                  const double2* __restrict__ twM, const PsCtl* ctl,
                                                                  int k, double tol) {
     if (ps_halted(ctl, k, tol)) return;
-    constexpr int M = BIG_M, E = BIG_E, T = M / E, L = R * M;
+    constexpr int E = M / BIG_T, T = BIG_T, L = R * M;
     constexpr int WIN = lds_slots(M);
     __shared__ double2 lds[lds_slots(M)];
     __shared__ double2 tw4[tw_slots<M, E>()];

@@ -19,7 +19,7 @@ struct PsConv {
     double* Z = nullptr;            // n_out x n
     const double2* spec = nullptr;  // (L/2 + 1) x L
     const double2* tw = nullptr;    // L twiddles exp(-2 pi i q / L)
-    const double2* twM = nullptr;   // sides above 8192: the 4096 twiddles of the inner length-4096 transforms
+    const double2* twM = nullptr;   // sides above 8192: the twiddles of the inner transforms (length 4096 or 8192)
     const PsCtl* ctl = nullptr;     // nullptr: no early exit
     double tol = 0.0;
 };
