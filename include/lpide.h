@@ -464,10 +464,12 @@ const char* lpide_last_error(void);
  * Pay-offs: LPIDE_PUT_AVG and LPIDE_PUT_1, cell averaged on the cells
  * [x_{m-1/2}, x_{m+1/2}]^2 that meet the kink when cell_avg = 1.  Options
  * used: tol, max_iter, damping, device, stream, fft_size (0: the smallest
- * supported transform side >= #in among 64, 128, 256, 512, 1024, 1536, 2048,
- * 3072, 4096, 6144, 8192, 12288, 16384, 24576; otherwise one of these or 768,
- * at least #in; sides above 8192 run as (3, 4, 6) transforms of length 4096
- * per sequence) and all_correlations (0: the explicit part of a step after one
+ * supported transform side >= #in among 64, 128, 256, 512, 640, 896, 1024,
+ * 1152, 1280, 1536, 1792, 2048, 2304, 2560, 3072, 3584, 4096, 4608, 5120,
+ * 6144, 7168, 8192, 12288, 16384, 24576 (largest prime factor at most 7, as
+ * Sec. 4 asks); otherwise one of these or 768, at least #in; sides above 8192
+ * run as (3, 4, 6) transforms of length 4096 per sequence) and
+ * all_correlations (0: the explicit part of a step after one
  * with theta > 0 from that step's implicit equation, as the log plan does;
  * 1: by the correlation).  precision must be LPIDE_FP64. */
 typedef struct {

@@ -22,7 +22,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblpide.so")
 
 SIZES = [64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096]
-PS_SIZES = SIZES + [6144, 8192, 12288, 16384, 24576]     # the price-space plan's transform sides
+# the price-space plan's transform sides: also 7-smooth sides 2^m p (p = 5, 7, 9) and the two-level sides
+PS_SIZES = SIZES + [640, 896, 1152, 1280, 1792, 2304, 2560, 3584, 4608, 5120, 6144, 7168, 8192, 12288, 16384, 24576]
 # (source, object, extra flags)
 UNITS = ([("lpide.hip", "lpide.o", []), ("host_plan.cpp", "host_plan.o", []), ("ps.hip", "ps.o", []),
           ("ps_host.cpp", "ps_host.o", [])] +

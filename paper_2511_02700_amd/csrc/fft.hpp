@@ -1,13 +1,13 @@
 // Workgroup-level Stockham FFT for CDNA4 (gfx950), FP64 and FP32 complex data
 // (twiddles always formed in FP64; see twmul).
 //
-// One workgroup transforms one length-L sequence, L = 2^m (64..4096) or
-// L = 3 * 2^m (768, 1536, 3072; transform sizes whose largest prime factor is
-// small, Sec. 4), with T = L/E threads, E in {4, 8, 16} elements per thread
-// held in registers in the canonical layout reg[e] = element (tid + e*T).  The
+// One workgroup transforms one length-L sequence, L = 2^m (64..8192) or
+// L = 2^m 3^a 5^b 7^c (transform sizes whose largest prime factor is at most
+// 7, Sec. 4), with T = L/E threads, E in {4, 8, 16} elements per thread held
+// in registers in the canonical layout reg[e] = element (tid + e*T).  The
 // power-of-two part is done by radix-E stages plus one smaller first stage
-// when its log2 is not a multiple of log2 E; for L = 3 * 2^m one radix-3 stage
-// follows the first stage.  Stages exchange data through one LDS buffer of L
+// when its log2 is not a multiple of log2 E; the odd factors are radix-3, 5
+// and 7 stages that follow the first stage.  Stages exchange data through one LDS buffer of L
 // complex values (plus padding).  Input and output of the whole transform are
 // in the canonical layout, so a load or store of element (tid + e*T) by thread
 // tid is coalesced, and the output registers of a forward transform are the
@@ -20,8 +20,10 @@
 // Twiddles W_N^m = exp(-+2 pi i m / N): per stage only W_N^k is stored in LDS
 // (see TwTab), its powers are formed in registers; conjugated for the inverse.
 // The power-of-two stages hold E/R butterflies per thread in registers; the
-// radix-3 stage (L/3 butterflies, not a multiple of T) reads its operands from
-// LDS and writes back to LDS, so it is never the first or the last stage.
+// odd stages (L/p butterflies, not a multiple of T) read their operands from
+// LDS and write back to LDS, so they are never the first stage; when no
+// power-of-two stage follows them, the result is read from LDS into the
+// canonical registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -166,6 +168,58 @@ __device__ __forceinline__ void dft3(C* v) {
     v[2] = CplxOps<C>::make(m.x - s3 * d.x, m.y - s3 * d.y);
 }
 
+// P-point DFT for odd P (5, 7) in the symmetric form: with A_j = v_j + v_{P-j},
+// B_j = v_j - v_{P-j} (j = 1..(P-1)/2), y_0 = v_0 + sum A_j and, for k = 1..(P-1)/2,
+//   y_k = v_0 + sum_j A_j cos(2 pi jk/P) - i sum_j B_j sin(2 pi jk/P),
+//   y_{P-k} = v_0 + sum_j A_j cos(2 pi jk/P) + i sum_j B_j sin(2 pi jk/P)
+// (forward; the i terms change sign for the inverse).
+template <int P>
+struct OddRoots;
+template <>
+struct OddRoots<5> {
+    static constexpr double c[3] = {1.0, 0.30901699437494745, -0.8090169943749473};   // cos(2 pi m/5)
+    static constexpr double s[3] = {0.0, 0.9510565162951535, 0.5877852522924732};     // sin(2 pi m/5)
+};
+template <>
+struct OddRoots<7> {
+    static constexpr double c[4] = {1.0, 0.6234898018587336, -0.22252093395631434, -0.900968867902419};
+    static constexpr double s[4] = {0.0, 0.7818314824680298, 0.9749279121818236, 0.43388373911755823};
+};
+
+template <int P, bool INV, typename C>
+__device__ __forceinline__ void dft_odd(C* v) {
+    using Rl = typename CplxOps<C>::real;
+    constexpr int H = (P - 1) / 2;
+    C A[H + 1], B[H + 1];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+        A[j] = cadd(v[j], v[P - j]);
+        B[j] = csub(v[j], v[P - j]);
+    }
+    C y[P];
+    y[0] = v[0];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) y[0] = cadd(y[0], A[j]);
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        C a = v[0], b = CplxOps<C>::make(Rl(0), Rl(0));
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            // cos and sin of 2 pi (jk mod P)/P from the half table (sin odd about P/2)
+            const int m = (j * k) % P;
+            const Rl cm = Rl(OddRoots<P>::c[m <= H ? m : P - m]);
+            const Rl sm = m <= H ? Rl(OddRoots<P>::s[m]) : -Rl(OddRoots<P>::s[P - m]);
+            a = CplxOps<C>::make(a.x + cm * A[j].x, a.y + cm * A[j].y);
+            b = CplxOps<C>::make(b.x + sm * B[j].x, b.y + sm * B[j].y);
+        }
+        const C d = mul_mi<INV>(b);
+        y[k] = cadd(a, d);
+        y[P - k] = csub(a, d);
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) v[k] = y[k];
+}
+
 template <int R, bool INV, typename C>
 __device__ __forceinline__ void dft(C* v) {
     if constexpr (R == 2) dft2<INV>(v);
@@ -196,23 +250,38 @@ __device__ __forceinline__ float2 twmul(float2 v, double2 w) {
     return make_float2(a.x + b.x, a.y + b.y);
 }
 
-// Odd factor of a transform size: 1 for powers of two, 3 for 3 * 2^m.
-constexpr int fft_odd(int L) { return (L % 3 == 0) ? 3 : 1; }
+// Odd factor of a transform size: 1 for powers of two, 3 for 3 * 2^m, and so on.
+constexpr int fft_odd(int L) { return (L % 2 == 0) ? fft_odd(L / 2) : L; }
+// Whether an odd factor has no prime factor above 7.
+constexpr bool seven_smooth_odd(int o) {
+    return o == 1 ? true : (o % 3 == 0 ? seven_smooth_odd(o / 3)
+                                       : (o % 5 == 0 ? seven_smooth_odd(o / 5)
+                                                     : (o % 7 == 0 ? seven_smooth_odd(o / 7) : false)));
+}
 
 // Whether the kernels run a size-L transform with E elements per thread: the
 // workgroup is a power of two (L a power of two), or whole waves (L = 3 * 2^m:
 // the block-level reductions and line scans work on whole waves), and a
 // radix-3 stage has a power-of-two stage before and after it.
+//
+// Other odd factors (5, 7, 9, 15, ...; the price-space plan's sides only):
+// the power-of-two part holds at least E (a full first stage), and at most
+// 1024 threads.
 constexpr bool fft_ok(int L, int E) {
     return (E == 4 || E == 8 || (E == 16 && L >= 256)) &&
-           (fft_odd(L) == 1 || ((L / E) % 64 == 0 && L / 3 > E));
+           (fft_odd(L) == 1 || (fft_odd(L) == 3 && (L / E) % 64 == 0 && L / 3 > E) ||
+            (fft_odd(L) != 3 && seven_smooth_odd(fft_odd(L)) && L / fft_odd(L) >= E && L / E <= 1024));
 }
 
 // Elements per thread of the stand-alone transform kernels (8 where allowed).
 constexpr int conv_e(int L) { return fft_ok(L, 8) ? 8 : 4; }
 
-// Stage twiddle tables.  Stage 0 (radix R0, no twiddles); for L = 3 * 2^m
-// stage 1 is radix 3; the others are radix E.  Stage s >= 1 with radix R and
+// Multiplicity of the prime p in m.
+constexpr int pcount(int m, int p) { return m % p == 0 ? 1 + pcount(m / p, p) : 0; }
+
+// Stage twiddle tables.  Stage 0 (radix R0, no twiddles); stages 1..NODD are
+// the odd factors (radix 3, then 5, then 7; for L = 3 * 2^m the single stage 1
+// is radix 3); the others are radix E.  Stage s >= 1 with radix R and
 // Ns = R_0 ... R_{s-1} needs, for butterfly k, W^r = exp(-+2 pi i r k / (R Ns)),
 // r = 1..R-1.  Only the base W = exp(-2 pi i k / (R Ns)), k in [0, Ns), is
 // stored (stage tables concatenated, k contiguous, so a wave reads consecutive
@@ -226,9 +295,13 @@ struct TwTab {
     static constexpr int LE = ilog2c(E);
     static constexpr int R0 = (LOG % LE) ? (1 << (LOG % LE)) : E;
     static constexpr int NP2 = LOG / LE + (LOG % LE ? 1 : 0);   // power-of-two stages
-    static constexpr int NST = NP2 + (ODD == 3 ? 1 : 0);
-    static constexpr int S3 = ODD == 3 ? 1 : -1;                 // the radix-3 stage
-    static constexpr __host__ __device__ int radix(int s) { return s == 0 ? R0 : (s == S3 ? 3 : E); }
+    static constexpr int N3 = pcount(ODD, 3), N5 = pcount(ODD, 5), N7 = pcount(ODD, 7);
+    static constexpr int NODD = N3 + N5 + N7;                    // odd stages 1..NODD
+    static constexpr int NST = NP2 + NODD;
+    static constexpr int S3 = ODD == 3 ? 1 : -1;                 // the radix-3 stage of L = 3 * 2^m
+    static constexpr __host__ __device__ int radix(int s) {
+        return s == 0 ? R0 : (s <= N3 ? 3 : (s <= N3 + N5 ? 5 : (s <= NODD ? 7 : E)));
+    }
     static constexpr __host__ __device__ int ns(int s) {
         int v = 1;
         for (int q = 0; q < s; ++q) v *= radix(q);
@@ -355,13 +428,63 @@ __device__ __forceinline__ void fft_stage3(C* lds, int toff, const double2* tab)
     __syncthreads();
 }
 
+// A radix-5 or radix-7 stage, LDS to LDS like the radix-3 stage: L/P
+// butterflies, thread tid takes j = tid, tid + T, ...; twiddle powers by
+// repeated products of the base W^k (in FP64).
+template <int L, int E, int P, int NS, bool INV, typename C>
+__device__ __forceinline__ void fft_stage_odd(C* lds, int toff, const double2* tab) {
+    constexpr int T = L / E;
+    constexpr int NBF = L / P;
+    constexpr int MB = (NBF + T - 1) / T;
+    const int tid = threadIdx.x;
+    C v[MB][P];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const int j = tid + b * T;
+        if (j < NBF) {
+#pragma unroll
+            for (int r = 0; r < P; ++r) v[b][r] = lds[lds_slot(j + r * NBF)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+        const int j = tid + b * T;
+        if (j < NBF) {
+            const int k = j % NS;
+            const double2 t = tab[toff + k];
+            const double2 w1 = make_double2(t.x, INV ? -t.y : t.y);
+            double2 w = w1;
+#pragma unroll
+            for (int r = 1; r < P; ++r) {
+                v[b][r] = twmul(v[b][r], w);
+                w = cmul(w, w1);
+            }
+            dft_odd<P, INV>(v[b]);
+            const int base = (j - k) * P + k;
+#pragma unroll
+            for (int r = 0; r < P; ++r) lds[lds_slot(base + r * NS)] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
 template <int L, int E, bool INV, int S, int NST, typename C>
 __device__ __forceinline__ void fft_stages(C (&reg)[E], C* lds, const double2* tab) {
     using TT = TwTab<L, E>;
     constexpr int R = TT::radix(S), NS = TT::ns(S), OFF = TT::off(S);
-    if constexpr (S == TT::S3) fft_stage3<L, E, NS, INV>(lds, OFF, tab);
+    constexpr bool ODDSTAGE = S >= 1 && S <= TT::NODD;
+    if constexpr (ODDSTAGE && R == 3) fft_stage3<L, E, NS, INV>(lds, OFF, tab);
+    else if constexpr (ODDSTAGE) fft_stage_odd<L, E, R, NS, INV>(lds, OFF, tab);
     else fft_stage<L, E, R, NS, INV, S == 0, S == NST - 1>(reg, lds, OFF, tab);
-    if constexpr (S + 1 < NST) fft_stages<L, E, INV, S + 1, NST>(reg, lds, tab);
+    if constexpr (S + 1 < NST) {
+        fft_stages<L, E, INV, S + 1, NST>(reg, lds, tab);
+    } else if constexpr (ODDSTAGE) {
+        // the last stage was an odd one: the result into the canonical registers
+        constexpr int T = L / E;
+#pragma unroll
+        for (int e = 0; e < E; ++e) reg[e] = lds[lds_slot(threadIdx.x + e * T)];
+    }
 }
 
 // Unnormalised length-L transform of the workgroup's sequence held in the
@@ -373,7 +496,8 @@ template <int L, int E, bool INV, typename C>
 __device__ __forceinline__ void fft_block(C (&reg)[E], C* lds, const double2* tab) {
     using TT = TwTab<L, E>;
     static_assert((1 << TT::LOG) * TT::ODD == L && L >= 64 && fft_ok(L, E), "unsupported transform size");
-    static_assert(TT::ODD == 1 || TT::NP2 >= 2, "the radix-3 stage sits between two power-of-two stages");
+    static_assert(TT::ODD != 3 || TT::NP2 >= 2, "the radix-3 stage of 3 * 2^m sits between two power-of-two stages");
+    static_assert(TT::NP2 >= 1, "a power-of-two first stage");
     fft_stages<L, E, INV, 0, TT::NST>(reg, lds, tab);
 }
 

@@ -35,11 +35,14 @@ using detail::fail;
 
 constexpr int POOLN = 6;        // 4 history grids, the current grid, the iterate
 
-// Transform sides of the price-space correlation: those of the workgroup FFT
-// up to 4096, 6144 = 3 * 2048 and 8192, which still fit one workgroup's LDS,
-// and the two-level sides 12288, 16384 and 24576 = (3, 4, 6) x 4096.
-constexpr int kPsSides[] = {64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192, 12288, 16384, 24576};
-constexpr int kPsAutoSides[] = {64, 128, 256, 512, 1024, 1536, 2048, 3072, 4096, 6144, 8192, 12288, 16384, 24576};
+// Transform sides of the price-space correlation: powers of two up to 8192,
+// sides 2^m p with odd factor p = 3, 5, 7 or 9 (largest prime factor at most
+// 7, Sec. 4) that one workgroup's LDS holds, and the two-level sides 12288,
+// 16384 and 24576 = (3, 4, 6) x 4096.
+constexpr int kPsSides[] = {64,   128,  256,  512,  640,  768,  896,  1024, 1152,  1280,  1536,  1792, 2048,
+                            2304, 2560, 3072, 3584, 4096, 4608, 5120, 6144, 7168, 8192, 12288, 16384, 24576};
+constexpr int kPsAutoSides[] = {64,   128,  256,  512,  640,  896,  1024, 1152, 1280,  1536,  1792,  2048, 2304,
+                                2560, 3072, 3584, 4096, 4608, 5120, 6144, 7168, 8192, 12288, 16384, 24576};
 
 bool ps_side_supported(int L) {
     for (int v : kPsSides)
@@ -143,9 +146,10 @@ void bapply(PsPlan* p, const PsConv& c, const double* Y, int k) {
     switch (p->L) {
 #define PS_CASE(Lc) \
     case Lc: PsL<Lc>::bapply(c, Y, k); break;
-        PS_CASE(64) PS_CASE(128) PS_CASE(256) PS_CASE(512) PS_CASE(768) PS_CASE(1024) PS_CASE(1536)
-        PS_CASE(2048) PS_CASE(3072) PS_CASE(4096) PS_CASE(6144) PS_CASE(8192) PS_CASE(12288) \
-        PS_CASE(16384) PS_CASE(24576)
+        PS_CASE(64) PS_CASE(128) PS_CASE(256) PS_CASE(512) PS_CASE(640) PS_CASE(768) PS_CASE(896)
+        PS_CASE(1024) PS_CASE(1152) PS_CASE(1280) PS_CASE(1536) PS_CASE(1792) PS_CASE(2048) PS_CASE(2304)
+        PS_CASE(2560) PS_CASE(3072) PS_CASE(3584) PS_CASE(4096) PS_CASE(4608) PS_CASE(5120) PS_CASE(6144)
+        PS_CASE(7168) PS_CASE(8192) PS_CASE(12288) PS_CASE(16384) PS_CASE(24576)
 #undef PS_CASE
         default: break;
     }
@@ -155,9 +159,10 @@ void spectrum(PsPlan* p, const double* W, int W2, double2* Xf) {
     switch (p->L) {
 #define PS_CASE(Lc) \
     case Lc: PsL<Lc>::spectrum(p->stream, W, W2, Xf, const_cast<double2*>(p->conv.spec), p->conv.tw, p->conv.twM); break;
-        PS_CASE(64) PS_CASE(128) PS_CASE(256) PS_CASE(512) PS_CASE(768) PS_CASE(1024) PS_CASE(1536)
-        PS_CASE(2048) PS_CASE(3072) PS_CASE(4096) PS_CASE(6144) PS_CASE(8192) PS_CASE(12288) \
-        PS_CASE(16384) PS_CASE(24576)
+        PS_CASE(64) PS_CASE(128) PS_CASE(256) PS_CASE(512) PS_CASE(640) PS_CASE(768) PS_CASE(896)
+        PS_CASE(1024) PS_CASE(1152) PS_CASE(1280) PS_CASE(1536) PS_CASE(1792) PS_CASE(2048) PS_CASE(2304)
+        PS_CASE(2560) PS_CASE(3072) PS_CASE(3584) PS_CASE(4096) PS_CASE(4608) PS_CASE(5120) PS_CASE(6144)
+        PS_CASE(7168) PS_CASE(8192) PS_CASE(12288) PS_CASE(16384) PS_CASE(24576)
 #undef PS_CASE
         default: break;
     }

@@ -47,6 +47,17 @@ extern template struct PsL<3072>;
 extern template struct PsL<4096>;
 extern template struct PsL<6144>;
 extern template struct PsL<8192>;
+extern template struct PsL<640>;
+extern template struct PsL<896>;
+extern template struct PsL<1152>;
+extern template struct PsL<1280>;
+extern template struct PsL<1792>;
+extern template struct PsL<2304>;
+extern template struct PsL<2560>;
+extern template struct PsL<3584>;
+extern template struct PsL<4608>;
+extern template struct PsL<5120>;
+extern template struct PsL<7168>;
 extern template struct PsL<12288>;
 extern template struct PsL<16384>;
 extern template struct PsL<24576>;

@@ -1,10 +1,12 @@
 // CPU check of the workgroup FFT of paper_2511_02700_amd/csrc/fft.hpp (the
 // unchanged header, compiled for the host against tests/cpu/emu): every
-// transform side and elements-per-thread choice the library instantiates, FP64
+// transform side up to 4096 and elements-per-thread choice the library
+// instantiates, and sides with odd factors 5, 7 and 9, FP64
 // and FP32 data, forward and inverse, one OS thread per GPU thread with a
 // barrier for __syncthreads, the LDS exchange buffer and the twiddle tables in
 // exactly sized heap arrays (so AddressSanitizer reports any access outside
-// them).  Each transform is compared with the DFT evaluated in long double.
+// them).  Each transform is compared with the DFT evaluated in long double (at
+// every output up to L = 2048, at 512 spread outputs above).
 // Prints one line per case and "ALL OK" at the end; exits non-zero on a
 // mismatch.
 #include <cmath>
@@ -74,7 +76,11 @@ bool check(std::mt19937_64& rng, double tol) {
         if (inv) run_block<L, E, true>(tw, x);
         else run_block<L, E, false>(tw, x);
         long double err = 0.0L, scale = 0.0L;
-        for (int k = 0; k < L; ++k) {
+        // every output up to 2048; above, 512 outputs spread over the whole range
+        // (a wrong stage corrupts far more outputs than that misses)
+        const int nk = L > 2048 ? 512 : L;
+        for (int t = 0; t < nk; ++t) {
+            const int k = L > 2048 ? int((unsigned long long)t * 2654435761ull % (unsigned long long)L) : t;
             long double re = 0.0L, im = 0.0L;
             for (int j = 0; j < L; ++j) {
                 const int q = int((long long)j * k % L);
@@ -116,6 +122,23 @@ bool all_sizes(std::mt19937_64& rng, double tol) {
     ok = sizes<2048, C>(rng, tol) && ok;
     ok = sizes<3072, C>(rng, tol) && ok;
     ok = sizes<4096, C>(rng, tol) && ok;
+    // sides with odd factors 5, 7 and 9 (radix-5, radix-7 and two radix-3
+    // stages): every E in FP64, the two smallest in FP32 as well (the stages
+    // are the same code for both), the largest with the 16 elements per thread
+    // the price-space plan uses there
+    ok = sizes<640, C>(rng, tol) && ok;
+    ok = sizes<896, C>(rng, tol) && ok;
+    if constexpr (sizeof(typename Real<C>::T) == 8) {
+        ok = sizes<1152, C>(rng, tol) && ok;
+        ok = sizes<1280, C>(rng, tol) && ok;
+        ok = sizes<1792, C>(rng, tol) && ok;
+        ok = sizes<2304, C>(rng, tol) && ok;
+        ok = sizes<2560, C>(rng, tol) && ok;
+        ok = sizes<3584, C>(rng, tol) && ok;
+        ok = check<4608, 16, C>(rng, tol) && ok;
+        ok = check<5120, 16, C>(rng, tol) && ok;
+        ok = check<7168, 16, C>(rng, tol) && ok;
+    }
     return ok;
 }
 
