@@ -552,6 +552,16 @@ int lpide_ps_apply_B(void* plan, const double* v, double* bv);
  * stream (the stopping rule is read back between batches of steps). */
 int lpide_ps_solve_steps(void* plan, int32_t steps, double* v_out);
 
+/* Delta and Gamma surfaces of a price-space grid at the nodes by the
+ * difference schemes of D (Sec. 3.2.1; the paper plots them in Sec. 4):
+ * delta_i = D1 along axis i, gamma_ii = D2 along axis i, gamma_12 = D1 along
+ * both axes, with the coefficients of Sec. 3.2.1 (central three-point on the
+ * nonuniform grid; zero on the x_i = 0 rows; at x_max the backward first
+ * difference and no second derivative).  v: device, (N_x+1)^2; out: device,
+ * 5 (N_x+1)^2 FP64, caller-owned, must not alias v: delta1, delta2, gamma11,
+ * gamma12, gamma22.  Enqueued on the plan's stream. */
+int lpide_ps_greeks(void* plan, const double* v, double* out);
+
 /* Prices at npts spot pairs by tensor-product cubic Lagrange interpolation in
  * x (stencils of the four nearest nodes): spots[2k], spots[2k+1] = (S1, S2),
  * price[k].  Device pointers; npts = 0 reads and writes nothing. */

@@ -284,6 +284,22 @@ class PriceSpaceProblem:
         return np.array(out)
 
 
+def greeks(x, V):
+    """Delta and Gamma surfaces on the price grid by the difference schemes of
+    D (Sec. 3.2.1; the paper plots them in Sec. 4): Delta_i = D1 along axis i,
+    Gamma_ii = D2 along axis i, Gamma_12 = D1 along both axes, with D1, D2 of
+    fd_matrices (their rows at x = 0 and, for D2, at x_max are zero).  Returns
+    (delta1, delta2, gamma11, gamma12, gamma22), each (N_x+1) x (N_x+1)."""
+    D1, D2 = fd_matrices(np.asarray(x, dtype=np.float64))
+    V = np.asarray(V, dtype=np.float64)
+    d1 = np.asarray(D1 @ V)                       # axis 1 (rows, m1)
+    d2 = np.asarray((D1 @ V.T).T)                 # axis 2 (columns, m2)
+    g11 = np.asarray(D2 @ V)
+    g22 = np.asarray((D2 @ V.T).T)
+    g12 = np.asarray(D1 @ d2)                     # D1 along axis 1 of D1 along axis 2
+    return d1, d2, g11, g12, g22
+
+
 def _cell_avg_put_avg(K, a1, b1, a2, b2, nq=8):
     """(1 / cell area) * integral over [a1, b1] x [a2, b2] of max(K - (x1 + x2)/2, 0):
     the inner integral in x2 in closed form, the outer one by Gauss-Legendre on

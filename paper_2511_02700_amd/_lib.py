@@ -157,6 +157,7 @@ SIGNATURES = {
     "lpide_ps_apply_B": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lpide_ps_solve_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "lpide_ps_price": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "lpide_ps_greeks": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 _lib = None

@@ -433,6 +433,14 @@ class PsPlan:
     def solve(self, out=None):
         return self.solve_steps(self.info()["n_steps"], out)
 
+    def greeks(self, v):
+        """Delta and Gamma surfaces (5, n, n): delta1, delta2, gamma11, gamma12, gamma22."""
+        torch = _torch()
+        v = v.to(self.device, torch.float64).contiguous()
+        out = torch.empty((5, self.n, self.n), dtype=torch.float64, device=self.device)
+        check(lib().lpide_ps_greeks(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(out.data_ptr())))
+        return out
+
     def price(self, v, spots):
         torch = _torch()
         sp = torch.as_tensor(spots, dtype=torch.float64).reshape(-1, 2).to(self.device).contiguous()

@@ -78,6 +78,8 @@ struct PsPlan {
     PsOps ops{};
     PsConv conv{};
     double* x_d = nullptr;
+    double* D1c = nullptr;          // difference coefficients (Greeks)
+    double* D2c = nullptr;
     double* V0 = nullptr;
     double* pool[POOLN] = {};
     double* Wb[2] = {};
@@ -264,7 +266,7 @@ int create(const lpide_ps_grid* g, const lpide_levy* lv, const lpide_payoff* pay
     const size_t N = size_t(n) * n;
     double *A1 = nullptr, *A2 = nullptr;
     if ((rc = upload(p, &p->x_d, hp.x)) || (rc = upload(p, &p->V0, v0)) || (rc = upload(p, &A1, hp.A1)) ||
-        (rc = upload(p, &A2, hp.A2)))
+        (rc = upload(p, &A2, hp.A2)) || (rc = upload(p, &p->D1c, hp.D1c)) || (rc = upload(p, &p->D2c, hp.D2c)))
         return bail(rc);
     for (int b = 0; b < POOLN; ++b)
         if ((rc = dalloc(p, &p->pool[b], N))) return bail(rc);
@@ -708,6 +710,20 @@ int lpide_ps_solve_steps(void* plan, int32_t steps, double* v_out) {
     if (steps < 0 || steps > int32_t(p->steps.size()))
         return fail(LPIDE_E_PARAM, "steps must lie in [0, " + std::to_string(p->steps.size()) + "]");
     return lpide::ps::march(p, steps, v_out);
+}
+
+int lpide_ps_greeks(void* plan, const double* v, double* out) {
+    if (!plan || !v || !out) return fail(LPIDE_E_PARAM, "NULL argument");
+    PsPlan* p = lpide::ps::as_plan(plan);
+    const size_t N = size_t(p->hp.n) * p->hp.n;
+    if (static_cast<const void*>(v) == static_cast<const void*>(out)) return fail(LPIDE_E_PARAM, "v and out must not alias");
+    hipError_t e = hipSetDevice(p->opts.device);
+    if (e != hipSuccess) return fail(LPIDE_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    hipLaunchKernelGGL(lpide::ps::ps_greeks, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, p->stream, v, out, p->hp.n,
+                       (const double*)p->D1c, (const double*)p->D2c);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(LPIDE_E_HIP, std::string("lpide_ps_greeks: ") + hipGetErrorString(e));
+    return LPIDE_OK;
 }
 
 int lpide_ps_price(void* plan, const double* v, int32_t npts, const double* spots, double* price) {

@@ -128,22 +128,29 @@ bool build_ps_host(const lpide_ps_grid& g, const lpide_levy& lv, double K, PsHos
     // At x = 0 both derivative terms vanish with their x factors; at x_max the
     // second derivative is dropped (v linear there) and the first difference
     // is the backward one.
-    hp.A1.assign(size_t(3) * n, 0.0);
-    hp.A2.assign(size_t(3) * n, 0.0);
+    hp.D1c.assign(size_t(3) * n, 0.0);
+    hp.D2c.assign(size_t(3) * n, 0.0);
     for (int m = 1; m < n - 1; ++m) {
-        const double hm = hp.x[m] - hp.x[m - 1], hq = hp.x[m + 1] - hp.x[m], xm = hp.x[m];
-        hp.A1[3 * m + 0] = xm * (-hq / (hm * (hm + hq)));
-        hp.A1[3 * m + 1] = xm * ((hq - hm) / (hm * hq));
-        hp.A1[3 * m + 2] = xm * (hm / (hq * (hm + hq)));
-        hp.A2[3 * m + 0] = 0.5 * xm * xm * (2.0 / (hm * (hm + hq)));
-        hp.A2[3 * m + 1] = 0.5 * xm * xm * (-2.0 / (hm * hq));
-        hp.A2[3 * m + 2] = 0.5 * xm * xm * (2.0 / (hq * (hm + hq)));
+        const double hm = hp.x[m] - hp.x[m - 1], hq = hp.x[m + 1] - hp.x[m];
+        hp.D1c[3 * m + 0] = -hq / (hm * (hm + hq));
+        hp.D1c[3 * m + 1] = (hq - hm) / (hm * hq);
+        hp.D1c[3 * m + 2] = hm / (hq * (hm + hq));
+        hp.D2c[3 * m + 0] = 2.0 / (hm * (hm + hq));
+        hp.D2c[3 * m + 1] = -2.0 / (hm * hq);
+        hp.D2c[3 * m + 2] = 2.0 / (hq * (hm + hq));
     }
     {
         const double hl = hp.x[n - 1] - hp.x[n - 2];
-        hp.A1[3 * (n - 1) + 0] = hp.x[n - 1] * (-1.0 / hl);
-        hp.A1[3 * (n - 1) + 1] = hp.x[n - 1] * (1.0 / hl);
+        hp.D1c[3 * (n - 1) + 0] = -1.0 / hl;
+        hp.D1c[3 * (n - 1) + 1] = 1.0 / hl;
     }
+    hp.A1.assign(size_t(3) * n, 0.0);
+    hp.A2.assign(size_t(3) * n, 0.0);
+    for (int m = 0; m < n; ++m)
+        for (int t = 0; t < 3; ++t) {
+            hp.A1[3 * m + t] = hp.x[m] * hp.D1c[3 * m + t];
+            hp.A2[3 * m + t] = 0.5 * hp.x[m] * hp.x[m] * hp.D2c[3 * m + t];
+        }
 
     hp.r = lv.r;
     for (int k = 0; k < 3; ++k) hp.sbs[k] = lv.sigma_bs[k];

@@ -40,8 +40,9 @@ struct PsHost {
     int N_ym = 0, N_yp = 0, N_ystar = 0, n_in = 0, n_out = 0, n_nz = 0;
     std::vector<Cubic> tin;             // n_nz rows of T^in (per axis; both axes alike)
     std::vector<Cubic> tout;            // n rows of T^out; row 0 is the linear extrapolation to x = 0
-    // D (Sec. 3.2.1) per node m: A1[3m + t] = x_m d1_{m, m-1+t}, A2[3m + t] = x_m^2 d2_{m, m-1+t} / 2
-    std::vector<double> A1, A2;
+    // D (Sec. 3.2.1) per node m: A1[3m + t] = x_m d1_{m, m-1+t}, A2[3m + t] = x_m^2 d2_{m, m-1+t} / 2,
+    // and the difference coefficients themselves, D1c[3m + t] = d1_{m, m-1+t}, D2c[3m + t] = d2_{m, m-1+t}
+    std::vector<double> A1, A2, D1c, D2c;
 };
 
 // Limit fraction F of the grid points in [0, x_int] for the constant c (Sec. 4).

@@ -448,6 +448,42 @@ static __global__ __launch_bounds__(256) void ps_fill(double* __restrict__ a, si
     if (i < cnt) a[i] = v;
 }
 
+// Delta and Gamma surfaces by the difference schemes of D (Sec. 3.2.1):
+// out = [delta1, delta2, gamma11, gamma12, gamma22], each n x n; D1c, D2c hold
+// the three coefficients per node (zero where the scheme drops a term).
+static __global__ __launch_bounds__(256) void ps_greeks(const double* __restrict__ V, double* __restrict__ out,
+                                                        int n, const double* __restrict__ D1c,
+                                                        const double* __restrict__ D2c) {
+    const size_t N = (size_t)n * n;
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= N) return;
+    const int i = int(idx / n), j = int(idx % n);
+    const int ii[3] = {i > 0 ? i - 1 : 0, i, i < n - 1 ? i + 1 : n - 1};
+    const int jj[3] = {j > 0 ? j - 1 : 0, j, j < n - 1 ? j + 1 : n - 1};
+    const double* a1 = D1c + 3 * i;
+    const double* b1 = D2c + 3 * i;
+    const double* a2 = D1c + 3 * j;
+    const double* b2 = D2c + 3 * j;
+    double d1 = 0.0, d2 = 0.0, g11 = 0.0, g12 = 0.0, g22 = 0.0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const double vi = V[(size_t)ii[t] * n + j], vj = V[(size_t)i * n + jj[t]];
+        d1 += a1[t] * vi;
+        g11 += b1[t] * vi;
+        d2 += a2[t] * vj;
+        g22 += b2[t] * vj;
+        double r = 0.0;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) r += a2[u] * V[(size_t)ii[t] * n + jj[u]];
+        g12 += a1[t] * r;
+    }
+    out[idx] = d1;
+    out[N + idx] = d2;
+    out[2 * N + idx] = g11;
+    out[3 * N + idx] = g12;
+    out[4 * N + idx] = g22;
+}
+
 // Prices at spot pairs: tensor-product cubic Lagrange on the four nearest
 // nodes of each axis (stencil start clamp(j - 1, 0, n - 4), x_j <= S < x_{j+1}).
 __device__ __forceinline__ int ps_stencil(const double* __restrict__ x, int n, double t, double* w) {

@@ -242,3 +242,22 @@ def test_table3_on_the_papers_grid(lp, name, L):
         name, info["n_in"], info["L"], plan.info()["total_iters"], info["n_steps"], err))
     assert info["L"] == L
     assert err < 1e-4
+
+
+def test_greeks_match_oracle(lp):
+    """The Delta and Gamma surfaces (the paper's schemes of Sec. 3.2.1, plotted in
+    Sec. 4) of a GPU march, against the oracle's stencils on the same grid:
+    within 1e-12 of each surface's largest value; and a put on the average has
+    -1/2 <= Delta_i <= 0 at every node."""
+    import torch
+    from oracle import price_space as ps
+    plan = _gpu_plan(lp, "VG1", 32, tol=1e-11)
+    V = plan.solve()
+    g = plan.greeks(V).cpu().numpy()
+    want = ps.greeks(plan.nodes(), V.cpu().numpy())
+    for q, name in enumerate(("delta1", "delta2", "gamma11", "gamma12", "gamma22")):
+        err = float(np.max(np.abs(g[q] - want[q]))) / float(np.max(np.abs(want[q])))
+        _note("VG1 N_x=32 %s: %.2e" % (name, err))
+        assert err < 1e-12
+    assert float(g[:2].max()) <= 1e-12 and float(g[:2].min()) >= -0.5 - 1e-9
+    assert torch.isfinite(torch.from_numpy(g)).all()

@@ -204,3 +204,45 @@ def test_table3_reached_at_second_order(name):
         V, _ = ps.solve(prob, tol=1e-10)
         errs.append(float(np.max(np.abs(prob.prices(V, spots) - want))))
     assert errs[1] < 0.08 and math.log2(errs[0] / errs[1]) > 1.8, errs
+
+
+def test_greeks_exact_on_quadratics():
+    """The Greek stencils are those of D (Sec. 3.2.1): exact for quadratics at
+    the inner nodes; on the x_i = 0 rows the derivatives in x_i are zero by the
+    scheme's convention, on the x_max rows Gamma in x_i is zero and Delta is the
+    backward difference (exact for the linear part)."""
+    x, _ = ps.x_grid(30, 100.0, 500.0)
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    u = 3.0 + 0.5 * X1 - 0.2 * X2 + 1e-3 * X1 ** 2 - 2e-3 * X1 * X2 + 3e-3 * X2 ** 2
+    d1, d2, g11, g12, g22 = ps.greeks(x, u)
+    inner = (slice(1, -1), slice(1, -1))
+    assert np.allclose(d1[inner], (0.5 + 2e-3 * X1 - 2e-3 * X2)[inner], rtol=1e-10, atol=1e-10)
+    assert np.allclose(d2[inner], (-0.2 - 2e-3 * X1 + 6e-3 * X2)[inner], rtol=1e-10, atol=1e-10)
+    assert np.allclose(g11[inner], 2e-3, rtol=1e-9) and np.allclose(g22[inner], 6e-3, rtol=1e-9)
+    assert np.allclose(g12[inner], -2e-3, rtol=1e-9)
+    assert np.all(d1[0, :] == 0.0) and np.all(g11[0, :] == 0.0) and np.all(g11[-1, :] == 0.0)
+    lin = 3.0 + 0.5 * X1 - 0.2 * X2
+    assert np.allclose(ps.greeks(x, lin)[0][-1, :], 0.5, rtol=1e-12)
+
+
+def test_greeks_black_scholes_put_price_space():
+    """Zero Levy measure, put on asset 1: Delta_1 and Gamma_11 of the price-space
+    march at the nodes near the money approach the Black-Scholes put Delta and
+    Gamma at second order (and do not depend on x_2).  Measured: Delta 6.1e-3,
+    1.5e-3, 3.7e-4 and Gamma 1.6e-4, 3.9e-5, 1.2e-5 at N_x = 32, 64, 128."""
+    from closed_forms import bs_put_delta_gamma
+    s1 = 0.25
+    cov = np.array([[s1 * s1, 0.02], [0.02, 0.04]])
+    errs = []
+    for N in (32, 64):
+        prob = ps.PriceSpaceProblem(None, N, 100.0, 500.0, 1.0, N // 2, 0.03, payoff="put_1", sigma_bs=cov)
+        V, _ = ps.solve(prob, tol=1e-12)
+        d1, _, g11, _, _ = ps.greeks(prob.x, V)
+        sel = [m for m in range(len(prob.x)) if 80.0 <= prob.x[m] <= 125.0]
+        e = 0.0
+        for m in sel:
+            dlt, gam = bs_put_delta_gamma(prob.x[m], 100.0, 1.0, 0.03, s1)
+            e = max(e, abs(d1[m, 5] - dlt), 100.0 * abs(g11[m, 5] - gam))
+            assert np.allclose(d1[m, 1:-1], d1[m, 5], rtol=0, atol=1e-9)
+        errs.append(e)
+    assert errs[1] < 5e-3 and math.log2(errs[0] / errs[1]) > 1.7, errs
