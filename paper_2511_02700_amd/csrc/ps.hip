@@ -348,8 +348,10 @@ int create(const lpide_ps_grid* g, const lpide_levy* lv, const lpide_payoff* pay
     p->conv.o = op;
     if ((rc = make_kinds(p))) return bail(rc);
     if (int(p->steps.size()) > p->N_t + 8) return bail(fail(LPIDE_E_PARAM, "step list longer than expected"));
-    p->P_rows = chunks_for(n, 16, 8);
-    p->P_cols = chunks_for(n, 16, 16);
+    // chunks of at most 4 elements per line-solve thread: at N_x = 400 the row
+    // solves then run 201 workgroups instead of 51 (march 9% faster than with 16)
+    p->P_rows = chunks_for(n, 4, 8);
+    p->P_cols = chunks_for(n, 4, 16);
     if ((n + p->P_rows - 1) / p->P_rows > LINE_MM || (n + p->P_cols - 1) / p->P_cols > LINE_MM)
         return bail(fail(LPIDE_E_PARAM, "N_x too large for the line solves"));
     hipLaunchKernelGGL(ps_ctl_reset, dim3(1), dim3(1), 0, p->stream, p->ctl, 1);
