@@ -240,6 +240,39 @@ __global__ __launch_bounds__(L / E) void ks_cols(const MarchArgs* __restrict__ A
 template <int L, int E>
 __global__ __launch_bounds__(L / E) void ks_rows_fwd(const MarchArgs* __restrict__ A);
 
+// The packed spectrum of the row pair (ra, ra+1) from the transposed half
+// spectra, into the canonical registers: z[k] = X_a[k] + i X_b[k] for k <= L/2
+// and z[L-k] = conj(X_a[k]) + i conj(X_b[k]) (imaginary parts dropped at DC and
+// Nyquist).  Item idx is frequency (idx >> 1) of row ra + (idx & 1), so a lane
+// pair reads the 32 contiguous bytes of one frequency once; the pair swaps its
+// values, the even lane forms z[k], the odd one z[L-k], and both go through LDS
+// to the canonical layout.
+template <int L, int E, typename C>
+__device__ __forceinline__ void rows_inv_gather(C (&reg)[E], C* lds, const C* __restrict__ X, int n, int ra,
+                                                bool hasb) {
+    constexpr int T = L / E, NI = (L + 2 + T - 1) / T;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int idx = tid + it * T;
+        const int kk = idx >> 1, r = idx & 1;
+        const bool in = kk <= L / 2;
+        const C v = (in && (r == 0 || hasb)) ? X[(size_t)kk * n + ra + r] : CplxOps<C>::make(0, 0);
+        // every lane of the wave takes part in the swap (pairs never straddle the range end)
+        const C u = CplxOps<C>::make(__shfl_xor(v.x, 1), __shfl_xor(v.y, 1));
+        const bool real_bin = kk == 0 || kk == L / 2;
+        const C ta = r == 0 ? v : u, tb = r == 0 ? u : v;
+        const C ha = CplxOps<C>::make(ta.x, real_bin ? 0 : ta.y);
+        const C hb = CplxOps<C>::make(tb.x, real_bin ? 0 : tb.y);
+        if (in && r == 0) lds[lds_slot(kk)] = CplxOps<C>::make(ha.x - hb.y, ha.y + hb.x);
+        if (in && r == 1 && kk > 0 && kk < L / 2)
+            lds[lds_slot(L - kk)] = CplxOps<C>::make(ha.x + hb.y, hb.x - ha.y);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) reg[e] = lds[lds_slot(tid + e * T)];
+}
+
 // Row inverse FFT of the pairs (2p, 2p+1) with a fused epilogue.
 // MODE 0 (once per step, FP64): E = V + dt(1-theta)((D - r_omega) V + B V) into R
 //         (theta < 1), and B V into BV (mixed form);
@@ -270,19 +303,7 @@ __global__ __launch_bounds__(L / E) void ks_rows_inv(const MarchArgs* __restrict
     const int tid = threadIdx.x;
     const C* X = xbuf<C>(a);
     C reg[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int idx = tid + e * T;
-        const bool lo = idx <= L / 2;
-        const int kk = lo ? idx : L - idx;
-        const C* xk = X + (size_t)kk * n;
-        const bool real_bin = kk == 0 || kk == L / 2;  // imaginary parts dropped at DC and Nyquist
-        const C ta = xk[ra];
-        const C tb = hasb ? xk[rb] : CplxOps<C>::make(0, 0);
-        const C ha = CplxOps<C>::make(ta.x, real_bin ? 0 : ta.y);
-        const C hb = CplxOps<C>::make(tb.x, real_bin ? 0 : tb.y);
-        reg[e] = lo ? CplxOps<C>::make(ha.x - hb.y, ha.y + hb.x) : CplxOps<C>::make(ha.x + hb.y, hb.x - ha.y);
-    }
+    rows_inv_gather<L, E>(reg, lds, X, n, ra, hasb);
     fft_block<L, E, true>(reg, lds, tw4);
     // FP64 iterations store B Y of the iterate for the start of later steps
     double* Bout = nullptr;
@@ -495,18 +516,20 @@ __device__ __forceinline__ void rows_fwd_store(C (&reg)[E], C* lds, const double
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[tid + e * T] = reg[e];
     __syncthreads();
-    for (int kk = tid; kk <= L / 2; kk += T) {
+    // item idx = frequency (idx >> 1) of row ra + (idx & 1): the two rows of a
+    // frequency are adjacent in X, so a lane pair stores them as one 32-byte piece
+    constexpr int NI = (L + 2 + T - 1) / T;
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int idx = tid + it * T;
+        const int kk = idx >> 1, r = idx & 1;
+        if (kk > L / 2 || (r == 1 && !hasb)) continue;
         const C z = lds[kk], w = lds[kk == 0 ? 0 : L - kk];
-        const C va = CplxOps<C>::make(Rl(0.5) * (z.x + w.x), Rl(0.5) * (z.y - w.y));
-        const C vb = CplxOps<C>::make(Rl(0.5) * (z.y + w.y), Rl(-0.5) * (z.x - w.x));
-        C* xk = X + (size_t)kk * n;
-        xk[ra] = va;
-        if (hasb) xk[ra + 1] = vb;
-        if (X2) {
-            C* x2 = X2 + (size_t)kk * n;
-            x2[ra] = va;
-            if (hasb) x2[ra + 1] = vb;
-        }
+        const C v = r == 0 ? CplxOps<C>::make(Rl(0.5) * (z.x + w.x), Rl(0.5) * (z.y - w.y))
+                           : CplxOps<C>::make(Rl(0.5) * (z.y + w.y), Rl(-0.5) * (z.x - w.x));
+        const size_t o = (size_t)kk * n + ra + r;
+        X[o] = v;
+        if (X2) X2[o] = v;
     }
 }
 
