@@ -518,7 +518,8 @@ bool initial_values(const HostPlan& hp, const lpide_payoff& pay, std::vector<dou
     return true;
 }
 
-// Thomas factors of the tridiagonal matrix with rows (sub[j], dia[j], up[j]).
+// Thomas factors of the tridiagonal matrix with rows (sub[j], dia[j], up[j]),
+// each followed by kLinePad zeros.
 void thomas_factors(const std::vector<double>& sub, const std::vector<double>& dia, const std::vector<double>& up,
                     std::vector<double>& fl, std::vector<double>& bu, std::vector<double>& bc) {
     const int n = int(dia.size());
@@ -539,6 +540,9 @@ void thomas_factors(const std::vector<double>& sub, const std::vector<double>& d
         bu[j] = 1.0 / d[j];
         bc[j] = -up[j] / d[j];
     }
+    fl.resize(n + kLinePad, 0.0);
+    bu.resize(n + kLinePad, 0.0);
+    bc.resize(n + kLinePad, 0.0);
 }
 
 namespace {

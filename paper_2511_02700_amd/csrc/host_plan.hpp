@@ -63,8 +63,14 @@ void small_jump_cov(const Nts& p, double half, double S[3]);
 void drift_and_rate(const std::vector<double>& omega, double h, int N_z, double r, double* sum_omega,
                     double kappa[2], double* r_omega);
 
+// Zeros after the n factors of each array: the chunked device solves read their
+// factors up to kLinePad - 1 elements past the end of a chunk without testing
+// the index (at least the chunk capacity of the device solves).
+constexpr int kLinePad = 32;
+
 // Thomas factors of the tridiagonal matrix with rows (sub[j], dia[j], up[j]):
-// forward multipliers fl, backward scales bu and couplings bc.
+// forward multipliers fl, backward scales bu and couplings bc, each of length
+// n + kLinePad (the last kLinePad zero).
 void thomas_factors(const std::vector<double>& sub, const std::vector<double>& dia, const std::vector<double>& up,
                     std::vector<double>& fl, std::vector<double>& bu, std::vector<double>& bc);
 

@@ -93,6 +93,9 @@ bool KTime::events(hipEvent_t* a, hipEvent_t* b) {
 using namespace lpide;
 using namespace lpide::detail;
 
+// the chunked line solves read up to LINE_MM - 1 factors past a line (its zero tail)
+static_assert(LINE_MM <= kLinePad, "factor arrays need a tail of at least the chunk capacity");
+
 // First-difference weights at index i of a line of n >= 3 nodes (spacing h):
 // central inside, second-order one-sided on the two ends; nodes p[0..2].
 __device__ __forceinline__ void d1_weights(int i, int n, double h, int* p, double* w) {

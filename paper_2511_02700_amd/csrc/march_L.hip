@@ -41,16 +41,19 @@ void launch_rows_fwd(Plan* p, const double* Y, hipStream_t s) {
 }
 
 // The axis-1 line-solve kernel for the launch's columns per block; bounds of
-// 256 threads where the block fits (no register cap of 128).
+// 256 threads where the block fits (no register cap of 128), and a chunk
+// capacity of 16 where every chunk fits (the chunks of the largest plan hold
+// ceil(n / P_cols) <= ceil(xcols cpb / P_cols) rows).
 template <typename Go>
 void with_line_cols(const Launch& c, Go&& go) {
     const bool small = c.cpb * c.P_cols <= 256;
+    const bool short_chunks = (c.xcols * c.cpb + c.P_cols - 1) / c.P_cols <= 16;
     if (c.cpb == 2) {
-        if (small) go(ks_line_cols<2, 256>);
-        else go(ks_line_cols<2, 1024>);
+        if (small) short_chunks ? go(ks_line_cols<2, 256, 16>) : go(ks_line_cols<2, 256, LINE_MM>);
+        else short_chunks ? go(ks_line_cols<2, 1024, 16>) : go(ks_line_cols<2, 1024, LINE_MM>);
     } else {
-        if (small) go(ks_line_cols<4, 256>);
-        else go(ks_line_cols<4, 1024>);
+        if (small) short_chunks ? go(ks_line_cols<4, 256, 16>) : go(ks_line_cols<4, 256, LINE_MM>);
+        else short_chunks ? go(ks_line_cols<4, 1024, 16>) : go(ks_line_cols<4, 1024, LINE_MM>);
     }
 }
 

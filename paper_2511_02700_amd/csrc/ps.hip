@@ -24,6 +24,8 @@
 #include "ps_big.hpp"
 #include "ps_plan.hpp"
 
+static_assert(lpide::LINE_MM <= lpide::kLinePad, "factor arrays need a tail of at least the chunk capacity");
+
 namespace lpide {
 namespace detail {
 int fail(int code, const std::string& msg);
@@ -389,10 +391,13 @@ void iteration(PsPlan* p, const Kind& kd, double* Y, const double* W, int k) {
     const double tol = p->opts.tol;
     if (p->jumps) bapply(p, p->conv, Y, k);
     const int lpb = 256 / p->P_rows;
-    hipLaunchKernelGGL(ps_resid_rows, dim3((n + lpb - 1) / lpb), dim3(256), 0, p->stream, (const double*)Y, W,
+    // chunk capacity 8 where every chunk fits (the plan's chunks hold at most 4 up to n = 1024)
+    auto rows = (n + p->P_rows - 1) / p->P_rows <= 8 ? ps_resid_rows<8> : ps_resid_rows<LINE_MM>;
+    auto cols = (n + p->P_cols - 1) / p->P_cols <= 8 ? ps_line_cols<8> : ps_line_cols<LINE_MM>;
+    hipLaunchKernelGGL(rows, dim3((n + lpb - 1) / lpb), dim3(256), 0, p->stream, (const double*)Y, W,
                        p->jumps ? (const double*)p->conv.Z : (const double*)nullptr, p->Q, p->ops, kd.sk, p->P_rows,
                        (const PsCtl*)p->ctl, k, tol);
-    hipLaunchKernelGGL(ps_line_cols, dim3((n + 3) / 4), dim3(4 * p->P_cols), 0, p->stream, (const double*)p->Q, Y,
+    hipLaunchKernelGGL(cols, dim3((n + 3) / 4), dim3(4 * p->P_cols), 0, p->stream, (const double*)p->Q, Y,
                        p->ops, kd.sk, p->P_cols, p->ctl, k, tol);
 }
 

@@ -267,9 +267,10 @@ __global__ __launch_bounds__(L / ps_e(L)) void ps_rows_inv(const double2* __rest
 
 // Residual of the step equation on grid rows and the axis-2 solve:
 // Q = T_2^{-1} (W - Y + c (D Y + B Y - r_omega Y)).  256 threads: 256 / P rows
-// per block, P chunks per row (P a power of two, n <= LINE_MM P).  Z = nullptr:
+// per block, P chunks per row (P a power of two, n <= MM P).  Z = nullptr:
 // no jumps (B = 0).
-static __global__ __launch_bounds__(256) void ps_resid_rows(const double* __restrict__ Y,
+template <int MM>
+__global__ __launch_bounds__(256) void ps_resid_rows(const double* __restrict__ Y,
                                                             const double* __restrict__ W,
                                                             const double* __restrict__ Z, double* __restrict__ Q,
                                                             PsOps o, PsStepK sk, int P, const PsCtl* ctl, int k,
@@ -282,9 +283,9 @@ static __global__ __launch_bounds__(256) void ps_resid_rows(const double* __rest
     const int mlen = (n + P - 1) / P;
     const int s = t * mlen;
     const int cnt = i < n ? max(0, min(mlen, n - s)) : 0;
-    double x[LINE_MM];
+    double x[MM];
 #pragma unroll
-    for (int q = 0; q < LINE_MM; ++q) {
+    for (int q = 0; q < MM; ++q) {
         x[q] = 0.0;
         if (q < cnt) {
             const int j = s + q;
@@ -294,16 +295,18 @@ static __global__ __launch_bounds__(256) void ps_resid_rows(const double* __rest
             x[q] = W[o_] - y + sk.c * (ps_DY(Y, o, i, j) + by - o.r_omega * y);
         }
     }
-    chunk_solve(x, s, cnt, g, t, P, 1, sk.fl2, sk.bu2, sk.bc2, wtot);
+    chunk_solve<MM>(x, s, cnt, g, t, P, 1, sk.fl2, sk.bu2, sk.bc2, wtot);
 #pragma unroll
-    for (int q = 0; q < LINE_MM; ++q)
+    for (int q = 0; q < MM; ++q)
         if (q < cnt) Q[(size_t)i * n + s + q] = x[q];
 }
 
 // Axis-1 solve of 4 adjacent columns (P chunks each, 4 P threads, P >= 16),
 // the update Y += delta and the block maximum of |delta| / max(1, |Y|) into
 // err[k] (non-negative doubles order like their bit patterns; NaN above inf).
-static __global__ __launch_bounds__(1024) void ps_line_cols(const double* __restrict__ Q, double* __restrict__ Y,
+// MM: chunk capacity (at least ceil(n / P)).
+template <int MM>
+__global__ __launch_bounds__(1024) void ps_line_cols(const double* __restrict__ Q, double* __restrict__ Y,
                                                             PsOps o, PsStepK sk, int P, PsCtl* ctl, int k,
                                                             double tol) {
     if (ps_halted(ctl, k, tol)) return;
@@ -315,13 +318,13 @@ static __global__ __launch_bounds__(1024) void ps_line_cols(const double* __rest
     const int mlen = (n + P - 1) / P;
     const int s = t * mlen;
     const int cnt = col < n ? max(0, min(mlen, n - s)) : 0;
-    double x[LINE_MM];
+    double x[MM];
 #pragma unroll
-    for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? Q[(size_t)(s + q) * n + col] : 0.0;
-    chunk_solve(x, s, cnt, c, t, P, 4, sk.fl1, sk.bu1, sk.bc1, wtot);
+    for (int q = 0; q < MM; ++q) x[q] = q < cnt ? Q[(size_t)(s + q) * n + col] : 0.0;
+    chunk_solve<MM>(x, s, cnt, c, t, P, 4, sk.fl1, sk.bu1, sk.bc1, wtot);
     double emax = 0.0;
 #pragma unroll
-    for (int q = 0; q < LINE_MM; ++q) {
+    for (int q = 0; q < MM; ++q) {
         if (q < cnt) {
             const size_t o_ = (size_t)(s + q) * n + col;
             const double y = Y[o_] + x[q];

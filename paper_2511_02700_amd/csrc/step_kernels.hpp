@@ -651,7 +651,8 @@ __global__ __launch_bounds__(L / E) void ks_sl(const MarchArgs* __restrict__ A) 
 
 // Axis-1 line solves R <- T_1^{-1} R: CPB adjacent columns x P chunks per block
 // (thread = column + CPB * chunk); launched with CPB * P <= MAXT threads.
-template <int CPB, int MAXT>
+// MM: chunk capacity (at least ceil(n / P_cols)).
+template <int CPB, int MAXT, int MM>
 __global__ __launch_bounds__(MAXT) void ks_line_cols(const MarchArgs* __restrict__ A, int k) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, k)) return;
@@ -665,12 +666,12 @@ __global__ __launch_bounds__(MAXT) void ks_line_cols(const MarchArgs* __restrict
     const int s = t * m;
     const int cnt = col < n ? max(0, min(m, n - s)) : 0;
     const StepDesc& sd = cur_set(a);
-    double x[LINE_MM];
+    double x[MM];
 #pragma unroll
-    for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? a.R[(size_t)(s + q) * n + col] : 0.0;
-    chunk_solve(x, s, cnt, c, t, P, CPB, sd.fl1, sd.bu1, sd.bc1, sbuf);
+    for (int q = 0; q < MM; ++q) x[q] = q < cnt ? a.R[(size_t)(s + q) * n + col] : 0.0;
+    chunk_solve<MM>(x, s, cnt, c, t, P, CPB, sd.fl1, sd.bu1, sd.bc1, sbuf);
 #pragma unroll
-    for (int q = 0; q < LINE_MM; ++q)
+    for (int q = 0; q < MM; ++q)
         if (q < cnt) a.R[(size_t)(s + q) * n + col] = x[q];
 }
 
@@ -689,11 +690,6 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
     // union: row buffer 2 (n + PR + 1) doubles (n <= L) | scan totals | FFT exchange buffer
     __shared__ double2 lds[L + (PR > L / 16 ? PR : L / 16) + 2];
     __shared__ double2 tw4[FFT ? tw_slots<L, E>() : 1];
-    // Up to L = 1024 the line factors are staged in LDS, so that every global
-    // read of the kernel is issued before the first barrier (at these sizes a
-    // block's time is mostly the latency of dependent global reads).
-    constexpr bool PF = L <= 1024;
-    __shared__ double fac[PF ? 3 * L : 1];
     if constexpr (FFT) load_twiddles<L, E>(a.tw, tw4);
     double* rows = reinterpret_cast<double*>(lds);
     const int ra = 2 * p, rb = 2 * p + 1;
@@ -713,19 +709,13 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
         yoa[e] = j < n ? Y[(size_t)ra * n + j] : 0.0;
         yob[e] = (j < n && hasb) ? Y[(size_t)rb * n + j] : 0.0;
     }
-    if constexpr (PF) {
-        for (int i = tid; i < n; i += T) {
-            fac[i] = sd.fl2[i];
-            fac[L + i] = sd.bu2[i];
-            fac[2 * L + i] = sd.bc2[i];
-        }
-    }
     // each thread reads its chunk of the residual row straight from memory: the
     // chunks of consecutive lanes are adjacent, so the reads stay coalesced
     const int r = tid / PR, ch = tid % PR;
     const int s = ch * m;
     const int cnt = (r == 1 && !hasb) ? 0 : max(0, min(m, n - s));
-    double x[LINE_MM];
+    constexpr int MM = 2 * E;             // n <= L = 2 E PR: chunks of at most 2E elements
+    double x[MM];
     {
         const double* Rr = a.R + (size_t)(r == 0 ? ra : rb) * n + s;
         if (((n | m) & 1) == 0) {
@@ -734,21 +724,19 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
             // instructions and addresses of element-wise reads)
             const double2* R2 = reinterpret_cast<const double2*>(Rr);
 #pragma unroll
-            for (int q = 0; q < LINE_MM / 2; ++q) {
+            for (int q = 0; q < MM / 2; ++q) {
                 const double2 v = 2 * q < cnt ? R2[q] : make_double2(0.0, 0.0);
                 x[2 * q] = v.x;
                 x[2 * q + 1] = v.y;
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < LINE_MM; ++q) x[q] = q < cnt ? Rr[q] : 0.0;
+            for (int q = 0; q < MM; ++q) x[q] = q < cnt ? Rr[q] : 0.0;
         }
     }
-    __syncthreads();                      // staged factors visible
-    if constexpr (PF) chunk_solve(x, s, cnt, r, ch, PR, 1, fac, fac + L, fac + 2 * L, lds);
-    else chunk_solve(x, s, cnt, r, ch, PR, 1, sd.fl2, sd.bu2, sd.bc2, lds);
+    chunk_solve<MM>(x, s, cnt, r, ch, PR, 1, sd.fl2, sd.bu2, sd.bc2, lds);
 #pragma unroll
-    for (int q = 0; q < LINE_MM; ++q)
+    for (int q = 0; q < MM; ++q)
         if (q < cnt) rows[r * stride + s + q + ch] = x[q];
     __syncthreads();
     double emax = 0.0;
