@@ -145,6 +145,15 @@ typedef struct {
                              The first steps of a march, whose grids did not come from it,
                              and steps after theta = 0 use the correlation.  1: every
                              product by the correlation, as Algorithm 1 reads. */
+    int32_t accel;        /* price-space plan only (the log plan requires 0): acceleration of
+                             the fixed-point iteration of Sec. 3.3.  0: the paper's iteration
+                             Y^k = Y^{k-1} + delta^k.  1..6: Anderson mixing of that depth,
+                             Y^k = Y^{k-1} + delta^k - sum_i gamma_i (dY_i + dF_i) with gamma
+                             the least-squares fit of delta^k by the step's last differences
+                             of increments dF (dY: of iterates); same fixed point and stopping
+                             rule, fewer iterations where the iteration contracts slowly.
+                             -1: depth 4 when the predicted contraction h_t theta sum_omega /
+                             (1 + h_t theta sum_omega) of the main steps exceeds 0.3, else 0. */
 } lpide_opts;
 
 /* Plan-time quantities and run statistics. */
@@ -502,6 +511,7 @@ typedef struct {
     int32_t max_step_iters;
     double  last_increment;           /* last stopping-rule value of the last march */
     int64_t device_bytes;
+    int32_t accel_depth;              /* Anderson depth in use (0: the paper's iteration) */
 } lpide_ps_info;
 
 /* The paper's settings on N_x intervals over [0, x_max]: x_int = 5K/2,

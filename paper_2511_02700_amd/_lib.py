@@ -36,7 +36,7 @@ class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
                 ("damping", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p), ("fft_radix", C.c_int32),
                 ("fft_size", C.c_int32), ("mixed_anchor", C.c_int32),
-                ("all_correlations", C.c_int32)]
+                ("all_correlations", C.c_int32), ("accel", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -95,7 +95,7 @@ class PsInfo(C.Structure):
                 ("h_z", C.c_double), ("z_star", C.c_double), ("sum_omega", C.c_double),
                 ("kappa", C.c_double * 2), ("r_omega", C.c_double), ("S", C.c_double * 3), ("a", C.c_double * 3),
                 ("total_iters", C.c_int64), ("max_step_iters", C.c_int32), ("last_increment", C.c_double),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("accel_depth", C.c_int32)]
 
     def to_dict(self):
         out = {}

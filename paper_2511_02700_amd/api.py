@@ -362,13 +362,16 @@ class PsPlan:
     """A price-space plan on one HIP device (see lpide_ps_plan_create)."""
 
     def __init__(self, grid, levy, payoff, theta=0.5, N_t=None, tol=1e-10, max_iter=128, damping=True, device=0,
-                 stream=None, fft_size=0, all_correlations=False):
+                 stream=None, fft_size=0, all_correlations=False, accel=-1):
+        """accel: 0 the paper's fixed-point iteration, 1..6 Anderson mixing of that depth,
+        -1 (default) depth 4 where the iteration is predicted to contract slowly."""
         torch = _torch()
         o = Opts()
         lib().lpide_opts_default(C.byref(o))
         o.tol, o.max_iter, o.damping, o.device = tol, max_iter, 1 if damping else 0, device
         o.fft_size = fft_size
         o.all_correlations = 1 if all_correlations else 0
+        o.accel = int(accel)
         if N_t is None:
             N_t = max(1, int(round(0.5 * grid.N_x)))     # Sec. 4: N_t = round(N_x / 2)
         self.device = torch.device("cuda", device)

@@ -440,10 +440,11 @@ Schedule default_schedule(int L) {
     if (fft_odd(L) == 3) {
         // the radix-3 stage favours many threads per transform in the row
         // passes; the column pass takes E = 8 at 1536 and 4 at 3072; the axis-2
-        // line solves want short chunks (E = 16 at 3072)
+        // line-row kernel E = 4 at 1536 (4% faster than 8 on a 1024^2 solve) and
+        // E = 16 at 3072 (fewest registers per chunk of the FFT's operands)
         s.cols = L == 1536 ? 8 : 4;
         s.rinv = 4;
-        s.lrows = supported_e(L, L >= 3072 ? 16 : 8);
+        s.lrows = supported_e(L, L >= 3072 ? 16 : 4);
         s.sl = 4;
         return s;
     }
@@ -1389,6 +1390,7 @@ int lpide_plan_create(const lpide_grid* grid, const lpide_levy* levy, const lpid
         return fail(LPIDE_E_PARAM, "fft_radix must be 0, 4, 8 or 16");
     if (o.mixed_anchor < 0) return fail(LPIDE_E_PARAM, "mixed_anchor must be >= 0");
     if (o.all_correlations != 0 && o.all_correlations != 1) return fail(LPIDE_E_PARAM, "all_correlations must be 0 or 1");
+    if (o.accel != 0) return fail(LPIDE_E_PARAM, "accel applies to the price-space plan only (0 here)");
     Plan* p = new Plan();
     std::string err;
     if (!build_host_plan(*grid, *levy, p->hp, err)) { delete p; return fail(LPIDE_E_PARAM, err); }

@@ -98,6 +98,8 @@ struct PsPlan {
     int64_t total_iters = 0;
     int max_step_iters = 0;
     double last_inc = 0.0;
+    int aa_m = 0;                   // Anderson depth (0: the paper's iteration)
+    PsAABufs aab{};
 };
 
 #define PS_TRY(call)                                                                                      \
@@ -226,6 +228,8 @@ int create(const lpide_ps_grid* g, const lpide_levy* lv, const lpide_payoff* pay
     if (o.max_iter < 1 || o.max_iter > PS_MAXK)
         return fail(LPIDE_E_PARAM, "max_iter must lie in [1, " + std::to_string(PS_MAXK) + "]");
     if (o.precision != LPIDE_FP64) return fail(LPIDE_E_PARAM, "the price-space plan computes in FP64 only");
+    if (o.accel < -1 || o.accel > PS_AA_MAX)
+        return fail(LPIDE_E_PARAM, "accel must lie in [-1, " + std::to_string(PS_AA_MAX) + "]");
     if (!(pay->K > 0.0) || !(pay->T > 0.0)) return fail(LPIDE_E_PARAM, "K and T must be positive");
     PsPlan* p = new PsPlan;
     std::string err;
@@ -278,6 +282,36 @@ int create(const lpide_ps_grid* g, const lpide_levy* lv, const lpide_payoff* pay
     {
         hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p->ctl_h), sizeof(PsCtl), hipHostMallocDefault);
         if (e != hipSuccess) { p->ctl_h = nullptr; return bail(fail(LPIDE_E_OOM, "hipHostMalloc ctl")); }
+    }
+    // Anderson mixing: the chosen depth, or depth 4 where the paper's iteration
+    // is predicted to contract slowly (factor c sum_omega / (1 + c sum_omega),
+    // c = h_t theta of the main steps)
+    p->aa_m = o.accel;
+    if (o.accel < 0) {
+        const double c = pay->T / N_t * theta, cs = c * hp.sum_omega;
+        p->aa_m = p->jumps && cs / (1.0 + cs) > 0.3 ? 4 : 0;
+    }
+    if (p->aa_m > 0) {
+        PsAABufs& b = p->aab;
+        b.m = p->aa_m;
+        b.nblk = int((N + PS_AA_T * PS_AA_EPT - 1) / (PS_AA_T * PS_AA_EPT));
+        double *Fp, *Yp, *dF, *dY, *part;
+        PsAA* st;
+        if ((rc = dalloc(p, &Fp, N)) || (rc = dalloc(p, &Yp, N)) || (rc = dalloc(p, &dF, size_t(b.m) * N)) ||
+            (rc = dalloc(p, &dY, size_t(b.m) * N)) || (rc = dalloc(p, &part, size_t(b.nblk) * 2 * b.m)) ||
+            (rc = dalloc(p, &st, 1)))
+            return bail(rc);
+        hipError_t e = hipMemset(dF, 0, size_t(b.m) * N * sizeof(double));
+        if (e == hipSuccess) e = hipMemset(dY, 0, size_t(b.m) * N * sizeof(double));
+        if (e == hipSuccess) e = hipMemset(st, 0, sizeof(PsAA));
+        if (e != hipSuccess) return bail(fail(LPIDE_E_HIP, std::string("hipMemset: ") + hipGetErrorString(e)));
+        b.F = p->Q;
+        b.Fp = Fp;
+        b.Yp = Yp;
+        b.dF = dF;
+        b.dY = dY;
+        b.part = part;
+        b.st = st;
     }
     PsOps& op = p->ops;
     op.n = n;
@@ -397,8 +431,18 @@ void iteration(PsPlan* p, const Kind& kd, double* Y, const double* W, int k) {
     hipLaunchKernelGGL(rows, dim3((n + lpb - 1) / lpb), dim3(256), 0, p->stream, (const double*)Y, W,
                        p->jumps ? (const double*)p->conv.Z : (const double*)nullptr, p->Q, p->ops, kd.sk, p->P_rows,
                        (const PsCtl*)p->ctl, k, tol);
-    hipLaunchKernelGGL(cols, dim3((n + 3) / 4), dim3(4 * p->P_cols), 0, p->stream, (const double*)p->Q, Y,
-                       p->ops, kd.sk, p->P_cols, p->ctl, k, tol);
+    const bool aa = p->aa_m > 0;
+    hipLaunchKernelGGL(cols, dim3((n + 3) / 4), dim3(4 * p->P_cols), 0, p->stream, p->Q, Y, p->ops, kd.sk,
+                       p->P_cols, p->ctl, k, tol, aa ? 1 : 0);
+    if (aa) {
+        const size_t N = size_t(n) * n;
+        const PsAABufs& b = p->aab;
+        hipLaunchKernelGGL(ps_aa_dots, dim3(b.nblk), dim3(PS_AA_T), 0, p->stream, (const double*)Y, b, N,
+                           (const PsCtl*)p->ctl, k, tol);
+        hipLaunchKernelGGL(ps_aa_solve, dim3(1), dim3(PS_AA_T), 0, p->stream, b, (const PsCtl*)p->ctl, k, tol);
+        hipLaunchKernelGGL(ps_aa_update, dim3(b.nblk), dim3(PS_AA_T), 0, p->stream, Y, b, N, (const PsCtl*)p->ctl,
+                           k, tol);
+    }
 }
 
 // Enqueue step s with kmax iterations; advances m.
@@ -670,6 +714,7 @@ int lpide_ps_plan_info(void* plan, lpide_ps_info* info) {
     info->max_step_iters = p->max_step_iters;
     info->last_increment = p->last_inc;
     info->device_bytes = p->bytes;
+    info->accel_depth = p->aa_m;
     return LPIDE_OK;
 }
 

@@ -302,13 +302,14 @@ __global__ __launch_bounds__(256) void ps_resid_rows(const double* __restrict__ 
 }
 
 // Axis-1 solve of 4 adjacent columns (P chunks each, 4 P threads, P >= 16),
-// the update Y += delta and the block maximum of |delta| / max(1, |Y|) into
-// err[k] (non-negative doubles order like their bit patterns; NaN above inf).
+// the update Y += delta (store_delta: delta back into Q instead, for Anderson
+// mixing) and the block maximum of |delta| / max(1, |Y + delta|) into err[k]
+// (non-negative doubles order like their bit patterns; NaN above inf).
 // MM: chunk capacity (at least ceil(n / P)).
 template <int MM>
-__global__ __launch_bounds__(1024) void ps_line_cols(const double* __restrict__ Q, double* __restrict__ Y,
-                                                            PsOps o, PsStepK sk, int P, PsCtl* ctl, int k,
-                                                            double tol) {
+__global__ __launch_bounds__(1024) void ps_line_cols(double* __restrict__ Q, double* __restrict__ Y, PsOps o,
+                                                     PsStepK sk, int P, PsCtl* ctl, int k, double tol,
+                                                     int store_delta) {
     if (ps_halted(ctl, k, tol)) return;
     __shared__ double2 wtot[256];
     __shared__ double wmax[16];
@@ -328,7 +329,8 @@ __global__ __launch_bounds__(1024) void ps_line_cols(const double* __restrict__ 
         if (q < cnt) {
             const size_t o_ = (size_t)(s + q) * n + col;
             const double y = Y[o_] + x[q];
-            Y[o_] = y;
+            if (store_delta) Q[o_] = x[q];        // each thread rewrites the elements it read
+            else Y[o_] = y;
             const double ev = fabs(x[q]) / fmax(1.0, fabs(y));
             emax = (ev > emax || ev != ev) ? ev : emax;
         }
@@ -345,6 +347,206 @@ __global__ __launch_bounds__(1024) void ps_line_cols(const double* __restrict__ 
         double b = wmax[0];
         for (int w = 1; w < nw; ++w) b = (wmax[w] > b || wmax[w] != wmax[w]) ? wmax[w] : b;
         atomicMax(&ctl->err[k], (unsigned long long)__double_as_longlong(b));
+    }
+}
+
+// Anderson mixing of the fixed-point iteration.  The paper iterates
+// Y_k = Y_{k-1} + delta_k with delta_k = T_1^{-1} T_2^{-1} r(Y_{k-1}) (Sec.
+// 3.3); mixing of depth m keeps that fixed point and stopping rule and takes
+//   Y_k = Y_{k-1} + delta_k - sum_i gamma_i (dY_i + dF_i),
+// gamma = argmin |delta_k - sum_i gamma_i dF_i|_2 over the last m difference
+// pairs dF = delta_j - delta_{j-1}, dY = Y_{j-1} - Y_{j-2} of the step's
+// iterations (a plain step at k = 1, when err_k already meets tol, and when
+// the small system is singular).  gamma solves the normal equations.
+constexpr int PS_AA_MAX = 6;          // largest depth
+constexpr int PS_AA_T = 256;          // threads of the grid-wide kernels
+constexpr int PS_AA_EPT = 4;          // elements per thread
+
+struct PsAA {
+    double G[PS_AA_MAX][PS_AA_MAX];   // Gram matrix of the dF columns, by ring slot
+    double gamma[PS_AA_MAX];          // coefficients of this iteration, by ring slot (0: unused)
+    int mk;                           // columns held (0..m)
+    int head;                         // ring slot of the newest column
+    int use;                          // gamma valid for this iteration
+    int stalls;                       // stalls in this step (two: plain steps to its end)
+};
+
+struct PsAABufs {
+    const double* F;                  // delta_k (written by the line solves)
+    double* Fp;                       // delta_{k-1}
+    double* Yp;                       // Y_{k-2}
+    double* dF;                       // m ring columns of N
+    double* dY;
+    double* part;                     // per-block partial sums, nblk x 2m
+    PsAA* st;
+    int m, nblk;
+};
+
+// Part 1, after the line solves of iteration k (Y = Y_{k-1}): the new pair
+// into the ring slot after head, each block's partial sums of dF_new . dF_i
+// (value i) and dF_i . delta_k (value m + i) over every slot (the new pair in
+// its slot), and delta_k, Y_{k-1} kept as the previous ones (k = 1: only
+// these).
+static __global__ __launch_bounds__(PS_AA_T) void ps_aa_dots(const double* __restrict__ Y, PsAABufs b, size_t N,
+                                                           const PsCtl* ctl, int k, double tol) {
+    if (ps_halted(ctl, k, tol) || ps_bits(ctl->err[k]) < tol || (k > 1 && b.st->stalls >= 2)) return;
+    const int m = b.m, slot = (b.st->head + 1) % m;
+    double acc[2 * PS_AA_MAX];
+#pragma unroll
+    for (int i = 0; i < 2 * PS_AA_MAX; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int e = 0; e < PS_AA_EPT; ++e) {
+        const size_t idx = ((size_t)blockIdx.x * PS_AA_EPT + e) * PS_AA_T + threadIdx.x;
+        if (idx >= N) break;
+        const double f = b.F[idx], y = Y[idx];
+        if (k > 1) {
+            const double dfn = f - b.Fp[idx];
+            b.dF[slot * N + idx] = dfn;
+            b.dY[slot * N + idx] = y - b.Yp[idx];
+#pragma unroll
+            for (int i = 0; i < PS_AA_MAX; ++i) {
+                if (i >= m) break;
+                const double v = i == slot ? dfn : b.dF[i * N + idx];
+                acc[i] += dfn * v;
+                acc[PS_AA_MAX + i] += v * f;
+            }
+        }
+        b.Fp[idx] = f;
+        b.Yp[idx] = y;
+    }
+    if (k == 1) return;
+    // block sums in a fixed order (wave shuffles, then the waves in order)
+    __shared__ double red[2 * PS_AA_MAX][PS_AA_T / 64];
+#pragma unroll
+    for (int i = 0; i < 2 * PS_AA_MAX; ++i) {
+        double v = acc[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((threadIdx.x & 63) == 0) red[i][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * m) {
+        const int i = threadIdx.x < m ? threadIdx.x : PS_AA_MAX + threadIdx.x - m;
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < PS_AA_T / 64; ++w) v += red[i][w];
+        b.part[(size_t)blockIdx.x * 2 * m + threadIdx.x] = v;
+    }
+}
+
+// Part 2, one block of PS_AA_T threads: the partial sums added in a fixed
+// order, the Gram matrix's new row and column, gamma from the normal equations
+// (Cholesky, diagonal shifted by 1e-10 of its largest entry).  Safeguards: a
+// stopping value that did not decrease since the last iteration (a stall), or
+// a non-positive pivot, drops the history and makes this a plain step; after
+// the second stall of a step its remaining iterations are plain (near the
+// rounding floor the largest increments are rounding noise, which no fit
+// removes, and the paper's iteration settles them).  k = 1 starts the step.
+static __global__ __launch_bounds__(PS_AA_T) void ps_aa_solve(PsAABufs b, const PsCtl* ctl, int k, double tol) {
+    if (ps_halted(ctl, k, tol)) return;
+    PsAA& s = *b.st;
+    const int m = b.m, nv = 2 * m;
+    const double ek = ps_bits(ctl->err[k]);
+    const bool stalled = k > 1 && !(ek < ps_bits(ctl->err[k - 1]));
+    if (k == 1 || ek < tol || stalled || s.stalls >= 2) {
+        if (threadIdx.x == 0) {
+            if (k == 1) {
+                s.head = m - 1;
+                s.stalls = 0;
+            }
+            if (k == 1 || stalled) s.mk = 0;
+            if (stalled) ++s.stalls;
+            s.use = 0;
+        }
+        return;
+    }
+    __shared__ double red[PS_AA_T];
+    __shared__ double d[2 * PS_AA_MAX];
+    for (int j = 0; j < nv; ++j) {
+        double v = 0.0;
+        for (int q = threadIdx.x; q < b.nblk; q += PS_AA_T) v += b.part[(size_t)q * nv + j];
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = PS_AA_T / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) d[j] = red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const int slot = (s.head + 1) % m;
+    for (int i = 0; i < m; ++i) s.G[slot][i] = s.G[i][slot] = d[i];
+    s.head = slot;
+    s.mk = s.mk < m ? s.mk + 1 : m;
+    const int mk = s.mk;
+    int c[PS_AA_MAX];
+    double A[PS_AA_MAX][PS_AA_MAX], r[PS_AA_MAX], gmax = 0.0;
+    for (int q = 0; q < mk; ++q) {
+        c[q] = (slot - q + m) % m;            // newest first
+        gmax = fmax(gmax, s.G[c[q]][c[q]]);
+    }
+    for (int q = 0; q < mk; ++q) {
+        for (int t = 0; t < mk; ++t) A[q][t] = s.G[c[q]][c[t]];
+        A[q][q] += 1e-10 * gmax;
+        r[q] = d[m + c[q]];
+    }
+    bool ok = gmax > 0.0 && gmax == gmax;
+    for (int j = 0; j < mk && ok; ++j) {      // A = R^T R, R upper triangular in A
+        double sum = A[j][j];
+        for (int q = 0; q < j; ++q) sum -= A[q][j] * A[q][j];
+        if (!(sum > 0.0)) {
+            ok = false;
+            break;
+        }
+        A[j][j] = sqrt(sum);
+        for (int t = j + 1; t < mk; ++t) {
+            double v = A[j][t];
+            for (int q = 0; q < j; ++q) v -= A[q][j] * A[q][t];
+            A[j][t] = v / A[j][j];
+        }
+    }
+    for (int i = 0; i < PS_AA_MAX; ++i) s.gamma[i] = 0.0;
+    if (!ok) {
+        s.mk = 0;
+        s.use = 0;
+        return;
+    }
+    double z[PS_AA_MAX];
+    for (int j = 0; j < mk; ++j) {            // R^T z = r
+        double v = r[j];
+        for (int q = 0; q < j; ++q) v -= A[q][j] * z[q];
+        z[j] = v / A[j][j];
+    }
+    for (int j = mk - 1; j >= 0; --j) {       // R g = z
+        double v = z[j];
+        for (int t = j + 1; t < mk; ++t) v -= A[j][t] * s.gamma[c[t]];
+        s.gamma[c[j]] = v / A[j][j];
+    }
+    s.use = 1;
+}
+
+// Part 3: Y_k = Y_{k-1} + delta_k - sum_i gamma_i (dY_i + dF_i) (plain step
+// without valid gamma).
+static __global__ __launch_bounds__(PS_AA_T) void ps_aa_update(double* __restrict__ Y, PsAABufs b, size_t N,
+                                                             const PsCtl* ctl, int k, double tol) {
+    if (ps_halted(ctl, k, tol)) return;
+    const PsAA& s = *b.st;
+    const bool mix = s.use && k > 1 && !(ps_bits(ctl->err[k]) < tol);
+#pragma unroll
+    for (int e = 0; e < PS_AA_EPT; ++e) {
+        const size_t idx = ((size_t)blockIdx.x * PS_AA_EPT + e) * PS_AA_T + threadIdx.x;
+        if (idx >= N) break;
+        double y = Y[idx] + b.F[idx];
+        if (mix) {
+#pragma unroll
+            for (int i = 0; i < PS_AA_MAX; ++i) {
+                if (i >= b.m) break;
+                const double g = s.gamma[i];
+                if (g != 0.0) y -= g * (b.dY[i * N + idx] + b.dF[i * N + idx]);
+            }
+        }
+        Y[idx] = y;
     }
 }
 

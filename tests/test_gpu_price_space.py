@@ -135,14 +135,18 @@ def test_apply_B_matches_oracle(lp, name, N_x, fft_size):
     assert e_all < 1e-12 * t0 * t0
 
 
-@pytest.mark.parametrize("name,fft_size", [("VG1", 0), ("NIG1", 0), ("NIG1", 24576)])
-def test_march_matches_oracle(lp, name, fft_size):
+@pytest.mark.parametrize("name,fft_size,accel", [("VG1", 0, -1), ("VG1", 0, 3), ("NIG1", 0, 0), ("NIG1", 0, 4),
+                                                  ("NIG1", 24576, -1)])
+def test_march_matches_oracle(lp, name, fft_size, accel):
     """N_x = 32 (19 step-list entries with the damped block): the grid after
     the damped block, after the first main steps and at the end; prices at
-    the Table 3 spots.  Also through the two-level transforms (L = 24576)."""
+    the Table 3 spots.  Also through the two-level transforms (L = 24576), and
+    with the paper's iteration (accel 0) and Anderson mixing (3, 4, automatic)
+    against the oracle's plain iteration: the same fixed point."""
     from oracle import price_space as ps
     N_x = 32
-    plan = _gpu_plan(lp, name, N_x, tol=1e-11, max_iter=128, fft_size=fft_size)
+    plan = _gpu_plan(lp, name, N_x, tol=1e-11, max_iter=128, fft_size=fft_size, accel=accel)
+    _note("%s accel %d: Anderson depth %d" % (name, accel, plan.info()["accel_depth"]))
     prob = _oracle_problem(name, N_x)
     spots, _ = _spots_and_table3(name)
     n_steps = plan.info()["n_steps"]
@@ -158,6 +162,26 @@ def test_march_matches_oracle(lp, name, fft_size):
     ep = float(np.max(np.abs(Pg - P) / np.abs(P)))
     _note("  prices %.2e" % ep)
     assert ep < 1e-10
+
+
+@pytest.mark.parametrize("name,N_x", [("NIG0", 64), ("NIG1", 64)])
+def test_anderson_same_fixed_point_fewer_iterations(lp, name, N_x):
+    """Anderson mixing (depth 4) against the paper's iteration on the sets
+    where it contracts slowly: both stop on the same rule (tol 1e-11), so the
+    grids agree to a few tol, with fewer iterations in all.  The automatic
+    choice picks mixing on these sets."""
+    plain = _gpu_plan(lp, name, N_x, tol=1e-11, accel=0)
+    mixed = _gpu_plan(lp, name, N_x, tol=1e-11, accel=4)
+    auto = _gpu_plan(lp, name, N_x, tol=1e-11)
+    assert plain.info()["accel_depth"] == 0 and mixed.info()["accel_depth"] == 4
+    assert auto.info()["accel_depth"] == 4
+    Vp = plain.solve().cpu().numpy()
+    Vm = mixed.solve().cpu().numpy()
+    ip, im = plain.info()["total_iters"], mixed.info()["total_iters"]
+    d = _rel(Vm, Vp)
+    _note("%s N_x=%d: iterations %d plain, %d Anderson(4); grids %.2e apart" % (name, N_x, ip, im, d))
+    assert d < 1e-9
+    assert im < 0.75 * ip
 
 
 def test_march_all_correlations_and_theta_one(lp):
