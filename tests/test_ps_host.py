@@ -81,3 +81,33 @@ def test_ps_validation(lp):
             lp.ps_discretize_host(g, lv, pay)
     with pytest.raises(lp.LpideError):
         lp.ps_discretize_host(lp.make_ps_grid(32, 500.0), lv, lp.make_payoff("exchange", 100.0, 1.0), want_v0=True)
+
+
+def test_accel_option_validated_before_any_device_work(lp):
+    """lpide_opts.accel: the price-space plan takes -1 (automatic), 0 (the
+    paper's iteration) or an Anderson depth 1..6 and refuses anything else;
+    the log plan refuses any value but 0.  Both are checked before a device is
+    touched, so the refusal is seen here."""
+    import ctypes as C
+    from paper_2511_02700_amd import _lib as L
+    lib = L.lib()
+    lv = lp.levy_black_scholes(0.0, (0.04, 0.0, 0.04))
+    pay = lp.make_payoff("put_avg", 100.0, 1.0)
+    g = lp.make_ps_grid(32, 500.0)
+    for bad in (-2, 7, 100):
+        o = L.Opts()
+        lib.lpide_opts_default(C.byref(o))
+        o.accel = bad
+        h = C.c_void_p()
+        rc = lib.lpide_ps_plan_create(C.byref(g), C.byref(lv), C.byref(pay), 0.5, 16, C.byref(o), C.byref(h))
+        assert L.ERRORS.get(rc) == "LPIDE_E_PARAM" and not h.value
+        assert b"accel" in lib.lpide_last_error()
+    o = L.Opts()
+    lib.lpide_opts_default(C.byref(o))
+    assert o.accel == 0                   # the default is the paper's iteration
+    o.accel = 4
+    lg = lp.make_grid(32, -2.0, 2.0)
+    h = C.c_void_p()
+    rc = lib.lpide_plan_create(C.byref(lg), C.byref(lv), C.byref(pay), 0.5, 8, C.byref(o), C.byref(h))
+    assert L.ERRORS.get(rc) == "LPIDE_E_PARAM" and not h.value
+    assert b"accel" in lib.lpide_last_error()
