@@ -67,3 +67,28 @@ def test_adjoint_twice_is_bitwise_equal(lp):
     _, n1, _ = plan.adjoint(vbar, checkpoint_every=4)
     _, n2, _ = plan.adjoint(vbar, checkpoint_every=4)
     assert np.array_equal(n1, n2)
+
+
+def test_price_space_march_twice_is_bitwise_equal(lp):
+    """The price-space plan, with the paper's iteration and with Anderson
+    mixing, whose inner products are summed per block and then over the
+    blocks in a fixed order: two marches, and a fresh plan, give the same
+    bytes."""
+    import csv
+    import os
+    import torch
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table1_params.csv")
+    with open(gold) as f:
+        q = {r["name"]: r for r in csv.DictReader(line for line in f if not line.startswith("#"))}["NIG1"]
+    lv = lp.levy_nts(float(q["alpha"]), float(q["delta"]), float(q["lambda"]), (float(q["eta1"]), float(q["eta2"])),
+                     (float(q["rho11"]), float(q["rho12"]), float(q["rho22"])), float(q["r"]))
+    pay = lp.make_payoff("put_avg", float(q["K"]), float(q["T"]))
+    for accel in (0, 4):
+        _note("determinism: price-space NIG1 N_x=48 accel=%d twice" % accel)
+        mk = lambda: lp.PsPlan(lp.make_ps_grid(48, 700.0, c=45.0189), lv, pay, N_t=24, tol=1e-11, accel=accel)
+        plan = mk()
+        a = plan.solve()
+        b = plan.solve()
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        assert torch.equal(mk().solve(), a)

@@ -164,6 +164,20 @@ def test_march_matches_oracle(lp, name, fft_size, accel):
     assert ep < 1e-10
 
 
+@pytest.mark.parametrize("depth", [1, 2, 6])
+def test_anderson_depths(lp, depth):
+    """Every depth reaches the paper's fixed point (NIG0, N_x = 48, against the
+    paper's iteration on the GPU at tol 1e-11) in fewer iterations."""
+    plain = _gpu_plan(lp, "NIG0", 48, tol=1e-11, accel=0)
+    mixed = _gpu_plan(lp, "NIG0", 48, tol=1e-11, accel=depth)
+    d = _rel(mixed.solve().cpu().numpy(), plain.solve().cpu().numpy())
+    ip, im = plain.info()["total_iters"], mixed.info()["total_iters"]
+    _note("NIG0 N_x=48 depth %d: %d iterations against %d; grids %.2e apart" % (depth, im, ip, d))
+    assert mixed.info()["accel_depth"] == depth
+    assert d < 1e-9
+    assert im < ip
+
+
 @pytest.mark.parametrize("name,N_x", [("NIG0", 64), ("NIG1", 64)])
 def test_anderson_same_fixed_point_fewer_iterations(lp, name, N_x):
     """Anderson mixing (depth 4) against the paper's iteration on the sets
@@ -184,20 +198,22 @@ def test_anderson_same_fixed_point_fewer_iterations(lp, name, N_x):
     assert im < 0.75 * ip
 
 
-def test_march_all_correlations_and_theta_one(lp):
+@pytest.mark.parametrize("accel", [-1, 4])
+def test_march_all_correlations_and_theta_one(lp, accel):
     """The explicit part by the correlation (all_correlations), and theta = 1
-    (no explicit part) without damping, against the oracle."""
+    (no explicit part) without damping, against the oracle; with the
+    automatic iteration (the paper's on VG1) and with Anderson mixing."""
     from oracle import price_space as ps
     prob = _oracle_problem("VG1", 24, N_t=8)
     V, _ = ps.solve(prob, tol=1e-14)
-    plan = _gpu_plan(lp, "VG1", 24, N_t=8, all_correlations=True)
+    plan = _gpu_plan(lp, "VG1", 24, N_t=8, all_correlations=True, accel=accel)
     err = _rel(plan.solve().cpu().numpy(), V)
     _note("VG1 N_x=24 all correlations: %.2e" % err)
     assert err < 1e-10
     prob1 = _oracle_problem("VG1", 24, N_t=8)
     prob1.theta, prob1.damping = 1.0, False
     V1, _ = ps.solve(prob1, tol=1e-14)
-    plan1 = _gpu_plan(lp, "VG1", 24, N_t=8, theta=1.0, damping=False)
+    plan1 = _gpu_plan(lp, "VG1", 24, N_t=8, theta=1.0, damping=False, accel=accel)
     err1 = _rel(plan1.solve().cpu().numpy(), V1)
     _note("VG1 N_x=24 theta=1 no damping: %.2e" % err1)
     assert err1 < 1e-10
