@@ -364,7 +364,9 @@ class PsPlan:
     def __init__(self, grid, levy, payoff, theta=0.5, N_t=None, tol=1e-10, max_iter=128, damping=True, device=0,
                  stream=None, fft_size=0, all_correlations=False, accel=-1):
         """accel: 0 the paper's fixed-point iteration, 1..6 Anderson mixing of that depth,
-        -1 (default) depth 4 where the iteration is predicted to contract slowly."""
+        -1 (default) depth 4 where the iteration is predicted to contract slowly.
+        tol: the stopping value's rounding floor grows with the grid on the NIG sets and lies
+        near 1e-10 on the paper's own grids (N_x = 400, 800); use 1e-9 there (the paper: 1e-7)."""
         torch = _torch()
         o = Opts()
         lib().lpide_opts_default(C.byref(o))
