@@ -109,35 +109,47 @@ bool sizes(std::mt19937_64& rng, double tol) {
     return ok;
 }
 
+// The cases are split into FFT_EMU_PARTS programs (compiled separately, in
+// parallel; part FFT_EMU_PART instantiates only its own cases): case I belongs
+// to part I mod FFT_EMU_PARTS.
+#ifndef FFT_EMU_PARTS
+#define FFT_EMU_PARTS 1
+#endif
+#ifndef FFT_EMU_PART
+#define FFT_EMU_PART 0
+#endif
+template <int I>
+constexpr bool mine() { return I % FFT_EMU_PARTS == FFT_EMU_PART; }
+
 template <typename C>
 bool all_sizes(std::mt19937_64& rng, double tol) {
     bool ok = true;
-    ok = sizes<64, C>(rng, tol) && ok;
-    ok = sizes<128, C>(rng, tol) && ok;
-    ok = sizes<256, C>(rng, tol) && ok;
-    ok = sizes<512, C>(rng, tol) && ok;
-    ok = sizes<768, C>(rng, tol) && ok;
-    ok = sizes<1024, C>(rng, tol) && ok;
-    ok = sizes<1536, C>(rng, tol) && ok;
-    ok = sizes<2048, C>(rng, tol) && ok;
-    ok = sizes<3072, C>(rng, tol) && ok;
-    ok = sizes<4096, C>(rng, tol) && ok;
+    if constexpr (mine<0>()) ok = sizes<64, C>(rng, tol) && ok;
+    if constexpr (mine<1>()) ok = sizes<128, C>(rng, tol) && ok;
+    if constexpr (mine<2>()) ok = sizes<256, C>(rng, tol) && ok;
+    if constexpr (mine<3>()) ok = sizes<512, C>(rng, tol) && ok;
+    if constexpr (mine<4>()) ok = sizes<768, C>(rng, tol) && ok;
+    if constexpr (mine<5>()) ok = sizes<1024, C>(rng, tol) && ok;
+    if constexpr (mine<6>()) ok = sizes<1536, C>(rng, tol) && ok;
+    if constexpr (mine<7>()) ok = sizes<2048, C>(rng, tol) && ok;
+    if constexpr (mine<8>()) ok = sizes<3072, C>(rng, tol) && ok;
+    if constexpr (mine<9>()) ok = sizes<4096, C>(rng, tol) && ok;
     // sides with odd factors 5, 7 and 9 (radix-5, radix-7 and two radix-3
     // stages): every E in FP64, the two smallest in FP32 as well (the stages
     // are the same code for both), the largest with the 16 elements per thread
     // the price-space plan uses there
-    ok = sizes<640, C>(rng, tol) && ok;
-    ok = sizes<896, C>(rng, tol) && ok;
+    if constexpr (mine<10>()) ok = sizes<640, C>(rng, tol) && ok;
+    if constexpr (mine<11>()) ok = sizes<896, C>(rng, tol) && ok;
     if constexpr (sizeof(typename Real<C>::T) == 8) {
-        ok = sizes<1152, C>(rng, tol) && ok;
-        ok = sizes<1280, C>(rng, tol) && ok;
-        ok = sizes<1792, C>(rng, tol) && ok;
-        ok = sizes<2304, C>(rng, tol) && ok;
-        ok = sizes<2560, C>(rng, tol) && ok;
-        ok = sizes<3584, C>(rng, tol) && ok;
-        ok = check<4608, 16, C>(rng, tol) && ok;
-        ok = check<5120, 16, C>(rng, tol) && ok;
-        ok = check<7168, 16, C>(rng, tol) && ok;
+        if constexpr (mine<12>()) ok = sizes<1152, C>(rng, tol) && ok;
+        if constexpr (mine<13>()) ok = sizes<1280, C>(rng, tol) && ok;
+        if constexpr (mine<14>()) ok = sizes<1792, C>(rng, tol) && ok;
+        if constexpr (mine<15>()) ok = sizes<2304, C>(rng, tol) && ok;
+        if constexpr (mine<16>()) ok = sizes<2560, C>(rng, tol) && ok;
+        if constexpr (mine<17>()) ok = sizes<3584, C>(rng, tol) && ok;
+        if constexpr (mine<18>()) ok = check<4608, 16, C>(rng, tol) && ok;
+        if constexpr (mine<19>()) ok = check<5120, 16, C>(rng, tol) && ok;
+        if constexpr (mine<20>()) ok = check<7168, 16, C>(rng, tol) && ok;
     }
     return ok;
 }

@@ -40,15 +40,26 @@ def _run(cmd, **kw):
 
 
 def test_workgroup_fft_emulated_under_sanitizers(tmp_path):
-    exe = str(tmp_path / "fft_emu")
-    r = _run([_gxx(), "-std=c++20"] + SAN + ["-I", os.path.join(CPU, "emu"), "-I", CSRC,
-                                             os.path.join(CPU, "fft_emu.cpp"), "-o", exe, "-lpthread"])
-    assert r.returncode == 0, r.stderr[-3000:]
-    r = _run([exe], timeout=600)
-    assert r.returncode == 0 and "ALL OK" in r.stdout, (r.stdout[-2000:], r.stderr[-3000:])
-    assert "ERROR: AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr, r.stderr[-3000:]
-    cases = [line for line in r.stdout.splitlines() if " ok" in line]
-    assert len(cases) >= 100          # sides x radices x {fp64, fp32} x {forward, inverse}
+    # the cases are compiled as PARTS programs in parallel (one translation unit
+    # takes about 100 s under the sanitizers), each run after its build
+    PARTS = 4
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    exes = [str(tmp_path / ("fft_emu%d" % q)) for q in range(PARTS)]
+    builds = [subprocess.Popen([_gxx(), "-std=c++20"] + SAN +
+                               ["-DFFT_EMU_PARTS=%d" % PARTS, "-DFFT_EMU_PART=%d" % q, "-I", os.path.join(CPU, "emu"),
+                                "-I", CSRC, os.path.join(CPU, "fft_emu.cpp"), "-o", exes[q], "-lpthread"],
+                               stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+              for q in range(PARTS)]
+    for b in builds:
+        _, err = b.communicate(timeout=900)
+        assert b.returncode == 0, err[-3000:]
+    cases = []
+    for exe in exes:
+        r = _run([exe], timeout=600)
+        assert r.returncode == 0 and "ALL OK" in r.stdout, (r.stdout[-2000:], r.stderr[-3000:])
+        assert "ERROR: AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr, r.stderr[-3000:]
+        cases += [line for line in r.stdout.splitlines() if " ok" in line]
+    assert len(cases) >= 160          # sides x radices x {fp64, fp32} x {forward, inverse}
 
 
 def test_host_plan_under_sanitizers(tmp_path):
