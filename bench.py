@@ -25,10 +25,13 @@ deltas, Delta/Gamma surfaces), the other candidate transform side, and a CPU
 baseline: the FP64 oracle timed on this host on a bounded sample of the same
 workload (in a child process, while the GPU extras run), and the plan time.
 Unless --no-extras: the 512^2 finite-variation workload (fv512), the paper's
-Table 3 prices against GPU marches, the adjoint form on its 1024^2 workload
-(ratio to the forward, with checkpoints every 32 steps and with every state
-kept), and the batched form on all 256 draws of the batched recipe (autotuned,
-against solo solves).
+Table 3 prices against GPU marches on the log grid, the price-space plan (the
+paper's own discretization) on each Table 1 set at the largest grid one
+workgroup's transform holds and (unless --no-paper-grids) on the paper's own
+grids, the adjoint form on its 1024^2 workload (ratio to the forward, with
+checkpoints every 32 steps and with every state kept), a vectorised device copy
+as the bandwidth reference, and the batched form on all 256 draws of the
+batched recipe (autotuned, against solo solves).
 """
 
 import argparse
@@ -673,9 +676,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip fv512, Table 3, the price-space plan, the adjoint and the batched measurements")
     ap.add_argument("--batch-count", type=int, default=256, help="draws of the batched recipe in the batched leg")
-    ap.add_argument("--table3-paper-grids", action="store_true",
-                    help="also run the four Table 3 sets on the paper's own price-space grids (N_x = 800, NIG0 "
-                         "400; a few minutes)")
+    ap.add_argument("--no-paper-grids", action="store_true",
+                    help="skip the four Table 3 sets on the paper's own price-space grids (N_x = 800, NIG0 400; "
+                         "about 35 s)")
     ap.add_argument("--fft-size", type=int, default=0,
                     help="transform side of the correlation (0: the smallest supported one, 2^m or 3*2^m)")
     ap.add_argument("--traffic-json", default=None,
@@ -726,7 +729,7 @@ def main():
     if not args.no_extras:
         result["paper_table3"] = table3_check(lp)
         result["price_space"] = price_space_check(lp)
-        if args.table3_paper_grids:
+        if not args.no_paper_grids:
             result["price_space_paper_grids"] = price_space_paper_grids(lp)
         result["adjoint"] = adjoint_measure(lp)
         result["batched"] = batch_measure(lp, count=args.batch_count)
