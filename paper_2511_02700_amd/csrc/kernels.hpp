@@ -67,6 +67,32 @@ __device__ __forceinline__ double apply_D(const double* __restrict__ U, const St
     return d;
 }
 
+// apply_D with all eight neighbours read at indices clamped into the grid
+// (the mixed term's nodes are those neighbours): every read valid and none
+// conditional, so that a node's reads are in flight together; the interior
+// tests select the arithmetic only (a zero a12 adds a zero mixed term).  For
+// row kernels with one element per thread and loop pass; kernels that unroll
+// many elements keep apply_D, whose branches throttle the reads in flight.
+__device__ __forceinline__ double apply_D_ahead(const double* __restrict__ U, const StencilArgs& s, int i, int j,
+                                                double u) {
+    const int n = s.n;
+    const double ih2 = 1.0 / (s.h * s.h), i2h = 0.5 / s.h;
+    const bool iin = i > 0 && i < n - 1, jin = j > 0 && j < n - 1;
+    const int im = i > 0 ? i - 1 : 0, ip = i < n - 1 ? i + 1 : n - 1;
+    const int jm = j > 0 ? j - 1 : 0, jp = j < n - 1 ? j + 1 : n - 1;
+    const double* rm = U + (size_t)im * n;
+    const double* rp = U + (size_t)ip * n;
+    const double u1m = rm[j], u1p = rp[j];
+    const double u2m = U[(size_t)i * n + jm], u2p = U[(size_t)i * n + jp];
+    const double u00 = rm[jm], u01 = rm[jp], u10 = rp[jm], u11 = rp[jp];
+    double d = 0.0;
+    if (iin) d += 0.5 * s.a11 * ((u1p - 2.0 * u + u1m) * ih2 - (u1p - u1m) * i2h);
+    if (jin) d += 0.5 * s.a22 * ((u2p - 2.0 * u + u2m) * ih2 - (u2p - u2m) * i2h);
+    const double gi = iin ? i2h : 1.0 / s.h, gj = jin ? i2h : 1.0 / s.h;
+    d += s.a12 * gi * gj * ((u11 - u10) - (u01 - u00));
+    return d;
+}
+
 // The three unit-coefficient parts of D at (i, j): D u = a11 d11 + a12 d12 + a22 d22
 // (the derivative of D u with respect to each coefficient).
 __device__ __forceinline__ void apply_D_parts(const double* __restrict__ U, int n, double h, int i, int j, double u,

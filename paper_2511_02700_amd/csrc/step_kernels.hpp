@@ -419,35 +419,52 @@ static __global__ __launch_bounds__(256) void ks_expl_identity(const MarchArgs* 
 // B Y^0 = sum_q coef_q B V^{src_q} from the stored products, the residual
 // R = W + dt theta((D - r_omega) Y^0 + B Y^0) - Y^0, and B Y^0 stored for the
 // iterate; one block per grid row (the row c2r kernel exits in these steps).
+// The row of ks_rows_lin with NS stored products: no branch in the element
+// loop and the arguments read once before it (the stores go through plain
+// pointers, after which they would be read again), so that an element's reads
+// are in flight together.
+template <int NS>
+__device__ __forceinline__ void rows_lin_row(const MarchArgs& a, int i, double cth) {
+    const Ctl* c = a.ctl;
+    const int n = a.n;
+    const double* __restrict__ Hb[NS];
+    double cf[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        Hb[q] = a.bpool[c->src[q]];
+        cf[q] = c->coef[q];
+    }
+    const double* __restrict__ U = a.pool[c->y];
+    const double* __restrict__ W = a.W;
+    double* __restrict__ R = a.R;
+    double* __restrict__ Bout = a.bpool[c->y];
+    const double r_omega = a.r_omega;
+    const StencilArgs st = a.st;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const size_t o = (size_t)i * n + j;
+        double bu = 0.0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) bu += cf[q] * Hb[q][o];
+        const double u = U[o];
+        const double d = apply_D_ahead(U, st, i, j, u);
+        R[o] = W[o] + cth * (d + bu - r_omega * u) - u;
+        Bout[o] = bu;
+    }
+}
+
 static __global__ __launch_bounds__(256) void ks_rows_lin(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
     if (halted(a, 1) || !start_by_linearity(a)) return;
     const int n = a.n;
     const int i = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows on one XCD (stencil reads share L2)
     if (i >= n) return;
-    const Ctl* c = a.ctl;
     const StepDesc& sd = cur_set(a);
     const double cth = sd.dt * sd.theta;
-    const int nsrc = c->nsrc;
-    const double* Hb[4];
-    double cf[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        Hb[q] = a.bpool[c->src[q]];
-        cf[q] = c->coef[q];
-    }
-    const double* U = a.pool[c->y];
-    double* Bout = a.bpool[c->y];
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const size_t o = (size_t)i * n + j;
-        double bu = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (q < nsrc) bu += cf[q] * Hb[q][o];
-        const double u = U[o];
-        const double d = apply_D(U, a.st, i, j, u);
-        a.R[o] = a.W[o] + cth * (d + bu - a.r_omega * u) - u;
-        Bout[o] = bu;
+    switch (a.ctl->nsrc) {                           // uniform: one loop per count of stored products (1..4)
+        case 1: rows_lin_row<1>(a, i, cth); break;
+        case 2: rows_lin_row<2>(a, i, cth); break;
+        case 3: rows_lin_row<3>(a, i, cth); break;
+        default: rows_lin_row<4>(a, i, cth); break;
     }
 }
 
