@@ -468,37 +468,37 @@ static __global__ __launch_bounds__(256) void ks_rows_lin(const MarchArgs* __res
     }
 }
 
-// SL gather W = T^SL E and start value Y^0 of an FP64 step whose B Y^0 comes by
-// linearity (no row transform of Y^0): one block per grid row, streaming.
-template <int P>
-__global__ __launch_bounds__(256) void ks_sl_lin(const MarchArgs* __restrict__ A) {
-    const MarchArgs& a = plan_args(A);
-    if (halted(a, 0) || a.mixed || !start_by_linearity(a)) return;
-    const int n = a.n;
-    const int i = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows share E rows in L2
-    if (i >= n) return;
+// The row of ks_sl_lin with NS history grids in the start value: no branch in
+// the element loop and the step's tables read once before it, so that an
+// element's reads are in flight together.
+template <int P, int NS>
+__device__ __forceinline__ void sl_lin_row(const MarchArgs& a, int i) {
     const Ctl* c = a.ctl;
+    const int n = a.n;
     const StepDesc& sd = cur_set(a);
     // the grids read (E, history) and written (W, Y) are distinct pool, R and W buffers
     const double* __restrict__ Ex = sd.theta < 1.0 ? a.R : a.pool[c->cur];
     double* __restrict__ Y = a.pool[c->y];
     double* __restrict__ Wo = a.W;
-    const int nsrc = c->nsrc;
-    const double* __restrict__ H0 = a.pool[c->src[0]];
-    const double* __restrict__ H1 = a.pool[c->src[1]];
-    const double* __restrict__ H2 = a.pool[c->src[2]];
-    const double* __restrict__ H3 = a.pool[c->src[3]];
-    const double c0 = c->coef[0], c1 = c->coef[1], c2 = c->coef[2], c3 = c->coef[3];
+    const double* __restrict__ H[NS];
+    double cf[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        H[q] = a.pool[c->src[q]];
+        cf[q] = c->coef[q];
+    }
     const int a0 = sd.s1[i];
     double w1[P + 1];
 #pragma unroll
     for (int q = 0; q <= P; ++q) w1[q] = sd.w1[i * (P + 1) + q];
     const double* __restrict__ er0 = Ex + (size_t)a0 * n;
+    const int* __restrict__ s2 = sd.s2;
+    const double* __restrict__ wt2 = sd.w2;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const int b0 = sd.s2[j];
+        const int b0 = s2[j];
         double w2[P + 1];
 #pragma unroll
-        for (int b = 0; b <= P; ++b) w2[b] = sd.w2[j * (P + 1) + b];
+        for (int b = 0; b <= P; ++b) w2[b] = wt2[j * (P + 1) + b];
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q <= P; ++q) {
@@ -509,12 +509,30 @@ __global__ __launch_bounds__(256) void ks_sl_lin(const MarchArgs* __restrict__ A
             acc += w1[q] * sq;
         }
         const size_t o = (size_t)i * n + j;
-        double y = c0 * H0[o];
-        if (nsrc > 1) y += c1 * H1[o];
-        if (nsrc > 2) y += c2 * H2[o];
-        if (nsrc > 3) y += c3 * H3[o];
+        double y = cf[0] * H[0][o];
+#pragma unroll
+        for (int q = 1; q < NS; ++q) y += cf[q] * H[q][o];
         Wo[o] = acc;
         Y[o] = y;
+    }
+}
+
+// SL gather W = T^SL E and start value Y^0 of an FP64 step whose B Y^0 comes by
+// linearity (no row transform of Y^0): one block per grid row, streaming; at
+// least 8 waves per SIMD (64 registers), so that the reads hoisted out of the
+// branch-free loop do not cost occupancy.
+template <int P>
+__global__ __launch_bounds__(256, 8) void ks_sl_lin(const MarchArgs* __restrict__ A) {
+    const MarchArgs& a = plan_args(A);
+    if (halted(a, 0) || a.mixed || !start_by_linearity(a)) return;
+    const int n = a.n;
+    const int i = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows share E rows in L2
+    if (i >= n) return;
+    switch (a.ctl->nsrc) {                           // uniform: one loop per count of history grids (1..4)
+        case 1: sl_lin_row<P, 1>(a, i); break;
+        case 2: sl_lin_row<P, 2>(a, i); break;
+        case 3: sl_lin_row<P, 3>(a, i); break;
+        default: sl_lin_row<P, 4>(a, i); break;
     }
 }
 
