@@ -319,6 +319,12 @@ __global__ __launch_bounds__(L / E) void ks_rows_inv(const MarchArgs* __restrict
     const double c0 = EXPL ? 0.0 : -1.0;
     const bool want_r = MODE != 0 || sd.theta < 1.0;
     const double* base = (MODE == 2 && k == 1) ? a.BV : a.BY;
+    // the arguments the loop needs, read once: the stores below go through
+    // plain pointers, after which every field of a would be read again
+    const StencilArgs st = a.st;
+    const double r_omega = a.r_omega;
+    double* const BY = a.BY;
+    double* const BV = a.mixed ? a.BV : nullptr;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int j = tid + e * T;
@@ -334,15 +340,15 @@ __global__ __launch_bounds__(L / E) void ks_rows_inv(const MarchArgs* __restrict
             }
             if constexpr (MODE == 2) {
                 bu += base[o];
-                a.BY[o] = bu;
+                BY[o] = bu;
             }
             if constexpr (MODE == 0) {
-                if (a.mixed) a.BV[o] = bu;
+                if (BV) BV[o] = bu;
             }
             if (want_r) {
                 const double u = U[o];
-                const double d = MODE >= 3 ? apply_DT(U, a.st, i, j, u) : apply_D(U, a.st, i, j, u);
-                out[o] = P0[o] + c * (d + bu - a.r_omega * u) + c0 * u;
+                const double d = MODE >= 3 ? apply_DT(U, st, i, j, u) : apply_D(U, st, i, j, u);
+                out[o] = P0[o] + c * (d + bu - r_omega * u) + c0 * u;
             }
         }
     }
