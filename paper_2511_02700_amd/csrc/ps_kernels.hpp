@@ -169,12 +169,18 @@ __global__ __launch_bounds__(L / ps_e(L)) void ps_rows_fwd(const double* __restr
 #pragma unroll
     for (int e = 0; e < KE; ++e) lds[tid + e * T] = reg[e];
     __syncthreads();
-    // Z = FFT(a + i b): A_k = (Z_k + conj Z_{L-k}) / 2, B_k = (Z_k - conj Z_{L-k}) / (2i)
-    for (int kk = tid; kk <= L / 2; kk += T) {
+    // Z = FFT(a + i b): A_k = (Z_k + conj Z_{L-k}) / 2, B_k = (Z_k - conj Z_{L-k}) / (2i).
+    // Item idx is frequency idx / 2 of row ra + idx mod 2: the two rows of a
+    // frequency are adjacent in X, so a lane pair stores them as one 32-byte piece.
+    constexpr int NI = (L + 2 + T - 1) / T;
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int idx = tid + it * T;
+        const int kk = idx >> 1, r = idx & 1;
+        if (kk > L / 2 || (r == 1 && !hasb)) continue;
         const double2 z = lds[kk], w = lds[kk == 0 ? 0 : L - kk];
-        double2* xk = X + (size_t)kk * o.ldx;
-        xk[ra] = make_double2(0.5 * (z.x + w.x), 0.5 * (z.y - w.y));
-        if (hasb) xk[rb] = make_double2(0.5 * (z.y + w.y), -0.5 * (z.x - w.x));
+        X[(size_t)kk * o.ldx + ra + r] = r == 0 ? make_double2(0.5 * (z.x + w.x), 0.5 * (z.y - w.y))
+                                                : make_double2(0.5 * (z.y + w.y), -0.5 * (z.x - w.x));
     }
 }
 
@@ -227,21 +233,31 @@ __global__ __launch_bounds__(L / ps_e(L)) void ps_rows_inv(const double2* __rest
     const int ra = 2 * p, rb = 2 * p + 1;
     const bool hasb = rb < m;
     const int tid = threadIdx.x;
-    double2 reg[KE];
+    // Z_k = A_k + i B_k for k <= L/2 and Z_{L-k} = conj A_k + i conj B_k (imaginary
+    // parts dropped at DC and Nyquist).  Item idx is frequency idx / 2 of row
+    // ra + idx mod 2: a lane pair reads the 32 contiguous bytes of one frequency
+    // once, swaps its values, the even lane forms Z_k and the odd one Z_{L-k},
+    // and LDS takes them to the canonical layout.
+    constexpr int NI = (L + 2 + T - 1) / T;
 #pragma unroll
-    for (int e = 0; e < KE; ++e) {
-        const int idx = tid + e * T;
-        const bool lo = idx <= L / 2;
-        const int kk = lo ? idx : L - idx;
-        const double2* xk = X + (size_t)kk * o.ldx;
-        const bool real_bin = kk == 0 || kk == L / 2;    // imaginary parts dropped at DC and Nyquist
-        const double2 ta = xk[ra];
-        const double2 tb = hasb ? xk[rb] : make_double2(0.0, 0.0);
+    for (int it = 0; it < NI; ++it) {
+        const int idx = tid + it * T;
+        const int kk = idx >> 1, r = idx & 1;
+        const bool in = kk <= L / 2;
+        const double2 v = (in && (r == 0 || hasb)) ? X[(size_t)kk * o.ldx + ra + r] : make_double2(0.0, 0.0);
+        // every lane of the wave takes part in the swap (pairs never straddle the range end)
+        const double2 u = make_double2(__shfl_xor(v.x, 1), __shfl_xor(v.y, 1));
+        const bool real_bin = kk == 0 || kk == L / 2;
+        const double2 ta = r == 0 ? v : u, tb = r == 0 ? u : v;
         const double2 ha = make_double2(ta.x, real_bin ? 0.0 : ta.y);
         const double2 hb = make_double2(tb.x, real_bin ? 0.0 : tb.y);
-        // Z_k = A_k + i B_k, with A_{L-k} = conj A_k, B_{L-k} = conj B_k
-        reg[e] = lo ? make_double2(ha.x - hb.y, ha.y + hb.x) : make_double2(ha.x + hb.y, hb.x - ha.y);
+        if (in && r == 0) lds[lds_slot(kk)] = make_double2(ha.x - hb.y, ha.y + hb.x);
+        if (in && r == 1 && kk > 0 && kk < L / 2) lds[lds_slot(L - kk)] = make_double2(ha.x + hb.y, hb.x - ha.y);
     }
+    __syncthreads();
+    double2 reg[KE];
+#pragma unroll
+    for (int e = 0; e < KE; ++e) reg[e] = lds[lds_slot(tid + e * T)];
     fft_block<L, KE, true>(reg, lds, tw4);
     __syncthreads();
     double* rows = reinterpret_cast<double*>(lds);       // row a at [0, L), row b at [L, 2L)
