@@ -501,4 +501,37 @@ __device__ __forceinline__ void fft_block(C (&reg)[E], C* lds, const double2* ta
     fft_stages<L, E, INV, 0, TT::NST>(reg, lds, tab);
 }
 
+// Two real columns a, b filtered by one transform pair: reg holds Z = FFT(a + i b)
+// in canonical order (a fft_block result).  The transforms of the real parts
+// follow from Hermitian symmetry, with W = Z_{L-m}:
+//   A_m = (Z_m + conj W) / 2,   B_m = (Z_m - conj W) / (2 i),
+// and reg becomes A sa + i B sb (CONJ: A conj(sa) + i B conj(sb)), both products
+// Hermitian, so the inverse transform returns p + i q with p, q the real
+// filtered columns.  sa, sb: the two spectrum columns (length L).  Goes through
+// LDS once (the partner W sits in another thread); all threads of the block call it.
+// The spectrum reads are not hoisted ahead of each other (one block of a launch
+// runs this; its registers must not raise the kernel's count).
+template <int L, int E, bool CONJ, typename C>
+__device__ __forceinline__ void mul_real_pair(C (&reg)[E], C* lds, const C* __restrict__ sa,
+                                              const C* __restrict__ sb) {
+    using Rl = typename CplxOps<C>::real;
+    constexpr int T = L / E;
+    const int tid = threadIdx.x;
+    __syncthreads();                      // the transform's last LDS reads are done
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[lds_slot(tid + e * T)] = reg[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int m = tid + e * T;
+        const C z = reg[e], w = lds[lds_slot(m == 0 ? 0 : L - m)];
+        const C A = CplxOps<C>::make(Rl(0.5) * (z.x + w.x), Rl(0.5) * (z.y - w.y));
+        const C B = CplxOps<C>::make(Rl(0.5) * (z.y + w.y), Rl(-0.5) * (z.x - w.x));
+        const C P = CONJ ? cmulc(A, sa[m]) : cmul(A, sa[m]);
+        const C Q = CONJ ? cmulc(B, sb[m]) : cmul(B, sb[m]);
+        reg[e] = CplxOps<C>::make(P.x - Q.y, P.y + Q.x);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 }  // namespace lpide

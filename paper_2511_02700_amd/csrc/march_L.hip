@@ -69,7 +69,7 @@ void launch_iteration(const Launch& c, int k) {
             KTime t(c.timer, LPIDE_K_COLS);
             with_E<L>(c.E_cols, [&](auto e) {
                 constexpr int E = decltype(e)::value;
-                t.launch((ks_cols<L, E, C>), dim3(L / 2 + 1, c.np), dim3(L / E), 0, c.stream, c.A, k);
+                t.launch((ks_cols<L, E, C>), dim3(L / 2, c.np), dim3(L / E), 0, c.stream, c.A, k);
             });
         }
         {
@@ -114,7 +114,7 @@ void launch_iteration(const Launch& c, int k) {
 template <int L, bool FFT, bool MIXED>
 void launch_step(const Launch& c, int kmax) {
     if (c.timer) c.timer->tag_k = 0;
-    const dim3 gr(c.xrows, c.np), gc(L / 2 + 1, c.np);
+    const dim3 gr(c.xrows, c.np), gc(L / 2, c.np);
     const bool lean = FFT && !MIXED && c.lean;
     if (FFT && !lean) {
         if (MIXED) {
@@ -198,7 +198,7 @@ template <int L>
 void launch_adj_iteration(const Launch& c, int k) {
     with_E<L>(c.E_cols, [&](auto e) {
         constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_cols<L, E, double2, true>), dim3(L / 2 + 1, 1), dim3(L / E), 0, c.stream, c.A, k);
+        hipLaunchKernelGGL((ks_cols<L, E, double2, true>), dim3(L / 2, 1), dim3(L / E), 0, c.stream, c.A, k);
     });
     with_E<L>(c.E_rinv, [&](auto e) {
         constexpr int E = decltype(e)::value;
@@ -303,7 +303,7 @@ int adj_step(Plan* p, const Launch& c, int s, int* kpred, const double* Y, const
     if (sd.theta < 1.0) {
         with_E<L>(c.E_cols, [&](auto e) {
             constexpr int E = decltype(e)::value;
-            hipLaunchKernelGGL((ks_cols<L, E, double2, true>), dim3(L / 2 + 1, 1), dim3(L / E), 0, c.stream, c.A, 0);
+            hipLaunchKernelGGL((ks_cols<L, E, double2, true>), dim3(L / 2, 1), dim3(L / E), 0, c.stream, c.A, 0);
         });
         with_E<L>(c.E_rinv, [&](auto e) {
             constexpr int E = decltype(e)::value;

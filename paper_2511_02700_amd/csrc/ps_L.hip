@@ -42,7 +42,7 @@ void PsL<L>::bapply(const PsConv& c, const double* Y, int k) {
         constexpr int T = L / ps_e(L);
         hipLaunchKernelGGL((ps_rows_fwd<L>), dim3((o.n_nz + 1) / 2), dim3(T), 0, c.stream, (const double*)c.U, c.X, o,
                            c.tw, c.ctl, k, c.tol);
-        hipLaunchKernelGGL((ps_cols<L>), dim3(L / 2 + 1), dim3(T), 0, c.stream, c.X, c.spec, o, c.tw, c.ctl, k, c.tol);
+        hipLaunchKernelGGL((ps_cols<L>), dim3(L / 2), dim3(T), 0, c.stream, c.X, c.spec, o, c.tw, c.ctl, k, c.tol);
         hipLaunchKernelGGL((ps_rows_inv<L>), dim3((o.n_out + 1) / 2), dim3(T), 0, c.stream, (const double2*)c.X, c.Z, o,
                            c.tw, c.ctl, k, c.tol);
     }

@@ -185,7 +185,9 @@ __global__ __launch_bounds__(L / ps_e(L)) void ps_rows_fwd(const double* __restr
 }
 
 // Column k2: FFT over the n_nz rows (zero padded to L), times the spectrum,
-// inverse FFT, the first n_out entries back into X.
+// inverse FFT, the first n_out entries back into X.  L/2 blocks for the L/2 + 1
+// columns: block 0 filters the two real columns 0 and L/2 as one complex column
+// (mul_real_pair; the row inverse reads only their real parts).
 template <int L>
 __global__ __launch_bounds__(L / ps_e(L)) void ps_cols(double2* __restrict__ X, const double2* __restrict__ spec,
                                                          PsOps o, const double2* __restrict__ tw, const PsCtl* ctl,
@@ -197,22 +199,35 @@ __global__ __launch_bounds__(L / ps_e(L)) void ps_cols(double2* __restrict__ X, 
     load_twiddles<L, KE>(tw, tw4);
     const int col = blockIdx.x;
     const int tid = threadIdx.x;
+    const bool pair = col == 0;
     double2* xc = X + (size_t)col * o.ldx;
+    double2* xn = X + (size_t)(L / 2) * o.ldx;
     double2 reg[KE];
 #pragma unroll
     for (int e = 0; e < KE; ++e) {
         const int idx = tid + e * T;
-        reg[e] = idx < o.n_nz ? xc[idx] : make_double2(0.0, 0.0);
+        if (idx < o.n_nz) reg[e] = pair ? make_double2(xc[idx].x, xn[idx].x) : xc[idx];
+        else reg[e] = make_double2(0.0, 0.0);
     }
     fft_block<L, KE, false>(reg, lds, tw4);
     const double2* sc = spec + (size_t)col * L;
+    if (pair) {
+        mul_real_pair<L, KE, false>(reg, lds, sc, spec + (size_t)(L / 2) * L);
+    } else {
 #pragma unroll
-    for (int e = 0; e < KE; ++e) reg[e] = cmul(reg[e], sc[tid + e * T]);
+        for (int e = 0; e < KE; ++e) reg[e] = cmul(reg[e], sc[tid + e * T]);
+    }
     fft_block<L, KE, true>(reg, lds, tw4);
 #pragma unroll
     for (int e = 0; e < KE; ++e) {
         const int idx = tid + e * T;
-        if (idx < o.n_out) xc[idx] = reg[e];
+        if (idx >= o.n_out) continue;
+        if (pair) {
+            xc[idx] = make_double2(reg[e].x, 0.0);
+            xn[idx] = make_double2(reg[e].y, 0.0);
+        } else {
+            xc[idx] = reg[e];
+        }
     }
 }
 

@@ -203,7 +203,12 @@ __device__ __forceinline__ bool needs_explicit_fft(const MarchArgs& a) {
 __device__ __forceinline__ const MarchArgs& plan_args(const MarchArgs* __restrict__ A) { return A[blockIdx.y]; }
 
 // Column pass of the correlation on the intermediate X (transposed half
-// spectra), FP64 (C = double2) or FP32 (C = float2).
+// spectra), FP64 (C = double2) or FP32 (C = float2); L/2 blocks for the
+// L/2 + 1 columns.  Columns 0 (DC) and L/2 (Nyquist) hold real values (the row
+// transforms of real rows; the row c2r kernels read only their real parts), so
+// block 0 filters both as one complex column (mul_real_pair): a launch of
+// L/2 + 1 blocks would end with a lone block after the last full round of
+// resident blocks.
 // CONJ (adjoint march): multiply by the conjugate spectrum, which applies B^T
 // (the correlation with the reflected kernel).
 template <int L, int E, typename C, bool CONJ = false>
@@ -215,9 +220,31 @@ __global__ __launch_bounds__(L / E) void ks_cols(const MarchArgs* __restrict__ A
     __shared__ double2 tw4[tw_slots<L, E>()];
     load_twiddles<L, E>(a.tw, tw4);
     const int n = a.n, col = blockIdx.x, tid = threadIdx.x;
+    C reg[E];
+    if (col == 0) {
+        C* x0 = xbuf<C>(a);
+        C* xh = x0 + (size_t)(L / 2) * n;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = tid + e * T;
+            reg[e] = idx < n ? CplxOps<C>::make(x0[idx].x, xh[idx].x) : CplxOps<C>::make(0, 0);
+        }
+        fft_block<L, E, false>(reg, lds, tw4);
+        mul_real_pair<L, E, CONJ>(reg, lds, specbuf<C>(a), specbuf<C>(a) + (size_t)(L / 2) * L);
+        fft_block<L, E, true>(reg, lds, tw4);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = tid + e * T;
+            if (idx < n) {
+                x0[idx] = CplxOps<C>::make(reg[e].x, 0);
+                xh[idx] = CplxOps<C>::make(reg[e].y, 0);
+            }
+        }
+        return;
+    }
     C* xc = xbuf<C>(a) + (size_t)col * n;
     const C* sc = specbuf<C>(a) + (size_t)col * L;
-    C reg[E], sp[E];
+    C sp[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int idx = tid + e * T;

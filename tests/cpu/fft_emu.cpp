@@ -100,6 +100,99 @@ bool check(std::mt19937_64& rng, double tol) {
     return ok;
 }
 
+// Two real columns a, b filtered as one complex column (mul_real_pair between a
+// forward and an inverse transform) against p = IDFT(DFT(a) sa) and
+// q = IDFT(DFT(b) sb) in long double, for Hermitian spectra sa, sb (the
+// transforms of real sequences); CONJ multiplies by their conjugates.
+template <int L, int E, bool CONJ, typename C>
+bool check_real_pair(std::mt19937_64& rng, double tol) {
+    using R = typename Real<C>::T;
+    constexpr int T = L / E;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<double2> tw(L);
+    std::vector<long double> cs(L), sn(L);
+    for (int q = 0; q < L; ++q) {
+        const long double ang = -2.0L * pi * q / L;
+        tw[q] = make_double2(double(cosl(ang)), double(sinl(ang)));
+        cs[q] = cosl(ang);
+        sn[q] = sinl(ang);
+    }
+    // DFT (sign -1) or inverse (sign +1, unnormalised) of a complex sequence in long double
+    auto dft = [&](const std::vector<long double>& re, const std::vector<long double>& im, int sign,
+                   std::vector<long double>& ore, std::vector<long double>& oim) {
+        ore.assign(L, 0.0L);
+        oim.assign(L, 0.0L);
+        for (int k = 0; k < L; ++k)
+            for (int j = 0; j < L; ++j) {
+                const int q = int((long long)j * k % L);
+                const long double c = cs[q], s = sign < 0 ? sn[q] : -sn[q];
+                ore[k] += re[j] * c - im[j] * s;
+                oim[k] += re[j] * s + im[j] * c;
+            }
+    };
+    std::normal_distribution<double> nd;
+    std::vector<long double> a(L), b(L), ga(L), gb(L), zero(L, 0.0L);
+    for (int j = 0; j < L; ++j) {
+        a[j] = R(nd(rng));
+        b[j] = R(nd(rng));
+        ga[j] = nd(rng);
+        gb[j] = nd(rng);
+    }
+    std::vector<long double> Ar, Ai, Br, Bi, Sar, Sai, Sbr, Sbi;
+    dft(a, zero, -1, Ar, Ai);
+    dft(b, zero, -1, Br, Bi);
+    dft(ga, zero, -1, Sar, Sai);
+    dft(gb, zero, -1, Sbr, Sbi);
+    std::vector<C> sa(L), sb(L), x(L);
+    std::vector<long double> Pr(L), Pi(L), Qr(L), Qi(L);
+    for (int m = 0; m < L; ++m) {
+        sa[m] = C{R(Sar[m]), R(Sai[m])};
+        sb[m] = C{R(Sbr[m]), R(Sbi[m])};
+        const long double sai = CONJ ? -(long double)sa[m].y : (long double)sa[m].y;
+        const long double sbi = CONJ ? -(long double)sb[m].y : (long double)sb[m].y;
+        Pr[m] = Ar[m] * sa[m].x - Ai[m] * sai;
+        Pi[m] = Ar[m] * sai + Ai[m] * sa[m].x;
+        Qr[m] = Br[m] * sb[m].x - Bi[m] * sbi;
+        Qi[m] = Br[m] * sbi + Bi[m] * sb[m].x;
+        x[m] = C{R(a[m]), R(b[m])};
+    }
+    std::vector<long double> pr, pi_, qr, qi;
+    dft(Pr, Pi, +1, pr, pi_);
+    dft(Qr, Qi, +1, qr, qi);
+    auto lds = std::make_unique<C[]>(lds_slots(L));
+    auto tab = std::make_unique<double2[]>(tw_slots<L, E>());
+    std::barrier<> bar(T);
+    emu_block_barrier = &bar;
+    std::vector<std::thread> th;
+    th.reserve(T);
+    for (int t = 0; t < T; ++t) {
+        th.emplace_back([&, t] {
+            threadIdx.x = unsigned(t);
+            load_twiddles<L, E>(tw.data(), tab.get());
+            C reg[E];
+            for (int e = 0; e < E; ++e) reg[e] = x[t + e * T];
+            bar.arrive_and_wait();
+            fft_block<L, E, false>(reg, lds.get(), tab.get());
+            mul_real_pair<L, E, CONJ>(reg, lds.get(), sa.data(), sb.data());
+            fft_block<L, E, true>(reg, lds.get(), tab.get());
+            bar.arrive_and_wait();       // every thread has finished before x is overwritten
+            for (int e = 0; e < E; ++e) x[t + e * T] = reg[e];
+        });
+    }
+    for (auto& h : th) h.join();
+    emu_block_barrier = nullptr;
+    long double err = 0.0L, scale = 0.0L;
+    for (int j = 0; j < L; ++j) {
+        err = std::max(err, fabsl(pr[j] - x[j].x) + fabsl(qr[j] - x[j].y));
+        scale = std::max(scale, fabsl(pr[j]) + fabsl(qr[j]));
+    }
+    const double rel = double(err / scale);
+    const bool good = rel < tol;
+    std::printf("L=%4d E=%2d %s real pair%s max rel err %.3e %s\n", L, E, sizeof(R) == 8 ? "fp64" : "fp32",
+                CONJ ? " (conj)" : "", rel, good ? "ok" : "FAIL");
+    return good;
+}
+
 template <int L, typename C>
 bool sizes(std::mt19937_64& rng, double tol) {
     bool ok = true;
@@ -150,6 +243,15 @@ bool all_sizes(std::mt19937_64& rng, double tol) {
         if constexpr (mine<18>()) ok = check<4608, 16, C>(rng, tol) && ok;
         if constexpr (mine<19>()) ok = check<5120, 16, C>(rng, tol) && ok;
         if constexpr (mine<20>()) ok = check<7168, 16, C>(rng, tol) && ok;
+    }
+    // DC and Nyquist columns filtered together (the column passes' block 0)
+    if constexpr (mine<21>()) {
+        ok = check_real_pair<3072, 4, false, C>(rng, tol) && ok;
+        ok = check_real_pair<3072, 4, true, C>(rng, tol) && ok;
+    }
+    if constexpr (mine<22>()) {
+        ok = check_real_pair<1024, 16, false, C>(rng, tol) && ok;
+        ok = check_real_pair<640, 4, false, C>(rng, tol) && ok;
     }
     return ok;
 }
