@@ -452,20 +452,23 @@ static __global__ __launch_bounds__(256) void ks_expl_identity(const MarchArgs* 
 // B Y^0 = sum_q coef_q B V^{src_q} from the stored products, the residual
 // R = W + dt theta((D - r_omega) Y^0 + B Y^0) - Y^0, and B Y^0 stored for the
 // iterate; one block per grid row (the row c2r kernel exits in these steps).
-// The row of ks_rows_lin with NS stored products: no branch in the element
-// loop and the arguments read once before it (the stores go through plain
-// pointers, after which they would be read again), so that an element's reads
-// are in flight together.
-template <int NS>
+// The element loop has no branch and the arguments are read once before it (the
+// stores go through plain pointers, after which they would be read again), so
+// that an element's reads are in flight together.  One loop serves every count
+// of stored products: the slots past the count take the first product at
+// weight zero (reads of lines the thread has just fetched, and the same sums:
+// adding a signed zero changes no value).  A dispatch to one loop per count
+// cost 10 us per launch at 2048^2 (90 against 80).
 __device__ __forceinline__ void rows_lin_row(const MarchArgs& a, int i, double cth) {
+    constexpr int NS = 4;
     const Ctl* c = a.ctl;
-    const int n = a.n;
+    const int n = a.n, ns = c->nsrc;
     const double* __restrict__ Hb[NS];
     double cf[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
-        Hb[q] = a.bpool[c->src[q]];
-        cf[q] = c->coef[q];
+        Hb[q] = a.bpool[c->src[q < ns ? q : 0]];
+        cf[q] = q < ns ? c->coef[q] : 0.0;
     }
     const double* __restrict__ U = a.pool[c->y];
     const double* __restrict__ W = a.W;
@@ -492,13 +495,7 @@ static __global__ __launch_bounds__(256) void ks_rows_lin(const MarchArgs* __res
     const int i = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows on one XCD (stencil reads share L2)
     if (i >= n) return;
     const StepDesc& sd = cur_set(a);
-    const double cth = sd.dt * sd.theta;
-    switch (a.ctl->nsrc) {                           // uniform: one loop per count of stored products (1..4)
-        case 1: rows_lin_row<1>(a, i, cth); break;
-        case 2: rows_lin_row<2>(a, i, cth); break;
-        case 3: rows_lin_row<3>(a, i, cth); break;
-        default: rows_lin_row<4>(a, i, cth); break;
-    }
+    rows_lin_row(a, i, sd.dt * sd.theta);
 }
 
 // The row of ks_sl_lin with NS history grids in the start value: no branch in
