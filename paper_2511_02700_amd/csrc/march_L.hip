@@ -164,8 +164,9 @@ void launch_step(const Launch& c, int kmax) {
     }
     if (FFT && !MIXED) {                  // steps with B Y^0 by linearity (ks_sl exits in them)
         KTime t(c.timer, LPIDE_K_SL_LIN);
-        if (c.sl_order == 1) t.launch(ks_sl_lin<1>, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
-        else t.launch(ks_sl_lin<3>, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
+        const size_t shm = sizeof(double) * c.xaff;   // the combined source rows of the largest plan
+        if (c.sl_order == 1) t.launch(ks_sl_lin<1>, dim3(c.xaff, c.np), dim3(256), shm, c.stream, c.A);
+        else t.launch(ks_sl_lin<3>, dim3(c.xaff, c.np), dim3(256), shm, c.stream, c.A);
     }
     if (c.record) hipLaunchKernelGGL(ks_store_E, dim3(c.store_blocks, c.np), dim3(256), 0, c.stream, c.A);
     for (int k = 1; k <= kmax; ++k) launch_iteration<L, FFT, MIXED>(c, k);

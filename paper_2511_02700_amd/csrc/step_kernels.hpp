@@ -55,7 +55,9 @@ struct Ctl {
     int hist[4];                      // pool indices, newest first
     int bvalid;                       // bit b: bpool[b] holds B applied to pool[b] (this march)
     int src[4];
-    double coef[4];                   // Y^0 = sum_q coef[q] pool[src[q]]
+    double coef[4];                   // Y^0 = sum_q coef[q] pool[src[q]]; past nsrc,
+                                      // src[q] = src[0] and coef[q] = 0 (so a loop
+                                      // over all four terms gives the same sums)
     // stopping-rule value after iteration k: the maximum over x of err[x][k]
     // (bit patterns of non-negative doubles).  The row blocks of the line-solve
     // kernel reduce into the partial of their XCD, so the atomics of one launch
@@ -455,20 +457,21 @@ static __global__ __launch_bounds__(256) void ks_expl_identity(const MarchArgs* 
 // The element loop has no branch and the arguments are read once before it (the
 // stores go through plain pointers, after which they would be read again), so
 // that an element's reads are in flight together.  One loop serves every count
-// of stored products: the slots past the count take the first product at
-// weight zero (reads of lines the thread has just fetched, and the same sums:
-// adding a signed zero changes no value).  A dispatch to one loop per count
-// cost 10 us per launch at 2048^2 (90 against 80).
+// of stored products: the terms past the count repeat the first product at
+// weight zero (Ctl: reads of lines the thread has just fetched, and the same
+// sums, since adding a signed zero changes no value).  A dispatch to one loop
+// per count cost 10 us per launch at 2048^2 (90 against 80).
+template <int UN = 4>
 __device__ __forceinline__ void rows_lin_row(const MarchArgs& a, int i, double cth) {
     constexpr int NS = 4;
     const Ctl* c = a.ctl;
-    const int n = a.n, ns = c->nsrc;
+    const int n = a.n;
     const double* __restrict__ Hb[NS];
     double cf[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
-        Hb[q] = a.bpool[c->src[q < ns ? q : 0]];
-        cf[q] = q < ns ? c->coef[q] : 0.0;
+        Hb[q] = a.bpool[c->src[q]];
+        cf[q] = c->coef[q];
     }
     const double* __restrict__ U = a.pool[c->y];
     const double* __restrict__ W = a.W;
@@ -476,15 +479,30 @@ __device__ __forceinline__ void rows_lin_row(const MarchArgs& a, int i, double c
     double* __restrict__ Bout = a.bpool[c->y];
     const double r_omega = a.r_omega;
     const StencilArgs st = a.st;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const size_t o = (size_t)i * n + j;
-        double bu = 0.0;
+    // UN elements per thread and pass, the products and W of all of them read
+    // first (their reads in flight together: 90 -> 80 -> 71 us per launch at
+    // 2048^2 with one loop per count, one loop, one loop of UN = 4)
+    for (int j0 = threadIdx.x; j0 < n; j0 += UN * blockDim.x) {
+        double bu[UN], w[UN];
 #pragma unroll
-        for (int q = 0; q < NS; ++q) bu += cf[q] * Hb[q][o];
-        const double u = U[o];
-        const double d = apply_D_ahead(U, st, i, j, u);
-        R[o] = W[o] + cth * (d + bu - r_omega * u) - u;
-        Bout[o] = bu;
+        for (int u = 0; u < UN; ++u) {
+            const int j = j0 + u * blockDim.x;
+            const size_t o = (size_t)i * n + (j < n ? j : j0);   // past the row end: a repeated read, not used
+            bu[u] = 0.0;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) bu[u] += cf[q] * Hb[q][o];
+            w[u] = W[o];
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const int j = j0 + u * blockDim.x;
+            if (j >= n) break;
+            const size_t o = (size_t)i * n + j;
+            const double y = U[o];
+            const double d = apply_D_ahead(U, st, i, j, y);
+            R[o] = w[u] + cth * (d + bu[u] - r_omega * y) - y;
+            Bout[o] = bu[u];
+        }
     }
 }
 
@@ -498,11 +516,14 @@ static __global__ __launch_bounds__(256) void ks_rows_lin(const MarchArgs* __res
     rows_lin_row(a, i, sd.dt * sd.theta);
 }
 
-// The row of ks_sl_lin with NS history grids in the start value: no branch in
-// the element loop and the step's tables read once before it, so that an
-// element's reads are in flight together.
+// The row of ks_sl_lin with NS history grids in the start value.  The gather
+// is taken in its separable order: the row weights combine the P + 1 source
+// rows into ec (LDS, n values: four coalesced reads per element instead of
+// (P + 1)^2 stencil reads), then each node takes its P + 1 column taps from ec.
+// Two elements per thread and pass, their history reads issued together; no
+// branch in the element loop and the step's tables read once before it.
 template <int P, int NS>
-__device__ __forceinline__ void sl_lin_row(const MarchArgs& a, int i) {
+__device__ __forceinline__ void sl_lin_row(const MarchArgs& a, int i, double* __restrict__ ec) {
     const Ctl* c = a.ctl;
     const int n = a.n;
     const StepDesc& sd = cur_set(a);
@@ -522,47 +543,62 @@ __device__ __forceinline__ void sl_lin_row(const MarchArgs& a, int i) {
 #pragma unroll
     for (int q = 0; q <= P; ++q) w1[q] = sd.w1[i * (P + 1) + q];
     const double* __restrict__ er0 = Ex + (size_t)a0 * n;
+    const int T = blockDim.x;
+    for (int k = threadIdx.x; k < n; k += T) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q <= P; ++q) v += w1[q] * er0[(size_t)q * n + k];
+        ec[k] = v;
+    }
+    __syncthreads();
     const int* __restrict__ s2 = sd.s2;
     const double* __restrict__ wt2 = sd.w2;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const int b0 = s2[j];
-        double w2[P + 1];
+    constexpr int UN = 2;
+    for (int j0 = threadIdx.x; j0 < n; j0 += UN * T) {
+        double hv[UN][NS];
 #pragma unroll
-        for (int b = 0; b <= P; ++b) w2[b] = wt2[j * (P + 1) + b];
-        double acc = 0.0;
+        for (int u = 0; u < UN; ++u) {
+            const int j = j0 + u * T;
+            const size_t o = (size_t)i * n + (j < n ? j : j0);   // past the row end: a repeated read, not used
 #pragma unroll
-        for (int q = 0; q <= P; ++q) {
-            const double* er = er0 + (size_t)q * n + b0;
-            double sq = 0.0;
-#pragma unroll
-            for (int b = 0; b <= P; ++b) sq += w2[b] * er[b];
-            acc += w1[q] * sq;
+            for (int q = 0; q < NS; ++q) hv[u][q] = H[q][o];
         }
-        const size_t o = (size_t)i * n + j;
-        double y = cf[0] * H[0][o];
 #pragma unroll
-        for (int q = 1; q < NS; ++q) y += cf[q] * H[q][o];
-        Wo[o] = acc;
-        Y[o] = y;
+        for (int u = 0; u < UN; ++u) {
+            const int j = j0 + u * T;
+            if (j >= n) break;
+            const int b0 = s2[j];
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b <= P; ++b) acc += wt2[j * (P + 1) + b] * ec[b0 + b];
+            const size_t o = (size_t)i * n + j;
+            double y = cf[0] * hv[u][0];
+#pragma unroll
+            for (int q = 1; q < NS; ++q) y += cf[q] * hv[u][q];
+            Wo[o] = acc;
+            Y[o] = y;
+        }
     }
 }
 
 // SL gather W = T^SL E and start value Y^0 of an FP64 step whose B Y^0 comes by
 // linearity (no row transform of Y^0): one block per grid row, streaming; at
 // least 8 waves per SIMD (64 registers), so that the reads hoisted out of the
-// branch-free loop do not cost occupancy.
+// branch-free loop do not cost occupancy.  Dynamic LDS: n doubles (the largest
+// n of the launch's plans).
 template <int P>
 __global__ __launch_bounds__(256, 8) void ks_sl_lin(const MarchArgs* __restrict__ A) {
+    extern __shared__ double sl_ec[];
     const MarchArgs& a = plan_args(A);
     if (halted(a, 0) || a.mixed || !start_by_linearity(a)) return;
     const int n = a.n;
     const int i = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows share E rows in L2
     if (i >= n) return;
     switch (a.ctl->nsrc) {                           // uniform: one loop per count of history grids (1..4)
-        case 1: sl_lin_row<P, 1>(a, i); break;
-        case 2: sl_lin_row<P, 2>(a, i); break;
-        case 3: sl_lin_row<P, 3>(a, i); break;
-        default: sl_lin_row<P, 4>(a, i); break;
+        case 1: sl_lin_row<P, 1>(a, i, sl_ec); break;
+        case 2: sl_lin_row<P, 2>(a, i, sl_ec); break;
+        case 3: sl_lin_row<P, 3>(a, i, sl_ec); break;
+        default: sl_lin_row<P, 4>(a, i, sl_ec); break;
     }
 }
 
@@ -908,6 +944,7 @@ static __global__ void ks_step_end(const MarchArgs* __restrict__ A, int kmax) {
                     else if (c->hc == 3) { c->coef[0] = 3.0; c->coef[1] = -3.0; c->coef[2] = 1.0; }
                     else { c->coef[0] = 4.0; c->coef[1] = -6.0; c->coef[2] = 4.0; c->coef[3] = -1.0; }
                 }
+                for (int q = c->nsrc; q < 4; ++q) c->src[q] = c->src[0];   // weight 0 (above)
             }
         }
     }
