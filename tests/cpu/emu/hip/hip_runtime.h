@@ -22,3 +22,5 @@ inline thread_local EmuThreadIdx threadIdx{0};
 // the barrier of the workgroup being emulated (set before its threads start)
 inline std::barrier<>* emu_block_barrier = nullptr;
 inline void __syncthreads() { emu_block_barrier->arrive_and_wait(); }
+// instruction-scheduling fence of the GPU compiler: nothing to do on the host
+inline void __builtin_amdgcn_sched_barrier(int) {}
