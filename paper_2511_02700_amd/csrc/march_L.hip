@@ -41,20 +41,39 @@ void launch_rows_fwd(Plan* p, const double* Y, hipStream_t s) {
 }
 
 // The axis-1 line-solve kernel for the launch's columns per block; bounds of
-// 256 threads where the block fits (no register cap of 128), and a chunk
-// capacity of 16 where every chunk fits (the chunks of the largest plan hold
-// ceil(n / P_cols) <= ceil(xcols cpb / P_cols) rows).
+// 256 threads where the block fits (no register cap of 128), and the smallest
+// chunk capacity of 8, 16 and LINE_MM that holds every chunk (the chunks of the
+// largest plan hold ceil(n / P_cols) <= ceil(xcols cpb / P_cols) rows; the
+// sweeps run over all capacity slots).
+template <int CPB, int MAXT, typename Go>
+void with_line_cols_mm(const Launch& c, Go&& go) {
+    const int ch = (c.xcols * c.cpb + c.P_cols - 1) / c.P_cols;
+    if (ch <= 8) go(ks_line_cols<CPB, MAXT, 8>);
+    else if (ch <= 16) go(ks_line_cols<CPB, MAXT, 16>);
+    else go(ks_line_cols<CPB, MAXT, LINE_MM>);
+}
+
 template <typename Go>
 void with_line_cols(const Launch& c, Go&& go) {
     const bool small = c.cpb * c.P_cols <= 256;
-    const bool short_chunks = (c.xcols * c.cpb + c.P_cols - 1) / c.P_cols <= 16;
     if (c.cpb == 2) {
-        if (small) short_chunks ? go(ks_line_cols<2, 256, 16>) : go(ks_line_cols<2, 256, LINE_MM>);
-        else short_chunks ? go(ks_line_cols<2, 1024, 16>) : go(ks_line_cols<2, 1024, LINE_MM>);
+        if (small) with_line_cols_mm<2, 256>(c, go);
+        else with_line_cols_mm<2, 1024>(c, go);
     } else {
-        if (small) short_chunks ? go(ks_line_cols<4, 256, 16>) : go(ks_line_cols<4, 256, LINE_MM>);
-        else short_chunks ? go(ks_line_cols<4, 1024, 16>) : go(ks_line_cols<4, 1024, LINE_MM>);
+        if (small) with_line_cols_mm<4, 256>(c, go);
+        else with_line_cols_mm<4, 1024>(c, go);
     }
+}
+
+// The line-row kernel with E elements per thread and the smallest chunk
+// capacity (E, 3E/2 or 2E) that holds the longest chunk of the launch's plans.
+template <int L, int E, bool FFT, bool MIXED, typename Go>
+void with_line_rows(const Launch& c, Go&& go) {
+    constexpr int PR = L / E / 2;
+    const int m = (c.xaff + PR - 1) / PR;
+    if (m <= E) go(ks_line_rows<L, E, FFT, MIXED, E>);
+    else if (m <= 3 * E / 2) go(ks_line_rows<L, E, FFT, MIXED, 3 * E / 2>);
+    else go(ks_line_rows<L, E, FFT, MIXED, 2 * E>);
 }
 
 template <int L, bool FFT, bool MIXED>
@@ -99,7 +118,9 @@ void launch_iteration(const Launch& c, int k) {
     KTime t(c.timer, LPIDE_K_LINE_ROWS);
     with_E<L>(c.E_lrows, [&](auto e) {
         constexpr int E = decltype(e)::value;
-        t.launch((ks_line_rows<L, E, FFT, MIXED>), dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A, k);
+        with_line_rows<L, E, FFT, MIXED>(c, [&](auto kern) {
+            t.launch(kern, dim3(c.xrows, c.np), dim3(L / E), 0, c.stream, c.A, k);
+        });
     });
 }
 
@@ -211,7 +232,9 @@ void launch_adj_iteration(const Launch& c, int k) {
     });
     with_E<L>(c.E_lrows, [&](auto e) {
         constexpr int E = decltype(e)::value;
-        hipLaunchKernelGGL((ks_line_rows<L, E, true, false>), dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);
+        with_line_rows<L, E, true, false>(c, [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(c.xrows, 1), dim3(L / E), 0, c.stream, c.A, k);
+        });
     });
 }
 

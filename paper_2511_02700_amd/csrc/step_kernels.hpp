@@ -779,8 +779,13 @@ __global__ __launch_bounds__(MAXT) void ks_line_cols(const MarchArgs* __restrict
 // Axis-2 line solves of a row pair, the update Y += delta, the stopping-rule
 // maximum err_k = max |delta| / max(1, |Y|), and (FFT) the row transform of the
 // updated Y (FP64) or, in the mixed form, of delta (FP32) for the next iteration.
-template <int L, int E, bool FFT, bool MIXED>
+// MM: the chunk capacity, at least the longest chunk ceil(n / PR) of the
+// launch's plans (at most 2E, since n <= L = 2 E PR); the line-solve sweeps run
+// over all MM slots, so the host takes the smallest of E, 3E/2 and 2E that
+// holds the chunks (24 instead of 32 at n = 2048, L = 3072: 65 -> 55 us alone).
+template <int L, int E, bool FFT, bool MIXED, int MM = 2 * E>
 __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restrict__ A, int k) {
+    static_assert(MM <= 2 * E && MM % 2 == 0, "chunk capacity: even, at most 2E");
     const MarchArgs& a = plan_args(A);
     if (halted(a, k)) return;
     constexpr int T = L / E, PR = T / 2;
@@ -815,7 +820,6 @@ __global__ __launch_bounds__(L / E) void ks_line_rows(const MarchArgs* __restric
     const int r = tid / PR, ch = tid % PR;
     const int s = ch * m;
     const int cnt = (r == 1 && !hasb) ? 0 : max(0, min(m, n - s));
-    constexpr int MM = 2 * E;             // n <= L = 2 E PR: chunks of at most 2E elements
     double x[MM];
     {
         const double* Rr = a.R + (size_t)(r == 0 ? ra : rb) * n + s;
