@@ -83,7 +83,9 @@ template <int MM = LINE_MM>
 __device__ __forceinline__ void chunk_solve(double (&x)[MM], int i0, int m, int g, int t, int P, int dl,
                                             const double* __restrict__ fl, const double* __restrict__ bu,
                                             const double* __restrict__ bc, double2* wtot) {
-    constexpr int W = LINE_W;
+    // reads ahead at most the capacity: every factor read of the chunk then
+    // lies in [i0, i0 + MM) (the backward sweeps start MM - 1 past i0)
+    constexpr int W = LINE_W < MM ? LINE_W : MM;
     const int b = m > 0 ? i0 : 0;                     // chunks past the line's end read from its start
     const gdouble* F = (const gdouble*)(fl + b);
     const gdouble* U = (const gdouble*)(bu + b);

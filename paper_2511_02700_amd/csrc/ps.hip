@@ -425,9 +425,11 @@ void iteration(PsPlan* p, const Kind& kd, double* Y, const double* W, int k) {
     const double tol = p->opts.tol;
     if (p->jumps) bapply(p, p->conv, Y, k);
     const int lpb = 256 / p->P_rows;
-    // chunk capacity 8 where every chunk fits (the plan's chunks hold at most 4 up to n = 1024)
-    auto rows = (n + p->P_rows - 1) / p->P_rows <= 8 ? ps_resid_rows<8> : ps_resid_rows<LINE_MM>;
-    auto cols = (n + p->P_cols - 1) / p->P_cols <= 8 ? ps_line_cols<8> : ps_line_cols<LINE_MM>;
+    // the smallest chunk capacity of 4, 8 and LINE_MM that holds every chunk (the
+    // plan's chunks hold at most 4 up to n = 1024; the sweeps run over all slots)
+    const int chr = (n + p->P_rows - 1) / p->P_rows, chc = (n + p->P_cols - 1) / p->P_cols;
+    auto rows = chr <= 4 ? ps_resid_rows<4> : chr <= 8 ? ps_resid_rows<8> : ps_resid_rows<LINE_MM>;
+    auto cols = chc <= 4 ? ps_line_cols<4> : chc <= 8 ? ps_line_cols<8> : ps_line_cols<LINE_MM>;
     hipLaunchKernelGGL(rows, dim3((n + lpb - 1) / lpb), dim3(256), 0, p->stream, (const double*)Y, W,
                        p->jumps ? (const double*)p->conv.Z : (const double*)nullptr, p->Q, p->ops, kd.sk, p->P_rows,
                        (const PsCtl*)p->ctl, k, tol);
