@@ -87,9 +87,18 @@ def algorithmic_bytes(cls, n, L, mixed=False):
     }[cls]
 
 
-def kernel_symbol(cls, L, mixed, sl_order, radix=(8, 8, 8, 8)):
+def line_rows_capacity(n, L, el):
+    """Chunk capacity the march launches the line-row kernel with: the smallest
+    of E, 3E/2 and 2E that holds the longest chunk ceil(n / PR), PR = L / E / 2."""
+    pr = L // el // 2
+    m = -(-n // pr)
+    return el if m <= el else (3 * el // 2 if m <= 3 * el // 2 else 2 * el)
+
+
+def kernel_symbol(cls, L, mixed, sl_order, radix=(8, 8, 8, 8), n=None):
     """The kernel instantiation a timing class launches in the march (radix =
-    elements per thread of the column pass, row c2r, line-row and SL kernels)."""
+    elements per thread of the column pass, row c2r, line-row and SL kernels;
+    n: grid side, for the line-row kernel's chunk capacity)."""
     tf = "true" if mixed else "false"
     c = "float" if mixed and cls == "cols" else "double"
     ec, er, el, es = radix
@@ -99,7 +108,8 @@ def kernel_symbol(cls, L, mixed, sl_order, radix=(8, 8, 8, 8)):
         "rows_inv": "lpide::ks_rows_inv<%d, %d, %d>" % (L, er, 2 if mixed else 1),
         "expl_rows": "lpide::ks_rows_inv<%d, %d, 0>" % (L, er),
         "line_cols": "lpide::ks_line_cols",
-        "line_rows": "lpide::ks_line_rows<%d, %d, true, %s>" % (L, el, tf),
+        "line_rows": "lpide::ks_line_rows<%d, %d, true, %s, %d>" % (L, el, tf,
+                                                                   line_rows_capacity(n or L, L, el)),
         "sl": "lpide::ks_sl<%d, %d, %d, true, %s>" % (L, es, sl_order, tf),
         "step_end": "lpide::ks_step_end",
         "rows_fwd": "lpide::ks_rows_fwd<%d, %d>" % (L, er),
@@ -132,7 +142,7 @@ def roofline(cls, n, L, mixed, launches, ms, traffic_json=None, sl_order=3, radi
     per_launch_ms = ms / max(1, launches)
     b = algorithmic_bytes(cls, n, L, mixed)
     achieved = b / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
-    sym = kernel_symbol(cls, L, mixed, sl_order, radix)
+    sym = kernel_symbol(cls, L, mixed, sl_order, radix, n)
     return {"kernel": cls, "symbol": sym, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(traffic_json, sym), "bytes_per_launch": b,
             "mean_launch_ms": per_launch_ms, "launches": launches}
