@@ -280,11 +280,15 @@ int harvest_times(Plan* p) {
         if ((r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS) && known && !p->mixed &&
             p->sets[p->step_set[r.step]].theta >= 1.0)
             continue;
-        if (p->mixed && known) {            // the mixed form runs either the anchor kernels or the carry
+        if (p->mixed && known) {            // the mixed form: the anchor kernels, the identity or the carry
             const bool anchor = (r.step - p->march_step0) % p->anchor_every == 0;
+            const bool ident = !p->opts.all_correlations && r.step > p->march_step0 && p->cn_rho[r.step] > 0.0;
+            const bool theta1 = p->sets[p->step_set[r.step]].theta >= 1.0;
             const bool anchor_cls =
                 r.cls == LPIDE_K_EXPL_COLS || r.cls == LPIDE_K_EXPL_ROWS || r.cls == LPIDE_K_ROWS_FWD;
-            if ((anchor_cls && !anchor) || (r.cls == LPIDE_K_CARRY && anchor)) continue;
+            if ((anchor_cls && !anchor) || (r.cls == LPIDE_K_CARRY && (anchor || ident || theta1)) ||
+                (r.cls == LPIDE_K_EXPL_ID && (anchor || !ident)))
+                continue;
         }
         if (known && r.k == 1) {            // iteration 1: B Y^0 by linearity or by the correlation
             if (lin[r.step] && (r.cls == LPIDE_K_COLS || r.cls == LPIDE_K_ROWS_INV)) continue;
@@ -376,7 +380,7 @@ MarchArgs march_args(const Plan* p) {
     a.nsteps = p->n_steps;
     a.step0 = 0;
     a.anchor_every = p->anchor_every;
-    a.cn_rho = (p->mixed || p->opts.all_correlations) ? nullptr : p->cn_rho_d;
+    a.cn_rho = p->opts.all_correlations ? nullptr : p->cn_rho_d;
     for (int b = 0; b < POOL; ++b) a.bpool[b] = p->bpool[b];
     return a;
 }

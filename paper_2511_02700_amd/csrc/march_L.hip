@@ -159,10 +159,11 @@ void launch_step(const Launch& c, int kmax) {
                 t.launch((ks_rows_inv<L, E, 0>), gr, dim3(L / E), 0, c.stream, c.A, 0);
             });
         }
-        if (MIXED) {                      // steps between anchors: B V^{n-1} carried (the three above exit)
+        if (MIXED) {                      // steps between anchors without the identity (the three above exit)
             KTime t(c.timer, LPIDE_K_CARRY);
             t.launch(ks_carry, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
-        } else {                          // explicit part from the previous step's equation (the two above exit)
+        }
+        {                                 // explicit part from the previous step's equation (the two above exit)
             KTime t(c.timer, LPIDE_K_EXPL_ID);
             t.launch(ks_expl_identity, dim3(c.xaff, c.np), dim3(256), 0, c.stream, c.A);
         }

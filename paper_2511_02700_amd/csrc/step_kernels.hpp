@@ -159,8 +159,8 @@ __device__ __forceinline__ bool needs_explicit(const MarchArgs& a) { return a.mi
 
 // Mixed form: the steps whose B V^{n-1} is computed afresh by the FP64
 // correlation (every anchor_every-th step of the march, its first step
-// included).  In the others B V^{n-1} is carried from the previous step
-// (ks_carry).
+// included).  In the others B V^{n-1} is carried from the previous step: its
+// last accumulated B Y, still in BY when the step's first iteration adds to it.
 __device__ __forceinline__ bool is_anchor(const MarchArgs& a) {
     return (a.ctl->step - a.step0) % a.anchor_every == 0;
 }
@@ -172,8 +172,9 @@ __device__ __forceinline__ bool is_anchor(const MarchArgs& a) {
 // rho = dt (1 - theta) / c: the same explicit part without applying B, exact
 // at the fixed point (the converged iterate leaves the stopping-rule residual).
 // Used from the second step of a march on, when the previous step had
-// theta > 0 (cn_rho > 0, set by the host; null for the mixed form and the
-// adjoint march).
+// theta > 0 (cn_rho > 0, set by the host; null with every product by the
+// correlation and in the adjoint march); in the mixed form outside its anchor
+// steps, whose FP64 correlation forms the explicit part.
 __device__ __forceinline__ bool explicit_by_identity(const MarchArgs& a) {
     return a.cn_rho && a.ctl->step > a.step0 && a.cn_rho[a.ctl->step] > 0.0;
 }
@@ -209,8 +210,8 @@ __device__ __forceinline__ const MarchArgs& plan_args(const MarchArgs* __restric
 // L/2 + 1 columns.  Columns 0 (DC) and L/2 (Nyquist) hold real values (the row
 // transforms of real rows; the row c2r kernels read only their real parts), so
 // block 0 filters both as one complex column (mul_real_pair): a launch of
-// L/2 + 1 blocks would end with a lone block after the last full round of
-// resident blocks.
+// L/2 + 1 blocks would end with one block running alone after the last full
+// set of resident blocks had finished.
 // CONJ (adjoint march): multiply by the conjugate spectrum, which applies B^T
 // (the correlation with the reflected kernel).
 template <int L, int E, typename C, bool CONJ = false>
@@ -306,8 +307,9 @@ __device__ __forceinline__ void rows_inv_gather(C (&reg)[E], C* lds, const C* __
 // MODE 0 (once per step, FP64): E = V + dt(1-theta)((D - r_omega) V + B V) into R
 //         (theta < 1), and B V into BV (mixed form);
 // MODE 1 (FP64 iteration):  R = W + dt theta((D - r_omega) Y + B Y) - Y;
-// MODE 2 (mixed iteration): B Y = (k == 1 ? BV : B Y) + B32(increment) into BY,
-//         then R as in MODE 1 with that B Y.
+// MODE 2 (mixed iteration): B Y = (k == 1 in an anchor step ? BV : B Y) + B32(increment)
+//         into BY, then R as in MODE 1 with that B Y (k == 1 elsewhere: BY still holds
+//         the previous step's last B Y, the carried B V^{n-1}).
 // Adjoint march (B^T from a CONJ column pass, D^T the transposed stencil):
 // MODE 3 (iteration): R = Ybar + dt theta ((D^T - r_omega) lam + B^T lam) - lam,
 //         with Ybar in W and lam the iterate;
@@ -347,7 +349,7 @@ __global__ __launch_bounds__(L / E) void ks_rows_inv(const MarchArgs* __restrict
     const double c = EXPL ? sd.dt * (1.0 - sd.theta) : sd.dt * sd.theta;
     const double c0 = EXPL ? 0.0 : -1.0;
     const bool want_r = MODE != 0 || sd.theta < 1.0;
-    const double* base = (MODE == 2 && k == 1) ? a.BV : a.BY;
+    const double* base = (MODE == 2 && k == 1 && is_anchor(a)) ? a.BV : a.BY;
     // the arguments the loop needs, read once: the stores below go through
     // plain pointers, after which every field of a would be read again
     const StencilArgs st = a.st;
@@ -405,38 +407,34 @@ __global__ __launch_bounds__(256) void ks_affine_noB(const MarchArgs* __restrict
     }
 }
 
-// Mixed form, steps between anchors: B V^{n-1} is carried from the previous
-// step, whose last iteration left B Y in BY (FP64 sums of FP32 correlations of
-// the increments; it misses B applied to the final increment, which is below
-// the stopping tolerance), and the explicit part
+// Mixed form, steps between anchors whose explicit part does not come from the
+// previous step's equation (explicit_by_identity): B V^{n-1} is carried from
+// the previous step, whose last iteration left B Y in BY (FP64 sums of FP32
+// correlations of the increments; it misses B applied to the final increment,
+// which is below the stopping tolerance), and the explicit part
 // E = V + dt (1 - theta)((D - r_omega) V + B V) (theta < 1) is formed without
 // a correlation.  One block per grid row.
 static __global__ __launch_bounds__(256) void ks_carry(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
-    if (halted(a, 0) || !a.mixed || is_anchor(a)) return;
+    if (halted(a, 0) || !a.mixed || is_anchor(a) || explicit_by_identity(a) || cur_set(a).theta >= 1.0) return;
     const int n = a.n;
     const int i = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows on one XCD (stencil reads share L2)
     if (i >= n) return;
     const StepDesc& sd = cur_set(a);
     const double* U = a.pool[a.ctl->cur];
     const double c = sd.dt * (1.0 - sd.theta);
-    const bool want_r = sd.theta < 1.0;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const size_t o = (size_t)i * n + j;
-        const double bv = a.BY[o];
-        a.BV[o] = bv;
-        if (want_r) {
-            const double u = U[o];
-            a.R[o] = u + c * (apply_D(U, a.st, i, j, u) + bv - a.r_omega * u);
-        }
+        const double u = U[o];
+        a.R[o] = u + c * (apply_D(U, a.st, i, j, u) + a.BY[o] - a.r_omega * u);
     }
 }
 
 // Explicit part from the previous step's implicit equation (explicit_by_identity):
-// R = V + rho (V - W); one block per grid row.
+// R = V + rho (V - W); one block per grid row.  Mixed form: not in anchor steps.
 static __global__ __launch_bounds__(256) void ks_expl_identity(const MarchArgs* __restrict__ A) {
     const MarchArgs& a = plan_args(A);
-    if (halted(a, 0) || !explicit_by_identity(a)) return;
+    if (halted(a, 0) || !explicit_by_identity(a) || (a.mixed && is_anchor(a))) return;
     const int n = a.n;
     const int i = blockIdx.x;
     if (i >= n) return;
